@@ -1,0 +1,126 @@
+"""Oracle for the C-l-AIR restriction setup -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, FP64 CPU implementations that the GPU library is checked
+against.  Only the tests, the smoke check and the benchmark's CPU-baseline leg
+may import this package; the product path never does.  It shares no code with
+the GPU library: the C oracle (``clair_oracle.c``) is built with gcc, and the
+NumPy modules (``dense``, ``literal``) use only NumPy/SciPy primitives.
+
+Modules
+-------
+``build_R``      -- ctypes wrapper around the C oracle (closed form of
+                    Algorithm 1 with exact local inverses, k = 1).
+``dense``        -- brute force on tiny inputs: neighbourhoods by dense
+                    boolean reachability, per-row dense solves, and the ideal
+                    restriction R_ideal = [-A_cf A_ff^{-1}, I].
+``literal``      -- Algorithm 1 step by step (tentative operator, least-squares
+                    constraint fit, residual update, explicit projection), for
+                    any number k of iterations.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "clair_oracle.c")
+_LIB = os.path.join(_HERE, "libclair_oracle.so")
+
+ORC_OK, ORC_ERR_INVALID, ORC_ERR_CAPACITY, ORC_ERR_SINGULAR, ORC_ERR_NOMEM = 0, 1, 2, 3, 4
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (-O2, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wextra",
+               "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        p = ctypes.c_void_p
+        i32, i64 = ctypes.c_int32, ctypes.c_int64
+        lib.orc_pattern_size.argtypes = [i32, p, p, p, p, i32, i32, p, p, p]
+        lib.orc_pattern_size.restype = ctypes.c_int
+        lib.orc_build_R.argtypes = [i32, p, p, p, p, p, i32, i32, p, p, p, i64, p, p]
+        lib.orc_build_R.restype = ctypes.c_int
+        lib.orc_max_threads.argtypes = []
+        lib.orc_max_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(msg)
+        self.code = code
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
+
+
+def pattern_size(n, row_ptr, col_idx, val, cf, ell, nthreads=0):
+    """(n_c, nnz_R, sizes[n_c]) with sizes[r] = |N(i_r)|."""
+    lib = _load()
+    rp = np.ascontiguousarray(row_ptr, np.int32)
+    ci = np.ascontiguousarray(col_idx, np.int32)
+    va = np.ascontiguousarray(val, np.float64)
+    cf = np.ascontiguousarray(cf, np.int8)
+    n_c = ctypes.c_int32(0)
+    nnz = ctypes.c_int64(0)
+    sizes = np.zeros(int((cf != 0).sum()) or 1, np.int32)
+    rc = lib.orc_pattern_size(n, _ptr(rp), _ptr(ci), _ptr(va), _ptr(cf), ell, nthreads,
+                              ctypes.byref(n_c), ctypes.byref(nnz), _ptr(sizes))
+    if rc:
+        raise OracleError(rc, f"oracle pattern_size failed ({rc})")
+    return n_c.value, nnz.value, sizes[: n_c.value]
+
+
+def build_R(n, row_ptr, col_idx, val, cf, B, ell, nthreads=0, allow_singular=False):
+    """FP64 oracle R (CSR arrays) plus statistics.
+
+    Returns dict(row_ptr, col_idx, val, n_c, nnz, n_uncovered, bad_row).
+    """
+    lib = _load()
+    rp = np.ascontiguousarray(row_ptr, np.int32)
+    ci = np.ascontiguousarray(col_idx, np.int32)
+    va = np.ascontiguousarray(val, np.float64)
+    cfa = np.ascontiguousarray(cf, np.int8)
+    Ba = None if B is None else np.ascontiguousarray(B, np.float64)
+    n_c, nnz, _ = pattern_size(n, rp, ci, va, cfa, ell, nthreads)
+    Rrp = np.zeros(n_c + 1, np.int32)
+    Rci = np.zeros(max(nnz, 1), np.int32)
+    Rva = np.zeros(max(nnz, 1), np.float64)
+    unc = ctypes.c_int64(0)
+    bad = ctypes.c_int32(-1)
+    rc = lib.orc_build_R(n, _ptr(rp), _ptr(ci), _ptr(va), _ptr(cfa), _ptr(Ba), ell, nthreads,
+                         _ptr(Rrp), _ptr(Rci), _ptr(Rva), nnz, ctypes.byref(unc), ctypes.byref(bad))
+    if rc and not (rc == ORC_ERR_SINGULAR and allow_singular):
+        raise OracleError(rc, f"oracle build_R failed ({rc}), bad_row={bad.value}")
+    return dict(row_ptr=Rrp, col_idx=Rci[:nnz], val=Rva[:nnz], n_c=n_c, nnz=nnz,
+                n_uncovered=unc.value, bad_row=bad.value, status=rc)
+
+
+def build_R_problem(p, nthreads=0, B="problem", **kw):
+    """Convenience: oracle R for a problems.Problem."""
+    Bv = p.B if (isinstance(B, str) and B == "problem") else B
+    return build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, Bv, p.ell, nthreads=nthreads, **kw)

@@ -1,0 +1,369 @@
+/*
+ * clair_oracle.c -- plain, slow, FP64 reference implementation of the
+ * constrained l-AIR (C-l-AIR) restriction setup.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the GPU library is
+ * checked against.  It shares no code, header, table or helper with the GPU
+ * path; only tests, the smoke check and the benchmark's CPU-baseline leg may
+ * load it.  Nothing in the product path calls it.
+ *
+ * What it computes (Ali, Brannick, Kahl, Krzysik, Schroder, Southworth,
+ * "Constrained Local Approximate Ideal Restriction for Advection-Diffusion
+ * Problems"):
+ *
+ *   R = [Z I] in reduction form (Section 2, eq. basicsplit), C-points
+ *   injected.  Row i of R (i a C-point) is obtained from Algorithm 1 applied to
+ *   A^T (Section 3.1.3): the pattern of the row is the distance-ell
+ *   F-neighbourhood N(i) of i (Algorithm 1, pattern expansion S^{m-1} T with
+ *   m = ell, theta = 0, interior vertices F), the local l-AIR system is
+ *   (A[N,N])^T z = -A[i,N]^T (Section 2.1, eq. system), and the mode
+ *   constraint R^T B_c = B on the F-points (Section 2.3, eq. global_const1;
+ *   Section 3.1, eq. Qdef) is imposed by the Euclidean projection
+ *   I - Q^T (Q Q^T)^{-1} Q of Algorithm 1 (projection step).
+ *
+ * With exact local inverses and k = 1 (Remark 2) the algorithm reduces to:
+ *   1. z0 = local l-AIR solution of every C-row (Remark 1);
+ *   2. for every F-column j with contributing C-rows I_j:
+ *        d_j = sum_{i in I_j} B_i^2,   r_j = sum_{i in I_j} z0_ij B_i - B_j,
+ *        z_ij = z0_ij - B_i r_j / d_j          (if d_j > 0).
+ *   Q's rows are the F-rows of W = R^T, so Q Q^T is diagonal with entries d_j.
+ *   Columns with d_j = 0 (no C-row reaches them) cannot be constrained; the
+ *   pseudo-inverse leaves them untouched and they are counted as uncovered.
+ *
+ * Everything is FP64.  Local systems are solved by Gaussian elimination with
+ * partial pivoting; a pivot with |pivot| <= 1e-14 * max|block| is reported as
+ * singular.  Rows are independent and may run in parallel (OpenMP); the
+ * projection sums every column in ascending row order, serially.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_ERR_INVALID 1
+#define ORC_ERR_CAPACITY 2
+#define ORC_ERR_SINGULAR 3
+#define ORC_ERR_NOMEM 4
+
+/* ------------------------------------------------------------------------ */
+/* Neighbourhood: the F-points reachable from C-point i by a walk of at most  */
+/* ell edges of A's graph whose interior vertices are all F-points.  An edge  */
+/* u -> v exists when u != v and a_uv is stored and nonzero (strength with    */
+/* theta = 0).  Breadth-first search, expanding F vertices only.              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t* mark;  /* length n, stamp per vertex */
+  int32_t stamp;
+  int32_t* list;  /* growing list of found F-points */
+  int32_t cap;
+} bfs_ws;
+
+static int cmp_i32(const void* a, const void* b) {
+  int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+  return (x > y) - (x < y);
+}
+
+static int ws_push(bfs_ws* w, int32_t len, int32_t v) {
+  if (len >= w->cap) {
+    int32_t nc = w->cap ? 2 * w->cap : 64;
+    int32_t* nl = (int32_t*)realloc(w->list, sizeof(int32_t) * (size_t)nc);
+    if (!nl) return -1;
+    w->list = nl;
+    w->cap = nc;
+  }
+  w->list[len] = v;
+  return 0;
+}
+
+/* Returns s = |N(i)| (>= 0), N(i) sorted ascending in w->list[0..s), or -1 on OOM. */
+static int32_t neighbourhood(int32_t i, int ell, const int32_t* rp, const int32_t* ci,
+                             const double* va, const int8_t* cf, bfs_ws* w) {
+  w->stamp++;
+  w->mark[i] = w->stamp;
+  int32_t len = 0;
+  int32_t lo = 0, hi = 0; /* current frontier = list[lo..hi); level 0 frontier is {i} */
+  for (int depth = 1; depth <= ell; ++depth) {
+    int32_t before = len;
+    if (depth == 1) {
+      for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+        int32_t k = ci[e];
+        if (k == i || va[e] == 0.0 || cf[k] != 0 || w->mark[k] == w->stamp) continue;
+        w->mark[k] = w->stamp;
+        if (ws_push(w, len, k)) return -1;
+        ++len;
+      }
+    } else {
+      for (int32_t t = lo; t < hi; ++t) {
+        int32_t u = w->list[t];
+        for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+          int32_t k = ci[e];
+          if (k == u || va[e] == 0.0 || cf[k] != 0 || w->mark[k] == w->stamp) continue;
+          w->mark[k] = w->stamp;
+          if (ws_push(w, len, k)) return -1;
+          ++len;
+        }
+      }
+    }
+    lo = before;
+    hi = len;
+    if (lo == hi) break;
+  }
+  qsort(w->list, (size_t)len, sizeof(int32_t), cmp_i32);
+  return len;
+}
+
+static int32_t find_sorted(const int32_t* a, int32_t len, int32_t key) {
+  int32_t l = 0, h = len;
+  while (l < h) {
+    int32_t m = (l + h) >> 1;
+    if (a[m] < key) l = m + 1; else h = m;
+  }
+  return (l < len && a[l] == key) ? l : -1;
+}
+
+/* Solve K x = f (K is s x s row-major, overwritten) by Gaussian elimination with
+ * partial pivoting.  Returns 0 on success, 1 if a pivot is negligible. */
+static int gepp_solve(double* K, double* f, int32_t s) {
+  double amax = 0.0;
+  for (int64_t t = 0; t < (int64_t)s * s; ++t) amax = fmax(amax, fabs(K[t]));
+  const double tiny = 1e-14 * amax;
+  for (int32_t k = 0; k < s; ++k) {
+    int32_t p = k;
+    double best = fabs(K[(int64_t)k * s + k]);
+    for (int32_t q = k + 1; q < s; ++q) {
+      double v = fabs(K[(int64_t)q * s + k]);
+      if (v > best) { best = v; p = q; }
+    }
+    if (!(best > tiny)) return 1;
+    if (p != k) {
+      for (int32_t c = 0; c < s; ++c) {
+        double t = K[(int64_t)k * s + c];
+        K[(int64_t)k * s + c] = K[(int64_t)p * s + c];
+        K[(int64_t)p * s + c] = t;
+      }
+      double t = f[k]; f[k] = f[p]; f[p] = t;
+    }
+    double piv = K[(int64_t)k * s + k];
+    for (int32_t q = k + 1; q < s; ++q) {
+      double l = K[(int64_t)q * s + k] / piv;
+      if (l == 0.0) continue;
+      for (int32_t c = k + 1; c < s; ++c) K[(int64_t)q * s + c] -= l * K[(int64_t)k * s + c];
+      f[q] -= l * f[k];
+    }
+  }
+  for (int32_t k = s - 1; k >= 0; --k) {
+    double acc = f[k];
+    for (int32_t c = k + 1; c < s; ++c) acc -= K[(int64_t)k * s + c] * f[c];
+    f[k] = acc / K[(int64_t)k * s + k];
+  }
+  return 0;
+}
+
+static int check_csr(int32_t n, const int32_t* rp, const int32_t* ci) {
+  if (n < 0 || !rp) return 1;
+  if (rp[0] != 0) return 1;
+  for (int32_t r = 0; r < n; ++r) {
+    if (rp[r + 1] < rp[r]) return 1;
+    for (int32_t e = rp[r]; e < rp[r + 1]; ++e) {
+      if (ci[e] < 0 || ci[e] >= n) return 1;
+      if (e > rp[r] && ci[e] <= ci[e - 1]) return 1; /* ascending, no duplicates */
+    }
+  }
+  return 0;
+}
+
+static int set_threads(int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) return nthreads;
+  return omp_get_max_threads();
+#else
+  (void)nthreads;
+  return 1;
+#endif
+}
+
+/* Number of C-points and nnz(R) = sum_i (|N(i)| + 1).  Also the per-row sizes
+ * when `sizes` (length n_c) is given. */
+int orc_pattern_size(int32_t n, const int32_t* rp, const int32_t* ci, const double* va,
+                     const int8_t* cf, int32_t ell, int32_t nthreads, int32_t* n_c_out,
+                     int64_t* nnz_out, int32_t* sizes) {
+  if (ell < 1 || check_csr(n, rp, ci)) return ORC_ERR_INVALID;
+  int32_t n_c = 0;
+  for (int32_t j = 0; j < n; ++j) n_c += (cf[j] != 0);
+  int32_t* clist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_c > 0 ? n_c : 1));
+  if (!clist) return ORC_ERR_NOMEM;
+  for (int32_t j = 0, r = 0; j < n; ++j) if (cf[j]) clist[r++] = j;
+  int64_t total = 0;
+  int err = 0;
+  int nt = set_threads(nthreads);
+#pragma omp parallel num_threads(nt) reduction(+ : total)
+  {
+    bfs_ws w;
+    w.mark = (int32_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+    w.stamp = 0; w.list = NULL; w.cap = 0;
+    if (!w.mark) {
+#pragma omp atomic write
+      err = 1;
+    } else {
+#pragma omp for schedule(static)
+      for (int32_t r = 0; r < n_c; ++r) {
+        int32_t s = neighbourhood(clist[r], ell, rp, ci, va, cf, &w);
+        if (s < 0) {
+#pragma omp atomic write
+          err = 1;
+          continue;
+        }
+        if (sizes) sizes[r] = s;
+        total += s + 1;
+      }
+    }
+    free(w.mark);
+    free(w.list);
+  }
+  free(clist);
+  if (err) return ORC_ERR_NOMEM;
+  *n_c_out = n_c;
+  *nnz_out = total;
+  return ORC_OK;
+}
+
+/*
+ * Build R.  B may be NULL (unconstrained: plain l-AIR rows, Remark 1).
+ * R_rp has n_c+1 entries; R_ci/R_va have `cap` entries.  Statistics (may be
+ * NULL): n_uncovered = F-points with d_j = 0 (only when B is given);
+ * bad_row = fine index of the first C-row whose local block is singular.
+ */
+int orc_build_R(int32_t n, const int32_t* rp, const int32_t* ci, const double* va, const int8_t* cf,
+                const double* B, int32_t ell, int32_t nthreads, int32_t* R_rp, int32_t* R_ci,
+                double* R_va, int64_t cap, int64_t* n_uncovered, int32_t* bad_row) {
+  if (ell < 1 || check_csr(n, rp, ci)) return ORC_ERR_INVALID;
+  int32_t n_c = 0;
+  int64_t nnz = 0;
+  for (int32_t j = 0; j < n; ++j) n_c += (cf[j] != 0);
+  int32_t* sizes = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_c > 0 ? n_c : 1));
+  int32_t* clist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_c > 0 ? n_c : 1));
+  if (!sizes || !clist) { free(sizes); free(clist); return ORC_ERR_NOMEM; }
+  int rc = orc_pattern_size(n, rp, ci, va, cf, ell, nthreads, &n_c, &nnz, sizes);
+  if (rc) { free(sizes); free(clist); return rc; }
+  if (nnz > cap) { free(sizes); free(clist); return ORC_ERR_CAPACITY; }
+  for (int32_t j = 0, r = 0; j < n; ++j) if (cf[j]) clist[r++] = j;
+  R_rp[0] = 0;
+  for (int32_t r = 0; r < n_c; ++r) R_rp[r + 1] = R_rp[r] + sizes[r] + 1;
+
+  /* Step 1: per-row local l-AIR solves, (A[N,N])^T z = -A[i,N]^T. */
+  int32_t first_bad = -1;
+  int err = 0;
+  int nt = set_threads(nthreads);
+#pragma omp parallel num_threads(nt)
+  {
+    bfs_ws w;
+    w.mark = (int32_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int32_t));
+    w.stamp = 0; w.list = NULL; w.cap = 0;
+    double* K = NULL;
+    double* f = NULL;
+    int64_t kcap = 0;
+    if (!w.mark) {
+#pragma omp atomic write
+      err = 1;
+    } else {
+#pragma omp for schedule(dynamic, 64)
+      for (int32_t r = 0; r < n_c; ++r) {
+        int32_t i = clist[r];
+        int32_t s = neighbourhood(i, ell, rp, ci, va, cf, &w);
+        if (s < 0) {
+#pragma omp atomic write
+          err = 1;
+          continue;
+        }
+        if ((int64_t)s * s > kcap || !K) {
+          kcap = (int64_t)s * s + 64;
+          free(K); free(f);
+          K = (double*)malloc(sizeof(double) * (size_t)kcap);
+          f = (double*)malloc(sizeof(double) * (size_t)(s + 8));
+          if (!K || !f) {
+#pragma omp atomic write
+            err = 1;
+            kcap = 0;
+            continue;
+          }
+        }
+        const int32_t* N = w.list;
+        /* K = (A[N,N])^T : K[q][p] = a_{N_p, N_q};  f = -A[i, N]. */
+        memset(K, 0, sizeof(double) * (size_t)s * (size_t)s);
+        for (int32_t p = 0; p < s; ++p) {
+          int32_t row = N[p];
+          for (int32_t e = rp[row]; e < rp[row + 1]; ++e) {
+            int32_t q = find_sorted(N, s, ci[e]);
+            if (q >= 0) K[(int64_t)q * s + p] = va[e];
+          }
+        }
+        for (int32_t q = 0; q < s; ++q) f[q] = 0.0;
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+          int32_t q = find_sorted(N, s, ci[e]);
+          if (q >= 0) f[q] = -va[e];
+        }
+        if (s > 0 && gepp_solve(K, f, s)) {
+#pragma omp critical
+          {
+            if (first_bad < 0 || i < first_bad) first_bad = i;
+          }
+          for (int32_t q = 0; q < s; ++q) f[q] = 0.0;
+        }
+        /* Row r of R: the F-entries of N(i) and the injected C-point i (= 1). */
+        int32_t pos = R_rp[r];
+        int inserted = 0;
+        for (int32_t p = 0; p < s; ++p) {
+          if (!inserted && i < N[p]) { R_ci[pos] = i; R_va[pos] = 1.0; ++pos; inserted = 1; }
+          R_ci[pos] = N[p]; R_va[pos] = f[p]; ++pos;
+        }
+        if (!inserted) { R_ci[pos] = i; R_va[pos] = 1.0; ++pos; }
+      }
+    }
+    free(K); free(f); free(w.mark); free(w.list);
+  }
+  free(sizes);
+  if (err) { free(clist); return ORC_ERR_NOMEM; }
+  if (bad_row) *bad_row = first_bad;
+
+  /* Step 2: Euclidean projection onto {Q w = B|_F}, column by column. */
+  int64_t uncovered = 0;
+  if (B) {
+    double* d = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    double* rs = (double*)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+    if (!d || !rs) { free(d); free(rs); free(clist); return ORC_ERR_NOMEM; }
+    for (int32_t r = 0; r < n_c; ++r) {
+      double bi = B[clist[r]];
+      for (int32_t e = R_rp[r]; e < R_rp[r + 1]; ++e) {
+        int32_t j = R_ci[e];
+        if (j == clist[r]) continue;
+        d[j] += bi * bi;
+        rs[j] += R_va[e] * bi;
+      }
+    }
+    for (int32_t j = 0; j < n; ++j) {
+      if (cf[j]) continue;
+      if (d[j] > 0.0) rs[j] -= B[j]; else ++uncovered;
+    }
+    for (int32_t r = 0; r < n_c; ++r) {
+      double bi = B[clist[r]];
+      for (int32_t e = R_rp[r]; e < R_rp[r + 1]; ++e) {
+        int32_t j = R_ci[e];
+        if (j == clist[r] || !(d[j] > 0.0)) continue;
+        R_va[e] -= bi * rs[j] / d[j];
+      }
+    }
+    free(d);
+    free(rs);
+  }
+  if (n_uncovered) *n_uncovered = uncovered;
+  free(clist);
+  return first_bad >= 0 ? ORC_ERR_SINGULAR : ORC_OK;
+}
+
+int orc_max_threads(void) { return set_threads(0); }

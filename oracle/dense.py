@@ -1,0 +1,88 @@
+"""Dense brute force on tiny inputs -- TEST INFRASTRUCTURE ONLY.
+
+Everything here is formulated with dense NumPy arrays so that it is an
+independent check of the C oracle:
+
+* ``neighbourhoods``: the distance-ell F-neighbourhood of every C-point by
+  boolean reachability (no queue, no visited marks).  N_1(i) is the F-part of
+  row i's off-diagonal nonzeros (theta = 0 strength, the base pattern
+  T = [S_fc, I] of Algorithm 1 applied to A^T); each further hop multiplies the
+  current F-set by the adjacency matrix and keeps only F-points, which is the
+  pattern expansion S^{m-1} T with F-point interior vertices.
+* ``lair_rows``: per-row local l-AIR solves (Section 2.1, eq. system) with
+  ``numpy.linalg.solve``; Remark 1 says the unconstrained algorithm returns
+  exactly these rows.
+* ``r_ideal``: the ideal restriction [-A_cf A_ff^{-1}, I] (Section 2.1,
+  eq. r_ideal) by a dense solve.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def to_dense(n, row_ptr, col_idx, val):
+    A = np.zeros((n, n))
+    for r in range(n):
+        for e in range(row_ptr[r], row_ptr[r + 1]):
+            A[r, col_idx[e]] = val[e]
+    return A
+
+
+def neighbourhoods(A: np.ndarray, cf: np.ndarray, ell: int):
+    """dict C-point -> sorted array of its distance-ell F-neighbourhood."""
+    n = A.shape[0]
+    adj = (A != 0) & ~np.eye(n, dtype=bool)
+    F = cf == 0
+    out = {}
+    for i in np.nonzero(cf != 0)[0]:
+        reach = adj[i] & F
+        for _ in range(ell - 1):
+            reach = reach | ((reach.astype(np.int64) @ adj.astype(np.int64)) > 0) & F
+        out[int(i)] = np.nonzero(reach)[0]
+    return out
+
+
+def lair_rows(A: np.ndarray, cf: np.ndarray, ell: int):
+    """Unconstrained rows: dict C-point -> (N, z) with (A[N,N])^T z = -A[i,N]^T."""
+    nb = neighbourhoods(A, cf, ell)
+    rows = {}
+    for i, N in nb.items():
+        if len(N) == 0:
+            rows[i] = (N, np.zeros(0))
+            continue
+        M = A[np.ix_(N, N)]
+        a = A[i, N]
+        rows[i] = (N, np.linalg.solve(M.T, -a))
+    return rows
+
+
+def rows_to_dense_R(rows, cf, n):
+    C = np.nonzero(cf != 0)[0]
+    R = np.zeros((len(C), n))
+    for r, i in enumerate(C):
+        N, z = rows[int(i)]
+        R[r, N] = z
+        R[r, i] = 1.0
+    return R
+
+
+def r_ideal(A: np.ndarray, cf: np.ndarray) -> np.ndarray:
+    """R_ideal = [-A_cf A_ff^{-1}, I], returned in the natural (unpermuted) column order."""
+    C = np.nonzero(cf != 0)[0]
+    F = np.nonzero(cf == 0)[0]
+    Acf = A[np.ix_(C, F)]
+    Aff = A[np.ix_(F, F)]
+    Z = np.linalg.solve(Aff.T, -Acf.T).T
+    R = np.zeros((len(C), A.shape[0]))
+    R[:, F] = Z
+    R[np.arange(len(C)), C] = 1.0
+    return R
+
+
+def csr_to_dense_R(Rrp, Rci, Rva, n):
+    m = len(Rrp) - 1
+    R = np.zeros((m, n))
+    for r in range(m):
+        for e in range(Rrp[r], Rrp[r + 1]):
+            R[r, Rci[e]] = Rva[e]
+    return R

@@ -1,0 +1,92 @@
+"""Algorithm 1 (C-l-AIR) carried out step by step -- TEST INFRASTRUCTURE ONLY.
+
+Follows Section 3.1.3 in the paper's order, applied to A^T to obtain R
+(Section 3.1.3: restriction is Algorithm 1 on the transpose), with every
+operator formed explicitly as a dense matrix on tiny problems:
+
+1. tentative operator W^t = -A_fc of A^T, i.e. W^t[f, c] = -a_{c f}, stored
+   on the expanded pattern (possibly zero entries);
+2. constraint fit: every F-row of W^t is replaced by the minimum-norm
+   (pseudo-inverse) solution of  w B_c|_pattern = B_f;
+3. exact block inverses of the local blocks A_ff^{(c)} of A^T;
+4. k iterations of: residual update  w_bar = A_ff^{-1}(-a_fc - A_ff w^t);
+   projection  w_bar <- (I - Q^T (Q Q^T)^+ Q) w_bar  with Q assembled entry by
+   entry from B_c (Section 3.1, eq. Qdef) and the pseudo-inverse of Q Q^T;
+   update  w^t <- w^t + w_bar.
+
+Remark 2 says the result does not change for k > 1 when the inverses are
+exact; the tests check that, and that the result equals the closed form the
+C oracle evaluates.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import dense
+
+
+def algorithm1_R(A: np.ndarray, cf: np.ndarray, B: np.ndarray, ell: int, k: int = 1,
+                 fit_constraint: bool = True):
+    """Dense R (n_c x n) from the literal Algorithm 1 on A^T."""
+    n = A.shape[0]
+    At = A.T
+    C = [int(i) for i in np.nonzero(cf != 0)[0]]
+    nb = dense.neighbourhoods(A, cf, ell)  # pattern of row c of R == column c of W(A^T)
+    # stacked unknown vector w*: the nonzeros of W in compressed-column order
+    slots = []  # (c, f)
+    col_start = {}
+    for c in C:
+        col_start[c] = len(slots)
+        for f in nb[c]:
+            slots.append((c, int(f)))
+    nw = len(slots)
+    Bc = {c: B[c] for c in C}
+
+    # 1. tentative operator [-A_fc, I] of A^T on the expanded pattern
+    wt = np.array([-At[f, c] for (c, f) in slots], dtype=np.float64)
+
+    # Q: one row per F-point f, entries B_c at the slots (c, f)
+    F = [int(f) for f in np.nonzero(cf == 0)[0]]
+    frow = {f: r for r, f in enumerate(F)}
+    Q = np.zeros((len(F), nw))
+    for s, (c, f) in enumerate(slots):
+        Q[frow[f], s] = Bc[c]
+    BF = np.array([B[f] for f in F])
+
+    # 2. enforce Q w^t = B|_F row by row: minimum-norm fit of each F-row
+    if fit_constraint:
+        for f in F:
+            idx = [s for s in range(nw) if slots[s][1] == f]
+            if not idx:
+                continue
+            bvec = np.array([Bc[slots[s][0]] for s in idx])
+            wt[idx] = np.linalg.pinv(bvec[None, :]) @ np.array([B[f]])
+
+    # 3. exact block inverses of A_ff^{(c)} (of A^T)
+    blocks = {}
+    for c in C:
+        N = nb[c]
+        blocks[c] = At[np.ix_(N, N)]
+
+    P = np.eye(nw) - Q.T @ np.linalg.pinv(Q @ Q.T) @ Q
+    for _ in range(k):
+        wbar = np.zeros(nw)
+        for c in C:
+            N = nb[c]
+            if len(N) == 0:
+                continue
+            s0 = col_start[c]
+            w_c = wt[s0:s0 + len(N)]
+            a_fc = At[N, c]
+            res = -a_fc - blocks[c] @ w_c
+            wbar[s0:s0 + len(N)] = np.linalg.solve(blocks[c], res)
+        wbar = P @ wbar
+        wt = wt + wbar
+
+    R = np.zeros((len(C), n))
+    for r, c in enumerate(C):
+        N = nb[c]
+        s0 = col_start[c]
+        R[r, N] = wt[s0:s0 + len(N)]
+        R[r, c] = 1.0
+    return R
