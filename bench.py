@@ -1,0 +1,292 @@
+#!/usr/bin/env python3
+"""Benchmark: C-l-AIR restriction setup, R rows per second, on one GPU.
+
+One step = the whole setup (neighbourhood search, C/F indexing, block gather,
+FP32 factorisation + FP64 refinement, R write, constraint projection) for
+every matrix of the workload, inputs resident in HBM.  Default workload: three
+512x512 5-point upwind advection-diffusion matrices (eps = 1e-6, 1e-2, 1),
+C-points every 2nd node, ell = 2, B = 1, set up in one batched pass.
+
+Prints one JSON line.  Besides the contract fields it carries
+* the plain FP64 per-row form measured on the same inputs and the ratio;
+* accuracy gates of the measured result against the FP64 oracle;
+* "roofline" for the dominant kernel (HIP events on the library's stream);
+* "cpu_baseline": the oracle on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "R rows/sec (CℓAIR setup), mixed+batched vs FP64 plain, at ≤1e-10 row error"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "cfg2": "3x 512^2 5-pt upwind adv-diff, eps in {1e-6,1e-2,1}, b=(cos pi/6, sin pi/6), C every 2nd node, ell=2, B=1",
+    "cfg1": "32^2 5-pt upwind adv-diff, eps=0.1, C=(even,even), ell=1, B=1",
+    "cfg3": "2048^2 9-pt upwind recirculating flow, eps=1e-4, C every 3rd node, ell=2, B=1",
+    "cfg4": "64x 5-pt upwind adv-diff, sides U{64..768}, eps 10^U(-6,0), random angle, ell U{1,2}, seed 0, B=1",
+    "cfg5": "128^3 7-pt upwind adv-diff, eps=1e-3, b=(1,.5,.25)/|b|, C every 2nd node, ell=2, B=1",
+}
+
+
+def make_problems(name):
+    from paper_2307_00229_amd import problems as P
+
+    return {"cfg1": lambda: [P.cfg1()], "cfg2": P.cfg2, "cfg3": lambda: [P.cfg3()], "cfg4": P.cfg4,
+            "cfg5": lambda: [P.cfg5()]}[name]()
+
+
+def algorithmic_bytes(problems, n_c_list, nnz_list):
+    """Bytes every implementation must move once: A's CSR, cf, B, R's CSR."""
+    whole, kernel = 0, 0
+    for p, n_c, nnz in zip(problems, n_c_list, nnz_list):
+        a = 4 * (p.n + 1) + 12 * p.nnz
+        r = 4 * (n_c + 1) + 12 * nnz
+        whole += a + p.n + 8 * p.n + r
+        # the numeric kernel reads A once, the C/F marker and B at the C-points,
+        # and writes R once
+        kernel += a + p.n + 8 * n_c + r
+    return whole, kernel
+
+
+def read_traffic_profile(workload, kernel_src_hash):
+    """Counter bytes per launch of the numeric kernel from a committed rocprofv3
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"k_numeric_{workload}_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_src_sha256") != kernel_src_hash:
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for fn in ("k_mixed.hip", "clair_device.h"):
+        with open(os.path.join(ROOT, "paper_2307_00229_amd", "csrc", fn), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def cpu_baseline(problems, budget_s):
+    import oracle
+
+    nthreads = oracle.max_threads()
+    rows = 0
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        for p in problems:
+            o = oracle.build_R_problem(p)
+            rows += o["n_c"]
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return dict(value=rows / el, unit="rows/s", cores=nthreads, kind="oracle",
+                sample=f"full workload x{reps} ({rows} R rows, {el:.1f} s, OpenMP over rows)")
+
+
+def check_against_oracle(problems, outs):
+    import numpy as np
+
+    import oracle
+
+    worst_row, worst_c = 0.0, 0.0
+    for p, o in zip(problems, outs):
+        rp, ci, va = (t.cpu().numpy() for t in o.trimmed())
+        ref = oracle.build_R_problem(p)
+        if not (np.array_equal(rp, ref["row_ptr"]) and np.array_equal(ci, ref["col_idx"])):
+            return dict(pattern_identical=False)
+        C = np.nonzero(p.cf)[0]
+        rows = np.repeat(np.arange(ref["n_c"]), np.diff(ref["row_ptr"]))
+        fm = ci != C[rows]
+        diff = np.zeros(ref["n_c"])
+        scale = np.zeros(ref["n_c"])
+        np.maximum.at(diff, rows[fm], np.abs(va[fm] - ref["val"][fm]))
+        np.maximum.at(scale, rows[fm], np.abs(ref["val"][fm]))
+        ok = scale > 0
+        if ok.any():
+            worst_row = max(worst_row, float(np.max(diff[ok] / scale[ok])))
+        if p.B is not None:
+            terms = va[fm] * p.B[C[rows[fm]]]
+            colsum = np.zeros(p.n)
+            colabs = np.zeros(p.n)
+            np.add.at(colsum, ci[fm], terms)
+            np.add.at(colabs, ci[fm], np.abs(terms))
+            cov = np.zeros(p.n, bool)
+            cov[ci[fm]] = True
+            Fc = cov & (p.cf == 0)
+            if Fc.any():
+                rel = np.abs(colsum[Fc] - p.B[Fc]) / (np.abs(p.B[Fc]) + colabs[Fc])
+                worst_c = max(worst_c, float(np.max(rel)))
+    return dict(pattern_identical=True, max_row_rel_err=worst_row, max_constraint_resid=worst_c)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
+    ap.add_argument("--plain-steps", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--mode", choices=["graph", "direct", "best"], default="best")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the multi-GPU "
+              "sharding is described in DESIGN.md and is not run.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2307_00229_amd import clair
+
+    assert torch.cuda.is_available(), "needs a GPU"
+    torch.cuda.set_device(0)
+    dev = "cuda:0"
+    problems = make_problems(args.workload)
+    As = [clair.CSR.from_problem(p, dev) for p in problems]
+    cfs = [torch.from_numpy(p.cf).to(dev) for p in problems]
+    Bs = [torch.from_numpy(p.B).to(dev) for p in problems]
+    ells = [p.ell for p in problems]
+    stream = torch.cuda.Stream()
+    ctx = clair.Context()
+    with torch.cuda.stream(stream):
+        n_c_list, nnz_list = clair.clair_size_R(As, cfs, ells, ctx=ctx, stream=stream)
+        outs = [clair.ROut(nc, nz, dev) for nc, nz in zip(n_c_list, nnz_list)]
+        if not args.no_autotune:
+            clair.clair_autotune(ctx, As, cfs, Bs, ells, outs, reps=3, stream=stream)
+        tuning = ctx.get_tuning()
+        rows = sum(n_c_list)
+
+        direct_step = clair.BatchedCall(ctx, As, cfs, Bs, ells, outs, async_=True, stream=stream)
+
+        graph, graph_error = None, None
+        try:
+            graph = clair.Graph(ctx, As, cfs, Bs, ells, outs, stream=stream)
+        except clair.ClairError as e:
+            graph_error = str(e)
+            print(f"graph capture unavailable: {e}", file=sys.stderr)
+
+        def graph_step():
+            graph.launch(stream)
+
+        def timed(step, k, w):
+            for _ in range(w):
+                step()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record(stream)
+            for _ in range(k):
+                step()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            return max(e0.elapsed_time(e1) / 1e3, 1e-12), wall
+
+        modes = {"graph": graph_step, "direct": direct_step}
+        results = {}
+        names = ["graph", "direct"] if args.mode == "best" else [args.mode]
+        if graph is None:
+            names = [n for n in names if n != "graph"] or ["direct"]
+        for name in names:
+            dev_s, wall_s = timed(modes[name], args.steps, args.warmup)
+            results[name] = dict(dev_s=dev_s, wall_s=wall_s)
+        best = min(results, key=lambda k: results[k]["wall_s"])
+        t_mixed = results[best]["wall_s"] / args.steps
+        # status of the measured runs
+        st, infos = graph.info() if best == "graph" else ctx.info(len(problems), outs)
+        assert st == 0, infos
+
+        # dominant kernel: per-stage HIP events on the library's stream
+        ctx.stage_times()
+        timed_step = clair.BatchedCall(ctx, As, cfs, Bs, ells, outs, async_=True, timing=True, stream=stream)
+        for _ in range(args.steps):
+            timed_step()
+        torch.cuda.synchronize()
+        stages = {k: v / args.steps for k, v in ctx.stage_times().items()}
+
+        # plain FP64 per-row form on the same inputs
+        plain_ctx = clair.Context()
+        outs_p = [clair.ROut(nc, nz, dev) for nc, nz in zip(n_c_list, nnz_list)]
+
+        plain_step = clair.BatchedCall(plain_ctx, As, cfs, Bs, ells, outs_p, precision=clair.CLAIR_PREC_FP64,
+                                       async_=False, stream=stream)
+
+        p_dev, p_wall = timed(plain_step, args.plain_steps, 2)
+        t_plain = p_wall / args.plain_steps
+
+        if args.copy_probe_mib:
+            x = torch.empty(args.copy_probe_mib * 2 ** 20 // 4, dtype=torch.float32, device=dev).fill_(1.0)
+            y = torch.empty_like(x)
+            torch.cuda.synchronize()
+            y.copy_(x)
+            torch.cuda.synchronize()
+
+    gates = check_against_oracle(problems, outs)
+    gates_plain = check_against_oracle(problems, outs_p)
+
+    whole_bytes, kern_bytes = algorithmic_bytes(problems, n_c_list, nnz_list)
+    t_kern = stages.get("numeric", float("nan")) / 1e3
+    achieved = kern_bytes / t_kern / 1e9 if t_kern > 0 else None
+    src_hash = kernel_source_hash()
+    traffic = read_traffic_profile(args.workload, src_hash)
+    roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=(achieved / HBM_PEAK_GBS) if achieved else None, traffic=traffic,
+                    kernel="k_numeric", kernel_ms=t_kern * 1e3, algorithmic_bytes_per_launch=kern_bytes,
+                    step_GBps=whole_bytes / t_mixed / 1e9, stage_ms=stages)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(problems, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": rows / t_mixed,
+        "unit": "rows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_mixed * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "matrices": len(problems),
+                   "R_rows": rows, "nnz_R": int(sum(nnz_list)), "launch": best, "tuning": tuning,
+                   "parallelism": "single GPU"},
+        "plain_fp64": {"value": rows / t_plain, "unit": "rows/s", "ms_per_step": t_plain * 1e3,
+                       "gates": gates_plain},
+        "speedup_vs_plain_fp64": t_plain / t_mixed,
+        "modes_ms_per_step": {k: v["wall_s"] / args.steps * 1e3 for k, v in results.items()},
+        "graph_error": graph_error,
+        "gates": gates,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

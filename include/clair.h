@@ -1,0 +1,211 @@
+/*
+ * clair.h -- C ABI of libclair: the restriction setup of constrained l-AIR
+ * (C-l-AIR) on AMD Instinct MI355X (gfx950).
+ *
+ * Method (Ali, Brannick, Kahl, Krzysik, Schroder, Southworth, "Constrained
+ * Local Approximate Ideal Restriction for Advection-Diffusion Problems"):
+ *
+ *   R = [Z I] in reduction form (Section 2, eq. basicsplit): one row per
+ *   C-point, the C-point itself injected with weight 1.  Row i is built by
+ *   Algorithm 1 applied to A^T (Section 3.1.3) with exact local inverses, for
+ *   which one iteration suffices (Remark 2):
+ *
+ *   1. pattern: N(i) = F-points reachable from C-point i by a walk of at most
+ *      `ell` edges of A's graph whose interior vertices are F-points (the
+ *      sparsity pattern (S^{m-1} T)|_F of Algorithm 1 with m = ell, classical
+ *      strength with threshold 0, i.e. every stored nonzero off-diagonal entry
+ *      is an edge);
+ *   2. local l-AIR system (Section 2.1, eq. system):
+ *      (A[N,N])^T z = -A[i,N]^T;
+ *   3. mode constraint R^T B_c = B on the F-points (Section 2.3,
+ *      eq. global_const1 and Section 3.1, eq. Qdef) imposed by the Euclidean
+ *      projection I - Q^T (Q Q^T)^{-1} Q of Algorithm 1.  Q Q^T is diagonal:
+ *      for F-column j with contributing rows I_j,
+ *        d_j = sum_{i in I_j} B_i^2,  r_j = sum_{i in I_j} z_ij B_i - B_j,
+ *        z_ij <- z_ij - B_i r_j / d_j.
+ *      Columns no row reaches (d_j = 0) are left alone and counted as
+ *      "uncovered".  B = NULL skips step 3: the rows are plain l-AIR (Remark 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All array pointers are DEVICE pointers (memory of the current HIP device),
+ *   owned by the caller.  Inputs are read only.  The library never frees or
+ *   reallocates caller memory.
+ * - A is square n x n CSR with int32 indices: row_ptr[n+1] (row_ptr[0] = 0),
+ *   col_idx[nnz] strictly ascending within each row (no duplicates), val[nnz]
+ *   float64.  A stored zero is not an edge.
+ * - cf_marker: int8[n], nonzero = C-point, 0 = F-point.
+ * - R (output) is n_c x n CSR, n_c = number of C-points.  Row r belongs to the
+ *   r-th C-point in ascending fine index.  Column indices are fine indices,
+ *   ascending within each row; the C-point's own column holds exactly 1.0.
+ *   row_ptr must hold n_c + 1 entries; col_idx and val must hold nnz(R).
+ * - Precision: CLAIR_PREC_MIXED (default) gathers the local blocks and
+ *   factorises them in FP32 and refines the solution with FP64 residuals
+ *   until the FP64 backward error is at rounding level; the projection is
+ *   FP64.  Rows whose FP32 factorisation is unreliable are redone in FP64.
+ *   CLAIR_PREC_FP64 is the plain per-row FP64 form (one thread per row, one
+ *   kernel per stage, one matrix at a time).
+ * - Errors: every entry point returns a clair_status (0 = CLAIR_OK).  Nothing
+ *   aborts and no C++ exception crosses the ABI.  Per-matrix details land in
+ *   clair_info_t.
+ * - Thread safety: one clair_ctx_t must not be used by two host threads at
+ *   once.  Different contexts are independent.
+ */
+#ifndef CLAIR_H
+#define CLAIR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum clair_status {
+  CLAIR_OK = 0,
+  CLAIR_ERR_INVALID = 1,     /* bad argument, unsorted/duplicate CSR, ell < 1, ... */
+  CLAIR_ERR_CAPACITY = 2,    /* R does not fit: required sizes are in clair_info_t / R_out */
+  CLAIR_ERR_SINGULAR = 3,    /* a local block is singular (first fine row in info.first_bad_row) */
+  CLAIR_ERR_HIP = 4,         /* a HIP runtime call failed */
+  CLAIR_ERR_UNSUPPORTED = 5, /* a neighbourhood exceeds CLAIR_MAX_BLOCK */
+  CLAIR_ERR_NOMEM = 6        /* workspace allocation failed */
+} clair_status;
+
+enum { CLAIR_PREC_MIXED = 0, CLAIR_PREC_FP64 = 1 };
+
+/* Largest local block (|N(i)|) any path accepts. */
+#define CLAIR_MAX_BLOCK 1024
+
+/* Input matrix.  Device pointers; see conventions above. */
+typedef struct clair_csr {
+  int32_t n;
+  int32_t nnz;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const double* val;
+} clair_csr_t;
+
+/* Output restriction.  Capacities are inputs; sizes are outputs. */
+typedef struct clair_csr_out {
+  int32_t n_rows;        /* out: n_c */
+  int32_t n_cols;        /* out: n */
+  int64_t nnz;           /* out: nnz(R), also reported with CLAIR_ERR_CAPACITY */
+  int32_t row_capacity;  /* in: entries available in row_ptr (needs n_c + 1) */
+  int32_t pad_;
+  int64_t nnz_capacity;  /* in: entries available in col_idx and val */
+  int32_t* row_ptr;      /* device */
+  int32_t* col_idx;      /* device */
+  double* val;           /* device */
+} clair_csr_out_t;
+
+/* Per-matrix result details. */
+typedef struct clair_info {
+  int32_t status;           /* clair_status of this matrix */
+  int32_t first_bad_row;    /* fine index of a singular / oversized row, or -1 */
+  int32_t n_c;              /* number of C-points (rows of R) */
+  int32_t max_block;        /* largest |N(i)| */
+  int64_t nnz;              /* nnz(R) */
+  int64_t n_uncovered;      /* F-points no row reaches (only when B != NULL) */
+  int32_t refine_iters_max; /* most FP64 refinement steps any row needed (mixed) */
+  int32_t n_fp64_rows;      /* rows solved by the FP64 fallback (mixed) */
+} clair_info_t;
+
+/* Options for the _ex entry points.  Zero-initialised = defaults. */
+typedef struct clair_opts {
+  void* stream;       /* hipStream_t to run on; NULL = null stream */
+  int32_t precision;  /* CLAIR_PREC_MIXED (0) or CLAIR_PREC_FP64 (1) */
+  int32_t async;      /* 1: only enqueue; read results later with clair_ctx_info */
+  int32_t validate;   /* 1: check CSR order / index range on the device first */
+  int32_t timing;     /* 1: record per-stage HIP events (see clair_ctx_stage_times) */
+} clair_opts_t;
+
+/* Opaque library context: owns device workspace and a pinned staging area. */
+typedef struct clair_ctx clair_ctx_t;
+
+/* Create a context on the current HIP device.  Returns CLAIR_ERR_HIP if no
+ * device is usable. */
+int clair_ctx_create(clair_ctx_t** ctx);
+void clair_ctx_destroy(clair_ctx_t* ctx);
+
+/*
+ * clair_build_R -- one matrix, synchronous, mixed precision, library-owned
+ * default context of the current device, null stream.
+ *   A          input matrix (device arrays)
+ *   cf_marker  device int8[n]
+ *   B          device float64[n] constraint vector, or NULL (plain l-AIR rows)
+ *   ell        pattern degree m of Algorithm 1, >= 1
+ *   R_out      capacities in, sizes out.  If the capacities are too small
+ *              (or col_idx == NULL) nothing is written except the sizes and
+ *              CLAIR_ERR_CAPACITY is returned: a size query.
+ */
+int clair_build_R(const clair_csr_t* A, const int8_t* cf_marker, const double* B, int32_t ell,
+                  clair_csr_out_t* R_out);
+
+/* Same for one matrix with explicit context, options and info (info may be NULL). */
+int clair_build_R_ex(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_marker,
+                     const double* B, int32_t ell, clair_csr_out_t* R_out, const clair_opts_t* opts,
+                     clair_info_t* info);
+
+/*
+ * clair_build_R_batched -- nmat independent setups in one pass: every stage
+ * is one kernel launch over the rows of all matrices.  Arrays of length nmat:
+ * A[k], cf[k], B[k] (entries may be NULL), ell[k], R_out[k], info[k] (info may
+ * be NULL).  Equivalent to nmat calls of clair_build_R_ex.  The return value
+ * is the first non-OK per-matrix status (CLAIR_OK if all succeeded).
+ * With opts->async = 1 the call only enqueues work on opts->stream (no host
+ * synchronisation, so it can be captured into a hipGraph); R_out sizes and
+ * info are then obtained with clair_ctx_info after the stream has finished.
+ * In async mode the capacities must already be large enough: a matrix that
+ * does not fit reports CLAIR_ERR_CAPACITY in its info and its R is not written.
+ */
+int clair_build_R_batched(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* A,
+                          const int8_t* const* cf_marker, const double* const* B, const int32_t* ell,
+                          clair_csr_out_t* R_out, const clair_opts_t* opts, clair_info_t* info);
+
+/* Results of the last call on ctx (synchronises its stream).  Fills nmat info
+ * entries and the sizes in R_out (may be NULL).  Returns the first non-OK status. */
+int clair_ctx_info(clair_ctx_t* ctx, int32_t nmat, clair_csr_out_t* R_out, clair_info_t* info);
+
+/* Sizes only (symbolic phase, synchronous): n_c and nnz(R) of each matrix. */
+int clair_size_R(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf_marker,
+                 const int32_t* ell, int32_t* n_c, int64_t* nnz, void* stream);
+
+/* Per-stage device time of the last call made with opts.timing = 1, in ms.
+ * names/ms arrays of length cap; returns the number of stages written. */
+int clair_ctx_stage_times(clair_ctx_t* ctx, const char** names, float* ms, int32_t cap);
+
+/*
+ * Tuning: kernel shape of the mixed path.  group = lanes per row (8, 16 or 32;
+ * rows with larger blocks go to the workgroup-per-row path), rows_per_wg
+ * scales the workgroup, chunk = fine points per workgroup in the symbolic
+ * pass.  0 keeps the current value.  clair_autotune picks them by timing
+ * candidates on the given inputs (and stores the result in ctx).
+ */
+int clair_ctx_set_tuning(clair_ctx_t* ctx, int32_t group, int32_t wg_threads, int32_t chunk);
+int clair_ctx_get_tuning(clair_ctx_t* ctx, int32_t* group, int32_t* wg_threads, int32_t* chunk);
+int clair_autotune(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf_marker,
+                   const double* const* B, const int32_t* ell, clair_csr_out_t* R_out, void* stream,
+                   int32_t reps);
+
+/* hipGraph replay of a batched setup on fixed buffers (values of A and B may
+ * change between launches; the pattern may change as long as R still fits).
+ * clair_graph_create captures clair_build_R_batched (async) on `stream`. */
+typedef struct clair_graph clair_graph_t;
+int clair_graph_create(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* A,
+                       const int8_t* const* cf_marker, const double* const* B, const int32_t* ell,
+                       clair_csr_out_t* R_out, void* stream, clair_graph_t** graph);
+int clair_graph_launch(clair_graph_t* graph, void* stream);
+void clair_graph_destroy(clair_graph_t* graph);
+/* Results of the last launch of `graph` (synchronises its stream), as clair_ctx_info. */
+int clair_graph_info(clair_graph_t* graph, int32_t nmat, clair_csr_out_t* R_out, clair_info_t* info);
+
+const char* clair_strerror(int status);
+
+/* Text of the last HIP failure seen by this host thread inside the library
+ * (empty if none): the failing call and the runtime's message. */
+const char* clair_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CLAIR_H */

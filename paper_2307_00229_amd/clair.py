@@ -1,0 +1,384 @@
+"""Thin ctypes binding of libclair (include/clair.h).
+
+Argument marshalling only: every step of the setup runs in the HIP kernels of
+``libclair.so``.  PyTorch supplies device memory (outputs are allocated as
+torch tensors) and streams.  The library must be built
+(``python -m paper_2307_00229_amd.build``); importing this module without it
+raises, and there is no CPU fallback.
+
+Names mirror the C ABI: ``clair_build_R``, ``clair_build_R_batched``,
+``clair_size_R``, ``clair_autotune``; ``Context`` and ``Graph`` wrap
+``clair_ctx_*`` and ``clair_graph_*``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libclair.so")
+
+CLAIR_OK, CLAIR_ERR_INVALID, CLAIR_ERR_CAPACITY, CLAIR_ERR_SINGULAR = 0, 1, 2, 3
+CLAIR_ERR_HIP, CLAIR_ERR_UNSUPPORTED, CLAIR_ERR_NOMEM = 4, 5, 6
+CLAIR_PREC_MIXED, CLAIR_PREC_FP64 = 0, 1
+CLAIR_MAX_BLOCK = 1024
+
+EXPORTED = [
+    "clair_ctx_create", "clair_ctx_destroy", "clair_build_R", "clair_build_R_ex", "clair_build_R_batched",
+    "clair_ctx_info", "clair_size_R", "clair_ctx_stage_times", "clair_ctx_set_tuning", "clair_ctx_get_tuning",
+    "clair_autotune", "clair_graph_create", "clair_graph_launch", "clair_graph_destroy", "clair_graph_info",
+    "clair_strerror", "clair_last_error",
+]
+
+
+class CsrIn(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int32), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class CsrOut(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int32), ("n_cols", ctypes.c_int32), ("nnz", ctypes.c_int64),
+                ("row_capacity", ctypes.c_int32), ("pad_", ctypes.c_int32), ("nnz_capacity", ctypes.c_int64),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("first_bad_row", ctypes.c_int32), ("n_c", ctypes.c_int32),
+                ("max_block", ctypes.c_int32), ("nnz", ctypes.c_int64), ("n_uncovered", ctypes.c_int64),
+                ("refine_iters_max", ctypes.c_int32), ("n_fp64_rows", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_void_p), ("precision", ctypes.c_int32), ("async_", ctypes.c_int32),
+                ("validate", ctypes.c_int32), ("timing", ctypes.c_int32)]
+
+
+class ClairError(RuntimeError):
+    def __init__(self, status: int, msg: str = ""):
+        self.status = status
+        detail = ""
+        if status == CLAIR_ERR_HIP and _lib is not None:
+            detail = " [" + _lib.clair_last_error().decode() + "]"
+        super().__init__(f"{strerror(status)} (status {status}){': ' + msg if msg else ''}{detail}")
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libclair.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libclair.so not built ({path}); run `python -m paper_2307_00229_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "clair_ctx_create": ([ctypes.POINTER(P)], ctypes.c_int),
+        "clair_ctx_destroy": ([P], None),
+        "clair_build_R": ([ctypes.POINTER(CsrIn), P, P, I32, ctypes.POINTER(CsrOut)], ctypes.c_int),
+        "clair_build_R_ex": ([P, ctypes.POINTER(CsrIn), P, P, I32, ctypes.POINTER(CsrOut), ctypes.POINTER(Opts),
+                              ctypes.POINTER(Info)], ctypes.c_int),
+        "clair_build_R_batched": ([P, I32, ctypes.POINTER(CsrIn), ctypes.POINTER(P), ctypes.POINTER(P),
+                                   ctypes.POINTER(I32), ctypes.POINTER(CsrOut), ctypes.POINTER(Opts),
+                                   ctypes.POINTER(Info)], ctypes.c_int),
+        "clair_ctx_info": ([P, I32, ctypes.POINTER(CsrOut), ctypes.POINTER(Info)], ctypes.c_int),
+        "clair_size_R": ([P, I32, ctypes.POINTER(CsrIn), ctypes.POINTER(P), ctypes.POINTER(I32),
+                          ctypes.POINTER(I32), ctypes.POINTER(I64), P], ctypes.c_int),
+        "clair_ctx_stage_times": ([P, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_float), I32],
+                                  ctypes.c_int),
+        "clair_ctx_set_tuning": ([P, I32, I32, I32], ctypes.c_int),
+        "clair_ctx_get_tuning": ([P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)], ctypes.c_int),
+        "clair_autotune": ([P, I32, ctypes.POINTER(CsrIn), ctypes.POINTER(P), ctypes.POINTER(P),
+                            ctypes.POINTER(I32), ctypes.POINTER(CsrOut), P, I32], ctypes.c_int),
+        "clair_graph_create": ([P, I32, ctypes.POINTER(CsrIn), ctypes.POINTER(P), ctypes.POINTER(P),
+                                ctypes.POINTER(I32), ctypes.POINTER(CsrOut), P, ctypes.POINTER(P)], ctypes.c_int),
+        "clair_graph_launch": ([P, P], ctypes.c_int),
+        "clair_graph_destroy": ([P], None),
+        "clair_graph_info": ([P, I32, ctypes.POINTER(CsrOut), ctypes.POINTER(Info)], ctypes.c_int),
+        "clair_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "clair_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def strerror(status: int) -> str:
+    try:
+        return load_library().clair_strerror(status).decode()
+    except RuntimeError:
+        return f"status {status}"
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_dev(t: torch.Tensor, dtype, name):
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class CSR:
+    """Device CSR triple (row_ptr int32, col_idx int32, val float64)."""
+
+    def __init__(self, row_ptr: torch.Tensor, col_idx: torch.Tensor, val: torch.Tensor, n: Optional[int] = None):
+        _check_dev(row_ptr, torch.int32, "row_ptr")
+        _check_dev(col_idx, torch.int32, "col_idx")
+        _check_dev(val, torch.float64, "val")
+        self.row_ptr, self.col_idx, self.val = row_ptr, col_idx, val
+        self.n = int(row_ptr.numel() - 1) if n is None else int(n)
+
+    def c(self) -> CsrIn:
+        return CsrIn(self.n, int(self.col_idx.numel()), self.row_ptr.data_ptr(),
+                     self.col_idx.data_ptr() if self.col_idx.numel() else None,
+                     self.val.data_ptr() if self.val.numel() else None)
+
+    @staticmethod
+    def from_problem(p, device="cuda"):
+        return CSR(torch.from_numpy(p.row_ptr).to(device), torch.from_numpy(p.col_idx).to(device),
+                   torch.from_numpy(p.val).to(device), n=p.n)
+
+
+class ROut:
+    """Output R buffers (device), with capacities."""
+
+    def __init__(self, n_c: int, nnz: int, device="cuda"):
+        self.row_ptr = torch.empty(n_c + 1, dtype=torch.int32, device=device)
+        self.col_idx = torch.empty(max(nnz, 1), dtype=torch.int32, device=device)
+        self.val = torch.empty(max(nnz, 1), dtype=torch.float64, device=device)
+        self.n_c = n_c
+        self.nnz = nnz
+        self.n = 0
+
+    def c(self) -> CsrOut:
+        return CsrOut(0, 0, 0, self.row_ptr.numel(), 0, self.col_idx.numel(), self.row_ptr.data_ptr(),
+                      self.col_idx.data_ptr(), self.val.data_ptr())
+
+    def trimmed(self):
+        return self.row_ptr[: self.n_c + 1], self.col_idx[: self.nnz], self.val[: self.nnz]
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+class Context:
+    """clair_ctx_t: device workspace, tuning and per-stage timing."""
+
+    def __init__(self):
+        lib = load_library()
+        h = ctypes.c_void_p()
+        st = lib.clair_ctx_create(ctypes.byref(h))
+        if st:
+            raise ClairError(st, "clair_ctx_create")
+        self._h = h
+        self._lib = lib
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            self._lib.clair_ctx_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tuning(self, group=0, wg_threads=0, chunk=0):
+        st = self._lib.clair_ctx_set_tuning(self._h, group, wg_threads, chunk)
+        if st:
+            raise ClairError(st, "clair_ctx_set_tuning")
+
+    def get_tuning(self):
+        g, t, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._lib.clair_ctx_get_tuning(self._h, ctypes.byref(g), ctypes.byref(t), ctypes.byref(c))
+        return dict(group=g.value, wg_threads=t.value, chunk=c.value)
+
+    def stage_times(self):
+        cap = 16
+        names = (ctypes.c_char_p * cap)()
+        ms = (ctypes.c_float * cap)()
+        n = self._lib.clair_ctx_stage_times(self._h, names, ms, cap)
+        return {names[k].decode(): float(ms[k]) for k in range(n)}
+
+    def info(self, nmat: int, outs: Optional[Sequence[ROut]] = None):
+        Rc = (CsrOut * nmat)()
+        inf = (Info * nmat)()
+        st = self._lib.clair_ctx_info(self._h, nmat, Rc, inf)
+        if outs is not None:
+            for o, r in zip(outs, Rc):
+                o.n_c, o.nnz = r.n_rows, r.nnz
+        return st, [x.as_dict() for x in inf]
+
+
+def _batch_args(As: Sequence[CSR], cfs, Bs, ells, outs: Sequence[ROut]):
+    nmat = len(As)
+    Ac = (CsrIn * nmat)(*[a.c() for a in As])
+    for a, cf in zip(As, cfs):
+        _check_dev(cf, torch.int8, "cf_marker")
+        if cf.numel() != a.n:
+            raise ValueError("cf_marker length != n")
+    cfp = (ctypes.c_void_p * nmat)(*[cf.data_ptr() for cf in cfs])
+    if Bs is None:
+        Bs = [None] * nmat
+    for a, B in zip(As, Bs):
+        if B is not None:
+            _check_dev(B, torch.float64, "B")
+            if B.numel() != a.n:
+                raise ValueError("B length != n")
+    Bp = (ctypes.c_void_p * nmat)(*[None if B is None else B.data_ptr() for B in Bs])
+    ellv = (ctypes.c_int32 * nmat)(*[int(e) for e in ells])
+    Rc = (CsrOut * nmat)(*[o.c() for o in outs])
+    return nmat, Ac, cfp, Bp, ellv, Rc
+
+
+def clair_size_R(As: Sequence[CSR], cfs, ells, ctx: Optional[Context] = None, stream=None):
+    """(n_c, nnz) per matrix: the symbolic phase only."""
+    ctx = ctx or Context()
+    nmat = len(As)
+    Ac = (CsrIn * nmat)(*[a.c() for a in As])
+    cfp = (ctypes.c_void_p * nmat)(*[cf.data_ptr() for cf in cfs])
+    ellv = (ctypes.c_int32 * nmat)(*[int(e) for e in ells])
+    nc = (ctypes.c_int32 * nmat)()
+    nz = (ctypes.c_int64 * nmat)()
+    st = load_library().clair_size_R(ctx.handle, nmat, Ac, cfp, ellv, nc, nz, _stream_ptr(stream))
+    if st:
+        raise ClairError(st, "clair_size_R")
+    return list(nc), list(nz)
+
+
+def clair_build_R_batched(As: Sequence[CSR], cfs, Bs, ells, *, ctx: Optional[Context] = None,
+                          outs: Optional[Sequence[ROut]] = None, precision: int = CLAIR_PREC_MIXED,
+                          async_: bool = False, validate: bool = False, timing: bool = False, stream=None,
+                          check: bool = True):
+    """Build R for several matrices in one pass.
+
+    Returns (outs, infos, status).  Without ``outs`` the sizes are queried first
+    and device buffers allocated.  With ``async_`` the call only enqueues;
+    infos are then empty and ``ctx.info`` reads them later.
+    """
+    lib = load_library()
+    ctx = ctx or Context()
+    if outs is None:
+        ncs, nzs = clair_size_R(As, cfs, ells, ctx=ctx, stream=stream)
+        outs = [ROut(nc, nz, device=a.row_ptr.device) for nc, nz, a in zip(ncs, nzs, As)]
+    nmat, Ac, cfp, Bp, ellv, Rc = _batch_args(As, cfs, Bs, ells, outs)
+    opts = Opts(_stream_ptr(stream), precision, 1 if async_ else 0, 1 if validate else 0, 1 if timing else 0)
+    inf = (Info * nmat)()
+    st = lib.clair_build_R_batched(ctx.handle, nmat, Ac, cfp, Bp, ellv, Rc, ctypes.byref(opts), inf)
+    if async_:
+        if check and st:
+            raise ClairError(st, "clair_build_R_batched (enqueue)")
+        return outs, [], st
+    for o, r in zip(outs, Rc):
+        o.n_c, o.nnz, o.n = r.n_rows, r.nnz, r.n_cols
+    infos = [x.as_dict() for x in inf]
+    if check and st:
+        raise ClairError(st, f"clair_build_R_batched infos={infos}")
+    return outs, infos, st
+
+
+class BatchedCall:
+    """clair_build_R_batched with its arguments marshalled once, for repeated
+    calls on fixed buffers (benchmarks, solver setups on a fixed pattern)."""
+
+    def __init__(self, ctx: Context, As, cfs, Bs, ells, outs, *, precision: int = CLAIR_PREC_MIXED,
+                 async_: bool = True, timing: bool = False, stream=None):
+        self._lib = load_library()
+        self.ctx = ctx
+        self.nmat, self._Ac, self._cfp, self._Bp, self._ellv, self._Rc = _batch_args(As, cfs, Bs, ells, outs)
+        self._opts = Opts(_stream_ptr(stream), precision, 1 if async_ else 0, 0, 1 if timing else 0)
+        self._inf = (Info * self.nmat)()
+        self._keep = (As, cfs, Bs, outs)
+
+    def __call__(self) -> int:
+        st = self._lib.clair_build_R_batched(self.ctx.handle, self.nmat, self._Ac, self._cfp, self._Bp, self._ellv,
+                                             self._Rc, ctypes.byref(self._opts), self._inf)
+        if st:
+            raise ClairError(st, "clair_build_R_batched")
+        return st
+
+
+def clair_build_R(A: CSR, cf: torch.Tensor, B: Optional[torch.Tensor], ell: int, **kw):
+    """One matrix: returns (row_ptr, col_idx, val) device tensors and the info dict."""
+    outs, infos, st = clair_build_R_batched([A], [cf], [B], [ell], **kw)
+    return outs[0].trimmed(), (infos[0] if infos else None)
+
+
+def clair_autotune(ctx: Context, As, cfs, Bs, ells, outs, reps: int = 3, stream=None):
+    nmat, Ac, cfp, Bp, ellv, Rc = _batch_args(As, cfs, Bs, ells, outs)
+    st = load_library().clair_autotune(ctx.handle, nmat, Ac, cfp, Bp, ellv, Rc, _stream_ptr(stream), reps)
+    if st:
+        raise ClairError(st, "clair_autotune")
+    return ctx.get_tuning()
+
+
+class Graph:
+    """hipGraph replay of a batched setup on fixed buffers (clair_graph_*)."""
+
+    def __init__(self, ctx: Context, As, cfs, Bs, ells, outs, stream=None):
+        lib = load_library()
+        self._lib = lib
+        nmat, Ac, cfp, Bp, ellv, Rc = _batch_args(As, cfs, Bs, ells, outs)
+        h = ctypes.c_void_p()
+        st = lib.clair_graph_create(ctx.handle, nmat, Ac, cfp, Bp, ellv, Rc, _stream_ptr(stream), ctypes.byref(h))
+        if st:
+            raise ClairError(st, "clair_graph_create")
+        self._h = h
+        self.nmat = nmat
+        self.outs = outs
+        # keep the argument tensors alive while the graph may run
+        self._keep = (As, cfs, Bs, outs)
+
+    def launch(self, stream=None):
+        st = self._lib.clair_graph_launch(self._h, _stream_ptr(stream))
+        if st:
+            raise ClairError(st, "clair_graph_launch")
+
+    def info(self):
+        Rc = (CsrOut * self.nmat)()
+        inf = (Info * self.nmat)()
+        st = self._lib.clair_graph_info(self._h, self.nmat, Rc, inf)
+        for o, r in zip(self.outs, Rc):
+            o.n_c, o.nnz = r.n_rows, r.nnz
+        return st, [x.as_dict() for x in inf]
+
+    def close(self):
+        if self._h:
+            self._lib.clair_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

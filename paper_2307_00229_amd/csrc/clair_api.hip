@@ -1,0 +1,906 @@
+// clair_api.hip -- the C ABI of libclair (declared in include/clair.h).
+//
+// Host side only: argument checks, the per-context device workspace, the
+// descriptor upload, kernel sequencing, status read-back, per-stage timing,
+// the autotuner and hipGraph capture.  Every arithmetic step of the setup runs
+// in the kernels of k_mixed.hip / k_plain.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "clair.h"
+#include "clair_device.h"
+#include "clair_launch.h"
+
+using namespace clair;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t size = 0;
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    size = 0;
+  }
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= size) return hipSuccess;
+    release();
+    size_t want = std::max<size_t>(bytes, 4096);
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    size = want;
+    return hipSuccess;
+  }
+};
+
+struct HostPinned {
+  void* p = nullptr;
+  size_t size = 0;
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    size = 0;
+  }
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= size) return hipSuccess;
+    release();
+    size_t want = std::max<size_t>(bytes, 4096);
+    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    size = want;
+    return hipSuccess;
+  }
+};
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Layout {
+  size_t desc, st, cnt, chunk_nc, chunk_nnz, chunk_rbase, chunk_nzbase, chunk_mat, clocal, lnz, dsum, rsum,
+      queue, total;
+  size_t head_bytes;  // desc + st + counters (the uploaded head)
+};
+
+Layout make_layout(int nmat, int nchunks, int64_t n_total) {
+  Layout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  L.desc = take(sizeof(MatDesc) * nmat);
+  L.st = o;
+  o += sizeof(MatStatus) * nmat;
+  L.cnt = o;
+  o += sizeof(Counters);
+  L.head_bytes = o - L.desc;
+  o = align_up(o, 256);
+  L.chunk_nc = take(sizeof(int32_t) * (nchunks + 1));
+  L.chunk_nnz = take(sizeof(int32_t) * (nchunks + 1));
+  L.chunk_rbase = take(sizeof(int32_t) * (nchunks + 2));
+  L.chunk_nzbase = take(sizeof(int32_t) * (nchunks + 1));
+  L.chunk_mat = take(sizeof(int32_t) * (nchunks + 1));
+  L.clocal = take(sizeof(int32_t) * (n_total + 1));
+  L.lnz = take(sizeof(int32_t) * (n_total + 1));
+  L.dsum = take(sizeof(double) * (n_total + 1));
+  L.rsum = take(sizeof(double) * (n_total + 1));
+  L.queue = take(sizeof(int32_t) * (n_total + 1));
+  L.total = o;
+  return L;
+}
+
+constexpr int kMaxStages = 8;
+
+struct StageEvents {
+  hipEvent_t ev[kMaxStages + 1];
+  const char* name[kMaxStages];
+  int n = 0;
+};
+
+}  // namespace
+
+struct clair_ctx {
+  int device = 0;
+  int cus = 256;
+  // tuning
+  int group = 8;
+  int wg_threads = 256;
+  int chunk = 2048;
+  // memory
+  DevBuf ws;
+  DevBuf scratch;  // FP64 blocks of oversized rows
+  int64_t scratch_slots = 0;
+  HostPinned stage;     // descriptor/status upload
+  HostPinned readback;  // status download
+  hipEvent_t upload_done = nullptr;
+  bool upload_pending = false;
+  bool capturing = false;  // inside hipStreamBeginCapture: no event records
+  // last call
+  int last_nmat = 0;
+  hipStream_t last_stream = nullptr;
+  Layout last_layout{};
+  Work last_work{};
+  bool last_plain = false;
+  std::vector<clair_info_t> plain_info;  // results of the last plain-form call
+  std::vector<int64_t> plain_nnz;
+  // timing
+  std::vector<StageEvents> timing;
+  size_t timing_used = 0;
+  // plain-form scratch
+  DevBuf plain_ws;
+  DevBuf plain_k;
+};
+
+namespace {
+
+std::mutex g_default_mu;
+std::vector<clair_ctx*> g_default;  // one per device
+
+thread_local char g_last_error[512] = "";
+
+void set_last_error(const char* what, hipError_t e, int line) {
+  snprintf(g_last_error, sizeof(g_last_error), "%s failed: %s (%d) at clair_api.hip:%d", what,
+           hipGetErrorString(e), (int)e, line);
+}
+
+#define HIPCHK(expr)                                \
+  do {                                              \
+    hipError_t e_ = (expr);                         \
+    if (e_ != hipSuccess) {                         \
+      set_last_error(#expr, e_, __LINE__);          \
+      return CLAIR_ERR_HIP;                         \
+    }                                               \
+  } while (0)
+
+// Per-stage events: c->timing[0..timing_used) are the sets recorded since the
+// last clair_ctx_stage_times; each set brackets the stages of one call.
+int timing_begin(clair_ctx* c, bool on) {
+  if (!on) return CLAIR_OK;
+  if (c->timing_used == c->timing.size()) {
+    StageEvents se;
+    for (int k = 0; k <= kMaxStages; ++k) HIPCHK(hipEventCreate(&se.ev[k]));
+    c->timing.push_back(se);
+  }
+  c->timing[c->timing_used].n = 0;
+  c->timing_used += 1;
+  return CLAIR_OK;
+}
+
+void timing_mark(clair_ctx* c, bool on, hipStream_t s, const char* name) {
+  if (!on || c->timing_used == 0) return;
+  StageEvents& se = c->timing[c->timing_used - 1];
+  if (se.n >= kMaxStages) return;
+  if (se.n == 0) (void)hipEventRecord(se.ev[0], s);
+  se.name[se.n] = name;
+  se.n += 1;
+  (void)hipEventRecord(se.ev[se.n], s);
+}
+
+// ---------------------------------------------------------------------------
+// batch preparation
+// ---------------------------------------------------------------------------
+struct Batch {
+  int nmat;
+  int nchunks;
+  int64_t n_total;
+  bool any_B;
+  Layout L;
+  Work w;
+};
+
+int check_args(int32_t nmat, const clair_csr_t* A, const int8_t* const* cf, const int32_t* ell,
+               clair_csr_out_t* R) {
+  if (nmat < 0 || (nmat > 0 && (!A || !cf || !ell || !R))) return CLAIR_ERR_INVALID;
+  for (int m = 0; m < nmat; ++m) {
+    if (A[m].n < 0 || A[m].nnz < 0 || ell[m] < 1 || ell[m] > 64) return CLAIR_ERR_INVALID;
+    if (A[m].n > 0 && (!A[m].row_ptr || !cf[m])) return CLAIR_ERR_INVALID;
+    if (A[m].nnz > 0 && (!A[m].col_idx || !A[m].val)) return CLAIR_ERR_INVALID;
+    if (R[m].row_capacity < 0 || R[m].nnz_capacity < 0) return CLAIR_ERR_INVALID;
+  }
+  return CLAIR_OK;
+}
+
+int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf,
+            const double* const* B, const int32_t* ell, const clair_csr_out_t* R, Batch* b) {
+  b->nmat = nmat;
+  b->nchunks = 0;
+  b->n_total = 0;
+  b->any_B = false;
+  for (int m = 0; m < nmat; ++m) {
+    b->nchunks += (A[m].n + c->chunk - 1) / c->chunk;
+    b->n_total += A[m].n;
+    b->any_B |= (B && B[m]);
+  }
+  b->L = make_layout(nmat, b->nchunks, b->n_total);
+  HIPCHK(c->ws.ensure(b->L.total));
+  HIPCHK(c->stage.ensure(b->L.head_bytes));
+  HIPCHK(c->readback.ensure(b->L.head_bytes));
+  // the previous upload must have left the staging buffer before it is rewritten
+  if (c->upload_pending) {
+    HIPCHK(hipEventSynchronize(c->upload_done));
+    c->upload_pending = false;
+  }
+  char* base = static_cast<char*>(c->ws.p);
+  Work& w = b->w;
+  w.desc = reinterpret_cast<MatDesc*>(base + b->L.desc);
+  w.st = reinterpret_cast<MatStatus*>(base + b->L.st);
+  w.cnt = reinterpret_cast<Counters*>(base + b->L.cnt);
+  w.chunk_nc = reinterpret_cast<int32_t*>(base + b->L.chunk_nc);
+  w.chunk_nnz = reinterpret_cast<int32_t*>(base + b->L.chunk_nnz);
+  w.chunk_rbase = reinterpret_cast<int32_t*>(base + b->L.chunk_rbase);
+  w.chunk_nzbase = reinterpret_cast<int32_t*>(base + b->L.chunk_nzbase);
+  w.chunk_mat = reinterpret_cast<int32_t*>(base + b->L.chunk_mat);
+  w.clocal = reinterpret_cast<int32_t*>(base + b->L.clocal);
+  w.lnz = reinterpret_cast<int32_t*>(base + b->L.lnz);
+  w.dsum = reinterpret_cast<double*>(base + b->L.dsum);
+  w.rsum = reinterpret_cast<double*>(base + b->L.rsum);
+  w.queue = reinterpret_cast<int32_t*>(base + b->L.queue);
+  w.scratch = static_cast<double*>(c->scratch.p);
+  w.scratch_slots = c->scratch_slots;
+  w.nmat = nmat;
+  w.nchunks = b->nchunks;
+  w.chunk = c->chunk;
+  w.queue_cap = (int32_t)std::min<int64_t>(b->n_total + 1, INT32_MAX);
+
+  char* h = static_cast<char*>(c->stage.p);
+  MatDesc* hd = reinterpret_cast<MatDesc*>(h);
+  MatStatus* hs = reinterpret_cast<MatStatus*>(h + (b->L.st - b->L.desc));
+  Counters* hc = reinterpret_cast<Counters*>(h + (b->L.cnt - b->L.desc));
+  int chunk0 = 0;
+  int64_t fine0 = 0;
+  for (int m = 0; m < nmat; ++m) {
+    MatDesc d{};
+    d.rp = A[m].row_ptr;
+    d.ci = A[m].col_idx;
+    d.va = A[m].val;
+    d.cf = cf[m];
+    d.B = B ? B[m] : nullptr;
+    d.Rrp = R[m].row_ptr;
+    d.Rci = R[m].col_idx;
+    d.Rva = R[m].val;
+    d.nnz_cap = R[m].nnz_capacity;
+    d.row_cap = R[m].row_capacity;
+    d.n = A[m].n;
+    d.ell = ell[m];
+    d.chunk0 = chunk0;
+    d.nnz = A[m].nnz;
+    d.nchunks = (A[m].n + c->chunk - 1) / c->chunk;
+    d.fine0 = fine0;
+    hd[m] = d;
+    chunk0 += d.nchunks;
+    fine0 += A[m].n;
+    MatStatus s{};
+    s.first_bad = INT32_MAX;
+    hs[m] = s;
+  }
+  *hc = Counters{};
+  return CLAIR_OK;
+}
+
+int upload(clair_ctx* c, const Batch& b, hipStream_t s) {
+  if (!c->upload_done) HIPCHK(hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming));
+  HIPCHK(hipMemcpyAsync(b.w.desc, c->stage.p, b.L.head_bytes, hipMemcpyHostToDevice, s));
+  if (!c->capturing) {
+    HIPCHK(hipEventRecord(c->upload_done, s));
+    c->upload_pending = true;
+  }
+  return CLAIR_OK;
+}
+
+int read_status(clair_ctx* c, const Batch& b, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(c->readback.p, b.w.desc, b.L.head_bytes, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return CLAIR_OK;
+}
+
+const MatStatus* host_status(clair_ctx* c, const Batch& b) {
+  return reinterpret_cast<const MatStatus*>(static_cast<char*>(c->readback.p) + (b.L.st - b.L.desc));
+}
+
+int occupancy_blocks(clair_ctx* c, int per_cu) { return std::max(8, c->cus * per_cu); }
+
+int ensure_scratch(clair_ctx* c, int slots) {
+  if (c->scratch_slots >= slots) return CLAIR_OK;
+  const size_t bytes = (size_t)slots * kMaxBlock * kMaxBlock * sizeof(double);
+  if (c->scratch.ensure(bytes) != hipSuccess) return CLAIR_ERR_NOMEM;
+  c->scratch_slots = slots;
+  return CLAIR_OK;
+}
+
+// enqueue the numeric half (after count + scan)
+int enqueue_numeric(clair_ctx* c, Batch& b, hipStream_t s, bool timing) {
+  b.w.scratch = static_cast<double*>(c->scratch.p);
+  b.w.scratch_slots = c->scratch_slots;
+  const int per_cu = (c->group == 32 || c->wg_threads == 64) ? 4 : 2;
+  HIPCHK(launch_numeric(b.w, c->group, c->wg_threads, occupancy_blocks(c, per_cu), s));
+  timing_mark(c, timing, s, "numeric");
+  HIPCHK(launch_rows_wg(b.w, occupancy_blocks(c, 1), s));
+  timing_mark(c, timing, s, "rows_wg");
+  if (b.any_B) {
+    HIPCHK(launch_project(b.w, occupancy_blocks(c, 4), s));
+    timing_mark(c, timing, s, "project");
+  }
+  return CLAIR_OK;
+}
+
+int enqueue_symbolic(clair_ctx* c, Batch& b, hipStream_t s, bool validate, bool timing) {
+  int rc = upload(c, b, s);
+  if (rc) return rc;
+  timing_mark(c, timing, s, "upload");
+  if (validate) {
+    HIPCHK(launch_validate(b.w, occupancy_blocks(c, 4), s));
+    timing_mark(c, timing, s, "validate");
+  }
+  HIPCHK(launch_count(b.w, s));
+  timing_mark(c, timing, s, "count");
+  HIPCHK(launch_scan(b.w, s));
+  timing_mark(c, timing, s, "scan");
+  return CLAIR_OK;
+}
+
+void fill_results(const MatStatus* hs, int nmat, clair_csr_out_t* R, clair_info_t* info, const clair_csr_t* A) {
+  for (int m = 0; m < nmat; ++m) {
+    if (R) {
+      R[m].n_rows = hs[m].n_c;
+      R[m].n_cols = A ? A[m].n : R[m].n_cols;
+      R[m].nnz = hs[m].nnz;
+    }
+    if (info) {
+      clair_info_t& in = info[m];
+      in.status = hs[m].status;
+      in.first_bad_row = hs[m].first_bad == INT32_MAX ? -1 : hs[m].first_bad;
+      in.n_c = hs[m].n_c;
+      in.max_block = hs[m].max_block;
+      in.nnz = hs[m].nnz;
+      in.n_uncovered = hs[m].n_uncovered;
+      in.refine_iters_max = hs[m].refine_max;
+      in.n_fp64_rows = hs[m].n_fp64;
+    }
+  }
+}
+
+int first_error(const MatStatus* hs, int nmat) {
+  for (int m = 0; m < nmat; ++m)
+    if (hs[m].status != 0) return hs[m].status;
+  return CLAIR_OK;
+}
+
+int run_mixed(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf, const double* const* B,
+              const int32_t* ell, clair_csr_out_t* R, const clair_opts_t* o, clair_info_t* info) {
+  const hipStream_t s = static_cast<hipStream_t>(o ? o->stream : nullptr);
+  const bool async = o && o->async;
+  const bool timing = o && o->timing;
+  const bool validate = o && o->validate;
+  Batch b;
+  int rc = prepare(c, nmat, A, cf, B, ell, R, &b);
+  if (rc) return rc;
+  c->last_nmat = nmat;
+  c->last_stream = s;
+  c->last_layout = b.L;
+  c->last_work = b.w;
+  c->last_plain = false;
+  if (timing) {
+    rc = timing_begin(c, true);
+    if (rc) return rc;
+  }
+  rc = enqueue_symbolic(c, b, s, validate, timing);
+  if (rc) return rc;
+  if (!async) {
+    rc = read_status(c, b, s);
+    if (rc) return rc;
+    const MatStatus* hs = host_status(c, b);
+    int maxb = 0;
+    bool any_live = false;
+    for (int m = 0; m < nmat; ++m) {
+      maxb = std::max(maxb, hs[m].max_block);
+      any_live |= (hs[m].status == 0);
+    }
+    if (!any_live) {
+      fill_results(hs, nmat, R, info, A);
+      return first_error(hs, nmat);
+    }
+    if (maxb > kLdsBlockMax) {
+      rc = ensure_scratch(c, std::min(64, c->cus / 4 > 0 ? c->cus / 4 : 1));
+      if (rc) return rc;
+    }
+  }
+  rc = enqueue_numeric(c, b, s, timing);
+  if (rc) return rc;
+  c->last_work = b.w;
+  if (async) return CLAIR_OK;
+  rc = read_status(c, b, s);
+  if (rc) return rc;
+  const MatStatus* hs = host_status(c, b);
+  fill_results(hs, nmat, R, info, A);
+  return first_error(hs, nmat);
+}
+
+// ---------------------------------------------------------------------------
+// plain FP64 per-row form
+// ---------------------------------------------------------------------------
+int run_plain_one(clair_ctx* c, const clair_csr_t& A, const int8_t* cf, const double* B, int ell,
+                  clair_csr_out_t* R, hipStream_t s, clair_info_t* info) {
+  const int n = A.n;
+  const int nb = (n + 255) / 256;
+  // workspace: blk_cnt[nb+1] clist[n] sizes[n+1] scan_tmp[nb+2] dsum[n] rsum[n] flags[8]
+  const size_t o_blk = 0;
+  const size_t o_clist = align_up(o_blk + sizeof(int32_t) * (nb + 2), 256);
+  const size_t o_sizes = align_up(o_clist + sizeof(int32_t) * (n + 1), 256);
+  const size_t o_tmp = align_up(o_sizes + sizeof(int32_t) * (n + 2), 256);
+  const size_t o_dsum = align_up(o_tmp + sizeof(int32_t) * (nb + 4), 256);
+  const size_t o_rsum = align_up(o_dsum + sizeof(double) * (n + 1), 256);
+  const size_t o_flags = align_up(o_rsum + sizeof(double) * (n + 1), 256);
+  const size_t total = o_flags + 64;
+  if (c->plain_ws.ensure(total) != hipSuccess) return CLAIR_ERR_NOMEM;
+  HIPCHK(c->readback.ensure(64));
+  char* base = static_cast<char*>(c->plain_ws.p);
+  PlainWork p{};
+  p.rp = A.row_ptr;
+  p.ci = A.col_idx;
+  p.va = A.val;
+  p.cf = cf;
+  p.B = B;
+  p.n = n;
+  p.ell = ell;
+  p.blk_cnt = reinterpret_cast<int32_t*>(base + o_blk);
+  p.clist = reinterpret_cast<int32_t*>(base + o_clist);
+  p.sizes = reinterpret_cast<int32_t*>(base + o_sizes);
+  p.scan_tmp = reinterpret_cast<int32_t*>(base + o_tmp);
+  p.dsum = reinterpret_cast<double*>(base + o_dsum);
+  p.rsum = reinterpret_cast<double*>(base + o_rsum);
+  p.flags = reinterpret_cast<int32_t*>(base + o_flags);
+  p.Rrp = R->row_ptr;
+  p.Rci = R->col_idx;
+  p.Rva = R->val;
+  int32_t hflags[8] = {0, INT32_MAX, 0, 0, 0, 0, 0, 0};
+  HIPCHK(hipMemcpyAsync(p.flags, hflags, sizeof(hflags), hipMemcpyHostToDevice, s));
+  HIPCHK(plain_count_c(p, s));
+  HIPCHK(plain_scan_blocks(p.blk_cnt, nb, s));
+  HIPCHK(plain_clist(p, s));
+  int32_t n_c = 0;
+  HIPCHK(hipMemcpyAsync(&n_c, p.blk_cnt + nb, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  clair_info_t in{};
+  in.first_bad_row = -1;
+  in.n_c = n_c;
+  if (n_c + 1 > R->row_capacity || !R->row_ptr) {
+    in.status = CLAIR_ERR_CAPACITY;
+  }
+  HIPCHK(plain_sizes(p, n_c, s));
+  // scan writes R.row_ptr; without row capacity scan into the workspace instead
+  PlainWork q = p;
+  if (in.status) q.Rrp = p.clist;  // clist is dead after sizes; it holds n+1 >= n_c+1 entries
+  HIPCHK(plain_scan(q, n_c, s));
+  int32_t nnz = 0;
+  HIPCHK(hipMemcpyAsync(&nnz, q.Rrp + n_c, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(hflags, p.flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  in.nnz = nnz;
+  in.max_block = hflags[2];
+  R->n_rows = n_c;
+  R->n_cols = n;
+  R->nnz = nnz;
+  if (in.status == 0 && (nnz > R->nnz_capacity || !R->col_idx || !R->val)) in.status = CLAIR_ERR_CAPACITY;
+  if (in.status == 0 && hflags[0]) {
+    in.status = hflags[0];
+    in.first_bad_row = hflags[1];
+  }
+  if (in.status) {
+    if (info) *info = in;
+    return in.status;
+  }
+  HIPCHK(plain_fill(p, n_c, s));
+  const int smax = std::max(1, hflags[2]);
+  const size_t kb = (size_t)n_c * ((size_t)smax * smax + smax) * sizeof(double);
+  if (c->plain_k.ensure(std::max<size_t>(kb, 64)) != hipSuccess) return CLAIR_ERR_NOMEM;
+  p.kbuf = static_cast<double*>(c->plain_k.p);
+  HIPCHK(plain_solve(p, n_c, smax, s));
+  if (B) {
+    HIPCHK(hipMemsetAsync(p.dsum, 0, sizeof(double) * (n + 1), s));
+    HIPCHK(hipMemsetAsync(p.rsum, 0, sizeof(double) * (n + 1), s));
+    HIPCHK(plain_colsum(p, n_c, s));
+    HIPCHK(plain_project(p, n_c, s));
+  }
+  HIPCHK(hipMemcpyAsync(hflags, p.flags, sizeof(hflags), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  in.status = hflags[0];
+  in.first_bad_row = hflags[0] ? hflags[1] : -1;
+  in.n_uncovered = B ? hflags[3] : 0;
+  in.n_fp64_rows = n_c;
+  if (info) *info = in;
+  return in.status;
+}
+
+int run_plain(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf, const double* const* B,
+              const int32_t* ell, clair_csr_out_t* R, const clair_opts_t* o, clair_info_t* info) {
+  const hipStream_t s = static_cast<hipStream_t>(o ? o->stream : nullptr);
+  const bool timing = o && o->timing;
+  int first = CLAIR_OK;
+  c->last_plain = true;
+  c->last_nmat = nmat;
+  c->plain_info.assign(nmat, clair_info_t{});
+  if (timing) {
+    int rc = timing_begin(c, true);
+    if (rc) return rc;
+    timing_mark(c, true, s, "start");
+  }
+  for (int m = 0; m < nmat; ++m) {
+    clair_info_t in{};
+    int rc = run_plain_one(c, A[m], cf[m], B ? B[m] : nullptr, ell[m], &R[m], s, &in);
+    if (rc == CLAIR_ERR_HIP || rc == CLAIR_ERR_NOMEM) return rc;
+    in.status = rc;
+    c->plain_info[m] = in;
+    if (info) info[m] = in;
+    if (rc && !first) first = rc;
+  }
+  if (timing) timing_mark(c, true, s, "plain");
+  return first;
+}
+
+clair_ctx* default_ctx() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_default_mu);
+  if ((int)g_default.size() <= dev) g_default.resize(dev + 1, nullptr);
+  if (!g_default[dev]) {
+    clair_ctx* c = nullptr;
+    if (clair_ctx_create(&c) != CLAIR_OK) return nullptr;
+    g_default[dev] = c;
+  }
+  return g_default[dev];
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int clair_ctx_create(clair_ctx_t** out) {
+  if (!out) return CLAIR_ERR_INVALID;
+  *out = nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CLAIR_ERR_HIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return CLAIR_ERR_HIP;
+  clair_ctx* c = new (std::nothrow) clair_ctx();
+  if (!c) return CLAIR_ERR_NOMEM;
+  c->device = dev;
+  c->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  *out = c;
+  return CLAIR_OK;
+}
+
+void clair_ctx_destroy(clair_ctx_t* c) {
+  if (!c) return;
+  int prev = 0;
+  (void)hipGetDevice(&prev);
+  (void)hipSetDevice(c->device);
+  (void)hipDeviceSynchronize();
+  c->ws.release();
+  c->scratch.release();
+  c->plain_ws.release();
+  c->plain_k.release();
+  c->stage.release();
+  c->readback.release();
+  if (c->upload_done) (void)hipEventDestroy(c->upload_done);
+  for (auto& se : c->timing)
+    for (int k = 0; k <= kMaxStages; ++k) (void)hipEventDestroy(se.ev[k]);
+  delete c;
+  (void)hipSetDevice(prev);
+}
+
+int clair_build_R_batched(clair_ctx_t* c, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf,
+                          const double* const* B, const int32_t* ell, clair_csr_out_t* R,
+                          const clair_opts_t* o, clair_info_t* info) {
+  if (!c) return CLAIR_ERR_INVALID;
+  int rc = check_args(nmat, A, cf, ell, R);
+  if (rc) return rc;
+  if (nmat == 0) return CLAIR_OK;
+  if (o && o->precision == CLAIR_PREC_FP64) return run_plain(c, nmat, A, cf, B, ell, R, o, info);
+  if (o && o->precision != CLAIR_PREC_MIXED) return CLAIR_ERR_INVALID;
+  try {
+    return run_mixed(c, nmat, A, cf, B, ell, R, o, info);
+  } catch (...) {
+    return CLAIR_ERR_NOMEM;
+  }
+}
+
+int clair_build_R_ex(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf, const double* B, int32_t ell,
+                     clair_csr_out_t* R, const clair_opts_t* o, clair_info_t* info) {
+  const double* Bs[1] = {B};
+  const int8_t* cfs[1] = {cf};
+  int32_t ells[1] = {ell};
+  return clair_build_R_batched(c, 1, A, cfs, Bs, ells, R, o, info);
+}
+
+int clair_build_R(const clair_csr_t* A, const int8_t* cf, const double* B, int32_t ell, clair_csr_out_t* R) {
+  clair_ctx* c = default_ctx();
+  if (!c) return CLAIR_ERR_HIP;
+  std::lock_guard<std::mutex> lk(g_default_mu);
+  return clair_build_R_ex(c, A, cf, B, ell, R, nullptr, nullptr);
+}
+
+int clair_ctx_info(clair_ctx_t* c, int32_t nmat, clair_csr_out_t* R, clair_info_t* info) {
+  if (!c || nmat < 0) return CLAIR_ERR_INVALID;
+  if (c->last_plain) {
+    if (nmat > (int)c->plain_info.size()) return CLAIR_ERR_INVALID;
+    int first = 0;
+    for (int m = 0; m < nmat; ++m) {
+      if (info) info[m] = c->plain_info[m];
+      if (R) {
+        R[m].n_rows = c->plain_info[m].n_c;
+        R[m].nnz = c->plain_info[m].nnz;
+      }
+      if (!first && c->plain_info[m].status) first = c->plain_info[m].status;
+    }
+    return first;
+  }
+  if (nmat > c->last_nmat) return CLAIR_ERR_INVALID;
+  Batch b;
+  b.L = c->last_layout;
+  b.w = c->last_work;
+  int rc = read_status(c, b, c->last_stream);
+  if (rc) return rc;
+  const MatStatus* hs = host_status(c, b);
+  fill_results(hs, nmat, R, info, nullptr);
+  return first_error(hs, nmat);
+}
+
+int clair_size_R(clair_ctx_t* c, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf, const int32_t* ell,
+                 int32_t* n_c, int64_t* nnz, void* stream) {
+  if (!c || !n_c || !nnz) return CLAIR_ERR_INVALID;
+  std::vector<clair_csr_out_t> R(nmat > 0 ? nmat : 1);
+  for (auto& r : R) r = clair_csr_out_t{};
+  int rc = check_args(nmat, A, cf, ell, R.data());
+  if (rc) return rc;
+  if (nmat == 0) return CLAIR_OK;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  Batch b;
+  rc = prepare(c, nmat, A, cf, nullptr, ell, R.data(), &b);
+  if (rc) return rc;
+  c->last_nmat = nmat;
+  c->last_stream = s;
+  c->last_layout = b.L;
+  c->last_work = b.w;
+  c->last_plain = false;
+  rc = enqueue_symbolic(c, b, s, false, false);
+  if (rc) return rc;
+  rc = read_status(c, b, s);
+  if (rc) return rc;
+  const MatStatus* hs = host_status(c, b);
+  int first = 0;
+  for (int m = 0; m < nmat; ++m) {
+    n_c[m] = hs[m].n_c;
+    nnz[m] = hs[m].nnz;
+    if (hs[m].status != 0 && hs[m].status != CLAIR_ERR_CAPACITY && !first) first = hs[m].status;
+  }
+  return first;
+}
+
+int clair_ctx_stage_times(clair_ctx_t* c, const char** names, float* ms, int32_t cap) {
+  if (!c) return 0;
+  int nst = 0;
+  std::vector<std::string> keys;
+  std::vector<float> acc;
+  for (size_t t = 0; t < c->timing_used; ++t) {
+    StageEvents& se = c->timing[t];
+    if (se.n == 0) continue;
+    if (hipEventSynchronize(se.ev[se.n]) != hipSuccess) return 0;
+    for (int k = 0; k < se.n; ++k) {
+      float v = 0.f;
+      (void)hipEventElapsedTime(&v, se.ev[k], se.ev[k + 1]);
+      std::string key = se.name[k];
+      auto it = std::find(keys.begin(), keys.end(), key);
+      if (it == keys.end()) {
+        keys.push_back(key);
+        acc.push_back(v);
+      } else {
+        acc[it - keys.begin()] += v;
+      }
+    }
+  }
+  for (size_t k = 0; k < keys.size() && (int)k < cap; ++k) {
+    if (names) {
+      // stage names are string literals with static storage
+      for (size_t t = 0; t < c->timing_used; ++t) {
+        StageEvents& se = c->timing[t];
+        for (int q = 0; q < se.n; ++q)
+          if (keys[k] == se.name[q]) names[k] = se.name[q];
+      }
+    }
+    if (ms) ms[k] = acc[k];
+    ++nst;
+  }
+  c->timing_used = 0;
+  return nst;
+}
+
+int clair_ctx_set_tuning(clair_ctx_t* c, int32_t group, int32_t wg_threads, int32_t chunk) {
+  if (!c) return CLAIR_ERR_INVALID;
+  if (group && group != 8 && group != 16 && group != 32) return CLAIR_ERR_INVALID;
+  if (wg_threads && wg_threads != 64 && wg_threads != 128 && wg_threads != 256) return CLAIR_ERR_INVALID;
+  if (chunk && (chunk < 256 || chunk > kMaxChunk || (chunk % 256))) return CLAIR_ERR_INVALID;
+  if (group) c->group = group;
+  if (wg_threads) c->wg_threads = wg_threads;
+  if (chunk) c->chunk = chunk;
+  return CLAIR_OK;
+}
+
+int clair_ctx_get_tuning(clair_ctx_t* c, int32_t* group, int32_t* wg_threads, int32_t* chunk) {
+  if (!c) return CLAIR_ERR_INVALID;
+  if (group) *group = c->group;
+  if (wg_threads) *wg_threads = c->wg_threads;
+  if (chunk) *chunk = c->chunk;
+  return CLAIR_OK;
+}
+
+int clair_autotune(clair_ctx_t* c, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf,
+                   const double* const* B, const int32_t* ell, clair_csr_out_t* R, void* stream, int32_t reps) {
+  if (!c || reps < 1) return CLAIR_ERR_INVALID;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  // block-size histogram bound: the largest block decides which groups can hold most rows
+  std::vector<clair_info_t> info(nmat);
+  clair_opts_t o{};
+  o.stream = stream;
+  int rc = clair_build_R_batched(c, nmat, A, cf, B, ell, R, &o, info.data());
+  if (rc) return rc;
+  const int groups[3] = {8, 16, 32};
+  const int threads[3] = {64, 128, 256};
+  const int chunks[3] = {512, 1024, 2048};
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bg = c->group, bt = c->wg_threads, bc = c->chunk;
+  o.async = 1;
+  for (int g : groups) {
+    for (int t : threads) {
+      if (g == 32 && t == 256) continue;
+      for (int ch : chunks) {
+        c->group = g;
+        c->wg_threads = t;
+        c->chunk = ch;
+        rc = clair_build_R_batched(c, nmat, A, cf, B, ell, R, &o, nullptr);  // warm-up
+        if (rc) break;
+        (void)hipEventRecord(e0, s);
+        for (int r = 0; r < reps && !rc; ++r) rc = clair_build_R_batched(c, nmat, A, cf, B, ell, R, &o, nullptr);
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (!rc && ms < best) {
+          best = ms;
+          bg = g;
+          bt = t;
+          bc = ch;
+        }
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->group = bg;
+  c->wg_threads = bt;
+  c->chunk = bc;
+  // leave R consistent with the chosen shape
+  o.async = 0;
+  return clair_build_R_batched(c, nmat, A, cf, B, ell, R, &o, nullptr);
+}
+
+struct clair_graph {
+  clair_ctx* ctx = nullptr;  // private context: its buffers are baked into the graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+int clair_graph_create(clair_ctx_t* parent, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf,
+                       const double* const* B, const int32_t* ell, clair_csr_out_t* R, void* stream,
+                       clair_graph_t** out) {
+  if (!parent || !out) return CLAIR_ERR_INVALID;
+  *out = nullptr;
+  clair_graph* g = new (std::nothrow) clair_graph();
+  if (!g) return CLAIR_ERR_NOMEM;
+  int rc = clair_ctx_create(&g->ctx);
+  if (rc) {
+    delete g;
+    return rc;
+  }
+  g->ctx->group = parent->group;
+  g->ctx->wg_threads = parent->wg_threads;
+  g->ctx->chunk = parent->chunk;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  clair_opts_t o{};
+  o.stream = stream;
+  // one synchronous run sizes every buffer (including scratch) and checks the inputs
+  rc = clair_build_R_batched(g->ctx, nmat, A, cf, B, ell, R, &o, nullptr);
+  if (rc) {
+    clair_graph_destroy(g);
+    return rc;
+  }
+  o.async = 1;
+  hipError_t eb = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (eb != hipSuccess) {
+    set_last_error("hipStreamBeginCapture", eb, __LINE__);
+    clair_graph_destroy(g);
+    return CLAIR_ERR_HIP;
+  }
+  // the staging buffer must not be waited on during capture; it keeps the
+  // captured descriptors for every replay
+  (void)hipEventSynchronize(g->ctx->upload_done);
+  g->ctx->upload_pending = false;
+  g->ctx->capturing = true;
+  rc = clair_build_R_batched(g->ctx, nmat, A, cf, B, ell, R, &o, nullptr);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &graph);
+  g->ctx->capturing = false;
+  if (rc || e != hipSuccess) {
+    if (e != hipSuccess) set_last_error("hipStreamEndCapture", e, __LINE__);
+    if (graph) (void)hipGraphDestroy(graph);
+    clair_graph_destroy(g);
+    return rc ? rc : CLAIR_ERR_HIP;
+  }
+  g->graph = graph;
+  hipError_t ei = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    set_last_error("hipGraphInstantiate", ei, __LINE__);
+    clair_graph_destroy(g);
+    return CLAIR_ERR_HIP;
+  }
+  *out = g;
+  return CLAIR_OK;
+}
+
+int clair_graph_launch(clair_graph_t* g, void* stream) {
+  if (!g || !g->exec) return CLAIR_ERR_INVALID;
+  g->ctx->last_stream = static_cast<hipStream_t>(stream);
+  HIPCHK(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+  return CLAIR_OK;
+}
+
+const char* clair_last_error(void) { return g_last_error; }
+
+void clair_graph_destroy(clair_graph_t* g) {
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  clair_ctx_destroy(g->ctx);
+  delete g;
+}
+
+// results of the last graph launch
+int clair_graph_info(clair_graph_t* g, int32_t nmat, clair_csr_out_t* R, clair_info_t* info) {
+  if (!g) return CLAIR_ERR_INVALID;
+  return clair_ctx_info(g->ctx, nmat, R, info);
+}
+
+const char* clair_strerror(int st) {
+  switch (st) {
+    case CLAIR_OK: return "ok";
+    case CLAIR_ERR_INVALID: return "invalid argument or malformed CSR input";
+    case CLAIR_ERR_CAPACITY: return "output capacity too small (required sizes reported)";
+    case CLAIR_ERR_SINGULAR: return "singular local block";
+    case CLAIR_ERR_HIP: return "HIP runtime error";
+    case CLAIR_ERR_UNSUPPORTED: return "neighbourhood larger than CLAIR_MAX_BLOCK";
+    case CLAIR_ERR_NOMEM: return "workspace allocation failed";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,223 @@
+// clair_device.h -- device-side types and building blocks of libclair.
+//
+// Layout of one setup pass over `nmat` matrices (all device memory):
+//   MatDesc[nmat]     caller pointers + per-matrix geometry
+//   MatStatus[nmat]   results and error state, reset by the host upload
+//   chunk arrays      the fine points of every matrix are cut into chunks of
+//                     `chunk` consecutive indices; the symbolic pass counts
+//                     C-rows and nnz(R) per chunk
+//   clocal / lnz      per chunk, the C-points of the chunk in ascending order
+//                     and the exclusive prefix of (|N(i)|+1) inside the chunk,
+//                     stored at the chunk's own fine offsets
+//   dsum / rsum       FP64 column accumulators of the projection, per fine point
+//   queue             global rows the lane-group solver hands to the
+//                     workgroup-per-row solver
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace clair {
+
+constexpr int kMaxBlock = 1024;  // largest |N(i)| accepted (CLAIR_MAX_BLOCK)
+
+struct MatDesc {
+  const int32_t* rp;
+  const int32_t* ci;
+  const double* va;
+  const int8_t* cf;
+  const double* B;  // may be null
+  int32_t* Rrp;
+  int32_t* Rci;
+  double* Rva;
+  int64_t nnz_cap;
+  int32_t row_cap;
+  int32_t n;
+  int32_t ell;
+  int32_t chunk0;   // first global chunk of this matrix
+  int32_t nchunks;
+  int32_t nnz;      // nnz(A)
+  int64_t fine0;    // offset of this matrix in fine-indexed workspaces
+};
+
+struct MatStatus {
+  int32_t status;      // clair_status code (0 = ok)
+  int32_t first_bad;   // smallest fine index of a failing row (INT32_MAX = none)
+  int32_t n_c;
+  int32_t max_block;
+  int64_t nnz;
+  int64_t n_uncovered;
+  int32_t refine_max;
+  int32_t n_fp64;
+  int32_t row_base;    // first global row of this matrix
+  int32_t pad0;
+};
+
+struct Counters {
+  int32_t total_rows;  // sum of n_c over all matrices
+  int32_t queue_len;   // rows queued for the workgroup solver
+  int32_t queue_big;   // queued rows too large for the LDS solver
+  int32_t pad0;
+};
+
+struct Work {
+  MatDesc* desc;
+  MatStatus* st;
+  Counters* cnt;
+  int32_t* chunk_nc;      // [nchunks]
+  int32_t* chunk_nnz;     // [nchunks]
+  int32_t* chunk_rbase;   // [nchunks+1] first global row of each chunk
+  int32_t* chunk_nzbase;  // [nchunks] first R entry of each chunk (per matrix)
+  int32_t* chunk_mat;     // [nchunks]
+  int32_t* clocal;        // [n_total]
+  int32_t* lnz;           // [n_total]
+  double* dsum;           // [n_total]
+  double* rsum;           // [n_total]
+  int32_t* queue;         // [queue_cap]
+  double* scratch;        // FP64 blocks for oversized rows: scratch_slots * kMaxBlock^2 (may be null)
+  int64_t scratch_slots;
+  int32_t nmat;
+  int32_t nchunks;
+  int32_t chunk;
+  int32_t queue_cap;
+};
+
+// status codes (mirror clair_status)
+enum : int32_t { ST_OK = 0, ST_INVALID = 1, ST_CAPACITY = 2, ST_SINGULAR = 3, ST_HIP = 4, ST_UNSUPPORTED = 5 };
+
+// ---------------------------------------------------------------------------
+// Team primitives.  A team is either a group of G lanes inside one wavefront
+// (communication through LDS with a wavefront fence) or a whole workgroup.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int G>
+struct GroupTeam {
+  static constexpr int size = G;
+  int lane;
+  __device__ __forceinline__ void sync() const { wave_sync(); }
+};
+
+struct BlockTeam {
+  int size;
+  int lane;
+  __device__ __forceinline__ void sync() const { __syncthreads(); }
+};
+
+// index of the first element >= key in sorted a[0..len)
+__device__ __forceinline__ int lower_bound_i32(const int* a, int len, int key) {
+  int lo = 0, hi = len;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < key) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int find_sorted(const int* a, int len, int key) {
+  int p = lower_bound_i32(a, len, key);
+  return (p < len && a[p] == key) ? p : -1;
+}
+
+// LDS buffers of one neighbourhood search.
+struct BfsBuf {
+  int* nb0;   // sorted neighbourhood, double buffered with nb1 [ncap]
+  int* nb1;
+  int* fr;    // newest level, sorted [ncap]
+  int* cand;  // candidates of the current level [ccap]
+  int* keep;  // flags [ccap]
+  int* cnt;   // two scalars: candidate count, kept count
+  int ncap;
+  int ccap;
+};
+
+// Distance-ell F-neighbourhood of C-point i: F-points reachable by at most ell
+// edges (u -> v with u != v and a stored nonzero a_uv) whose interior vertices
+// are F-points.  Level-synchronous: each level collects the F-neighbours of the
+// newest level, removes duplicates and already-found points, and merges the
+// sorted result into the neighbourhood.  Returns |N(i)| with the sorted list in
+// *out, or -1 when a buffer capacity is exceeded (team-uniform).  Column
+// indices outside [0, n) are skipped.
+template <class Team>
+__device__ int team_bfs(const Team& tm, int n, int i, int ell, const int32_t* __restrict__ rp,
+                        const int32_t* __restrict__ ci, const double* __restrict__ va,
+                        const int8_t* __restrict__ cf, const BfsBuf& b, int** out) {
+  int* cur = b.nb0;
+  int* nxt = b.nb1;
+  int s = 0;
+  int fsz = 1;  // level-0 frontier is {i}
+  for (int depth = 1; depth <= ell && fsz > 0; ++depth) {
+    if (tm.lane == 0) { b.cnt[0] = 0; b.cnt[1] = 0; }
+    tm.sync();
+    for (int t = tm.lane; t < fsz; t += tm.size) {
+      const int u = (depth == 1) ? i : b.fr[t];
+      const int e1 = rp[u + 1];
+      for (int e = rp[u]; e < e1; ++e) {
+        const int k = ci[e];
+        if (k == u || (unsigned)k >= (unsigned)n || va[e] == 0.0 || cf[k] != 0) continue;
+        const int pos = atomicAdd(&b.cnt[0], 1);
+        if (pos < b.ccap) b.cand[pos] = k;
+      }
+    }
+    tm.sync();
+    const int m = b.cnt[0];
+    if (m > b.ccap) return -1;
+    int kept = 0;
+    for (int t = tm.lane; t < m; t += tm.size) {
+      const int x = b.cand[t];
+      bool k = find_sorted(cur, s, x) < 0;
+      for (int u = 0; u < t && k; ++u) k = (b.cand[u] != x);
+      b.keep[t] = k ? 1 : 0;
+      kept += k ? 1 : 0;
+    }
+    if (kept) atomicAdd(&b.cnt[1], kept);
+    tm.sync();
+    const int nnew = b.cnt[1];
+    if (s + nnew > b.ncap) return -1;
+    for (int t = tm.lane; t < m; t += tm.size) {
+      if (b.keep[t]) {
+        const int x = b.cand[t];
+        int rank = 0;
+        for (int u = 0; u < m; ++u) rank += (b.keep[u] && b.cand[u] < x) ? 1 : 0;
+        b.fr[rank] = x;
+      }
+    }
+    tm.sync();
+    for (int t = tm.lane; t < s; t += tm.size) {
+      const int y = cur[t];
+      nxt[t + lower_bound_i32(b.fr, nnew, y)] = y;
+    }
+    for (int t = tm.lane; t < nnew; t += tm.size) {
+      const int x = b.fr[t];
+      nxt[t + lower_bound_i32(cur, s, x)] = x;
+    }
+    tm.sync();
+    int* tmp = cur; cur = nxt; nxt = tmp;
+    s += nnew;
+    fsz = nnew;
+  }
+  *out = cur;
+  return s;
+}
+
+// matrix owning global chunk c (desc[].chunk0 ascending)
+__device__ __forceinline__ int chunk_matrix(const MatDesc* desc, int nmat, int c) {
+  int lo = 0, hi = nmat - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (desc[mid].chunk0 <= c) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ void flag_row(MatStatus* st, int32_t code, int fine_row) {
+  atomicCAS(&st->status, 0, code);
+  atomicMin(&st->first_bad, fine_row);
+}
+
+}  // namespace clair

@@ -1,0 +1,53 @@
+// clair_launch.h -- host-side launchers of the libclair kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "clair_device.h"
+
+namespace clair {
+
+constexpr int kMaxChunk = 2048;   // fine points per symbolic-pass workgroup (upper bound)
+constexpr int kLdsBlockMax = 64;  // workgroup FP64 solver keeps blocks up to this size in LDS
+
+// mixed (default) path
+hipError_t launch_validate(const Work& w, int blocks, hipStream_t s);
+hipError_t launch_count(const Work& w, hipStream_t s);
+hipError_t launch_scan(const Work& w, hipStream_t s);
+hipError_t launch_numeric(const Work& w, int group, int wg_threads, int blocks, hipStream_t s);
+hipError_t launch_rows_wg(const Work& w, int blocks, hipStream_t s);
+hipError_t launch_project(const Work& w, int blocks, hipStream_t s);
+
+// plain FP64 per-row form: one matrix, one thread per row, one kernel per stage
+struct PlainWork {
+  const int32_t* rp;
+  const int32_t* ci;
+  const double* va;
+  const int8_t* cf;
+  const double* B;
+  int32_t n;
+  int32_t ell;
+  int32_t* blk_cnt;   // [nblk + 1]
+  int32_t* clist;     // [n]   C-points in ascending order
+  int32_t* sizes;     // [n+1] |N(i)| then exclusive scan of |N(i)|+1
+  int32_t* scan_tmp;  // [n/256 + 2]
+  double* kbuf;       // [n_c * (smax * smax + smax)]
+  double* dsum;       // [n]
+  double* rsum;       // [n]
+  int32_t* flags;     // [8]: status, first_bad, max_block, ...
+  int32_t* Rrp;
+  int32_t* Rci;
+  double* Rva;
+};
+
+hipError_t plain_count_c(const PlainWork& p, hipStream_t s);                 // blk_cnt
+hipError_t plain_scan_blocks(int32_t* a, int n, hipStream_t s);             // exclusive, a[n] = total
+hipError_t plain_clist(const PlainWork& p, hipStream_t s);                   // clist
+hipError_t plain_sizes(const PlainWork& p, int n_c, hipStream_t s);          // sizes, flags
+hipError_t plain_scan(const PlainWork& p, int n_c, hipStream_t s);           // sizes -> offsets, Rrp
+hipError_t plain_fill(const PlainWork& p, int n_c, hipStream_t s);           // Rci
+hipError_t plain_solve(const PlainWork& p, int n_c, int smax, hipStream_t s);  // Rva
+hipError_t plain_colsum(const PlainWork& p, int n_c, hipStream_t s);         // dsum, rsum
+hipError_t plain_project(const PlainWork& p, int n_c, hipStream_t s);        // Rva
+
+}  // namespace clair

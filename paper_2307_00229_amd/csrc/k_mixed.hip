@@ -1,0 +1,797 @@
+// k_mixed.hip -- the batched, mixed-precision restriction setup.
+//
+// Stages (one launch each, over all matrices of a batch):
+//   k_count    symbolic pass per chunk of fine points: C-points of the chunk,
+//              |N(i)| of each (neighbourhood search), chunk-local prefix of
+//              |N(i)|+1; clears the projection accumulators of the chunk.
+//   k_scan     one workgroup: chunk bases -> global row numbers, R offsets,
+//              n_c and nnz(R) per matrix, capacity check, R.row_ptr[n_c].
+//   k_numeric  persistent, G lanes per C-row: neighbourhood (again), gather of
+//              the local block into LDS, FP32 LU + FP64 iterative refinement of
+//              (A[N,N])^T z = -A[i,N]^T, R row write, projection sums.  Rows that
+//              do not fit G lanes, or whose FP32 factorisation is unreliable,
+//              are queued for k_rows_wg.
+//   k_rows_wg  persistent, one workgroup per queued row: FP64 LU with partial
+//              pivoting (block in LDS, or in global scratch when large).
+//   k_project  persistent: z_ij -= B_i (sum_k z_kj B_k - B_j) / sum_k B_k^2 per
+//              F-entry; counts F-points no row reaches.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "clair_device.h"
+#include "clair_launch.h"
+
+namespace clair {
+
+namespace {
+
+constexpr int kNT = 256;  // threads per workgroup of the symbolic pass
+// per-group search caps of the symbolic pass; bigger neighbourhoods use the
+// whole workgroup
+constexpr int kCountG = 8;
+constexpr int kCountGN = 32;
+constexpr int kCountGC = 128;
+// workgroup-wide search caps
+constexpr int kWN = kMaxBlock;
+constexpr int kWC = 4096;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int* total) {
+  // sh: blockDim.x ints.  Hillis-Steele over one value per thread.
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+    int t = (tid >= off) ? sh[tid - off] : 0;
+    __syncthreads();
+    sh[tid] += t;
+    __syncthreads();
+  }
+  int incl = sh[tid];
+  *total = sh[blockDim.x - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+// locate global row g: chunk index by binary search in chunk_rbase[0..nch]
+__device__ __forceinline__ int row_chunk(const int32_t* rbase, int nch, int g) {
+  int lo = 0, hi = nch - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (rbase[mid] <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+struct RowInfo {
+  int m;     // matrix
+  int i;     // fine index of the C-point
+  int r;     // matrix-local row of R
+  int off;   // first R entry of the row
+  int s;     // |N(i)|
+  int64_t fine0;
+};
+
+__device__ __forceinline__ RowInfo row_info(const Work& w, int c, int g) {
+  RowInfo ri;
+  ri.m = w.chunk_mat[c];
+  const MatDesc& d = w.desc[ri.m];
+  const int t = g - w.chunk_rbase[c];
+  const int64_t base = d.fine0 + (int64_t)(c - d.chunk0) * w.chunk;
+  ri.i = w.clocal[base + t];
+  const int l0 = w.lnz[base + t];
+  const int l1 = (t + 1 < w.chunk_nc[c]) ? w.lnz[base + t + 1] : w.chunk_nnz[c];
+  ri.off = w.chunk_nzbase[c] + l0;
+  ri.s = l1 - l0 - 1;
+  ri.r = g - w.st[ri.m].row_base;
+  ri.fine0 = d.fine0;
+  return ri;
+}
+
+__device__ __forceinline__ bool matrix_live(const MatStatus& st) {
+  return st.status != ST_CAPACITY && st.status != ST_INVALID;
+}
+
+// logical workgroup index: consecutive logical indices share an XCD (the
+// hardware deals workgroups to the 8 XCDs round-robin)
+__device__ __forceinline__ int xcd_logical_block() {
+  const int b = blockIdx.x, nb = gridDim.x;
+  if (nb % 8) return b;
+  return (b % 8) * (nb / 8) + b / 8;
+}
+
+// ---------------------------------------------------------------------------
+// validation: CSR sorted, in range; cf is not checked (any nonzero is C)
+// ---------------------------------------------------------------------------
+__global__ void k_validate(Work w) {
+  for (int m = 0; m < w.nmat; ++m) {
+    const MatDesc d = w.desc[m];
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < d.n; r += gridDim.x * blockDim.x) {
+      const int e0 = d.rp[r], e1 = d.rp[r + 1];
+      bool bad = (e1 < e0) || e0 < 0 || e1 > d.nnz || (r == 0 && e0 != 0) || (r == d.n - 1 && e1 != d.nnz);
+      for (int e = e0; e < e1 && !bad; ++e) {
+        const int k = d.ci[e];
+        bad = (k < 0 || k >= d.n || (e > e0 && k <= d.ci[e - 1]));
+      }
+      if (bad) flag_row(&w.st[m], ST_INVALID, r);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// symbolic pass
+// ---------------------------------------------------------------------------
+struct CountGroupBuf {
+  int nb0[kCountGN], nb1[kCountGN], fr[kCountGN];
+  int cand[kCountGC], keep[kCountGC];
+  int cnt[2];
+};
+struct CountBlockBuf {
+  int nb0[kWN], nb1[kWN], fr[kWN];
+  int cand[kWC], keep[kWC];
+  int cnt[2];
+};
+
+__global__ __launch_bounds__(kNT) void k_count(Work w) {
+  constexpr int NG = kNT / kCountG;
+  __shared__ int s_rows[kMaxChunk];
+  __shared__ int s_size[kMaxChunk];
+  __shared__ int s_scan[kNT];
+  __shared__ union {
+    CountGroupBuf g[NG];
+    CountBlockBuf b;
+  } u;
+  __shared__ int s_flag;
+
+  const int c = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int m = chunk_matrix(w.desc, w.nmat, c);
+  const MatDesc d = w.desc[m];
+  MatStatus* st = &w.st[m];
+  const int f0 = (c - d.chunk0) * w.chunk;
+  const int f1 = min(f0 + w.chunk, d.n);
+  const int64_t base = d.fine0 + f0;
+
+  if (st->status == ST_INVALID) {  // validation failed: contribute nothing
+    if (tid == 0) { w.chunk_nc[c] = 0; w.chunk_nnz[c] = 0; w.chunk_mat[c] = m; }
+    return;
+  }
+
+  // clear the projection accumulators of this chunk's fine points
+  if (d.B) {
+    for (int j = f0 + tid; j < f1; j += kNT) { w.dsum[d.fine0 + j] = 0.0; w.rsum[d.fine0 + j] = 0.0; }
+  }
+
+  // compaction of the chunk's C-points, ascending
+  const int per = (w.chunk + kNT - 1) / kNT;
+  const int j0 = f0 + tid * per;
+  int myc = 0;
+  for (int j = j0; j < min(j0 + per, f1); ++j) myc += d.cf[j] != 0;
+  int nc;
+  int rank = block_exclusive_scan(myc, s_scan, &nc);
+  for (int j = j0; j < min(j0 + per, f1); ++j) {
+    if (d.cf[j] != 0) { s_rows[rank] = j; w.clocal[base + rank] = j; ++rank; }
+  }
+  __syncthreads();
+
+  // |N(i)| per C-row, kCountG lanes per row
+  {
+    const int grp = tid / kCountG;
+    GroupTeam<kCountG> tm{tid % kCountG};
+    CountGroupBuf& gb = u.g[grp];
+    BfsBuf bb{gb.nb0, gb.nb1, gb.fr, gb.cand, gb.keep, gb.cnt, kCountGN, kCountGC};
+    for (int t = grp; t < nc; t += NG) {
+      int* nl;
+      const int s = team_bfs(tm, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf, bb, &nl);
+      if (tm.lane == 0) s_size[t] = s;
+      wave_sync();
+    }
+  }
+  __syncthreads();
+  // rows the group buffers could not hold: whole workgroup
+  {
+    BlockTeam tm{kNT, tid};
+    BfsBuf bb{u.b.nb0, u.b.nb1, u.b.fr, u.b.cand, u.b.keep, u.b.cnt, kWN, kWC};
+    for (int t = 0; t < nc; ++t) {
+      if (s_size[t] >= 0) continue;  // uniform: s_size is shared and stable here
+      int* nl;
+      const int s = team_bfs(tm, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf, bb, &nl);
+      __syncthreads();
+      if (tid == 0) {
+        if (s < 0) {
+          flag_row(st, ST_UNSUPPORTED, s_rows[t]);
+          s_size[t] = 0;
+        } else {
+          s_size[t] = s;
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // chunk-local exclusive prefix of (s+1)
+  const int per2 = (nc + kNT - 1) / kNT;
+  const int t0 = tid * per2;
+  int mysum = 0, mymax = 0;
+  for (int t = t0; t < min(t0 + per2, nc); ++t) { mysum += s_size[t] + 1; mymax = max(mymax, s_size[t]); }
+  int tot;
+  int pre = block_exclusive_scan(mysum, s_scan, &tot);
+  for (int t = t0; t < min(t0 + per2, nc); ++t) { w.lnz[base + t] = pre; pre += s_size[t] + 1; }
+  // chunk maximum
+  if (tid == 0) s_flag = 0;
+  __syncthreads();
+  atomicMax(&s_flag, mymax);
+  __syncthreads();
+  if (tid == 0) {
+    w.chunk_nc[c] = nc;
+    w.chunk_nnz[c] = tot;
+    w.chunk_mat[c] = m;
+    atomicMax(&st->max_block, s_flag);
+  }
+}
+
+// one workgroup: per-matrix scans of the chunk counts
+__global__ __launch_bounds__(1024) void k_scan(Work w) {
+  __shared__ int sh[1024];
+  __shared__ int s_carry_r, s_carry_z;
+  const int tid = threadIdx.x;
+  int rows_total = 0;
+  for (int m = 0; m < w.nmat; ++m) {
+    const MatDesc d = w.desc[m];
+    if (tid == 0) { s_carry_r = 0; s_carry_z = 0; }
+    __syncthreads();
+    for (int c0 = 0; c0 < d.nchunks; c0 += 1024) {
+      const int c = d.chunk0 + c0 + tid;
+      const bool in = (c0 + tid) < d.nchunks;
+      const int vr = in ? w.chunk_nc[c] : 0;
+      const int vz = in ? w.chunk_nnz[c] : 0;
+      int tr, tz;
+      const int pr = block_exclusive_scan(vr, sh, &tr);
+      const int pz = block_exclusive_scan(vz, sh, &tz);
+      if (in) {
+        w.chunk_rbase[c] = rows_total + s_carry_r + pr;
+        w.chunk_nzbase[c] = s_carry_z + pz;
+      }
+      __syncthreads();
+      if (tid == 0) { s_carry_r += tr; s_carry_z += tz; }
+      __syncthreads();
+    }
+    const int n_c = s_carry_r;
+    const int nnz = s_carry_z;
+    if (tid == 0) {
+      MatStatus* st = &w.st[m];
+      st->n_c = n_c;
+      st->nnz = nnz;
+      st->row_base = rows_total;
+      if (st->status != ST_INVALID) {
+        const bool fits = d.Rrp && d.Rci && d.Rva && (int64_t)n_c + 1 <= d.row_cap && (int64_t)nnz <= d.nnz_cap;
+        if (!fits) {
+          st->status = ST_CAPACITY;
+        } else {
+          d.Rrp[n_c] = nnz;
+        }
+      }
+    }
+    rows_total += n_c;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    w.chunk_rbase[w.nchunks] = rows_total;
+    w.cnt->total_rows = rows_total;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// numeric pass: G lanes per row
+// ---------------------------------------------------------------------------
+template <int G>
+struct NumGroupBuf {
+  static constexpr int CC = (G < 16 ? 128 : 8 * G);
+  double K[G * (G + 1)];   // FP64 block, row q = row q of (A[N,N])^T, stride G+1
+  double f[G];             // -A[i,N]
+  double z[G];             // refinement broadcast
+  float U[G * G];          // pivot rows
+  int nb0[G], nb1[G], fr[G];
+  int cand[CC], keep[CC];
+  int cnt[2];
+};
+
+template <int G>
+__device__ __forceinline__ float group_maxf(float v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, G));
+  return v;
+}
+template <int G>
+__device__ __forceinline__ double group_maxd(double v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, G));
+  return v;
+}
+template <int G>
+__device__ __forceinline__ int group_ori(int v) {
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o, G);
+  return v;
+}
+
+// forward then backward substitution with the packed LU of this lane's row:
+// kf[k] (k < lane) = L[lane][k], kf[k] (k >= lane) = U[lane][k].
+template <int G>
+__device__ __forceinline__ float lu_solve(const float (&kf)[G], float uinv, int lane, float y) {
+#pragma unroll
+  for (int k = 0; k < G; ++k) {
+    const float yk = __shfl(y, k, G);
+    if (lane > k) y = fmaf(-kf[k], yk, y);
+  }
+#pragma unroll
+  for (int k = G - 1; k >= 0; --k) {
+    if (lane == k) y *= uinv;
+    const float zk = __shfl(y, k, G);
+    if (lane < k) y = fmaf(-kf[k], zk, y);
+  }
+  return y;
+}
+
+constexpr int kRefineMax = 5;
+
+template <int G, int NT>
+__global__ __launch_bounds__(NT) void k_numeric(Work w) {
+  constexpr int NG = NT / G;
+  constexpr int LD = G + 1;
+  constexpr int LCH = 64;
+  __shared__ NumGroupBuf<G> sb[NG];
+  __shared__ int s_rb[LCH + 1];
+  __shared__ int s_c0, s_ncl;
+
+  const int tid = threadIdx.x;
+  const int grp = tid / G;
+  const int lane = tid % G;
+  NumGroupBuf<G>& gb = sb[grp];
+  GroupTeam<G> tm{lane};
+
+  const int total = w.cnt->total_rows;
+  const int lb = xcd_logical_block();
+  const int per = (total + gridDim.x - 1) / gridDim.x;
+  const int r0 = lb * per;
+  const int r1 = min(total, r0 + per);
+  if (r0 >= r1) return;
+
+  if (tid == 0) {
+    const int c0 = row_chunk(w.chunk_rbase, w.nchunks, r0);
+    const int c1 = row_chunk(w.chunk_rbase, w.nchunks, r1 - 1);
+    s_c0 = c0;
+    s_ncl = c1 - c0 + 1;
+  }
+  __syncthreads();
+  const int c0 = s_c0, ncl = s_ncl;
+  for (int t = tid; t <= min(ncl, LCH); t += NT) s_rb[t] = w.chunk_rbase[c0 + t];
+  __syncthreads();
+
+  for (int gbase = r0; gbase < r1; gbase += NG) {
+    const int g = gbase + grp;
+    if (g >= r1) break;  // group-uniform
+    int c;
+    if (ncl <= LCH) {
+      int lo = 0, hi = ncl - 1;
+      while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (s_rb[mid] <= g) lo = mid; else hi = mid - 1;
+      }
+      c = c0 + lo;
+    } else {
+      c = row_chunk(w.chunk_rbase, w.nchunks, g);
+    }
+    const RowInfo ri = row_info(w, c, g);
+    MatStatus* st = &w.st[ri.m];
+    if (!matrix_live(*st)) continue;
+    const MatDesc& d = w.desc[ri.m];
+    if (lane == 0) d.Rrp[ri.r] = ri.off;
+    if (ri.s > G) {
+      if (lane == 0) {
+        const int q = atomicAdd(&w.cnt->queue_len, 1);
+        if (q < w.queue_cap) w.queue[q] = g;
+      }
+      continue;
+    }
+    const int i = ri.i;
+    int* N;
+    const int s = team_bfs(tm, d.n, i, d.ell, d.rp, d.ci, d.va, d.cf,
+                           BfsBuf{gb.nb0, gb.nb1, gb.fr, gb.cand, gb.keep, gb.cnt, G, NumGroupBuf<G>::CC}, &N);
+    if (s != ri.s) {
+      // candidate buffer overflow (s < 0): workgroup solver; a size mismatch
+      // cannot happen for a consistent input and is reported
+      if (lane == 0) {
+        if (s < 0) {
+          const int q = atomicAdd(&w.cnt->queue_len, 1);
+          if (q < w.queue_cap) w.queue[q] = g;
+        } else {
+          flag_row(st, ST_INVALID, i);
+        }
+      }
+      continue;
+    }
+    // R row layout: the C-point's own column goes where it sorts
+    const int myN = (lane < s) ? N[lane] : 0x7fffffff;
+    const uint64_t below = __ballot(lane < s && myN < i);
+    const int dpos = __popcll((below >> ((threadIdx.x & 63) - lane)) & ((G >= 64) ? ~0ull : ((1ull << G) - 1)));
+
+    // ---- gather: K = (A[N,N])^T (padded with identity), f = -A[i,N] ----
+#pragma unroll
+    for (int t = 0; t < G; ++t) gb.K[t * LD + lane] = (t == lane && t >= s) ? 1.0 : 0.0;
+    gb.f[lane] = 0.0;
+    wave_sync();
+    if (lane < s) {
+      const int e1 = d.rp[myN + 1];
+      for (int e = d.rp[myN]; e < e1; ++e) {
+        const int q = find_sorted(N, s, d.ci[e]);
+        if (q >= 0) gb.K[q * LD + lane] = d.va[e];
+      }
+    }
+    {
+      const int e1 = d.rp[i + 1];
+      for (int e = d.rp[i] + lane; e < e1; e += G) {
+        const int q = find_sorted(N, s, d.ci[e]);
+        if (q >= 0) gb.f[q] = -d.va[e];
+      }
+    }
+    wave_sync();
+
+    // ---- FP32 LU of the row-scaled block ----
+    float amax = 0.f;
+    double knorm = 0.0;
+#pragma unroll
+    for (int p = 0; p < G; ++p) {
+      const double v = gb.K[lane * LD + p];
+      amax = fmaxf(amax, (float)fabs(v));
+      knorm += fabs(v);
+    }
+    amax = group_maxf<G>(amax);
+    knorm = group_maxd<G>(knorm);
+    int ex = 0;
+    frexpf(amax, &ex);
+    const double scale = ldexp(1.0, -ex);
+    float kf[G];
+#pragma unroll
+    for (int p = 0; p < G; ++p) kf[p] = (float)(gb.K[lane * LD + p] * scale);
+    float uinv = 1.f;
+    int bad = !(amax > 0.f) || !(amax < 3.0e38f);
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      if (lane == k) {
+#pragma unroll
+        for (int p = k; p < G; ++p) gb.U[k * G + p] = kf[p];
+      }
+      wave_sync();
+      const float piv = gb.U[k * G + k];
+      if (lane == k) uinv = 1.f / piv;
+      bad |= !(fabsf(piv) >= 0x1p-24f);
+      if (lane > k) {
+        const float l = kf[k] / piv;
+        kf[k] = l;
+#pragma unroll
+        for (int p = k + 1; p < G; ++p) kf[p] = fmaf(-l, gb.U[k * G + p], kf[p]);
+      }
+    }
+    bad = group_ori<G>(bad);
+
+    // ---- solve and refine in FP64 ----
+    const double fq = gb.f[lane];
+    const double fnorm = group_maxd<G>(fabs(fq));
+    double z = 0.0;
+    int it = 0;
+    bool conv = false;
+    if (!bad) {
+      z = (double)lu_solve<G>(kf, uinv, lane, (float)(fq * scale));
+      for (it = 1; it <= kRefineMax; ++it) {
+        gb.z[lane] = z;
+        wave_sync();
+        double r = fq;
+#pragma unroll
+        for (int p = 0; p < G; ++p) r = fma(-gb.K[lane * LD + p], gb.z[p], r);
+        const double rn = group_maxd<G>(fabs(r));
+        const double zn = group_maxd<G>(fabs(z));
+        if (rn <= 0x1p-47 * (knorm * zn + fnorm)) { conv = true; break; }
+        const float dz = lu_solve<G>(kf, uinv, lane, (float)(r * scale));
+        z += (double)dz;
+        wave_sync();
+      }
+      if (!(z == z)) conv = false;  // NaN guard (lane-uniform after the test below)
+      conv = group_ori<G>(conv ? 0 : 1) == 0;
+    }
+    if (!conv) {
+      if (lane == 0) {
+        const int q = atomicAdd(&w.cnt->queue_len, 1);
+        if (q < w.queue_cap) w.queue[q] = g;
+      }
+      continue;
+    }
+    if (lane == 0) atomicMax(&st->refine_max, it);
+
+    // ---- R row: F-entries of N(i) around the injected C-point ----
+    if (lane < s) {
+      const int pos = ri.off + lane + (lane >= dpos ? 1 : 0);
+      d.Rci[pos] = myN;
+      d.Rva[pos] = z;
+      if (d.B) {
+        const double bi = d.B[i];
+        unsafeAtomicAdd(&w.dsum[ri.fine0 + myN], bi * bi);
+        unsafeAtomicAdd(&w.rsum[ri.fine0 + myN], z * bi);
+      }
+    }
+    if (lane == 0) {
+      d.Rci[ri.off + dpos] = i;
+      d.Rva[ri.off + dpos] = 1.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// workgroup-per-row FP64 solver (queued rows)
+// ---------------------------------------------------------------------------
+struct WgBuf {
+  int nb0[kWN], nb1[kWN], fr[kWN];
+  int cand[kWC], keep[kWC];
+  int cnt[2];
+};
+
+constexpr int kWT = 256;
+
+__device__ __forceinline__ void block_argmax(double v, int idx, double* shv, int* shi, double* outv, int* outi) {
+  const int tid = threadIdx.x;
+  shv[tid] = v;
+  shi[tid] = idx;
+  __syncthreads();
+  for (int o = kWT / 2; o > 0; o >>= 1) {
+    if (tid < o) {
+      const double a = shv[tid], b = shv[tid + o];
+      const int ia = shi[tid], ib = shi[tid + o];
+      if (b > a || (b == a && ib < ia)) { shv[tid] = b; shi[tid] = ib; }
+    }
+    __syncthreads();
+  }
+  *outv = shv[0];
+  *outi = shi[0];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
+  __shared__ WgBuf bb;
+  __shared__ double sK[kLdsBlockMax * (kLdsBlockMax + 1)];
+  __shared__ double sf[kMaxBlock];
+  __shared__ double shv[kWT];
+  __shared__ int shi[kWT];
+  __shared__ int s_bad;
+
+  const int tid = threadIdx.x;
+  BlockTeam tm{kWT, tid};
+  const int qlen = min(w.cnt->queue_len, w.queue_cap);
+  if (tid == 0 && blockIdx.x == 0 && w.cnt->queue_len > w.queue_cap) {
+    for (int m = 0; m < w.nmat; ++m) atomicCAS(&w.st[m].status, 0, (int)ST_UNSUPPORTED);
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    // pass 0: blocks that fit in LDS, all workgroups; pass 1: larger blocks,
+    // one global scratch slot per workgroup
+    if (pass == 1 && (int64_t)blockIdx.x >= w.scratch_slots) {
+      // no scratch slot: report oversized rows instead of solving them
+      for (int qi = blockIdx.x; qi < qlen; qi += gridDim.x) {
+        const int g = w.queue[qi];
+        const int c = row_chunk(w.chunk_rbase, w.nchunks, g);
+        const RowInfo ri = row_info(w, c, g);
+        if (ri.s > kLdsBlockMax && tid == 0 && w.scratch_slots == 0) flag_row(&w.st[ri.m], ST_UNSUPPORTED, ri.i);
+      }
+      continue;
+    }
+    const int stride = (pass == 0) ? gridDim.x : (int)min<int64_t>(gridDim.x, w.scratch_slots);
+    for (int qi = blockIdx.x; qi < qlen; qi += stride) {
+      const int g = w.queue[qi];
+      const int c = row_chunk(w.chunk_rbase, w.nchunks, g);
+      const RowInfo ri = row_info(w, c, g);
+      const bool big = ri.s > kLdsBlockMax;
+      if (big != (pass == 1)) continue;
+      MatStatus* st = &w.st[ri.m];
+      const MatDesc& d = w.desc[ri.m];
+      const int i = ri.i;
+      int* N;
+      const int s = team_bfs(tm, d.n, i, d.ell, d.rp, d.ci, d.va, d.cf,
+                             BfsBuf{bb.nb0, bb.nb1, bb.fr, bb.cand, bb.keep, bb.cnt, kWN, kWC}, &N);
+      __syncthreads();
+      if (s != ri.s) {
+        if (tid == 0) flag_row(st, s < 0 ? ST_UNSUPPORTED : ST_INVALID, i);
+        __syncthreads();
+        continue;
+      }
+      const int ld = big ? s : (kLdsBlockMax + 1);
+      double* K = big ? (w.scratch + (int64_t)blockIdx.x * kMaxBlock * kMaxBlock) : sK;
+      for (int t = tid; t < s * ld; t += kWT) K[t] = 0.0;
+      for (int t = tid; t < s; t += kWT) sf[t] = 0.0;
+      __syncthreads();
+      // K[q][p] = a_{N_p, N_q}: thread p walks row N_p
+      for (int p = tid; p < s; p += kWT) {
+        const int u = N[p];
+        const int e1 = d.rp[u + 1];
+        for (int e = d.rp[u]; e < e1; ++e) {
+          const int q = find_sorted(N, s, d.ci[e]);
+          if (q >= 0) K[(int64_t)q * ld + p] = d.va[e];
+        }
+      }
+      for (int e = d.rp[i] + tid; e < d.rp[i + 1]; e += kWT) {
+        const int q = find_sorted(N, s, d.ci[e]);
+        if (q >= 0) sf[q] = -d.va[e];
+      }
+      __syncthreads();
+      // max |K| for the singularity threshold
+      double amax = 0.0;
+      for (int t = tid; t < s * s; t += kWT) amax = fmax(amax, fabs(K[(int64_t)(t / s) * ld + (t % s)]));
+      int dummy;
+      block_argmax(amax, 0, shv, shi, &amax, &dummy);
+      const double tiny = 1e-14 * amax;
+      if (tid == 0) s_bad = 0;
+      __syncthreads();
+      for (int k = 0; k < s; ++k) {
+        double best = -1.0;
+        int bi = k;
+        for (int q = k + tid; q < s; q += kWT) {
+          const double v = fabs(K[(int64_t)q * ld + k]);
+          if (v > best) { best = v; bi = q; }
+        }
+        int p;
+        block_argmax(best, bi, shv, shi, &best, &p);
+        if (!(best > tiny)) { if (tid == 0) s_bad = 1; __syncthreads(); break; }
+        if (p != k) {
+          for (int cc = tid; cc < s; cc += kWT) {
+            const double t0 = K[(int64_t)k * ld + cc];
+            K[(int64_t)k * ld + cc] = K[(int64_t)p * ld + cc];
+            K[(int64_t)p * ld + cc] = t0;
+          }
+          if (tid == 0) { const double t0 = sf[k]; sf[k] = sf[p]; sf[p] = t0; }
+          __syncthreads();
+        }
+        const double piv = K[(int64_t)k * ld + k];
+        const int rem = s - k - 1;
+        for (int t = tid; t < rem * (rem + 1); t += kWT) {
+          const int q = k + 1 + t / (rem + 1);
+          const int cc = k + t % (rem + 1);  // cc == k handles the right-hand side
+          const double l = K[(int64_t)q * ld + k] / piv;
+          if (cc == k) sf[q] -= l * sf[k];
+          else K[(int64_t)q * ld + cc] -= l * K[(int64_t)k * ld + cc];
+        }
+        __syncthreads();
+      }
+      if (s_bad) {
+        if (tid == 0) flag_row(st, ST_SINGULAR, i);
+        for (int t = tid; t < s; t += kWT) sf[t] = 0.0;
+        __syncthreads();
+      } else {
+        for (int k = s - 1; k >= 0; --k) {
+          if (tid == 0) sf[k] /= K[(int64_t)k * ld + k];
+          __syncthreads();
+          for (int q = tid; q < k; q += kWT) sf[q] -= K[(int64_t)q * ld + k] * sf[k];
+          __syncthreads();
+        }
+      }
+      if (tid == 0) atomicAdd(&st->n_fp64, 1);
+      // R row
+      int dpos = 0;
+      {
+        int cntb = 0;
+        for (int p = tid; p < s; p += kWT) cntb += N[p] < i;
+        shi[tid] = cntb;
+        __syncthreads();
+        for (int o = kWT / 2; o > 0; o >>= 1) { if (tid < o) shi[tid] += shi[tid + o]; __syncthreads(); }
+        dpos = shi[0];
+        __syncthreads();
+      }
+      for (int p = tid; p < s; p += kWT) {
+        const int pos = ri.off + p + (p >= dpos ? 1 : 0);
+        d.Rci[pos] = N[p];
+        d.Rva[pos] = sf[p];
+        if (d.B) {
+          const double bi = d.B[i];
+          unsafeAtomicAdd(&w.dsum[ri.fine0 + N[p]], bi * bi);
+          unsafeAtomicAdd(&w.rsum[ri.fine0 + N[p]], sf[p] * bi);
+        }
+      }
+      if (tid == 0) {
+        d.Rci[ri.off + dpos] = i;
+        d.Rva[ri.off + dpos] = 1.0;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// projection
+// ---------------------------------------------------------------------------
+constexpr int kPG = 8;  // lanes per row
+
+__global__ __launch_bounds__(256) void k_project(Work w) {
+  const int tid = threadIdx.x;
+  const int lane = tid % kPG;
+  const int grp = tid / kPG;
+  constexpr int NG = 256 / kPG;
+  const int total = w.cnt->total_rows;
+  const int lb = xcd_logical_block();
+  const int per = (total + gridDim.x - 1) / gridDim.x;
+  const int r0 = lb * per;
+  const int r1 = min(total, r0 + per);
+  int c = (r0 < r1) ? row_chunk(w.chunk_rbase, w.nchunks, r0) : 0;
+  for (int gbase = r0; gbase < r1; gbase += NG) {
+    const int g = gbase + grp;
+    if (g >= r1) break;
+    while (w.chunk_rbase[c + 1] <= g) ++c;
+    const RowInfo ri = row_info(w, c, g);
+    const MatStatus& st = w.st[ri.m];
+    const MatDesc& d = w.desc[ri.m];
+    if (!matrix_live(st) || !d.B) continue;
+    const double bi = d.B[ri.i];
+    for (int e = ri.off + lane; e <= ri.off + ri.s; e += kPG) {
+      const int j = d.Rci[e];
+      if (j == ri.i) continue;
+      const double dj = w.dsum[ri.fine0 + j];
+      if (dj > 0.0) d.Rva[e] -= bi * (w.rsum[ri.fine0 + j] - d.B[j]) / dj;
+    }
+  }
+  // uncovered F-points
+  for (int m = 0; m < w.nmat; ++m) {
+    const MatDesc& d = w.desc[m];
+    if (!d.B || !matrix_live(w.st[m])) continue;
+    int cnt = 0;
+    for (int j = blockIdx.x * blockDim.x + tid; j < d.n; j += gridDim.x * blockDim.x)
+      cnt += (d.cf[j] == 0 && !(w.dsum[d.fine0 + j] > 0.0)) ? 1 : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    if ((tid & 63) == 0 && cnt) atomicAdd((unsigned long long*)&w.st[m].n_uncovered, (unsigned long long)cnt);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_validate(const Work& w, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_validate, dim3(blocks), dim3(256), 0, s, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_count(const Work& w, hipStream_t s) {
+  if (w.nchunks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_count, dim3(w.nchunks), dim3(kNT), 0, s, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan(const Work& w, hipStream_t s) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_numeric(const Work& w, int group, int wg_threads, int blocks, hipStream_t s) {
+  blocks = (blocks + 7) / 8 * 8;
+#define CLAIR_NUM(GG, NTT)                                                      \
+  if (group == GG && wg_threads == NTT) {                                       \
+    hipLaunchKernelGGL((k_numeric<GG, NTT>), dim3(blocks), dim3(NTT), 0, s, w); \
+    return hipGetLastError();                                                   \
+  }
+  CLAIR_NUM(8, 256)
+  CLAIR_NUM(8, 128)
+  CLAIR_NUM(8, 64)
+  CLAIR_NUM(16, 256)
+  CLAIR_NUM(16, 128)
+  CLAIR_NUM(16, 64)
+  CLAIR_NUM(32, 256)
+  CLAIR_NUM(32, 128)
+  CLAIR_NUM(32, 64)
+#undef CLAIR_NUM
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_rows_wg(const Work& w, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_rows_wg, dim3(blocks), dim3(kWT), 0, s, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_project(const Work& w, int blocks, hipStream_t s) {
+  blocks = (blocks + 7) / 8 * 8;
+  hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), 0, s, w);
+  return hipGetLastError();
+}
+
+}  // namespace clair

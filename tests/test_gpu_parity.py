@@ -1,0 +1,189 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Every case compares the GPU restriction with the oracle on the same seeded
+input, entry by entry: identical row_ptr / col_idx, relative row error
+<= 1e-10 (mixed FP32 factorisation + FP64 refinement, and the plain FP64
+form), exact C-point entries, constraint residual <= 1e-12 and the same number
+of uncovered F-points.  The five workloads run at their full sizes (the oracle
+finishes each in about a second), plus larger-neighbourhood stress variants
+that exercise the workgroup-per-row solver and its global-scratch blocks.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_00229_amd import problems as P
+
+from ._util import assert_matches_oracle, gpu_build
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2307_00229_amd import clair
+
+    clair.load_library()
+
+
+def _check(problems, precision=0, **kw):
+    from paper_2307_00229_amd import clair
+
+    print(f"[gpu] {[p.name for p in problems]} precision={precision} {kw}", flush=True)
+    res, infos, st = gpu_build(problems, precision=precision, **kw)
+    assert st == 0, (st, infos)
+    for p, g, inf in zip(problems, res, infos):
+        o = oracle.build_R_problem(p)
+        assert_matches_oracle(p, g, o, inf)
+    return res, infos
+
+
+# ---------------------------------------------------------------------------
+# the five workloads at full size
+# ---------------------------------------------------------------------------
+
+def test_cfg1_32x32_l1_mixed_and_plain():
+    p = P.cfg1()
+    _check([p], precision=0)
+    _check([p], precision=1)
+
+
+def test_cfg2_512_three_eps_batched():
+    ps = P.cfg2()
+    res, infos = _check(ps, precision=0)
+    for inf in infos:
+        assert inf["max_block"] == 8
+        assert inf["n_fp64_rows"] == 0
+        assert 1 <= inf["refine_iters_max"] <= 5
+
+
+def test_cfg2_512_plain_fp64():
+    _check(P.cfg2(), precision=1)
+
+
+def test_cfg3_2048_9pt_recirc_every3():
+    p = P.cfg3()
+    res, infos = _check([p], precision=0)
+    assert infos[0]["max_block"] == 24
+
+
+def test_cfg4_64_matrices_batched():
+    ps = P.cfg4()
+    res, infos = _check(ps, precision=0)
+    assert sum(i["n_c"] for i in infos) == 3189226
+
+
+def test_cfg5_128cube_7pt():
+    p = P.cfg5()
+    res, infos = _check([p], precision=0)
+    assert infos[0]["max_block"] == 18
+    assert infos[0]["n_uncovered"] == 262144
+
+
+# ---------------------------------------------------------------------------
+# larger neighbourhoods: lane groups of 8/16/32, workgroup-per-row in LDS and
+# in global scratch
+# ---------------------------------------------------------------------------
+
+def test_cfg3_shape_ell3_workgroup_lds_path():
+    p = P.cfg3(N=300, ell=3)
+    res, infos = _check([p], precision=0)
+    assert infos[0]["max_block"] == 40
+    assert infos[0]["n_fp64_rows"] > 0
+
+
+def test_cfg3_shape_ell5_scratch_path():
+    p = P.cfg3(N=150, ell=5)
+    res, infos = _check([p], precision=0)
+    assert infos[0]["max_block"] == 108
+
+
+def test_cfg5_shape_ell4_scratch_path():
+    p = P.cfg5(N=24, ell=4)
+    res, infos = _check([p], precision=0)
+    assert infos[0]["max_block"] == 98
+
+
+@pytest.mark.parametrize("group,wg,chunk", [(8, 64, 512), (8, 128, 1024), (16, 64, 2048), (16, 256, 512),
+                                            (32, 64, 1024), (32, 128, 2048)])
+def test_tuning_shapes(group, wg, chunk):
+    from paper_2307_00229_amd import clair
+
+    ctx = clair.Context()
+    ctx.set_tuning(group, wg, chunk)
+    ps = [P.small_2d(97, stencil=9, eps=1e-3, angle=0.4, k=3, ell=2),
+          P.small_2d(130, stencil=5, eps=0.5, angle=2.0, ell=2),
+          P.small_3d(21, eps=0.01, b=(0.3, -0.6, 0.7), ell=2),
+          P.small_2d(61, stencil=5, eps=1e-5, angle=4.0, ell=1)]
+    _check(ps, precision=0, ctx=ctx)
+
+
+# ---------------------------------------------------------------------------
+# general sparse inputs and degenerate cases
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_nonsymmetric_patterns(seed):
+    ps = [P.random_sparse(300, 0.01, 40 + seed, ell=2),
+          P.random_sparse(200, 0.02, 50 + seed, ell=3, nonsym_pattern=False),
+          P.random_sparse(150, 0.015, 60 + seed, ell=1, B="ones")]
+    _check(ps, precision=0)
+    # the plain form keeps a neighbourhood in 64 private slots per thread
+    _check([ps[0], ps[2]], precision=1)
+
+
+def test_random_nondominant_needs_pivoting():
+    # no diagonal dominance: the FP32 no-pivot factorisation is not trusted
+    # for every row, and the FP64 partial-pivoting solver takes over
+    ps = [P.random_sparse(200, 0.02, 7 + s, ell=2, dominant=False) for s in range(3)]
+    for p in ps:
+        o = oracle.build_R_problem(p, allow_singular=True)
+        if o["status"] != 0:
+            pytest.skip("random matrix happened to have a singular block")
+    _check(ps, precision=0)
+
+
+def test_unconstrained_rows_are_lair():
+    p = P.small_2d(80, stencil=9, eps=1e-2, angle=1.1, k=3, ell=2)
+    p.B = None
+    _check([p], precision=0)
+    _check([p], precision=1)
+
+
+def test_no_c_points_and_all_c_points():
+    p0 = P.small_2d(20, ell=2)
+    p0.cf = np.zeros(p0.n, np.int8)
+    p1 = P.small_2d(20, ell=2)
+    p1.cf = np.ones(p1.n, np.int8)
+    p2 = P.small_2d(33, ell=2)
+    _check([p0, p1, p2], precision=0)
+    _check([p0, p1, p2], precision=1)
+
+
+def test_isolated_c_point_and_empty_matrix():
+    n = 3
+    p = P.Problem("iso", n, np.array([0, 2, 4, 6], np.int32), np.array([0, 1, 0, 1, 1, 2], np.int32),
+                  np.array([2.0, -1.0, -1.0, 2.0, -1.0, 2.0]), np.array([1, 1, 0], np.int8), np.ones(3), 2)
+    e = P.Problem("empty", 0, np.array([0], np.int32), np.zeros(0, np.int32), np.zeros(0), np.zeros(0, np.int8),
+                  np.zeros(0), 1)
+    _check([p, e, P.cfg1()], precision=0)
+
+
+def test_explicit_zero_not_an_edge():
+    n = 3
+    p = P.Problem("zero", n, np.array([0, 2, 5, 7], np.int32), np.array([0, 1, 0, 1, 2, 1, 2], np.int32),
+                  np.array([2.0, 0.0, -1.0, 2.0, -1.0, -1.0, 2.0]), np.array([1, 0, 0], np.int8), None, 2)
+    res, _ = _check([p], precision=0)
+    assert res[0]["col_idx"].tolist() == [0]
+
+
+def test_scaling_extremes():
+    # the FP32 factorisation works on a power-of-two scaled block
+    for alpha in (1e-250, 1e250):
+        p = P.small_2d(64, stencil=5, eps=1e-2, angle=0.3, ell=2)
+        p.val = p.val * alpha
+        _check([p], precision=0)
