@@ -182,7 +182,10 @@ def main():
 
         graph, graph_error = None, None
         try:
-            graph = clair.Graph(ctx, As, cfs, Bs, ells, outs, stream=stream)
+            # capture on a stream of its own: a failed capture must not leave
+            # the measurement stream unusable
+            cap_stream = torch.cuda.Stream()
+            graph = clair.Graph(ctx, As, cfs, Bs, ells, outs, stream=cap_stream)
         except clair.ClairError as e:
             graph_error = str(e)
             print(f"graph capture unavailable: {e}", file=sys.stderr)

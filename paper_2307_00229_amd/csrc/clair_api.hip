@@ -71,11 +71,12 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
   size_t desc, st, cnt, chunk_nc, chunk_nnz, chunk_rbase, chunk_nzbase, chunk_mat, clocal, lnz, dsum, rsum,
-      queue, total;
+      slotA, slotB, binC, ovf, total;
   size_t head_bytes;  // desc + st + counters (the uploaded head)
+  int64_t capC;
 };
 
-Layout make_layout(int nmat, int nchunks, int64_t n_total) {
+Layout make_layout(int nmat, int nchunks, int64_t n_total, int GA) {
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -90,6 +91,7 @@ Layout make_layout(int nmat, int nchunks, int64_t n_total) {
   o += sizeof(Counters);
   L.head_bytes = o - L.desc;
   o = align_up(o, 256);
+  L.capC = n_total + 1;
   L.chunk_nc = take(sizeof(int32_t) * (nchunks + 1));
   L.chunk_nnz = take(sizeof(int32_t) * (nchunks + 1));
   L.chunk_rbase = take(sizeof(int32_t) * (nchunks + 2));
@@ -99,7 +101,10 @@ Layout make_layout(int nmat, int nchunks, int64_t n_total) {
   L.lnz = take(sizeof(int32_t) * (n_total + 1));
   L.dsum = take(sizeof(double) * (n_total + 1));
   L.rsum = take(sizeof(double) * (n_total + 1));
-  L.queue = take(sizeof(int32_t) * (n_total + 1));
+  L.slotA = take(sizeof(int32_t) * (n_total + 1) * GA);
+  L.slotB = take(sizeof(int32_t) * (n_total + 1) * (GA < 32 ? 32 : 1));
+  L.binC = take(sizeof(int32_t) * L.capC);
+  L.ovf = take(sizeof(int32_t) * (nchunks + 1));
   L.total = o;
   return L;
 }
@@ -156,6 +161,20 @@ thread_local char g_last_error[512] = "";
 void set_last_error(const char* what, hipError_t e, int line) {
   snprintf(g_last_error, sizeof(g_last_error), "%s failed: %s (%d) at clair_api.hip:%d", what,
            hipGetErrorString(e), (int)e, line);
+}
+
+// While capturing, name the first operation after which the capture is no
+// longer active (the runtime only reports the failure at hipStreamEndCapture).
+int capture_check(bool capturing, hipStream_t s, const char* what, int line) {
+  if (!capturing) return 0;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(s, &cs);
+  if (e != hipSuccess || cs != hipStreamCaptureStatusActive) {
+    snprintf(g_last_error, sizeof(g_last_error), "stream capture not active after %s (status %d, err %d) at clair_api.hip:%d",
+             what, (int)cs, (int)e, line);
+    return 1;
+  }
+  return 0;
 }
 
 #define HIPCHK(expr)                                \
@@ -226,7 +245,7 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
     b->n_total += A[m].n;
     b->any_B |= (B && B[m]);
   }
-  b->L = make_layout(nmat, b->nchunks, b->n_total);
+  b->L = make_layout(nmat, b->nchunks, b->n_total, c->group);
   HIPCHK(c->ws.ensure(b->L.total));
   HIPCHK(c->stage.ensure(b->L.head_bytes));
   HIPCHK(c->readback.ensure(b->L.head_bytes));
@@ -249,13 +268,17 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
   w.lnz = reinterpret_cast<int32_t*>(base + b->L.lnz);
   w.dsum = reinterpret_cast<double*>(base + b->L.dsum);
   w.rsum = reinterpret_cast<double*>(base + b->L.rsum);
-  w.queue = reinterpret_cast<int32_t*>(base + b->L.queue);
+  w.slotA = reinterpret_cast<int32_t*>(base + b->L.slotA);
+  w.slotB = reinterpret_cast<int32_t*>(base + b->L.slotB);
+  w.binC = reinterpret_cast<int32_t*>(base + b->L.binC);
+  w.ovf_chunks = reinterpret_cast<int32_t*>(base + b->L.ovf);
   w.scratch = static_cast<double*>(c->scratch.p);
   w.scratch_slots = c->scratch_slots;
   w.nmat = nmat;
   w.nchunks = b->nchunks;
   w.chunk = c->chunk;
-  w.queue_cap = (int32_t)std::min<int64_t>(b->n_total + 1, INT32_MAX);
+  w.GA = c->group;
+  w.capC = (int32_t)std::min<int64_t>(b->L.capC, INT32_MAX);
 
   char* h = static_cast<char*>(c->stage.p);
   MatDesc* hd = reinterpret_cast<MatDesc*>(h);
@@ -295,6 +318,7 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
 int upload(clair_ctx* c, const Batch& b, hipStream_t s) {
   if (!c->upload_done) HIPCHK(hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming));
   HIPCHK(hipMemcpyAsync(b.w.desc, c->stage.p, b.L.head_bytes, hipMemcpyHostToDevice, s));
+  if (capture_check(c->capturing, s, "descriptor upload", __LINE__)) return CLAIR_ERR_HIP;
   if (!c->capturing) {
     HIPCHK(hipEventRecord(c->upload_done, s));
     c->upload_pending = true;
@@ -322,17 +346,32 @@ int ensure_scratch(clair_ctx* c, int slots) {
   return CLAIR_OK;
 }
 
-// enqueue the numeric half (after count + scan)
-int enqueue_numeric(clair_ctx* c, Batch& b, hipStream_t s, bool timing) {
+const Counters* host_counters(clair_ctx* c, const Batch& b) {
+  return reinterpret_cast<const Counters*>(static_cast<char*>(c->readback.p) + (b.L.cnt - b.L.desc));
+}
+
+// enqueue the numeric half (after the symbolic pass).  `known` holds the queue
+// lengths when the host has read them back (synchronous calls): empty queues
+// then launch nothing.
+int enqueue_numeric(clair_ctx* c, Batch& b, hipStream_t s, bool timing, const Counters* known) {
   b.w.scratch = static_cast<double*>(c->scratch.p);
   b.w.scratch_slots = c->scratch_slots;
-  const int per_cu = (c->group == 32 || c->wg_threads == 64) ? 4 : 2;
-  HIPCHK(launch_numeric(b.w, c->group, c->wg_threads, occupancy_blocks(c, per_cu), s));
+  if (!known || known->nA > 0) {
+    HIPCHK(launch_numeric(b.w, 0, c->group, c->wg_threads, c->cus, s));
+    if (capture_check(c->capturing, s, "k_numeric", __LINE__)) return CLAIR_ERR_HIP;
+  }
   timing_mark(c, timing, s, "numeric");
+  if (c->group < 32 && (!known || known->nB > 0)) {
+    HIPCHK(launch_numeric(b.w, 1, 32, 128, c->cus, s));
+    if (capture_check(c->capturing, s, "k_numeric32", __LINE__)) return CLAIR_ERR_HIP;
+    timing_mark(c, timing, s, "numeric32");
+  }
   HIPCHK(launch_rows_wg(b.w, occupancy_blocks(c, 1), s));
+  if (capture_check(c->capturing, s, "k_rows_wg", __LINE__)) return CLAIR_ERR_HIP;
   timing_mark(c, timing, s, "rows_wg");
   if (b.any_B) {
     HIPCHK(launch_project(b.w, occupancy_blocks(c, 4), s));
+    if (capture_check(c->capturing, s, "k_project", __LINE__)) return CLAIR_ERR_HIP;
     timing_mark(c, timing, s, "project");
   }
   return CLAIR_OK;
@@ -347,8 +386,13 @@ int enqueue_symbolic(clair_ctx* c, Batch& b, hipStream_t s, bool validate, bool 
     timing_mark(c, timing, s, "validate");
   }
   HIPCHK(launch_count(b.w, s));
+  if (capture_check(c->capturing, s, "k_count", __LINE__)) return CLAIR_ERR_HIP;
   timing_mark(c, timing, s, "count");
+  HIPCHK(launch_count_big(b.w, std::max(8, c->cus / 4), s));
+  if (capture_check(c->capturing, s, "k_count_big", __LINE__)) return CLAIR_ERR_HIP;
+  timing_mark(c, timing, s, "count_big");
   HIPCHK(launch_scan(b.w, s));
+  if (capture_check(c->capturing, s, "k_scan", __LINE__)) return CLAIR_ERR_HIP;
   timing_mark(c, timing, s, "scan");
   return CLAIR_OK;
 }
@@ -419,7 +463,9 @@ int run_mixed(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* co
       if (rc) return rc;
     }
   }
-  rc = enqueue_numeric(c, b, s, timing);
+  Counters known{};
+  if (!async) known = *host_counters(c, b);
+  rc = enqueue_numeric(c, b, s, timing, async ? nullptr : &known);
   if (rc) return rc;
   c->last_work = b.w;
   if (async) return CLAIR_OK;
@@ -835,23 +881,29 @@ int clair_graph_create(clair_ctx_t* parent, int32_t nmat, const clair_csr_t* A, 
     return rc;
   }
   o.async = 1;
+  // the staging buffer must not be waited on during capture (no synchronising
+  // call may run inside it); it keeps the captured descriptors for every replay
+  hipError_t es = hipEventSynchronize(g->ctx->upload_done);
+  if (es != hipSuccess) {
+    set_last_error("hipEventSynchronize", es, __LINE__);
+    clair_graph_destroy(g);
+    return CLAIR_ERR_HIP;
+  }
+  g->ctx->upload_pending = false;
   hipError_t eb = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
   if (eb != hipSuccess) {
     set_last_error("hipStreamBeginCapture", eb, __LINE__);
     clair_graph_destroy(g);
     return CLAIR_ERR_HIP;
   }
-  // the staging buffer must not be waited on during capture; it keeps the
-  // captured descriptors for every replay
-  (void)hipEventSynchronize(g->ctx->upload_done);
-  g->ctx->upload_pending = false;
   g->ctx->capturing = true;
-  rc = clair_build_R_batched(g->ctx, nmat, A, cf, B, ell, R, &o, nullptr);
+  rc = capture_check(true, s, "hipStreamBeginCapture", __LINE__) ? CLAIR_ERR_HIP
+                                                                 : clair_build_R_batched(g->ctx, nmat, A, cf, B, ell, R, &o, nullptr);
   hipGraph_t graph = nullptr;
   hipError_t e = hipStreamEndCapture(s, &graph);
   g->ctx->capturing = false;
   if (rc || e != hipSuccess) {
-    if (e != hipSuccess) set_last_error("hipStreamEndCapture", e, __LINE__);
+    if (e != hipSuccess && !rc) set_last_error("hipStreamEndCapture", e, __LINE__);
     if (graph) (void)hipGraphDestroy(graph);
     clair_graph_destroy(g);
     return rc ? rc : CLAIR_ERR_HIP;

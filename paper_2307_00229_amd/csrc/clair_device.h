@@ -10,8 +10,9 @@
 //                     and the exclusive prefix of (|N(i)|+1) inside the chunk,
 //                     stored at the chunk's own fine offsets
 //   dsum / rsum       FP64 column accumulators of the projection, per fine point
-//   queue             global rows the lane-group solver hands to the
-//                     workgroup-per-row solver
+//   slots A / B       sorted neighbourhoods of rows small enough for the
+//                     lane-group solvers, per fine point
+//   bin C             rows queued for the workgroup-per-row solver
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -55,11 +56,17 @@ struct MatStatus {
 
 struct Counters {
   int32_t total_rows;  // sum of n_c over all matrices
-  int32_t queue_len;   // rows queued for the workgroup solver
-  int32_t queue_big;   // queued rows too large for the LDS solver
-  int32_t pad0;
+  int32_t nA;          // rows for the small lane-group solver (|N| <= GA)
+  int32_t nB;          // rows for the 32-lane solver (GA < |N| <= 32)
+  int32_t nC;          // rows queued for the workgroup solver (larger, or FP32 not trusted)
+  int32_t novf;        // chunks holding rows the lane-group search could not size
+  int32_t pad0, pad1, pad2;
 };
 
+// Row t of chunk c: fine offset base = fine0 + (c - chunk0) * chunk of its
+// matrix; its sorted neighbourhood sits at slotA[(base + t) * GA] when
+// |N| <= GA, else at slotB[(base + t) * 32] when |N| <= 32.  Rows for the
+// workgroup solver are queued as c * chunk + t.
 struct Work {
   MatDesc* desc;
   MatStatus* st;
@@ -69,17 +76,22 @@ struct Work {
   int32_t* chunk_rbase;   // [nchunks+1] first global row of each chunk
   int32_t* chunk_nzbase;  // [nchunks] first R entry of each chunk (per matrix)
   int32_t* chunk_mat;     // [nchunks]
-  int32_t* clocal;        // [n_total]
-  int32_t* lnz;           // [n_total]
+  int32_t* clocal;        // [n_total] chunk-local C-points (negative while unsized)
+  int32_t* lnz;           // [n_total] chunk-local prefix of |N(i)|+1
   double* dsum;           // [n_total]
   double* rsum;           // [n_total]
-  int32_t* queue;         // [queue_cap]
+  int32_t* slotA;         // [n_total * GA]
+  int32_t* slotB;         // [n_total * 32]
+  int32_t* binC;          // [capC] rows for the workgroup solver
+  int32_t* ovf_chunks;    // [nchunks]
   double* scratch;        // FP64 blocks for oversized rows: scratch_slots * kMaxBlock^2 (may be null)
   int64_t scratch_slots;
   int32_t nmat;
   int32_t nchunks;
   int32_t chunk;
-  int32_t queue_cap;
+  int32_t GA;             // lane-group size of the small solver (8, 16 or 32)
+  int32_t capC;
+  int32_t pad0;
 };
 
 // status codes (mirror clair_status)
@@ -154,14 +166,40 @@ __device__ int team_bfs(const Team& tm, int n, int i, int ell, const int32_t* __
   for (int depth = 1; depth <= ell && fsz > 0; ++depth) {
     if (tm.lane == 0) { b.cnt[0] = 0; b.cnt[1] = 0; }
     tm.sync();
-    for (int t = tm.lane; t < fsz; t += tm.size) {
-      const int u = (depth == 1) ? i : b.fr[t];
-      const int e1 = rp[u + 1];
-      for (int e = rp[u]; e < e1; ++e) {
+    if (depth == 1) {
+      // the row of i: one entry per lane
+      const int e1 = rp[i + 1];
+      for (int e = rp[i] + tm.lane; e < e1; e += tm.size) {
         const int k = ci[e];
-        if (k == u || (unsigned)k >= (unsigned)n || va[e] == 0.0 || cf[k] != 0) continue;
+        if (k == i || (unsigned)k >= (unsigned)n || va[e] == 0.0 || cf[k] != 0) continue;
         const int pos = atomicAdd(&b.cnt[0], 1);
         if (pos < b.ccap) b.cand[pos] = k;
+      }
+    } else {
+      // one frontier vertex per lane; its entries in batches of four independent loads
+      for (int t = tm.lane; t < fsz; t += tm.size) {
+        const int u = b.fr[t];
+        const int e1 = rp[u + 1];
+        for (int e = rp[u]; e < e1; e += 4) {
+          int k[4];
+          double v[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            k[j] = u;
+            v[j] = 0.0;
+            if (e + j < e1) { k[j] = ci[e + j]; v[j] = va[e + j]; }
+          }
+          int8_t c8[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) c8[j] = ((unsigned)k[j] < (unsigned)n) ? cf[k[j]] : (int8_t)1;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (k[j] != u && v[j] != 0.0 && c8[j] == 0) {
+              const int pos = atomicAdd(&b.cnt[0], 1);
+              if (pos < b.ccap) b.cand[pos] = k[j];
+            }
+          }
+        }
       }
     }
     tm.sync();

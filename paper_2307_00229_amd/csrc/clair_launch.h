@@ -13,8 +13,10 @@ constexpr int kLdsBlockMax = 64;  // workgroup FP64 solver keeps blocks up to th
 // mixed (default) path
 hipError_t launch_validate(const Work& w, int blocks, hipStream_t s);
 hipError_t launch_count(const Work& w, hipStream_t s);
+hipError_t launch_count_big(const Work& w, int blocks, hipStream_t s);
 hipError_t launch_scan(const Work& w, hipStream_t s);
-hipError_t launch_numeric(const Work& w, int group, int wg_threads, int blocks, hipStream_t s);
+// which = 0: bin A with group = GA; which = 1: bin B with group = 32
+hipError_t launch_numeric(const Work& w, int which, int group, int wg_threads, int cus, hipStream_t s);
 hipError_t launch_rows_wg(const Work& w, int blocks, hipStream_t s);
 hipError_t launch_project(const Work& w, int blocks, hipStream_t s);
 

@@ -1,22 +1,29 @@
 // k_mixed.hip -- the batched, mixed-precision restriction setup.
 //
 // Stages (one launch each, over all matrices of a batch):
-//   k_count    symbolic pass per chunk of fine points: C-points of the chunk,
-//              |N(i)| of each (neighbourhood search), chunk-local prefix of
-//              |N(i)|+1; clears the projection accumulators of the chunk.
-//   k_scan     one workgroup: chunk bases -> global row numbers, R offsets,
-//              n_c and nnz(R) per matrix, capacity check, R.row_ptr[n_c].
-//   k_numeric  persistent, G lanes per C-row: neighbourhood (again), gather of
-//              the local block into LDS, FP32 LU + FP64 iterative refinement of
-//              (A[N,N])^T z = -A[i,N]^T, R row write, projection sums.  Rows that
-//              do not fit G lanes, or whose FP32 factorisation is unreliable,
-//              are queued for k_rows_wg.
-//   k_rows_wg  persistent, one workgroup per queued row: FP64 LU with partial
-//              pivoting (block in LDS, or in global scratch when large).
-//   k_project  persistent: z_ij -= B_i (sum_k z_kj B_k - B_j) / sum_k B_k^2 per
-//              F-entry; counts F-points no row reaches.
+//   k_count      symbolic pass per chunk of fine points: the C-points of the
+//                chunk, the neighbourhood N(i) of each (lane-group search) kept
+//                in a per-row slot when |N| <= 32 (else the row is queued for
+//                the workgroup solver), the chunk-local prefix of |N(i)|+1;
+//                clears the projection accumulators of the chunk.
+//   k_count_big  the rare chunks with rows the lane-group search could not size:
+//                one workgroup per chunk finishes them.
+//   k_scan       one workgroup: chunk bases -> global row numbers, R offsets,
+//                n_c and nnz(R) per matrix, capacity check, R.row_ptr[n_c].
+//   k_numeric    persistent over the rows in grid order (each XCD a contiguous
+//                slice), G lanes per row with |N| <= G (G = GA), or with
+//                GA < |N| <= 32 (G = 32): gather of the local block into LDS,
+//                FP32 LU and FP64 iterative refinement of
+//                (A[N,N])^T z = -A[i,N]^T, R row write, projection sums.  Rows
+//                whose FP32 factorisation is not trusted are queued for k_rows_wg.
+//   k_rows_wg    persistent, one workgroup per queued row: FP64 LU with partial
+//                pivoting (block in LDS, or in global scratch when large).
+//   k_project    persistent: z_ij -= B_i (sum_k z_kj B_k - B_j) / sum_k B_k^2 per
+//                F-entry; counts F-points no row reaches.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "clair_device.h"
 #include "clair_launch.h"
@@ -26,8 +33,8 @@ namespace clair {
 namespace {
 
 constexpr int kNT = 256;  // threads per workgroup of the symbolic pass
-// per-group search caps of the symbolic pass; bigger neighbourhoods use the
-// whole workgroup
+// lane-group search of the symbolic pass: 8 lanes per row, neighbourhoods up
+// to 32 points and 128 candidates per level; larger rows go to k_count_big
 constexpr int kCountG = 8;
 constexpr int kCountGN = 32;
 constexpr int kCountGC = 128;
@@ -52,7 +59,7 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int* total) 
   return incl - v;
 }
 
-// locate global row g: chunk index by binary search in chunk_rbase[0..nch]
+// chunk index of global row g: binary search in chunk_rbase[0..nch]
 __device__ __forceinline__ int row_chunk(const int32_t* rbase, int nch, int g) {
   int lo = 0, hi = nch - 1;
   while (lo < hi) {
@@ -71,18 +78,18 @@ struct RowInfo {
   int64_t fine0;
 };
 
-__device__ __forceinline__ RowInfo row_info(const Work& w, int c, int g) {
+// row t of chunk c
+__device__ __forceinline__ RowInfo row_info(const Work& w, int c, int t) {
   RowInfo ri;
   ri.m = w.chunk_mat[c];
   const MatDesc& d = w.desc[ri.m];
-  const int t = g - w.chunk_rbase[c];
   const int64_t base = d.fine0 + (int64_t)(c - d.chunk0) * w.chunk;
   ri.i = w.clocal[base + t];
   const int l0 = w.lnz[base + t];
   const int l1 = (t + 1 < w.chunk_nc[c]) ? w.lnz[base + t + 1] : w.chunk_nnz[c];
   ri.off = w.chunk_nzbase[c] + l0;
   ri.s = l1 - l0 - 1;
-  ri.r = g - w.st[ri.m].row_base;
+  ri.r = w.chunk_rbase[c] + t - w.st[ri.m].row_base;
   ri.fine0 = d.fine0;
   return ri;
 }
@@ -91,12 +98,30 @@ __device__ __forceinline__ bool matrix_live(const MatStatus& st) {
   return st.status != ST_CAPACITY && st.status != ST_INVALID;
 }
 
-// logical workgroup index: consecutive logical indices share an XCD (the
-// hardware deals workgroups to the 8 XCDs round-robin)
+// Logical workgroup index: the hardware deals workgroups to the 8 XCDs
+// round-robin (block b runs on XCD b % 8).  Give each XCD a contiguous range
+// of logical indices, so the rows one XCD works on are neighbours in the grid
+// and share its L2.
 __device__ __forceinline__ int xcd_logical_block() {
   const int b = blockIdx.x, nb = gridDim.x;
-  if (nb % 8) return b;
-  return (b % 8) * (nb / 8) + b / 8;
+  const int x = b % 8, q = nb / 8, r = nb % 8;
+  return x * q + min(x, r) + b / 8;
+}
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// wave-aggregated queue append: every lane with `want` gets a distinct slot
+// (or -1 once the queue is full); one atomic per wave
+__device__ __forceinline__ int wave_append(bool want, int32_t* counter, int cap) {
+  const uint64_t mask = __ballot(want);
+  if (!mask) return -1;
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  int base = 0;
+  if (lane_id() == leader) base = atomicAdd(counter, __popcll(mask));
+  base = __shfl(base, leader, 64);
+  const int rank = __popcll(mask & ((1ull << lane_id()) - 1ull));
+  const int slot = base + rank;
+  return (want && slot < cap) ? slot : -1;
 }
 
 // ---------------------------------------------------------------------------
@@ -125,24 +150,16 @@ struct CountGroupBuf {
   int cand[kCountGC], keep[kCountGC];
   int cnt[2];
 };
-struct CountBlockBuf {
-  int nb0[kWN], nb1[kWN], fr[kWN];
-  int cand[kWC], keep[kWC];
-  int cnt[2];
-};
 
 __global__ __launch_bounds__(kNT) void k_count(Work w) {
   constexpr int NG = kNT / kCountG;
   __shared__ int s_rows[kMaxChunk];
   __shared__ int s_size[kMaxChunk];
   __shared__ int s_scan[kNT];
-  __shared__ union {
-    CountGroupBuf g[NG];
-    CountBlockBuf b;
-  } u;
-  __shared__ int s_flag;
+  __shared__ CountGroupBuf gbuf[NG];
+  __shared__ int s_flag[4];  // max |N|, unresolved rows, rows in slots A, rows in slots B
 
-  const int c = blockIdx.x;
+  const int c = xcd_logical_block();
   const int tid = threadIdx.x;
   const int m = chunk_matrix(w.desc, w.nmat, c);
   const MatDesc d = w.desc[m];
@@ -169,44 +186,57 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
   int nc;
   int rank = block_exclusive_scan(myc, s_scan, &nc);
   for (int j = j0; j < min(j0 + per, f1); ++j) {
-    if (d.cf[j] != 0) { s_rows[rank] = j; w.clocal[base + rank] = j; ++rank; }
+    if (d.cf[j] != 0) { s_rows[rank] = j; ++rank; }
   }
+  if (tid == 0) { s_flag[0] = 0; s_flag[1] = 0; s_flag[2] = 0; s_flag[3] = 0; }
   __syncthreads();
 
-  // |N(i)| per C-row, kCountG lanes per row
-  {
-    const int grp = tid / kCountG;
-    GroupTeam<kCountG> tm{tid % kCountG};
-    CountGroupBuf& gb = u.g[grp];
-    BfsBuf bb{gb.nb0, gb.nb1, gb.fr, gb.cand, gb.keep, gb.cnt, kCountGN, kCountGC};
-    for (int t = grp; t < nc; t += NG) {
-      int* nl;
-      const int s = team_bfs(tm, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf, bb, &nl);
-      if (tm.lane == 0) s_size[t] = s;
-      wave_sync();
-    }
-  }
-  __syncthreads();
-  // rows the group buffers could not hold: whole workgroup
-  {
-    BlockTeam tm{kNT, tid};
-    BfsBuf bb{u.b.nb0, u.b.nb1, u.b.fr, u.b.cand, u.b.keep, u.b.cnt, kWN, kWC};
-    for (int t = 0; t < nc; ++t) {
-      if (s_size[t] >= 0) continue;  // uniform: s_size is shared and stable here
-      int* nl;
-      const int s = team_bfs(tm, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf, bb, &nl);
-      __syncthreads();
-      if (tid == 0) {
-        if (s < 0) {
-          flag_row(st, ST_UNSUPPORTED, s_rows[t]);
-          s_size[t] = 0;
-        } else {
-          s_size[t] = s;
-        }
+  // N(i) per C-row, kCountG lanes per row; queue by block size
+  const int grp = tid / kCountG;
+  const int gl = tid % kCountG;
+  GroupTeam<kCountG> tm{gl};
+  CountGroupBuf& gb = gbuf[grp];
+  const BfsBuf bb{gb.nb0, gb.nb1, gb.fr, gb.cand, gb.keep, gb.cnt, kCountGN, kCountGC};
+  const int GA = w.GA;
+  int unresolved = 0, inA = 0, inB = 0;
+  for (int t0 = 0; t0 < nc; t0 += NG) {  // uniform trip count: all groups meet at the append
+    const int t = t0 + grp;
+    const bool active = t < nc;
+    int s = 0;
+    int* nl = gb.nb0;
+    int i = 0;
+    if (active) {
+      i = s_rows[t];
+      s = team_bfs(tm, d.n, i, d.ell, d.rp, d.ci, d.va, d.cf, bb, &nl);
+      if (s >= 0 && s <= GA) {
+        for (int p = gl; p < s; p += kCountG) w.slotA[(base + t) * GA + p] = nl[p];
+        inA += (gl == 0);
+      } else if (s > GA && s <= 32) {
+        for (int p = gl; p < s; p += kCountG) w.slotB[(base + t) * 32 + p] = nl[p];
+        inB += (gl == 0);
       }
-      __syncthreads();
     }
+    const bool lead = active && gl == 0;
+    // rows the lane-group solvers cannot take: workgroup solver (s < 0 is
+    // sized by k_count_big first)
+    const int qc = wave_append(lead && s > 32, &w.cnt->nC, w.capC);
+    if (qc >= 0) w.binC[qc] = c * w.chunk + t;
+    if (lead) {
+      if (s < 0) {
+        ++unresolved;
+        s_size[t] = 0;
+        w.clocal[base + t] = -(i + 1);  // k_count_big sizes it
+      } else {
+        s_size[t] = s;
+        w.clocal[base + t] = i;
+      }
+    }
+    wave_sync();
   }
+  if (inA) atomicAdd(&s_flag[2], inA);
+  if (inB) atomicAdd(&s_flag[3], inB);
+  if (unresolved) atomicAdd(&s_flag[1], unresolved);
+  __syncthreads();
 
   // chunk-local exclusive prefix of (s+1)
   const int per2 = (nc + kNT - 1) / kNT;
@@ -216,16 +246,100 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
   int tot;
   int pre = block_exclusive_scan(mysum, s_scan, &tot);
   for (int t = t0; t < min(t0 + per2, nc); ++t) { w.lnz[base + t] = pre; pre += s_size[t] + 1; }
-  // chunk maximum
-  if (tid == 0) s_flag = 0;
-  __syncthreads();
-  atomicMax(&s_flag, mymax);
+  atomicMax(&s_flag[0], mymax);
   __syncthreads();
   if (tid == 0) {
     w.chunk_nc[c] = nc;
     w.chunk_nnz[c] = tot;
     w.chunk_mat[c] = m;
-    atomicMax(&st->max_block, s_flag);
+    atomicMax(&st->max_block, s_flag[0]);
+    if (s_flag[2]) atomicAdd(&w.cnt->nA, s_flag[2]);
+    if (s_flag[3]) atomicAdd(&w.cnt->nB, s_flag[3]);
+    if (s_flag[1]) {
+      const int q = atomicAdd(&w.cnt->novf, 1);
+      w.ovf_chunks[q] = c;
+    }
+  }
+}
+
+// chunks with rows the lane-group search could not size: one workgroup each
+struct BigBuf {
+  int nb0[kWN], nb1[kWN], fr[kWN];
+  int cand[kWC], keep[kWC];
+  int cnt[2];
+};
+
+__global__ __launch_bounds__(kNT) void k_count_big(Work w) {
+  __shared__ BigBuf bb;
+  __shared__ int s_size[kMaxChunk];
+  __shared__ int s_scan[kNT];
+  __shared__ int s_max;
+  const int tid = threadIdx.x;
+  BlockTeam tm{kNT, tid};
+  const int nov = w.cnt->novf;
+  for (int k = blockIdx.x; k < nov; k += gridDim.x) {
+    const int c = w.ovf_chunks[k];
+    const int m = w.chunk_mat[c];
+    const MatDesc d = w.desc[m];
+    MatStatus* st = &w.st[m];
+    const int64_t base = d.fine0 + (int64_t)(c - d.chunk0) * w.chunk;
+    const int nc = w.chunk_nc[c];
+    // sizes of the rows already done, from the prefix
+    for (int t = tid; t < nc; t += kNT) {
+      const int l1 = (t + 1 < nc) ? w.lnz[base + t + 1] : w.chunk_nnz[c];
+      s_size[t] = l1 - w.lnz[base + t] - 1;
+    }
+    if (tid == 0) s_max = 0;
+    __syncthreads();
+    for (int t = 0; t < nc; ++t) {
+      const int ci = w.clocal[base + t];
+      if (ci >= 0) continue;  // uniform
+      const int i = -ci - 1;
+      int* nl;
+      const int s = team_bfs(tm, d.n, i, d.ell, d.rp, d.ci, d.va, d.cf,
+                             BfsBuf{bb.nb0, bb.nb1, bb.fr, bb.cand, bb.keep, bb.cnt, kWN, kWC}, &nl);
+      __syncthreads();
+      // small enough for a lane-group solver: its slot; else the workgroup solver
+      if (s >= 0 && s <= w.GA) {
+        for (int p = tid; p < s; p += kNT) w.slotA[(base + t) * w.GA + p] = nl[p];
+      } else if (s > w.GA && s <= 32) {
+        for (int p = tid; p < s; p += kNT) w.slotB[(base + t) * 32 + p] = nl[p];
+      }
+      if (tid == 0) {
+        w.clocal[base + t] = i;
+        if (s < 0) {
+          flag_row(st, ST_UNSUPPORTED, i);
+          s_size[t] = 0;
+        } else {
+          s_size[t] = s;
+          s_max = max(s_max, s);
+          if (s <= w.GA) {
+            atomicAdd(&w.cnt->nA, 1);
+          } else if (s <= 32) {
+            atomicAdd(&w.cnt->nB, 1);
+          } else {
+            const int q = atomicAdd(&w.cnt->nC, 1);
+            if (q < w.capC) w.binC[q] = c * w.chunk + t;
+            else flag_row(st, ST_UNSUPPORTED, i);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // redo the chunk-local prefix
+    const int per2 = (nc + kNT - 1) / kNT;
+    const int t0 = tid * per2;
+    int mysum = 0;
+    for (int t = t0; t < min(t0 + per2, nc); ++t) mysum += s_size[t] + 1;
+    int tot;
+    int pre = block_exclusive_scan(mysum, s_scan, &tot);
+    for (int t = t0; t < min(t0 + per2, nc); ++t) { w.lnz[base + t] = pre; pre += s_size[t] + 1; }
+    __syncthreads();
+    if (tid == 0) {
+      w.chunk_nnz[c] = tot;
+      atomicMax(&st->max_block, s_max);
+    }
+    __syncthreads();
   }
 }
 
@@ -281,18 +395,15 @@ __global__ __launch_bounds__(1024) void k_scan(Work w) {
 }
 
 // ---------------------------------------------------------------------------
-// numeric pass: G lanes per row
+// numeric pass: G lanes per queued row
 // ---------------------------------------------------------------------------
 template <int G>
 struct NumGroupBuf {
-  static constexpr int CC = (G < 16 ? 128 : 8 * G);
-  double K[G * (G + 1)];   // FP64 block, row q = row q of (A[N,N])^T, stride G+1
-  double f[G];             // -A[i,N]
-  double z[G];             // refinement broadcast
-  float U[G * G];          // pivot rows
-  int nb0[G], nb1[G], fr[G];
-  int cand[CC], keep[CC];
-  int cnt[2];
+  double K[G * (G + 1)];  // FP64 block, row q = row q of (A[N,N])^T, stride G+1
+  double f[G];            // -A[i,N]
+  double z[G];            // refinement broadcast
+  float U[G * G];         // pivot rows
+  int nb[G];              // sorted N(i)
 };
 
 template <int G>
@@ -335,103 +446,84 @@ __device__ __forceinline__ float lu_solve(const float (&kf)[G], float uinv, int 
 constexpr int kRefineMax = 5;
 
 template <int G, int NT>
-__global__ __launch_bounds__(NT) void k_numeric(Work w) {
+__global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
   constexpr int NG = NT / G;
   constexpr int LD = G + 1;
-  constexpr int LCH = 64;
   __shared__ NumGroupBuf<G> sb[NG];
-  __shared__ int s_rb[LCH + 1];
-  __shared__ int s_c0, s_ncl;
+  __shared__ int s_itmax;
 
   const int tid = threadIdx.x;
   const int grp = tid / G;
   const int lane = tid % G;
   NumGroupBuf<G>& gb = sb[grp];
-  GroupTeam<G> tm{lane};
 
+  // rows of this solver: |N| <= G (small solver) or GA < |N| <= 32 (which = 1)
+  if ((which ? w.cnt->nB : w.cnt->nA) == 0) return;
+  const int smin = which ? w.GA + 1 : 0;
+  const int32_t* slots = which ? w.slotB : w.slotA;
+  const int sstride = which ? 32 : w.GA;
   const int total = w.cnt->total_rows;
   const int lb = xcd_logical_block();
   const int per = (total + gridDim.x - 1) / gridDim.x;
   const int r0 = lb * per;
   const int r1 = min(total, r0 + per);
   if (r0 >= r1) return;
-
-  if (tid == 0) {
-    const int c0 = row_chunk(w.chunk_rbase, w.nchunks, r0);
-    const int c1 = row_chunk(w.chunk_rbase, w.nchunks, r1 - 1);
-    s_c0 = c0;
-    s_ncl = c1 - c0 + 1;
-  }
-  __syncthreads();
-  const int c0 = s_c0, ncl = s_ncl;
-  for (int t = tid; t <= min(ncl, LCH); t += NT) s_rb[t] = w.chunk_rbase[c0 + t];
+  int c = row_chunk(w.chunk_rbase, w.nchunks, min(r0 + grp, r1 - 1));
+  // statistics of the workgroup's first matrix gather in LDS (one global
+  // atomic per workgroup); rows of later matrices in the range go straight out
+  const int m0 = w.chunk_mat[row_chunk(w.chunk_rbase, w.nchunks, r0)];
+  if (tid == 0) s_itmax = 0;
   __syncthreads();
 
   for (int gbase = r0; gbase < r1; gbase += NG) {
     const int g = gbase + grp;
     if (g >= r1) break;  // group-uniform
-    int c;
-    if (ncl <= LCH) {
-      int lo = 0, hi = ncl - 1;
-      while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (s_rb[mid] <= g) lo = mid; else hi = mid - 1;
-      }
-      c = c0 + lo;
-    } else {
-      c = row_chunk(w.chunk_rbase, w.nchunks, g);
-    }
-    const RowInfo ri = row_info(w, c, g);
+    while (w.chunk_rbase[c + 1] <= g) ++c;
+    const int t = g - w.chunk_rbase[c];
+    const RowInfo ri = row_info(w, c, t);
+    if (ri.s < smin || ri.s > G) continue;  // another solver's row (group-uniform)
+    const int64_t fbase = ri.fine0 + (int64_t)(c - w.desc[ri.m].chunk0) * w.chunk;
+    const int myN0 = slots[(fbase + t) * sstride + min(lane, sstride - 1)];
+    const int entry = c * w.chunk + t;
     MatStatus* st = &w.st[ri.m];
     if (!matrix_live(*st)) continue;
     const MatDesc& d = w.desc[ri.m];
-    if (lane == 0) d.Rrp[ri.r] = ri.off;
-    if (ri.s > G) {
-      if (lane == 0) {
-        const int q = atomicAdd(&w.cnt->queue_len, 1);
-        if (q < w.queue_cap) w.queue[q] = g;
-      }
-      continue;
-    }
+    const int s = ri.s;
     const int i = ri.i;
-    int* N;
-    const int s = team_bfs(tm, d.n, i, d.ell, d.rp, d.ci, d.va, d.cf,
-                           BfsBuf{gb.nb0, gb.nb1, gb.fr, gb.cand, gb.keep, gb.cnt, G, NumGroupBuf<G>::CC}, &N);
-    if (s != ri.s) {
-      // candidate buffer overflow (s < 0): workgroup solver; a size mismatch
-      // cannot happen for a consistent input and is reported
-      if (lane == 0) {
-        if (s < 0) {
-          const int q = atomicAdd(&w.cnt->queue_len, 1);
-          if (q < w.queue_cap) w.queue[q] = g;
-        } else {
-          flag_row(st, ST_INVALID, i);
-        }
-      }
-      continue;
-    }
-    // R row layout: the C-point's own column goes where it sorts
-    const int myN = (lane < s) ? N[lane] : 0x7fffffff;
+    if (lane == 0) d.Rrp[ri.r] = ri.off;
+    const int myN = (lane < s) ? myN0 : 0x7fffffff;
+    gb.nb[lane] = myN;
     const uint64_t below = __ballot(lane < s && myN < i);
     const int dpos = __popcll((below >> ((threadIdx.x & 63) - lane)) & ((G >= 64) ? ~0ull : ((1ull << G) - 1)));
 
     // ---- gather: K = (A[N,N])^T (padded with identity), f = -A[i,N] ----
 #pragma unroll
-    for (int t = 0; t < G; ++t) gb.K[t * LD + lane] = (t == lane && t >= s) ? 1.0 : 0.0;
+    for (int tt = 0; tt < G; ++tt) gb.K[tt * LD + lane] = (tt == lane && tt >= s) ? 1.0 : 0.0;
     gb.f[lane] = 0.0;
     wave_sync();
     if (lane < s) {
       const int e1 = d.rp[myN + 1];
-      for (int e = d.rp[myN]; e < e1; ++e) {
-        const int q = find_sorted(N, s, d.ci[e]);
-        if (q >= 0) gb.K[q * LD + lane] = d.va[e];
+      for (int e = d.rp[myN]; e < e1; e += 4) {
+        int k[4];
+        double v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          k[j] = -1;
+          v[j] = 0.0;
+          if (e + j < e1) { k[j] = d.ci[e + j]; v[j] = d.va[e + j]; }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int qq = find_sorted(gb.nb, s, k[j]);
+          if (qq >= 0) gb.K[qq * LD + lane] = v[j];
+        }
       }
     }
     {
       const int e1 = d.rp[i + 1];
       for (int e = d.rp[i] + lane; e < e1; e += G) {
-        const int q = find_sorted(N, s, d.ci[e]);
-        if (q >= 0) gb.f[q] = -d.va[e];
+        const int qq = find_sorted(gb.nb, s, d.ci[e]);
+        if (qq >= 0) gb.f[qq] = -d.va[e];
       }
     }
     wave_sync();
@@ -495,17 +587,22 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w) {
         z += (double)dz;
         wave_sync();
       }
-      if (!(z == z)) conv = false;  // NaN guard (lane-uniform after the test below)
+      if (!(z == z)) conv = false;
       conv = group_ori<G>(conv ? 0 : 1) == 0;
     }
     if (!conv) {
+      // FP32 factorisation not trusted: the workgroup solver redoes the row in FP64
       if (lane == 0) {
-        const int q = atomicAdd(&w.cnt->queue_len, 1);
-        if (q < w.queue_cap) w.queue[q] = g;
+        const int qc = atomicAdd(&w.cnt->nC, 1);
+        if (qc < w.capC) w.binC[qc] = entry;
+        else flag_row(st, ST_UNSUPPORTED, i);
       }
       continue;
     }
-    if (lane == 0) atomicMax(&st->refine_max, it);
+    if (lane == 0) {
+      if (ri.m == m0) atomicMax(&s_itmax, it);
+      else atomicMax(&st->refine_max, it);
+    }
 
     // ---- R row: F-entries of N(i) around the injected C-point ----
     if (lane < s) {
@@ -523,10 +620,12 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w) {
       d.Rva[ri.off + dpos] = 1.0;
     }
   }
+  __syncthreads();
+  if (tid == 0 && s_itmax > 0) atomicMax(&w.st[m0].refine_max, s_itmax);
 }
 
 // ---------------------------------------------------------------------------
-// workgroup-per-row FP64 solver (queued rows)
+// workgroup-per-row FP64 solver (bin C)
 // ---------------------------------------------------------------------------
 struct WgBuf {
   int nb0[kWN], nb1[kWN], fr[kWN];
@@ -564,33 +663,36 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
 
   const int tid = threadIdx.x;
   BlockTeam tm{kWT, tid};
-  const int qlen = min(w.cnt->queue_len, w.queue_cap);
-  if (tid == 0 && blockIdx.x == 0 && w.cnt->queue_len > w.queue_cap) {
-    for (int m = 0; m < w.nmat; ++m) atomicCAS(&w.st[m].status, 0, (int)ST_UNSUPPORTED);
-  }
+  const int qlen = min(w.cnt->nC, w.capC);
+  // FP64 rows solved by this workgroup, per run of rows of one matrix
+  int run_m = -1, run_n = 0;
   for (int pass = 0; pass < 2; ++pass) {
     // pass 0: blocks that fit in LDS, all workgroups; pass 1: larger blocks,
     // one global scratch slot per workgroup
     if (pass == 1 && (int64_t)blockIdx.x >= w.scratch_slots) {
-      // no scratch slot: report oversized rows instead of solving them
-      for (int qi = blockIdx.x; qi < qlen; qi += gridDim.x) {
-        const int g = w.queue[qi];
-        const int c = row_chunk(w.chunk_rbase, w.nchunks, g);
-        const RowInfo ri = row_info(w, c, g);
-        if (ri.s > kLdsBlockMax && tid == 0 && w.scratch_slots == 0) flag_row(&w.st[ri.m], ST_UNSUPPORTED, ri.i);
+      if (w.scratch_slots == 0) {
+        // no scratch: report oversized rows instead of solving them
+        for (int qi = blockIdx.x; qi < qlen; qi += gridDim.x) {
+          const int e = w.binC[qi];
+          const int c = e / w.chunk;
+          const RowInfo ri = row_info(w, c, e - c * w.chunk);
+          if (ri.s > kLdsBlockMax && tid == 0) flag_row(&w.st[ri.m], ST_UNSUPPORTED, ri.i);
+        }
       }
       continue;
     }
     const int stride = (pass == 0) ? gridDim.x : (int)min<int64_t>(gridDim.x, w.scratch_slots);
     for (int qi = blockIdx.x; qi < qlen; qi += stride) {
-      const int g = w.queue[qi];
-      const int c = row_chunk(w.chunk_rbase, w.nchunks, g);
-      const RowInfo ri = row_info(w, c, g);
+      const int e = w.binC[qi];
+      const int c = e / w.chunk;
+      const RowInfo ri = row_info(w, c, e - c * w.chunk);
       const bool big = ri.s > kLdsBlockMax;
       if (big != (pass == 1)) continue;
       MatStatus* st = &w.st[ri.m];
+      if (!matrix_live(*st)) continue;
       const MatDesc& d = w.desc[ri.m];
       const int i = ri.i;
+      if (tid == 0) d.Rrp[ri.r] = ri.off;
       int* N;
       const int s = team_bfs(tm, d.n, i, d.ell, d.rp, d.ci, d.va, d.cf,
                              BfsBuf{bb.nb0, bb.nb1, bb.fr, bb.cand, bb.keep, bb.cnt, kWN, kWC}, &N);
@@ -609,14 +711,14 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
       for (int p = tid; p < s; p += kWT) {
         const int u = N[p];
         const int e1 = d.rp[u + 1];
-        for (int e = d.rp[u]; e < e1; ++e) {
-          const int q = find_sorted(N, s, d.ci[e]);
-          if (q >= 0) K[(int64_t)q * ld + p] = d.va[e];
+        for (int ee = d.rp[u]; ee < e1; ++ee) {
+          const int q = find_sorted(N, s, d.ci[ee]);
+          if (q >= 0) K[(int64_t)q * ld + p] = d.va[ee];
         }
       }
-      for (int e = d.rp[i] + tid; e < d.rp[i + 1]; e += kWT) {
-        const int q = find_sorted(N, s, d.ci[e]);
-        if (q >= 0) sf[q] = -d.va[e];
+      for (int ee = d.rp[i] + tid; ee < d.rp[i + 1]; ee += kWT) {
+        const int q = find_sorted(N, s, d.ci[ee]);
+        if (q >= 0) sf[q] = -d.va[ee];
       }
       __syncthreads();
       // max |K| for the singularity threshold
@@ -669,7 +771,14 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
           __syncthreads();
         }
       }
-      if (tid == 0) atomicAdd(&st->n_fp64, 1);
+      if (tid == 0) {
+        if (ri.m != run_m) {
+          if (run_n) atomicAdd(&w.st[run_m].n_fp64, run_n);
+          run_m = ri.m;
+          run_n = 0;
+        }
+        ++run_n;
+      }
       // R row
       int dpos = 0;
       {
@@ -698,6 +807,7 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
       __syncthreads();
     }
   }
+  if (tid == 0 && run_n) atomicAdd(&w.st[run_m].n_fp64, run_n);
 }
 
 // ---------------------------------------------------------------------------
@@ -720,7 +830,7 @@ __global__ __launch_bounds__(256) void k_project(Work w) {
     const int g = gbase + grp;
     if (g >= r1) break;
     while (w.chunk_rbase[c + 1] <= g) ++c;
-    const RowInfo ri = row_info(w, c, g);
+    const RowInfo ri = row_info(w, c, g - w.chunk_rbase[c]);
     const MatStatus& st = w.st[ri.m];
     const MatDesc& d = w.desc[ri.m];
     if (!matrix_live(st) || !d.B) continue;
@@ -732,16 +842,21 @@ __global__ __launch_bounds__(256) void k_project(Work w) {
       if (dj > 0.0) d.Rva[e] -= bi * (w.rsum[ri.fine0 + j] - d.B[j]) / dj;
     }
   }
-  // uncovered F-points
+  // uncovered F-points: one global atomic per workgroup and matrix
+  __shared__ int s_unc;
   for (int m = 0; m < w.nmat; ++m) {
     const MatDesc& d = w.desc[m];
-    if (!d.B || !matrix_live(w.st[m])) continue;
+    if (!d.B || !matrix_live(w.st[m])) continue;  // uniform
+    if (tid == 0) s_unc = 0;
+    __syncthreads();
     int cnt = 0;
     for (int j = blockIdx.x * blockDim.x + tid; j < d.n; j += gridDim.x * blockDim.x)
       cnt += (d.cf[j] == 0 && !(w.dsum[d.fine0 + j] > 0.0)) ? 1 : 0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-    if ((tid & 63) == 0 && cnt) atomicAdd((unsigned long long*)&w.st[m].n_uncovered, (unsigned long long)cnt);
+    if ((tid & 63) == 0 && cnt) atomicAdd(&s_unc, cnt);
+    __syncthreads();
+    if (tid == 0 && s_unc) atomicAdd((unsigned long long*)&w.st[m].n_uncovered, (unsigned long long)s_unc);
   }
 }
 
@@ -758,17 +873,27 @@ hipError_t launch_count(const Work& w, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_count_big(const Work& w, int blocks, hipStream_t s) {
+  if (w.nchunks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_count_big, dim3(blocks), dim3(kNT), 0, s, w);
+  return hipGetLastError();
+}
+
 hipError_t launch_scan(const Work& w, hipStream_t s) {
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, w);
   return hipGetLastError();
 }
 
-hipError_t launch_numeric(const Work& w, int group, int wg_threads, int blocks, hipStream_t s) {
-  blocks = (blocks + 7) / 8 * 8;
-#define CLAIR_NUM(GG, NTT)                                                      \
-  if (group == GG && wg_threads == NTT) {                                       \
-    hipLaunchKernelGGL((k_numeric<GG, NTT>), dim3(blocks), dim3(NTT), 0, s, w); \
-    return hipGetLastError();                                                   \
+// persistent grid: as many workgroups as fit on the device at once
+hipError_t launch_numeric(const Work& w, int which, int group, int wg_threads, int cus, hipStream_t s) {
+#define CLAIR_NUM(GG, NTT)                                                                        \
+  if (group == GG && wg_threads == NTT) {                                                         \
+    int per = 0;                                                                                  \
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_numeric<GG, NTT>, NTT, 0); \
+    if (e != hipSuccess) return e;                                                                \
+    const int blocks = (std::max(1, per) * cus + 7) / 8 * 8;                                     \
+    hipLaunchKernelGGL((k_numeric<GG, NTT>), dim3(blocks), dim3(NTT), 0, s, w, which);            \
+    return hipGetLastError();                                                                     \
   }
   CLAIR_NUM(8, 256)
   CLAIR_NUM(8, 128)

@@ -112,17 +112,24 @@ __global__ void k_p_clist(PlainWork p) {
 
 __global__ void k_p_sizes(PlainWork p, int n_c) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_c) return;
-  int N[kPlainCap];
-  const int i = p.clist[r];
-  const int s = plain_bfs(p, i, N);
-  if (s < 0) {
-    pflag(p.flags, ST_UNSUPPORTED, i);
-    p.sizes[r] = 1;
-    return;
+  int s = 0;
+  if (r < n_c) {
+    int N[kPlainCap];
+    const int i = p.clist[r];
+    s = plain_bfs(p, i, N);
+    if (s < 0) {
+      pflag(p.flags, ST_UNSUPPORTED, i);
+      s = 0;
+    }
+    p.sizes[r] = s + 1;
   }
-  p.sizes[r] = s + 1;
-  atomicMax(&p.flags[PF_MAX_BLOCK], s);
+  // largest block: reduced over the workgroup, one atomic per workgroup
+  __shared__ int smax;
+  if (threadIdx.x == 0) smax = 0;
+  __syncthreads();
+  atomicMax(&smax, s);
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(&p.flags[PF_MAX_BLOCK], smax);
 }
 
 // three-phase scan of sizes[0..n) into R.row_ptr
@@ -258,8 +265,8 @@ __global__ void k_p_colsum(PlainWork p, int n_c) {
   for (int e = p.Rrp[r]; e < p.Rrp[r + 1]; ++e) {
     const int j = p.Rci[e];
     if (j == i) continue;
-    atomicAdd(&p.dsum[j], bi * bi);
-    atomicAdd(&p.rsum[j], p.Rva[e] * bi);
+    unsafeAtomicAdd(&p.dsum[j], bi * bi);
+    unsafeAtomicAdd(&p.rsum[j], p.Rva[e] * bi);
   }
 }
 

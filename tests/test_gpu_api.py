@@ -1,0 +1,186 @@
+"""GPU tests of the entry points around the setup: asynchronous calls,
+hipGraph replay, size queries and capacity errors, device-side validation,
+singular blocks, per-stage timing and the autotuner."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_00229_amd import problems as P
+
+from ._util import assert_matches_oracle, to_device
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _fetch(o):
+    rp, ci, va = o.trimmed()
+    return dict(row_ptr=rp.cpu().numpy(), col_idx=ci.cpu().numpy(), val=va.cpu().numpy(), n_c=o.n_c, nnz=o.nnz)
+
+
+def _cases():
+    return [P.small_2d(200, stencil=5, eps=1e-3, angle=0.5, ell=2),
+            P.small_2d(150, stencil=9, eps=0.1, angle=3.0, k=3, ell=2),
+            P.small_3d(24, eps=1e-2, b=(1.0, 0.5, 0.25), ell=2)]
+
+
+def test_async_then_ctx_info():
+    from paper_2307_00229_amd import clair
+
+    ps = _cases()
+    As, cfs, Bs, ells = to_device(ps)
+    ctx = clair.Context()
+    ncs, nzs = clair.clair_size_R(As, cfs, ells, ctx=ctx)
+    outs = [clair.ROut(a, b) for a, b in zip(ncs, nzs)]
+    s = torch.cuda.Stream()
+    print("[gpu] async enqueue", flush=True)
+    for _ in range(3):
+        clair.clair_build_R_batched(As, cfs, Bs, ells, ctx=ctx, outs=outs, async_=True, stream=s)
+    st, infos = ctx.info(len(ps), outs)
+    assert st == 0, infos
+    for p, o, inf in zip(ps, outs, infos):
+        assert_matches_oracle(p, _fetch(o), oracle.build_R_problem(p), inf)
+
+
+def test_graph_replay_matches_eager():
+    from paper_2307_00229_amd import clair
+
+    ps = _cases()
+    As, cfs, Bs, ells = to_device(ps)
+    ctx = clair.Context()
+    eager, _, _ = clair.clair_build_R_batched(As, cfs, Bs, ells, ctx=ctx)
+    ref = [_fetch(o) for o in eager]
+    outs = [clair.ROut(o.n_c, o.nnz) for o in eager]
+    s = torch.cuda.Stream()
+    print("[gpu] graph capture", flush=True)
+    g = clair.Graph(ctx, As, cfs, Bs, ells, outs, stream=s)
+    for rep in range(4):
+        for o in outs:
+            o.val.fill_(-7.0)
+            o.col_idx.fill_(-1)
+        torch.cuda.synchronize()
+        g.launch(s)
+        s.synchronize()
+        st, infos = g.info()
+        assert st == 0, infos
+        # eager work between replays
+        clair.clair_build_R_batched(As, cfs, Bs, ells, ctx=ctx)
+        for r, o, inf in zip(ref, outs, infos):
+            got = _fetch(o)
+            assert np.array_equal(got["row_ptr"], r["row_ptr"]) and np.array_equal(got["col_idx"], r["col_idx"])
+            np.testing.assert_allclose(got["val"], r["val"], rtol=1e-13, atol=1e-15)
+            assert inf["nnz"] == r["nnz"]
+    # new values in A (same pattern) flow into the next replay
+    for a in As:
+        a.val.mul_(3.0)
+    g.launch(s)
+    s.synchronize()
+    for p, o in zip(ps, outs):
+        q = P.Problem(p.name, p.n, p.row_ptr, p.col_idx, p.val * 3.0, p.cf, p.B, p.ell)
+        assert_matches_oracle(q, _fetch(o), oracle.build_R_problem(q))
+    g.close()
+
+
+def test_size_query_and_capacity_error():
+    from paper_2307_00229_amd import clair
+
+    p = P.cfg1()
+    As, cfs, Bs, ells = to_device([p])
+    ctx = clair.Context()
+    small = [clair.ROut(256, 100)]
+    outs, infos, st = clair.clair_build_R_batched(As, cfs, Bs, ells, ctx=ctx, outs=small, check=False)
+    assert st == clair.CLAIR_ERR_CAPACITY
+    assert infos[0]["nnz"] == 1248 and infos[0]["n_c"] == 256
+    short_rows = [clair.ROut(10, 5000)]
+    outs, infos, st = clair.clair_build_R_batched(As, cfs, Bs, ells, ctx=ctx, outs=short_rows, check=False)
+    assert st == clair.CLAIR_ERR_CAPACITY
+    # one matrix too small in a batch does not stop the others
+    ps = [p, P.small_2d(40, ell=2)]
+    As2, cfs2, Bs2, ells2 = to_device(ps)
+    ncs, nzs = clair.clair_size_R(As2, cfs2, ells2, ctx=ctx)
+    outs = [clair.ROut(ncs[0], 10), clair.ROut(ncs[1], nzs[1])]
+    outs, infos, st = clair.clair_build_R_batched(As2, cfs2, Bs2, ells2, ctx=ctx, outs=outs, check=False)
+    assert st == clair.CLAIR_ERR_CAPACITY
+    assert infos[0]["status"] == clair.CLAIR_ERR_CAPACITY and infos[1]["status"] == 0
+    assert_matches_oracle(ps[1], _fetch(outs[1]), oracle.build_R_problem(ps[1]))
+
+
+def test_validation_rejects_unsorted_and_out_of_range():
+    from paper_2307_00229_amd import clair
+
+    p = P.small_2d(16, ell=2)
+    ci = p.col_idx.copy()
+    ci[1], ci[2] = ci[2], ci[1]
+    q = P.Problem("unsorted", p.n, p.row_ptr, ci, p.val, p.cf, p.B, 2)
+    r = P.Problem("range", p.n, p.row_ptr, np.where(np.arange(len(ci)) == 7, p.n + 5, p.col_idx).astype(np.int32),
+                  p.val, p.cf, p.B, 2)
+    As, cfs, Bs, ells = to_device([q, r, p])
+    ctx = clair.Context()
+    outs = [clair.ROut(p.n, 20 * p.n) for _ in range(3)]
+    outs, infos, st = clair.clair_build_R_batched(As, cfs, Bs, ells, ctx=ctx, outs=outs, validate=True, check=False)
+    assert infos[0]["status"] == clair.CLAIR_ERR_INVALID and infos[0]["first_bad_row"] == 0
+    assert infos[1]["status"] == clair.CLAIR_ERR_INVALID
+    assert infos[2]["status"] == 0
+    assert_matches_oracle(p, _fetch(outs[2]), oracle.build_R_problem(p))
+
+
+def test_bad_arguments_rejected_on_host():
+    from paper_2307_00229_amd import clair
+
+    p = P.small_2d(8, ell=1)
+    As, cfs, Bs, ells = to_device([p])
+    with pytest.raises(clair.ClairError) as e:
+        clair.clair_build_R_batched(As, cfs, Bs, [0], outs=[clair.ROut(16, 100)])
+    assert e.value.status == clair.CLAIR_ERR_INVALID
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_singular_block_reported(precision):
+    from paper_2307_00229_amd import clair
+
+    n = 3
+    p = P.Problem("sing", n, np.array([0, 3, 6, 9], np.int32), np.array([0, 1, 2] * 3, np.int32),
+                  np.array([4.0, -1.0, -1.0, -1.0, 1.0, 1.0, -1.0, 1.0, 1.0]), np.array([1, 0, 0], np.int8), None, 1)
+    As, cfs, Bs, ells = to_device([p])
+    outs, infos, st = clair.clair_build_R_batched(As, cfs, Bs, ells, outs=[clair.ROut(1, 3)], precision=precision,
+                                                  check=False)
+    assert st == clair.CLAIR_ERR_SINGULAR
+    assert infos[0]["first_bad_row"] == 0
+
+
+def test_stage_timing_and_autotune():
+    from paper_2307_00229_amd import clair
+
+    ps = _cases()
+    As, cfs, Bs, ells = to_device(ps)
+    ctx = clair.Context()
+    ncs, nzs = clair.clair_size_R(As, cfs, ells, ctx=ctx)
+    outs = [clair.ROut(a, b) for a, b in zip(ncs, nzs)]
+    tuning = clair.clair_autotune(ctx, As, cfs, Bs, ells, outs, reps=1)
+    assert tuning["group"] in (8, 16, 32)
+    for p, o in zip(ps, outs):
+        assert_matches_oracle(p, _fetch(o), oracle.build_R_problem(p))
+    ctx.stage_times()
+    for _ in range(2):
+        clair.clair_build_R_batched(As, cfs, Bs, ells, ctx=ctx, outs=outs, timing=True)
+    t = ctx.stage_times()
+    assert {"count", "scan", "numeric", "project"} <= set(t)
+    assert all(v >= 0 for v in t.values())
+
+
+def test_repeat_runs_identical_pattern_and_close_values():
+    from paper_2307_00229_amd import clair
+
+    p = P.cfg1()
+    As, cfs, Bs, ells = to_device([p])
+    a = _fetch(clair.clair_build_R_batched(As, cfs, Bs, ells)[0][0])
+    b = _fetch(clair.clair_build_R_batched(As, cfs, Bs, ells)[0][0])
+    assert np.array_equal(a["col_idx"], b["col_idx"])
+    # the projection sums use FP64 atomics: only the last bits may differ
+    np.testing.assert_allclose(a["val"], b["val"], rtol=1e-14, atol=1e-16)
