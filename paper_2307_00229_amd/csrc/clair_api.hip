@@ -101,7 +101,7 @@ Layout make_layout(int nmat, int nchunks, int64_t n_total, int GA) {
   L.lnz = take(sizeof(int32_t) * (n_total + 1));
   L.dsum = take(sizeof(double) * (n_total + 1));
   L.rsum = take(sizeof(double) * (n_total + 1));
-  L.slotA = take(sizeof(int32_t) * (n_total + 1) * GA);
+  L.slotA = take(sizeof(int32_t) * (GA >= 8 ? (n_total + 1) * GA : 1));
   L.slotB = take(sizeof(int32_t) * (n_total + 1) * (GA < 32 ? 32 : 1));
   L.binC = take(sizeof(int32_t) * L.capC);
   L.ovf = take(sizeof(int32_t) * (nchunks + 1));
@@ -123,7 +123,7 @@ struct clair_ctx {
   int device = 0;
   int cus = 256;
   // tuning
-  int group = 8;
+  int group = 1;  // 1: one thread per row for |N| <= 8; 8/16/32: lane groups
   int wg_threads = 256;
   int chunk = 2048;
   // memory
@@ -357,7 +357,11 @@ int enqueue_numeric(clair_ctx* c, Batch& b, hipStream_t s, bool timing, const Co
   b.w.scratch = static_cast<double*>(c->scratch.p);
   b.w.scratch_slots = c->scratch_slots;
   if (!known || known->nA > 0) {
-    HIPCHK(launch_numeric(b.w, 0, c->group, c->wg_threads, c->cus, s));
+    if (c->group == 1) {
+      HIPCHK(launch_rows8(b.w, c->wg_threads, c->cus, s));
+    } else {
+      HIPCHK(launch_numeric(b.w, 0, c->group, c->wg_threads, c->cus, s));
+    }
     if (capture_check(c->capturing, s, "k_numeric", __LINE__)) return CLAIR_ERR_HIP;
   }
   timing_mark(c, timing, s, "numeric");
@@ -780,7 +784,7 @@ int clair_ctx_stage_times(clair_ctx_t* c, const char** names, float* ms, int32_t
 
 int clair_ctx_set_tuning(clair_ctx_t* c, int32_t group, int32_t wg_threads, int32_t chunk) {
   if (!c) return CLAIR_ERR_INVALID;
-  if (group && group != 8 && group != 16 && group != 32) return CLAIR_ERR_INVALID;
+  if (group && group != 1 && group != 8 && group != 16 && group != 32) return CLAIR_ERR_INVALID;
   if (wg_threads && wg_threads != 64 && wg_threads != 128 && wg_threads != 256) return CLAIR_ERR_INVALID;
   if (chunk && (chunk < 256 || chunk > kMaxChunk || (chunk % 256))) return CLAIR_ERR_INVALID;
   if (group) c->group = group;
@@ -807,7 +811,7 @@ int clair_autotune(clair_ctx_t* c, int32_t nmat, const clair_csr_t* A, const int
   o.stream = stream;
   int rc = clair_build_R_batched(c, nmat, A, cf, B, ell, R, &o, info.data());
   if (rc) return rc;
-  const int groups[3] = {8, 16, 32};
+  const int groups[4] = {1, 8, 16, 32};
   const int threads[3] = {64, 128, 256};
   const int chunks[3] = {512, 1024, 2048};
   hipEvent_t e0, e1;

@@ -243,6 +243,99 @@ __device__ int team_bfs(const Team& tm, int n, int i, int ell, const int32_t* __
   return s;
 }
 
+// Register-resident neighbourhood search of one thread, for neighbourhoods of
+// at most SM points: the same set as team_bfs, kept sorted in N[0..s) (empty
+// slots hold INT32_MAX).  Returns s, or -1 when more than SM points are found.
+template <int SM>
+struct RegSet {
+  int v[SM];    // sorted points
+  int lev[SM];  // the level (hop count) at which each point was found
+  int s;
+  bool ovf;
+
+  __device__ __forceinline__ void clear() {
+#pragma unroll
+    for (int j = 0; j < SM; ++j) { v[j] = 0x7fffffff; lev[j] = 0; }
+    s = 0;
+    ovf = false;
+  }
+  __device__ __forceinline__ void insert(int k, int L) {
+    bool present = false;
+    int pos = 0;
+#pragma unroll
+    for (int j = 0; j < SM; ++j) {
+      present |= (v[j] == k);
+      pos += (v[j] < k) ? 1 : 0;
+    }
+    if (present) return;
+    if (s == SM) { ovf = true; return; }
+#pragma unroll
+    for (int j = SM - 1; j > 0; --j) {
+      if (j > pos) { v[j] = v[j - 1]; lev[j] = lev[j - 1]; }
+    }
+#pragma unroll
+    for (int j = 0; j < SM; ++j) {
+      if (j == pos) { v[j] = k; lev[j] = L; }
+    }
+    ++s;
+  }
+};
+
+// the F-neighbours of u (edges with a stored nonzero), added at level L;
+// entries are read four at a time
+template <int SM>
+__device__ __forceinline__ void reg_expand(RegSet<SM>& S, int n, int u, int L, const int32_t* __restrict__ rp,
+                                           const int32_t* __restrict__ ci, const double* __restrict__ va,
+                                           const int8_t* __restrict__ cf) {
+  const int e1 = rp[u + 1];
+  for (int e = rp[u]; e < e1 && !S.ovf; e += 4) {
+    int k[4];
+    double v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      k[j] = u;
+      v[j] = 0.0;
+      if (e + j < e1) { k[j] = ci[e + j]; v[j] = va[e + j]; }
+    }
+    int8_t c8[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c8[j] = ((unsigned)k[j] < (unsigned)n) ? cf[k[j]] : (int8_t)1;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (k[j] != u && v[j] != 0.0 && c8[j] == 0) S.insert(k[j], L);
+    }
+  }
+}
+
+template <int SM>
+__device__ __forceinline__ int reg_bfs(RegSet<SM>& S, int n, int i, int ell, const int32_t* __restrict__ rp,
+                                       const int32_t* __restrict__ ci, const double* __restrict__ va,
+                                       const int8_t* __restrict__ cf) {
+  S.clear();
+  reg_expand(S, n, i, 1, rp, ci, va, cf);
+  for (int L = 2; L <= ell && !S.ovf; ++L) {
+    // expand the points found at level L-1 in ascending order (from a
+    // snapshot: inserts move entries); only compile-time register indices
+    int fv[SM], fl[SM];
+#pragma unroll
+    for (int j = 0; j < SM; ++j) { fv[j] = S.v[j]; fl[j] = S.lev[j]; }
+    int last = -1;
+    bool any = false;
+    while (!S.ovf) {
+      int u = 0x7fffffff;
+#pragma unroll
+      for (int j = 0; j < SM; ++j)
+        if (fl[j] == L - 1 && fv[j] > last && fv[j] < u) u = fv[j];
+      if (u == 0x7fffffff) break;
+      reg_expand(S, n, u, L, rp, ci, va, cf);
+      last = u;
+      any = true;
+    }
+    if (!any) break;
+  }
+  return S.ovf ? -1 : S.s;
+}
+
 // matrix owning global chunk c (desc[].chunk0 ascending)
 __device__ __forceinline__ int chunk_matrix(const MatDesc* desc, int nmat, int c) {
   int lo = 0, hi = nmat - 1;

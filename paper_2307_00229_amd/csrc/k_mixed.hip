@@ -37,7 +37,8 @@ constexpr int kNT = 256;  // threads per workgroup of the symbolic pass
 // to 32 points and 128 candidates per level; larger rows go to k_count_big
 constexpr int kCountG = 8;
 constexpr int kCountGN = 32;
-constexpr int kCountGC = 128;
+constexpr int kCountGC = 64;
+constexpr int kCountNG2 = 16;  // lane groups of the second phase (two wavefronts)
 // workgroup-wide search caps
 constexpr int kWN = kMaxBlock;
 constexpr int kWC = 4096;
@@ -151,13 +152,18 @@ struct CountGroupBuf {
   int cnt[2];
 };
 
+// rows the small solvers take: |N| <= 8 for the thread-per-row solver
+// (GA == 1), |N| <= GA for the lane-group solver
+__device__ __forceinline__ int small_limit(int GA) { return GA == 1 ? 8 : GA; }
+
 __global__ __launch_bounds__(kNT) void k_count(Work w) {
-  constexpr int NG = kNT / kCountG;
+  constexpr int NG = kCountNG2;
   __shared__ int s_rows[kMaxChunk];
-  __shared__ int s_size[kMaxChunk];
+  __shared__ int16_t s_size[kMaxChunk];
   __shared__ int s_scan[kNT];
   __shared__ CountGroupBuf gbuf[NG];
-  __shared__ int s_flag[4];  // max |N|, unresolved rows, rows in slots A, rows in slots B
+  __shared__ int16_t s_list[kMaxChunk];  // rows left for the lane-group search
+  __shared__ int s_flag[5];  // max |N|, unresolved rows, rows in bin A, rows in bin B, list length
 
   const int c = xcd_logical_block();
   const int tid = threadIdx.x;
@@ -186,49 +192,73 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
   int nc;
   int rank = block_exclusive_scan(myc, s_scan, &nc);
   for (int j = j0; j < min(j0 + per, f1); ++j) {
-    if (d.cf[j] != 0) { s_rows[rank] = j; ++rank; }
+    if (d.cf[j] != 0) { s_rows[rank] = j; w.clocal[base + rank] = j; ++rank; }
   }
-  if (tid == 0) { s_flag[0] = 0; s_flag[1] = 0; s_flag[2] = 0; s_flag[3] = 0; }
+  if (tid == 0) { s_flag[0] = 0; s_flag[1] = 0; s_flag[2] = 0; s_flag[3] = 0; s_flag[4] = 0; }
   __syncthreads();
 
-  // N(i) per C-row, kCountG lanes per row; queue by block size
+  const int GA = w.GA;
+  const int lim = small_limit(GA);
+  int inA = 0, inB = 0, unresolved = 0;
+
+  // phase 1: one thread per C-row, neighbourhoods of up to 8 points in registers
+  for (int t = tid; t < nc; t += kNT) {
+    RegSet<8> S;
+    const int sz = reg_bfs(S, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf);
+    if (sz >= 0) {
+      s_size[t] = sz;
+      ++inA;  // sz <= 8 <= lim
+      if (GA >= 8) {
+#pragma unroll
+        for (int p = 0; p < 8; ++p)
+          if (p < sz) w.slotA[(base + t) * GA + p] = S.v[p];
+      }
+    } else {
+      s_size[t] = -1;
+      s_list[atomicAdd(&s_flag[4], 1)] = t;
+    }
+  }
+  __syncthreads();
+
+  // phase 2: kCountG lanes per remaining row, up to 32 points in LDS
+  const int nl2 = s_flag[4];
   const int grp = tid / kCountG;
   const int gl = tid % kCountG;
   GroupTeam<kCountG> tm{gl};
-  CountGroupBuf& gb = gbuf[grp];
+  CountGroupBuf& gb = gbuf[grp < NG ? grp : 0];
   const BfsBuf bb{gb.nb0, gb.nb1, gb.fr, gb.cand, gb.keep, gb.cnt, kCountGN, kCountGC};
-  const int GA = w.GA;
-  int unresolved = 0, inA = 0, inB = 0;
-  for (int t0 = 0; t0 < nc; t0 += NG) {  // uniform trip count: all groups meet at the append
-    const int t = t0 + grp;
-    const bool active = t < nc;
-    int s = 0;
+  // the first NG groups (whole wavefronts) take these rows; the loop trip
+  // count is uniform so all groups of a wavefront meet at the append
+  for (int k0 = 0; k0 < nl2 && tid < NG * kCountG; k0 += NG) {
+    const int k = k0 + grp;
+    const bool active = k < nl2;
+    int sz = 0;
     int* nl = gb.nb0;
-    int i = 0;
+    int t = 0;
     if (active) {
-      i = s_rows[t];
-      s = team_bfs(tm, d.n, i, d.ell, d.rp, d.ci, d.va, d.cf, bb, &nl);
-      if (s >= 0 && s <= GA) {
-        for (int p = gl; p < s; p += kCountG) w.slotA[(base + t) * GA + p] = nl[p];
+      t = s_list[k];
+      sz = team_bfs(tm, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf, bb, &nl);
+      if (sz >= 0 && sz <= lim) {
+        if (GA >= 8)
+          for (int p = gl; p < sz; p += kCountG) w.slotA[(base + t) * GA + p] = nl[p];
         inA += (gl == 0);
-      } else if (s > GA && s <= 32) {
-        for (int p = gl; p < s; p += kCountG) w.slotB[(base + t) * 32 + p] = nl[p];
+      } else if (sz > lim && sz <= 32) {
+        for (int p = gl; p < sz; p += kCountG) w.slotB[(base + t) * 32 + p] = nl[p];
         inB += (gl == 0);
       }
     }
     const bool lead = active && gl == 0;
-    // rows the lane-group solvers cannot take: workgroup solver (s < 0 is
-    // sized by k_count_big first)
-    const int qc = wave_append(lead && s > 32, &w.cnt->nC, w.capC);
+    // more than 32 points: the workgroup solver (unsized rows are sized by
+    // k_count_big first)
+    const int qc = wave_append(lead && sz > 32, &w.cnt->nC, w.capC);
     if (qc >= 0) w.binC[qc] = c * w.chunk + t;
     if (lead) {
-      if (s < 0) {
+      if (sz < 0) {
         ++unresolved;
         s_size[t] = 0;
-        w.clocal[base + t] = -(i + 1);  // k_count_big sizes it
+        w.clocal[base + t] = -(s_rows[t] + 1);  // k_count_big sizes it
       } else {
-        s_size[t] = s;
-        w.clocal[base + t] = i;
+        s_size[t] = sz;
       }
     }
     wave_sync();
@@ -300,9 +330,11 @@ __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
                              BfsBuf{bb.nb0, bb.nb1, bb.fr, bb.cand, bb.keep, bb.cnt, kWN, kWC}, &nl);
       __syncthreads();
       // small enough for a lane-group solver: its slot; else the workgroup solver
-      if (s >= 0 && s <= w.GA) {
-        for (int p = tid; p < s; p += kNT) w.slotA[(base + t) * w.GA + p] = nl[p];
-      } else if (s > w.GA && s <= 32) {
+      const int lim = small_limit(w.GA);
+      if (s >= 0 && s <= lim) {
+        if (w.GA >= 8)
+          for (int p = tid; p < s; p += kNT) w.slotA[(base + t) * w.GA + p] = nl[p];
+      } else if (s > lim && s <= 32) {
         for (int p = tid; p < s; p += kNT) w.slotB[(base + t) * 32 + p] = nl[p];
       }
       if (tid == 0) {
@@ -313,7 +345,7 @@ __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
         } else {
           s_size[t] = s;
           s_max = max(s_max, s);
-          if (s <= w.GA) {
+          if (s <= lim) {
             atomicAdd(&w.cnt->nA, 1);
           } else if (s <= 32) {
             atomicAdd(&w.cnt->nB, 1);
@@ -459,7 +491,7 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
 
   // rows of this solver: |N| <= G (small solver) or GA < |N| <= 32 (which = 1)
   if ((which ? w.cnt->nB : w.cnt->nA) == 0) return;
-  const int smin = which ? w.GA + 1 : 0;
+  const int smin = which ? small_limit(w.GA) + 1 : 0;
   const int32_t* slots = which ? w.slotB : w.slotA;
   const int sstride = which ? 32 : w.GA;
   const int total = w.cnt->total_rows;
@@ -619,6 +651,232 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
       d.Rci[ri.off + dpos] = i;
       d.Rva[ri.off + dpos] = 1.0;
     }
+  }
+  __syncthreads();
+  if (tid == 0 && s_itmax > 0) atomicMax(&w.st[m0].refine_max, s_itmax);
+}
+
+// ---------------------------------------------------------------------------
+// numeric pass, one thread per row with |N| <= 8: neighbourhood search, the
+// FP32 block, its LU and both triangular solves all stay in registers; the
+// FP64 residual re-reads the block's entries from A (cache-resident).  In a
+// wavefront, consecutive lanes take consecutive C-points, so their loads of
+// the same neighbour's row fall on neighbouring cache lines.
+// ---------------------------------------------------------------------------
+constexpr int kS8 = 8;
+
+// position of column k in the sorted neighbourhood N (and whether it is there)
+__device__ __forceinline__ int pos8(const int (&N)[kS8], int k, bool* hit) {
+  int q = 0;
+  bool h = false;
+#pragma unroll
+  for (int j = 0; j < kS8; ++j) {
+    q += (N[j] < k) ? 1 : 0;
+    h |= (N[j] == k);
+  }
+  *hit = h;
+  return q;
+}
+
+// y <- K^{-1} y with the packed no-pivot LU of K (unit lower L, upper U)
+__device__ __forceinline__ void lu8_solve(const float (&K)[kS8][kS8], const float (&inv)[kS8], float (&y)[kS8]) {
+#pragma unroll
+  for (int q = 1; q < kS8; ++q)
+#pragma unroll
+    for (int k = 0; k < q; ++k) y[q] = fmaf(-K[q][k], y[k], y[q]);
+#pragma unroll
+  for (int q = kS8 - 1; q >= 0; --q) {
+#pragma unroll
+    for (int k = q + 1; k < kS8; ++k) y[q] = fmaf(-K[q][k], y[k], y[q]);
+    y[q] *= inv[q];
+  }
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_rows8(Work w) {
+  __shared__ int s_itmax;
+  if (w.cnt->nA == 0) return;
+  const int tid = threadIdx.x;
+  const int total = w.cnt->total_rows;
+  const int lb = xcd_logical_block();
+  const int per = (total + gridDim.x - 1) / gridDim.x;
+  const int r0 = lb * per;
+  const int r1 = min(total, r0 + per);
+  if (r0 >= r1) return;
+  const int m0 = w.chunk_mat[row_chunk(w.chunk_rbase, w.nchunks, r0)];
+  if (tid == 0) s_itmax = 0;
+  __syncthreads();
+  int c = row_chunk(w.chunk_rbase, w.nchunks, min(r0 + tid, r1 - 1));
+
+  for (int g = r0 + tid; g < r1; g += NT) {
+    while (w.chunk_rbase[c + 1] <= g) ++c;
+    const RowInfo ri = row_info(w, c, g - w.chunk_rbase[c]);
+    if (ri.s > kS8) continue;
+    MatStatus* st = &w.st[ri.m];
+    if (!matrix_live(*st)) continue;
+    const MatDesc& d = w.desc[ri.m];
+    const int32_t* __restrict__ rp = d.rp;
+    const int32_t* __restrict__ ci = d.ci;
+    const double* __restrict__ va = d.va;
+    const int i = ri.i;
+    const int s = ri.s;
+    d.Rrp[ri.r] = ri.off;
+
+    RegSet<kS8> S;
+    if (reg_bfs(S, d.n, i, d.ell, rp, ci, va, d.cf) != s) {
+      flag_row(st, ST_INVALID, i);
+      continue;
+    }
+    const int(&N)[kS8] = S.v;
+
+    // f = -A[i,N]; the block is scaled by a power of two from row i's magnitude
+    double f[kS8];
+#pragma unroll
+    for (int q = 0; q < kS8; ++q) f[q] = 0.0;
+    double amax_i = 0.0;
+    {
+      const int e1 = rp[i + 1];
+      for (int e = rp[i]; e < e1; ++e) {
+        const int k = ci[e];
+        const double v = va[e];
+        amax_i = fmax(amax_i, fabs(v));
+        bool hit;
+        const int q = pos8(N, k, &hit);
+#pragma unroll
+        for (int qq = 0; qq < kS8; ++qq)
+          if (hit && q == qq) f[qq] = -v;
+      }
+    }
+    int ex = 0;
+    frexp(amax_i > 0.0 ? amax_i : 1.0, &ex);
+    const double scale = ldexp(1.0, -ex);
+
+    // K = (A[N,N])^T in FP32, identity on the padding
+    float K[kS8][kS8];
+#pragma unroll
+    for (int q = 0; q < kS8; ++q)
+#pragma unroll
+      for (int p = 0; p < kS8; ++p) K[q][p] = (q == p && q >= s) ? 1.f : 0.f;
+    int lo[kS8], hi[kS8];
+    double amaxK = 0.0;
+#pragma unroll
+    for (int p = 0; p < kS8; ++p) {
+      lo[p] = 0;
+      hi[p] = 0;
+      if (p < s) {
+        lo[p] = rp[N[p]];
+        hi[p] = rp[N[p] + 1];
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < kS8; ++p) {
+      for (int e = lo[p]; e < hi[p]; ++e) {
+        const int k = ci[e];
+        const double v = va[e];
+        bool hit;
+        const int q = pos8(N, k, &hit);
+        if (hit) amaxK = fmax(amaxK, fabs(v));
+        const float vs = (float)(v * scale);
+#pragma unroll
+        for (int qq = 0; qq < kS8; ++qq)
+          if (hit && q == qq) K[qq][p] = vs;
+      }
+    }
+
+    // FP32 LU without pivoting; a small or non-finite pivot hands the row to
+    // the FP64 solver with partial pivoting
+    const float tiny = (float)(amaxK * scale) * 0x1p-20f;
+    float inv[kS8];
+    bool bad = !(amaxK * scale < 1e30);
+#pragma unroll
+    for (int k = 0; k < kS8; ++k) {
+      const float piv = K[k][k];
+      bad |= !(fabsf(piv) > tiny);
+      inv[k] = 1.f / piv;
+#pragma unroll
+      for (int q = k + 1; q < kS8; ++q) {
+        const float l = K[q][k] * inv[k];
+        K[q][k] = l;
+#pragma unroll
+        for (int p = k + 1; p < kS8; ++p) K[q][p] = fmaf(-l, K[k][p], K[q][p]);
+      }
+    }
+
+    double z[kS8];
+    int it = 0;
+    bool conv = false;
+    if (!bad) {
+      float y[kS8];
+#pragma unroll
+      for (int q = 0; q < kS8; ++q) y[q] = (float)(f[q] * scale);
+      lu8_solve(K, inv, y);
+#pragma unroll
+      for (int q = 0; q < kS8; ++q) z[q] = (double)y[q];
+      double fnorm = 0.0;
+#pragma unroll
+      for (int q = 0; q < kS8; ++q) fnorm = fmax(fnorm, fabs(f[q]));
+      const double knorm = amaxK * s;
+      for (it = 1; it <= kRefineMax; ++it) {
+        // r = f - K z with the FP64 entries of A[N,N]
+        double r[kS8];
+#pragma unroll
+        for (int q = 0; q < kS8; ++q) r[q] = f[q];
+#pragma unroll
+        for (int p = 0; p < kS8; ++p) {
+          for (int e = lo[p]; e < hi[p]; ++e) {
+            bool hit;
+            const int q = pos8(N, ci[e], &hit);
+            const double t = va[e] * z[p];
+#pragma unroll
+            for (int qq = 0; qq < kS8; ++qq)
+              if (hit && q == qq) r[qq] -= t;
+          }
+        }
+        double rn = 0.0, zn = 0.0;
+#pragma unroll
+        for (int q = 0; q < kS8; ++q) {
+          rn = fmax(rn, fabs(r[q]));
+          zn = fmax(zn, fabs(z[q]));
+        }
+        if (rn <= 0x1p-47 * (knorm * zn + fnorm)) { conv = true; break; }
+#pragma unroll
+        for (int q = 0; q < kS8; ++q) y[q] = (float)(r[q] * scale);
+        lu8_solve(K, inv, y);
+#pragma unroll
+        for (int q = 0; q < kS8; ++q) z[q] += (double)y[q];
+      }
+#pragma unroll
+      for (int q = 0; q < kS8; ++q) conv &= (z[q] == z[q]);
+    }
+    if (!conv) {
+      // FP32 factorisation not trusted: the workgroup solver redoes the row in FP64
+      const int qc = atomicAdd(&w.cnt->nC, 1);
+      if (qc < w.capC) w.binC[qc] = c * w.chunk + (g - w.chunk_rbase[c]);
+      else flag_row(st, ST_UNSUPPORTED, i);
+      continue;
+    }
+    if (ri.m == m0) atomicMax(&s_itmax, it);
+    else atomicMax(&st->refine_max, it);
+
+    // R row: the F-entries of N(i) around the injected C-point
+    int dpos = 0;
+#pragma unroll
+    for (int p = 0; p < kS8; ++p) dpos += (N[p] < i) ? 1 : 0;
+    const double bi = d.B ? d.B[i] : 0.0;
+#pragma unroll
+    for (int p = 0; p < kS8; ++p) {
+      if (p < s) {
+        const int pos = ri.off + p + (p >= dpos ? 1 : 0);
+        d.Rci[pos] = N[p];
+        d.Rva[pos] = z[p];
+        if (d.B) {
+          unsafeAtomicAdd(&w.dsum[ri.fine0 + N[p]], bi * bi);
+          unsafeAtomicAdd(&w.rsum[ri.fine0 + N[p]], z[p] * bi);
+        }
+      }
+    }
+    d.Rci[ri.off + dpos] = i;
+    d.Rva[ri.off + dpos] = 1.0;
   }
   __syncthreads();
   if (tid == 0 && s_itmax > 0) atomicMax(&w.st[m0].refine_max, s_itmax);
@@ -905,6 +1163,23 @@ hipError_t launch_numeric(const Work& w, int which, int group, int wg_threads, i
   CLAIR_NUM(32, 128)
   CLAIR_NUM(32, 64)
 #undef CLAIR_NUM
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_rows8(const Work& w, int wg_threads, int cus, hipStream_t s) {
+#define CLAIR_R8(NTT)                                                                       \
+  if (wg_threads == NTT) {                                                                  \
+    int per = 0;                                                                            \
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_rows8<NTT>, NTT, 0); \
+    if (e != hipSuccess) return e;                                                          \
+    const int blocks = (std::max(1, per) * cus + 7) / 8 * 8;                               \
+    hipLaunchKernelGGL((k_rows8<NTT>), dim3(blocks), dim3(NTT), 0, s, w);                   \
+    return hipGetLastError();                                                               \
+  }
+  CLAIR_R8(256)
+  CLAIR_R8(128)
+  CLAIR_R8(64)
+#undef CLAIR_R8
   return hipErrorInvalidValue;
 }
 

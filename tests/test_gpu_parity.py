@@ -85,8 +85,8 @@ def test_cfg5_128cube_7pt():
 
 
 # ---------------------------------------------------------------------------
-# larger neighbourhoods: lane groups of 8/16/32, workgroup-per-row in LDS and
-# in global scratch
+# larger neighbourhoods: one thread per row (|N| <= 8), lane groups of
+# 8/16/32, workgroup-per-row in LDS and in global scratch
 # ---------------------------------------------------------------------------
 
 def test_cfg3_shape_ell3_workgroup_lds_path():
@@ -108,8 +108,8 @@ def test_cfg5_shape_ell4_scratch_path():
     assert infos[0]["max_block"] == 98
 
 
-@pytest.mark.parametrize("group,wg,chunk", [(8, 64, 512), (8, 128, 1024), (16, 64, 2048), (16, 256, 512),
-                                            (32, 64, 1024), (32, 128, 2048)])
+@pytest.mark.parametrize("group,wg,chunk", [(1, 256, 2048), (1, 64, 512), (8, 64, 512), (8, 128, 1024),
+                                            (16, 64, 2048), (16, 256, 512), (32, 64, 1024), (32, 128, 2048)])
 def test_tuning_shapes(group, wg, chunk):
     from paper_2307_00229_amd import clair
 
