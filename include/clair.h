@@ -174,10 +174,13 @@ int clair_size_R(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* A, const int
 int clair_ctx_stage_times(clair_ctx_t* ctx, const char** names, float* ms, int32_t cap);
 
 /*
- * Tuning: kernel shape of the mixed path.  group = lanes per row (8, 16 or 32;
- * rows with larger blocks go to the workgroup-per-row path), rows_per_wg
- * scales the workgroup, chunk = fine points per workgroup in the symbolic
- * pass.  0 keeps the current value.  clair_autotune picks them by timing
+ * Tuning: kernel shape of the mixed path.  group = lanes that solve one row
+ * of |N| <= 8 (1, 4 or 8) or the largest |N| the lane-group solver takes
+ * (16 or 32, one lane per block row); rows with larger blocks go to the
+ * workgroup-per-row path.  wg_threads = threads per workgroup (64, 128 or
+ * 256), chunk = fine points per workgroup in the symbolic pass (multiple of
+ * 256, at most 2048).  0 keeps the current value; defaults 8, 256, 1024.
+ * Invalid values return CLAIR_ERR_INVALID and change nothing.  clair_autotune picks them by timing
  * candidates on the given inputs (and stores the result in ctx).
  */
 int clair_ctx_set_tuning(clair_ctx_t* ctx, int32_t group, int32_t wg_threads, int32_t chunk);

@@ -95,13 +95,14 @@ Layout make_layout(int nmat, int nchunks, int64_t n_total, int GA) {
   L.chunk_nc = take(sizeof(int32_t) * (nchunks + 1));
   L.chunk_nnz = take(sizeof(int32_t) * (nchunks + 1));
   L.chunk_rbase = take(sizeof(int32_t) * (nchunks + 2));
-  L.chunk_nzbase = take(sizeof(int32_t) * (nchunks + 1));
+  L.chunk_nzbase = take(sizeof(int64_t) * (nchunks + 1));
   L.chunk_mat = take(sizeof(int32_t) * (nchunks + 1));
   L.clocal = take(sizeof(int32_t) * (n_total + 1));
   L.lnz = take(sizeof(int32_t) * (n_total + 1));
   L.dsum = take(sizeof(double) * (n_total + 1));
   L.rsum = take(sizeof(double) * (n_total + 1));
-  L.slotA = take(sizeof(int32_t) * (GA >= 8 ? (n_total + 1) * GA : 1));
+  const int SA = GA == 1 ? 0 : (GA == 4 ? 8 : GA);  // slot stride of bin A
+  L.slotA = take(sizeof(int32_t) * (SA ? (n_total + 1) * SA : 1));
   L.slotB = take(sizeof(int32_t) * (n_total + 1) * (GA < 32 ? 32 : 1));
   L.binC = take(sizeof(int32_t) * L.capC);
   L.ovf = take(sizeof(int32_t) * (nchunks + 1));
@@ -123,9 +124,9 @@ struct clair_ctx {
   int device = 0;
   int cus = 256;
   // tuning
-  int group = 1;  // 1: one thread per row for |N| <= 8; 8/16/32: lane groups
+  int group = 8;  // lanes per row of the small solver: 1, 4 or 8 (|N| <= 8), 16/32 (|N| <= group)
   int wg_threads = 256;
-  int chunk = 2048;
+  int chunk = 1024;
   // memory
   DevBuf ws;
   DevBuf scratch;  // FP64 blocks of oversized rows
@@ -262,7 +263,7 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
   w.chunk_nc = reinterpret_cast<int32_t*>(base + b->L.chunk_nc);
   w.chunk_nnz = reinterpret_cast<int32_t*>(base + b->L.chunk_nnz);
   w.chunk_rbase = reinterpret_cast<int32_t*>(base + b->L.chunk_rbase);
-  w.chunk_nzbase = reinterpret_cast<int32_t*>(base + b->L.chunk_nzbase);
+  w.chunk_nzglob = reinterpret_cast<int64_t*>(base + b->L.chunk_nzbase);
   w.chunk_mat = reinterpret_cast<int32_t*>(base + b->L.chunk_mat);
   w.clocal = reinterpret_cast<int32_t*>(base + b->L.clocal);
   w.lnz = reinterpret_cast<int32_t*>(base + b->L.lnz);
@@ -359,6 +360,8 @@ int enqueue_numeric(clair_ctx* c, Batch& b, hipStream_t s, bool timing, const Co
   if (!known || known->nA > 0) {
     if (c->group == 1) {
       HIPCHK(launch_rows8(b.w, c->wg_threads, c->cus, s));
+    } else if (c->group == 4) {
+      HIPCHK(launch_quad8(b.w, c->wg_threads, c->cus, s));
     } else {
       HIPCHK(launch_numeric(b.w, 0, c->group, c->wg_threads, c->cus, s));
     }
@@ -784,7 +787,7 @@ int clair_ctx_stage_times(clair_ctx_t* c, const char** names, float* ms, int32_t
 
 int clair_ctx_set_tuning(clair_ctx_t* c, int32_t group, int32_t wg_threads, int32_t chunk) {
   if (!c) return CLAIR_ERR_INVALID;
-  if (group && group != 1 && group != 8 && group != 16 && group != 32) return CLAIR_ERR_INVALID;
+  if (group && group != 1 && group != 4 && group != 8 && group != 16 && group != 32) return CLAIR_ERR_INVALID;
   if (wg_threads && wg_threads != 64 && wg_threads != 128 && wg_threads != 256) return CLAIR_ERR_INVALID;
   if (chunk && (chunk < 256 || chunk > kMaxChunk || (chunk % 256))) return CLAIR_ERR_INVALID;
   if (group) c->group = group;
@@ -811,7 +814,7 @@ int clair_autotune(clair_ctx_t* c, int32_t nmat, const clair_csr_t* A, const int
   o.stream = stream;
   int rc = clair_build_R_batched(c, nmat, A, cf, B, ell, R, &o, info.data());
   if (rc) return rc;
-  const int groups[4] = {1, 8, 16, 32};
+  const int groups[5] = {1, 4, 8, 16, 32};
   const int threads[3] = {64, 128, 256};
   const int chunks[3] = {512, 1024, 2048};
   hipEvent_t e0, e1;

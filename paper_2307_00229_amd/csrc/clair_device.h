@@ -52,6 +52,7 @@ struct MatStatus {
   int32_t n_fp64;
   int32_t row_base;    // first global row of this matrix
   int32_t pad0;
+  int64_t nz_base;     // first global R entry of this matrix (batch-wide numbering)
 };
 
 struct Counters {
@@ -74,7 +75,7 @@ struct Work {
   int32_t* chunk_nc;      // [nchunks]
   int32_t* chunk_nnz;     // [nchunks]
   int32_t* chunk_rbase;   // [nchunks+1] first global row of each chunk
-  int32_t* chunk_nzbase;  // [nchunks] first R entry of each chunk (per matrix)
+  int64_t* chunk_nzglob;  // [nchunks] first R entry of each chunk, batch-wide
   int32_t* chunk_mat;     // [nchunks]
   int32_t* clocal;        // [n_total] chunk-local C-points (negative while unsized)
   int32_t* lnz;           // [n_total] chunk-local prefix of |N(i)|+1

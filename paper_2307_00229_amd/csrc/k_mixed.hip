@@ -88,7 +88,7 @@ __device__ __forceinline__ RowInfo row_info(const Work& w, int c, int t) {
   ri.i = w.clocal[base + t];
   const int l0 = w.lnz[base + t];
   const int l1 = (t + 1 < w.chunk_nc[c]) ? w.lnz[base + t + 1] : w.chunk_nnz[c];
-  ri.off = w.chunk_nzbase[c] + l0;
+  ri.off = (int)(w.chunk_nzglob[c] - w.st[ri.m].nz_base) + l0;
   ri.s = l1 - l0 - 1;
   ri.r = w.chunk_rbase[c] + t - w.st[ri.m].row_base;
   ri.fine0 = d.fine0;
@@ -98,6 +98,58 @@ __device__ __forceinline__ RowInfo row_info(const Work& w, int c, int t) {
 __device__ __forceinline__ bool matrix_live(const MatStatus& st) {
   return st.status != ST_CAPACITY && st.status != ST_INVALID;
 }
+
+// Per-lane cache of the chunk a run of consecutive rows lies in: reloaded only
+// when the row index crosses into another chunk, so a row costs one level of
+// (coalesced) per-row loads instead of the chunk -> matrix -> descriptor chain.
+struct ChunkCursor {
+  int c = -1;
+  int rb = 0, re = 0;   // global rows [rb, re) of chunk c
+  int m = 0;
+  int nc = 0;           // C-rows in the chunk
+  int tot = 0;          // nnz(R) of the chunk
+  int zoff = 0;         // R offset of the chunk inside its matrix
+  int rbase_m = 0;      // first global row of the matrix
+  int64_t fbase = 0;    // fine offset of the chunk's first point (batch-wide)
+  int64_t fine0 = 0;    // fine offset of the matrix (batch-wide)
+  bool live = false;
+  MatDesc md;           // the matrix's pointers and geometry
+
+  __device__ __forceinline__ void seek(const Work& w, int g) {
+    if (c >= 0 && g >= rb && g < re) return;
+    if (c < 0 || g < rb) c = 0;
+    // forward walk from the current chunk (rows only move forward in a run)
+    int lo = c, hi = w.nchunks - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (w.chunk_rbase[mid] <= g) lo = mid; else hi = mid - 1;
+    }
+    c = lo;
+    rb = w.chunk_rbase[c];
+    re = w.chunk_rbase[c + 1];
+    m = w.chunk_mat[c];
+    md = w.desc[m];
+    const MatStatus& st = w.st[m];
+    nc = w.chunk_nc[c];
+    tot = w.chunk_nnz[c];
+    zoff = (int)(w.chunk_nzglob[c] - st.nz_base);
+    rbase_m = st.row_base;
+    fine0 = md.fine0;
+    fbase = md.fine0 + (int64_t)(c - md.chunk0) * w.chunk;
+    live = matrix_live(st);
+  }
+  // row g (inside the chunk): fine index, R offset and |N|
+  __device__ __forceinline__ void row(const Work& w, int g, int* t, int* i, int* off, int* sz) const {
+    const int tt = g - rb;
+    *t = tt;
+    *i = w.clocal[fbase + tt];
+    const int l0 = w.lnz[fbase + tt];
+    const int l1 = (tt + 1 < nc) ? w.lnz[fbase + tt + 1] : tot;
+    *off = zoff + l0;
+    *sz = l1 - l0 - 1;
+  }
+};
+
 
 // Logical workgroup index: the hardware deals workgroups to the 8 XCDs
 // round-robin (block b runs on XCD b % 8).  Give each XCD a contiguous range
@@ -154,7 +206,9 @@ struct CountGroupBuf {
 
 // rows the small solvers take: |N| <= 8 for the thread-per-row solver
 // (GA == 1), |N| <= GA for the lane-group solver
-__device__ __forceinline__ int small_limit(int GA) { return GA == 1 ? 8 : GA; }
+__device__ __forceinline__ int small_limit(int GA) { return GA <= 4 ? 8 : GA; }
+// stride of a row's slot in slotA (0: the small solver searches itself)
+__device__ __forceinline__ int slot_stride(int GA) { return GA == 1 ? 0 : (GA == 4 ? 8 : GA); }
 
 __global__ __launch_bounds__(kNT) void k_count(Work w) {
   constexpr int NG = kCountNG2;
@@ -199,6 +253,7 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
 
   const int GA = w.GA;
   const int lim = small_limit(GA);
+  const int SA = slot_stride(GA);
   int inA = 0, inB = 0, unresolved = 0;
 
   // phase 1: one thread per C-row, neighbourhoods of up to 8 points in registers
@@ -208,10 +263,10 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
     if (sz >= 0) {
       s_size[t] = sz;
       ++inA;  // sz <= 8 <= lim
-      if (GA >= 8) {
+      if (SA) {
 #pragma unroll
         for (int p = 0; p < 8; ++p)
-          if (p < sz) w.slotA[(base + t) * GA + p] = S.v[p];
+          if (p < sz) w.slotA[(base + t) * SA + p] = S.v[p];
       }
     } else {
       s_size[t] = -1;
@@ -239,8 +294,8 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
       t = s_list[k];
       sz = team_bfs(tm, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf, bb, &nl);
       if (sz >= 0 && sz <= lim) {
-        if (GA >= 8)
-          for (int p = gl; p < sz; p += kCountG) w.slotA[(base + t) * GA + p] = nl[p];
+        if (SA)
+          for (int p = gl; p < sz; p += kCountG) w.slotA[(base + t) * SA + p] = nl[p];
         inA += (gl == 0);
       } else if (sz > lim && sz <= 32) {
         for (int p = gl; p < sz; p += kCountG) w.slotB[(base + t) * 32 + p] = nl[p];
@@ -332,8 +387,9 @@ __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
       // small enough for a lane-group solver: its slot; else the workgroup solver
       const int lim = small_limit(w.GA);
       if (s >= 0 && s <= lim) {
-        if (w.GA >= 8)
-          for (int p = tid; p < s; p += kNT) w.slotA[(base + t) * w.GA + p] = nl[p];
+        const int SA = slot_stride(w.GA);
+        if (SA)
+          for (int p = tid; p < s; p += kNT) w.slotA[(base + t) * SA + p] = nl[p];
       } else if (s > lim && s <= 32) {
         for (int p = tid; p < s; p += kNT) w.slotB[(base + t) * 32 + p] = nl[p];
       }
@@ -375,54 +431,69 @@ __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
   }
 }
 
-// one workgroup: per-matrix scans of the chunk counts
+// One workgroup: global row base and global R offset of every chunk (all
+// matrices in order).  Each thread sums a contiguous run of chunks, one block
+// scan joins the runs; then one thread per matrix sizes R, checks capacity and
+// writes R.row_ptr[n_c].  Per-matrix R offsets are the global ones minus the
+// matrix's base.
 __global__ __launch_bounds__(1024) void k_scan(Work w) {
-  __shared__ int sh[1024];
-  __shared__ int s_carry_r, s_carry_z;
+  __shared__ long long shr[1024];
+  __shared__ long long shz[1024];
   const int tid = threadIdx.x;
-  int rows_total = 0;
-  for (int m = 0; m < w.nmat; ++m) {
-    const MatDesc d = w.desc[m];
-    if (tid == 0) { s_carry_r = 0; s_carry_z = 0; }
+  const int nch = w.nchunks;
+  const int per = (nch + 1023) / 1024;
+  const int c0 = min(nch, tid * per), c1 = min(nch, c0 + per);
+  long long sr = 0, sz = 0;
+  for (int c = c0; c < c1; ++c) { sr += w.chunk_nc[c]; sz += w.chunk_nnz[c]; }
+  shr[tid] = sr;
+  shz[tid] = sz;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const long long a = tid >= off ? shr[tid - off] : 0;
+    const long long b = tid >= off ? shz[tid - off] : 0;
     __syncthreads();
-    for (int c0 = 0; c0 < d.nchunks; c0 += 1024) {
-      const int c = d.chunk0 + c0 + tid;
-      const bool in = (c0 + tid) < d.nchunks;
-      const int vr = in ? w.chunk_nc[c] : 0;
-      const int vz = in ? w.chunk_nnz[c] : 0;
-      int tr, tz;
-      const int pr = block_exclusive_scan(vr, sh, &tr);
-      const int pz = block_exclusive_scan(vz, sh, &tz);
-      if (in) {
-        w.chunk_rbase[c] = rows_total + s_carry_r + pr;
-        w.chunk_nzbase[c] = s_carry_z + pz;
-      }
-      __syncthreads();
-      if (tid == 0) { s_carry_r += tr; s_carry_z += tz; }
-      __syncthreads();
-    }
-    const int n_c = s_carry_r;
-    const int nnz = s_carry_z;
-    if (tid == 0) {
-      MatStatus* st = &w.st[m];
-      st->n_c = n_c;
-      st->nnz = nnz;
-      st->row_base = rows_total;
-      if (st->status != ST_INVALID) {
-        const bool fits = d.Rrp && d.Rci && d.Rva && (int64_t)n_c + 1 <= d.row_cap && (int64_t)nnz <= d.nnz_cap;
-        if (!fits) {
-          st->status = ST_CAPACITY;
-        } else {
-          d.Rrp[n_c] = nnz;
-        }
-      }
-    }
-    rows_total += n_c;
+    shr[tid] += a;
+    shz[tid] += b;
     __syncthreads();
   }
+  long long rr = shr[tid] - sr;
+  long long zz = shz[tid] - sz;
+  const long long rows_total = shr[1023];
+  const long long nnz_total = shz[1023];
+  for (int c = c0; c < c1; ++c) {
+    w.chunk_rbase[c] = (int32_t)rr;
+    w.chunk_nzglob[c] = zz;
+    rr += w.chunk_nc[c];
+    zz += w.chunk_nnz[c];
+  }
+  __syncthreads();
+  for (int m = tid; m < w.nmat; m += 1024) {
+    const MatDesc& d = w.desc[m];
+    MatStatus* st = &w.st[m];
+    const int cb = d.chunk0, ce = d.chunk0 + d.nchunks;
+    const long long rb = cb < nch ? w.chunk_rbase[cb] : rows_total;
+    const long long re = ce < nch ? w.chunk_rbase[ce] : rows_total;
+    const long long zb = cb < nch ? w.chunk_nzglob[cb] : nnz_total;
+    const long long ze = ce < nch ? w.chunk_nzglob[ce] : nnz_total;
+    const int n_c = (int)(re - rb);
+    const long long nnz = ze - zb;
+    st->row_base = (int32_t)rb;
+    st->nz_base = zb;
+    st->n_c = n_c;
+    st->nnz = nnz;
+    if (st->status != ST_INVALID) {
+      const bool fits = d.Rrp && d.Rci && d.Rva && (int64_t)n_c + 1 <= d.row_cap && nnz <= d.nnz_cap &&
+                        nnz <= 0x7fffffffLL;
+      if (!fits) {
+        st->status = ST_CAPACITY;
+      } else {
+        d.Rrp[n_c] = (int32_t)nnz;
+      }
+    }
+  }
   if (tid == 0) {
-    w.chunk_rbase[w.nchunks] = rows_total;
-    w.cnt->total_rows = rows_total;
+    w.chunk_rbase[nch] = (int32_t)rows_total;
+    w.cnt->total_rows = (int32_t)rows_total;
   }
 }
 
@@ -500,28 +571,33 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
   const int r0 = lb * per;
   const int r1 = min(total, r0 + per);
   if (r0 >= r1) return;
-  int c = row_chunk(w.chunk_rbase, w.nchunks, min(r0 + grp, r1 - 1));
   // statistics of the workgroup's first matrix gather in LDS (one global
   // atomic per workgroup); rows of later matrices in the range go straight out
   const int m0 = w.chunk_mat[row_chunk(w.chunk_rbase, w.nchunks, r0)];
   if (tid == 0) s_itmax = 0;
   __syncthreads();
+  ChunkCursor cc;
 
   for (int gbase = r0; gbase < r1; gbase += NG) {
     const int g = gbase + grp;
     if (g >= r1) break;  // group-uniform
-    while (w.chunk_rbase[c + 1] <= g) ++c;
-    const int t = g - w.chunk_rbase[c];
-    const RowInfo ri = row_info(w, c, t);
-    if (ri.s < smin || ri.s > G) continue;  // another solver's row (group-uniform)
-    const int64_t fbase = ri.fine0 + (int64_t)(c - w.desc[ri.m].chunk0) * w.chunk;
-    const int myN0 = slots[(fbase + t) * sstride + min(lane, sstride - 1)];
+    cc.seek(w, g);
+    int t, i, off, s;
+    cc.row(w, g, &t, &i, &off, &s);
+    if (s < smin || s > G) continue;  // another solver's row (group-uniform)
+    const int myN0 = slots[(cc.fbase + t) * sstride + min(lane, sstride - 1)];
+    if (!cc.live) continue;
+    const int c = cc.c;
     const int entry = c * w.chunk + t;
-    MatStatus* st = &w.st[ri.m];
-    if (!matrix_live(*st)) continue;
-    const MatDesc& d = w.desc[ri.m];
-    const int s = ri.s;
-    const int i = ri.i;
+    const MatDesc& d = cc.md;
+    MatStatus* st = &w.st[cc.m];
+    RowInfo ri;
+    ri.m = cc.m;
+    ri.i = i;
+    ri.r = g - cc.rbase_m;
+    ri.off = off;
+    ri.s = s;
+    ri.fine0 = cc.fine0;
     if (lane == 0) d.Rrp[ri.r] = ri.off;
     const int myN = (lane < s) ? myN0 : 0x7fffffff;
     gb.nb[lane] = myN;
@@ -650,6 +726,289 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
     if (lane == 0) {
       d.Rci[ri.off + dpos] = i;
       d.Rva[ri.off + dpos] = 1.0;
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && s_itmax > 0) atomicMax(&w.st[m0].refine_max, s_itmax);
+}
+
+// ---------------------------------------------------------------------------
+// numeric pass, four lanes (a quad) per row with |N| <= 8.  Lane l of the quad
+// owns rows 2l and 2l+1 of K = (A[N,N])^T.  The block is transposed once
+// through LDS after the gather; the LU, both triangular solves and the FP64
+// residual then broadcast within the quad with DPP quad permutations
+// (register moves, no LDS round trip).
+// ---------------------------------------------------------------------------
+// lane src of the quad, to all four (src is a constant once the calling loops
+// are unrolled, so the switch folds to one DPP move)
+__device__ __forceinline__ int qbi(int v, int src) {
+  switch (src) {
+    case 0: return __builtin_amdgcn_mov_dpp(v, 0x00, 0xF, 0xF, false);
+    case 1: return __builtin_amdgcn_mov_dpp(v, 0x55, 0xF, 0xF, false);
+    case 2: return __builtin_amdgcn_mov_dpp(v, 0xAA, 0xF, 0xF, false);
+    default: return __builtin_amdgcn_mov_dpp(v, 0xFF, 0xF, 0xF, false);
+  }
+}
+__device__ __forceinline__ float qb(float v, int src) { return __int_as_float(qbi(__float_as_int(v), src)); }
+__device__ __forceinline__ double qbd(double v, int src) {
+  return __hiloint2double(qbi(__double2hiint(v), src), qbi(__double2loint(v), src));
+}
+// quad reductions: partners lane^1 and lane^2 (quad_perm [1,0,3,2] and [2,3,0,1])
+__device__ __forceinline__ float qmaxf(float v) {
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false)));
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false)));
+  return v;
+}
+__device__ __forceinline__ double qxd(double v, int ctrl_is_b1) {
+  const int lo = ctrl_is_b1 ? __builtin_amdgcn_mov_dpp(__double2loint(v), 0xB1, 0xF, 0xF, false)
+                            : __builtin_amdgcn_mov_dpp(__double2loint(v), 0x4E, 0xF, 0xF, false);
+  const int hi = ctrl_is_b1 ? __builtin_amdgcn_mov_dpp(__double2hiint(v), 0xB1, 0xF, 0xF, false)
+                            : __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x4E, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double qmaxd(double v) {
+  v = fmax(v, qxd(v, 1));
+  v = fmax(v, qxd(v, 0));
+  return v;
+}
+__device__ __forceinline__ int qori(int v) {
+  v |= __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);
+  v |= __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);
+  return v;
+}
+
+struct QuadBuf {
+  double K[8 * 9];  // gathered block, row q of K at stride 9
+  double f[8];
+  int nb[8];
+};
+
+// value of register slot S (0/1) of lane SRC = row 2*SRC+S, broadcast in the quad
+#define QB_ROW(arr0, arr1, k, p) ((k) & 1 ? qb(arr1[p], (k) / 2) : qb(arr0[p], (k) / 2))
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_quad8(Work w) {
+  constexpr int NQ = NT / 4;
+  __shared__ QuadBuf qbuf[NQ];
+  __shared__ int s_itmax;
+  const int tid = threadIdx.x;
+  const int qd = tid >> 2;
+  const int ql = tid & 3;
+  QuadBuf& B = qbuf[qd];
+  if (w.cnt->nA == 0) return;
+  const int total = w.cnt->total_rows;
+  const int lb = xcd_logical_block();
+  const int per = (total + gridDim.x - 1) / gridDim.x;
+  const int r0 = lb * per;
+  const int r1 = min(total, r0 + per);
+  if (r0 >= r1) return;
+  const int m0 = w.chunk_mat[row_chunk(w.chunk_rbase, w.nchunks, r0)];
+  if (tid == 0) s_itmax = 0;
+  __syncthreads();
+  const int q0 = 2 * ql, q1 = 2 * ql + 1;  // this lane's rows of K
+  ChunkCursor cc;
+
+  for (int g = r0 + qd; g < r1; g += NQ) {  // quad-uniform
+    cc.seek(w, g);
+    int t, i, off, s;
+    cc.row(w, g, &t, &i, &off, &s);
+    if (s > 8 || !cc.live) continue;
+    const int c = cc.c;
+    MatStatus* st = &w.st[cc.m];
+    const MatDesc& d = cc.md;
+    RowInfo ri;
+    ri.m = cc.m;
+    ri.i = i;
+    ri.r = g - cc.rbase_m;
+    ri.off = off;
+    ri.s = s;
+    ri.fine0 = cc.fine0;
+    const int64_t fbase = cc.fbase;
+    const int2 nn = *reinterpret_cast<const int2*>(w.slotA + (fbase + t) * 8 + q0);
+    const int n0 = q0 < s ? nn.x : 0x7fffffff;
+    const int n1 = q1 < s ? nn.y : 0x7fffffff;
+    if (ql == 0) d.Rrp[ri.r] = ri.off;
+    B.nb[q0] = n0;
+    B.nb[q1] = n1;
+#pragma unroll
+    for (int u = 0; u < 18; ++u) {  // zero the block, identity on the padding
+      const int idx = ql * 18 + u;
+      const int rq = idx / 9, cp = idx % 9;
+      B.K[idx] = (rq == cp && rq >= s) ? 1.0 : 0.0;
+    }
+    B.f[q0] = 0.0;
+    B.f[q1] = 0.0;
+    wave_sync();
+    // gather: lane l walks rows N_{2l}, N_{2l+1} of A (columns 2l, 2l+1 of K)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int p = q0 + h;
+      const int u = h ? n1 : n0;
+      if (p < s) {
+        const int e1 = d.rp[u + 1];
+        for (int e = d.rp[u]; e < e1; e += 4) {
+          int k[4];
+          double v[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            k[j] = -1;
+            v[j] = 0.0;
+            if (e + j < e1) { k[j] = d.ci[e + j]; v[j] = d.va[e + j]; }
+          }
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int qq = find_sorted(B.nb, s, k[j]);
+            if (qq >= 0) B.K[qq * 9 + p] = v[j];
+          }
+        }
+      }
+    }
+    {
+      const int e1 = d.rp[i + 1];
+      for (int e = d.rp[i] + ql; e < e1; e += 4) {
+        const int qq = find_sorted(B.nb, s, d.ci[e]);
+        if (qq >= 0) B.f[qq] = -d.va[e];
+      }
+    }
+    wave_sync();
+    // rows q0, q1 of K (FP64), scaled FP32 copies
+    double k0[8], k1[8];
+    float amax = 0.f;
+    double rs0 = 0.0, rs1 = 0.0;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      k0[p] = B.K[q0 * 9 + p];
+      k1[p] = B.K[q1 * 9 + p];
+      amax = fmaxf(amax, fmaxf((float)fabs(k0[p]), (float)fabs(k1[p])));
+      rs0 += fabs(k0[p]);
+      rs1 += fabs(k1[p]);
+    }
+    const double f0 = B.f[q0], f1 = B.f[q1];
+    amax = qmaxf(amax);
+    const double knorm = qmaxd(fmax(rs0, rs1));
+    const double fnorm = qmaxd(fmax(fabs(f0), fabs(f1)));
+    int ex = 0;
+    frexpf(amax, &ex);
+    const double scale = ldexp(1.0, -ex);
+    float a0[8], a1[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      a0[p] = (float)(k0[p] * scale);
+      a1[p] = (float)(k1[p] * scale);
+    }
+    // LU without pivoting: lane-local rows, pivot rows broadcast in the quad
+    int bad = !(amax > 0.f) || !(amax < 3.0e38f);
+    float ui0 = 1.f, ui1 = 1.f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      float pr[8];
+#pragma unroll
+      for (int p = k; p < 8; ++p) pr[p] = QB_ROW(a0, a1, k, p);
+      const float piv = pr[k];
+      bad |= !(fabsf(piv) >= 0x1p-24f);
+      const float pinv = 1.f / piv;
+      if (q0 == k) ui0 = pinv;
+      if (q1 == k) ui1 = pinv;
+      if (q0 > k) {
+        const float l = a0[k] * pinv;
+        a0[k] = l;
+#pragma unroll
+        for (int p = k + 1; p < 8; ++p) a0[p] = fmaf(-l, pr[p], a0[p]);
+      }
+      if (q1 > k) {
+        const float l = a1[k] * pinv;
+        a1[k] = l;
+#pragma unroll
+        for (int p = k + 1; p < 8; ++p) a1[p] = fmaf(-l, pr[p], a1[p]);
+      }
+    }
+    bad = qori(bad);
+
+    double z0 = 0.0, z1 = 0.0;
+    int it = 0;
+    bool conv = false;
+    if (!bad) {
+      // solve K y = rhs for this lane's two entries y0, y1
+      auto solve = [&](float y0, float y1, float* o0, float* o1) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {  // forward, unit lower
+          const float yk = (k & 1) ? qb(y1, k / 2) : qb(y0, k / 2);
+          if (q0 > k) y0 = fmaf(-a0[k], yk, y0);
+          if (q1 > k) y1 = fmaf(-a1[k], yk, y1);
+        }
+#pragma unroll
+        for (int k = 7; k >= 0; --k) {  // backward, upper
+          if (q0 == k) y0 *= ui0;
+          if (q1 == k) y1 *= ui1;
+          const float zk = (k & 1) ? qb(y1, k / 2) : qb(y0, k / 2);
+          if (q0 < k) y0 = fmaf(-a0[k], zk, y0);
+          if (q1 < k) y1 = fmaf(-a1[k], zk, y1);
+        }
+        *o0 = y0;
+        *o1 = y1;
+      };
+      float y0, y1;
+      solve((float)(f0 * scale), (float)(f1 * scale), &y0, &y1);
+      z0 = y0;
+      z1 = y1;
+      for (it = 1; it <= kRefineMax; ++it) {
+        // r = f - K z in FP64: all of z broadcast in the quad
+        double zall[8];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) zall[p] = (p & 1) ? qbd(z1, p / 2) : qbd(z0, p / 2);
+        double r0 = f0, r1 = f1;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+          r0 = fma(-k0[p], zall[p], r0);
+          r1 = fma(-k1[p], zall[p], r1);
+        }
+        const double rn = qmaxd(fmax(fabs(r0), fabs(r1)));
+        const double zn = qmaxd(fmax(fabs(z0), fabs(z1)));
+        if (rn <= 0x1p-47 * (knorm * zn + fnorm)) { conv = true; break; }
+        float d0, d1;
+        solve((float)(r0 * scale), (float)(r1 * scale), &d0, &d1);
+        z0 += (double)d0;
+        z1 += (double)d1;
+      }
+      conv = conv && (z0 == z0) && (z1 == z1);
+      conv = qori(conv ? 0 : 1) == 0;
+    }
+    if (!conv) {
+      // FP32 factorisation not trusted: the workgroup solver redoes the row in FP64
+      if (ql == 0) {
+        const int qc = atomicAdd(&w.cnt->nC, 1);
+        if (qc < w.capC) w.binC[qc] = c * w.chunk + t;
+        else flag_row(st, ST_UNSUPPORTED, i);
+      }
+      continue;
+    }
+    if (ql == 0) {
+      if (ri.m == m0) atomicMax(&s_itmax, it);
+      else atomicMax(&st->refine_max, it);
+    }
+    // R row
+    const int dpos_l = (n0 < i ? 1 : 0) + (n1 < i ? 1 : 0);
+    const int dpos = dpos_l + __builtin_amdgcn_mov_dpp(dpos_l, 0xB1, 0xF, 0xF, false);
+    const int dposq = dpos + __builtin_amdgcn_mov_dpp(dpos, 0x4E, 0xF, 0xF, false);
+    const double bi = d.B ? d.B[i] : 0.0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int p = q0 + h;
+      if (p < s) {
+        const int np = h ? n1 : n0;
+        const double zp = h ? z1 : z0;
+        const int pos = ri.off + p + (p >= dposq ? 1 : 0);
+        d.Rci[pos] = np;
+        d.Rva[pos] = zp;
+        if (d.B) {
+          unsafeAtomicAdd(&w.dsum[ri.fine0 + np], bi * bi);
+          unsafeAtomicAdd(&w.rsum[ri.fine0 + np], zp * bi);
+        }
+      }
+    }
+    if (ql == 0) {
+      d.Rci[ri.off + dposq] = i;
+      d.Rva[ri.off + dposq] = 1.0;
     }
   }
   __syncthreads();
@@ -1083,21 +1442,21 @@ __global__ __launch_bounds__(256) void k_project(Work w) {
   const int per = (total + gridDim.x - 1) / gridDim.x;
   const int r0 = lb * per;
   const int r1 = min(total, r0 + per);
-  int c = (r0 < r1) ? row_chunk(w.chunk_rbase, w.nchunks, r0) : 0;
+  ChunkCursor cc;
   for (int gbase = r0; gbase < r1; gbase += NG) {
     const int g = gbase + grp;
     if (g >= r1) break;
-    while (w.chunk_rbase[c + 1] <= g) ++c;
-    const RowInfo ri = row_info(w, c, g - w.chunk_rbase[c]);
-    const MatStatus& st = w.st[ri.m];
-    const MatDesc& d = w.desc[ri.m];
-    if (!matrix_live(st) || !d.B) continue;
-    const double bi = d.B[ri.i];
-    for (int e = ri.off + lane; e <= ri.off + ri.s; e += kPG) {
+    cc.seek(w, g);
+    if (!cc.live || !cc.md.B) continue;
+    int t, i, off, sz;
+    cc.row(w, g, &t, &i, &off, &sz);
+    const MatDesc& d = cc.md;
+    const double bi = d.B[i];
+    for (int e = off + lane; e <= off + sz; e += kPG) {
       const int j = d.Rci[e];
-      if (j == ri.i) continue;
-      const double dj = w.dsum[ri.fine0 + j];
-      if (dj > 0.0) d.Rva[e] -= bi * (w.rsum[ri.fine0 + j] - d.B[j]) / dj;
+      if (j == i) continue;
+      const double dj = w.dsum[cc.fine0 + j];
+      if (dj > 0.0) d.Rva[e] -= bi * (w.rsum[cc.fine0 + j] - d.B[j]) / dj;
     }
   }
   // uncovered F-points: one global atomic per workgroup and matrix
@@ -1180,6 +1539,23 @@ hipError_t launch_rows8(const Work& w, int wg_threads, int cus, hipStream_t s) {
   CLAIR_R8(128)
   CLAIR_R8(64)
 #undef CLAIR_R8
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_quad8(const Work& w, int wg_threads, int cus, hipStream_t s) {
+#define CLAIR_Q8(NTT)                                                                       \
+  if (wg_threads == NTT) {                                                                  \
+    int per = 0;                                                                            \
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_quad8<NTT>, NTT, 0); \
+    if (e != hipSuccess) return e;                                                          \
+    const int blocks = (std::max(1, per) * cus + 7) / 8 * 8;                               \
+    hipLaunchKernelGGL((k_quad8<NTT>), dim3(blocks), dim3(NTT), 0, s, w);                   \
+    return hipGetLastError();                                                               \
+  }
+  CLAIR_Q8(256)
+  CLAIR_Q8(128)
+  CLAIR_Q8(64)
+#undef CLAIR_Q8
   return hipErrorInvalidValue;
 }
 

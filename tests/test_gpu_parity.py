@@ -108,7 +108,8 @@ def test_cfg5_shape_ell4_scratch_path():
     assert infos[0]["max_block"] == 98
 
 
-@pytest.mark.parametrize("group,wg,chunk", [(1, 256, 2048), (1, 64, 512), (8, 64, 512), (8, 128, 1024),
+@pytest.mark.parametrize("group,wg,chunk", [(1, 256, 2048), (1, 64, 512), (4, 256, 1024), (4, 64, 2048),
+                                            (8, 64, 512), (8, 128, 1024),
                                             (16, 64, 2048), (16, 256, 512), (32, 64, 1024), (32, 128, 2048)])
 def test_tuning_shapes(group, wg, chunk):
     from paper_2307_00229_amd import clair
