@@ -60,6 +60,126 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int* total) 
   return incl - v;
 }
 
+// Workgroup-wide neighbourhood search for rows of any size up to kWN points:
+// the same set as team_bfs (F-points reachable from C-point i by at most ell
+// edges with F-points inside the walk).  The entries of a level's frontier
+// rows are taken in windows of kWC: each window is sorted (bitonic, in LDS),
+// reduced to points that are new (first of their run, not yet in N, not yet
+// in this level) and merged into the level.  No bound on the number of
+// candidates, so dense coarse-level rows work too.
+struct WideBuf {
+  int nb0[kWN], nb1[kWN];  // neighbourhood, double buffered, sorted
+  int fr[kWN];             // frontier: the previous level's new points, sorted
+  int nl[kWN];             // this level's new points so far, sorted
+  int dp[kWN + 1];         // prefix of the frontier's row lengths
+  int cand[kWC];           // window candidates (sorted in place)
+  int kb[kWC];             // kept candidates of the window, sorted
+  int sh[kNT];             // scan scratch
+};
+
+// Returns |N(i)| with the sorted list in *out, or -1 when it exceeds kWN
+// (block-uniform).  Must be called by all kNT threads of the workgroup.
+__device__ int block_bfs(int n, int i, int ell, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                         const double* __restrict__ va, const int8_t* __restrict__ cf, WideBuf& b, int** out) {
+  const int tid = threadIdx.x;
+  constexpr int nt = kNT;
+  int* cur = b.nb0;
+  int* nxt = b.nb1;
+  int s = 0;
+  int fsz = 1;  // level-0 frontier is {i}
+  for (int depth = 1; depth <= ell && fsz > 0; ++depth) {
+    // row lengths of the frontier, prefix
+    const int per = (fsz + nt - 1) / nt;
+    const int t0 = tid * per, t1 = min(t0 + per, fsz);
+    int sum = 0;
+    for (int t = t0; t < t1; ++t) {
+      const int u = (depth == 1) ? i : b.fr[t];
+      sum += rp[u + 1] - rp[u];
+    }
+    int E;
+    int pre = block_exclusive_scan(sum, b.sh, &E);
+    for (int t = t0; t < t1; ++t) {
+      const int u = (depth == 1) ? i : b.fr[t];
+      b.dp[t] = pre;
+      pre += rp[u + 1] - rp[u];
+    }
+    if (tid == 0) b.dp[fsz] = E;
+    __syncthreads();
+    int nnl = 0;
+    for (int w0 = 0; w0 < E; w0 += kWC) {
+      const int wn = min(kWC, E - w0);
+      int P = 1;
+      while (P < wn) P <<= 1;
+      for (int t = tid; t < P; t += nt) {
+        int k = INT32_MAX;
+        if (t < wn) {
+          const int ef = w0 + t;
+          int lo = 0, hi = fsz - 1;  // last frontier vertex with dp <= ef
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (b.dp[mid] <= ef) lo = mid; else hi = mid - 1;
+          }
+          const int u = (depth == 1) ? i : b.fr[lo];
+          const int e = rp[u] + (ef - b.dp[lo]);
+          const int kk = ci[e];
+          if (kk != u && (unsigned)kk < (unsigned)n && va[e] != 0.0 && cf[kk] == 0) k = kk;
+        }
+        b.cand[t] = k;
+      }
+      __syncthreads();
+      for (int kk = 2; kk <= P; kk <<= 1) {
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+          for (int t = tid; t < P; t += nt) {
+            const int x = t ^ j;
+            if (x > t) {
+              const int a = b.cand[t], c2 = b.cand[x];
+              if ((a > c2) == ((t & kk) == 0)) { b.cand[t] = c2; b.cand[x] = a; }
+            }
+          }
+          __syncthreads();
+        }
+      }
+      const int per2 = (P + nt - 1) / nt;
+      const int q0 = tid * per2, q1 = min(q0 + per2, P);
+      int kept = 0;
+      for (int t = q0; t < q1; ++t) {
+        const int x = b.cand[t];
+        kept += (x != INT32_MAX && (t == 0 || b.cand[t - 1] != x) && find_sorted(cur, s, x) < 0 &&
+                 find_sorted(b.nl, nnl, x) < 0) ? 1 : 0;
+      }
+      int kn;
+      int kp = block_exclusive_scan(kept, b.sh, &kn);
+      for (int t = q0; t < q1; ++t) {
+        const int x = b.cand[t];
+        if (x != INT32_MAX && (t == 0 || b.cand[t - 1] != x) && find_sorted(cur, s, x) < 0 &&
+            find_sorted(b.nl, nnl, x) < 0)
+          b.kb[kp++] = x;
+      }
+      __syncthreads();
+      if (s + nnl + kn > kWN) return -1;
+      for (int t = tid; t < nnl; t += nt) nxt[t + lower_bound_i32(b.kb, kn, b.nl[t])] = b.nl[t];
+      for (int t = tid; t < kn; t += nt) nxt[t + lower_bound_i32(b.nl, nnl, b.kb[t])] = b.kb[t];
+      __syncthreads();
+      nnl += kn;
+      for (int t = tid; t < nnl; t += nt) b.nl[t] = nxt[t];
+      __syncthreads();
+    }
+    for (int t = tid; t < s; t += nt) nxt[t + lower_bound_i32(b.nl, nnl, cur[t])] = cur[t];
+    for (int t = tid; t < nnl; t += nt) {
+      nxt[t + lower_bound_i32(cur, s, b.nl[t])] = b.nl[t];
+      b.fr[t] = b.nl[t];
+    }
+    __syncthreads();
+    int* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+    s += nnl;
+    fsz = nnl;
+  }
+  *out = cur;
+  return s;
+}
+
 // chunk index of global row g: binary search in chunk_rbase[0..nch]
 __device__ __forceinline__ int row_chunk(const int32_t* rbase, int nch, int g) {
   int lo = 0, hi = nch - 1;
@@ -348,19 +468,12 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
 }
 
 // chunks with rows the lane-group search could not size: one workgroup each
-struct BigBuf {
-  int nb0[kWN], nb1[kWN], fr[kWN];
-  int cand[kWC], keep[kWC];
-  int cnt[2];
-};
-
 __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
-  __shared__ BigBuf bb;
+  __shared__ WideBuf bb;
   __shared__ int s_size[kMaxChunk];
   __shared__ int s_scan[kNT];
   __shared__ int s_max;
   const int tid = threadIdx.x;
-  BlockTeam tm{kNT, tid};
   const int nov = w.cnt->novf;
   for (int k = blockIdx.x; k < nov; k += gridDim.x) {
     const int c = w.ovf_chunks[k];
@@ -381,8 +494,7 @@ __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
       if (ci >= 0) continue;  // uniform
       const int i = -ci - 1;
       int* nl;
-      const int s = team_bfs(tm, d.n, i, d.ell, d.rp, d.ci, d.va, d.cf,
-                             BfsBuf{bb.nb0, bb.nb1, bb.fr, bb.cand, bb.keep, bb.cnt, kWN, kWC}, &nl);
+      const int s = block_bfs(d.n, i, d.ell, d.rp, d.ci, d.va, d.cf, bb, &nl);
       __syncthreads();
       // small enough for a lane-group solver: its slot; else the workgroup solver
       const int lim = small_limit(w.GA);
@@ -1244,13 +1356,8 @@ __global__ __launch_bounds__(NT) void k_rows8(Work w) {
 // ---------------------------------------------------------------------------
 // workgroup-per-row FP64 solver (bin C)
 // ---------------------------------------------------------------------------
-struct WgBuf {
-  int nb0[kWN], nb1[kWN], fr[kWN];
-  int cand[kWC], keep[kWC];
-  int cnt[2];
-};
-
 constexpr int kWT = 256;
+static_assert(kWT == kNT, "block_bfs runs on kNT threads");
 
 __device__ __forceinline__ void block_argmax(double v, int idx, double* shv, int* shi, double* outv, int* outi) {
   const int tid = threadIdx.x;
@@ -1271,7 +1378,7 @@ __device__ __forceinline__ void block_argmax(double v, int idx, double* shv, int
 }
 
 __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
-  __shared__ WgBuf bb;
+  __shared__ WideBuf bb;
   __shared__ double sK[kLdsBlockMax * (kLdsBlockMax + 1)];
   __shared__ double sf[kMaxBlock];
   __shared__ double shv[kWT];
@@ -1279,7 +1386,6 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
   __shared__ int s_bad;
 
   const int tid = threadIdx.x;
-  BlockTeam tm{kWT, tid};
   const int qlen = min(w.cnt->nC, w.capC);
   // FP64 rows solved by this workgroup, per run of rows of one matrix
   int run_m = -1, run_n = 0;
@@ -1311,8 +1417,7 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
       const int i = ri.i;
       if (tid == 0) d.Rrp[ri.r] = ri.off;
       int* N;
-      const int s = team_bfs(tm, d.n, i, d.ell, d.rp, d.ci, d.va, d.cf,
-                             BfsBuf{bb.nb0, bb.nb1, bb.fr, bb.cand, bb.keep, bb.cnt, kWN, kWC}, &N);
+      const int s = block_bfs(d.n, i, d.ell, d.rp, d.ci, d.va, d.cf, bb, &N);
       __syncthreads();
       if (s != ri.s) {
         if (tid == 0) flag_row(st, s < 0 ? ST_UNSUPPORTED : ST_INVALID, i);

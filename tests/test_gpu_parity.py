@@ -137,6 +137,15 @@ def test_random_nonsymmetric_patterns(seed):
     _check([ps[0], ps[2]], precision=1)
 
 
+def test_dense_rows_windowed_search():
+    # about 90 entries per row: a level's candidates overflow one LDS window
+    # of the workgroup search several times; blocks up to ~430 points are
+    # solved in global scratch
+    ps = [P.random_sparse(600, 0.15, 5, ell=2), P.random_sparse(400, 0.1, 6, ell=2)]
+    res, infos = _check(ps, precision=0)
+    assert infos[0]["max_block"] > 400
+
+
 def test_random_nondominant_needs_pivoting():
     # no diagonal dominance: the FP32 no-pivot factorisation is not trusted
     # for every row, and the FP64 partial-pivoting solver takes over
