@@ -283,26 +283,26 @@ struct RegSet {
 };
 
 // the F-neighbours of u (edges with a stored nonzero), added at level L;
-// entries are read four at a time
+// entries are read eight at a time (one batch for most stencil rows)
 template <int SM>
 __device__ __forceinline__ void reg_expand(RegSet<SM>& S, int n, int u, int L, const int32_t* __restrict__ rp,
                                            const int32_t* __restrict__ ci, const double* __restrict__ va,
                                            const int8_t* __restrict__ cf) {
   const int e1 = rp[u + 1];
-  for (int e = rp[u]; e < e1 && !S.ovf; e += 4) {
-    int k[4];
-    double v[4];
+  for (int e = rp[u]; e < e1 && !S.ovf; e += 8) {
+    int k[8];
+    double v[8];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 8; ++j) {
       k[j] = u;
       v[j] = 0.0;
       if (e + j < e1) { k[j] = ci[e + j]; v[j] = va[e + j]; }
     }
-    int8_t c8[4];
+    int8_t c8[8];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) c8[j] = ((unsigned)k[j] < (unsigned)n) ? cf[k[j]] : (int8_t)1;
+    for (int j = 0; j < 8; ++j) c8[j] = ((unsigned)k[j] < (unsigned)n) ? cf[k[j]] : (int8_t)1;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 8; ++j) {
       if (k[j] != u && v[j] != 0.0 && c8[j] == 0) S.insert(k[j], L);
     }
   }

@@ -621,22 +621,72 @@ struct NumGroupBuf {
   int nb[G];              // sorted N(i)
 };
 
+// Communication inside a group of G lanes (G = 8, 16 or 32; groups are
+// aligned runs of G lanes of a wavefront).
+//
+// gbi: lane k of the group to all its lanes.  ds_swizzle in bit mode keeps
+// the lane bits above the group (and-mask 32 - G) and sets the rest to k; the
+// pattern is an immediate, so k must fold to a constant (unrolled loops).
+template <int G>
+__device__ __forceinline__ int gbi(int v, int k) {
+  static_assert(G == 8 || G == 16 || G == 32, "group size");
+#define CLAIR_SWZ(K) \
+  case K: return __builtin_amdgcn_ds_swizzle(v, (32 - G) | ((K) << 5));
+  switch (k) {
+    CLAIR_SWZ(0) CLAIR_SWZ(1) CLAIR_SWZ(2) CLAIR_SWZ(3) CLAIR_SWZ(4) CLAIR_SWZ(5) CLAIR_SWZ(6) CLAIR_SWZ(7)
+    CLAIR_SWZ(8) CLAIR_SWZ(9) CLAIR_SWZ(10) CLAIR_SWZ(11) CLAIR_SWZ(12) CLAIR_SWZ(13) CLAIR_SWZ(14) CLAIR_SWZ(15)
+    CLAIR_SWZ(16) CLAIR_SWZ(17) CLAIR_SWZ(18) CLAIR_SWZ(19) CLAIR_SWZ(20) CLAIR_SWZ(21) CLAIR_SWZ(22) CLAIR_SWZ(23)
+    CLAIR_SWZ(24) CLAIR_SWZ(25) CLAIR_SWZ(26) CLAIR_SWZ(27) CLAIR_SWZ(28) CLAIR_SWZ(29) CLAIR_SWZ(30)
+    default: return __builtin_amdgcn_ds_swizzle(v, (32 - G) | (31 << 5));
+  }
+#undef CLAIR_SWZ
+}
+template <int G>
+__device__ __forceinline__ float gbf(float v, int k) { return __int_as_float(gbi<G>(__float_as_int(v), k)); }
+
+// gpart: the value of a partner lane for a butterfly-like reduction.  Steps 1
+// and 2 pair lanes inside a quad (DPP quad_perm [1,0,3,2] and [2,3,0,1]), step
+// 4 mirrors the halves of 8 lanes (DPP row_half_mirror), step 8 mirrors the
+// halves of 16 (DPP row_mirror), step 16 swaps the halves of 32 (ds_swizzle
+// xor 16).  After the steps up to G/2 every lane holds the group's reduction.
+template <int STEP>
+__device__ __forceinline__ int gpart(int v) {
+  if constexpr (STEP == 1) return __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);
+  else if constexpr (STEP == 2) return __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);
+  else if constexpr (STEP == 4) return __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false);
+  else if constexpr (STEP == 8) return __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false);
+  else return __builtin_amdgcn_ds_swizzle(v, 0x1f | (0x10 << 10));
+}
+template <int STEP>
+__device__ __forceinline__ double gpartd(double v) {
+  return __hiloint2double(gpart<STEP>(__double2hiint(v)), gpart<STEP>(__double2loint(v)));
+}
+
 template <int G>
 __device__ __forceinline__ float group_maxf(float v) {
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, G));
+  v = fmaxf(v, __int_as_float(gpart<1>(__float_as_int(v))));
+  v = fmaxf(v, __int_as_float(gpart<2>(__float_as_int(v))));
+  if constexpr (G >= 8) v = fmaxf(v, __int_as_float(gpart<4>(__float_as_int(v))));
+  if constexpr (G >= 16) v = fmaxf(v, __int_as_float(gpart<8>(__float_as_int(v))));
+  if constexpr (G >= 32) v = fmaxf(v, __int_as_float(gpart<16>(__float_as_int(v))));
   return v;
 }
 template <int G>
 __device__ __forceinline__ double group_maxd(double v) {
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, G));
+  v = fmax(v, gpartd<1>(v));
+  v = fmax(v, gpartd<2>(v));
+  if constexpr (G >= 8) v = fmax(v, gpartd<4>(v));
+  if constexpr (G >= 16) v = fmax(v, gpartd<8>(v));
+  if constexpr (G >= 32) v = fmax(v, gpartd<16>(v));
   return v;
 }
 template <int G>
 __device__ __forceinline__ int group_ori(int v) {
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o, G);
+  v |= gpart<1>(v);
+  v |= gpart<2>(v);
+  if constexpr (G >= 8) v |= gpart<4>(v);
+  if constexpr (G >= 16) v |= gpart<8>(v);
+  if constexpr (G >= 32) v |= gpart<16>(v);
   return v;
 }
 
@@ -646,16 +696,27 @@ template <int G>
 __device__ __forceinline__ float lu_solve(const float (&kf)[G], float uinv, int lane, float y) {
 #pragma unroll
   for (int k = 0; k < G; ++k) {
-    const float yk = __shfl(y, k, G);
+    const float yk = gbf<G>(y, k);
     if (lane > k) y = fmaf(-kf[k], yk, y);
   }
 #pragma unroll
   for (int k = G - 1; k >= 0; --k) {
     if (lane == k) y *= uinv;
-    const float zk = __shfl(y, k, G);
+    const float zk = gbf<G>(y, k);
     if (lane < k) y = fmaf(-kf[k], zk, y);
   }
   return y;
+}
+
+// Position of key in the G sorted entries nb[0..G) (padded with INT32_MAX),
+// or -1: a branch-free lower bound of fixed depth log2(G).  Several searches
+// in a row have no loop between them, so their LDS reads overlap.
+template <int G>
+__device__ __forceinline__ int find_pos(const int* nb, int key) {
+  int pos = 0;
+#pragma unroll
+  for (int step = G / 2; step >= 1; step >>= 1) pos += (nb[pos + step - 1] < key) ? step : 0;
+  return (pos < G && nb[pos] == key) ? pos : -1;
 }
 
 constexpr int kRefineMax = 5;
@@ -689,16 +750,49 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
   if (tid == 0) s_itmax = 0;
   __syncthreads();
   ChunkCursor cc;
+  // The group works one row ahead: while row g is solved, the chunk-local
+  // data, the slot entry and the A-row bounds of row g + NG (same chunk) are
+  // already on their way, so a row starts with only its A entries to load.
+  int nx_t = 0, nx_i = 0, nx_off = 0, nx_s = -1, nx_N = 0, nx_e0 = 0, nx_e1 = 0, nx_f0 = 0, nx_f1 = 0;
+  bool ahead = false;
 
   for (int gbase = r0; gbase < r1; gbase += NG) {
     const int g = gbase + grp;
     if (g >= r1) break;  // group-uniform
-    cc.seek(w, g);
-    int t, i, off, s;
-    cc.row(w, g, &t, &i, &off, &s);
-    if (s < smin || s > G) continue;  // another solver's row (group-uniform)
-    const int myN0 = slots[(cc.fbase + t) * sstride + min(lane, sstride - 1)];
-    if (!cc.live) continue;
+    int t, i, off, s, myN0, ae0, ae1, fe0, fe1;
+    if (ahead) {
+      t = nx_t; i = nx_i; off = nx_off; s = nx_s; myN0 = nx_N;
+      ae0 = nx_e0; ae1 = nx_e1; fe0 = nx_f0; fe1 = nx_f1;
+    } else {
+      cc.seek(w, g);
+      cc.row(w, g, &t, &i, &off, &s);
+      myN0 = slots[(cc.fbase + t) * sstride + min(lane, sstride - 1)];
+      ae0 = 0; ae1 = 0; fe0 = 0; fe1 = 0;
+      if (s >= smin && s <= G && cc.live) {
+        if (lane < s) { ae0 = cc.md.rp[myN0]; ae1 = cc.md.rp[myN0 + 1]; }
+        fe0 = cc.md.rp[i];
+        fe1 = cc.md.rp[i + 1];
+      }
+    }
+    // the next row of this group, if it lies in the same chunk: its
+    // chunk-local data and slot entry now, its A-row bounds after the gather
+    const int gn = g + NG;
+    ahead = gn < r1 && gn < cc.re;
+    if (ahead) {
+      cc.row(w, gn, &nx_t, &nx_i, &nx_off, &nx_s);
+      nx_N = slots[(cc.fbase + nx_t) * sstride + min(lane, sstride - 1)];
+    }
+    const bool mine = s >= smin && s <= G && cc.live;  // group-uniform
+    const bool nx_mine = ahead && nx_s >= smin && nx_s <= G && cc.live;
+    if (!mine) {
+      if (nx_mine) {
+        nx_e0 = 0; nx_e1 = 0;
+        if (lane < nx_s) { nx_e0 = cc.md.rp[nx_N]; nx_e1 = cc.md.rp[nx_N + 1]; }
+        nx_f0 = cc.md.rp[nx_i];
+        nx_f1 = cc.md.rp[nx_i + 1];
+      }
+      continue;  // another solver's row
+    }
     const int c = cc.c;
     const int entry = c * w.chunk + t;
     const MatDesc& d = cc.md;
@@ -721,32 +815,32 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
     for (int tt = 0; tt < G; ++tt) gb.K[tt * LD + lane] = (tt == lane && tt >= s) ? 1.0 : 0.0;
     gb.f[lane] = 0.0;
     wave_sync();
-    if (lane < s) {
-      const int e1 = d.rp[myN + 1];
-      for (int e = d.rp[myN]; e < e1; e += 4) {
-        int k[4];
-        double v[4];
+    for (int e = ae0; e < ae1; e += 4) {
+      int k[4];
+      double v[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          k[j] = -1;
-          v[j] = 0.0;
-          if (e + j < e1) { k[j] = d.ci[e + j]; v[j] = d.va[e + j]; }
-        }
+      for (int j = 0; j < 4; ++j) {
+        k[j] = -1;
+        v[j] = 0.0;
+        if (e + j < ae1) { k[j] = d.ci[e + j]; v[j] = d.va[e + j]; }
+      }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int qq = find_sorted(gb.nb, s, k[j]);
-          if (qq >= 0) gb.K[qq * LD + lane] = v[j];
-        }
+      for (int j = 0; j < 4; ++j) {
+        const int qq = find_pos<G>(gb.nb, k[j]);
+        if (qq >= 0) gb.K[qq * LD + lane] = v[j];
       }
     }
-    {
-      const int e1 = d.rp[i + 1];
-      for (int e = d.rp[i] + lane; e < e1; e += G) {
-        const int qq = find_sorted(gb.nb, s, d.ci[e]);
-        if (qq >= 0) gb.f[qq] = -d.va[e];
-      }
+    for (int e = fe0 + lane; e < fe1; e += G) {
+      const int qq = find_pos<G>(gb.nb, d.ci[e]);
+      if (qq >= 0) gb.f[qq] = -d.va[e];
     }
     wave_sync();
+    if (nx_mine) {
+      nx_e0 = 0; nx_e1 = 0;
+      if (lane < nx_s) { nx_e0 = d.rp[nx_N]; nx_e1 = d.rp[nx_N + 1]; }
+      nx_f0 = d.rp[nx_i];
+      nx_f1 = d.rp[nx_i + 1];
+    }
 
     // ---- FP32 LU of the row-scaled block ----
     float amax = 0.f;
@@ -775,10 +869,13 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
       }
       wave_sync();
       const float piv = gb.U[k * G + k];
-      if (lane == k) uinv = 1.f / piv;
+      // FP32 factors only precondition the FP64 refinement: the hardware
+      // reciprocal (1 ulp) is accurate enough
+      const float pinv = __builtin_amdgcn_rcpf(piv);
+      if (lane == k) uinv = pinv;
       bad |= !(fabsf(piv) >= 0x1p-24f);
       if (lane > k) {
-        const float l = kf[k] / piv;
+        const float l = kf[k] * pinv;
         kf[k] = l;
 #pragma unroll
         for (int p = k + 1; p < G; ++p) kf[p] = fmaf(-l, gb.U[k * G + p], kf[p]);
