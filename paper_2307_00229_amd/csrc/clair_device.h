@@ -77,6 +77,7 @@ struct Work {
   int32_t* chunk_rbase;   // [nchunks+1] first global row of each chunk
   int64_t* chunk_nzglob;  // [nchunks] first R entry of each chunk, batch-wide
   int32_t* chunk_mat;     // [nchunks]
+  int2* chunk_bins;       // [nchunks] rows of the chunk in bin A (x) and bin B (y)
   int32_t* clocal;        // [n_total] chunk-local C-points (negative while unsized)
   int32_t* lnz;           // [n_total] chunk-local prefix of |N(i)|+1
   double* dsum;           // [n_total]

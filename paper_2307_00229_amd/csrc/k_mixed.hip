@@ -44,20 +44,28 @@ constexpr int kWN = kMaxBlock;
 constexpr int kWC = 4096;
 
 __device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int* total) {
-  // sh: blockDim.x ints.  Hillis-Steele over one value per thread.
-  const int tid = threadIdx.x;
-  sh[tid] = v;
-  __syncthreads();
-  for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-    int t = (tid >= off) ? sh[tid - off] : 0;
-    __syncthreads();
-    sh[tid] += t;
-    __syncthreads();
+  // sh: at least blockDim.x / 64 ints.  Inclusive scan inside each wavefront
+  // (six shuffle steps), then the wavefront totals through LDS: two barriers.
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
   }
-  int incl = sh[tid];
-  *total = sh[blockDim.x - 1];
+  if (lane == 63) sh[wid] = x;
   __syncthreads();
-  return incl - v;
+  int base = 0, tot = 0;
+  for (int k = 0; k < nw; ++k) {
+    const int t = sh[k];
+    base += (k < wid) ? t : 0;
+    tot += t;
+  }
+  *total = tot;
+  __syncthreads();
+  return base + x - v;
 }
 
 // Workgroup-wide neighbourhood search for rows of any size up to kWN points:
@@ -349,7 +357,7 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
   const int64_t base = d.fine0 + f0;
 
   if (st->status == ST_INVALID) {  // validation failed: contribute nothing
-    if (tid == 0) { w.chunk_nc[c] = 0; w.chunk_nnz[c] = 0; w.chunk_mat[c] = m; }
+    if (tid == 0) { w.chunk_nc[c] = 0; w.chunk_nnz[c] = 0; w.chunk_mat[c] = m; w.chunk_bins[c] = make_int2(0, 0); }
     return;
   }
 
@@ -457,9 +465,11 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
     w.chunk_nc[c] = nc;
     w.chunk_nnz[c] = tot;
     w.chunk_mat[c] = m;
-    atomicMax(&st->max_block, s_flag[0]);
-    if (s_flag[2]) atomicAdd(&w.cnt->nA, s_flag[2]);
-    if (s_flag[3]) atomicAdd(&w.cnt->nB, s_flag[3]);
+    // bin sizes per chunk (summed by k_scan); the largest block only when it
+    // grows, so that few workgroups meet at one address
+    w.chunk_bins[c] = make_int2(s_flag[2], s_flag[3]);
+    if (s_flag[0] > __hip_atomic_load(&st->max_block, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(&st->max_block, s_flag[0]);
     if (s_flag[1]) {
       const int q = atomicAdd(&w.cnt->novf, 1);
       w.ovf_chunks[q] = c;
@@ -514,9 +524,9 @@ __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
           s_size[t] = s;
           s_max = max(s_max, s);
           if (s <= lim) {
-            atomicAdd(&w.cnt->nA, 1);
+            w.chunk_bins[c].x += 1;
           } else if (s <= 32) {
-            atomicAdd(&w.cnt->nB, 1);
+            w.chunk_bins[c].y += 1;
           } else {
             const int q = atomicAdd(&w.cnt->nC, 1);
             if (q < w.capC) w.binC[q] = c * w.chunk + t;
@@ -549,29 +559,47 @@ __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
 // writes R.row_ptr[n_c].  Per-matrix R offsets are the global ones minus the
 // matrix's base.
 __global__ __launch_bounds__(1024) void k_scan(Work w) {
-  __shared__ long long shr[1024];
-  __shared__ long long shz[1024];
+  __shared__ long long s_wr[16], s_wz[16];
+  __shared__ int s_wa[16], s_wb[16];
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wid = tid >> 6;
   const int nch = w.nchunks;
   const int per = (nch + 1023) / 1024;
   const int c0 = min(nch, tid * per), c1 = min(nch, c0 + per);
   long long sr = 0, sz = 0;
-  for (int c = c0; c < c1; ++c) { sr += w.chunk_nc[c]; sz += w.chunk_nnz[c]; }
-  shr[tid] = sr;
-  shz[tid] = sz;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const long long a = tid >= off ? shr[tid - off] : 0;
-    const long long b = tid >= off ? shz[tid - off] : 0;
-    __syncthreads();
-    shr[tid] += a;
-    shz[tid] += b;
-    __syncthreads();
+  int ba = 0, bb = 0;
+  for (int c = c0; c < c1; ++c) {
+    sr += w.chunk_nc[c];
+    sz += w.chunk_nnz[c];
+    const int2 bn = w.chunk_bins[c];
+    ba += bn.x;
+    bb += bn.y;
   }
-  long long rr = shr[tid] - sr;
-  long long zz = shz[tid] - sz;
-  const long long rows_total = shr[1023];
-  const long long nnz_total = shz[1023];
+  // inclusive scans inside each wavefront, then across the 16 wavefronts
+  long long xr = sr, xz = sz;
+  int xa = ba, xb = bb;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const long long yr = __shfl_up(xr, o, 64);
+    const long long yz = __shfl_up(xz, o, 64);
+    const int ya = __shfl_up(xa, o, 64);
+    const int yb = __shfl_up(xb, o, 64);
+    if (lane >= o) { xr += yr; xz += yz; xa += ya; xb += yb; }
+  }
+  if (lane == 63) { s_wr[wid] = xr; s_wz[wid] = xz; s_wa[wid] = xa; s_wb[wid] = xb; }
+  __syncthreads();
+  long long br = 0, bz = 0, rows_total = 0, nnz_total = 0;
+  int na = 0, nb = 0;
+  for (int k = 0; k < 16; ++k) {
+    const long long r = s_wr[k], z = s_wz[k];
+    if (k < wid) { br += r; bz += z; }
+    rows_total += r;
+    nnz_total += z;
+    na += s_wa[k];
+    nb += s_wb[k];
+  }
+  long long rr = br + xr - sr;
+  long long zz = bz + xz - sz;
   for (int c = c0; c < c1; ++c) {
     w.chunk_rbase[c] = (int32_t)rr;
     w.chunk_nzglob[c] = zz;
@@ -606,6 +634,8 @@ __global__ __launch_bounds__(1024) void k_scan(Work w) {
   if (tid == 0) {
     w.chunk_rbase[nch] = (int32_t)rows_total;
     w.cnt->total_rows = (int32_t)rows_total;
+    w.cnt->nA = na;
+    w.cnt->nB = nb;
   }
 }
 
@@ -938,7 +968,8 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
     }
   }
   __syncthreads();
-  if (tid == 0 && s_itmax > 0) atomicMax(&w.st[m0].refine_max, s_itmax);
+  if (tid == 0 && s_itmax > __hip_atomic_load(&w.st[m0].refine_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax(&w.st[m0].refine_max, s_itmax);
 }
 
 // ---------------------------------------------------------------------------
@@ -1221,7 +1252,8 @@ __global__ __launch_bounds__(NT) void k_quad8(Work w) {
     }
   }
   __syncthreads();
-  if (tid == 0 && s_itmax > 0) atomicMax(&w.st[m0].refine_max, s_itmax);
+  if (tid == 0 && s_itmax > __hip_atomic_load(&w.st[m0].refine_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax(&w.st[m0].refine_max, s_itmax);
 }
 
 // ---------------------------------------------------------------------------
@@ -1447,7 +1479,8 @@ __global__ __launch_bounds__(NT) void k_rows8(Work w) {
     d.Rva[ri.off + dpos] = 1.0;
   }
   __syncthreads();
-  if (tid == 0 && s_itmax > 0) atomicMax(&w.st[m0].refine_max, s_itmax);
+  if (tid == 0 && s_itmax > __hip_atomic_load(&w.st[m0].refine_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax(&w.st[m0].refine_max, s_itmax);
 }
 
 // ---------------------------------------------------------------------------
