@@ -70,7 +70,7 @@ struct HostPinned {
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-  size_t desc, st, cnt, chunk_nc, chunk_nnz, chunk_rbase, chunk_nzbase, chunk_mat, chunk_bins, clocal, lnz, dsum, rsum,
+  size_t desc, st, cnt, chunk_nc, chunk_nnz, chunk_rbase, chunk_nzbase, chunk_mat, chunk_bins, row_block_chunk, clocal, lnz, dsum, rsum,
       slotA, slotB, binC, ovf, total;
   size_t head_bytes;  // desc + st + counters (the uploaded head)
   int64_t capC;
@@ -98,11 +98,12 @@ Layout make_layout(int nmat, int nchunks, int64_t n_total, int GA) {
   L.chunk_nzbase = take(sizeof(int64_t) * (nchunks + 1));
   L.chunk_mat = take(sizeof(int32_t) * (nchunks + 1));
   L.chunk_bins = take(sizeof(int2) * (nchunks + 1));
+  L.row_block_chunk = take(sizeof(int32_t) * (n_total / 256 + 2));
   L.clocal = take(sizeof(int32_t) * (n_total + 1));
   L.lnz = take(sizeof(int32_t) * (n_total + 1));
   L.dsum = take(sizeof(double) * (n_total + 1));
   L.rsum = take(sizeof(double) * (n_total + 1));
-  const int SA = GA == 1 ? 0 : (GA == 4 ? 8 : GA);  // slot stride of bin A
+  const int SA = GA <= 4 ? 8 : GA;  // slot stride of bin A
   L.slotA = take(sizeof(int32_t) * (SA ? (n_total + 1) * SA : 1));
   L.slotB = take(sizeof(int32_t) * (n_total + 1) * (GA < 32 ? 32 : 1));
   L.binC = take(sizeof(int32_t) * L.capC);
@@ -267,6 +268,7 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
   w.chunk_nzglob = reinterpret_cast<int64_t*>(base + b->L.chunk_nzbase);
   w.chunk_mat = reinterpret_cast<int32_t*>(base + b->L.chunk_mat);
   w.chunk_bins = reinterpret_cast<int2*>(base + b->L.chunk_bins);
+  w.row_block_chunk = reinterpret_cast<int32_t*>(base + b->L.row_block_chunk);
   w.clocal = reinterpret_cast<int32_t*>(base + b->L.clocal);
   w.lnz = reinterpret_cast<int32_t*>(base + b->L.lnz);
   w.dsum = reinterpret_cast<double*>(base + b->L.dsum);

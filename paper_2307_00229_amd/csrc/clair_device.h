@@ -78,6 +78,7 @@ struct Work {
   int64_t* chunk_nzglob;  // [nchunks] first R entry of each chunk, batch-wide
   int32_t* chunk_mat;     // [nchunks]
   int2* chunk_bins;       // [nchunks] rows of the chunk in bin A (x) and bin B (y)
+  int32_t* row_block_chunk;  // [n_total / 256 + 2] chunk holding global row 256 b
   int32_t* clocal;        // [n_total] chunk-local C-points (negative while unsized)
   int32_t* lnz;           // [n_total] chunk-local prefix of |N(i)|+1
   double* dsum;           // [n_total]

@@ -198,6 +198,15 @@ __device__ __forceinline__ int row_chunk(const int32_t* rbase, int nch, int g) {
   return lo;
 }
 
+// chunk index of global row g (0 <= g < total rows): the chunk holding the
+// first row of g's block of kRowBlock rows, then a short forward walk
+constexpr int kRowBlockLog = 8;
+__device__ __forceinline__ int row_chunk_fast(const Work& w, int g) {
+  int c = w.row_block_chunk[g >> kRowBlockLog];
+  while (w.chunk_rbase[c + 1] <= g) ++c;
+  return c;
+}
+
 struct RowInfo {
   int m;     // matrix
   int i;     // fine index of the C-point
@@ -245,14 +254,7 @@ struct ChunkCursor {
 
   __device__ __forceinline__ void seek(const Work& w, int g) {
     if (c >= 0 && g >= rb && g < re) return;
-    if (c < 0 || g < rb) c = 0;
-    // forward walk from the current chunk (rows only move forward in a run)
-    int lo = c, hi = w.nchunks - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (w.chunk_rbase[mid] <= g) lo = mid; else hi = mid - 1;
-    }
-    c = lo;
+    c = row_chunk_fast(w, g);
     rb = w.chunk_rbase[c];
     re = w.chunk_rbase[c + 1];
     m = w.chunk_mat[c];
@@ -335,8 +337,8 @@ struct CountGroupBuf {
 // rows the small solvers take: |N| <= 8 for the thread-per-row solver
 // (GA == 1), |N| <= GA for the lane-group solver
 __device__ __forceinline__ int small_limit(int GA) { return GA <= 4 ? 8 : GA; }
-// stride of a row's slot in slotA (0: the small solver searches itself)
-__device__ __forceinline__ int slot_stride(int GA) { return GA == 1 ? 0 : (GA == 4 ? 8 : GA); }
+// stride of a row's slot in slotA
+__device__ __forceinline__ int slot_stride(int GA) { return GA <= 4 ? 8 : GA; }
 
 __global__ __launch_bounds__(kNT) void k_count(Work w) {
   constexpr int NG = kCountNG2;
@@ -603,7 +605,11 @@ __global__ __launch_bounds__(1024) void k_scan(Work w) {
   for (int c = c0; c < c1; ++c) {
     w.chunk_rbase[c] = (int32_t)rr;
     w.chunk_nzglob[c] = zz;
-    rr += w.chunk_nc[c];
+    const int nc = w.chunk_nc[c];
+    // row blocks whose first row lies in this chunk
+    for (long long b = (rr + (1 << kRowBlockLog) - 1) >> kRowBlockLog; (b << kRowBlockLog) < rr + nc; ++b)
+      w.row_block_chunk[b] = c;
+    rr += nc;
     zz += w.chunk_nnz[c];
   }
   __syncthreads();
@@ -776,7 +782,7 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
   if (r0 >= r1) return;
   // statistics of the workgroup's first matrix gather in LDS (one global
   // atomic per workgroup); rows of later matrices in the range go straight out
-  const int m0 = w.chunk_mat[row_chunk(w.chunk_rbase, w.nchunks, r0)];
+  const int m0 = w.chunk_mat[row_chunk_fast(w, r0)];
   if (tid == 0) s_itmax = 0;
   __syncthreads();
   ChunkCursor cc;
@@ -1042,7 +1048,7 @@ __global__ __launch_bounds__(NT) void k_quad8(Work w) {
   const int r0 = lb * per;
   const int r1 = min(total, r0 + per);
   if (r0 >= r1) return;
-  const int m0 = w.chunk_mat[row_chunk(w.chunk_rbase, w.nchunks, r0)];
+  const int m0 = w.chunk_mat[row_chunk_fast(w, r0)];
   if (tid == 0) s_itmax = 0;
   __syncthreads();
   const int q0 = 2 * ql, q1 = 2 * ql + 1;  // this lane's rows of K
@@ -1079,34 +1085,37 @@ __global__ __launch_bounds__(NT) void k_quad8(Work w) {
     B.f[q0] = 0.0;
     B.f[q1] = 0.0;
     wave_sync();
-    // gather: lane l walks rows N_{2l}, N_{2l+1} of A (columns 2l, 2l+1 of K)
+    // gather: lane l walks rows N_{2l}, N_{2l+1} of A (columns 2l, 2l+1 of
+    // K) side by side, four entries of each at a time
+    {
+      int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+      if (q0 < s) { a0 = d.rp[n0]; a1 = d.rp[n0 + 1]; }
+      if (q1 < s) { b0 = d.rp[n1]; b1 = d.rp[n1 + 1]; }
+      for (int o = 0; a0 + o < a1 || b0 + o < b1; o += 4) {
+        int ka[4], kb[4];
+        double va_[4], vb_[4];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int p = q0 + h;
-      const int u = h ? n1 : n0;
-      if (p < s) {
-        const int e1 = d.rp[u + 1];
-        for (int e = d.rp[u]; e < e1; e += 4) {
-          int k[4];
-          double v[4];
+        for (int j = 0; j < 4; ++j) {
+          ka[j] = -1;
+          kb[j] = -1;
+          va_[j] = 0.0;
+          vb_[j] = 0.0;
+          if (a0 + o + j < a1) { ka[j] = d.ci[a0 + o + j]; va_[j] = d.va[a0 + o + j]; }
+          if (b0 + o + j < b1) { kb[j] = d.ci[b0 + o + j]; vb_[j] = d.va[b0 + o + j]; }
+        }
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            k[j] = -1;
-            v[j] = 0.0;
-            if (e + j < e1) { k[j] = d.ci[e + j]; v[j] = d.va[e + j]; }
-          }
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int qq = find_sorted(B.nb, s, k[j]);
-            if (qq >= 0) B.K[qq * 9 + p] = v[j];
-          }
+        for (int j = 0; j < 4; ++j) {
+          const int qa = find_pos<8>(B.nb, ka[j]);
+          const int qb_ = find_pos<8>(B.nb, kb[j]);
+          if (qa >= 0) B.K[qa * 9 + q0] = va_[j];
+          if (qb_ >= 0) B.K[qb_ * 9 + q1] = vb_[j];
         }
       }
     }
     {
       const int e1 = d.rp[i + 1];
       for (int e = d.rp[i] + ql; e < e1; e += 4) {
-        const int qq = find_sorted(B.nb, s, d.ci[e]);
+        const int qq = find_pos<8>(B.nb, d.ci[e]);
         if (qq >= 0) B.f[qq] = -d.va[e];
       }
     }
@@ -1146,7 +1155,7 @@ __global__ __launch_bounds__(NT) void k_quad8(Work w) {
       for (int p = k; p < 8; ++p) pr[p] = QB_ROW(a0, a1, k, p);
       const float piv = pr[k];
       bad |= !(fabsf(piv) >= 0x1p-24f);
-      const float pinv = 1.f / piv;
+      const float pinv = __builtin_amdgcn_rcpf(piv);
       if (q0 == k) ui0 = pinv;
       if (q1 == k) ui1 = pinv;
       if (q0 > k) {
@@ -1257,11 +1266,12 @@ __global__ __launch_bounds__(NT) void k_quad8(Work w) {
 }
 
 // ---------------------------------------------------------------------------
-// numeric pass, one thread per row with |N| <= 8: neighbourhood search, the
-// FP32 block, its LU and both triangular solves all stay in registers; the
-// FP64 residual re-reads the block's entries from A (cache-resident).  In a
-// wavefront, consecutive lanes take consecutive C-points, so their loads of
-// the same neighbour's row fall on neighbouring cache lines.
+// numeric pass, one thread per row with |N| <= 8.  The neighbourhood comes
+// from the row's slot; the FP64 block, its FP32 LU and the right-hand side
+// stay in the thread's registers, so the solve needs no communication.  A
+// wavefront takes 64 consecutive rows (neighbouring C-points: their A rows
+// share cache lines), and the rows of A are read eight entries at a time, two
+// rows side by side.
 // ---------------------------------------------------------------------------
 constexpr int kS8 = 8;
 
@@ -1292,191 +1302,226 @@ __device__ __forceinline__ void lu8_solve(const float (&K)[kS8][kS8], const floa
   }
 }
 
+// K[q][p] = A[N_p][N_q] for the entries of rows N_pa and N_pb (columns pa, pb
+// of K), eight entries of each row per batch
+template <int PA>
+__device__ __forceinline__ void gather8_pair(const int32_t* __restrict__ ci, const double* __restrict__ va,
+                                             const int (&N)[kS8], const int (&e0)[kS8], const int (&e1)[kS8],
+                                             double (&K)[kS8][kS8]) {
+  constexpr int PB = PA + 1;
+  for (int o = 0; e0[PA] + o < e1[PA] || e0[PB] + o < e1[PB]; o += 8) {
+    int ka[8], kb[8];
+    double xa[8], xb[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      ka[j] = -1;
+      kb[j] = -1;
+      xa[j] = 0.0;
+      xb[j] = 0.0;
+      if (e0[PA] + o + j < e1[PA]) { ka[j] = ci[e0[PA] + o + j]; xa[j] = va[e0[PA] + o + j]; }
+      if (e0[PB] + o + j < e1[PB]) { kb[j] = ci[e0[PB] + o + j]; xb[j] = va[e0[PB] + o + j]; }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (ka[j] >= 0) {
+        bool hit;
+        const int q = pos8(N, ka[j], &hit);
+#pragma unroll
+        for (int qq = 0; qq < kS8; ++qq)
+          if (hit && q == qq) K[qq][PA] = xa[j];
+      }
+      if (kb[j] >= 0) {
+        bool hit;
+        const int q = pos8(N, kb[j], &hit);
+#pragma unroll
+        for (int qq = 0; qq < kS8; ++qq)
+          if (hit && q == qq) K[qq][PB] = xb[j];
+      }
+    }
+  }
+}
+
 template <int NT>
 __global__ __launch_bounds__(NT) void k_rows8(Work w) {
   __shared__ int s_itmax;
   if (w.cnt->nA == 0) return;
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
   const int total = w.cnt->total_rows;
   const int lb = xcd_logical_block();
   const int per = (total + gridDim.x - 1) / gridDim.x;
   const int r0 = lb * per;
   const int r1 = min(total, r0 + per);
   if (r0 >= r1) return;
-  const int m0 = w.chunk_mat[row_chunk(w.chunk_rbase, w.nchunks, r0)];
+  const int m0 = w.chunk_mat[row_chunk_fast(w, r0)];
   if (tid == 0) s_itmax = 0;
   __syncthreads();
-  int c = row_chunk(w.chunk_rbase, w.nchunks, min(r0 + tid, r1 - 1));
+  ChunkCursor cc;
 
-  for (int g = r0 + tid; g < r1; g += NT) {
-    while (w.chunk_rbase[c + 1] <= g) ++c;
-    const RowInfo ri = row_info(w, c, g - w.chunk_rbase[c]);
-    if (ri.s > kS8) continue;
-    MatStatus* st = &w.st[ri.m];
-    if (!matrix_live(*st)) continue;
-    const MatDesc& d = w.desc[ri.m];
-    const int32_t* __restrict__ rp = d.rp;
-    const int32_t* __restrict__ ci = d.ci;
-    const double* __restrict__ va = d.va;
-    const int i = ri.i;
-    const int s = ri.s;
-    d.Rrp[ri.r] = ri.off;
+  for (int gw = r0 + (tid & ~63); gw < r1; gw += NT) {
+    const int g = gw + lane;
+    const int gend = min(gw + 64, r1);
+    for (int gc = gw; gc < gend;) {  // wavefront-uniform: one chunk at a time
+      cc.seek(w, __builtin_amdgcn_readfirstlane(gc));
+      const int cend = min(gend, cc.re);
+      int t = 0, i = 0, off = 0, s = kS8 + 1;
+      if (g >= gc && g < cend && cc.live) cc.row(w, g, &t, &i, &off, &s);
+      gc = cend;
+      if (s > kS8) continue;  // not this thread's row, or another solver's
+      const MatDesc& d = cc.md;
+      MatStatus* st = &w.st[cc.m];
+      const int32_t* __restrict__ rp = d.rp;
+      const int32_t* __restrict__ ci = d.ci;
+      const double* __restrict__ va = d.va;
+      d.Rrp[g - cc.rbase_m] = off;
 
-    RegSet<kS8> S;
-    if (reg_bfs(S, d.n, i, d.ell, rp, ci, va, d.cf) != s) {
-      flag_row(st, ST_INVALID, i);
-      continue;
-    }
-    const int(&N)[kS8] = S.v;
-
-    // f = -A[i,N]; the block is scaled by a power of two from row i's magnitude
-    double f[kS8];
+      // N(i) from the slot; unused entries INT32_MAX
+      const int4* sp = reinterpret_cast<const int4*>(w.slotA + (cc.fbase + t) * kS8);
+      const int4 sa = sp[0], sb = sp[1];
+      int N[kS8] = {sa.x, sa.y, sa.z, sa.w, sb.x, sb.y, sb.z, sb.w};
+      int e0[kS8], e1[kS8];
 #pragma unroll
-    for (int q = 0; q < kS8; ++q) f[q] = 0.0;
-    double amax_i = 0.0;
-    {
-      const int e1 = rp[i + 1];
-      for (int e = rp[i]; e < e1; ++e) {
-        const int k = ci[e];
-        const double v = va[e];
-        amax_i = fmax(amax_i, fabs(v));
-        bool hit;
-        const int q = pos8(N, k, &hit);
-#pragma unroll
-        for (int qq = 0; qq < kS8; ++qq)
-          if (hit && q == qq) f[qq] = -v;
+      for (int p = 0; p < kS8; ++p) {
+        if (p >= s) N[p] = 0x7fffffff;
+        e0[p] = 0;
+        e1[p] = 0;
+        if (p < s) { e0[p] = rp[N[p]]; e1[p] = rp[N[p] + 1]; }
       }
-    }
-    int ex = 0;
-    frexp(amax_i > 0.0 ? amax_i : 1.0, &ex);
-    const double scale = ldexp(1.0, -ex);
+      const int fi0 = rp[i], fi1 = rp[i + 1];
 
-    // K = (A[N,N])^T in FP32, identity on the padding
-    float K[kS8][kS8];
+      // f = -A[i,N]
+      double f[kS8];
 #pragma unroll
-    for (int q = 0; q < kS8; ++q)
+      for (int q = 0; q < kS8; ++q) f[q] = 0.0;
+      for (int e = fi0; e < fi1; e += 8) {
+        int kk[8];
+        double xx[8];
 #pragma unroll
-      for (int p = 0; p < kS8; ++p) K[q][p] = (q == p && q >= s) ? 1.f : 0.f;
-    int lo[kS8], hi[kS8];
-    double amaxK = 0.0;
+        for (int j = 0; j < 8; ++j) {
+          kk[j] = -1;
+          xx[j] = 0.0;
+          if (e + j < fi1) { kk[j] = ci[e + j]; xx[j] = va[e + j]; }
+        }
 #pragma unroll
-    for (int p = 0; p < kS8; ++p) {
-      lo[p] = 0;
-      hi[p] = 0;
-      if (p < s) {
-        lo[p] = rp[N[p]];
-        hi[p] = rp[N[p] + 1];
-      }
-    }
-#pragma unroll
-    for (int p = 0; p < kS8; ++p) {
-      for (int e = lo[p]; e < hi[p]; ++e) {
-        const int k = ci[e];
-        const double v = va[e];
-        bool hit;
-        const int q = pos8(N, k, &hit);
-        if (hit) amaxK = fmax(amaxK, fabs(v));
-        const float vs = (float)(v * scale);
-#pragma unroll
-        for (int qq = 0; qq < kS8; ++qq)
-          if (hit && q == qq) K[qq][p] = vs;
-      }
-    }
-
-    // FP32 LU without pivoting; a small or non-finite pivot hands the row to
-    // the FP64 solver with partial pivoting
-    const float tiny = (float)(amaxK * scale) * 0x1p-20f;
-    float inv[kS8];
-    bool bad = !(amaxK * scale < 1e30);
-#pragma unroll
-    for (int k = 0; k < kS8; ++k) {
-      const float piv = K[k][k];
-      bad |= !(fabsf(piv) > tiny);
-      inv[k] = 1.f / piv;
-#pragma unroll
-      for (int q = k + 1; q < kS8; ++q) {
-        const float l = K[q][k] * inv[k];
-        K[q][k] = l;
-#pragma unroll
-        for (int p = k + 1; p < kS8; ++p) K[q][p] = fmaf(-l, K[k][p], K[q][p]);
-      }
-    }
-
-    double z[kS8];
-    int it = 0;
-    bool conv = false;
-    if (!bad) {
-      float y[kS8];
-#pragma unroll
-      for (int q = 0; q < kS8; ++q) y[q] = (float)(f[q] * scale);
-      lu8_solve(K, inv, y);
-#pragma unroll
-      for (int q = 0; q < kS8; ++q) z[q] = (double)y[q];
-      double fnorm = 0.0;
-#pragma unroll
-      for (int q = 0; q < kS8; ++q) fnorm = fmax(fnorm, fabs(f[q]));
-      const double knorm = amaxK * s;
-      for (it = 1; it <= kRefineMax; ++it) {
-        // r = f - K z with the FP64 entries of A[N,N]
-        double r[kS8];
-#pragma unroll
-        for (int q = 0; q < kS8; ++q) r[q] = f[q];
-#pragma unroll
-        for (int p = 0; p < kS8; ++p) {
-          for (int e = lo[p]; e < hi[p]; ++e) {
+        for (int j = 0; j < 8; ++j) {
+          if (kk[j] >= 0) {
             bool hit;
-            const int q = pos8(N, ci[e], &hit);
-            const double t = va[e] * z[p];
+            const int q = pos8(N, kk[j], &hit);
 #pragma unroll
             for (int qq = 0; qq < kS8; ++qq)
-              if (hit && q == qq) r[qq] -= t;
+              if (hit && q == qq) f[qq] = -xx[j];
           }
         }
-        double rn = 0.0, zn = 0.0;
-#pragma unroll
-        for (int q = 0; q < kS8; ++q) {
-          rn = fmax(rn, fabs(r[q]));
-          zn = fmax(zn, fabs(z[q]));
-        }
-        if (rn <= 0x1p-47 * (knorm * zn + fnorm)) { conv = true; break; }
-#pragma unroll
-        for (int q = 0; q < kS8; ++q) y[q] = (float)(r[q] * scale);
-        lu8_solve(K, inv, y);
-#pragma unroll
-        for (int q = 0; q < kS8; ++q) z[q] += (double)y[q];
       }
-#pragma unroll
-      for (int q = 0; q < kS8; ++q) conv &= (z[q] == z[q]);
-    }
-    if (!conv) {
-      // FP32 factorisation not trusted: the workgroup solver redoes the row in FP64
-      const int qc = atomicAdd(&w.cnt->nC, 1);
-      if (qc < w.capC) w.binC[qc] = c * w.chunk + (g - w.chunk_rbase[c]);
-      else flag_row(st, ST_UNSUPPORTED, i);
-      continue;
-    }
-    if (ri.m == m0) atomicMax(&s_itmax, it);
-    else atomicMax(&st->refine_max, it);
 
-    // R row: the F-entries of N(i) around the injected C-point
-    int dpos = 0;
+      // K = (A[N,N])^T in FP64, identity on the padding
+      double K[kS8][kS8];
 #pragma unroll
-    for (int p = 0; p < kS8; ++p) dpos += (N[p] < i) ? 1 : 0;
-    const double bi = d.B ? d.B[i] : 0.0;
+      for (int q = 0; q < kS8; ++q)
 #pragma unroll
-    for (int p = 0; p < kS8; ++p) {
-      if (p < s) {
-        const int pos = ri.off + p + (p >= dpos ? 1 : 0);
-        d.Rci[pos] = N[p];
-        d.Rva[pos] = z[p];
-        if (d.B) {
-          unsafeAtomicAdd(&w.dsum[ri.fine0 + N[p]], bi * bi);
-          unsafeAtomicAdd(&w.rsum[ri.fine0 + N[p]], z[p] * bi);
+        for (int p = 0; p < kS8; ++p) K[q][p] = (q == p && q >= s) ? 1.0 : 0.0;
+      gather8_pair<0>(ci, va, N, e0, e1, K);
+      gather8_pair<2>(ci, va, N, e0, e1, K);
+      gather8_pair<4>(ci, va, N, e0, e1, K);
+      gather8_pair<6>(ci, va, N, e0, e1, K);
+
+      // scale by a power of two, FP32 LU without pivoting; a small or
+      // non-finite pivot hands the row to the FP64 solver with pivoting
+      double amax = 0.0, knorm = 0.0, fnorm = 0.0;
+#pragma unroll
+      for (int q = 0; q < kS8; ++q) {
+        double rs = 0.0;
+#pragma unroll
+        for (int p = 0; p < kS8; ++p) {
+          amax = fmax(amax, fabs(K[q][p]));
+          rs += fabs(K[q][p]);
+        }
+        knorm = fmax(knorm, rs);
+        fnorm = fmax(fnorm, fabs(f[q]));
+      }
+      int ex = 0;
+      frexp(amax > 0.0 ? amax : 1.0, &ex);
+      const double scale = ldexp(1.0, -ex);
+      float L[kS8][kS8];
+#pragma unroll
+      for (int q = 0; q < kS8; ++q)
+#pragma unroll
+        for (int p = 0; p < kS8; ++p) L[q][p] = (float)(K[q][p] * scale);
+      float inv[kS8];
+      bool bad = !(amax > 0.0) || !(amax * scale < 1e30);
+#pragma unroll
+      for (int k = 0; k < kS8; ++k) {
+        const float piv = L[k][k];
+        bad |= !(fabsf(piv) >= 0x1p-24f);
+        inv[k] = __builtin_amdgcn_rcpf(piv);
+#pragma unroll
+        for (int q = k + 1; q < kS8; ++q) {
+          const float l = L[q][k] * inv[k];
+          L[q][k] = l;
+#pragma unroll
+          for (int p = k + 1; p < kS8; ++p) L[q][p] = fmaf(-l, L[k][p], L[q][p]);
         }
       }
+
+      double z[kS8];
+      int it = 0;
+      bool conv = false;
+      if (!bad) {
+        float y[kS8];
+#pragma unroll
+        for (int q = 0; q < kS8; ++q) y[q] = (float)(f[q] * scale);
+        lu8_solve(L, inv, y);
+#pragma unroll
+        for (int q = 0; q < kS8; ++q) z[q] = (double)y[q];
+        for (it = 1; it <= kRefineMax; ++it) {
+          double rn = 0.0, zn = 0.0;
+#pragma unroll
+          for (int q = 0; q < kS8; ++q) {
+            double r = f[q];
+#pragma unroll
+            for (int p = 0; p < kS8; ++p) r = fma(-K[q][p], z[p], r);
+            y[q] = (float)(r * scale);
+            rn = fmax(rn, fabs(r));
+            zn = fmax(zn, fabs(z[q]));
+          }
+          if (rn <= 0x1p-47 * (knorm * zn + fnorm)) { conv = true; break; }
+          lu8_solve(L, inv, y);
+#pragma unroll
+          for (int q = 0; q < kS8; ++q) z[q] += (double)y[q];
+        }
+#pragma unroll
+        for (int q = 0; q < kS8; ++q) conv &= (z[q] == z[q]);
+      }
+      if (!conv) {
+        // FP32 factorisation not trusted: the workgroup solver redoes the row in FP64
+        const int qc = atomicAdd(&w.cnt->nC, 1);
+        if (qc < w.capC) w.binC[qc] = cc.c * w.chunk + t;
+        else flag_row(st, ST_UNSUPPORTED, i);
+        continue;
+      }
+      if (cc.m == m0) atomicMax(&s_itmax, it);
+      else atomicMax(&st->refine_max, it);
+
+      // R row: the F-entries of N(i) around the injected C-point
+      int dpos = 0;
+#pragma unroll
+      for (int p = 0; p < kS8; ++p) dpos += (N[p] < i) ? 1 : 0;
+      const double bi = d.B ? d.B[i] : 0.0;
+#pragma unroll
+      for (int p = 0; p < kS8; ++p) {
+        if (p < s) {
+          const int pos = off + p + (p >= dpos ? 1 : 0);
+          d.Rci[pos] = N[p];
+          d.Rva[pos] = z[p];
+          if (d.B) {
+            unsafeAtomicAdd(&w.dsum[cc.fine0 + N[p]], bi * bi);
+            unsafeAtomicAdd(&w.rsum[cc.fine0 + N[p]], z[p] * bi);
+          }
+        }
+      }
+      d.Rci[off + dpos] = i;
+      d.Rva[off + dpos] = 1.0;
     }
-    d.Rci[ri.off + dpos] = i;
-    d.Rva[ri.off + dpos] = 1.0;
   }
   __syncthreads();
   if (tid == 0 && s_itmax > __hip_atomic_load(&w.st[m0].refine_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
@@ -1665,33 +1710,54 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
 // ---------------------------------------------------------------------------
 // projection
 // ---------------------------------------------------------------------------
-constexpr int kPG = 8;  // lanes per row
-
 __global__ __launch_bounds__(256) void k_project(Work w) {
+  // one thread per row: a wavefront covers 64 consecutive rows, i.e. a
+  // contiguous run of R; a row's entries are read eight at a time and all
+  // their column sums are gathered before any is used.  The chunk data is
+  // looked up once per wavefront and chunk (wavefront-uniform values).
   const int tid = threadIdx.x;
-  const int lane = tid % kPG;
-  const int grp = tid / kPG;
-  constexpr int NG = 256 / kPG;
+  const int lane = tid & 63;
   const int total = w.cnt->total_rows;
   const int lb = xcd_logical_block();
   const int per = (total + gridDim.x - 1) / gridDim.x;
   const int r0 = lb * per;
   const int r1 = min(total, r0 + per);
   ChunkCursor cc;
-  for (int gbase = r0; gbase < r1; gbase += NG) {
-    const int g = gbase + grp;
-    if (g >= r1) break;
-    cc.seek(w, g);
-    if (!cc.live || !cc.md.B) continue;
-    int t, i, off, sz;
-    cc.row(w, g, &t, &i, &off, &sz);
-    const MatDesc& d = cc.md;
-    const double bi = d.B[i];
-    for (int e = off + lane; e <= off + sz; e += kPG) {
-      const int j = d.Rci[e];
-      if (j == i) continue;
-      const double dj = w.dsum[cc.fine0 + j];
-      if (dj > 0.0) d.Rva[e] -= bi * (w.rsum[cc.fine0 + j] - d.B[j]) / dj;
+  for (int gw = r0 + (tid & ~63); gw < r1; gw += blockDim.x) {
+    const int g = gw + lane;
+    const int gend = min(gw + 64, r1);
+    for (int gc = gw; gc < gend;) {  // wavefront-uniform
+      cc.seek(w, __builtin_amdgcn_readfirstlane(gc));
+      const int cend = min(gend, cc.re);
+      if (g >= gc && g < cend && cc.live && cc.md.B) {
+        int t, i, off, sz;
+        cc.row(w, g, &t, &i, &off, &sz);
+        const MatDesc& d = cc.md;
+        const double bi = d.B[i];
+        const int64_t f0 = cc.fine0;
+        const int e1 = off + sz + 1;
+        for (int e0 = off; e0 < e1; e0 += 8) {
+          int j[8];
+          double z[8], dj[8], rj[8], bj[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            j[k] = -1;
+            z[k] = 0.0;
+            if (e0 + k < e1) { j[k] = d.Rci[e0 + k]; z[k] = d.Rva[e0 + k]; }
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            dj[k] = 0.0;
+            rj[k] = 0.0;
+            bj[k] = 0.0;
+            if (j[k] >= 0 && j[k] != i) { dj[k] = w.dsum[f0 + j[k]]; rj[k] = w.rsum[f0 + j[k]]; bj[k] = d.B[j[k]]; }
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            if (dj[k] > 0.0) d.Rva[e0 + k] = z[k] - bi * (rj[k] - bj[k]) / dj[k];
+        }
+      }
+      gc = cend;
     }
   }
   // uncovered F-points: one global atomic per workgroup and matrix
