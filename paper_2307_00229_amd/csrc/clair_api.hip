@@ -127,6 +127,8 @@ struct clair_ctx {
   int cus = 256;
   // tuning
   int group = 8;  // lanes per row of the small solver: 1, 4 or 8 (|N| <= 8), 16/32 (|N| <= group)
+  int binB_max = 32;  // largest block of the last batch whose sizes were read back (9..32)
+  int last_maxb = 0;  // the same, unclamped (0: none read back yet)
   int wg_threads = 256;
   int chunk = 1024;
   // memory
@@ -367,13 +369,17 @@ int enqueue_numeric(clair_ctx* c, Batch& b, hipStream_t s, bool timing, const Co
     } else if (c->group == 4) {
       HIPCHK(launch_quad8(b.w, c->wg_threads, c->cus, s));
     } else {
-      HIPCHK(launch_numeric(b.w, 0, c->group, c->wg_threads, c->cus, s));
+      HIPCHK(launch_numeric(b.w, 0, c->group, c->group, c->wg_threads, c->cus, s));
     }
     if (capture_check(c->capturing, s, "k_numeric", __LINE__)) return CLAIR_ERR_HIP;
   }
   timing_mark(c, timing, s, "numeric");
   if (c->group < 32 && (!known || known->nB > 0)) {
-    HIPCHK(launch_numeric(b.w, 1, 32, 128, c->cus, s));
+    // bin B: the smallest block bound that holds the largest block seen (rows
+    // beyond it go to the workgroup solver, so any bound is correct)
+    const int bg = c->binB_max <= 16 ? 16 : 32;
+    const int bsm = c->binB_max <= 16 ? 16 : (c->binB_max <= 24 ? 24 : 32);
+    HIPCHK(launch_numeric(b.w, 1, bg, bsm, 128, c->cus, s));
     if (capture_check(c->capturing, s, "k_numeric32", __LINE__)) return CLAIR_ERR_HIP;
     timing_mark(c, timing, s, "numeric32");
   }
@@ -381,7 +387,8 @@ int enqueue_numeric(clair_ctx* c, Batch& b, hipStream_t s, bool timing, const Co
   if (capture_check(c->capturing, s, "k_rows_wg", __LINE__)) return CLAIR_ERR_HIP;
   timing_mark(c, timing, s, "rows_wg");
   if (b.any_B) {
-    HIPCHK(launch_project(b.w, occupancy_blocks(c, 4), s));
+    // rows of up to 8 points: one thread per row; longer rows: eight lanes each
+    HIPCHK(launch_project(b.w, occupancy_blocks(c, 4), c->last_maxb > 8 ? 8 : 1, s));
     if (capture_check(c->capturing, s, "k_project", __LINE__)) return CLAIR_ERR_HIP;
     timing_mark(c, timing, s, "project");
   }
@@ -399,7 +406,7 @@ int enqueue_symbolic(clair_ctx* c, Batch& b, hipStream_t s, bool validate, bool 
   HIPCHK(launch_count(b.w, s));
   if (capture_check(c->capturing, s, "k_count", __LINE__)) return CLAIR_ERR_HIP;
   timing_mark(c, timing, s, "count");
-  HIPCHK(launch_count_big(b.w, std::max(8, c->cus / 4), s));
+  HIPCHK(launch_count_big(b.w, std::max(8, c->cus * 2), s));
   if (capture_check(c->capturing, s, "k_count_big", __LINE__)) return CLAIR_ERR_HIP;
   timing_mark(c, timing, s, "count_big");
   HIPCHK(launch_scan(b.w, s));
@@ -469,6 +476,8 @@ int run_mixed(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* co
       fill_results(hs, nmat, R, info, A);
       return first_error(hs, nmat);
     }
+    c->binB_max = std::max(9, std::min(32, maxb));
+    c->last_maxb = maxb;
     if (maxb > kLdsBlockMax) {
       rc = ensure_scratch(c, std::min(64, c->cus / 4 > 0 ? c->cus / 4 : 1));
       if (rc) return rc;
@@ -742,12 +751,15 @@ int clair_size_R(clair_ctx_t* c, int32_t nmat, const clair_csr_t* A, const int8_
   rc = read_status(c, b, s);
   if (rc) return rc;
   const MatStatus* hs = host_status(c, b);
-  int first = 0;
+  int first = 0, maxb = 0;
   for (int m = 0; m < nmat; ++m) {
     n_c[m] = hs[m].n_c;
     nnz[m] = hs[m].nnz;
+    maxb = std::max(maxb, hs[m].max_block);
     if (hs[m].status != 0 && hs[m].status != CLAIR_ERR_CAPACITY && !first) first = hs[m].status;
   }
+  c->binB_max = std::max(9, std::min(32, maxb));
+  c->last_maxb = maxb;
   return first;
 }
 

@@ -100,29 +100,13 @@ struct Work {
 // status codes (mirror clair_status)
 enum : int32_t { ST_OK = 0, ST_INVALID = 1, ST_CAPACITY = 2, ST_SINGULAR = 3, ST_HIP = 4, ST_UNSUPPORTED = 5 };
 
-// ---------------------------------------------------------------------------
-// Team primitives.  A team is either a group of G lanes inside one wavefront
-// (communication through LDS with a wavefront fence) or a whole workgroup.
-// ---------------------------------------------------------------------------
-
+// wavefront-local fence and barrier: lanes of one wavefront exchange data
+// through LDS
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-
-template <int G>
-struct GroupTeam {
-  static constexpr int size = G;
-  int lane;
-  __device__ __forceinline__ void sync() const { wave_sync(); }
-};
-
-struct BlockTeam {
-  int size;
-  int lane;
-  __device__ __forceinline__ void sync() const { __syncthreads(); }
-};
 
 // index of the first element >= key in sorted a[0..len)
 __device__ __forceinline__ int lower_bound_i32(const int* a, int len, int key) {
@@ -139,116 +123,11 @@ __device__ __forceinline__ int find_sorted(const int* a, int len, int key) {
   return (p < len && a[p] == key) ? p : -1;
 }
 
-// LDS buffers of one neighbourhood search.
-struct BfsBuf {
-  int* nb0;   // sorted neighbourhood, double buffered with nb1 [ncap]
-  int* nb1;
-  int* fr;    // newest level, sorted [ncap]
-  int* cand;  // candidates of the current level [ccap]
-  int* keep;  // flags [ccap]
-  int* cnt;   // two scalars: candidate count, kept count
-  int ncap;
-  int ccap;
-};
-
-// Distance-ell F-neighbourhood of C-point i: F-points reachable by at most ell
-// edges (u -> v with u != v and a stored nonzero a_uv) whose interior vertices
-// are F-points.  Level-synchronous: each level collects the F-neighbours of the
-// newest level, removes duplicates and already-found points, and merges the
-// sorted result into the neighbourhood.  Returns |N(i)| with the sorted list in
-// *out, or -1 when a buffer capacity is exceeded (team-uniform).  Column
-// indices outside [0, n) are skipped.
-template <class Team>
-__device__ int team_bfs(const Team& tm, int n, int i, int ell, const int32_t* __restrict__ rp,
-                        const int32_t* __restrict__ ci, const double* __restrict__ va,
-                        const int8_t* __restrict__ cf, const BfsBuf& b, int** out) {
-  int* cur = b.nb0;
-  int* nxt = b.nb1;
-  int s = 0;
-  int fsz = 1;  // level-0 frontier is {i}
-  for (int depth = 1; depth <= ell && fsz > 0; ++depth) {
-    if (tm.lane == 0) { b.cnt[0] = 0; b.cnt[1] = 0; }
-    tm.sync();
-    if (depth == 1) {
-      // the row of i: one entry per lane
-      const int e1 = rp[i + 1];
-      for (int e = rp[i] + tm.lane; e < e1; e += tm.size) {
-        const int k = ci[e];
-        if (k == i || (unsigned)k >= (unsigned)n || va[e] == 0.0 || cf[k] != 0) continue;
-        const int pos = atomicAdd(&b.cnt[0], 1);
-        if (pos < b.ccap) b.cand[pos] = k;
-      }
-    } else {
-      // one frontier vertex per lane; its entries in batches of four independent loads
-      for (int t = tm.lane; t < fsz; t += tm.size) {
-        const int u = b.fr[t];
-        const int e1 = rp[u + 1];
-        for (int e = rp[u]; e < e1; e += 4) {
-          int k[4];
-          double v[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            k[j] = u;
-            v[j] = 0.0;
-            if (e + j < e1) { k[j] = ci[e + j]; v[j] = va[e + j]; }
-          }
-          int8_t c8[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) c8[j] = ((unsigned)k[j] < (unsigned)n) ? cf[k[j]] : (int8_t)1;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            if (k[j] != u && v[j] != 0.0 && c8[j] == 0) {
-              const int pos = atomicAdd(&b.cnt[0], 1);
-              if (pos < b.ccap) b.cand[pos] = k[j];
-            }
-          }
-        }
-      }
-    }
-    tm.sync();
-    const int m = b.cnt[0];
-    if (m > b.ccap) return -1;
-    int kept = 0;
-    for (int t = tm.lane; t < m; t += tm.size) {
-      const int x = b.cand[t];
-      bool k = find_sorted(cur, s, x) < 0;
-      for (int u = 0; u < t && k; ++u) k = (b.cand[u] != x);
-      b.keep[t] = k ? 1 : 0;
-      kept += k ? 1 : 0;
-    }
-    if (kept) atomicAdd(&b.cnt[1], kept);
-    tm.sync();
-    const int nnew = b.cnt[1];
-    if (s + nnew > b.ncap) return -1;
-    for (int t = tm.lane; t < m; t += tm.size) {
-      if (b.keep[t]) {
-        const int x = b.cand[t];
-        int rank = 0;
-        for (int u = 0; u < m; ++u) rank += (b.keep[u] && b.cand[u] < x) ? 1 : 0;
-        b.fr[rank] = x;
-      }
-    }
-    tm.sync();
-    for (int t = tm.lane; t < s; t += tm.size) {
-      const int y = cur[t];
-      nxt[t + lower_bound_i32(b.fr, nnew, y)] = y;
-    }
-    for (int t = tm.lane; t < nnew; t += tm.size) {
-      const int x = b.fr[t];
-      nxt[t + lower_bound_i32(cur, s, x)] = x;
-    }
-    tm.sync();
-    int* tmp = cur; cur = nxt; nxt = tmp;
-    s += nnew;
-    fsz = nnew;
-  }
-  *out = cur;
-  return s;
-}
-
 // Register-resident neighbourhood search of one thread, for neighbourhoods of
-// at most SM points: the same set as team_bfs, kept sorted in N[0..s) (empty
-// slots hold INT32_MAX).  Returns s, or -1 when more than SM points are found.
+// at most SM points.  N(i) = the F-points reachable from C-point i by a walk
+// of at most ell edges (u -> v with u != v and a stored nonzero a_uv) whose
+// interior vertices are F-points; kept sorted in v[0..s) (empty slots hold
+// INT32_MAX).  Returns s, or -1 when more than SM points are found.
 template <int SM>
 struct RegSet {
   int v[SM];    // sorted points
@@ -335,6 +214,97 @@ __device__ __forceinline__ int reg_bfs(RegSet<SM>& S, int n, int i, int ell, con
       any = true;
     }
     if (!any) break;
+  }
+  return S.ovf ? -1 : S.s;
+}
+
+// The same search for neighbourhoods of up to SM <= 32 points with less
+// register state: instead of a level per slot, bit masks over the slots mark
+// the points found at the current level and the previous level's points not
+// yet expanded; every sorted insert moves the mask bits with the entries.
+template <int SM>
+struct RegSetM {
+  int v[SM];      // sorted points, INT32_MAX beyond s
+  uint64_t cur;   // slots found at the current level
+  uint64_t todo;  // slots of the previous level still to expand
+  int s;
+  bool ovf;
+
+  __device__ __forceinline__ void clear() {
+#pragma unroll
+    for (int j = 0; j < SM; ++j) v[j] = 0x7fffffff;
+    cur = 0;
+    todo = 0;
+    s = 0;
+    ovf = false;
+  }
+  __device__ __forceinline__ void insert(int k) {
+    bool present = false;
+    int pos = 0;
+#pragma unroll
+    for (int j = 0; j < SM; ++j) {
+      present |= (v[j] == k);
+      pos += (v[j] < k) ? 1 : 0;
+    }
+    if (present) return;
+    if (s == SM) { ovf = true; return; }
+#pragma unroll
+    for (int j = SM - 1; j > 0; --j)
+      if (j > pos) v[j] = v[j - 1];
+#pragma unroll
+    for (int j = 0; j < SM; ++j)
+      if (j == pos) v[j] = k;
+    const uint64_t low = (1ull << pos) - 1;
+    todo = (todo & low) | ((todo & ~low) << 1);
+    cur = (cur & low) | ((cur & ~low) << 1) | (1ull << pos);
+    ++s;
+  }
+};
+
+// F-neighbours of u (stored nonzero, u excluded), eight entries per batch
+template <int SM>
+__device__ __forceinline__ void regm_expand(RegSetM<SM>& S, int n, int u, const int32_t* __restrict__ rp,
+                                            const int32_t* __restrict__ ci, const double* __restrict__ va,
+                                            const int8_t* __restrict__ cf) {
+  const int e1 = rp[u + 1];
+  for (int e = rp[u]; e < e1 && !S.ovf; e += 8) {
+    int k[8];
+    double x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      k[j] = u;
+      x[j] = 0.0;
+      if (e + j < e1) { k[j] = ci[e + j]; x[j] = va[e + j]; }
+    }
+    int8_t c8[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) c8[j] = ((unsigned)k[j] < (unsigned)n) ? cf[k[j]] : (int8_t)1;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (k[j] != u && x[j] != 0.0 && c8[j] == 0) S.insert(k[j]);
+  }
+}
+
+template <int SM>
+__device__ __forceinline__ int regm_bfs(RegSetM<SM>& S, int n, int i, int ell, const int32_t* __restrict__ rp,
+                                        const int32_t* __restrict__ ci, const double* __restrict__ va,
+                                        const int8_t* __restrict__ cf) {
+  S.clear();
+  regm_expand(S, n, i, rp, ci, va, cf);
+  for (int L = 2; L <= ell && !S.ovf; ++L) {
+    S.todo = S.cur;
+    S.cur = 0;
+    if (!S.todo) break;
+    while (S.todo && !S.ovf) {
+      // the lowest slot still to expand (the smallest such point)
+      const int j0 = __builtin_ctzll(S.todo);
+      S.todo &= S.todo - 1;
+      int u = 0;
+#pragma unroll
+      for (int j = 0; j < SM; ++j)
+        if (j == j0) u = S.v[j];
+      regm_expand(S, n, u, rp, ci, va, cf);
+    }
   }
   return S.ovf ? -1 : S.s;
 }

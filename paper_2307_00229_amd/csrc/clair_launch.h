@@ -16,12 +16,12 @@ hipError_t launch_count(const Work& w, hipStream_t s);
 hipError_t launch_count_big(const Work& w, int blocks, hipStream_t s);
 hipError_t launch_scan(const Work& w, hipStream_t s);
 // which = 0: bin A with group = GA; which = 1: bin B with group = 32
-hipError_t launch_numeric(const Work& w, int which, int group, int wg_threads, int cus, hipStream_t s);
+hipError_t launch_numeric(const Work& w, int which, int group, int sm, int wg_threads, int cus, hipStream_t s);
 // one thread per row with |N| <= 8 (GA == 1); four lanes per row (GA == 4)
 hipError_t launch_quad8(const Work& w, int wg_threads, int cus, hipStream_t s);
 hipError_t launch_rows8(const Work& w, int wg_threads, int cus, hipStream_t s);
 hipError_t launch_rows_wg(const Work& w, int blocks, hipStream_t s);
-hipError_t launch_project(const Work& w, int blocks, hipStream_t s);
+hipError_t launch_project(const Work& w, int blocks, int lanes_per_row, hipStream_t s);
 
 // plain FP64 per-row form: one matrix, one thread per row, one kernel per stage
 struct PlainWork {

@@ -2,24 +2,29 @@
 //
 // Stages (one launch each, over all matrices of a batch):
 //   k_count      symbolic pass per chunk of fine points: the C-points of the
-//                chunk, the neighbourhood N(i) of each (lane-group search) kept
-//                in a per-row slot when |N| <= 32 (else the row is queued for
-//                the workgroup solver), the chunk-local prefix of |N(i)|+1;
-//                clears the projection accumulators of the chunk.
-//   k_count_big  the rare chunks with rows the lane-group search could not size:
-//                one workgroup per chunk finishes them.
+//                chunk, the neighbourhood N(i) of each (one thread per row,
+//                up to 8 points in registers) kept in a per-row slot, the
+//                chunk-local prefix of |N(i)|+1; clears the projection
+//                accumulators of the chunk.  Larger rows are left unsized.
+//   k_count_big  the chunks with unsized rows: one thread per row with up to
+//                32 points in registers (slot of bin A or B), larger rows by
+//                a workgroup-wide search (queued for the workgroup solver).
 //   k_scan       one workgroup: chunk bases -> global row numbers, R offsets,
-//                n_c and nnz(R) per matrix, capacity check, R.row_ptr[n_c].
+//                n_c and nnz(R) per matrix, bin sizes, capacity check,
+//                R.row_ptr[n_c].
 //   k_numeric    persistent over the rows in grid order (each XCD a contiguous
-//                slice), G lanes per row with |N| <= G (G = GA), or with
-//                GA < |N| <= 32 (G = 32): gather of the local block into LDS,
-//                FP32 LU and FP64 iterative refinement of
+//                slice), G lanes per row with |N| <= G (bin A, G = GA), or with
+//                GA < |N| <= 32 (bin B, G = 16 or 32): gather of the local
+//                block into LDS, FP32 LU and FP64 iterative refinement of
 //                (A[N,N])^T z = -A[i,N]^T, R row write, projection sums.  Rows
 //                whose FP32 factorisation is not trusted are queued for k_rows_wg.
+//                k_quad8 (4 lanes per row) and k_rows8 (one thread per row)
+//                are the other bin-A solvers.
 //   k_rows_wg    persistent, one workgroup per queued row: FP64 LU with partial
 //                pivoting (block in LDS, or in global scratch when large).
-//   k_project    persistent: z_ij -= B_i (sum_k z_kj B_k - B_j) / sum_k B_k^2 per
-//                F-entry; counts F-points no row reaches.
+//   k_project    persistent, one thread per row:
+//                z_ij -= B_i (sum_k z_kj B_k - B_j) / sum_k B_k^2 per F-entry;
+//                counts F-points no row reaches.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -33,12 +38,6 @@ namespace clair {
 namespace {
 
 constexpr int kNT = 256;  // threads per workgroup of the symbolic pass
-// lane-group search of the symbolic pass: 8 lanes per row, neighbourhoods up
-// to 32 points and 128 candidates per level; larger rows go to k_count_big
-constexpr int kCountG = 8;
-constexpr int kCountGN = 32;
-constexpr int kCountGC = 64;
-constexpr int kCountNG2 = 16;  // lane groups of the second phase (two wavefronts)
 // workgroup-wide search caps
 constexpr int kWN = kMaxBlock;
 constexpr int kWC = 4096;
@@ -69,7 +68,7 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int* total) 
 }
 
 // Workgroup-wide neighbourhood search for rows of any size up to kWN points:
-// the same set as team_bfs (F-points reachable from C-point i by at most ell
+// the same set as reg_bfs (F-points reachable from C-point i by at most ell
 // edges with F-points inside the walk).  The entries of a level's frontier
 // rows are taken in windows of kWC: each window is sorted (bitonic, in LDS),
 // reduced to points that are new (first of their run, not yet in N, not yet
@@ -328,11 +327,6 @@ __global__ void k_validate(Work w) {
 // ---------------------------------------------------------------------------
 // symbolic pass
 // ---------------------------------------------------------------------------
-struct CountGroupBuf {
-  int nb0[kCountGN], nb1[kCountGN], fr[kCountGN];
-  int cand[kCountGC], keep[kCountGC];
-  int cnt[2];
-};
 
 // rows the small solvers take: |N| <= 8 for the thread-per-row solver
 // (GA == 1), |N| <= GA for the lane-group solver
@@ -341,13 +335,12 @@ __device__ __forceinline__ int small_limit(int GA) { return GA <= 4 ? 8 : GA; }
 __device__ __forceinline__ int slot_stride(int GA) { return GA <= 4 ? 8 : GA; }
 
 __global__ __launch_bounds__(kNT) void k_count(Work w) {
-  constexpr int NG = kCountNG2;
   __shared__ int s_rows[kMaxChunk];
   __shared__ int16_t s_size[kMaxChunk];
   __shared__ int s_scan[kNT];
-  __shared__ CountGroupBuf gbuf[NG];
-  __shared__ int16_t s_list[kMaxChunk];  // rows left for the lane-group search
-  __shared__ int s_flag[5];  // max |N|, unresolved rows, rows in bin A, rows in bin B, list length
+  __shared__ int s_flag[4];  // max |N|, unresolved rows, rows in bin A, rows in bin B
+  __shared__ int16_t s_list[kMaxChunk];  // rows with more than 8 points
+  __shared__ int s_nlist;
 
   const int c = xcd_logical_block();
   const int tid = threadIdx.x;
@@ -378,15 +371,14 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
   for (int j = j0; j < min(j0 + per, f1); ++j) {
     if (d.cf[j] != 0) { s_rows[rank] = j; w.clocal[base + rank] = j; ++rank; }
   }
-  if (tid == 0) { s_flag[0] = 0; s_flag[1] = 0; s_flag[2] = 0; s_flag[3] = 0; s_flag[4] = 0; }
+  if (tid == 0) { s_flag[0] = 0; s_flag[1] = 0; s_flag[2] = 0; s_flag[3] = 0; s_nlist = 0; }
   __syncthreads();
 
-  const int GA = w.GA;
-  const int lim = small_limit(GA);
-  const int SA = slot_stride(GA);
+  const int SA = slot_stride(w.GA);
   int inA = 0, inB = 0, unresolved = 0;
 
-  // phase 1: one thread per C-row, neighbourhoods of up to 8 points in registers
+  // one thread per C-row, neighbourhoods of up to 8 points in registers; the
+  // larger ones are left unsized for k_count_big
   for (int t = tid; t < nc; t += kNT) {
     RegSet<8> S;
     const int sz = reg_bfs(S, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf);
@@ -400,53 +392,37 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
       }
     } else {
       s_size[t] = -1;
-      s_list[atomicAdd(&s_flag[4], 1)] = t;
+      s_list[atomicAdd(&s_nlist, 1)] = t;
     }
   }
   __syncthreads();
-
-  // phase 2: kCountG lanes per remaining row, up to 32 points in LDS
-  const int nl2 = s_flag[4];
-  const int grp = tid / kCountG;
-  const int gl = tid % kCountG;
-  GroupTeam<kCountG> tm{gl};
-  CountGroupBuf& gb = gbuf[grp < NG ? grp : 0];
-  const BfsBuf bb{gb.nb0, gb.nb1, gb.fr, gb.cand, gb.keep, gb.cnt, kCountGN, kCountGC};
-  // the first NG groups (whole wavefronts) take these rows; the loop trip
-  // count is uniform so all groups of a wavefront meet at the append
-  for (int k0 = 0; k0 < nl2 && tid < NG * kCountG; k0 += NG) {
-    const int k = k0 + grp;
-    const bool active = k < nl2;
-    int sz = 0;
-    int* nl = gb.nb0;
-    int t = 0;
-    if (active) {
-      t = s_list[k];
-      sz = team_bfs(tm, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf, bb, &nl);
-      if (sz >= 0 && sz <= lim) {
-        if (SA)
-          for (int p = gl; p < sz; p += kCountG) w.slotA[(base + t) * SA + p] = nl[p];
-        inA += (gl == 0);
-      } else if (sz > lim && sz <= 32) {
-        for (int p = gl; p < sz; p += kCountG) w.slotB[(base + t) * 32 + p] = nl[p];
-        inB += (gl == 0);
-      }
-    }
-    const bool lead = active && gl == 0;
-    // more than 32 points: the workgroup solver (unsized rows are sized by
-    // k_count_big first)
-    const int qc = wave_append(lead && sz > 32, &w.cnt->nC, w.capC);
-    if (qc >= 0) w.binC[qc] = c * w.chunk + t;
-    if (lead) {
+  // rows with more than 8 points: one thread per row, up to 32 points in
+  // registers (slot of bin A or B); larger rows are left unsized for k_count_big
+  {
+    const int lim = small_limit(w.GA);
+    const int nl2 = s_nlist;
+    for (int k = tid; k < nl2; k += kNT) {
+      const int t = s_list[k];
+      RegSetM<32> S;
+      const int sz = regm_bfs(S, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf);
       if (sz < 0) {
-        ++unresolved;
         s_size[t] = 0;
-        w.clocal[base + t] = -(s_rows[t] + 1);  // k_count_big sizes it
+        w.clocal[base + t] = -(s_rows[t] + 1);
+        ++unresolved;
+      } else if (sz <= lim) {
+        s_size[t] = sz;
+        ++inA;
+#pragma unroll
+        for (int p = 0; p < 32; ++p)
+          if (p < sz) w.slotA[(base + t) * SA + p] = S.v[p];
       } else {
         s_size[t] = sz;
+        ++inB;
+#pragma unroll
+        for (int p = 0; p < 32; ++p)
+          if (p < sz) w.slotB[(base + t) * 32 + p] = S.v[p];
       }
     }
-    wave_sync();
   }
   if (inA) atomicAdd(&s_flag[2], inA);
   if (inB) atomicAdd(&s_flag[3], inB);
@@ -483,8 +459,9 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
 __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
   __shared__ WideBuf bb;
   __shared__ int s_size[kMaxChunk];
+  __shared__ int s_lrows[kMaxChunk];
   __shared__ int s_scan[kNT];
-  __shared__ int s_max;
+  __shared__ int s_max, s_left;
   const int tid = threadIdx.x;
   const int nov = w.cnt->novf;
   for (int k = blockIdx.x; k < nov; k += gridDim.x) {
@@ -501,22 +478,22 @@ __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
     }
     if (tid == 0) s_max = 0;
     __syncthreads();
-    for (int t = 0; t < nc; ++t) {
-      const int ci = w.clocal[base + t];
-      if (ci >= 0) continue;  // uniform
-      const int i = -ci - 1;
+    // rows the register searches could not size (more than 32 points)
+    if (tid == 0) {
+      int k = 0;
+      for (int t = 0; t < nc; ++t)
+        if (w.clocal[base + t] < 0) s_lrows[k++] = t;
+      s_left = k;
+    }
+    __syncthreads();
+    const int nleft = s_left;
+    for (int k = 0; k < nleft; ++k) {
+      const int t = s_lrows[k];
+      const int i = -w.clocal[base + t] - 1;
       int* nl;
       const int s = block_bfs(d.n, i, d.ell, d.rp, d.ci, d.va, d.cf, bb, &nl);
       __syncthreads();
-      // small enough for a lane-group solver: its slot; else the workgroup solver
-      const int lim = small_limit(w.GA);
-      if (s >= 0 && s <= lim) {
-        const int SA = slot_stride(w.GA);
-        if (SA)
-          for (int p = tid; p < s; p += kNT) w.slotA[(base + t) * SA + p] = nl[p];
-      } else if (s > lim && s <= 32) {
-        for (int p = tid; p < s; p += kNT) w.slotB[(base + t) * 32 + p] = nl[p];
-      }
+      // more than 32 points (the register search said so): the workgroup solver
       if (tid == 0) {
         w.clocal[base + t] = i;
         if (s < 0) {
@@ -525,19 +502,14 @@ __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
         } else {
           s_size[t] = s;
           s_max = max(s_max, s);
-          if (s <= lim) {
-            w.chunk_bins[c].x += 1;
-          } else if (s <= 32) {
-            w.chunk_bins[c].y += 1;
-          } else {
-            const int q = atomicAdd(&w.cnt->nC, 1);
-            if (q < w.capC) w.binC[q] = c * w.chunk + t;
-            else flag_row(st, ST_UNSUPPORTED, i);
-          }
+          const int q = atomicAdd(&w.cnt->nC, 1);
+          if (q < w.capC) w.binC[q] = c * w.chunk + t;
+          else flag_row(st, ST_UNSUPPORTED, i);
         }
       }
       __syncthreads();
     }
+
     // redo the chunk-local prefix
     const int per2 = (nc + kNT - 1) / kNT;
     const int t0 = tid * per2;
@@ -549,7 +521,8 @@ __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
     __syncthreads();
     if (tid == 0) {
       w.chunk_nnz[c] = tot;
-      atomicMax(&st->max_block, s_max);
+      if (s_max > __hip_atomic_load(&st->max_block, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(&st->max_block, s_max);
     }
     __syncthreads();
   }
@@ -648,13 +621,14 @@ __global__ __launch_bounds__(1024) void k_scan(Work w) {
 // ---------------------------------------------------------------------------
 // numeric pass: G lanes per queued row
 // ---------------------------------------------------------------------------
-template <int G>
+// LDS of one lane group: blocks of up to SM points (SM <= G)
+template <int G, int SM>
 struct NumGroupBuf {
-  double K[G * (G + 1)];  // FP64 block, row q = row q of (A[N,N])^T, stride G+1
-  double f[G];            // -A[i,N]
-  double z[G];            // refinement broadcast
-  float U[G * G];         // pivot rows
-  int nb[G];              // sorted N(i)
+  double K[SM * (SM + 1)];  // FP64 block, row q = row q of (A[N,N])^T, stride SM+1
+  double f[SM];             // -A[i,N]
+  double z[SM];             // refinement broadcast
+  float U[SM * SM];         // pivot rows
+  int nb[G];                // sorted N(i), INT32_MAX beyond |N|
 };
 
 // Communication inside a group of G lanes (G = 8, 16 or 32; groups are
@@ -727,16 +701,17 @@ __device__ __forceinline__ int group_ori(int v) {
 }
 
 // forward then backward substitution with the packed LU of this lane's row:
-// kf[k] (k < lane) = L[lane][k], kf[k] (k >= lane) = U[lane][k].
-template <int G>
-__device__ __forceinline__ float lu_solve(const float (&kf)[G], float uinv, int lane, float y) {
+// kf[k] (k < lane) = L[lane][k], kf[k] (k >= lane) = U[lane][k].  Lanes at
+// or beyond SM hold no row (kf = 0) and keep y = 0.
+template <int G, int SM>
+__device__ __forceinline__ float lu_solve(const float (&kf)[SM], float uinv, int lane, float y) {
 #pragma unroll
-  for (int k = 0; k < G; ++k) {
+  for (int k = 0; k < SM; ++k) {
     const float yk = gbf<G>(y, k);
     if (lane > k) y = fmaf(-kf[k], yk, y);
   }
 #pragma unroll
-  for (int k = G - 1; k >= 0; --k) {
+  for (int k = SM - 1; k >= 0; --k) {
     if (lane == k) y *= uinv;
     const float zk = gbf<G>(y, k);
     if (lane < k) y = fmaf(-kf[k], zk, y);
@@ -757,19 +732,24 @@ __device__ __forceinline__ int find_pos(const int* nb, int key) {
 
 constexpr int kRefineMax = 5;
 
-template <int G, int NT>
+// G lanes per row, blocks of up to SM <= G points.  which = 0: bin A
+// (|N| <= G = GA); which = 1: bin B (GA < |N| <= 32), rows with |N| > SM are
+// handed to the workgroup solver.
+template <int G, int NT, int SM>
 __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
+  static_assert(SM <= G, "block bound");
   constexpr int NG = NT / G;
-  constexpr int LD = G + 1;
-  __shared__ NumGroupBuf<G> sb[NG];
+  constexpr int LD = SM + 1;
+  __shared__ NumGroupBuf<G, SM> sb[NG];
   __shared__ int s_itmax;
 
   const int tid = threadIdx.x;
   const int grp = tid / G;
   const int lane = tid % G;
-  NumGroupBuf<G>& gb = sb[grp];
+  const bool rowl = lane < SM;  // this lane can hold a row of the block
+  NumGroupBuf<G, SM>& gb = sb[grp];
 
-  // rows of this solver: |N| <= G (small solver) or GA < |N| <= 32 (which = 1)
+  // rows of this solver
   if ((which ? w.cnt->nB : w.cnt->nA) == 0) return;
   const int smin = which ? small_limit(w.GA) + 1 : 0;
   const int32_t* slots = which ? w.slotB : w.slotA;
@@ -804,7 +784,7 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
       cc.row(w, g, &t, &i, &off, &s);
       myN0 = slots[(cc.fbase + t) * sstride + min(lane, sstride - 1)];
       ae0 = 0; ae1 = 0; fe0 = 0; fe1 = 0;
-      if (s >= smin && s <= G && cc.live) {
+      if (s >= smin && s <= SM && cc.live) {
         if (lane < s) { ae0 = cc.md.rp[myN0]; ae1 = cc.md.rp[myN0 + 1]; }
         fe0 = cc.md.rp[i];
         fe1 = cc.md.rp[i + 1];
@@ -818,9 +798,15 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
       cc.row(w, gn, &nx_t, &nx_i, &nx_off, &nx_s);
       nx_N = slots[(cc.fbase + nx_t) * sstride + min(lane, sstride - 1)];
     }
-    const bool mine = s >= smin && s <= G && cc.live;  // group-uniform
-    const bool nx_mine = ahead && nx_s >= smin && nx_s <= G && cc.live;
+    const bool mine = s >= smin && s <= SM && cc.live;  // group-uniform
+    const bool nx_mine = ahead && nx_s >= smin && nx_s <= SM && cc.live;
     if (!mine) {
+      if (which && s > SM && s <= 32 && cc.live && lane == 0) {
+        // a bin-B row larger than this kernel's blocks: the workgroup solver
+        const int qc = atomicAdd(&w.cnt->nC, 1);
+        if (qc < w.capC) w.binC[qc] = cc.c * w.chunk + t;
+        else flag_row(&w.st[cc.m], ST_UNSUPPORTED, i);
+      }
       if (nx_mine) {
         nx_e0 = 0; nx_e1 = 0;
         if (lane < nx_s) { nx_e0 = cc.md.rp[nx_N]; nx_e1 = cc.md.rp[nx_N + 1]; }
@@ -847,9 +833,11 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
     const int dpos = __popcll((below >> ((threadIdx.x & 63) - lane)) & ((G >= 64) ? ~0ull : ((1ull << G) - 1)));
 
     // ---- gather: K = (A[N,N])^T (padded with identity), f = -A[i,N] ----
+    if (rowl) {
 #pragma unroll
-    for (int tt = 0; tt < G; ++tt) gb.K[tt * LD + lane] = (tt == lane && tt >= s) ? 1.0 : 0.0;
-    gb.f[lane] = 0.0;
+      for (int tt = 0; tt < SM; ++tt) gb.K[tt * LD + lane] = (tt == lane && tt >= s) ? 1.0 : 0.0;
+      gb.f[lane] = 0.0;
+    }
     wave_sync();
     for (int e = ae0; e < ae1; e += 4) {
       int k[4];
@@ -882,8 +870,8 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
     float amax = 0.f;
     double knorm = 0.0;
 #pragma unroll
-    for (int p = 0; p < G; ++p) {
-      const double v = gb.K[lane * LD + p];
+    for (int p = 0; p < SM; ++p) {
+      const double v = rowl ? gb.K[lane * LD + p] : 0.0;
       amax = fmaxf(amax, (float)fabs(v));
       knorm += fabs(v);
     }
@@ -892,51 +880,53 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
     int ex = 0;
     frexpf(amax, &ex);
     const double scale = ldexp(1.0, -ex);
-    float kf[G];
+    float kf[SM];
 #pragma unroll
-    for (int p = 0; p < G; ++p) kf[p] = (float)(gb.K[lane * LD + p] * scale);
+    for (int p = 0; p < SM; ++p) kf[p] = rowl ? (float)(gb.K[lane * LD + p] * scale) : 0.f;
     float uinv = 1.f;
     int bad = !(amax > 0.f) || !(amax < 3.0e38f);
 #pragma unroll
-    for (int k = 0; k < G; ++k) {
+    for (int k = 0; k < SM; ++k) {
       if (lane == k) {
 #pragma unroll
-        for (int p = k; p < G; ++p) gb.U[k * G + p] = kf[p];
+        for (int p = k; p < SM; ++p) gb.U[k * SM + p] = kf[p];
       }
       wave_sync();
-      const float piv = gb.U[k * G + k];
+      const float piv = gb.U[k * SM + k];
       // FP32 factors only precondition the FP64 refinement: the hardware
       // reciprocal (1 ulp) is accurate enough
       const float pinv = __builtin_amdgcn_rcpf(piv);
       if (lane == k) uinv = pinv;
       bad |= !(fabsf(piv) >= 0x1p-24f);
-      if (lane > k) {
+      if (lane > k && rowl) {
         const float l = kf[k] * pinv;
         kf[k] = l;
 #pragma unroll
-        for (int p = k + 1; p < G; ++p) kf[p] = fmaf(-l, gb.U[k * G + p], kf[p]);
+        for (int p = k + 1; p < SM; ++p) kf[p] = fmaf(-l, gb.U[k * SM + p], kf[p]);
       }
     }
     bad = group_ori<G>(bad);
 
     // ---- solve and refine in FP64 ----
-    const double fq = gb.f[lane];
+    const double fq = rowl ? gb.f[lane] : 0.0;
     const double fnorm = group_maxd<G>(fabs(fq));
     double z = 0.0;
     int it = 0;
     bool conv = false;
     if (!bad) {
-      z = (double)lu_solve<G>(kf, uinv, lane, (float)(fq * scale));
+      z = (double)lu_solve<G, SM>(kf, uinv, lane, (float)(fq * scale));
       for (it = 1; it <= kRefineMax; ++it) {
-        gb.z[lane] = z;
+        if (rowl) gb.z[lane] = z;
         wave_sync();
         double r = fq;
+        if (rowl) {
 #pragma unroll
-        for (int p = 0; p < G; ++p) r = fma(-gb.K[lane * LD + p], gb.z[p], r);
+          for (int p = 0; p < SM; ++p) r = fma(-gb.K[lane * LD + p], gb.z[p], r);
+        }
         const double rn = group_maxd<G>(fabs(r));
         const double zn = group_maxd<G>(fabs(z));
         if (rn <= 0x1p-47 * (knorm * zn + fnorm)) { conv = true; break; }
-        const float dz = lu_solve<G>(kf, uinv, lane, (float)(r * scale));
+        const float dz = lu_solve<G, SM>(kf, uinv, lane, (float)(r * scale));
         z += (double)dz;
         wave_sync();
       }
@@ -1710,12 +1700,17 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
 // ---------------------------------------------------------------------------
 // projection
 // ---------------------------------------------------------------------------
+// LPR = 1: one thread per row (short rows: a wavefront covers 64
+// consecutive rows, a contiguous run of R).  LPR = 8: eight lanes per row,
+// entry by entry (long rows).
+template <int LPR>
 __global__ __launch_bounds__(256) void k_project(Work w) {
+  const int tid = threadIdx.x;
+  if constexpr (LPR == 1) {
   // one thread per row: a wavefront covers 64 consecutive rows, i.e. a
   // contiguous run of R; a row's entries are read eight at a time and all
   // their column sums are gathered before any is used.  The chunk data is
   // looked up once per wavefront and chunk (wavefront-uniform values).
-  const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int total = w.cnt->total_rows;
   const int lb = xcd_logical_block();
@@ -1760,6 +1755,33 @@ __global__ __launch_bounds__(256) void k_project(Work w) {
       gc = cend;
     }
   }
+  } else {
+    const int lane = tid % LPR;
+    const int grp = tid / LPR;
+    constexpr int NG = 256 / LPR;
+    const int total = w.cnt->total_rows;
+    const int lb = xcd_logical_block();
+    const int per = (total + gridDim.x - 1) / gridDim.x;
+    const int r0 = lb * per;
+    const int r1 = min(total, r0 + per);
+    ChunkCursor cc;
+    for (int gbase = r0; gbase < r1; gbase += NG) {
+      const int g = gbase + grp;
+      if (g >= r1) break;
+      cc.seek(w, g);
+      if (!cc.live || !cc.md.B) continue;
+      int t, i, off, sz;
+      cc.row(w, g, &t, &i, &off, &sz);
+      const MatDesc& d = cc.md;
+      const double bi = d.B[i];
+      for (int e = off + lane; e <= off + sz; e += LPR) {
+        const int j = d.Rci[e];
+        if (j == i) continue;
+        const double dj = w.dsum[cc.fine0 + j];
+        if (dj > 0.0) d.Rva[e] -= bi * (w.rsum[cc.fine0 + j] - d.B[j]) / dj;
+      }
+    }
+  }
   // uncovered F-points: one global atomic per workgroup and matrix
   __shared__ int s_unc;
   for (int m = 0; m < w.nmat; ++m) {
@@ -1802,26 +1824,29 @@ hipError_t launch_scan(const Work& w, hipStream_t s) {
   return hipGetLastError();
 }
 
-// persistent grid: as many workgroups as fit on the device at once
-hipError_t launch_numeric(const Work& w, int which, int group, int wg_threads, int cus, hipStream_t s) {
-#define CLAIR_NUM(GG, NTT)                                                                        \
-  if (group == GG && wg_threads == NTT) {                                                         \
-    int per = 0;                                                                                  \
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_numeric<GG, NTT>, NTT, 0); \
-    if (e != hipSuccess) return e;                                                                \
-    const int blocks = (std::max(1, per) * cus + 7) / 8 * 8;                                     \
-    hipLaunchKernelGGL((k_numeric<GG, NTT>), dim3(blocks), dim3(NTT), 0, s, w, which);            \
-    return hipGetLastError();                                                                     \
+// persistent grid: as many workgroups as fit on the device at once.
+// which = 0: bin A with `group` lanes per row; which = 1: bin B with blocks of
+// up to sm points (16: 16 lanes per row; 24 or 32: 32 lanes per row).
+hipError_t launch_numeric(const Work& w, int which, int group, int sm, int wg_threads, int cus, hipStream_t s) {
+#define CLAIR_NUM(GG, NTT, SMM)                                                                         \
+  if (group == GG && wg_threads == NTT && sm == SMM) {                                                  \
+    int per = 0;                                                                                        \
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_numeric<GG, NTT, SMM>, NTT, 0); \
+    if (e != hipSuccess) return e;                                                                      \
+    const int blocks = (std::max(1, per) * cus + 7) / 8 * 8;                                           \
+    hipLaunchKernelGGL((k_numeric<GG, NTT, SMM>), dim3(blocks), dim3(NTT), 0, s, w, which);             \
+    return hipGetLastError();                                                                           \
   }
-  CLAIR_NUM(8, 256)
-  CLAIR_NUM(8, 128)
-  CLAIR_NUM(8, 64)
-  CLAIR_NUM(16, 256)
-  CLAIR_NUM(16, 128)
-  CLAIR_NUM(16, 64)
-  CLAIR_NUM(32, 256)
-  CLAIR_NUM(32, 128)
-  CLAIR_NUM(32, 64)
+  CLAIR_NUM(8, 256, 8)
+  CLAIR_NUM(8, 128, 8)
+  CLAIR_NUM(8, 64, 8)
+  CLAIR_NUM(16, 256, 16)
+  CLAIR_NUM(16, 128, 16)
+  CLAIR_NUM(16, 64, 16)
+  CLAIR_NUM(32, 256, 32)
+  CLAIR_NUM(32, 128, 32)
+  CLAIR_NUM(32, 64, 32)
+  CLAIR_NUM(32, 128, 24)
 #undef CLAIR_NUM
   return hipErrorInvalidValue;
 }
@@ -1865,9 +1890,12 @@ hipError_t launch_rows_wg(const Work& w, int blocks, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_project(const Work& w, int blocks, hipStream_t s) {
+hipError_t launch_project(const Work& w, int blocks, int lanes_per_row, hipStream_t s) {
   blocks = (blocks + 7) / 8 * 8;
-  hipLaunchKernelGGL(k_project, dim3(blocks), dim3(256), 0, s, w);
+  if (lanes_per_row == 1)
+    hipLaunchKernelGGL(k_project<1>, dim3(blocks), dim3(256), 0, s, w);
+  else
+    hipLaunchKernelGGL(k_project<8>, dim3(blocks), dim3(256), 0, s, w);
   return hipGetLastError();
 }
 
