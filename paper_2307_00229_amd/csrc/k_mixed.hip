@@ -627,7 +627,7 @@ struct NumGroupBuf {
   double K[SM * (SM + 1)];  // FP64 block, row q = row q of (A[N,N])^T, stride SM+1
   double f[SM];             // -A[i,N]
   double z[SM];             // refinement broadcast
-  float U[SM * SM];         // pivot rows
+  float U[G == 8 ? 1 : SM * SM];  // pivot rows (LDS broadcast for G > 8)
   int nb[G];                // sorted N(i), INT32_MAX beyond |N|
 };
 
@@ -887,22 +887,38 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
     int bad = !(amax > 0.f) || !(amax < 3.0e38f);
 #pragma unroll
     for (int k = 0; k < SM; ++k) {
-      if (lane == k) {
-#pragma unroll
-        for (int p = k; p < SM; ++p) gb.U[k * SM + p] = kf[p];
-      }
-      wave_sync();
-      const float piv = gb.U[k * SM + k];
-      // FP32 factors only precondition the FP64 refinement: the hardware
-      // reciprocal (1 ulp) is accurate enough
-      const float pinv = __builtin_amdgcn_rcpf(piv);
-      if (lane == k) uinv = pinv;
-      bad |= !(fabsf(piv) >= 0x1p-24f);
-      if (lane > k && rowl) {
+      float piv, pinv;
+      if constexpr (G == 8) {
+        // eight lanes: the pivot row by ds_swizzle broadcasts
+        piv = gbf<G>(kf[k], k);
+        pinv = __builtin_amdgcn_rcpf(piv);
+        if (lane == k) uinv = pinv;
+        bad |= !(fabsf(piv) >= 0x1p-24f);
         const float l = kf[k] * pinv;
-        kf[k] = l;
+        if (lane > k) kf[k] = l;
 #pragma unroll
-        for (int p = k + 1; p < SM; ++p) kf[p] = fmaf(-l, gb.U[k * SM + p], kf[p]);
+        for (int p = k + 1; p < SM; ++p) {
+          const float ukp = gbf<G>(kf[p], k);
+          if (lane > k) kf[p] = fmaf(-l, ukp, kf[p]);
+        }
+      } else {
+        if (lane == k) {
+#pragma unroll
+          for (int p = k; p < SM; ++p) gb.U[k * SM + p] = kf[p];
+        }
+        wave_sync();
+        piv = gb.U[k * SM + k];
+        // FP32 factors only precondition the FP64 refinement: the hardware
+        // reciprocal (1 ulp) is accurate enough
+        pinv = __builtin_amdgcn_rcpf(piv);
+        if (lane == k) uinv = pinv;
+        bad |= !(fabsf(piv) >= 0x1p-24f);
+        if (lane > k && rowl) {
+          const float l = kf[k] * pinv;
+          kf[k] = l;
+#pragma unroll
+          for (int p = k + 1; p < SM; ++p) kf[p] = fmaf(-l, gb.U[k * SM + p], kf[p]);
+        }
       }
     }
     bad = group_ori<G>(bad);
@@ -923,9 +939,13 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
 #pragma unroll
           for (int p = 0; p < SM; ++p) r = fma(-gb.K[lane * LD + p], gb.z[p], r);
         }
-        const double rn = group_maxd<G>(fabs(r));
-        const double zn = group_maxd<G>(fabs(z));
-        if (rn <= 0x1p-47 * (knorm * zn + fnorm)) { conv = true; break; }
+        // the FP32 solution itself is never accurate to FP64 rounding: the
+        // first correction is applied unchecked
+        if (it > 1) {
+          const double rn = group_maxd<G>(fabs(r));
+          const double zn = group_maxd<G>(fabs(z));
+          if (rn <= 0x1p-47 * (knorm * zn + fnorm)) { conv = true; break; }
+        }
         const float dz = lu_solve<G, SM>(kf, uinv, lane, (float)(r * scale));
         z += (double)dz;
         wave_sync();
