@@ -11,7 +11,9 @@ Prints one JSON line.  Besides the contract fields it carries
 * the plain FP64 per-row form measured on the same inputs and the ratio;
 * accuracy gates of the measured result against the FP64 oracle;
 * "roofline" for the dominant kernel (HIP events on the library's stream);
-* "cpu_baseline": the oracle on the host cores.
+* "cpu_baseline": the oracle on the host cores;
+* "plan_numeric_only": repeated setups on a fixed pattern (symbolic phase
+  once, numeric phase per step), beside the headline, never as it.
 """
 from __future__ import annotations
 
@@ -146,6 +148,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-plan", action="store_true", help="skip the fixed-pattern (plan) measurement")
     ap.add_argument("--mode", choices=["graph", "direct", "best"], default="best")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
@@ -239,6 +242,23 @@ def main():
         p_dev, p_wall = timed(plain_step, args.plain_steps, 2)
         t_plain = p_wall / args.plain_steps
 
+        # repeated setups on a fixed pattern: symbolic phase once (a plan),
+        # numeric phase per step (reported beside the headline, not as it)
+        plan_res = None
+        if not args.no_plan:
+            outs_pl = [clair.ROut(nc, nz, dev) for nc, nz in zip(n_c_list, nnz_list)]
+            plan = clair.Plan(ctx, As, cfs, ells, outs_pl, stream=stream)
+
+            def plan_step():
+                plan.execute(As, Bs, outs_pl, async_=True, stream=stream)
+
+            pl_dev, pl_wall = timed(plan_step, args.steps, args.warmup)
+            st_pl, _ = plan.info()
+            assert st_pl == 0
+            t_pl = pl_wall / args.steps
+            plan_res = {"value": rows / t_pl, "unit": "rows/s", "ms_per_step": t_pl * 1e3,
+                        "gates": None, "_outs": outs_pl}
+
         if args.copy_probe_mib:
             x = torch.empty(args.copy_probe_mib * 2 ** 20 // 4, dtype=torch.float32, device=dev).fill_(1.0)
             y = torch.empty_like(x)
@@ -247,6 +267,8 @@ def main():
             torch.cuda.synchronize()
 
     gates = check_against_oracle(problems, outs)
+    if plan_res is not None:
+        plan_res["gates"] = check_against_oracle(problems, plan_res.pop("_outs"))
     gates_plain = check_against_oracle(problems, outs_p)
 
     whole_bytes, kern_bytes = algorithmic_bytes(problems, n_c_list, nnz_list)
@@ -282,6 +304,7 @@ def main():
         "plain_fp64": {"value": rows / t_plain, "unit": "rows/s", "ms_per_step": t_plain * 1e3,
                        "gates": gates_plain},
         "speedup_vs_plain_fp64": t_plain / t_mixed,
+        "plan_numeric_only": plan_res,
         "modes_ms_per_step": {k: v["wall_s"] / args.steps * 1e3 for k, v in results.items()},
         "graph_error": graph_error,
         "gates": gates,

@@ -201,6 +201,40 @@ void clair_graph_destroy(clair_graph_t* graph);
 /* Results of the last launch of `graph` (synchronises its stream), as clair_ctx_info. */
 int clair_graph_info(clair_graph_t* graph, int32_t nmat, clair_csr_out_t* R_out, clair_info_t* info);
 
+/*
+ * Symbolic/numeric split for repeated setups on one sparsity pattern (for
+ * instance a time-dependent operator whose values change while its graph
+ * does not).  The neighbourhoods N(i) and the layout of R depend only on the
+ * pattern of A (Algorithm 1, pattern expansion), the local solves and the
+ * constraint projection on its values and on B.
+ *
+ * clair_plan_create runs the symbolic phase of a batch once (C/F indexing,
+ * N(i), sizes of R) and keeps its state in a private context copied from
+ * ctx's tuning.  R_out[k] gives the capacities; on return n_rows and nnz hold
+ * the sizes.  If a matrix does not fit, or its input is invalid, no plan is
+ * made and the first non-OK status is returned (CLAIR_ERR_CAPACITY: a size
+ * query).  The cf_marker arrays must stay valid and unchanged while the plan
+ * exists.
+ *
+ * clair_plan_execute runs the numeric phase: block gather, FP32 factorisation
+ * with FP64 refinement, R write and projection.  A[k] must have the pattern
+ * the plan was made with: the same n, row_ptr and col_idx contents, and the
+ * same set of stored entries that are nonzero (a value that becomes exactly
+ * zero removes an edge and needs a new plan); the arrays themselves may be
+ * other buffers.  B[k] may change (NULL: unconstrained rows).  R_out[k] must
+ * hold the sizes the plan reported.  opts->precision must be MIXED; with
+ * opts->async = 1 the call only enqueues (results by clair_plan_info).
+ * Returns the first non-OK per-matrix status.
+ */
+typedef struct clair_plan clair_plan_t;
+int clair_plan_create(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf_marker,
+                      const int32_t* ell, clair_csr_out_t* R_out, void* stream, clair_plan_t** plan);
+int clair_plan_execute(clair_plan_t* plan, int32_t nmat, const clair_csr_t* A, const double* const* B,
+                       clair_csr_out_t* R_out, const clair_opts_t* opts, clair_info_t* info);
+/* Results of the last execute of `plan` (synchronises its stream), as clair_ctx_info. */
+int clair_plan_info(clair_plan_t* plan, int32_t nmat, clair_csr_out_t* R_out, clair_info_t* info);
+void clair_plan_destroy(clair_plan_t* plan);
+
 const char* clair_strerror(int status);
 
 /* Text of the last HIP failure seen by this host thread inside the library

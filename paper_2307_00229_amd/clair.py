@@ -30,6 +30,7 @@ EXPORTED = [
     "clair_ctx_create", "clair_ctx_destroy", "clair_build_R", "clair_build_R_ex", "clair_build_R_batched",
     "clair_ctx_info", "clair_size_R", "clair_ctx_stage_times", "clair_ctx_set_tuning", "clair_ctx_get_tuning",
     "clair_autotune", "clair_graph_create", "clair_graph_launch", "clair_graph_destroy", "clair_graph_info",
+    "clair_plan_create", "clair_plan_execute", "clair_plan_info", "clair_plan_destroy",
     "clair_strerror", "clair_last_error",
 ]
 
@@ -103,6 +104,12 @@ def load_library(path: str = LIB_PATH):
         "clair_graph_launch": ([P, P], ctypes.c_int),
         "clair_graph_destroy": ([P], None),
         "clair_graph_info": ([P, I32, ctypes.POINTER(CsrOut), ctypes.POINTER(Info)], ctypes.c_int),
+        "clair_plan_create": ([P, I32, ctypes.POINTER(CsrIn), ctypes.POINTER(P), ctypes.POINTER(I32),
+                               ctypes.POINTER(CsrOut), P, ctypes.POINTER(P)], ctypes.c_int),
+        "clair_plan_execute": ([P, I32, ctypes.POINTER(CsrIn), ctypes.POINTER(P), ctypes.POINTER(CsrOut),
+                                ctypes.POINTER(Opts), ctypes.POINTER(Info)], ctypes.c_int),
+        "clair_plan_info": ([P, I32, ctypes.POINTER(CsrOut), ctypes.POINTER(Info)], ctypes.c_int),
+        "clair_plan_destroy": ([P], None),
         "clair_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "clair_last_error": ([], ctypes.c_char_p),
     }
@@ -375,6 +382,71 @@ class Graph:
     def close(self):
         if self._h:
             self._lib.clair_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Plan:
+    """Symbolic/numeric split on one sparsity pattern (clair_plan_*): the
+    symbolic phase runs once here, `execute` runs the numeric phase with new
+    values of A (same pattern) and new B."""
+
+    def __init__(self, ctx: Context, As, cfs, ells, outs, stream=None):
+        lib = load_library()
+        self._lib = lib
+        self._h = ctypes.c_void_p()
+        nmat, Ac, cfp, _, ellv, Rc = _batch_args(As, cfs, None, ells, outs)
+        st = lib.clair_plan_create(ctx.handle, nmat, Ac, cfp, ellv, Rc, _stream_ptr(stream), ctypes.byref(self._h))
+        for o, r in zip(outs, Rc):
+            o.n_c, o.nnz, o.n = r.n_rows, r.nnz, r.n_cols
+        if st:
+            raise ClairError(st, "clair_plan_create")
+        self.nmat = nmat
+        self.outs = outs
+        # the C/F markers must outlive the plan
+        self._keep = (cfs,)
+
+    def execute(self, As, Bs, outs=None, async_=False, stream=None, timing=False, check=True):
+        outs = self.outs if outs is None else outs
+        nmat = len(As)
+        Ac = (CsrIn * nmat)(*[a.c() for a in As])
+        if Bs is None:
+            Bs = [None] * nmat
+        for a, B in zip(As, Bs):
+            if B is not None:
+                _check_dev(B, torch.float64, "B")
+                if B.numel() != a.n:
+                    raise ValueError("B length != n")
+        Bp = (ctypes.c_void_p * nmat)(*[None if B is None else B.data_ptr() for B in Bs])
+        Rc = (CsrOut * nmat)(*[o.c() for o in outs])
+        opts = Opts(_stream_ptr(stream), CLAIR_PREC_MIXED, 1 if async_ else 0, 0, 1 if timing else 0)
+        inf = (Info * nmat)()
+        st = self._lib.clair_plan_execute(self._h, nmat, Ac, Bp, Rc, ctypes.byref(opts), inf)
+        if async_:
+            if check and st:
+                raise ClairError(st, "clair_plan_execute (enqueue)")
+            return [], st
+        for o, r in zip(outs, Rc):
+            o.n_c, o.nnz, o.n = r.n_rows, r.nnz, r.n_cols
+        infos = [x.as_dict() for x in inf]
+        if check and st:
+            raise ClairError(st, f"clair_plan_execute infos={infos}")
+        return infos, st
+
+    def info(self):
+        Rc = (CsrOut * self.nmat)()
+        inf = (Info * self.nmat)()
+        st = self._lib.clair_plan_info(self._h, self.nmat, Rc, inf)
+        return st, [x.as_dict() for x in inf]
+
+    def close(self):
+        if self._h:
+            self._lib.clair_plan_destroy(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):

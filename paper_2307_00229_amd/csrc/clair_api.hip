@@ -949,6 +949,156 @@ int clair_graph_launch(clair_graph_t* g, void* stream) {
   return CLAIR_OK;
 }
 
+struct clair_plan {
+  clair_ctx* ctx = nullptr;  // private context: holds the symbolic state
+  Batch b;                   // layout and device pointers of the planned batch
+  std::vector<char> head;    // descriptors, status and counters after the symbolic phase
+  std::vector<int32_t> n, n_c;
+  std::vector<int64_t> nnz, nnzA;
+};
+
+int clair_plan_create(clair_ctx_t* parent, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf,
+                      const int32_t* ell, clair_csr_out_t* R, void* stream, clair_plan_t** out) {
+  if (!parent || !out) return CLAIR_ERR_INVALID;
+  *out = nullptr;
+  int rc = check_args(nmat, A, cf, ell, R);
+  if (rc) return rc;
+  if (nmat == 0) return CLAIR_ERR_INVALID;
+  clair_plan* pl = new (std::nothrow) clair_plan();
+  if (!pl) return CLAIR_ERR_NOMEM;
+  try {
+    rc = clair_ctx_create(&pl->ctx);
+    if (rc) {
+      delete pl;
+      return rc;
+    }
+    clair_ctx* c = pl->ctx;
+    c->group = parent->group;
+    c->wg_threads = parent->wg_threads;
+    c->chunk = parent->chunk;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    Batch& b = pl->b;
+    rc = prepare(c, nmat, A, cf, nullptr, ell, R, &b);
+    if (!rc) rc = enqueue_symbolic(c, b, s, false, false);
+    if (!rc) rc = read_status(c, b, s);
+    if (rc) {
+      clair_plan_destroy(pl);
+      return rc;
+    }
+    const MatStatus* hs = host_status(c, b);
+    fill_results(hs, nmat, R, nullptr, A);
+    const int first = first_error(hs, nmat);
+    if (first) {
+      clair_plan_destroy(pl);
+      return first;
+    }
+    int maxb = 0;
+    for (int m = 0; m < nmat; ++m) maxb = std::max(maxb, hs[m].max_block);
+    c->binB_max = std::max(9, std::min(32, maxb));
+    c->last_maxb = maxb;
+    if (maxb > kLdsBlockMax) {
+      rc = ensure_scratch(c, std::min(64, c->cus / 4 > 0 ? c->cus / 4 : 1));
+      if (rc) {
+        clair_plan_destroy(pl);
+        return rc;
+      }
+    }
+    const char* rb = static_cast<const char*>(c->readback.p);
+    pl->head.assign(rb, rb + b.L.head_bytes);
+    for (int m = 0; m < nmat; ++m) {
+      pl->n.push_back(A[m].n);
+      pl->nnzA.push_back(A[m].nnz);
+      pl->n_c.push_back(hs[m].n_c);
+      pl->nnz.push_back(hs[m].nnz);
+    }
+  } catch (...) {
+    clair_plan_destroy(pl);
+    return CLAIR_ERR_NOMEM;
+  }
+  *out = pl;
+  return CLAIR_OK;
+}
+
+int clair_plan_execute(clair_plan_t* pl, int32_t nmat, const clair_csr_t* A, const double* const* B,
+                       clair_csr_out_t* R, const clair_opts_t* o, clair_info_t* info) {
+  if (!pl || !A || !R || nmat != pl->b.nmat) return CLAIR_ERR_INVALID;
+  if (o && o->precision != CLAIR_PREC_MIXED) return CLAIR_ERR_INVALID;
+  for (int m = 0; m < nmat; ++m) {
+    if (A[m].n != pl->n[m] || A[m].nnz != pl->nnzA[m]) return CLAIR_ERR_INVALID;
+    if (A[m].n > 0 && !A[m].row_ptr) return CLAIR_ERR_INVALID;
+    if (A[m].nnz > 0 && (!A[m].col_idx || !A[m].val)) return CLAIR_ERR_INVALID;
+    if (R[m].row_capacity < (int64_t)pl->n_c[m] + 1 || R[m].nnz_capacity < pl->nnz[m] || !R[m].row_ptr ||
+        (pl->nnz[m] > 0 && (!R[m].col_idx || !R[m].val)))
+      return CLAIR_ERR_CAPACITY;
+  }
+  clair_ctx* c = pl->ctx;
+  const hipStream_t s = static_cast<hipStream_t>(o ? o->stream : nullptr);
+  const bool async = o && o->async;
+  const bool timing = o && o->timing;
+  Batch b = pl->b;
+  // the previous upload must have left the staging buffer before it is rewritten
+  if (c->upload_pending) {
+    HIPCHK(hipEventSynchronize(c->upload_done));
+    c->upload_pending = false;
+  }
+  // descriptors with the new values, B and R; status and counters as the
+  // symbolic phase left them
+  char* h = static_cast<char*>(c->stage.p);
+  std::memcpy(h, pl->head.data(), pl->head.size());
+  MatDesc* hd = reinterpret_cast<MatDesc*>(h);
+  b.any_B = false;
+  for (int m = 0; m < nmat; ++m) {
+    hd[m].rp = A[m].row_ptr;
+    hd[m].ci = A[m].col_idx;
+    hd[m].va = A[m].val;
+    hd[m].B = B ? B[m] : nullptr;
+    hd[m].Rrp = R[m].row_ptr;
+    hd[m].Rci = R[m].col_idx;
+    hd[m].Rva = R[m].val;
+    hd[m].nnz_cap = R[m].nnz_capacity;
+    hd[m].row_cap = R[m].row_capacity;
+    b.any_B |= (B && B[m]);
+  }
+  c->last_nmat = nmat;
+  c->last_stream = s;
+  c->last_layout = b.L;
+  c->last_work = b.w;
+  c->last_plain = false;
+  int rc = 0;
+  if (timing) {
+    rc = timing_begin(c, true);
+    if (rc) return rc;
+  }
+  rc = upload(c, b, s);
+  if (rc) return rc;
+  timing_mark(c, timing, s, "upload");
+  // zero projection sums (k_count did that in a full call) and R.row_ptr[n_c]
+  // of the (possibly new) R buffers
+  HIPCHK(launch_clear_sums(b.w, b.n_total, occupancy_blocks(c, 4), s));
+  if (capture_check(c->capturing, s, "k_clear_sums", __LINE__)) return CLAIR_ERR_HIP;
+  timing_mark(c, timing, s, "clear");
+  const Counters* known = async ? nullptr : reinterpret_cast<const Counters*>(pl->head.data() + (b.L.cnt - b.L.desc));
+  rc = enqueue_numeric(c, b, s, timing, known);
+  if (rc) return rc;
+  if (async) return CLAIR_OK;
+  rc = read_status(c, b, s);
+  if (rc) return rc;
+  const MatStatus* hs = host_status(c, b);
+  fill_results(hs, nmat, R, info, A);
+  return first_error(hs, nmat);
+}
+
+int clair_plan_info(clair_plan_t* pl, int32_t nmat, clair_csr_out_t* R, clair_info_t* info) {
+  if (!pl) return CLAIR_ERR_INVALID;
+  return clair_ctx_info(pl->ctx, nmat, R, info);
+}
+
+void clair_plan_destroy(clair_plan_t* pl) {
+  if (!pl) return;
+  clair_ctx_destroy(pl->ctx);
+  delete pl;
+}
+
 const char* clair_last_error(void) { return g_last_error; }
 
 void clair_graph_destroy(clair_graph_t* g) {

@@ -11,6 +11,7 @@ constexpr int kMaxChunk = 2048;   // fine points per symbolic-pass workgroup (up
 constexpr int kLdsBlockMax = 64;  // workgroup FP64 solver keeps blocks up to this size in LDS
 
 // mixed (default) path
+hipError_t launch_clear_sums(const Work& w, int64_t n_total, int blocks, hipStream_t s);
 hipError_t launch_validate(const Work& w, int blocks, hipStream_t s);
 hipError_t launch_count(const Work& w, hipStream_t s);
 hipError_t launch_count_big(const Work& w, int blocks, hipStream_t s);

@@ -1820,7 +1820,28 @@ __global__ __launch_bounds__(256) void k_project(Work w) {
   }
 }
 
+// a numeric pass without the symbolic pass before it: projection sums of all
+// fine points to zero, and R.row_ptr[n_c] of every matrix
+__global__ void k_clear_sums(Work w, int64_t n) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    w.dsum[j] = 0.0;
+    w.rsum[j] = 0.0;
+  }
+  if (blockIdx.x == 0) {
+    for (int m = threadIdx.x; m < w.nmat; m += blockDim.x) {
+      const MatStatus& st = w.st[m];
+      if (matrix_live(st) && w.desc[m].Rrp) w.desc[m].Rrp[st.n_c] = (int32_t)st.nnz;
+    }
+  }
+}
+
 }  // namespace
+
+// a kernel, not a memset: the call may be captured into a graph
+hipError_t launch_clear_sums(const Work& w, int64_t n_total, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_sums, dim3(blocks), dim3(256), 0, s, w, n_total);
+  return hipGetLastError();
+}
 
 hipError_t launch_validate(const Work& w, int blocks, hipStream_t s) {
   hipLaunchKernelGGL(k_validate, dim3(blocks), dim3(256), 0, s, w);

@@ -1,6 +1,9 @@
 """GPU tests of the entry points around the setup: asynchronous calls,
 hipGraph replay, size queries and capacity errors, device-side validation,
-singular blocks, per-stage timing and the autotuner."""
+singular blocks, per-stage timing, the autotuner, and the symbolic/numeric
+split (plans)."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -206,3 +209,94 @@ def test_repeat_runs_identical_pattern_and_close_values():
     assert np.array_equal(a["col_idx"], b["col_idx"])
     # the projection sums use FP64 atomics: only the last bits may differ
     np.testing.assert_allclose(a["val"], b["val"], rtol=1e-14, atol=1e-16)
+
+
+# ---------------------------------------------------------------------------
+# symbolic/numeric split (clair_plan_*)
+# ---------------------------------------------------------------------------
+
+def _same_pattern_new_values():
+    # same grids, stencils and flow directions (so the same upwind pattern),
+    # other diffusion constants; random B
+    old = _cases()
+    new = [P.small_2d(200, stencil=5, eps=0.3, angle=0.5, ell=2),
+           P.small_2d(150, stencil=9, eps=1e-3, angle=3.0, k=3, ell=2),
+           P.small_3d(24, eps=1.0, b=(1.0, 0.5, 0.25), ell=2)]
+    rng = np.random.default_rng(11)
+    for a, b in zip(old, new):
+        assert np.array_equal(a.row_ptr, b.row_ptr) and np.array_equal(a.col_idx, b.col_idx)
+        b.B = rng.uniform(0.5, 1.5, b.n)
+    return old, new
+
+
+def test_plan_execute_matches_full_setup_on_new_values():
+    from paper_2307_00229_amd import clair
+
+    old, new = _same_pattern_new_values()
+    A0, c0, B0, l0 = to_device(old)
+    ctx = clair.Context()
+    ncs, nzs = clair.clair_size_R(A0, c0, l0, ctx=ctx)
+    outs = [clair.ROut(a, b) for a, b in zip(ncs, nzs)]
+    print("[gpu] plan create", flush=True)
+    plan = clair.Plan(ctx, A0, c0, l0, outs)
+    assert [o.n_c for o in outs] == ncs and [o.nnz for o in outs] == nzs
+    infos, st = plan.execute(A0, B0)
+    for p, o, inf in zip(old, outs, infos):
+        assert_matches_oracle(p, _fetch(o), oracle.build_R_problem(p), inf)
+    # new values and B on the same pattern, twice, into fresh R buffers
+    A1, _, B1, _ = to_device(new)
+    outs1 = [clair.ROut(a, b) for a, b in zip(ncs, nzs)]
+    for _ in range(2):
+        infos, st = plan.execute(A1, B1, outs1)
+        for p, o, inf in zip(new, outs1, infos):
+            assert_matches_oracle(p, _fetch(o), oracle.build_R_problem(p), inf)
+    # unconstrained rows
+    infos, st = plan.execute(A1, None, outs1)
+    for p, o in zip(new, outs1):
+        q = dataclasses.replace(p, B=None)
+        assert_matches_oracle(q, _fetch(o), oracle.build_R_problem(q))
+    plan.close()
+
+
+def test_plan_async_execute_and_info():
+    from paper_2307_00229_amd import clair
+
+    old, new = _same_pattern_new_values()
+    A0, c0, B0, l0 = to_device(old)
+    A1, _, B1, _ = to_device(new)
+    ctx = clair.Context()
+    ncs, nzs = clair.clair_size_R(A0, c0, l0, ctx=ctx)
+    outs = [clair.ROut(a, b) for a, b in zip(ncs, nzs)]
+    plan = clair.Plan(ctx, A0, c0, l0, outs)
+    s = torch.cuda.Stream()
+    for k in range(4):
+        plan.execute(A1 if k % 2 else A0, B1 if k % 2 else B0, async_=True, stream=s)
+    st, infos = plan.info()
+    assert st == 0, infos
+    for p, o, inf in zip(new, outs, infos):
+        assert_matches_oracle(p, _fetch(o), oracle.build_R_problem(p), inf)
+
+
+def test_plan_with_workgroup_rows_and_bad_arguments():
+    from paper_2307_00229_amd import clair
+
+    # neighbourhoods up to 40 points: rows queued for the workgroup solver by
+    # the symbolic phase must be solved again on every execute
+    p = P.cfg3(N=90, ell=3)
+    As, cfs, Bs, ells = to_device([p])
+    ctx = clair.Context()
+    ncs, nzs = clair.clair_size_R(As, cfs, ells, ctx=ctx)
+    outs = [clair.ROut(ncs[0], nzs[0])]
+    plan = clair.Plan(ctx, As, cfs, ells, outs)
+    ref = oracle.build_R_problem(p)
+    for _ in range(3):
+        infos, st = plan.execute(As, Bs)
+        assert infos[0]["max_block"] > 32
+        assert_matches_oracle(p, _fetch(outs[0]), ref, infos[0])
+    # another size than planned, or too small R: rejected before any work
+    q = P.cfg3(N=60, ell=3)
+    Aq, _, Bq, _ = to_device([q])
+    infos, st = plan.execute(Aq, Bq, check=False)
+    assert st == clair.CLAIR_ERR_INVALID
+    infos, st = plan.execute(As, Bs, [clair.ROut(ncs[0], nzs[0] - 1)], check=False)
+    assert st == clair.CLAIR_ERR_CAPACITY
