@@ -71,7 +71,7 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
   size_t desc, st, cnt, chunk_nc, chunk_nnz, chunk_rbase, chunk_nzbase, chunk_mat, chunk_bins, row_block_chunk, clocal, lnz, dsum, rsum,
-      slotA, slotB, binC, ovf, total;
+      slotA, slotB, binC, bigq, big_size, ovf, total;
   size_t head_bytes;  // desc + st + counters (the uploaded head)
   int64_t capC;
 };
@@ -107,6 +107,8 @@ Layout make_layout(int nmat, int nchunks, int64_t n_total, int GA) {
   L.slotA = take(sizeof(int32_t) * (SA ? (n_total + 1) * SA : 1));
   L.slotB = take(sizeof(int32_t) * (n_total + 1) * (GA < 32 ? 32 : 1));
   L.binC = take(sizeof(int32_t) * L.capC);
+  L.bigq = take(sizeof(int32_t) * L.capC);
+  L.big_size = take(sizeof(int32_t) * (n_total + 1));
   L.ovf = take(sizeof(int32_t) * (nchunks + 1));
   L.total = o;
   return L;
@@ -278,7 +280,9 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
   w.slotA = reinterpret_cast<int32_t*>(base + b->L.slotA);
   w.slotB = reinterpret_cast<int32_t*>(base + b->L.slotB);
   w.binC = reinterpret_cast<int32_t*>(base + b->L.binC);
-  w.ovf_chunks = reinterpret_cast<int32_t*>(base + b->L.ovf);
+  w.chunk_unsized = reinterpret_cast<int32_t*>(base + b->L.ovf);
+  w.bigq = reinterpret_cast<int32_t*>(base + b->L.bigq);
+  w.big_size = reinterpret_cast<int32_t*>(base + b->L.big_size);
   w.scratch = static_cast<double*>(c->scratch.p);
   w.scratch_slots = c->scratch_slots;
   w.nmat = nmat;

@@ -60,7 +60,7 @@ struct Counters {
   int32_t nA;          // rows for the small lane-group solver (|N| <= GA)
   int32_t nB;          // rows for the 32-lane solver (GA < |N| <= 32)
   int32_t nC;          // rows queued for the workgroup solver (larger, or FP32 not trusted)
-  int32_t novf;        // chunks holding rows the lane-group search could not size
+  int32_t nbig;        // rows with more than 32 points queued for k_count_big
   int32_t pad0, pad1, pad2;
 };
 
@@ -86,7 +86,9 @@ struct Work {
   int32_t* slotA;         // [n_total * GA]
   int32_t* slotB;         // [n_total * 32]
   int32_t* binC;          // [capC] rows for the workgroup solver
-  int32_t* ovf_chunks;    // [nchunks]
+  int32_t* chunk_unsized;  // [nchunks] rows of the chunk not yet sized (more than 32 points)
+  int32_t* bigq;           // [capC] those rows, c * chunk + t
+  int32_t* big_size;       // [n_total] their sizes, until the chunk's prefix is redone
   double* scratch;        // FP64 blocks for oversized rows: scratch_slots * kMaxBlock^2 (may be null)
   int64_t scratch_slots;
   int32_t nmat;

@@ -339,8 +339,9 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
   __shared__ int16_t s_size[kMaxChunk];
   __shared__ int s_scan[kNT];
   __shared__ int s_flag[4];  // max |N|, unresolved rows, rows in bin A, rows in bin B
-  __shared__ int16_t s_list[kMaxChunk];  // rows with more than 8 points
-  __shared__ int s_nlist;
+  __shared__ int16_t s_list[kMaxChunk];   // rows with more than 8 points
+  __shared__ int16_t s_unres[kMaxChunk];  // rows with more than 32 points
+  __shared__ int s_nlist, s_qbase;
 
   const int c = xcd_logical_block();
   const int tid = threadIdx.x;
@@ -352,7 +353,7 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
   const int64_t base = d.fine0 + f0;
 
   if (st->status == ST_INVALID) {  // validation failed: contribute nothing
-    if (tid == 0) { w.chunk_nc[c] = 0; w.chunk_nnz[c] = 0; w.chunk_mat[c] = m; w.chunk_bins[c] = make_int2(0, 0); }
+    if (tid == 0) { w.chunk_nc[c] = 0; w.chunk_nnz[c] = 0; w.chunk_mat[c] = m; w.chunk_bins[c] = make_int2(0, 0); w.chunk_unsized[c] = 0; }
     return;
   }
 
@@ -375,7 +376,7 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
   __syncthreads();
 
   const int SA = slot_stride(w.GA);
-  int inA = 0, inB = 0, unresolved = 0;
+  int inA = 0, inB = 0;
 
   // one thread per C-row, neighbourhoods of up to 8 points in registers; the
   // larger ones are left unsized for k_count_big
@@ -408,7 +409,7 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
       if (sz < 0) {
         s_size[t] = 0;
         w.clocal[base + t] = -(s_rows[t] + 1);
-        ++unresolved;
+        s_unres[atomicAdd(&s_flag[1], 1)] = t;
       } else if (sz <= lim) {
         s_size[t] = sz;
         ++inA;
@@ -426,8 +427,18 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
   }
   if (inA) atomicAdd(&s_flag[2], inA);
   if (inB) atomicAdd(&s_flag[3], inB);
-  if (unresolved) atomicAdd(&s_flag[1], unresolved);
   __syncthreads();
+  // rows of more than 32 points: one queue entry each for k_count_big
+  const int nunres = s_flag[1];
+  if (nunres) {
+    if (tid == 0) s_qbase = atomicAdd(&w.cnt->nbig, nunres);
+    __syncthreads();
+    for (int k = tid; k < nunres; k += kNT) {
+      const int q = s_qbase + k;
+      if (q < w.capC) w.bigq[q] = c * w.chunk + s_unres[k];
+      else flag_row(st, ST_UNSUPPORTED, s_rows[s_unres[k]]);
+    }
+  }
 
   // chunk-local exclusive prefix of (s+1)
   const int per2 = (nc + kNT - 1) / kNT;
@@ -448,81 +459,72 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
     w.chunk_bins[c] = make_int2(s_flag[2], s_flag[3]);
     if (s_flag[0] > __hip_atomic_load(&st->max_block, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
       atomicMax(&st->max_block, s_flag[0]);
-    if (s_flag[1]) {
-      const int q = atomicAdd(&w.cnt->novf, 1);
-      w.ovf_chunks[q] = c;
-    }
+    w.chunk_unsized[c] = nunres;
   }
 }
 
-// chunks with rows the lane-group search could not size: one workgroup each
+// Rows with more than 32 points, one workgroup per row (grid-stride over the
+// queue): the workgroup search sizes the row, which is queued for the
+// workgroup solver.  The workgroup that sizes the last such row of a chunk
+// then redoes the chunk's prefix.
 __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
   __shared__ WideBuf bb;
   __shared__ int s_size[kMaxChunk];
-  __shared__ int s_lrows[kMaxChunk];
   __shared__ int s_scan[kNT];
-  __shared__ int s_max, s_left;
+  __shared__ int s_last;
   const int tid = threadIdx.x;
-  const int nov = w.cnt->novf;
-  for (int k = blockIdx.x; k < nov; k += gridDim.x) {
-    const int c = w.ovf_chunks[k];
+  const int nq = min(w.cnt->nbig, w.capC);
+  for (int qi = blockIdx.x; qi < nq; qi += gridDim.x) {
+    const int e = w.bigq[qi];
+    const int c = e / w.chunk, t = e - c * w.chunk;
     const int m = w.chunk_mat[c];
-    const MatDesc d = w.desc[m];
+    const MatDesc& d = w.desc[m];
     MatStatus* st = &w.st[m];
     const int64_t base = d.fine0 + (int64_t)(c - d.chunk0) * w.chunk;
-    const int nc = w.chunk_nc[c];
-    // sizes of the rows already done, from the prefix
-    for (int t = tid; t < nc; t += kNT) {
-      const int l1 = (t + 1 < nc) ? w.lnz[base + t + 1] : w.chunk_nnz[c];
-      s_size[t] = l1 - w.lnz[base + t] - 1;
-    }
-    if (tid == 0) s_max = 0;
+    const int i = -w.clocal[base + t] - 1;
+    int* nl;
+    const int s = block_bfs(d.n, i, d.ell, d.rp, d.ci, d.va, d.cf, bb, &nl);
     __syncthreads();
-    // rows the register searches could not size (more than 32 points)
     if (tid == 0) {
-      int k = 0;
-      for (int t = 0; t < nc; ++t)
-        if (w.clocal[base + t] < 0) s_lrows[k++] = t;
-      s_left = k;
+      w.big_size[base + t] = s < 0 ? 0 : s;
+      if (s < 0) {
+        flag_row(st, ST_UNSUPPORTED, i);
+      } else {
+        if (s > __hip_atomic_load(&st->max_block, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+          atomicMax(&st->max_block, s);
+        const int q = atomicAdd(&w.cnt->nC, 1);
+        if (q < w.capC) w.binC[q] = e;
+        else flag_row(st, ST_UNSUPPORTED, i);
+      }
+      __threadfence();  // the size is visible before the count drops
+      s_last = atomicSub(&w.chunk_unsized[c], 1) == 1;
     }
     __syncthreads();
-    const int nleft = s_left;
-    for (int k = 0; k < nleft; ++k) {
-      const int t = s_lrows[k];
-      const int i = -w.clocal[base + t] - 1;
-      int* nl;
-      const int s = block_bfs(d.n, i, d.ell, d.rp, d.ci, d.va, d.cf, bb, &nl);
-      __syncthreads();
-      // more than 32 points (the register search said so): the workgroup solver
-      if (tid == 0) {
-        w.clocal[base + t] = i;
-        if (s < 0) {
-          flag_row(st, ST_UNSUPPORTED, i);
-          s_size[t] = 0;
-        } else {
-          s_size[t] = s;
-          s_max = max(s_max, s);
-          const int q = atomicAdd(&w.cnt->nC, 1);
-          if (q < w.capC) w.binC[q] = c * w.chunk + t;
-          else flag_row(st, ST_UNSUPPORTED, i);
-        }
+    if (s_last) {
+      __threadfence();  // every size of the chunk is visible here
+      // sizes: k_count's prefix (0 for the unsized rows) and the unsized
+      // rows' own sizes; their C-point index is restored
+      const int nc = w.chunk_nc[c];
+      for (int tt = tid; tt < nc; tt += kNT) {
+        const int l1 = (tt + 1 < nc) ? w.lnz[base + tt + 1] : w.chunk_nnz[c];
+        int sz = l1 - w.lnz[base + tt] - 1;
+        const int ci = w.clocal[base + tt];
+        if (ci < 0) sz = w.big_size[base + tt];
+        s_size[tt] = sz;
       }
       __syncthreads();
-    }
-
-    // redo the chunk-local prefix
-    const int per2 = (nc + kNT - 1) / kNT;
-    const int t0 = tid * per2;
-    int mysum = 0;
-    for (int t = t0; t < min(t0 + per2, nc); ++t) mysum += s_size[t] + 1;
-    int tot;
-    int pre = block_exclusive_scan(mysum, s_scan, &tot);
-    for (int t = t0; t < min(t0 + per2, nc); ++t) { w.lnz[base + t] = pre; pre += s_size[t] + 1; }
-    __syncthreads();
-    if (tid == 0) {
-      w.chunk_nnz[c] = tot;
-      if (s_max > __hip_atomic_load(&st->max_block, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-        atomicMax(&st->max_block, s_max);
+      for (int tt = tid; tt < nc; tt += kNT) {
+        const int ci = w.clocal[base + tt];
+        if (ci < 0) w.clocal[base + tt] = -ci - 1;
+      }
+      const int per2 = (nc + kNT - 1) / kNT;
+      const int t0 = tid * per2;
+      int mysum = 0;
+      for (int tt = t0; tt < min(t0 + per2, nc); ++tt) mysum += s_size[tt] + 1;
+      int tot;
+      int pre = block_exclusive_scan(mysum, s_scan, &tot);
+      for (int tt = t0; tt < min(t0 + per2, nc); ++tt) { w.lnz[base + tt] = pre; pre += s_size[tt] + 1; }
+      if (tid == 0) w.chunk_nnz[c] = tot;
     }
     __syncthreads();
   }
