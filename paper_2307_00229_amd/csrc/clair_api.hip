@@ -483,7 +483,7 @@ int run_mixed(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* co
     c->binB_max = std::max(9, std::min(32, maxb));
     c->last_maxb = maxb;
     if (maxb > kLdsBlockMax) {
-      rc = ensure_scratch(c, std::min(64, c->cus / 4 > 0 ? c->cus / 4 : 1));
+      rc = ensure_scratch(c, std::max(1, c->cus));
       if (rc) return rc;
     }
   }
@@ -1001,7 +1001,7 @@ int clair_plan_create(clair_ctx_t* parent, int32_t nmat, const clair_csr_t* A, c
     c->binB_max = std::max(9, std::min(32, maxb));
     c->last_maxb = maxb;
     if (maxb > kLdsBlockMax) {
-      rc = ensure_scratch(c, std::min(64, c->cus / 4 > 0 ? c->cus / 4 : 1));
+      rc = ensure_scratch(c, std::max(1, c->cus));
       if (rc) {
         clair_plan_destroy(pl);
         return rc;

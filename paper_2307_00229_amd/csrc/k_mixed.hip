@@ -1564,13 +1564,216 @@ __device__ __forceinline__ void block_argmax(double v, int idx, double* shv, int
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// blocks of 32 < |N| <= 128 in the workgroup solver: FP32 LU of the scaled
+// block in LDS, blocked by panels of 32 columns, the trailing updates on the
+// matrix cores (v_mfma_f32_32x32x2f32, one 32x32 tile per wavefront and
+// step), FP32 triangular solves, FP64 residuals from A's CSR rows and
+// iterative refinement.  No pivoting: a tiny pivot or no convergence hands
+// the row to the FP64 solver with partial pivoting.
+// ---------------------------------------------------------------------------
+constexpr int kMfmaMax = 128;
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// max of v over the workgroup (all threads call; result to all)
+__device__ __forceinline__ double block_maxd(double v, double* shv) {
+  const int tid = threadIdx.x;
+  shv[tid] = v;
+  __syncthreads();
+  for (int o = kWT / 2; o > 0; o >>= 1) {
+    if (tid < o) shv[tid] = fmax(shv[tid], shv[tid + o]);
+    __syncthreads();
+  }
+  const double r = shv[0];
+  __syncthreads();
+  return r;
+}
+
+// y <- K^{-1} y for the packed LU (unit lower L, upper U) of the S x S block in
+// LDS (stride lda).  Wavefront 0 only: lane l holds rows l and l + 64; the
+// solved entry of each step goes to all lanes by readlane.
+__device__ __forceinline__ void mf_lu_solve(const float* K, int lda, int S, float& y0, float& y1) {
+  const int l = threadIdx.x & 63;
+  const int r0 = l, r1 = l + 64;
+  for (int k = 0; k < S; ++k) {  // forward, unit lower
+    const float yk = (k < 64) ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y0), k))
+                              : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y1), k - 64));
+    if (r0 > k && r0 < S) y0 = fmaf(-K[r0 * lda + k], yk, y0);
+    if (r1 > k && r1 < S) y1 = fmaf(-K[r1 * lda + k], yk, y1);
+  }
+  for (int k = S - 1; k >= 0; --k) {  // backward, upper
+    const float ukk = K[k * lda + k];
+    if (r0 == k) y0 = y0 / ukk;
+    if (r1 == k) y1 = y1 / ukk;
+    const float yk = (k < 64) ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y0), k))
+                              : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y1), k - 64));
+    if (r0 < k) y0 = fmaf(-K[r0 * lda + k], yk, y0);
+    if (r1 < k && r1 < S) y1 = fmaf(-K[r1 * lda + k], yk, y1);
+  }
+}
+
+// Returns true with the solution in z[0..s) when the row converged.
+// N: sorted neighbourhood (LDS); K: LDS buffer of (kMfmaMax+1)*kMfmaMax
+// floats; f, z, r: LDS FP64 vectors of kMfmaMax.
+__device__ __forceinline__ bool mixed_big_row(const MatDesc& d, int i, const int* N, int s, float* K, double* f, double* z,
+                              double* r, double* shv, int* s_flag, int* it_out) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int S = (s + 31) & ~31;
+  const int lda = S + 1;
+  // scale: a power of two from the largest entry of the rows of N; norms
+  double amax = 0.0, rsum = 0.0;
+  for (int p = tid; p < s; p += kWT) {
+    const int u = N[p];
+    double rs = 0.0;
+    for (int ee = d.rp[u]; ee < d.rp[u + 1]; ++ee) {
+      const double v = fabs(d.va[ee]);
+      amax = fmax(amax, v);
+      rs += v;
+    }
+    rsum = fmax(rsum, rs);
+  }
+  amax = block_maxd(amax, shv);
+  const double knorm = block_maxd(rsum, shv);
+  if (!(amax > 0.0) || !(amax < 1e300)) return false;
+  int ex = 0;
+  frexp(amax, &ex);
+  const double scale = ldexp(1.0, -ex);
+  // the scaled block in FP32, identity on the padding; f = -A[i,N] in FP64
+  for (int t = tid; t < S * lda; t += kWT) {
+    const int q = t / lda, p = t - q * lda;
+    K[t] = (q == p && q >= s) ? 1.f : 0.f;
+  }
+  for (int t = tid; t < kMfmaMax; t += kWT) { f[t] = 0.0; z[t] = 0.0; }
+  __syncthreads();
+  for (int p = tid; p < s; p += kWT) {
+    const int u = N[p];
+    for (int ee = d.rp[u]; ee < d.rp[u + 1]; ++ee) {
+      const int q = find_sorted(N, s, d.ci[ee]);
+      if (q >= 0) K[q * lda + p] = (float)(d.va[ee] * scale);
+    }
+  }
+  for (int ee = d.rp[i] + tid; ee < d.rp[i + 1]; ee += kWT) {
+    const int q = find_sorted(N, s, d.ci[ee]);
+    if (q >= 0) f[q] = -d.va[ee];
+  }
+  if (tid == 0) s_flag[0] = 0;
+  __syncthreads();
+
+  // ---- blocked LU, panels of 32 columns ----
+  for (int P0 = 0; P0 < S; P0 += 32) {
+    const int Pe = P0 + 32;
+    for (int k = P0; k < Pe; ++k) {
+      const float piv = K[k * lda + k];
+      if (tid == 0 && !(fabsf(piv) >= 0x1p-24f)) s_flag[0] = 1;
+      const float pinv = __builtin_amdgcn_rcpf(piv);
+      for (int q = k + 1 + tid; q < S; q += kWT) K[q * lda + k] *= pinv;
+      __syncthreads();
+      // rows of this block row: every column to the right (they become U);
+      // rows below: the panel's columns only
+      const int nr1 = Pe - k - 1, nc1 = S - k - 1;  // block-row part
+      const int nr2 = S - Pe, nc2 = Pe - k - 1;     // panel part below
+      const int n1 = nr1 * nc1, n2 = nr2 * nc2;
+      for (int t = tid; t < n1 + n2; t += kWT) {
+        int q, c;
+        if (t < n1) { q = k + 1 + t / nc1; c = k + 1 + t % nc1; }
+        else { const int u = t - n1; q = Pe + u / nc2; c = k + 1 + u % nc2; }
+        K[q * lda + c] = fmaf(-K[q * lda + k], K[k * lda + c], K[q * lda + c]);
+      }
+      __syncthreads();
+    }
+    // trailing update K22 -= L21 U12 on the matrix cores
+    const int T = (S - Pe) / 32;
+    for (int tile = wv; tile < T * T; tile += kWT / 64) {
+      const int i0 = Pe + 32 * (tile / T), j0 = Pe + 32 * (tile % T);
+      floatx16 acc;
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) {
+        const int row = i0 + 8 * (rr / 4) + 4 * (lane / 32) + (rr % 4);
+        acc[rr] = K[row * lda + j0 + (lane % 32)];
+      }
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        const int kc = P0 + 2 * kk + lane / 32;
+        const float a = -K[(i0 + lane % 32) * lda + kc];
+        const float b = K[kc * lda + j0 + lane % 32];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int rr = 0; rr < 16; ++rr) {
+        const int row = i0 + 8 * (rr / 4) + 4 * (lane / 32) + (rr % 4);
+        K[row * lda + j0 + (lane % 32)] = acc[rr];
+      }
+    }
+    __syncthreads();
+  }
+  if (s_flag[0]) return false;
+
+  // ---- solve and refine ----
+  const double fnorm = [&] {
+    double m = 0.0;
+    for (int t = tid; t < s; t += kWT) m = fmax(m, fabs(f[t]));
+    return block_maxd(m, shv);
+  }();
+  if (wv == 0) {
+    float y0 = (lane < s) ? (float)(f[lane] * scale) : 0.f;
+    float y1 = (lane + 64 < s) ? (float)(f[lane + 64] * scale) : 0.f;
+    mf_lu_solve(K, lda, S, y0, y1);
+    if (lane < s) z[lane] = y0;
+    if (lane + 64 < s) z[lane + 64] = y1;
+  }
+  __syncthreads();
+  for (int it = 1; it <= kRefineMax; ++it) {
+    // r = f - K z with the FP64 entries of A: row N_p adds -a_{N_p, N_q} z_p to r_q
+    for (int t = tid; t < s; t += kWT) r[t] = f[t];
+    __syncthreads();
+    for (int p = tid; p < s; p += kWT) {
+      const int u = N[p];
+      const double zp = z[p];
+      for (int ee = d.rp[u]; ee < d.rp[u + 1]; ++ee) {
+        const int q = find_sorted(N, s, d.ci[ee]);
+        if (q >= 0) atomicAdd(&r[q], -d.va[ee] * zp);
+      }
+    }
+    __syncthreads();
+    if (it > 1) {
+      double rn = 0.0, zn = 0.0;
+      for (int t = tid; t < s; t += kWT) { rn = fmax(rn, fabs(r[t])); zn = fmax(zn, fabs(z[t])); }
+      rn = block_maxd(rn, shv);
+      zn = block_maxd(zn, shv);
+      if (rn <= 0x1p-47 * (knorm * zn + fnorm)) {
+        *it_out = it;
+        bool finite = true;
+        for (int t = 0; t < s; ++t) finite &= (z[t] == z[t]);
+        return finite;
+      }
+    }
+    if (wv == 0) {
+      float y0 = (lane < s) ? (float)(r[lane] * scale) : 0.f;
+      float y1 = (lane + 64 < s) ? (float)(r[lane + 64] * scale) : 0.f;
+      mf_lu_solve(K, lda, S, y0, y1);
+      if (lane < s) z[lane] += (double)y0;
+      if (lane + 64 < s) z[lane + 64] += (double)y1;
+    }
+    __syncthreads();
+  }
+  return false;
+}
+
 __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
   __shared__ WideBuf bb;
-  __shared__ double sK[kLdsBlockMax * (kLdsBlockMax + 1)];
+  // the FP64 block of the pivoting solver and the FP32 block of the mixed
+  // solver share this buffer (one row at a time)
+  constexpr int kBlkBytes = (int)std::max(sizeof(double) * kLdsBlockMax * (kLdsBlockMax + 1),
+                                          sizeof(float) * kMfmaMax * (kMfmaMax + 1));
+  __shared__ __align__(16) char s_blk[kBlkBytes];
+  double* sK = reinterpret_cast<double*>(s_blk);
+  float* sK32 = reinterpret_cast<float*>(s_blk);
   __shared__ double sf[kMaxBlock];
+  __shared__ double s_z[kMfmaMax], s_r[kMfmaMax];
   __shared__ double shv[kWT];
   __shared__ int shi[kWT];
-  __shared__ int s_bad;
+  __shared__ int s_bad, s_mflag;
 
   const int tid = threadIdx.x;
   const int qlen = min(w.cnt->nC, w.capC);
@@ -1611,6 +1814,16 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
         __syncthreads();
         continue;
       }
+      // blocks above 32 points: the mixed solver first
+      int itm = 0;
+      const bool mixed_ok = s > 32 && s <= kMfmaMax &&
+                            mixed_big_row(d, i, N, s, sK32, sf, s_z, s_r, shv, &s_mflag, &itm);
+      if (mixed_ok) {
+        for (int t = tid; t < s; t += kWT) sf[t] = s_z[t];
+        if (tid == 0 && itm > __hip_atomic_load(&st->refine_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+          atomicMax(&st->refine_max, itm);
+        __syncthreads();
+      } else {
       const int ld = big ? s : (kLdsBlockMax + 1);
       double* K = big ? (w.scratch + (int64_t)blockIdx.x * kMaxBlock * kMaxBlock) : sK;
       for (int t = tid; t < s * ld; t += kWT) K[t] = 0.0;
@@ -1688,6 +1901,7 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
         }
         ++run_n;
       }
+      }  // FP64 solver
       // R row
       int dpos = 0;
       {

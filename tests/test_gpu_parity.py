@@ -89,11 +89,13 @@ def test_cfg5_128cube_7pt():
 # 8/16/32, workgroup-per-row in LDS and in global scratch
 # ---------------------------------------------------------------------------
 
-def test_cfg3_shape_ell3_workgroup_lds_path():
+def test_cfg3_shape_ell3_workgroup_mixed_path():
+    # blocks of 33..40 points: the workgroup solver's FP32 blocked LU (matrix
+    # cores) with FP64 refinement takes them all
     p = P.cfg3(N=300, ell=3)
     res, infos = _check([p], precision=0)
     assert infos[0]["max_block"] == 40
-    assert infos[0]["n_fp64_rows"] > 0
+    assert infos[0]["n_fp64_rows"] == 0
 
 
 def test_cfg3_shape_ell5_scratch_path():
