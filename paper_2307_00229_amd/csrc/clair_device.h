@@ -41,6 +41,58 @@ struct MatDesc {
   int64_t fine0;    // offset of this matrix in fine-indexed workspaces
 };
 
+// Pointers into device (global) memory.  Pointers that kernels load from a
+// descriptor in memory are generic to the compiler, and generic (flat) loads
+// count against the LDS/scalar wait counter too, so every LDS or scalar wait
+// would also wait for them.  Kernels read the matrix descriptor through GDesc,
+// whose loads and stores compile to global_* instructions.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> to_global(T* p) {
+  return (gptr<T>)p;
+}
+
+struct GDesc {
+  gptr<const int32_t> rp;
+  gptr<const int32_t> ci;
+  gptr<const double> va;
+  gptr<const int8_t> cf;
+  gptr<const double> B;  // may be null
+  gptr<int32_t> Rrp;
+  gptr<int32_t> Rci;
+  gptr<double> Rva;
+  int64_t nnz_cap;
+  int32_t row_cap;
+  int32_t n;
+  int32_t ell;
+  int32_t chunk0;
+  int32_t nchunks;
+  int32_t nnz;
+  int64_t fine0;
+};
+
+__device__ __forceinline__ GDesc gview(const MatDesc& m) {
+  GDesc g;
+  g.rp = to_global(m.rp);
+  g.ci = to_global(m.ci);
+  g.va = to_global(m.va);
+  g.cf = to_global(m.cf);
+  g.B = to_global(m.B);
+  g.Rrp = to_global(m.Rrp);
+  g.Rci = to_global(m.Rci);
+  g.Rva = to_global(m.Rva);
+  g.nnz_cap = m.nnz_cap;
+  g.row_cap = m.row_cap;
+  g.n = m.n;
+  g.ell = m.ell;
+  g.chunk0 = m.chunk0;
+  g.nchunks = m.nchunks;
+  g.nnz = m.nnz;
+  g.fine0 = m.fine0;
+  return g;
+}
+
 struct MatStatus {
   int32_t status;      // clair_status code (0 = ok)
   int32_t first_bad;   // smallest fine index of a failing row (INT32_MAX = none)
@@ -168,9 +220,9 @@ struct RegSet {
 // the F-neighbours of u (edges with a stored nonzero), added at level L;
 // entries are read eight at a time (one batch for most stencil rows)
 template <int SM>
-__device__ __forceinline__ void reg_expand(RegSet<SM>& S, int n, int u, int L, const int32_t* __restrict__ rp,
-                                           const int32_t* __restrict__ ci, const double* __restrict__ va,
-                                           const int8_t* __restrict__ cf) {
+__device__ __forceinline__ void reg_expand(RegSet<SM>& S, int n, int u, int L, gptr<const int32_t> __restrict__ rp,
+                                           gptr<const int32_t> __restrict__ ci, gptr<const double> __restrict__ va,
+                                           gptr<const int8_t> __restrict__ cf) {
   const int e1 = rp[u + 1];
   for (int e = rp[u]; e < e1 && !S.ovf; e += 8) {
     int k[8];
@@ -192,9 +244,9 @@ __device__ __forceinline__ void reg_expand(RegSet<SM>& S, int n, int u, int L, c
 }
 
 template <int SM>
-__device__ __forceinline__ int reg_bfs(RegSet<SM>& S, int n, int i, int ell, const int32_t* __restrict__ rp,
-                                       const int32_t* __restrict__ ci, const double* __restrict__ va,
-                                       const int8_t* __restrict__ cf) {
+__device__ __forceinline__ int reg_bfs(RegSet<SM>& S, int n, int i, int ell, gptr<const int32_t> __restrict__ rp,
+                                       gptr<const int32_t> __restrict__ ci, gptr<const double> __restrict__ va,
+                                       gptr<const int8_t> __restrict__ cf) {
   S.clear();
   reg_expand(S, n, i, 1, rp, ci, va, cf);
   for (int L = 2; L <= ell && !S.ovf; ++L) {
@@ -265,9 +317,9 @@ struct RegSetM {
 
 // F-neighbours of u (stored nonzero, u excluded), eight entries per batch
 template <int SM>
-__device__ __forceinline__ void regm_expand(RegSetM<SM>& S, int n, int u, const int32_t* __restrict__ rp,
-                                            const int32_t* __restrict__ ci, const double* __restrict__ va,
-                                            const int8_t* __restrict__ cf) {
+__device__ __forceinline__ void regm_expand(RegSetM<SM>& S, int n, int u, gptr<const int32_t> __restrict__ rp,
+                                            gptr<const int32_t> __restrict__ ci, gptr<const double> __restrict__ va,
+                                            gptr<const int8_t> __restrict__ cf) {
   const int e1 = rp[u + 1];
   for (int e = rp[u]; e < e1 && !S.ovf; e += 8) {
     int k[8];
@@ -288,9 +340,9 @@ __device__ __forceinline__ void regm_expand(RegSetM<SM>& S, int n, int u, const 
 }
 
 template <int SM>
-__device__ __forceinline__ int regm_bfs(RegSetM<SM>& S, int n, int i, int ell, const int32_t* __restrict__ rp,
-                                        const int32_t* __restrict__ ci, const double* __restrict__ va,
-                                        const int8_t* __restrict__ cf) {
+__device__ __forceinline__ int regm_bfs(RegSetM<SM>& S, int n, int i, int ell, gptr<const int32_t> __restrict__ rp,
+                                        gptr<const int32_t> __restrict__ ci, gptr<const double> __restrict__ va,
+                                        gptr<const int8_t> __restrict__ cf) {
   S.clear();
   regm_expand(S, n, i, rp, ci, va, cf);
   for (int L = 2; L <= ell && !S.ovf; ++L) {

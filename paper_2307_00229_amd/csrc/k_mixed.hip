@@ -86,8 +86,8 @@ struct WideBuf {
 
 // Returns |N(i)| with the sorted list in *out, or -1 when it exceeds kWN
 // (block-uniform).  Must be called by all kNT threads of the workgroup.
-__device__ int block_bfs(int n, int i, int ell, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                         const double* __restrict__ va, const int8_t* __restrict__ cf, WideBuf& b, int** out) {
+__device__ int block_bfs(int n, int i, int ell, gptr<const int32_t> __restrict__ rp, gptr<const int32_t> __restrict__ ci,
+                         gptr<const double> __restrict__ va, gptr<const int8_t> __restrict__ cf, WideBuf& b, int** out) {
   const int tid = threadIdx.x;
   constexpr int nt = kNT;
   int* cur = b.nb0;
@@ -219,7 +219,7 @@ struct RowInfo {
 __device__ __forceinline__ RowInfo row_info(const Work& w, int c, int t) {
   RowInfo ri;
   ri.m = w.chunk_mat[c];
-  const MatDesc& d = w.desc[ri.m];
+  const GDesc d = gview(w.desc[ri.m]);
   const int64_t base = d.fine0 + (int64_t)(c - d.chunk0) * w.chunk;
   ri.i = w.clocal[base + t];
   const int l0 = w.lnz[base + t];
@@ -249,7 +249,7 @@ struct ChunkCursor {
   int64_t fbase = 0;    // fine offset of the chunk's first point (batch-wide)
   int64_t fine0 = 0;    // fine offset of the matrix (batch-wide)
   bool live = false;
-  MatDesc md;           // the matrix's pointers and geometry
+  GDesc md;             // the matrix's pointers and geometry
 
   __device__ __forceinline__ void seek(const Work& w, int g) {
     if (c >= 0 && g >= rb && g < re) return;
@@ -257,7 +257,7 @@ struct ChunkCursor {
     rb = w.chunk_rbase[c];
     re = w.chunk_rbase[c + 1];
     m = w.chunk_mat[c];
-    md = w.desc[m];
+    md = gview(w.desc[m]);
     const MatStatus& st = w.st[m];
     nc = w.chunk_nc[c];
     tot = w.chunk_nnz[c];
@@ -311,7 +311,7 @@ __device__ __forceinline__ int wave_append(bool want, int32_t* counter, int cap)
 // ---------------------------------------------------------------------------
 __global__ void k_validate(Work w) {
   for (int m = 0; m < w.nmat; ++m) {
-    const MatDesc d = w.desc[m];
+    const GDesc d = gview(w.desc[m]);
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < d.n; r += gridDim.x * blockDim.x) {
       const int e0 = d.rp[r], e1 = d.rp[r + 1];
       bool bad = (e1 < e0) || e0 < 0 || e1 > d.nnz || (r == 0 && e0 != 0) || (r == d.n - 1 && e1 != d.nnz);
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
   const int c = xcd_logical_block();
   const int tid = threadIdx.x;
   const int m = chunk_matrix(w.desc, w.nmat, c);
-  const MatDesc d = w.desc[m];
+  const GDesc d = gview(w.desc[m]);
   MatStatus* st = &w.st[m];
   const int f0 = (c - d.chunk0) * w.chunk;
   const int f1 = min(f0 + w.chunk, d.n);
@@ -478,7 +478,7 @@ __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
     const int e = w.bigq[qi];
     const int c = e / w.chunk, t = e - c * w.chunk;
     const int m = w.chunk_mat[c];
-    const MatDesc& d = w.desc[m];
+    const GDesc d = gview(w.desc[m]);
     MatStatus* st = &w.st[m];
     const int64_t base = d.fine0 + (int64_t)(c - d.chunk0) * w.chunk;
     const int i = -w.clocal[base + t] - 1;
@@ -589,7 +589,7 @@ __global__ __launch_bounds__(1024) void k_scan(Work w) {
   }
   __syncthreads();
   for (int m = tid; m < w.nmat; m += 1024) {
-    const MatDesc& d = w.desc[m];
+    const GDesc d = gview(w.desc[m]);
     MatStatus* st = &w.st[m];
     const int cb = d.chunk0, ce = d.chunk0 + d.nchunks;
     const long long rb = cb < nch ? w.chunk_rbase[cb] : rows_total;
@@ -819,7 +819,7 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
     }
     const int c = cc.c;
     const int entry = c * w.chunk + t;
-    const MatDesc& d = cc.md;
+    const GDesc& d = cc.md;
     MatStatus* st = &w.st[cc.m];
     RowInfo ri;
     ri.m = cc.m;
@@ -1073,7 +1073,7 @@ __global__ __launch_bounds__(NT) void k_quad8(Work w) {
     if (s > 8 || !cc.live) continue;
     const int c = cc.c;
     MatStatus* st = &w.st[cc.m];
-    const MatDesc& d = cc.md;
+    const GDesc& d = cc.md;
     RowInfo ri;
     ri.m = cc.m;
     ri.i = i;
@@ -1317,7 +1317,7 @@ __device__ __forceinline__ void lu8_solve(const float (&K)[kS8][kS8], const floa
 // K[q][p] = A[N_p][N_q] for the entries of rows N_pa and N_pb (columns pa, pb
 // of K), eight entries of each row per batch
 template <int PA>
-__device__ __forceinline__ void gather8_pair(const int32_t* __restrict__ ci, const double* __restrict__ va,
+__device__ __forceinline__ void gather8_pair(gptr<const int32_t> __restrict__ ci, gptr<const double> __restrict__ va,
                                              const int (&N)[kS8], const int (&e0)[kS8], const int (&e1)[kS8],
                                              double (&K)[kS8][kS8]) {
   constexpr int PB = PA + 1;
@@ -1380,11 +1380,11 @@ __global__ __launch_bounds__(NT) void k_rows8(Work w) {
       if (g >= gc && g < cend && cc.live) cc.row(w, g, &t, &i, &off, &s);
       gc = cend;
       if (s > kS8) continue;  // not this thread's row, or another solver's
-      const MatDesc& d = cc.md;
+      const GDesc& d = cc.md;
       MatStatus* st = &w.st[cc.m];
-      const int32_t* __restrict__ rp = d.rp;
-      const int32_t* __restrict__ ci = d.ci;
-      const double* __restrict__ va = d.va;
+      const gptr<const int32_t> __restrict__ rp = d.rp;
+      const gptr<const int32_t> __restrict__ ci = d.ci;
+      const gptr<const double> __restrict__ va = d.va;
       d.Rrp[g - cc.rbase_m] = off;
 
       // N(i) from the slot; unused entries INT32_MAX
@@ -1615,7 +1615,7 @@ __device__ __forceinline__ void mf_lu_solve(const float* K, int lda, int S, floa
 // Returns true with the solution in z[0..s) when the row converged.
 // N: sorted neighbourhood (LDS); K: LDS buffer of (kMfmaMax+1)*kMfmaMax
 // floats; f, z, r: LDS FP64 vectors of kMfmaMax.
-__device__ __forceinline__ bool mixed_big_row(const MatDesc& d, int i, const int* N, int s, float* K, double* f, double* z,
+__device__ __forceinline__ bool mixed_big_row(const GDesc& d, int i, const int* N, int s, float* K, double* f, double* z,
                               double* r, double* shv, int* s_flag, int* it_out) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
@@ -1803,7 +1803,7 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
       if (big != (pass == 1)) continue;
       MatStatus* st = &w.st[ri.m];
       if (!matrix_live(*st)) continue;
-      const MatDesc& d = w.desc[ri.m];
+      const GDesc d = gview(w.desc[ri.m]);
       const int i = ri.i;
       if (tid == 0) d.Rrp[ri.r] = ri.off;
       int* N;
@@ -1963,7 +1963,7 @@ __global__ __launch_bounds__(256) void k_project(Work w) {
       if (g >= gc && g < cend && cc.live && cc.md.B) {
         int t, i, off, sz;
         cc.row(w, g, &t, &i, &off, &sz);
-        const MatDesc& d = cc.md;
+        const GDesc& d = cc.md;
         const double bi = d.B[i];
         const int64_t f0 = cc.fine0;
         const int e1 = off + sz + 1;
@@ -2008,7 +2008,7 @@ __global__ __launch_bounds__(256) void k_project(Work w) {
       if (!cc.live || !cc.md.B) continue;
       int t, i, off, sz;
       cc.row(w, g, &t, &i, &off, &sz);
-      const MatDesc& d = cc.md;
+      const GDesc& d = cc.md;
       const double bi = d.B[i];
       for (int e = off + lane; e <= off + sz; e += LPR) {
         const int j = d.Rci[e];
@@ -2021,7 +2021,7 @@ __global__ __launch_bounds__(256) void k_project(Work w) {
   // uncovered F-points: one global atomic per workgroup and matrix
   __shared__ int s_unc;
   for (int m = 0; m < w.nmat; ++m) {
-    const MatDesc& d = w.desc[m];
+    const GDesc d = gview(w.desc[m]);
     if (!d.B || !matrix_live(w.st[m])) continue;  // uniform
     if (tid == 0) s_unc = 0;
     __syncthreads();
