@@ -382,7 +382,7 @@ int enqueue_numeric(clair_ctx* c, Batch& b, hipStream_t s, bool timing, const Co
     // bin B: the smallest block bound that holds the largest block seen (rows
     // beyond it go to the workgroup solver, so any bound is correct)
     const int bg = c->binB_max <= 16 ? 16 : 32;
-    const int bsm = c->binB_max <= 16 ? 16 : (c->binB_max <= 24 ? 24 : 32);
+    const int bsm = c->binB_max <= 16 ? 16 : c->binB_max <= 20 ? 20 : c->binB_max <= 24 ? 24 : 32;
     HIPCHK(launch_numeric(b.w, 1, bg, bsm, 128, c->cus, s));
     if (capture_check(c->capturing, s, "k_numeric32", __LINE__)) return CLAIR_ERR_HIP;
     timing_mark(c, timing, s, "numeric32");

@@ -3,25 +3,30 @@
 // Stages (one launch each, over all matrices of a batch):
 //   k_count      symbolic pass per chunk of fine points: the C-points of the
 //                chunk, the neighbourhood N(i) of each (one thread per row,
-//                up to 8 points in registers) kept in a per-row slot, the
-//                chunk-local prefix of |N(i)|+1; clears the projection
-//                accumulators of the chunk.  Larger rows are left unsized.
-//   k_count_big  the chunks with unsized rows: one thread per row with up to
-//                32 points in registers (slot of bin A or B), larger rows by
-//                a workgroup-wide search (queued for the workgroup solver).
+//                up to 8 points in registers, then up to 32 for the rows that
+//                overflowed) kept in a per-row slot, the chunk-local prefix of
+//                |N(i)|+1; clears the projection accumulators of the chunk.
+//                Rows of more than 32 points are queued, unsized.
+//   k_count_big  one workgroup per queued row: a workgroup-wide search sizes
+//                it (queued for the workgroup solver); the last row of a chunk
+//                to be sized redoes the chunk's prefix.
 //   k_scan       one workgroup: chunk bases -> global row numbers, R offsets,
 //                n_c and nnz(R) per matrix, bin sizes, capacity check,
 //                R.row_ptr[n_c].
 //   k_numeric    persistent over the rows in grid order (each XCD a contiguous
 //                slice), G lanes per row with |N| <= G (bin A, G = GA), or with
 //                GA < |N| <= 32 (bin B, G = 16 or 32): gather of the local
-//                block into LDS, FP32 LU and FP64 iterative refinement of
-//                (A[N,N])^T z = -A[i,N]^T, R row write, projection sums.  Rows
-//                whose FP32 factorisation is not trusted are queued for k_rows_wg.
+//                block into LDS, FP32 inverse (Gauss-Jordan) and FP64
+//                iterative refinement of (A[N,N])^T z = -A[i,N]^T, R row
+//                write, projection sums.  Rows whose FP32 factorisation is not
+//                trusted are queued for k_rows_wg.
 //                k_quad8 (4 lanes per row) and k_rows8 (one thread per row)
 //                are the other bin-A solvers.
-//   k_rows_wg    persistent, one workgroup per queued row: FP64 LU with partial
-//                pivoting (block in LDS, or in global scratch when large).
+//   k_rows_wg    persistent, one workgroup per queued row: for 33..128 points
+//                an FP32 blocked LU with matrix-core trailing updates and FP64
+//                refinement; otherwise, or when that does not converge, FP64 LU
+//                with partial pivoting (block in LDS, or in global scratch when
+//                large).
 //   k_project    persistent, one thread per row:
 //                z_ij -= B_i (sum_k z_kj B_k - B_j) / sum_k B_k^2 per F-entry;
 //                counts F-points no row reaches.
@@ -629,7 +634,7 @@ struct NumGroupBuf {
   double K[SM * (SM + 1)];  // FP64 block, row q = row q of (A[N,N])^T, stride SM+1
   double f[SM];             // -A[i,N]
   double z[SM];             // refinement broadcast
-  float U[G == 8 ? 1 : SM * SM];  // pivot rows (LDS broadcast for G > 8)
+  float y[SM];              // right-hand side of a correction, FP32
   int nb[G];                // sorted N(i), INT32_MAX beyond |N|
 };
 
@@ -702,22 +707,18 @@ __device__ __forceinline__ int group_ori(int v) {
   return v;
 }
 
-// forward then backward substitution with the packed LU of this lane's row:
-// kf[k] (k < lane) = L[lane][k], kf[k] (k >= lane) = U[lane][k].  Lanes at
-// or beyond SM hold no row (kf = 0) and keep y = 0.
-template <int G, int SM>
-__device__ __forceinline__ float lu_solve(const float (&kf)[SM], float uinv, int lane, float y) {
+// y_lane = sum_p Kinv[lane][p] v_p: the group's right-hand side goes through
+// LDS once (v_p from lane p), then every lane reads all of it (broadcast
+// reads, no dependence between the steps).  kf holds this lane's row of the
+// FP32 inverse; lanes at or beyond SM hold no row.
+template <int SM>
+__device__ __forceinline__ float inv_apply(const float (&kf)[SM], float* ybuf, bool rowl, int lane, float v) {
+  if (rowl) ybuf[lane] = v;
+  wave_sync();
+  float y = 0.f;
 #pragma unroll
-  for (int k = 0; k < SM; ++k) {
-    const float yk = gbf<G>(y, k);
-    if (lane > k) y = fmaf(-kf[k], yk, y);
-  }
-#pragma unroll
-  for (int k = SM - 1; k >= 0; --k) {
-    if (lane == k) y *= uinv;
-    const float zk = gbf<G>(y, k);
-    if (lane < k) y = fmaf(-kf[k], zk, y);
-  }
+  for (int p = 0; p < SM; ++p) y = fmaf(kf[p], ybuf[p], y);
+  wave_sync();  // the buffer is reused by the next call
   return y;
 }
 
@@ -868,7 +869,7 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
       nx_f1 = d.rp[nx_i + 1];
     }
 
-    // ---- FP32 LU of the row-scaled block ----
+    // ---- FP32 inverse of the row-scaled block ----
     float amax = 0.f;
     double knorm = 0.0;
 #pragma unroll
@@ -885,43 +886,29 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
     float kf[SM];
 #pragma unroll
     for (int p = 0; p < SM; ++p) kf[p] = rowl ? (float)(gb.K[lane * LD + p] * scale) : 0.f;
-    float uinv = 1.f;
     int bad = !(amax > 0.f) || !(amax < 3.0e38f);
+    // Gauss-Jordan in place, no pivoting: step k scales pivot row k and
+    // clears column k in every other row; column k then holds the inverse's
+    // column k.  The pivots are those of the LU factorisation, so the same
+    // tiny-pivot test applies.  Each lane holds one row; the pivot row reaches
+    // the group by ds_swizzle.  One update serves every lane: the pivot lane
+    // subtracts (1 - 1/pivot) times its own row, which scales it by 1/pivot.
 #pragma unroll
     for (int k = 0; k < SM; ++k) {
-      float piv, pinv;
-      if constexpr (G == 8) {
-        // eight lanes: the pivot row by ds_swizzle broadcasts
-        piv = gbf<G>(kf[k], k);
-        pinv = __builtin_amdgcn_rcpf(piv);
-        if (lane == k) uinv = pinv;
-        bad |= !(fabsf(piv) >= 0x1p-24f);
-        const float l = kf[k] * pinv;
-        if (lane > k) kf[k] = l;
+      float u[SM];
 #pragma unroll
-        for (int p = k + 1; p < SM; ++p) {
-          const float ukp = gbf<G>(kf[p], k);
-          if (lane > k) kf[p] = fmaf(-l, ukp, kf[p]);
-        }
-      } else {
-        if (lane == k) {
+      for (int p = 0; p < SM; ++p) u[p] = gbf<G>(kf[p], k);
+      // FP32 factors only precondition the FP64 refinement: the hardware
+      // reciprocal (1 ulp) is accurate enough
+      const float pinv = __builtin_amdgcn_rcpf(u[k]);
+      bad |= !(fabsf(u[k]) >= 0x1p-24f);
+      const bool pl = lane == k;
+      const float lk = kf[k] * pinv;
+      const float l = pl ? 1.f - pinv : lk;
 #pragma unroll
-          for (int p = k; p < SM; ++p) gb.U[k * SM + p] = kf[p];
-        }
-        wave_sync();
-        piv = gb.U[k * SM + k];
-        // FP32 factors only precondition the FP64 refinement: the hardware
-        // reciprocal (1 ulp) is accurate enough
-        pinv = __builtin_amdgcn_rcpf(piv);
-        if (lane == k) uinv = pinv;
-        bad |= !(fabsf(piv) >= 0x1p-24f);
-        if (lane > k && rowl) {
-          const float l = kf[k] * pinv;
-          kf[k] = l;
-#pragma unroll
-          for (int p = k + 1; p < SM; ++p) kf[p] = fmaf(-l, gb.U[k * SM + p], kf[p]);
-        }
-      }
+      for (int p = 0; p < SM; ++p)
+        if (p != k) kf[p] = fmaf(-l, u[p], kf[p]);
+      kf[k] = pl ? pinv : -lk;
     }
     bad = group_ori<G>(bad);
 
@@ -932,7 +919,7 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
     int it = 0;
     bool conv = false;
     if (!bad) {
-      z = (double)lu_solve<G, SM>(kf, uinv, lane, (float)(fq * scale));
+      z = (double)inv_apply<SM>(kf, gb.y, rowl, lane, (float)(fq * scale));
       for (it = 1; it <= kRefineMax; ++it) {
         if (rowl) gb.z[lane] = z;
         wave_sync();
@@ -948,7 +935,7 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
           const double zn = group_maxd<G>(fabs(z));
           if (rn <= 0x1p-47 * (knorm * zn + fnorm)) { conv = true; break; }
         }
-        const float dz = lu_solve<G, SM>(kf, uinv, lane, (float)(r * scale));
+        const float dz = inv_apply<SM>(kf, gb.y, rowl, lane, (float)(r * scale));
         z += (double)dz;
         wave_sync();
       }
@@ -2083,7 +2070,7 @@ hipError_t launch_scan(const Work& w, hipStream_t s) {
 
 // persistent grid: as many workgroups as fit on the device at once.
 // which = 0: bin A with `group` lanes per row; which = 1: bin B with blocks of
-// up to sm points (16: 16 lanes per row; 24 or 32: 32 lanes per row).
+// up to sm points (16: 16 lanes per row; 20, 24 or 32: 32 lanes per row).
 hipError_t launch_numeric(const Work& w, int which, int group, int sm, int wg_threads, int cus, hipStream_t s) {
 #define CLAIR_NUM(GG, NTT, SMM)                                                                         \
   if (group == GG && wg_threads == NTT && sm == SMM) {                                                  \
@@ -2103,6 +2090,7 @@ hipError_t launch_numeric(const Work& w, int which, int group, int sm, int wg_th
   CLAIR_NUM(32, 256, 32)
   CLAIR_NUM(32, 128, 32)
   CLAIR_NUM(32, 64, 32)
+  CLAIR_NUM(32, 128, 20)
   CLAIR_NUM(32, 128, 24)
 #undef CLAIR_NUM
   return hipErrorInvalidValue;
