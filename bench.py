@@ -155,8 +155,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the multi-GPU "
-              "sharding is described in DESIGN.md and is not run.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); sharding the "
+              "setup over several GPUs is not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch

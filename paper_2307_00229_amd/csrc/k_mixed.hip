@@ -1576,34 +1576,62 @@ __device__ __forceinline__ double block_maxd(double v, double* shv) {
   return r;
 }
 
-// y <- K^{-1} y for the packed LU (unit lower L, upper U) of the S x S block in
-// LDS (stride lda).  Wavefront 0 only: lane l holds rows l and l + 64; the
-// solved entry of each step goes to all lanes by readlane.
-__device__ __forceinline__ void mf_lu_solve(const float* K, int lda, int S, float& y0, float& y1) {
-  const int l = threadIdx.x & 63;
-  const int r0 = l, r1 = l + 64;
-  for (int k = 0; k < S; ++k) {  // forward, unit lower
-    const float yk = (k < 64) ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y0), k))
-                              : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y1), k - 64));
-    if (r0 > k && r0 < S) y0 = fmaf(-K[r0 * lda + k], yk, y0);
-    if (r1 > k && r1 < S) y1 = fmaf(-K[r1 * lda + k], yk, y1);
+// y <- K^{-1} y for the packed LU (unit lower L below the diagonal, U on and
+// above it) of the S x S block in LDS (stride lda, S a multiple of 32); y in
+// LDS.  All threads call.  Blocked by 32: wavefront 0 solves a diagonal block
+// (unrolled, the solved entry of each step to all lanes by v_readlane), then
+// every thread updates the remaining entries with that block's column strip,
+// one mat-vec row per thread.
+__device__ __forceinline__ void mf_lu_solve(const float* K, int lda, int S, float* y) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  for (int o = 0; o < S; o += 32) {  // forward, unit lower
+    if (tid < 64) {
+      float v = (lane < 32) ? y[o + lane] : 0.f;
+#pragma unroll
+      for (int k = 0; k < 32; ++k) {
+        const float yk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+        if (lane > k && lane < 32) v = fmaf(-K[(o + lane) * lda + o + k], yk, v);
+      }
+      if (lane < 32) y[o + lane] = v;
+    }
+    __syncthreads();
+    for (int q = o + 32 + tid; q < S; q += kWT) {
+      float acc = y[q];
+#pragma unroll 8
+      for (int k = 0; k < 32; ++k) acc = fmaf(-K[q * lda + o + k], y[o + k], acc);
+      y[q] = acc;
+    }
+    __syncthreads();
   }
-  for (int k = S - 1; k >= 0; --k) {  // backward, upper
-    const float ukk = K[k * lda + k];
-    if (r0 == k) y0 = y0 / ukk;
-    if (r1 == k) y1 = y1 / ukk;
-    const float yk = (k < 64) ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y0), k))
-                              : __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y1), k - 64));
-    if (r0 < k) y0 = fmaf(-K[r0 * lda + k], yk, y0);
-    if (r1 < k && r1 < S) y1 = fmaf(-K[r1 * lda + k], yk, y1);
+  for (int o = S - 32; o >= 0; o -= 32) {  // backward, upper
+    if (tid < 64) {
+      float v = (lane < 32) ? y[o + lane] : 0.f;
+#pragma unroll
+      for (int k = 31; k >= 0; --k) {
+        if (lane == k) v = v / K[(o + k) * lda + o + k];
+        const float yk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+        if (lane < k) v = fmaf(-K[(o + lane) * lda + o + k], yk, v);
+      }
+      if (lane < 32) y[o + lane] = v;
+    }
+    __syncthreads();
+    for (int q = tid; q < o; q += kWT) {
+      float acc = y[q];
+#pragma unroll 8
+      for (int k = 0; k < 32; ++k) acc = fmaf(-K[q * lda + o + k], y[o + k], acc);
+      y[q] = acc;
+    }
+    __syncthreads();
   }
 }
 
 // Returns true with the solution in z[0..s) when the row converged.
 // N: sorted neighbourhood (LDS); K: LDS buffer of (kMfmaMax+1)*kMfmaMax
-// floats; f, z, r: LDS FP64 vectors of kMfmaMax.
+// floats; f, z, r: LDS FP64 vectors of kMfmaMax; y: LDS FP32 vector of
+// kMfmaMax.
 __device__ __forceinline__ bool mixed_big_row(const GDesc& d, int i, const int* N, int s, float* K, double* f, double* z,
-                              double* r, double* shv, int* s_flag, int* it_out) {
+                              double* r, float* y, double* shv, int* s_flag, int* it_out) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int S = (s + 31) & ~31;
@@ -1702,13 +1730,10 @@ __device__ __forceinline__ bool mixed_big_row(const GDesc& d, int i, const int* 
     for (int t = tid; t < s; t += kWT) m = fmax(m, fabs(f[t]));
     return block_maxd(m, shv);
   }();
-  if (wv == 0) {
-    float y0 = (lane < s) ? (float)(f[lane] * scale) : 0.f;
-    float y1 = (lane + 64 < s) ? (float)(f[lane + 64] * scale) : 0.f;
-    mf_lu_solve(K, lda, S, y0, y1);
-    if (lane < s) z[lane] = y0;
-    if (lane + 64 < s) z[lane + 64] = y1;
-  }
+  for (int t = tid; t < S; t += kWT) y[t] = (t < s) ? (float)(f[t] * scale) : 0.f;
+  __syncthreads();
+  mf_lu_solve(K, lda, S, y);
+  for (int t = tid; t < s; t += kWT) z[t] = y[t];
   __syncthreads();
   for (int it = 1; it <= kRefineMax; ++it) {
     // r = f - K z with the FP64 entries of A: row N_p adds -a_{N_p, N_q} z_p to r_q
@@ -1735,13 +1760,10 @@ __device__ __forceinline__ bool mixed_big_row(const GDesc& d, int i, const int* 
         return finite;
       }
     }
-    if (wv == 0) {
-      float y0 = (lane < s) ? (float)(r[lane] * scale) : 0.f;
-      float y1 = (lane + 64 < s) ? (float)(r[lane + 64] * scale) : 0.f;
-      mf_lu_solve(K, lda, S, y0, y1);
-      if (lane < s) z[lane] += (double)y0;
-      if (lane + 64 < s) z[lane + 64] += (double)y1;
-    }
+    for (int t = tid; t < S; t += kWT) y[t] = (t < s) ? (float)(r[t] * scale) : 0.f;
+    __syncthreads();
+    mf_lu_solve(K, lda, S, y);
+    for (int t = tid; t < s; t += kWT) z[t] += (double)y[t];
     __syncthreads();
   }
   return false;
@@ -1758,6 +1780,7 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
   float* sK32 = reinterpret_cast<float*>(s_blk);
   __shared__ double sf[kMaxBlock];
   __shared__ double s_z[kMfmaMax], s_r[kMfmaMax];
+  __shared__ float s_y[kMfmaMax];
   __shared__ double shv[kWT];
   __shared__ int shi[kWT];
   __shared__ int s_bad, s_mflag;
@@ -1804,7 +1827,7 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
       // blocks above 32 points: the mixed solver first
       int itm = 0;
       const bool mixed_ok = s > 32 && s <= kMfmaMax &&
-                            mixed_big_row(d, i, N, s, sK32, sf, s_z, s_r, shv, &s_mflag, &itm);
+                            mixed_big_row(d, i, N, s, sK32, sf, s_z, s_r, s_y, shv, &s_mflag, &itm);
       if (mixed_ok) {
         for (int t = tid; t < s; t += kWT) sf[t] = s_z[t];
         if (tid == 0 && itm > __hip_atomic_load(&st->refine_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
