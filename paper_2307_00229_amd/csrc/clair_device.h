@@ -217,14 +217,14 @@ struct RegSet {
   }
 };
 
-// the F-neighbours of u (edges with a stored nonzero), added at level L;
-// entries are read eight at a time (one batch for most stencil rows)
+// the F-neighbours of u (edges with a stored nonzero; row u of A is entries
+// [e0, e1)), added at level L; entries are read eight at a time (one batch
+// for most stencil rows)
 template <int SM>
-__device__ __forceinline__ void reg_expand(RegSet<SM>& S, int n, int u, int L, gptr<const int32_t> __restrict__ rp,
+__device__ __forceinline__ void reg_expand(RegSet<SM>& S, int n, int u, int e0, int e1, int L,
                                            gptr<const int32_t> __restrict__ ci, gptr<const double> __restrict__ va,
                                            gptr<const int8_t> __restrict__ cf) {
-  const int e1 = rp[u + 1];
-  for (int e = rp[u]; e < e1 && !S.ovf; e += 8) {
+  for (int e = e0; e < e1 && !S.ovf; e += 8) {
     int k[8];
     double v[8];
 #pragma unroll
@@ -248,22 +248,30 @@ __device__ __forceinline__ int reg_bfs(RegSet<SM>& S, int n, int i, int ell, gpt
                                        gptr<const int32_t> __restrict__ ci, gptr<const double> __restrict__ va,
                                        gptr<const int8_t> __restrict__ cf) {
   S.clear();
-  reg_expand(S, n, i, 1, rp, ci, va, cf);
+  reg_expand(S, n, i, rp[i], rp[i + 1], 1, ci, va, cf);
   for (int L = 2; L <= ell && !S.ovf; ++L) {
     // expand the points found at level L-1 in ascending order (from a
-    // snapshot: inserts move entries); only compile-time register indices
-    int fv[SM], fl[SM];
+    // snapshot: inserts move entries); only compile-time register indices.
+    // The row bounds of the whole level are loaded first, all in flight
+    // together, so each expansion waits for its entries only.
+    int fv[SM], fl[SM], b0[SM], b1[SM];
 #pragma unroll
-    for (int j = 0; j < SM; ++j) { fv[j] = S.v[j]; fl[j] = S.lev[j]; }
+    for (int j = 0; j < SM; ++j) {
+      fv[j] = S.v[j];
+      fl[j] = S.lev[j];
+      b0[j] = 0;
+      b1[j] = 0;
+      if (fl[j] == L - 1) { b0[j] = rp[fv[j]]; b1[j] = rp[fv[j] + 1]; }
+    }
     int last = -1;
     bool any = false;
     while (!S.ovf) {
-      int u = 0x7fffffff;
+      int u = 0x7fffffff, e0 = 0, e1 = 0;
 #pragma unroll
       for (int j = 0; j < SM; ++j)
-        if (fl[j] == L - 1 && fv[j] > last && fv[j] < u) u = fv[j];
+        if (fl[j] == L - 1 && fv[j] > last && fv[j] < u) { u = fv[j]; e0 = b0[j]; e1 = b1[j]; }
       if (u == 0x7fffffff) break;
-      reg_expand(S, n, u, L, rp, ci, va, cf);
+      reg_expand(S, n, u, e0, e1, L, ci, va, cf);
       last = u;
       any = true;
     }

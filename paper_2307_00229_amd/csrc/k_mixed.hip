@@ -386,6 +386,14 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
   // one thread per C-row, neighbourhoods of up to 8 points in registers; the
   // larger ones are left unsized for k_count_big
   for (int t = tid; t < nc; t += kNT) {
+    // a row of seven or more entries (six or more neighbours) at ell >= 2
+    // nearly always reaches more than 8 points: it goes straight to the
+    // 32-point search below (either search gives the same set)
+    if (d.ell >= 2 && d.rp[s_rows[t] + 1] - d.rp[s_rows[t]] >= 7) {
+      s_size[t] = -1;
+      s_list[atomicAdd(&s_nlist, 1)] = t;
+      continue;
+    }
     RegSet<8> S;
     const int sz = reg_bfs(S, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf);
     if (sz >= 0) {
