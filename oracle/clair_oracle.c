@@ -15,7 +15,8 @@
  *   injected.  Row i of R (i a C-point) is obtained from Algorithm 1 applied to
  *   A^T (Section 3.1.3): the pattern of the row is the distance-ell
  *   F-neighbourhood N(i) of i (Algorithm 1, pattern expansion S^{m-1} T with
- *   m = ell, theta = 0, interior vertices F), the local l-AIR system is
+ *   m = ell, interior vertices F, S the classical strength matrix of A^T with
+ *   threshold theta), the local l-AIR system is
  *   (A[N,N])^T z = -A[i,N]^T (Section 2.1, eq. system), and the mode
  *   constraint R^T B_c = B on the F-points (Section 2.3, eq. global_const1;
  *   Section 3.1, eq. Qdef) is imposed by the Euclidean projection
@@ -53,8 +54,16 @@
 /* ------------------------------------------------------------------------ */
 /* Neighbourhood: the F-points reachable from C-point i by a walk of at most  */
 /* ell edges of A's graph whose interior vertices are all F-points.  An edge  */
-/* u -> v exists when u != v and a_uv is stored and nonzero (strength with    */
-/* theta = 0).  Breadth-first search, expanding F vertices only.              */
+/* u -> v exists when u != v, a_uv is stored and nonzero, and                 */
+/* |a_uv| >= theta * cmax[v] with cmax[v] = max_{w != v} |a_wv|.              */
+/* Breadth-first search, expanding F vertices only.                           */
+/*                                                                            */
+/* Why a column maximum: Algorithm 1 runs on M = A^T, whose classical         */
+/* strength matrix has S_xy != 0 when |m_xy| >= theta max_{w != x} |m_xw|,    */
+/* i.e. |a_yx| >= theta max_{w != x} |a_wx|.  A pattern entry (f, c) of       */
+/* S^{m-1} T is a chain f -> ... -> c of such entries; walking it backwards   */
+/* from c, each step from u to v uses S_vu, the test above.  theta = 0 keeps  */
+/* every stored nonzero.                                                      */
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
@@ -81,9 +90,26 @@ static int ws_push(bfs_ws* w, int32_t len, int32_t v) {
   return 0;
 }
 
+/* Is u -> v (entry e of row u) an edge of the search? */
+static int is_edge(int32_t u, int32_t e, const int32_t* ci, const double* va, double theta,
+                   const double* cmax) {
+  const int32_t v = ci[e];
+  if (v == u || va[e] == 0.0) return 0;
+  return theta == 0.0 || fabs(va[e]) >= theta * cmax[v];
+}
+
+/* cmax[v] = max over the off-diagonal entries of column v of |a_wv|. */
+static void column_max(int32_t n, const int32_t* rp, const int32_t* ci, const double* va, double* cmax) {
+  for (int32_t v = 0; v < n; ++v) cmax[v] = 0.0;
+  for (int32_t w = 0; w < n; ++w)
+    for (int32_t e = rp[w]; e < rp[w + 1]; ++e)
+      if (ci[e] != w) cmax[ci[e]] = fmax(cmax[ci[e]], fabs(va[e]));
+}
+
 /* Returns s = |N(i)| (>= 0), N(i) sorted ascending in w->list[0..s), or -1 on OOM. */
 static int32_t neighbourhood(int32_t i, int ell, const int32_t* rp, const int32_t* ci,
-                             const double* va, const int8_t* cf, bfs_ws* w) {
+                             const double* va, const int8_t* cf, double theta, const double* cmax,
+                             bfs_ws* w) {
   w->stamp++;
   w->mark[i] = w->stamp;
   int32_t len = 0;
@@ -93,7 +119,7 @@ static int32_t neighbourhood(int32_t i, int ell, const int32_t* rp, const int32_
     if (depth == 1) {
       for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
         int32_t k = ci[e];
-        if (k == i || va[e] == 0.0 || cf[k] != 0 || w->mark[k] == w->stamp) continue;
+        if (!is_edge(i, e, ci, va, theta, cmax) || cf[k] != 0 || w->mark[k] == w->stamp) continue;
         w->mark[k] = w->stamp;
         if (ws_push(w, len, k)) return -1;
         ++len;
@@ -103,7 +129,7 @@ static int32_t neighbourhood(int32_t i, int ell, const int32_t* rp, const int32_
         int32_t u = w->list[t];
         for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
           int32_t k = ci[e];
-          if (k == u || va[e] == 0.0 || cf[k] != 0 || w->mark[k] == w->stamp) continue;
+          if (!is_edge(u, e, ci, va, theta, cmax) || cf[k] != 0 || w->mark[k] == w->stamp) continue;
           w->mark[k] = w->stamp;
           if (ws_push(w, len, k)) return -1;
           ++len;
@@ -191,13 +217,19 @@ static int set_threads(int nthreads) {
 /* Number of C-points and nnz(R) = sum_i (|N(i)| + 1).  Also the per-row sizes
  * when `sizes` (length n_c) is given. */
 int orc_pattern_size(int32_t n, const int32_t* rp, const int32_t* ci, const double* va,
-                     const int8_t* cf, int32_t ell, int32_t nthreads, int32_t* n_c_out,
+                     const int8_t* cf, int32_t ell, double theta, int32_t nthreads, int32_t* n_c_out,
                      int64_t* nnz_out, int32_t* sizes) {
-  if (ell < 1 || check_csr(n, rp, ci)) return ORC_ERR_INVALID;
+  if (ell < 1 || !(theta >= 0.0 && theta <= 1.0) || check_csr(n, rp, ci)) return ORC_ERR_INVALID;
+  double* cmax = NULL;
+  if (theta > 0.0) {
+    cmax = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!cmax) return ORC_ERR_NOMEM;
+    column_max(n, rp, ci, va, cmax);
+  }
   int32_t n_c = 0;
   for (int32_t j = 0; j < n; ++j) n_c += (cf[j] != 0);
   int32_t* clist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_c > 0 ? n_c : 1));
-  if (!clist) return ORC_ERR_NOMEM;
+  if (!clist) { free(cmax); return ORC_ERR_NOMEM; }
   for (int32_t j = 0, r = 0; j < n; ++j) if (cf[j]) clist[r++] = j;
   int64_t total = 0;
   int err = 0;
@@ -213,7 +245,7 @@ int orc_pattern_size(int32_t n, const int32_t* rp, const int32_t* ci, const doub
     } else {
 #pragma omp for schedule(static)
       for (int32_t r = 0; r < n_c; ++r) {
-        int32_t s = neighbourhood(clist[r], ell, rp, ci, va, cf, &w);
+        int32_t s = neighbourhood(clist[r], ell, rp, ci, va, cf, theta, cmax, &w);
         if (s < 0) {
 #pragma omp atomic write
           err = 1;
@@ -227,6 +259,7 @@ int orc_pattern_size(int32_t n, const int32_t* rp, const int32_t* ci, const doub
     free(w.list);
   }
   free(clist);
+  free(cmax);
   if (err) return ORC_ERR_NOMEM;
   *n_c_out = n_c;
   *nnz_out = total;
@@ -240,18 +273,24 @@ int orc_pattern_size(int32_t n, const int32_t* rp, const int32_t* ci, const doub
  * bad_row = fine index of the first C-row whose local block is singular.
  */
 int orc_build_R(int32_t n, const int32_t* rp, const int32_t* ci, const double* va, const int8_t* cf,
-                const double* B, int32_t ell, int32_t nthreads, int32_t* R_rp, int32_t* R_ci,
+                const double* B, int32_t ell, double theta, int32_t nthreads, int32_t* R_rp, int32_t* R_ci,
                 double* R_va, int64_t cap, int64_t* n_uncovered, int32_t* bad_row) {
-  if (ell < 1 || check_csr(n, rp, ci)) return ORC_ERR_INVALID;
+  if (ell < 1 || !(theta >= 0.0 && theta <= 1.0) || check_csr(n, rp, ci)) return ORC_ERR_INVALID;
   int32_t n_c = 0;
   int64_t nnz = 0;
   for (int32_t j = 0; j < n; ++j) n_c += (cf[j] != 0);
   int32_t* sizes = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_c > 0 ? n_c : 1));
   int32_t* clist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_c > 0 ? n_c : 1));
   if (!sizes || !clist) { free(sizes); free(clist); return ORC_ERR_NOMEM; }
-  int rc = orc_pattern_size(n, rp, ci, va, cf, ell, nthreads, &n_c, &nnz, sizes);
+  int rc = orc_pattern_size(n, rp, ci, va, cf, ell, theta, nthreads, &n_c, &nnz, sizes);
   if (rc) { free(sizes); free(clist); return rc; }
   if (nnz > cap) { free(sizes); free(clist); return ORC_ERR_CAPACITY; }
+  double* cmax = NULL;
+  if (theta > 0.0) {
+    cmax = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    if (!cmax) { free(sizes); free(clist); return ORC_ERR_NOMEM; }
+    column_max(n, rp, ci, va, cmax);
+  }
   for (int32_t j = 0, r = 0; j < n; ++j) if (cf[j]) clist[r++] = j;
   R_rp[0] = 0;
   for (int32_t r = 0; r < n_c; ++r) R_rp[r + 1] = R_rp[r] + sizes[r] + 1;
@@ -275,7 +314,7 @@ int orc_build_R(int32_t n, const int32_t* rp, const int32_t* ci, const double* v
 #pragma omp for schedule(dynamic, 64)
       for (int32_t r = 0; r < n_c; ++r) {
         int32_t i = clist[r];
-        int32_t s = neighbourhood(i, ell, rp, ci, va, cf, &w);
+        int32_t s = neighbourhood(i, ell, rp, ci, va, cf, theta, cmax, &w);
         if (s < 0) {
 #pragma omp atomic write
           err = 1;
@@ -328,6 +367,7 @@ int orc_build_R(int32_t n, const int32_t* rp, const int32_t* ci, const double* v
     free(K); free(f); free(w.mark); free(w.list);
   }
   free(sizes);
+  free(cmax);
   if (err) { free(clist); return ORC_ERR_NOMEM; }
   if (bad_row) *bad_row = first_bad;
 

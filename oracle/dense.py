@@ -4,11 +4,13 @@ Everything here is formulated with dense NumPy arrays so that it is an
 independent check of the C oracle:
 
 * ``neighbourhoods``: the distance-ell F-neighbourhood of every C-point by
-  boolean reachability (no queue, no visited marks).  N_1(i) is the F-part of
-  row i's off-diagonal nonzeros (theta = 0 strength, the base pattern
-  T = [S_fc, I] of Algorithm 1 applied to A^T); each further hop multiplies the
-  current F-set by the adjacency matrix and keeps only F-points, which is the
-  pattern expansion S^{m-1} T with F-point interior vertices.
+  boolean reachability (no queue, no visited marks), straight from the
+  pattern expansion S^{m-1} T of Algorithm 1 applied to M = A^T.  S is the
+  classical strength matrix of M: S_xy = 1 for y != x when m_xy != 0 and
+  |m_xy| >= theta max_{w != x} |m_xw| (theta = 0: every stored nonzero);
+  T = S_fc.  The F-points f with T_fc = 1 form the first hop of column c; each
+  further hop adds the F-points x with S_xy = 1 for some y already reached
+  (F-point interior vertices).
 * ``lair_rows``: per-row local l-AIR solves (Section 2.1, eq. system) with
   ``numpy.linalg.solve``; Remark 1 says the unconstrained algorithm returns
   exactly these rows.
@@ -28,23 +30,32 @@ def to_dense(n, row_ptr, col_idx, val):
     return A
 
 
-def neighbourhoods(A: np.ndarray, cf: np.ndarray, ell: int):
+def strength_transposed(A: np.ndarray, theta: float = 0.0) -> np.ndarray:
+    """Classical strength matrix S of M = A^T (boolean, diagonal excluded)."""
+    M = A.T
+    n = M.shape[0]
+    off = ~np.eye(n, dtype=bool)
+    mag = np.where(off, np.abs(M), 0.0)
+    rowmax = mag.max(axis=1) if n else np.zeros(0)
+    return off & (M != 0) & (mag >= theta * rowmax[:, None])
+
+
+def neighbourhoods(A: np.ndarray, cf: np.ndarray, ell: int, theta: float = 0.0):
     """dict C-point -> sorted array of its distance-ell F-neighbourhood."""
-    n = A.shape[0]
-    adj = (A != 0) & ~np.eye(n, dtype=bool)
+    S = strength_transposed(A, theta).astype(np.int64)
     F = cf == 0
     out = {}
-    for i in np.nonzero(cf != 0)[0]:
-        reach = adj[i] & F
+    for c in np.nonzero(cf != 0)[0]:
+        reach = (S[:, c] > 0) & F  # T = S_fc, column c
         for _ in range(ell - 1):
-            reach = reach | ((reach.astype(np.int64) @ adj.astype(np.int64)) > 0) & F
-        out[int(i)] = np.nonzero(reach)[0]
+            reach = reach | ((S @ reach.astype(np.int64)) > 0) & F
+        out[int(c)] = np.nonzero(reach)[0]
     return out
 
 
-def lair_rows(A: np.ndarray, cf: np.ndarray, ell: int):
+def lair_rows(A: np.ndarray, cf: np.ndarray, ell: int, theta: float = 0.0):
     """Unconstrained rows: dict C-point -> (N, z) with (A[N,N])^T z = -A[i,N]^T."""
-    nb = neighbourhoods(A, cf, ell)
+    nb = neighbourhoods(A, cf, ell, theta)
     rows = {}
     for i, N in nb.items():
         if len(N) == 0:

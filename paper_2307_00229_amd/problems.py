@@ -53,6 +53,7 @@ class Problem:
     B: Optional[np.ndarray]  # float64 [n] or None (unconstrained)
     ell: int
     meta: dict = dataclasses.field(default_factory=dict)
+    theta: float = 0.0  # strength threshold of the pattern (0: every stored nonzero)
 
     @property
     def nnz(self) -> int:

@@ -1,0 +1,159 @@
+"""Oracle pins for the strength-filtered pattern (CPU only).
+
+Algorithm 1 (Section 3.1.3) takes the pattern of W from the classical strength
+matrix S of the matrix it is applied to; R is Algorithm 1 on A^T, and the
+paper's experiments use thresholds theta = 0.05 to 0.5 (Section 4).  The C
+oracle walks A's rows from each C-point and tests each step u -> v against the
+largest off-diagonal magnitude of column v (the transposition worked out in
+its header).  These tests pin that walk against:
+
+* a hand-worked four-point example where a row-based reading would give a
+  different pattern;
+* ``dense.neighbourhoods``: S of A^T formed literally (row maxima of A^T) and
+  the expansion S^{m-1} T by boolean matrix products;
+* theta = 0 equal to the plain stored-nonzero graph of A, written out here;
+* monotonicity in theta, and the theta = 1, ell = 1 pattern written out;
+* unconstrained rows equal to dense solves, and the literal Algorithm 1 equal
+  to the closed form, on strength-filtered patterns.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dense, literal
+from paper_2307_00229_amd import problems as P
+
+
+def _csr(A):
+    n = A.shape[0]
+    rp, ci, va = [0], [], []
+    for r in range(n):
+        cols = np.nonzero(A[r])[0]
+        ci.extend(cols.tolist())
+        va.extend(A[r, cols].tolist())
+        rp.append(len(ci))
+    return np.asarray(rp, np.int32), np.asarray(ci, np.int32), np.asarray(va, np.float64)
+
+
+def _patterns(p, theta, B=None):
+    o = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, B, p.ell, theta=theta)
+    C = np.nonzero(p.cf)[0]
+    pats = {}
+    for r, i in enumerate(C):
+        cols = o["col_idx"][o["row_ptr"][r]:o["row_ptr"][r + 1]]
+        pats[int(i)] = [int(c) for c in cols if c != i]
+    return pats, o
+
+
+def test_hand_example_uses_column_maxima():
+    # points 0 (C), 1, 2, 3 (F); ell = 1, theta = 0.5
+    #   a_01 = -1, a_02 = -0.1, a_31 = -5
+    # column maxima (off-diagonal): cmax_1 = 5, cmax_2 = 0.1
+    #   0 -> 1: |a_01| = 1   >= 0.5 * 5   = 2.5  fails
+    #   0 -> 2: |a_02| = 0.1 >= 0.5 * 0.1 = 0.05 holds
+    # so N(0) = {2}.  (Measuring against row 0's own maximum, 1, would keep 1
+    # and drop 2 instead.)
+    A = np.array([[4.0, -1.0, -0.1, 0.0],
+                  [0.0, 4.0, 0.0, 0.0],
+                  [0.0, 0.0, 4.0, 0.0],
+                  [0.0, -5.0, 0.0, 9.0]])
+    rp, ci, va = _csr(A)
+    p = P.Problem("hand4", 4, rp, ci, va, np.array([1, 0, 0, 0], np.int8), None, 1)
+    pats, _ = _patterns(p, 0.5)
+    assert pats == {0: [2]}
+    assert dense.neighbourhoods(A, p.cf, 1, 0.5) [0].tolist() == [2]
+    # theta = 0: both neighbours
+    pats0, _ = _patterns(p, 0.0)
+    assert pats0 == {0: [1, 2]}
+
+
+CASES = [
+    lambda ell: P.random_sparse(40, 0.08, 21, ell=ell, B=None),
+    lambda ell: P.random_sparse(36, 0.12, 22, ell=ell, nonsym_pattern=False, B=None),
+    lambda ell: P.small_2d(9, stencil=9, eps=1e-3, angle=2.2, k=3, ell=ell),
+    lambda ell: P.small_2d(10, stencil=5, eps=0.02, angle=0.4, ell=ell),
+    lambda ell: P.small_3d(5, eps=0.05, b=(-1.0, 0.2, 0.7), ell=ell),
+]
+
+
+@pytest.mark.parametrize("theta", [0.05, 0.25, 0.5, 1.0])
+@pytest.mark.parametrize("ell", [1, 2, 3])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_pattern_equals_literal_strength_expansion(case, ell, theta):
+    p = CASES[case](ell)
+    A = dense.to_dense(p.n, p.row_ptr, p.col_idx, p.val)
+    pats, _ = _patterns(p, theta)
+    nb = dense.neighbourhoods(A, p.cf, ell, theta)
+    assert pats == {i: v.tolist() for i, v in nb.items()}
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_theta_zero_is_the_stored_nonzero_graph(case):
+    p = CASES[case](2)
+    A = dense.to_dense(p.n, p.row_ptr, p.col_idx, p.val)
+    n = p.n
+    adj = (A != 0) & ~np.eye(n, dtype=bool)  # u -> v when a_uv != 0
+    F = p.cf == 0
+    pats, _ = _patterns(p, 0.0)
+    for i in np.nonzero(p.cf)[0]:
+        reach = adj[i] & F
+        reach = reach | ((reach.astype(np.int64) @ adj.astype(np.int64)) > 0) & F
+        assert pats[int(i)] == np.nonzero(reach)[0].tolist()
+    nb = dense.neighbourhoods(A, p.cf, 2, 0.0)
+    assert pats == {i: v.tolist() for i, v in nb.items()}
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_patterns_shrink_as_theta_grows(case):
+    p = CASES[case](3)
+    prev = None
+    for theta in [0.0, 0.1, 0.3, 0.6, 1.0]:
+        pats, _ = _patterns(p, theta)
+        if prev is not None:
+            for i, v in pats.items():
+                assert set(v) <= set(prev[i])
+        prev = pats
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_theta_one_distance_one_keeps_the_column_maxima(case):
+    p = CASES[case](1)
+    A = dense.to_dense(p.n, p.row_ptr, p.col_idx, p.val)
+    off = np.abs(A) * (1 - np.eye(p.n))
+    cmax = off.max(axis=0)
+    pats, _ = _patterns(p, 1.0)
+    for i in np.nonzero(p.cf)[0]:
+        want = [v for v in range(p.n) if v != i and p.cf[v] == 0 and A[i, v] != 0 and abs(A[i, v]) >= cmax[v]]
+        assert pats[int(i)] == want
+
+
+@pytest.mark.parametrize("theta", [0.05, 0.5])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_strength_rows_equal_dense_solves(case, theta):
+    p = CASES[case](2)
+    A = dense.to_dense(p.n, p.row_ptr, p.col_idx, p.val)
+    rows = dense.lair_rows(A, p.cf, 2, theta)
+    _, o = _patterns(p, theta)
+    R = dense.csr_to_dense_R(o["row_ptr"], o["col_idx"], o["val"], p.n)
+    Rd = dense.rows_to_dense_R(rows, p.cf, p.n)
+    scale = np.maximum(np.max(np.abs(Rd), axis=1, keepdims=True), 1e-300)
+    assert np.max(np.abs(R - Rd) / scale) <= 1e-12
+
+
+@pytest.mark.parametrize("case", [0, 2, 4])
+def test_literal_algorithm1_with_strength_matches_closed_form(case):
+    p = CASES[case](2)
+    rng = np.random.default_rng(100 + case)
+    B = rng.uniform(0.5, 1.5, p.n)
+    A = dense.to_dense(p.n, p.row_ptr, p.col_idx, p.val)
+    _, o = _patterns(p, 0.25, B=B)
+    R = dense.csr_to_dense_R(o["row_ptr"], o["col_idx"], o["val"], p.n)
+    R1 = literal.algorithm1_R(A, p.cf, B, 2, k=1, theta=0.25)
+    assert np.max(np.abs(R1 - R)) <= 1e-12 * np.max(np.abs(R))
+
+
+def test_invalid_theta_rejected():
+    p = CASES[0](2)
+    for bad in (-0.1, 1.5, float("nan")):
+        with pytest.raises(oracle.OracleError):
+            oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, None, 2, theta=bad)
