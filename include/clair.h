@@ -185,6 +185,23 @@ int clair_ctx_stage_times(clair_ctx_t* ctx, const char** names, float* ms, int32
  */
 int clair_ctx_set_tuning(clair_ctx_t* ctx, int32_t group, int32_t wg_threads, int32_t chunk);
 int clair_ctx_get_tuning(clair_ctx_t* ctx, int32_t* group, int32_t* wg_threads, int32_t* chunk);
+
+/*
+ * Strength threshold theta of the neighbourhood search.  Algorithm 1
+ * (Section 3.1.3) grows the pattern from a classical strength-of-connection
+ * matrix S; Section 4 uses thresholds between 0.05 and 0.5.  R is Algorithm 1
+ * applied to A^T, so the walk from C-point i takes the step u -> v when u != v,
+ * a_uv is stored and nonzero, and |a_uv| >= theta * max_{w != v} |a_wv| (in
+ * A^T, v depends strongly on u).  theta = 0 (the default) keeps every stored
+ * nonzero.  The values of A are compared in FP64.
+ * The setting applies to later calls on ctx (both precisions), to graphs
+ * captured and to plans created after it; a plan keeps the pattern of its
+ * creation (rows of more than 32 points are searched again at execute, and a
+ * row whose pattern the new values change is reported as CLAIR_ERR_INVALID).
+ * theta outside [0, 1], or NaN, returns CLAIR_ERR_INVALID and changes nothing.
+ */
+int clair_ctx_set_strength(clair_ctx_t* ctx, double theta);
+int clair_ctx_get_strength(clair_ctx_t* ctx, double* theta);
 int clair_autotune(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf_marker,
                    const double* const* B, const int32_t* ell, clair_csr_out_t* R_out, void* stream,
                    int32_t reps);

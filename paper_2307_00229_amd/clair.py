@@ -29,6 +29,7 @@ CLAIR_MAX_BLOCK = 1024
 EXPORTED = [
     "clair_ctx_create", "clair_ctx_destroy", "clair_build_R", "clair_build_R_ex", "clair_build_R_batched",
     "clair_ctx_info", "clair_size_R", "clair_ctx_stage_times", "clair_ctx_set_tuning", "clair_ctx_get_tuning",
+    "clair_ctx_set_strength", "clair_ctx_get_strength",
     "clair_autotune", "clair_graph_create", "clair_graph_launch", "clair_graph_destroy", "clair_graph_info",
     "clair_plan_create", "clair_plan_execute", "clair_plan_info", "clair_plan_destroy",
     "clair_strerror", "clair_last_error",
@@ -97,6 +98,8 @@ def load_library(path: str = LIB_PATH):
                                   ctypes.c_int),
         "clair_ctx_set_tuning": ([P, I32, I32, I32], ctypes.c_int),
         "clair_ctx_get_tuning": ([P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)], ctypes.c_int),
+        "clair_ctx_set_strength": ([P, ctypes.c_double], ctypes.c_int),
+        "clair_ctx_get_strength": ([P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "clair_autotune": ([P, I32, ctypes.POINTER(CsrIn), ctypes.POINTER(P), ctypes.POINTER(P),
                             ctypes.POINTER(I32), ctypes.POINTER(CsrOut), P, I32], ctypes.c_int),
         "clair_graph_create": ([P, I32, ctypes.POINTER(CsrIn), ctypes.POINTER(P), ctypes.POINTER(P),
@@ -224,6 +227,17 @@ class Context:
         st = self._lib.clair_ctx_set_tuning(self._h, group, wg_threads, chunk)
         if st:
             raise ClairError(st, "clair_ctx_set_tuning")
+
+    def set_strength(self, theta: float):
+        """Strength threshold of the neighbourhood search (0 keeps every stored nonzero)."""
+        st = self._lib.clair_ctx_set_strength(self._h, float(theta))
+        if st:
+            raise ClairError(st, "clair_ctx_set_strength")
+
+    def get_strength(self) -> float:
+        t = ctypes.c_double()
+        self._lib.clair_ctx_get_strength(self._h, ctypes.byref(t))
+        return t.value
 
     def get_tuning(self):
         g, t, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()

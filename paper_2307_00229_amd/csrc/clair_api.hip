@@ -71,7 +71,7 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
   size_t desc, st, cnt, chunk_nc, chunk_nnz, chunk_rbase, chunk_nzbase, chunk_mat, chunk_bins, row_block_chunk, clocal, lnz, dsum, rsum,
-      slotA, slotB, binC, bigq, big_size, ovf, total;
+      slotA, slotB, binC, bigq, big_size, ovf, cmax, total;
   size_t head_bytes;  // desc + st + counters (the uploaded head)
   int64_t capC;
 };
@@ -110,11 +110,12 @@ Layout make_layout(int nmat, int nchunks, int64_t n_total, int GA) {
   L.bigq = take(sizeof(int32_t) * L.capC);
   L.big_size = take(sizeof(int32_t) * (n_total + 1));
   L.ovf = take(sizeof(int32_t) * (nchunks + 1));
+  L.cmax = take(sizeof(double) * (n_total + 1));
   L.total = o;
   return L;
 }
 
-constexpr int kMaxStages = 8;
+constexpr int kMaxStages = 12;
 
 struct StageEvents {
   hipEvent_t ev[kMaxStages + 1];
@@ -129,6 +130,7 @@ struct clair_ctx {
   int cus = 256;
   // tuning
   int group = 8;  // lanes per row of the small solver: 1, 4 or 8 (|N| <= 8), 16/32 (|N| <= group)
+  double theta = 0.0;  // strength threshold of the neighbourhood search
   int binB_max = 32;  // largest block of the last batch whose sizes were read back (9..32)
   int last_maxb = 0;  // the same, unclamped (0: none read back yet)
   int wg_threads = 256;
@@ -283,6 +285,7 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
   w.chunk_unsized = reinterpret_cast<int32_t*>(base + b->L.ovf);
   w.bigq = reinterpret_cast<int32_t*>(base + b->L.bigq);
   w.big_size = reinterpret_cast<int32_t*>(base + b->L.big_size);
+  w.cmax = reinterpret_cast<double*>(base + b->L.cmax);
   w.scratch = static_cast<double*>(c->scratch.p);
   w.scratch_slots = c->scratch_slots;
   w.nmat = nmat;
@@ -315,6 +318,8 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
     d.nnz = A[m].nnz;
     d.nchunks = (A[m].n + c->chunk - 1) / c->chunk;
     d.fine0 = fine0;
+    d.cmax = w.cmax + fine0;
+    d.theta = c->theta;
     hd[m] = d;
     chunk0 += d.nchunks;
     fine0 += A[m].n;
@@ -406,6 +411,11 @@ int enqueue_symbolic(clair_ctx* c, Batch& b, hipStream_t s, bool validate, bool 
   if (validate) {
     HIPCHK(launch_validate(b.w, occupancy_blocks(c, 4), s));
     timing_mark(c, timing, s, "validate");
+  }
+  if (c->theta > 0.0) {
+    HIPCHK(launch_colmax(b.w, b.n_total, occupancy_blocks(c, 4), s));
+    if (capture_check(c->capturing, s, "k_colmax", __LINE__)) return CLAIR_ERR_HIP;
+    timing_mark(c, timing, s, "colmax");
   }
   HIPCHK(launch_count(b.w, s));
   if (capture_check(c->capturing, s, "k_count", __LINE__)) return CLAIR_ERR_HIP;
@@ -514,7 +524,8 @@ int run_plain_one(clair_ctx* c, const clair_csr_t& A, const int8_t* cf, const do
   const size_t o_tmp = align_up(o_sizes + sizeof(int32_t) * (n + 2), 256);
   const size_t o_dsum = align_up(o_tmp + sizeof(int32_t) * (nb + 4), 256);
   const size_t o_rsum = align_up(o_dsum + sizeof(double) * (n + 1), 256);
-  const size_t o_flags = align_up(o_rsum + sizeof(double) * (n + 1), 256);
+  const size_t o_cmax = align_up(o_rsum + sizeof(double) * (n + 1), 256);
+  const size_t o_flags = align_up(o_cmax + sizeof(double) * (n + 1), 256);
   const size_t total = o_flags + 64;
   if (c->plain_ws.ensure(total) != hipSuccess) return CLAIR_ERR_NOMEM;
   HIPCHK(c->readback.ensure(64));
@@ -527,6 +538,8 @@ int run_plain_one(clair_ctx* c, const clair_csr_t& A, const int8_t* cf, const do
   p.B = B;
   p.n = n;
   p.ell = ell;
+  p.theta = c->theta;
+  p.cmax = reinterpret_cast<double*>(base + o_cmax);
   p.blk_cnt = reinterpret_cast<int32_t*>(base + o_blk);
   p.clist = reinterpret_cast<int32_t*>(base + o_clist);
   p.sizes = reinterpret_cast<int32_t*>(base + o_sizes);
@@ -539,6 +552,7 @@ int run_plain_one(clair_ctx* c, const clair_csr_t& A, const int8_t* cf, const do
   p.Rva = R->val;
   int32_t hflags[8] = {0, INT32_MAX, 0, 0, 0, 0, 0, 0};
   HIPCHK(hipMemcpyAsync(p.flags, hflags, sizeof(hflags), hipMemcpyHostToDevice, s));
+  HIPCHK(plain_colmax(p, s));
   HIPCHK(plain_count_c(p, s));
   HIPCHK(plain_scan_blocks(p.blk_cnt, nb, s));
   HIPCHK(plain_clist(p, s));
@@ -816,6 +830,18 @@ int clair_ctx_set_tuning(clair_ctx_t* c, int32_t group, int32_t wg_threads, int3
   return CLAIR_OK;
 }
 
+int clair_ctx_set_strength(clair_ctx_t* c, double theta) {
+  if (!c || !(theta >= 0.0 && theta <= 1.0)) return CLAIR_ERR_INVALID;
+  c->theta = theta;
+  return CLAIR_OK;
+}
+
+int clair_ctx_get_strength(clair_ctx_t* c, double* theta) {
+  if (!c || !theta) return CLAIR_ERR_INVALID;
+  *theta = c->theta;
+  return CLAIR_OK;
+}
+
 int clair_ctx_get_tuning(clair_ctx_t* c, int32_t* group, int32_t* wg_threads, int32_t* chunk) {
   if (!c) return CLAIR_ERR_INVALID;
   if (group) *group = c->group;
@@ -898,6 +924,7 @@ int clair_graph_create(clair_ctx_t* parent, int32_t nmat, const clair_csr_t* A, 
   g->ctx->group = parent->group;
   g->ctx->wg_threads = parent->wg_threads;
   g->ctx->chunk = parent->chunk;
+  g->ctx->theta = parent->theta;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   clair_opts_t o{};
   o.stream = stream;
@@ -980,6 +1007,7 @@ int clair_plan_create(clair_ctx_t* parent, int32_t nmat, const clair_csr_t* A, c
     c->group = parent->group;
     c->wg_threads = parent->wg_threads;
     c->chunk = parent->chunk;
+    c->theta = parent->theta;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     Batch& b = pl->b;
     rc = prepare(c, nmat, A, cf, nullptr, ell, R, &b);

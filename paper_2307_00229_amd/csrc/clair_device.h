@@ -39,6 +39,8 @@ struct MatDesc {
   int32_t nchunks;
   int32_t nnz;      // nnz(A)
   int64_t fine0;    // offset of this matrix in fine-indexed workspaces
+  const double* cmax;  // largest off-diagonal |a_wv| of column v (filled when theta > 0)
+  double theta;        // strength threshold of the search (0: every stored nonzero)
 };
 
 // Pointers into device (global) memory.  Pointers that kernels load from a
@@ -70,6 +72,8 @@ struct GDesc {
   int32_t nchunks;
   int32_t nnz;
   int64_t fine0;
+  gptr<const double> cmax;
+  double theta;
 };
 
 __device__ __forceinline__ GDesc gview(const MatDesc& m) {
@@ -90,7 +94,17 @@ __device__ __forceinline__ GDesc gview(const MatDesc& m) {
   g.nchunks = m.nchunks;
   g.nnz = m.nnz;
   g.fine0 = m.fine0;
+  g.cmax = to_global(m.cmax);
+  g.theta = m.theta;
   return g;
+}
+
+// The search's edge test beyond "stored, nonzero, off-diagonal": the pattern
+// comes from the classical strength matrix of A^T (the matrix the algorithm
+// runs on for R), in which v depends strongly on u when |a_uv| is at least
+// theta times the largest off-diagonal magnitude of column v of A.
+__device__ __forceinline__ bool strong_edge(double a_uv, int v, double theta, gptr<const double> cmax) {
+  return theta == 0.0 || fabs(a_uv) >= theta * cmax[v];
 }
 
 struct MatStatus {
@@ -141,6 +155,7 @@ struct Work {
   int32_t* chunk_unsized;  // [nchunks] rows of the chunk not yet sized (more than 32 points)
   int32_t* bigq;           // [capC] those rows, c * chunk + t
   int32_t* big_size;       // [n_total] their sizes, until the chunk's prefix is redone
+  double* cmax;            // [n_total] column maxima for the strength test (theta > 0)
   double* scratch;        // FP64 blocks for oversized rows: scratch_slots * kMaxBlock^2 (may be null)
   int64_t scratch_slots;
   int32_t nmat;
@@ -179,7 +194,8 @@ __device__ __forceinline__ int find_sorted(const int* a, int len, int key) {
 
 // Register-resident neighbourhood search of one thread, for neighbourhoods of
 // at most SM points.  N(i) = the F-points reachable from C-point i by a walk
-// of at most ell edges (u -> v with u != v and a stored nonzero a_uv) whose
+// of at most ell edges (u -> v with u != v, a stored nonzero a_uv and
+// strong_edge) whose
 // interior vertices are F-points; kept sorted in v[0..s) (empty slots hold
 // INT32_MAX).  Returns s, or -1 when more than SM points are found.
 template <int SM>
@@ -223,7 +239,8 @@ struct RegSet {
 template <int SM>
 __device__ __forceinline__ void reg_expand(RegSet<SM>& S, int n, int u, int e0, int e1, int L,
                                            gptr<const int32_t> __restrict__ ci, gptr<const double> __restrict__ va,
-                                           gptr<const int8_t> __restrict__ cf) {
+                                           gptr<const int8_t> __restrict__ cf, double theta,
+                                           gptr<const double> __restrict__ cmax) {
   for (int e = e0; e < e1 && !S.ovf; e += 8) {
     int k[8];
     double v[8];
@@ -238,7 +255,7 @@ __device__ __forceinline__ void reg_expand(RegSet<SM>& S, int n, int u, int e0, 
     for (int j = 0; j < 8; ++j) c8[j] = ((unsigned)k[j] < (unsigned)n) ? cf[k[j]] : (int8_t)1;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      if (k[j] != u && v[j] != 0.0 && c8[j] == 0) S.insert(k[j], L);
+      if (k[j] != u && v[j] != 0.0 && c8[j] == 0 && strong_edge(v[j], k[j], theta, cmax)) S.insert(k[j], L);
     }
   }
 }
@@ -246,9 +263,10 @@ __device__ __forceinline__ void reg_expand(RegSet<SM>& S, int n, int u, int e0, 
 template <int SM>
 __device__ __forceinline__ int reg_bfs(RegSet<SM>& S, int n, int i, int ell, gptr<const int32_t> __restrict__ rp,
                                        gptr<const int32_t> __restrict__ ci, gptr<const double> __restrict__ va,
-                                       gptr<const int8_t> __restrict__ cf) {
+                                       gptr<const int8_t> __restrict__ cf, double theta,
+                                       gptr<const double> __restrict__ cmax) {
   S.clear();
-  reg_expand(S, n, i, rp[i], rp[i + 1], 1, ci, va, cf);
+  reg_expand(S, n, i, rp[i], rp[i + 1], 1, ci, va, cf, theta, cmax);
   for (int L = 2; L <= ell && !S.ovf; ++L) {
     // expand the points found at level L-1 in ascending order (from a
     // snapshot: inserts move entries); only compile-time register indices.
@@ -271,7 +289,7 @@ __device__ __forceinline__ int reg_bfs(RegSet<SM>& S, int n, int i, int ell, gpt
       for (int j = 0; j < SM; ++j)
         if (fl[j] == L - 1 && fv[j] > last && fv[j] < u) { u = fv[j]; e0 = b0[j]; e1 = b1[j]; }
       if (u == 0x7fffffff) break;
-      reg_expand(S, n, u, e0, e1, L, ci, va, cf);
+      reg_expand(S, n, u, e0, e1, L, ci, va, cf, theta, cmax);
       last = u;
       any = true;
     }
@@ -327,7 +345,8 @@ struct RegSetM {
 template <int SM>
 __device__ __forceinline__ void regm_expand(RegSetM<SM>& S, int n, int u, gptr<const int32_t> __restrict__ rp,
                                             gptr<const int32_t> __restrict__ ci, gptr<const double> __restrict__ va,
-                                            gptr<const int8_t> __restrict__ cf) {
+                                            gptr<const int8_t> __restrict__ cf, double theta,
+                                            gptr<const double> __restrict__ cmax) {
   const int e1 = rp[u + 1];
   for (int e = rp[u]; e < e1 && !S.ovf; e += 8) {
     int k[8];
@@ -343,16 +362,17 @@ __device__ __forceinline__ void regm_expand(RegSetM<SM>& S, int n, int u, gptr<c
     for (int j = 0; j < 8; ++j) c8[j] = ((unsigned)k[j] < (unsigned)n) ? cf[k[j]] : (int8_t)1;
 #pragma unroll
     for (int j = 0; j < 8; ++j)
-      if (k[j] != u && x[j] != 0.0 && c8[j] == 0) S.insert(k[j]);
+      if (k[j] != u && x[j] != 0.0 && c8[j] == 0 && strong_edge(x[j], k[j], theta, cmax)) S.insert(k[j]);
   }
 }
 
 template <int SM>
 __device__ __forceinline__ int regm_bfs(RegSetM<SM>& S, int n, int i, int ell, gptr<const int32_t> __restrict__ rp,
                                         gptr<const int32_t> __restrict__ ci, gptr<const double> __restrict__ va,
-                                        gptr<const int8_t> __restrict__ cf) {
+                                        gptr<const int8_t> __restrict__ cf, double theta,
+                                        gptr<const double> __restrict__ cmax) {
   S.clear();
-  regm_expand(S, n, i, rp, ci, va, cf);
+  regm_expand(S, n, i, rp, ci, va, cf, theta, cmax);
   for (int L = 2; L <= ell && !S.ovf; ++L) {
     S.todo = S.cur;
     S.cur = 0;
@@ -365,7 +385,7 @@ __device__ __forceinline__ int regm_bfs(RegSetM<SM>& S, int n, int i, int ell, g
 #pragma unroll
       for (int j = 0; j < SM; ++j)
         if (j == j0) u = S.v[j];
-      regm_expand(S, n, u, rp, ci, va, cf);
+      regm_expand(S, n, u, rp, ci, va, cf, theta, cmax);
     }
   }
   return S.ovf ? -1 : S.s;

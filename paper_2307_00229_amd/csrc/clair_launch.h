@@ -13,6 +13,8 @@ constexpr int kLdsBlockMax = 64;  // workgroup FP64 solver keeps blocks up to th
 // mixed (default) path
 hipError_t launch_clear_sums(const Work& w, int64_t n_total, int blocks, hipStream_t s);
 hipError_t launch_validate(const Work& w, int blocks, hipStream_t s);
+// column maxima of every matrix with theta > 0 (w.cmax, batch-wide fine numbering)
+hipError_t launch_colmax(const Work& w, int64_t n_total, int blocks, hipStream_t s);
 hipError_t launch_count(const Work& w, hipStream_t s);
 hipError_t launch_count_big(const Work& w, int blocks, hipStream_t s);
 hipError_t launch_scan(const Work& w, hipStream_t s);
@@ -33,6 +35,8 @@ struct PlainWork {
   const double* B;
   int32_t n;
   int32_t ell;
+  double theta;       // strength threshold of the search (0: every stored nonzero)
+  double* cmax;       // [n] largest off-diagonal |a_wv| of column v (when theta > 0)
   int32_t* blk_cnt;   // [nblk + 1]
   int32_t* clist;     // [n]   C-points in ascending order
   int32_t* sizes;     // [n+1] |N(i)| then exclusive scan of |N(i)|+1
@@ -46,6 +50,7 @@ struct PlainWork {
   double* Rva;
 };
 
+hipError_t plain_colmax(const PlainWork& p, hipStream_t s);                  // cmax
 hipError_t plain_count_c(const PlainWork& p, hipStream_t s);                 // blk_cnt
 hipError_t plain_scan_blocks(int32_t* a, int n, hipStream_t s);             // exclusive, a[n] = total
 hipError_t plain_clist(const PlainWork& p, hipStream_t s);                   // clist

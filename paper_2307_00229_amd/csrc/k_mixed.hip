@@ -92,7 +92,8 @@ struct WideBuf {
 // Returns |N(i)| with the sorted list in *out, or -1 when it exceeds kWN
 // (block-uniform).  Must be called by all kNT threads of the workgroup.
 __device__ int block_bfs(int n, int i, int ell, gptr<const int32_t> __restrict__ rp, gptr<const int32_t> __restrict__ ci,
-                         gptr<const double> __restrict__ va, gptr<const int8_t> __restrict__ cf, WideBuf& b, int** out) {
+                         gptr<const double> __restrict__ va, gptr<const int8_t> __restrict__ cf, double theta,
+                         gptr<const double> __restrict__ cmax, WideBuf& b, int** out) {
   const int tid = threadIdx.x;
   constexpr int nt = kNT;
   int* cur = b.nb0;
@@ -134,7 +135,9 @@ __device__ int block_bfs(int n, int i, int ell, gptr<const int32_t> __restrict__
           const int u = (depth == 1) ? i : b.fr[lo];
           const int e = rp[u] + (ef - b.dp[lo]);
           const int kk = ci[e];
-          if (kk != u && (unsigned)kk < (unsigned)n && va[e] != 0.0 && cf[kk] == 0) k = kk;
+          if (kk != u && (unsigned)kk < (unsigned)n && va[e] != 0.0 && cf[kk] == 0 &&
+              strong_edge(va[e], kk, theta, cmax))
+            k = kk;
         }
         b.cand[t] = k;
       }
@@ -395,7 +398,7 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
       continue;
     }
     RegSet<8> S;
-    const int sz = reg_bfs(S, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf);
+    const int sz = reg_bfs(S, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf, d.theta, d.cmax);
     if (sz >= 0) {
       s_size[t] = sz;
       ++inA;  // sz <= 8 <= lim
@@ -418,7 +421,7 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
     for (int k = tid; k < nl2; k += kNT) {
       const int t = s_list[k];
       RegSetM<32> S;
-      const int sz = regm_bfs(S, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf);
+      const int sz = regm_bfs(S, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf, d.theta, d.cmax);
       if (sz < 0) {
         s_size[t] = 0;
         w.clocal[base + t] = -(s_rows[t] + 1);
@@ -496,7 +499,7 @@ __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
     const int64_t base = d.fine0 + (int64_t)(c - d.chunk0) * w.chunk;
     const int i = -w.clocal[base + t] - 1;
     int* nl;
-    const int s = block_bfs(d.n, i, d.ell, d.rp, d.ci, d.va, d.cf, bb, &nl);
+    const int s = block_bfs(d.n, i, d.ell, d.rp, d.ci, d.va, d.cf, d.theta, d.cmax, bb, &nl);
     __syncthreads();
     if (tid == 0) {
       w.big_size[base + t] = s < 0 ? 0 : s;
@@ -1825,7 +1828,7 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
       const int i = ri.i;
       if (tid == 0) d.Rrp[ri.r] = ri.off;
       int* N;
-      const int s = block_bfs(d.n, i, d.ell, d.rp, d.ci, d.va, d.cf, bb, &N);
+      const int s = block_bfs(d.n, i, d.ell, d.rp, d.ci, d.va, d.cf, d.theta, d.cmax, bb, &N);
       __syncthreads();
       if (s != ri.s) {
         if (tid == 0) flag_row(st, s < 0 ? ST_UNSUPPORTED : ST_INVALID, i);
@@ -2056,6 +2059,34 @@ __global__ __launch_bounds__(256) void k_project(Work w) {
 
 // a numeric pass without the symbolic pass before it: projection sums of all
 // fine points to zero, and R.row_ptr[n_c] of every matrix
+// Column maxima for the strength test: cmax[v] = max over w != v of |a_wv|,
+// for every matrix of the batch (batch-wide fine numbering).  Non-negative
+// doubles order like their bit patterns, so an unsigned 64-bit atomic max
+// takes the maximum.
+__global__ void k_colmax_clear(Work w, int64_t n_total) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n_total; g += (int64_t)gridDim.x * blockDim.x)
+    w.cmax[g] = 0.0;
+}
+
+__global__ void k_colmax(Work w, int64_t n_total) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n_total; g += (int64_t)gridDim.x * blockDim.x) {
+    int lo = 0, hi = w.nmat - 1;  // the matrix holding fine point g
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (w.desc[mid].fine0 <= g) lo = mid; else hi = mid - 1;
+    }
+    const GDesc d = gview(w.desc[lo]);
+    if (d.theta == 0.0 || !matrix_live(w.st[lo])) continue;
+    const int u = (int)(g - d.fine0);
+    for (int e = d.rp[u]; e < d.rp[u + 1]; ++e) {
+      const int v = d.ci[e];
+      if (v == u || (unsigned)v >= (unsigned)d.n) continue;
+      atomicMax(reinterpret_cast<unsigned long long*>(w.cmax + d.fine0 + v),
+                (unsigned long long)__double_as_longlong(fabs(d.va[e])));
+    }
+  }
+}
+
 __global__ void k_clear_sums(Work w, int64_t n) {
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
     w.dsum[j] = 0.0;
@@ -2074,6 +2105,12 @@ __global__ void k_clear_sums(Work w, int64_t n) {
 // a kernel, not a memset: the call may be captured into a graph
 hipError_t launch_clear_sums(const Work& w, int64_t n_total, int blocks, hipStream_t s) {
   hipLaunchKernelGGL(k_clear_sums, dim3(blocks), dim3(256), 0, s, w, n_total);
+  return hipGetLastError();
+}
+
+hipError_t launch_colmax(const Work& w, int64_t n_total, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_colmax_clear, dim3(blocks), dim3(256), 0, s, w, n_total);
+  hipLaunchKernelGGL(k_colmax, dim3(blocks), dim3(256), 0, s, w, n_total);
   return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ __device__ int plain_bfs(const PlainWork& p, int i, int* N) {
       for (int e = p.rp[u]; e < p.rp[u + 1]; ++e) {
         const int k = p.ci[e];
         if (k == u || p.va[e] == 0.0 || p.cf[k] != 0) continue;
+        if (p.theta != 0.0 && !(fabs(p.va[e]) >= p.theta * p.cmax[k])) continue;  // strength of A^T
         bool seen = false;
         for (int q = 0; q < s && !seen; ++q) seen = (N[q] == k);
         if (seen) continue;
@@ -56,6 +57,24 @@ __device__ int plain_bfs(const PlainWork& p, int i, int* N) {
     N[b + 1] = v;
   }
   return s;
+}
+
+// cmax[v] = max over w != v of |a_wv| (bit patterns of non-negative doubles
+// order like their values)
+__global__ void k_p_colmax_clear(PlainWork p) {
+  const int j = blockIdx.x * kPT + threadIdx.x;
+  if (j < p.n) p.cmax[j] = 0.0;
+}
+
+__global__ void k_p_colmax(PlainWork p) {
+  const int u = blockIdx.x * kPT + threadIdx.x;
+  if (u >= p.n) return;
+  for (int e = p.rp[u]; e < p.rp[u + 1]; ++e) {
+    const int v = p.ci[e];
+    if (v != u && (unsigned)v < (unsigned)p.n)
+      atomicMax(reinterpret_cast<unsigned long long*>(p.cmax + v),
+                          (unsigned long long)__double_as_longlong(fabs(p.va[e])));
+  }
 }
 
 __global__ void k_p_count_c(PlainWork p) {
@@ -296,6 +315,13 @@ inline int nblk(int n) { return (n + kPT - 1) / kPT; }
 
 }  // namespace
 
+hipError_t plain_colmax(const PlainWork& p, hipStream_t s) {
+  if (p.n > 0 && p.theta != 0.0) {
+    hipLaunchKernelGGL(k_p_colmax_clear, dim3(nblk(p.n)), dim3(kPT), 0, s, p);
+    hipLaunchKernelGGL(k_p_colmax, dim3(nblk(p.n)), dim3(kPT), 0, s, p);
+  }
+  return hipGetLastError();
+}
 hipError_t plain_count_c(const PlainWork& p, hipStream_t s) {
   if (p.n > 0) hipLaunchKernelGGL(k_p_count_c, dim3(nblk(p.n)), dim3(kPT), 0, s, p);
   return hipGetLastError();
