@@ -148,6 +148,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--theta", type=float, default=0.0,
+                    help="strength threshold of the pattern (0: every stored nonzero)")
     ap.add_argument("--no-plan", action="store_true", help="skip the fixed-pattern (plan) measurement")
     ap.add_argument("--mode", choices=["graph", "direct", "best"], default="best")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -167,12 +169,17 @@ def main():
     torch.cuda.set_device(0)
     dev = "cuda:0"
     problems = make_problems(args.workload)
+    if args.theta:
+        import dataclasses
+
+        problems = [dataclasses.replace(p, theta=args.theta) for p in problems]
     As = [clair.CSR.from_problem(p, dev) for p in problems]
     cfs = [torch.from_numpy(p.cf).to(dev) for p in problems]
     Bs = [torch.from_numpy(p.B).to(dev) for p in problems]
     ells = [p.ell for p in problems]
     stream = torch.cuda.Stream()
     ctx = clair.Context()
+    ctx.set_strength(args.theta)
     with torch.cuda.stream(stream):
         n_c_list, nnz_list = clair.clair_size_R(As, cfs, ells, ctx=ctx, stream=stream)
         outs = [clair.ROut(nc, nz, dev) for nc, nz in zip(n_c_list, nnz_list)]
@@ -234,6 +241,7 @@ def main():
 
         # plain FP64 per-row form on the same inputs
         plain_ctx = clair.Context()
+        plain_ctx.set_strength(args.theta)
         outs_p = [clair.ROut(nc, nz, dev) for nc, nz in zip(n_c_list, nnz_list)]
 
         plain_step = clair.BatchedCall(plain_ctx, As, cfs, Bs, ells, outs_p, precision=clair.CLAIR_PREC_FP64,
@@ -275,7 +283,8 @@ def main():
     t_kern = stages.get("numeric", float("nan")) / 1e3
     achieved = kern_bytes / t_kern / 1e9 if t_kern > 0 else None
     src_hash = kernel_source_hash()
-    traffic = read_traffic_profile(args.workload, src_hash)
+    # the committed counters were taken at theta = 0
+    traffic = read_traffic_profile(args.workload, src_hash) if args.theta == 0 else None
     roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=(achieved / HBM_PEAK_GBS) if achieved else None, traffic=traffic,
                     kernel="k_numeric", kernel_ms=t_kern * 1e3, algorithmic_bytes_per_launch=kern_bytes,
@@ -300,6 +309,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "matrices": len(problems),
                    "R_rows": rows, "nnz_R": int(sum(nnz_list)), "launch": best, "tuning": tuning,
+                   "theta": args.theta,
                    "parallelism": "single GPU"},
         "plain_fp64": {"value": rows / t_plain, "unit": "rows/s", "ms_per_step": t_plain * 1e3,
                        "gates": gates_plain},
