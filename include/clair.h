@@ -161,6 +161,33 @@ int clair_build_R_batched(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* A,
                           const int8_t* const* cf_marker, const double* const* B, const int32_t* ell,
                           clair_csr_out_t* R_out, const clair_opts_t* opts, clair_info_t* info);
 
+/*
+ * clair_transpose -- AT = A^T for an A of A->n rows and ncol columns (sorted
+ * CSR in, sorted CSR out; values copied exactly).  AT_out: n_rows = ncol,
+ * n_cols = A->n, nnz = A->nnz are set; with too small capacities (row_ptr
+ * needs ncol + 1 entries) nothing else is written and CLAIR_ERR_CAPACITY is
+ * returned.  A column index outside [0, ncol) returns CLAIR_ERR_INVALID.
+ * Synchronises `stream`.
+ */
+int clair_transpose(clair_ctx_t* ctx, const clair_csr_t* A, int32_t ncol, clair_csr_out_t* AT_out, void* stream);
+
+/*
+ * clair_build_P -- interpolation by the same method: P = W(A), Algorithm 1
+ * applied to A itself (Section 3.1.3; R is the same algorithm applied to
+ * A^T).  Computed as P = (restriction of A^T)^T on the device: A^T is formed
+ * in library buffers, its restriction built with opts (precision; the
+ * context's strength threshold, which then measures strength in A), and
+ * transposed into P_out.  B is the constraint vector for P (a near-null
+ * vector of A), or NULL.  P is n x n_c: row f holds the C-columns (coarse
+ * indices 0..n_c-1) whose pattern reaches f; a C-point's row is its own
+ * injection.  P_out: n_rows = n, n_cols = n_c, nnz are set; too small
+ * capacities return CLAIR_ERR_CAPACITY (a size query).  info describes the
+ * restriction of A^T (n_c, max_block, refinement).  Synchronous: opts->async
+ * and opts->timing are ignored.
+ */
+int clair_build_P(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_marker, const double* B, int32_t ell,
+                  clair_csr_out_t* P_out, const clair_opts_t* opts, clair_info_t* info);
+
 /* Results of the last call on ctx (synchronises its stream).  Fills nmat info
  * entries and the sizes in R_out (may be NULL).  Returns the first non-OK status. */
 int clair_ctx_info(clair_ctx_t* ctx, int32_t nmat, clair_csr_out_t* R_out, clair_info_t* info);

@@ -29,7 +29,7 @@ CLAIR_MAX_BLOCK = 1024
 EXPORTED = [
     "clair_ctx_create", "clair_ctx_destroy", "clair_build_R", "clair_build_R_ex", "clair_build_R_batched",
     "clair_ctx_info", "clair_size_R", "clair_ctx_stage_times", "clair_ctx_set_tuning", "clair_ctx_get_tuning",
-    "clair_ctx_set_strength", "clair_ctx_get_strength",
+    "clair_ctx_set_strength", "clair_ctx_get_strength", "clair_transpose", "clair_build_P",
     "clair_autotune", "clair_graph_create", "clair_graph_launch", "clair_graph_destroy", "clair_graph_info",
     "clair_plan_create", "clair_plan_execute", "clair_plan_info", "clair_plan_destroy",
     "clair_strerror", "clair_last_error",
@@ -113,6 +113,9 @@ def load_library(path: str = LIB_PATH):
                                 ctypes.POINTER(Opts), ctypes.POINTER(Info)], ctypes.c_int),
         "clair_plan_info": ([P, I32, ctypes.POINTER(CsrOut), ctypes.POINTER(Info)], ctypes.c_int),
         "clair_plan_destroy": ([P], None),
+        "clair_transpose": ([P, ctypes.POINTER(CsrIn), I32, ctypes.POINTER(CsrOut), P], ctypes.c_int),
+        "clair_build_P": ([P, ctypes.POINTER(CsrIn), P, P, I32, ctypes.POINTER(CsrOut), ctypes.POINTER(Opts),
+                           ctypes.POINTER(Info)], ctypes.c_int),
         "clair_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "clair_last_error": ([], ctypes.c_char_p),
     }
@@ -353,6 +356,50 @@ def clair_build_R(A: CSR, cf: torch.Tensor, B: Optional[torch.Tensor], ell: int,
     """One matrix: returns (row_ptr, col_idx, val) device tensors and the info dict."""
     outs, infos, st = clair_build_R_batched([A], [cf], [B], [ell], **kw)
     return outs[0].trimmed(), (infos[0] if infos else None)
+
+
+def clair_transpose(A: CSR, ncol: Optional[int] = None, *, ctx: Optional[Context] = None, stream=None):
+    """A^T of an A.n x ncol matrix (ncol defaults to A.n): (row_ptr, col_idx, val) device tensors."""
+    lib = load_library()
+    ctx = ctx or Context()
+    ncol = A.n if ncol is None else int(ncol)
+    nnz = int(A.col_idx.numel())
+    out = ROut(ncol, nnz, device=A.row_ptr.device)
+    oc = out.c()
+    st = lib.clair_transpose(ctx.handle, ctypes.byref(A.c()), ncol, ctypes.byref(oc), _stream_ptr(stream))
+    if st:
+        raise ClairError(st, "clair_transpose")
+    return out.trimmed()
+
+
+def clair_build_P(A: CSR, cf: torch.Tensor, B: Optional[torch.Tensor], ell: int, *, ctx: Optional[Context] = None,
+                  precision: int = CLAIR_PREC_MIXED, stream=None, check: bool = True):
+    """Interpolation P = W(A) (n x n_c): returns ((row_ptr, col_idx, val), n_c, info, status).
+
+    The first call with empty buffers reads the sizes (CLAIR_ERR_CAPACITY),
+    the second builds P.
+    """
+    lib = load_library()
+    ctx = ctx or Context()
+    _check_dev(cf, torch.int8, "cf")
+    if B is not None:
+        _check_dev(B, torch.float64, "B")
+    o = Opts(_stream_ptr(stream), precision, 0, 0, 0)
+    info = Info()
+    probe = CsrOut()
+    st = lib.clair_build_P(ctx.handle, ctypes.byref(A.c()), cf.data_ptr(), _ptr(B), ell, ctypes.byref(probe),
+                           ctypes.byref(o), ctypes.byref(info))
+    if st not in (CLAIR_OK, CLAIR_ERR_CAPACITY):
+        if check:
+            raise ClairError(st, "clair_build_P")
+        return None, probe.n_cols, info.as_dict(), st
+    out = ROut(A.n, int(probe.nnz), device=A.row_ptr.device)
+    oc = out.c()
+    st = lib.clair_build_P(ctx.handle, ctypes.byref(A.c()), cf.data_ptr(), _ptr(B), ell, ctypes.byref(oc),
+                           ctypes.byref(o), ctypes.byref(info))
+    if st and check:
+        raise ClairError(st, "clair_build_P")
+    return out.trimmed(), int(oc.n_cols), info.as_dict(), st
 
 
 def clair_autotune(ctx: Context, As, cfs, Bs, ells, outs, reps: int = 3, stream=None):

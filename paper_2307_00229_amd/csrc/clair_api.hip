@@ -158,6 +158,8 @@ struct clair_ctx {
   // plain-form scratch
   DevBuf plain_ws;
   DevBuf plain_k;
+  // transpose and P-side buffers: A^T, the restriction built on it, scratch
+  DevBuf t_rp, t_ci, t_va, q_rp, q_ci, q_va, t_scratch;
 };
 
 namespace {
@@ -719,6 +721,96 @@ int clair_build_R(const clair_csr_t* A, const int8_t* cf, const double* B, int32
   if (!c) return CLAIR_ERR_HIP;
   std::lock_guard<std::mutex> lk(g_default_mu);
   return clair_build_R_ex(c, A, cf, B, ell, R, nullptr, nullptr);
+}
+
+namespace {
+
+// B = A^T (A: m x ncol) into device arrays of sufficient size; synchronous
+int transpose_into(clair_ctx* c, const clair_csr_t& A, int32_t ncol, int32_t* trp, int32_t* tci, double* tva,
+                   hipStream_t s) {
+  const size_t ints = transpose_scratch_ints(ncol);
+  HIPCHK(c->t_scratch.ensure(sizeof(int32_t) * ints));
+  int32_t* scr = static_cast<int32_t*>(c->t_scratch.p);
+  HIPCHK(launch_transpose(A.n, ncol, A.row_ptr, A.col_idx, A.val, trp, tci, tva, scr, c->cus, s));
+  int32_t bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, scr + ncol, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return bad ? CLAIR_ERR_INVALID : CLAIR_OK;
+}
+
+int check_csr_args(const clair_csr_t* A) {
+  if (!A || A->n < 0 || A->nnz < 0) return CLAIR_ERR_INVALID;
+  if (A->n > 0 && !A->row_ptr) return CLAIR_ERR_INVALID;
+  if (A->nnz > 0 && (!A->col_idx || !A->val)) return CLAIR_ERR_INVALID;
+  return CLAIR_OK;
+}
+
+}  // namespace
+
+int clair_transpose(clair_ctx_t* c, const clair_csr_t* A, int32_t ncol, clair_csr_out_t* AT, void* stream) {
+  if (!c || !AT || ncol < 0 || check_csr_args(A)) return CLAIR_ERR_INVALID;
+  AT->n_rows = ncol;
+  AT->n_cols = A->n;
+  AT->nnz = A->nnz;
+  if (AT->row_capacity < ncol + 1 || AT->nnz_capacity < A->nnz || !AT->row_ptr ||
+      (A->nnz > 0 && (!AT->col_idx || !AT->val)))
+    return CLAIR_ERR_CAPACITY;
+  try {
+    return transpose_into(c, *A, ncol, AT->row_ptr, AT->col_idx, AT->val, static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return CLAIR_ERR_NOMEM;
+  }
+}
+
+int clair_build_P(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf, const double* B, int32_t ell,
+                  clair_csr_out_t* P, const clair_opts_t* o, clair_info_t* info) {
+  if (!c || !P || !cf || ell < 1 || ell > 64 || check_csr_args(A)) return CLAIR_ERR_INVALID;
+  if (o && o->precision != CLAIR_PREC_MIXED && o->precision != CLAIR_PREC_FP64) return CLAIR_ERR_INVALID;
+  const hipStream_t s = static_cast<hipStream_t>(o ? o->stream : nullptr);
+  const int32_t n = A->n;
+  try {
+    // A^T
+    HIPCHK(c->t_rp.ensure(sizeof(int32_t) * ((size_t)n + 1)));
+    HIPCHK(c->t_ci.ensure(sizeof(int32_t) * std::max<size_t>(1, (size_t)A->nnz)));
+    HIPCHK(c->t_va.ensure(sizeof(double) * std::max<size_t>(1, (size_t)A->nnz)));
+    clair_csr_t At{n, A->nnz, static_cast<int32_t*>(c->t_rp.p), static_cast<int32_t*>(c->t_ci.p),
+                   static_cast<double*>(c->t_va.p)};
+    int rc = transpose_into(c, *A, n, static_cast<int32_t*>(c->t_rp.p), static_cast<int32_t*>(c->t_ci.p),
+                            static_cast<double*>(c->t_va.p), s);
+    if (rc) return rc;
+    // the restriction of A^T, Q = (W(A))^T, in library buffers
+    int32_t n_c = 0;
+    int64_t nnz = 0;
+    rc = clair_size_R(c, 1, &At, &cf, &ell, &n_c, &nnz, s);
+    if (rc && rc != CLAIR_ERR_CAPACITY) return rc;
+    if (nnz > INT32_MAX) return CLAIR_ERR_UNSUPPORTED;
+    HIPCHK(c->q_rp.ensure(sizeof(int32_t) * ((size_t)n_c + 1)));
+    HIPCHK(c->q_ci.ensure(sizeof(int32_t) * std::max<int64_t>(1, nnz)));
+    HIPCHK(c->q_va.ensure(sizeof(double) * std::max<int64_t>(1, nnz)));
+    clair_csr_out_t Q{};
+    Q.row_capacity = n_c + 1;
+    Q.nnz_capacity = nnz;
+    Q.row_ptr = static_cast<int32_t*>(c->q_rp.p);
+    Q.col_idx = static_cast<int32_t*>(c->q_ci.p);
+    Q.val = static_cast<double*>(c->q_va.p);
+    clair_opts_t so = o ? *o : clair_opts_t{};
+    so.async = 0;
+    so.timing = 0;
+    clair_info_t qi{};
+    rc = clair_build_R_ex(c, &At, cf, B, ell, &Q, &so, &qi);
+    if (info) *info = qi;
+    P->n_rows = n;
+    P->n_cols = n_c;
+    P->nnz = nnz;
+    if (rc) return rc;
+    // P = Q^T: n x n_c
+    if (P->row_capacity < n + 1 || P->nnz_capacity < nnz || !P->row_ptr || (nnz > 0 && (!P->col_idx || !P->val)))
+      return CLAIR_ERR_CAPACITY;
+    clair_csr_t Qin{n_c, (int32_t)nnz, Q.row_ptr, Q.col_idx, Q.val};
+    return transpose_into(c, Qin, n, P->row_ptr, P->col_idx, P->val, s);
+  } catch (...) {
+    return CLAIR_ERR_NOMEM;
+  }
 }
 
 int clair_ctx_info(clair_ctx_t* c, int32_t nmat, clair_csr_out_t* R, clair_info_t* info) {

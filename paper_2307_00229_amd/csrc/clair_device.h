@@ -177,6 +177,32 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// exclusive prefix sum of v over the workgroup (blockDim.x a multiple of 64)
+__device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int* total) {
+  // sh: at least blockDim.x / 64 ints.  Inclusive scan inside each wavefront
+  // (six shuffle steps), then the wavefront totals through LDS: two barriers.
+  const int lane = threadIdx.x & 63;
+  const int wid = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wid] = x;
+  __syncthreads();
+  int base = 0, tot = 0;
+  for (int k = 0; k < nw; ++k) {
+    const int t = sh[k];
+    base += (k < wid) ? t : 0;
+    tot += t;
+  }
+  *total = tot;
+  __syncthreads();
+  return base + x - v;
+}
+
 // index of the first element >= key in sorted a[0..len)
 __device__ __forceinline__ int lower_bound_i32(const int* a, int len, int key) {
   int lo = 0, hi = len;

@@ -26,6 +26,13 @@ hipError_t launch_rows8(const Work& w, int wg_threads, int cus, hipStream_t s);
 hipError_t launch_rows_wg(const Work& w, int blocks, hipStream_t s);
 hipError_t launch_project(const Work& w, int blocks, int lanes_per_row, hipStream_t s);
 
+// CSR transpose of an m x ncol matrix: trp[ncol+1], tci/tva[nnz]; scratch of
+// transpose_scratch_ints(ncol) ints (column cursors, a flag set to 1 for an
+// index outside [0, ncol), block totals)
+size_t transpose_scratch_ints(int ncol);
+hipError_t launch_transpose(int m, int ncol, const int32_t* rp, const int32_t* ci, const double* va, int32_t* trp,
+                            int32_t* tci, double* tva, int32_t* scratch, int cus, hipStream_t s);
+
 // plain FP64 per-row form: one matrix, one thread per row, one kernel per stage
 struct PlainWork {
   const int32_t* rp;

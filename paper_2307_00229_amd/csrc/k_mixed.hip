@@ -47,31 +47,6 @@ constexpr int kNT = 256;  // threads per workgroup of the symbolic pass
 constexpr int kWN = kMaxBlock;
 constexpr int kWC = 4096;
 
-__device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int* total) {
-  // sh: at least blockDim.x / 64 ints.  Inclusive scan inside each wavefront
-  // (six shuffle steps), then the wavefront totals through LDS: two barriers.
-  const int lane = threadIdx.x & 63;
-  const int wid = threadIdx.x >> 6;
-  const int nw = blockDim.x >> 6;
-  int x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh[wid] = x;
-  __syncthreads();
-  int base = 0, tot = 0;
-  for (int k = 0; k < nw; ++k) {
-    const int t = sh[k];
-    base += (k < wid) ? t : 0;
-    tot += t;
-  }
-  *total = tot;
-  __syncthreads();
-  return base + x - v;
-}
-
 // Workgroup-wide neighbourhood search for rows of any size up to kWN points:
 // the same set as reg_bfs (F-points reachable from C-point i by at most ell
 // edges with F-points inside the walk).  The entries of a level's frontier
