@@ -188,6 +188,29 @@ int clair_transpose(clair_ctx_t* ctx, const clair_csr_t* A, int32_t ncol, clair_
 int clair_build_P(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_marker, const double* B, int32_t ell,
                   clair_csr_out_t* P_out, const clair_opts_t* opts, clair_info_t* info);
 
+/*
+ * clair_spgemm -- C = X Y for X of X->n rows and x_cols columns and Y of
+ * Y->n = x_cols rows and y_cols columns (sorted CSR in and out, FP64).  The
+ * pattern is structural: every column that some product x_ij y_jc reaches,
+ * also where the products cancel.  Each row's sum is formed in no fixed
+ * order, so values agree with a sequential product to rounding.  C_out:
+ * n_rows, n_cols, nnz are set; too small capacities return
+ * CLAIR_ERR_CAPACITY (a size query).  A row of C with more than 1536 columns
+ * returns CLAIR_ERR_UNSUPPORTED; an index out of range CLAIR_ERR_INVALID.
+ * Synchronises `stream`.
+ */
+int clair_spgemm(clair_ctx_t* ctx, const clair_csr_t* X, int32_t x_cols, const clair_csr_t* Y, int32_t y_cols,
+                 clair_csr_out_t* C_out, void* stream);
+
+/*
+ * clair_galerkin -- the coarse operator A_c = R A P of the next level
+ * (Section 1), R: n_c x n, A: n x n, P: n x n_c, as R (A P) with the
+ * intermediate A P in library buffers.  Same pattern, rounding, capacity and
+ * error rules as clair_spgemm.  Synchronises `stream`.
+ */
+int clair_galerkin(clair_ctx_t* ctx, const clair_csr_t* R, const clair_csr_t* A, const clair_csr_t* P, int32_t n_c,
+                   clair_csr_out_t* Ac_out, void* stream);
+
 /* Results of the last call on ctx (synchronises its stream).  Fills nmat info
  * entries and the sizes in R_out (may be NULL).  Returns the first non-OK status. */
 int clair_ctx_info(clair_ctx_t* ctx, int32_t nmat, clair_csr_out_t* R_out, clair_info_t* info);

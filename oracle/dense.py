@@ -16,6 +16,9 @@ independent check of the C oracle:
   exactly these rows.
 * ``r_ideal``: the ideal restriction [-A_cf A_ff^{-1}, I] (Section 2.1,
   eq. r_ideal) by a dense solve.
+* ``product_reference``: a sparse product X Y with its structural pattern
+  (every column some product reaches) and a rounding scale per entry, for
+  the Galerkin coarse operator R A P (Section 1).
 """
 from __future__ import annotations
 
@@ -97,3 +100,23 @@ def csr_to_dense_R(Rrp, Rci, Rva, n):
         for e in range(Rrp[r], Rrp[r + 1]):
             R[r, Rci[e]] = Rva[e]
     return R
+
+
+def product_reference(X, Y):
+    """Reference for C = X Y (scipy CSR in): (C on the structural pattern, scale).
+
+    The pattern is that of |X| |Y| (no cancellation among non-negative
+    products); values are X Y on it (zero where the products cancel); scale
+    = (|X| |Y|) entry by entry, the size of the terms of each sum.
+    """
+    import scipy.sparse as sp
+
+    X = sp.csr_matrix(X)
+    Y = sp.csr_matrix(Y)
+    S = sp.csr_matrix(abs(X) @ abs(Y))
+    S.sort_indices()
+    V = sp.csr_matrix(X @ Y)
+    vals = np.asarray(V[S.nonzero()]).ravel() if S.nnz else np.zeros(0)
+    # S.nonzero() walks rows in order and columns sorted within a row
+    C = sp.csr_matrix((vals, S.indices.copy(), S.indptr.copy()), shape=S.shape)
+    return C, S

@@ -30,6 +30,7 @@ EXPORTED = [
     "clair_ctx_create", "clair_ctx_destroy", "clair_build_R", "clair_build_R_ex", "clair_build_R_batched",
     "clair_ctx_info", "clair_size_R", "clair_ctx_stage_times", "clair_ctx_set_tuning", "clair_ctx_get_tuning",
     "clair_ctx_set_strength", "clair_ctx_get_strength", "clair_transpose", "clair_build_P",
+    "clair_spgemm", "clair_galerkin",
     "clair_autotune", "clair_graph_create", "clair_graph_launch", "clair_graph_destroy", "clair_graph_info",
     "clair_plan_create", "clair_plan_execute", "clair_plan_info", "clair_plan_destroy",
     "clair_strerror", "clair_last_error",
@@ -116,6 +117,10 @@ def load_library(path: str = LIB_PATH):
         "clair_transpose": ([P, ctypes.POINTER(CsrIn), I32, ctypes.POINTER(CsrOut), P], ctypes.c_int),
         "clair_build_P": ([P, ctypes.POINTER(CsrIn), P, P, I32, ctypes.POINTER(CsrOut), ctypes.POINTER(Opts),
                            ctypes.POINTER(Info)], ctypes.c_int),
+        "clair_spgemm": ([P, ctypes.POINTER(CsrIn), I32, ctypes.POINTER(CsrIn), I32, ctypes.POINTER(CsrOut), P],
+                         ctypes.c_int),
+        "clair_galerkin": ([P, ctypes.POINTER(CsrIn), ctypes.POINTER(CsrIn), ctypes.POINTER(CsrIn), I32,
+                            ctypes.POINTER(CsrOut), P], ctypes.c_int),
         "clair_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "clair_last_error": ([], ctypes.c_char_p),
     }
@@ -400,6 +405,45 @@ def clair_build_P(A: CSR, cf: torch.Tensor, B: Optional[torch.Tensor], ell: int,
     if st and check:
         raise ClairError(st, "clair_build_P")
     return out.trimmed(), int(oc.n_cols), info.as_dict(), st
+
+
+def _two_pass(call, n_rows: int, device):
+    """Size query (empty buffers), then the call into buffers of that size."""
+    probe = CsrOut()
+    st = call(probe)
+    if st not in (CLAIR_OK, CLAIR_ERR_CAPACITY):
+        return None, probe, st
+    out = ROut(n_rows, int(probe.nnz), device=device)
+    oc = out.c()
+    st = call(oc)
+    return out, oc, st
+
+
+def clair_spgemm(X: CSR, x_cols: int, Y: CSR, y_cols: int, *, ctx: Optional[Context] = None, stream=None):
+    """C = X Y on the device: (row_ptr, col_idx, val) tensors."""
+    lib = load_library()
+    ctx = ctx or Context()
+    xc, yc = X.c(), Y.c()
+    out, oc, st = _two_pass(lambda o: lib.clair_spgemm(ctx.handle, ctypes.byref(xc), int(x_cols), ctypes.byref(yc),
+                                                       int(y_cols), ctypes.byref(o), _stream_ptr(stream)),
+                            X.n, X.row_ptr.device)
+    if st:
+        raise ClairError(st, "clair_spgemm")
+    return out.trimmed()
+
+
+def clair_galerkin(R: CSR, A: CSR, Pm: CSR, n_c: int, *, ctx: Optional[Context] = None, stream=None):
+    """A_c = R A P on the device: (row_ptr, col_idx, val) tensors (n_c x n_c)."""
+    lib = load_library()
+    ctx = ctx or Context()
+    rc_, ac_, pc_ = R.c(), A.c(), Pm.c()
+    out, oc, st = _two_pass(lambda o: lib.clair_galerkin(ctx.handle, ctypes.byref(rc_), ctypes.byref(ac_),
+                                                         ctypes.byref(pc_), int(n_c), ctypes.byref(o),
+                                                         _stream_ptr(stream)),
+                            n_c, A.row_ptr.device)
+    if st:
+        raise ClairError(st, "clair_galerkin")
+    return out.trimmed()
 
 
 def clair_autotune(ctx: Context, As, cfs, Bs, ells, outs, reps: int = 3, stream=None):

@@ -160,6 +160,8 @@ struct clair_ctx {
   DevBuf plain_k;
   // transpose and P-side buffers: A^T, the restriction built on it, scratch
   DevBuf t_rp, t_ci, t_va, q_rp, q_ci, q_va, t_scratch;
+  // sparse products: row pointers of a product, the intermediate A P
+  DevBuf g_rp, g_cnt, ap_rp, ap_ci, ap_va;
 };
 
 namespace {
@@ -808,6 +810,106 @@ int clair_build_P(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf, const 
       return CLAIR_ERR_CAPACITY;
     clair_csr_t Qin{n_c, (int32_t)nnz, Q.row_ptr, Q.col_idx, Q.val};
     return transpose_into(c, Qin, n, P->row_ptr, P->col_idx, P->val, s);
+  } catch (...) {
+    return CLAIR_ERR_NOMEM;
+  }
+}
+
+namespace {
+
+// Symbolic phase of C = X Y (X: X.n rows, k columns; Y: k rows, ny columns):
+// row pointers into c->g_rp (X.n + 1 entries) and nnz(C).  Synchronous.
+int spgemm_symbolic(clair_ctx* c, const clair_csr_t& X, int32_t k, const clair_csr_t& Y, int32_t ny, int64_t* nnz,
+                    hipStream_t s) {
+  const int m = X.n;
+  HIPCHK(c->g_rp.ensure(sizeof(int32_t) * ((size_t)m + 1)));
+  HIPCHK(c->g_cnt.ensure(sizeof(int32_t) * ((size_t)m + 4 + scan_scratch_ints(m))));
+  int32_t* cnt = static_cast<int32_t*>(c->g_cnt.p);
+  int32_t* flags = cnt + m;
+  int32_t* sums = flags + 4;
+  int32_t* crp = static_cast<int32_t*>(c->g_rp.p);
+  HIPCHK(hipMemsetAsync(flags, 0, sizeof(int32_t) * 4, s));
+  HIPCHK(launch_spgemm_count(m, X.row_ptr, X.col_idx, k, Y.row_ptr, Y.col_idx, ny, cnt, flags, c->cus, s));
+  HIPCHK(launch_exclusive_scan(cnt, m, crp, sums, c->cus, s));
+  int32_t hf[2] = {0, 0};
+  int32_t total = 0;
+  HIPCHK(hipMemcpyAsync(hf, flags, sizeof(hf), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&total, crp + m, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (hf[1]) return CLAIR_ERR_INVALID;
+  if (hf[0]) return CLAIR_ERR_UNSUPPORTED;
+  *nnz = total;
+  return CLAIR_OK;
+}
+
+int check_product_args(const clair_csr_t* X, int32_t x_cols, const clair_csr_t* Y, int32_t y_cols) {
+  if (check_csr_args(X) || check_csr_args(Y) || x_cols < 0 || y_cols < 0 || x_cols != Y->n) return CLAIR_ERR_INVALID;
+  return CLAIR_OK;
+}
+
+// C = X Y into C (capacities already checked); symbolic phase done (g_rp)
+int spgemm_numeric(clair_ctx* c, const clair_csr_t& X, const clair_csr_t& Y, int32_t* crp, int32_t* cci, double* cva,
+                   hipStream_t s) {
+  const int m = X.n;
+  if (crp != c->g_rp.p)
+    HIPCHK(hipMemcpyAsync(crp, c->g_rp.p, sizeof(int32_t) * ((size_t)m + 1), hipMemcpyDeviceToDevice, s));
+  HIPCHK(launch_spgemm_fill(m, X.row_ptr, X.col_idx, X.val, Y.row_ptr, Y.col_idx, Y.val, crp, cci, cva, c->cus, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return CLAIR_OK;
+}
+
+bool fits(const clair_csr_out_t* C, int32_t rows, int64_t nnz) {
+  return C->row_capacity >= rows + 1 && C->nnz_capacity >= nnz && C->row_ptr && (nnz == 0 || (C->col_idx && C->val));
+}
+
+}  // namespace
+
+int clair_spgemm(clair_ctx_t* c, const clair_csr_t* X, int32_t x_cols, const clair_csr_t* Y, int32_t y_cols,
+                 clair_csr_out_t* C, void* stream) {
+  if (!c || !C || check_product_args(X, x_cols, Y, y_cols)) return CLAIR_ERR_INVALID;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  try {
+    int64_t nnz = 0;
+    int rc = spgemm_symbolic(c, *X, x_cols, *Y, y_cols, &nnz, s);
+    C->n_rows = X->n;
+    C->n_cols = y_cols;
+    C->nnz = nnz;
+    if (rc) return rc;
+    if (!fits(C, X->n, nnz)) return CLAIR_ERR_CAPACITY;
+    return spgemm_numeric(c, *X, *Y, C->row_ptr, C->col_idx, C->val, s);
+  } catch (...) {
+    return CLAIR_ERR_NOMEM;
+  }
+}
+
+int clair_galerkin(clair_ctx_t* c, const clair_csr_t* R, const clair_csr_t* A, const clair_csr_t* P, int32_t n_c,
+                   clair_csr_out_t* Ac, void* stream) {
+  if (!c || !Ac || !A || !R || !P || R->n != n_c || P->n != A->n) return CLAIR_ERR_INVALID;
+  if (check_product_args(A, A->n, P, n_c) || check_product_args(R, A->n, A, A->n)) return CLAIR_ERR_INVALID;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  try {
+    // A P (n x n_c) in library buffers
+    int64_t nnz_ap = 0;
+    int rc = spgemm_symbolic(c, *A, A->n, *P, n_c, &nnz_ap, s);
+    if (rc) return rc;
+    if (nnz_ap > INT32_MAX) return CLAIR_ERR_UNSUPPORTED;
+    HIPCHK(c->ap_rp.ensure(sizeof(int32_t) * ((size_t)A->n + 1)));
+    HIPCHK(c->ap_ci.ensure(sizeof(int32_t) * std::max<int64_t>(1, nnz_ap)));
+    HIPCHK(c->ap_va.ensure(sizeof(double) * std::max<int64_t>(1, nnz_ap)));
+    rc = spgemm_numeric(c, *A, *P, static_cast<int32_t*>(c->ap_rp.p), static_cast<int32_t*>(c->ap_ci.p),
+                        static_cast<double*>(c->ap_va.p), s);
+    if (rc) return rc;
+    const clair_csr_t AP{A->n, (int32_t)nnz_ap, static_cast<int32_t*>(c->ap_rp.p), static_cast<int32_t*>(c->ap_ci.p),
+                         static_cast<double*>(c->ap_va.p)};
+    // R (A P)
+    int64_t nnz = 0;
+    rc = spgemm_symbolic(c, *R, A->n, AP, n_c, &nnz, s);
+    Ac->n_rows = n_c;
+    Ac->n_cols = n_c;
+    Ac->nnz = nnz;
+    if (rc) return rc;
+    if (!fits(Ac, n_c, nnz)) return CLAIR_ERR_CAPACITY;
+    return spgemm_numeric(c, *R, AP, Ac->row_ptr, Ac->col_idx, Ac->val, s);
   } catch (...) {
     return CLAIR_ERR_NOMEM;
   }

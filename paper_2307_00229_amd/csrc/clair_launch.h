@@ -33,6 +33,21 @@ size_t transpose_scratch_ints(int ncol);
 hipError_t launch_transpose(int m, int ncol, const int32_t* rp, const int32_t* ci, const double* va, int32_t* trp,
                             int32_t* tci, double* tva, int32_t* scratch, int cus, hipStream_t s);
 
+// out[0..n) = exclusive prefix of cnt, out[n] = total; sums: scan_scratch_ints(n)
+size_t scan_scratch_ints(int n);
+hipError_t launch_exclusive_scan(const int32_t* cnt, int n, int32_t* out, int32_t* sums, int cus, hipStream_t s);
+
+// sparse product C = X Y (X: m rows, Y: k x ny), one wavefront per row of C.
+// Symbolic: cnt[i] = distinct columns of row i; flags[0] = 1 for a row above
+// kSpgemmMaxRow columns, flags[1] = 1 for an index out of range.  Numeric:
+// sorted rows at crp[i] (crp from the scan of cnt).
+constexpr int kSpgemmMaxRow = 1536;
+hipError_t launch_spgemm_count(int m, const int32_t* xrp, const int32_t* xci, int k, const int32_t* yrp,
+                               const int32_t* yci, int ny, int32_t* cnt, int32_t* flags, int cus, hipStream_t s);
+hipError_t launch_spgemm_fill(int m, const int32_t* xrp, const int32_t* xci, const double* xva, const int32_t* yrp,
+                              const int32_t* yci, const double* yva, const int32_t* crp, int32_t* cci, double* cva,
+                              int cus, hipStream_t s);
+
 // plain FP64 per-row form: one matrix, one thread per row, one kernel per stage
 struct PlainWork {
   const int32_t* rp;

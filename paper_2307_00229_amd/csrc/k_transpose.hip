@@ -128,6 +128,16 @@ int grid_for(int n, int cus) { return std::max(1, std::min((n + kTT - 1) / kTT, 
 
 size_t transpose_scratch_ints(int ncol) { return (size_t)ncol + (size_t)(ncol / kTBlk + 2) + 1; }
 
+size_t scan_scratch_ints(int n) { return (size_t)(n / kTBlk + 2); }
+
+hipError_t launch_exclusive_scan(const int32_t* cnt, int n, int32_t* out, int32_t* sums, int cus, hipStream_t s) {
+  const int nb = (n + kTBlk - 1) / kTBlk;
+  if (nb > 0) hipLaunchKernelGGL(k_t_scan_blocks, dim3(nb), dim3(kTT), 0, s, cnt, n, out, sums);
+  hipLaunchKernelGGL(k_t_scan_sums, dim3(1), dim3(kTT), 0, s, sums, nb);
+  hipLaunchKernelGGL(k_t_scan_add, dim3(grid_for(n, cus)), dim3(kTT), 0, s, out, n, sums, nb);
+  return hipGetLastError();
+}
+
 hipError_t launch_transpose(int m, int ncol, const int32_t* rp, const int32_t* ci, const double* va, int32_t* trp,
                             int32_t* tci, double* tva, int32_t* scratch, int cus, hipStream_t s) {
   int32_t* cursor = scratch;

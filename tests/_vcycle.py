@@ -81,8 +81,12 @@ class Level:
         self.omega = None
 
 
-def build_hierarchy(A, shape, k, ell, build, min_coarse=64, max_levels=10):
-    """Levels from fine to coarse.  `build(A_csr_parts, cf, B, ell)` returns R as scipy CSR."""
+def build_hierarchy(A, shape, k, ell, build, min_coarse=64, max_levels=10, build_P=None, galerkin=None):
+    """Levels from fine to coarse.  `build(A_csr_parts, cf, B, ell)` returns R as scipy CSR.
+
+    Optional: `build_P(A_csr_parts, cf, B, ell)` returns P directly (else P is
+    the transpose of `build` on A^T), and `galerkin(R, A, P)` the coarse
+    operator (else R @ A @ P with scipy)."""
     levels = []
     A = sp.csr_matrix(A)
     for _ in range(max_levels):
@@ -93,10 +97,13 @@ def build_hierarchy(A, shape, k, ell, build, min_coarse=64, max_levels=10):
             break
         B = np.ones(A.shape[0])
         lev.R = build(csr_parts(A), cf, B, ell)
-        lev.P = sp.csr_matrix(build(csr_parts(A.T), cf, B, ell).T)
+        if build_P is None:
+            lev.P = sp.csr_matrix(build(csr_parts(A.T), cf, B, ell).T)
+        else:
+            lev.P = build_P(csr_parts(A), cf, B, ell)
         Dinv = sp.diags(1.0 / lev.D)
         lev.omega = 1.0 / arnoldi_rho(Dinv @ A)
-        A = sp.csr_matrix(lev.R @ A @ lev.P)
+        A = sp.csr_matrix(lev.R @ A @ lev.P) if galerkin is None else galerkin(lev.R, A, lev.P)
         shape = tuple((s + k - 1) // k for s in shape)
     last = levels[-1]
     last.lu = spla.splu(sp.csc_matrix(last.A))
