@@ -138,6 +138,59 @@ def check_against_oracle(problems, outs):
     return dict(pattern_identical=True, max_row_rel_err=worst_row, max_constraint_resid=worst_c)
 
 
+def time_next_level(clair, ctx, A, cf, B, ell, R_out, stream, reps=5):
+    """A^T, P = W(A) and A_c = R A P on one matrix: C calls into preallocated
+    buffers (sizes read once beforehand), wall time of the synchronous call."""
+    import ctypes
+
+    import torch
+
+    lib = clair.load_library()
+    sp_ = clair._stream_ptr(stream)
+
+    def best_of(fn):
+        assert fn() == 0
+        t = float("inf")
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = fn()
+            torch.cuda.synchronize()
+            t = min(t, time.perf_counter() - t0)
+            assert st == 0
+        return t * 1e3
+
+    rp, ci, va = R_out.trimmed()
+    R = clair.CSR(rp, ci, va, n=R_out.n_c)
+    Ac_, Rc_ = A.c(), R.c()
+    T = clair.ROut(A.n, int(A.col_idx.numel()), device=A.row_ptr.device)
+    Tc = T.c()
+    t_ms = best_of(lambda: lib.clair_transpose(ctx.handle, ctypes.byref(Ac_), A.n, ctypes.byref(Tc), sp_))
+    o = clair.Opts(sp_, clair.CLAIR_PREC_MIXED, 0, 0, 0)
+    info = clair.Info()
+    probe = clair.CsrOut()
+    lib.clair_build_P(ctx.handle, ctypes.byref(Ac_), cf.data_ptr(), clair._ptr(B), ell, ctypes.byref(probe),
+                      ctypes.byref(o), ctypes.byref(info))
+    Pout = clair.ROut(A.n, int(probe.nnz), device=A.row_ptr.device)
+    Pc = Pout.c()
+    p_ms = best_of(lambda: lib.clair_build_P(ctx.handle, ctypes.byref(Ac_), cf.data_ptr(), clair._ptr(B), ell,
+                                             ctypes.byref(Pc), ctypes.byref(o), ctypes.byref(info)))
+    n_c = int(Pc.n_cols)
+    prp, pci, pva = Pout.trimmed()
+    Pm = clair.CSR(prp, pci, pva, n=A.n)
+    Pmc = Pm.c()
+    probe = clair.CsrOut()
+    lib.clair_galerkin(ctx.handle, ctypes.byref(Rc_), ctypes.byref(Ac_), ctypes.byref(Pmc), n_c, ctypes.byref(probe),
+                       sp_)
+    G = clair.ROut(n_c, int(probe.nnz), device=A.row_ptr.device)
+    Gc = G.c()
+    g_ms = best_of(lambda: lib.clair_galerkin(ctx.handle, ctypes.byref(Rc_), ctypes.byref(Ac_), ctypes.byref(Pmc),
+                                              n_c, ctypes.byref(Gc), sp_))
+    return {"matrix": "first of the workload", "transpose_ms": t_ms, "build_P_ms": p_ms, "galerkin_ms": g_ms,
+            "nnz_A": int(A.col_idx.numel()), "nnz_P": int(Pc.nnz), "nnz_Ac": int(Gc.nnz),
+            "note": "synchronous C calls into preallocated buffers, wall time, best of 5"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +204,8 @@ def main():
     ap.add_argument("--theta", type=float, default=0.0,
                     help="strength threshold of the pattern (0: every stored nonzero)")
     ap.add_argument("--no-plan", action="store_true", help="skip the fixed-pattern (plan) measurement")
+    ap.add_argument("--no-next-level", action="store_true",
+                    help="skip timing P, the transpose and the Galerkin product on the first matrix")
     ap.add_argument("--mode", choices=["graph", "direct", "best"], default="best")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
@@ -267,6 +322,12 @@ def main():
             plan_res = {"value": rows / t_pl, "unit": "rows/s", "ms_per_step": t_pl * 1e3,
                         "gates": None, "_outs": outs_pl}
 
+        # the rest of a two-level setup on the first matrix (synchronous calls):
+        # A^T, P = W(A), and A_c = R A P with the R measured above
+        next_level = None
+        if not args.no_next_level:
+            next_level = time_next_level(clair, ctx, As[0], cfs[0], Bs[0], ells[0], outs[0], stream)
+
         if args.copy_probe_mib:
             x = torch.empty(args.copy_probe_mib * 2 ** 20 // 4, dtype=torch.float32, device=dev).fill_(1.0)
             y = torch.empty_like(x)
@@ -315,6 +376,7 @@ def main():
                        "gates": gates_plain},
         "speedup_vs_plain_fp64": t_plain / t_mixed,
         "plan_numeric_only": plan_res,
+        "next_level": next_level,
         "modes_ms_per_step": {k: v["wall_s"] / args.steps * 1e3 for k, v in results.items()},
         "graph_error": graph_error,
         "gates": gates,
