@@ -211,6 +211,22 @@ int clair_spgemm(clair_ctx_t* ctx, const clair_csr_t* X, int32_t x_cols, const c
 int clair_galerkin(clair_ctx_t* ctx, const clair_csr_t* R, const clair_csr_t* A, const clair_csr_t* P, int32_t n_c,
                    clair_csr_out_t* Ac_out, void* stream);
 
+/*
+ * clair_smooth_B -- the constraint vector after `iterations` of
+ * CFF-weighted Jacobi for M x = 0 (Section 4 pre-smooths B = 1 with 5 such
+ * iterations on every level): per iteration one weighted Jacobi sweep on the
+ * C-points (cf != 0), then two on the F-points; a sweep on a set S sets
+ * x_i <- x_i - omega (M x)_i / m_ii for every i in S from the same old x.
+ * M = A (transpose = 0: the vector for P) or A^T (transpose = 1: the vector
+ * for R, which is built from A^T).  omega is the caller's (the paper uses
+ * 1 / rho(D^{-1} A)).  B_in and B_out: device float64[n]; they may be the
+ * same array.  A zero diagonal on a swept point returns CLAIR_ERR_SINGULAR
+ * (B_out then holds the result with those points left unchanged); an index
+ * out of range returns CLAIR_ERR_INVALID.  Synchronises `stream`.
+ */
+int clair_smooth_B(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_marker, const double* B_in,
+                   double* B_out, int32_t iterations, double omega, int32_t transpose, void* stream);
+
 /* Results of the last call on ctx (synchronises its stream).  Fills nmat info
  * entries and the sizes in R_out (may be NULL).  Returns the first non-OK status. */
 int clair_ctx_info(clair_ctx_t* ctx, int32_t nmat, clair_csr_out_t* R_out, clair_info_t* info);

@@ -16,6 +16,7 @@ Modules
 ``literal``      -- Algorithm 1 step by step (tentative operator, least-squares
                     constraint fit, residual update, explicit projection), for
                     any number k of iterations.
+``smoothing``    -- CFF-weighted-Jacobi smoothing of the constraint vector.
 """
 from __future__ import annotations
 

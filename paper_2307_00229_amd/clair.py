@@ -30,7 +30,7 @@ EXPORTED = [
     "clair_ctx_create", "clair_ctx_destroy", "clair_build_R", "clair_build_R_ex", "clair_build_R_batched",
     "clair_ctx_info", "clair_size_R", "clair_ctx_stage_times", "clair_ctx_set_tuning", "clair_ctx_get_tuning",
     "clair_ctx_set_strength", "clair_ctx_get_strength", "clair_transpose", "clair_build_P",
-    "clair_spgemm", "clair_galerkin",
+    "clair_spgemm", "clair_galerkin", "clair_smooth_B",
     "clair_autotune", "clair_graph_create", "clair_graph_launch", "clair_graph_destroy", "clair_graph_info",
     "clair_plan_create", "clair_plan_execute", "clair_plan_info", "clair_plan_destroy",
     "clair_strerror", "clair_last_error",
@@ -121,6 +121,7 @@ def load_library(path: str = LIB_PATH):
                          ctypes.c_int),
         "clair_galerkin": ([P, ctypes.POINTER(CsrIn), ctypes.POINTER(CsrIn), ctypes.POINTER(CsrIn), I32,
                             ctypes.POINTER(CsrOut), P], ctypes.c_int),
+        "clair_smooth_B": ([P, ctypes.POINTER(CsrIn), P, P, P, I32, ctypes.c_double, I32, P], ctypes.c_int),
         "clair_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "clair_last_error": ([], ctypes.c_char_p),
     }
@@ -444,6 +445,21 @@ def clair_galerkin(R: CSR, A: CSR, Pm: CSR, n_c: int, *, ctx: Optional[Context] 
     if st:
         raise ClairError(st, "clair_galerkin")
     return out.trimmed()
+
+
+def clair_smooth_B(A: CSR, cf: torch.Tensor, B: torch.Tensor, iterations: int, omega: float, *, transpose: bool = False,
+                   out: Optional[torch.Tensor] = None, ctx: Optional[Context] = None, stream=None) -> torch.Tensor:
+    """B after CFF-weighted-Jacobi iterations on A (or A^T): a new device tensor (or `out`)."""
+    lib = load_library()
+    ctx = ctx or Context()
+    _check_dev(cf, torch.int8, "cf")
+    _check_dev(B, torch.float64, "B")
+    out = torch.empty_like(B) if out is None else out
+    st = lib.clair_smooth_B(ctx.handle, ctypes.byref(A.c()), cf.data_ptr(), B.data_ptr(), out.data_ptr(),
+                            int(iterations), float(omega), 1 if transpose else 0, _stream_ptr(stream))
+    if st:
+        raise ClairError(st, "clair_smooth_B")
+    return out
 
 
 def clair_autotune(ctx: Context, As, cfs, Bs, ells, outs, reps: int = 3, stream=None):

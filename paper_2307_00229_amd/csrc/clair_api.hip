@@ -162,6 +162,8 @@ struct clair_ctx {
   DevBuf t_rp, t_ci, t_va, q_rp, q_ci, q_va, t_scratch;
   // sparse products: row pointers of a product, the intermediate A P
   DevBuf g_rp, g_cnt, ap_rp, ap_ci, ap_va;
+  // smoothing of B: two vectors and a flag
+  DevBuf sm_x, sm_y, sm_flag;
 };
 
 namespace {
@@ -910,6 +912,52 @@ int clair_galerkin(clair_ctx_t* c, const clair_csr_t* R, const clair_csr_t* A, c
     if (rc) return rc;
     if (!fits(Ac, n_c, nnz)) return CLAIR_ERR_CAPACITY;
     return spgemm_numeric(c, *R, AP, Ac->row_ptr, Ac->col_idx, Ac->val, s);
+  } catch (...) {
+    return CLAIR_ERR_NOMEM;
+  }
+}
+
+int clair_smooth_B(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf, const double* B_in, double* B_out,
+                   int32_t iterations, double omega, int32_t transpose, void* stream) {
+  if (!c || check_csr_args(A) || iterations < 0 || !(omega == omega) || (A->n > 0 && (!cf || !B_in || !B_out)))
+    return CLAIR_ERR_INVALID;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const int n = A->n;
+  if (n == 0) return CLAIR_OK;
+  try {
+    clair_csr_t M = *A;
+    if (transpose) {
+      HIPCHK(c->t_rp.ensure(sizeof(int32_t) * ((size_t)n + 1)));
+      HIPCHK(c->t_ci.ensure(sizeof(int32_t) * std::max<size_t>(1, (size_t)A->nnz)));
+      HIPCHK(c->t_va.ensure(sizeof(double) * std::max<size_t>(1, (size_t)A->nnz)));
+      int rc = transpose_into(c, *A, n, static_cast<int32_t*>(c->t_rp.p), static_cast<int32_t*>(c->t_ci.p),
+                              static_cast<double*>(c->t_va.p), s);
+      if (rc) return rc;
+      M = clair_csr_t{n, A->nnz, static_cast<int32_t*>(c->t_rp.p), static_cast<int32_t*>(c->t_ci.p),
+                      static_cast<double*>(c->t_va.p)};
+    }
+    HIPCHK(c->sm_x.ensure(sizeof(double) * n));
+    HIPCHK(c->sm_y.ensure(sizeof(double) * n));
+    HIPCHK(c->sm_flag.ensure(sizeof(int32_t)));
+    double* x = static_cast<double*>(c->sm_x.p);
+    double* y = static_cast<double*>(c->sm_y.p);
+    int32_t* flag = static_cast<int32_t*>(c->sm_flag.p);
+    HIPCHK(hipMemsetAsync(flag, 0, sizeof(int32_t), s));
+    HIPCHK(hipMemcpyAsync(x, B_in, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    for (int it = 0; it < iterations; ++it) {
+      const int which[3] = {1, 0, 0};  // C, then F twice
+      for (int w = 0; w < 3; ++w) {
+        HIPCHK(launch_jacobi_sweep(n, M.row_ptr, M.col_idx, M.val, cf, which[w], omega, x, y, flag, c->cus, s));
+        std::swap(x, y);
+      }
+    }
+    HIPCHK(hipMemcpyAsync(B_out, x, sizeof(double) * n, hipMemcpyDeviceToDevice, s));
+    int32_t hf = 0;
+    HIPCHK(hipMemcpyAsync(&hf, flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hf == 2) return CLAIR_ERR_INVALID;
+    if (hf == 1) return CLAIR_ERR_SINGULAR;
+    return CLAIR_OK;
   } catch (...) {
     return CLAIR_ERR_NOMEM;
   }

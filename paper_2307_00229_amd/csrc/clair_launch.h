@@ -48,6 +48,12 @@ hipError_t launch_spgemm_fill(int m, const int32_t* xrp, const int32_t* xci, con
                               const int32_t* yci, const double* yva, const int32_t* crp, int32_t* cci, double* cva,
                               int cus, hipStream_t s);
 
+// one weighted Jacobi sweep for M x = 0 on the points with (cf != 0) == which_c
+// (M's rows given); flag: 1 = zero diagonal on a swept row, 2 = bad index
+hipError_t launch_jacobi_sweep(int n, const int32_t* rp, const int32_t* ci, const double* va, const int8_t* cf,
+                               int which_c, double omega, const double* x, double* y, int32_t* flag, int cus,
+                               hipStream_t s);
+
 // plain FP64 per-row form: one matrix, one thread per row, one kernel per stage
 struct PlainWork {
   const int32_t* rp;
