@@ -186,7 +186,12 @@ def time_next_level(clair, ctx, A, cf, B, ell, R_out, stream, reps=5):
     Gc = G.c()
     g_ms = best_of(lambda: lib.clair_galerkin(ctx.handle, ctypes.byref(Rc_), ctypes.byref(Ac_), ctypes.byref(Pmc),
                                               n_c, ctypes.byref(Gc), sp_))
+    Bs_out = torch.empty(A.n, dtype=torch.float64, device=A.row_ptr.device)
+    ones = torch.ones(A.n, dtype=torch.float64, device=A.row_ptr.device)
+    s_ms = best_of(lambda: lib.clair_smooth_B(ctx.handle, ctypes.byref(Ac_), cf.data_ptr(), ones.data_ptr(),
+                                              Bs_out.data_ptr(), 5, 2.0 / 3.0, 1, sp_))
     return {"matrix": "first of the workload", "transpose_ms": t_ms, "build_P_ms": p_ms, "galerkin_ms": g_ms,
+            "smooth_B_5_cff_on_AT_ms": s_ms,
             "nnz_A": int(A.col_idx.numel()), "nnz_P": int(Pc.nnz), "nnz_Ac": int(Gc.nnz),
             "note": "synchronous C calls into preallocated buffers, wall time, best of 5"}
 
