@@ -56,9 +56,9 @@ def _load():
         p = ctypes.c_void_p
         i32, i64 = ctypes.c_int32, ctypes.c_int64
         f64 = ctypes.c_double
-        lib.orc_pattern_size.argtypes = [i32, p, p, p, p, i32, f64, i32, p, p, p]
+        lib.orc_pattern_size.argtypes = [i32, p, p, p, p, p, i32, f64, i32, p, p, p]
         lib.orc_pattern_size.restype = ctypes.c_int
-        lib.orc_build_R.argtypes = [i32, p, p, p, p, p, i32, f64, i32, p, p, p, i64, p, p]
+        lib.orc_build_R.argtypes = [i32, p, p, p, p, p, p, i32, f64, i32, p, p, p, i64, p, p]
         lib.orc_build_R.restype = ctypes.c_int
         lib.orc_max_threads.argtypes = []
         lib.orc_max_threads.restype = ctypes.c_int
@@ -80,24 +80,27 @@ def max_threads() -> int:
     return int(_load().orc_max_threads())
 
 
-def pattern_size(n, row_ptr, col_idx, val, cf, ell, nthreads=0, theta=0.0):
-    """(n_c, nnz_R, sizes[n_c]) with sizes[r] = |N(i_r)|.  theta: strength threshold."""
+def pattern_size(n, row_ptr, col_idx, val, cf, ell, nthreads=0, theta=0.0, agg=None):
+    """(n_c, nnz_R, sizes[n_c]) with sizes[r] = |N(i_r)|.  theta: strength
+    threshold; agg: root C-point of every point's aggregate (or -1), for the
+    aggregation-based base pattern."""
     lib = _load()
     rp = np.ascontiguousarray(row_ptr, np.int32)
     ci = np.ascontiguousarray(col_idx, np.int32)
     va = np.ascontiguousarray(val, np.float64)
     cf = np.ascontiguousarray(cf, np.int8)
+    ag = None if agg is None else np.ascontiguousarray(agg, np.int32)
     n_c = ctypes.c_int32(0)
     nnz = ctypes.c_int64(0)
     sizes = np.zeros(int((cf != 0).sum()) or 1, np.int32)
-    rc = lib.orc_pattern_size(n, _ptr(rp), _ptr(ci), _ptr(va), _ptr(cf), ell, float(theta), nthreads,
+    rc = lib.orc_pattern_size(n, _ptr(rp), _ptr(ci), _ptr(va), _ptr(cf), _ptr(ag), ell, float(theta), nthreads,
                               ctypes.byref(n_c), ctypes.byref(nnz), _ptr(sizes))
     if rc:
         raise OracleError(rc, f"oracle pattern_size failed ({rc})")
     return n_c.value, nnz.value, sizes[: n_c.value]
 
 
-def build_R(n, row_ptr, col_idx, val, cf, B, ell, nthreads=0, allow_singular=False, theta=0.0):
+def build_R(n, row_ptr, col_idx, val, cf, B, ell, nthreads=0, allow_singular=False, theta=0.0, agg=None):
     """FP64 oracle R (CSR arrays) plus statistics.  theta: strength threshold
     of the pattern (0 keeps every stored nonzero).
 
@@ -109,13 +112,14 @@ def build_R(n, row_ptr, col_idx, val, cf, B, ell, nthreads=0, allow_singular=Fal
     va = np.ascontiguousarray(val, np.float64)
     cfa = np.ascontiguousarray(cf, np.int8)
     Ba = None if B is None else np.ascontiguousarray(B, np.float64)
-    n_c, nnz, _ = pattern_size(n, rp, ci, va, cfa, ell, nthreads, theta=theta)
+    ag = None if agg is None else np.ascontiguousarray(agg, np.int32)
+    n_c, nnz, _ = pattern_size(n, rp, ci, va, cfa, ell, nthreads, theta=theta, agg=ag)
     Rrp = np.zeros(n_c + 1, np.int32)
     Rci = np.zeros(max(nnz, 1), np.int32)
     Rva = np.zeros(max(nnz, 1), np.float64)
     unc = ctypes.c_int64(0)
     bad = ctypes.c_int32(-1)
-    rc = lib.orc_build_R(n, _ptr(rp), _ptr(ci), _ptr(va), _ptr(cfa), _ptr(Ba), ell, float(theta), nthreads,
+    rc = lib.orc_build_R(n, _ptr(rp), _ptr(ci), _ptr(va), _ptr(cfa), _ptr(ag), _ptr(Ba), ell, float(theta), nthreads,
                          _ptr(Rrp), _ptr(Rci), _ptr(Rva), nnz, ctypes.byref(unc), ctypes.byref(bad))
     if rc and not (rc == ORC_ERR_SINGULAR and allow_singular):
         raise OracleError(rc, f"oracle build_R failed ({rc}), bad_row={bad.value}")
@@ -127,4 +131,5 @@ def build_R_problem(p, nthreads=0, B="problem", **kw):
     """Convenience: oracle R for a problems.Problem."""
     Bv = p.B if (isinstance(B, str) and B == "problem") else B
     kw.setdefault("theta", getattr(p, "theta", 0.0))
+    kw.setdefault("agg", getattr(p, "agg", None))
     return build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, Bv, p.ell, nthreads=nthreads, **kw)

@@ -16,7 +16,8 @@
  *   A^T (Section 3.1.3): the pattern of the row is the distance-ell
  *   F-neighbourhood N(i) of i (Algorithm 1, pattern expansion S^{m-1} T with
  *   m = ell, interior vertices F, S the classical strength matrix of A^T with
- *   threshold theta), the local l-AIR system is
+ *   threshold theta; T = S_fc for classical C/F coarsening, or the
+ *   aggregation operator when aggregates are given), the local l-AIR system is
  *   (A[N,N])^T z = -A[i,N]^T (Section 2.1, eq. system), and the mode
  *   constraint R^T B_c = B on the F-points (Section 2.3, eq. global_const1;
  *   Section 3.1, eq. Qdef) is imposed by the Euclidean projection
@@ -106,17 +107,36 @@ static void column_max(int32_t n, const int32_t* rp, const int32_t* ci, const do
       if (ci[e] != w) cmax[ci[e]] = fmax(cmax[ci[e]], fabs(va[e]));
 }
 
+/* Aggregates (may be NULL): agg[j] = the root C-point of j's aggregate or
+ * -1.  The base pattern T is then the aggregation operator (Section 3.1.3,
+ * aggregation-based coarsening): column c holds the F-points of c's
+ * aggregate, and the expansion S^{m-1} T adds m-1 steps from them.  Members
+ * of root c are listed in mem[mrp[c] .. mrp[c+1]). */
+typedef struct {
+  const int32_t* mrp;
+  const int32_t* mem;
+} agg_lists;
+
 /* Returns s = |N(i)| (>= 0), N(i) sorted ascending in w->list[0..s), or -1 on OOM. */
 static int32_t neighbourhood(int32_t i, int ell, const int32_t* rp, const int32_t* ci,
                              const double* va, const int8_t* cf, double theta, const double* cmax,
-                             bfs_ws* w) {
+                             const agg_lists* ag, bfs_ws* w) {
   w->stamp++;
   w->mark[i] = w->stamp;
   int32_t len = 0;
   int32_t lo = 0, hi = 0; /* current frontier = list[lo..hi); level 0 frontier is {i} */
   for (int depth = 1; depth <= ell; ++depth) {
     int32_t before = len;
-    if (depth == 1) {
+    if (depth == 1 && ag) {
+      /* the aggregate's F-points */
+      for (int32_t t = ag->mrp[i]; t < ag->mrp[i + 1]; ++t) {
+        int32_t k = ag->mem[t];
+        if (cf[k] != 0 || w->mark[k] == w->stamp) continue;
+        w->mark[k] = w->stamp;
+        if (ws_push(w, len, k)) return -1;
+        ++len;
+      }
+    } else if (depth == 1) {
       for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
         int32_t k = ci[e];
         if (!is_edge(i, e, ci, va, theta, cmax) || cf[k] != 0 || w->mark[k] == w->stamp) continue;
@@ -214,11 +234,34 @@ static int set_threads(int nthreads) {
 #endif
 }
 
+/* Member lists of the aggregates: mrp[n+1], mem[n]; an F-point j joins the
+ * aggregate of agg[j] when that is a C-point index in range. */
+static int build_agg_lists(int32_t n, const int8_t* cf, const int32_t* agg, int32_t** mrp_out, int32_t** mem_out) {
+  int32_t* mrp = (int32_t*)calloc((size_t)n + 1, sizeof(int32_t));
+  int32_t* mem = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+  if (!mrp || !mem) { free(mrp); free(mem); return ORC_ERR_NOMEM; }
+  for (int32_t j = 0; j < n; ++j) {
+    int32_t r = agg[j];
+    if (cf[j] == 0 && r >= 0 && r < n && cf[r] != 0) mrp[r + 1]++;
+  }
+  for (int32_t r = 0; r < n; ++r) mrp[r + 1] += mrp[r];
+  int32_t* fill = (int32_t*)calloc((size_t)n + 1, sizeof(int32_t));
+  if (!fill) { free(mrp); free(mem); return ORC_ERR_NOMEM; }
+  for (int32_t j = 0; j < n; ++j) { /* ascending j: each list comes out sorted */
+    int32_t r = agg[j];
+    if (cf[j] == 0 && r >= 0 && r < n && cf[r] != 0) mem[mrp[r] + fill[r]++] = j;
+  }
+  free(fill);
+  *mrp_out = mrp;
+  *mem_out = mem;
+  return ORC_OK;
+}
+
 /* Number of C-points and nnz(R) = sum_i (|N(i)| + 1).  Also the per-row sizes
  * when `sizes` (length n_c) is given. */
 int orc_pattern_size(int32_t n, const int32_t* rp, const int32_t* ci, const double* va,
-                     const int8_t* cf, int32_t ell, double theta, int32_t nthreads, int32_t* n_c_out,
-                     int64_t* nnz_out, int32_t* sizes) {
+                     const int8_t* cf, const int32_t* agg, int32_t ell, double theta, int32_t nthreads,
+                     int32_t* n_c_out, int64_t* nnz_out, int32_t* sizes) {
   if (ell < 1 || !(theta >= 0.0 && theta <= 1.0) || check_csr(n, rp, ci)) return ORC_ERR_INVALID;
   double* cmax = NULL;
   if (theta > 0.0) {
@@ -226,10 +269,17 @@ int orc_pattern_size(int32_t n, const int32_t* rp, const int32_t* ci, const doub
     if (!cmax) return ORC_ERR_NOMEM;
     column_max(n, rp, ci, va, cmax);
   }
+  agg_lists ag = {NULL, NULL};
+  if (agg) {
+    int32_t *mrp = NULL, *mem = NULL;
+    if (build_agg_lists(n, cf, agg, &mrp, &mem)) { free(cmax); return ORC_ERR_NOMEM; }
+    ag.mrp = mrp;
+    ag.mem = mem;
+  }
   int32_t n_c = 0;
   for (int32_t j = 0; j < n; ++j) n_c += (cf[j] != 0);
   int32_t* clist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_c > 0 ? n_c : 1));
-  if (!clist) { free(cmax); return ORC_ERR_NOMEM; }
+  if (!clist) { free(cmax); free((void*)ag.mrp); free((void*)ag.mem); return ORC_ERR_NOMEM; }
   for (int32_t j = 0, r = 0; j < n; ++j) if (cf[j]) clist[r++] = j;
   int64_t total = 0;
   int err = 0;
@@ -245,7 +295,7 @@ int orc_pattern_size(int32_t n, const int32_t* rp, const int32_t* ci, const doub
     } else {
 #pragma omp for schedule(static)
       for (int32_t r = 0; r < n_c; ++r) {
-        int32_t s = neighbourhood(clist[r], ell, rp, ci, va, cf, theta, cmax, &w);
+        int32_t s = neighbourhood(clist[r], ell, rp, ci, va, cf, theta, cmax, agg ? &ag : NULL, &w);
         if (s < 0) {
 #pragma omp atomic write
           err = 1;
@@ -260,6 +310,8 @@ int orc_pattern_size(int32_t n, const int32_t* rp, const int32_t* ci, const doub
   }
   free(clist);
   free(cmax);
+  free((void*)ag.mrp);
+  free((void*)ag.mem);
   if (err) return ORC_ERR_NOMEM;
   *n_c_out = n_c;
   *nnz_out = total;
@@ -273,8 +325,8 @@ int orc_pattern_size(int32_t n, const int32_t* rp, const int32_t* ci, const doub
  * bad_row = fine index of the first C-row whose local block is singular.
  */
 int orc_build_R(int32_t n, const int32_t* rp, const int32_t* ci, const double* va, const int8_t* cf,
-                const double* B, int32_t ell, double theta, int32_t nthreads, int32_t* R_rp, int32_t* R_ci,
-                double* R_va, int64_t cap, int64_t* n_uncovered, int32_t* bad_row) {
+                const int32_t* agg, const double* B, int32_t ell, double theta, int32_t nthreads, int32_t* R_rp,
+                int32_t* R_ci, double* R_va, int64_t cap, int64_t* n_uncovered, int32_t* bad_row) {
   if (ell < 1 || !(theta >= 0.0 && theta <= 1.0) || check_csr(n, rp, ci)) return ORC_ERR_INVALID;
   int32_t n_c = 0;
   int64_t nnz = 0;
@@ -282,7 +334,7 @@ int orc_build_R(int32_t n, const int32_t* rp, const int32_t* ci, const double* v
   int32_t* sizes = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_c > 0 ? n_c : 1));
   int32_t* clist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_c > 0 ? n_c : 1));
   if (!sizes || !clist) { free(sizes); free(clist); return ORC_ERR_NOMEM; }
-  int rc = orc_pattern_size(n, rp, ci, va, cf, ell, theta, nthreads, &n_c, &nnz, sizes);
+  int rc = orc_pattern_size(n, rp, ci, va, cf, agg, ell, theta, nthreads, &n_c, &nnz, sizes);
   if (rc) { free(sizes); free(clist); return rc; }
   if (nnz > cap) { free(sizes); free(clist); return ORC_ERR_CAPACITY; }
   double* cmax = NULL;
@@ -290,6 +342,13 @@ int orc_build_R(int32_t n, const int32_t* rp, const int32_t* ci, const double* v
     cmax = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     if (!cmax) { free(sizes); free(clist); return ORC_ERR_NOMEM; }
     column_max(n, rp, ci, va, cmax);
+  }
+  agg_lists ag = {NULL, NULL};
+  if (agg) {
+    int32_t *mrp = NULL, *mem = NULL;
+    if (build_agg_lists(n, cf, agg, &mrp, &mem)) { free(sizes); free(clist); free(cmax); return ORC_ERR_NOMEM; }
+    ag.mrp = mrp;
+    ag.mem = mem;
   }
   for (int32_t j = 0, r = 0; j < n; ++j) if (cf[j]) clist[r++] = j;
   R_rp[0] = 0;
@@ -314,7 +373,7 @@ int orc_build_R(int32_t n, const int32_t* rp, const int32_t* ci, const double* v
 #pragma omp for schedule(dynamic, 64)
       for (int32_t r = 0; r < n_c; ++r) {
         int32_t i = clist[r];
-        int32_t s = neighbourhood(i, ell, rp, ci, va, cf, theta, cmax, &w);
+        int32_t s = neighbourhood(i, ell, rp, ci, va, cf, theta, cmax, agg ? &ag : NULL, &w);
         if (s < 0) {
 #pragma omp atomic write
           err = 1;
@@ -368,6 +427,8 @@ int orc_build_R(int32_t n, const int32_t* rp, const int32_t* ci, const double* v
   }
   free(sizes);
   free(cmax);
+  free((void*)ag.mrp);
+  free((void*)ag.mem);
   if (err) { free(clist); return ORC_ERR_NOMEM; }
   if (bad_row) *bad_row = first_bad;
 

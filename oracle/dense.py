@@ -43,22 +43,29 @@ def strength_transposed(A: np.ndarray, theta: float = 0.0) -> np.ndarray:
     return off & (M != 0) & (mag >= theta * rowmax[:, None])
 
 
-def neighbourhoods(A: np.ndarray, cf: np.ndarray, ell: int, theta: float = 0.0):
-    """dict C-point -> sorted array of its distance-ell F-neighbourhood."""
+def neighbourhoods(A: np.ndarray, cf: np.ndarray, ell: int, theta: float = 0.0, agg=None):
+    """dict C-point -> sorted array of its distance-ell F-neighbourhood.
+
+    agg (optional): the root C-point of every point's aggregate, or -1; then
+    T is the aggregation operator (column c = the F-points of c's aggregate)
+    instead of S_fc."""
     S = strength_transposed(A, theta).astype(np.int64)
     F = cf == 0
     out = {}
     for c in np.nonzero(cf != 0)[0]:
-        reach = (S[:, c] > 0) & F  # T = S_fc, column c
+        if agg is None:
+            reach = (S[:, c] > 0) & F  # T = S_fc, column c
+        else:
+            reach = (np.asarray(agg) == c) & F  # T = aggregation operator, column c
         for _ in range(ell - 1):
             reach = reach | ((S @ reach.astype(np.int64)) > 0) & F
         out[int(c)] = np.nonzero(reach)[0]
     return out
 
 
-def lair_rows(A: np.ndarray, cf: np.ndarray, ell: int, theta: float = 0.0):
+def lair_rows(A: np.ndarray, cf: np.ndarray, ell: int, theta: float = 0.0, agg=None):
     """Unconstrained rows: dict C-point -> (N, z) with (A[N,N])^T z = -A[i,N]^T."""
-    nb = neighbourhoods(A, cf, ell, theta)
+    nb = neighbourhoods(A, cf, ell, theta, agg)
     rows = {}
     for i, N in nb.items():
         if len(N) == 0:

@@ -26,12 +26,12 @@ from . import dense
 
 
 def algorithm1_R(A: np.ndarray, cf: np.ndarray, B: np.ndarray, ell: int, k: int = 1,
-                 fit_constraint: bool = True, theta: float = 0.0):
+                 fit_constraint: bool = True, theta: float = 0.0, agg=None):
     """Dense R (n_c x n) from the literal Algorithm 1 on A^T (strength threshold theta)."""
     n = A.shape[0]
     At = A.T
     C = [int(i) for i in np.nonzero(cf != 0)[0]]
-    nb = dense.neighbourhoods(A, cf, ell, theta)  # pattern of row c of R == column c of W(A^T)
+    nb = dense.neighbourhoods(A, cf, ell, theta, agg)  # pattern of row c of R == column c of W(A^T)
     # stacked unknown vector w*: the nonzeros of W in compressed-column order
     slots = []  # (c, f)
     col_start = {}

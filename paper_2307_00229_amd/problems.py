@@ -54,6 +54,7 @@ class Problem:
     ell: int
     meta: dict = dataclasses.field(default_factory=dict)
     theta: float = 0.0  # strength threshold of the pattern (0: every stored nonzero)
+    agg: Optional[np.ndarray] = None  # int32 [n]: root C-point of each point's aggregate, or -1
 
     @property
     def nnz(self) -> int:
@@ -315,3 +316,28 @@ def random_sparse(n: int, density: float, seed: int, *, c_frac: float = 0.3, ell
         Bv = B
     return Problem(f"rand_n{n}_s{seed}", n, np.asarray(rp, np.int32), np.asarray(ci, np.int32),
                    np.asarray(va, np.float64), cf, Bv, ell, dict(seed=seed))
+
+
+def greedy_aggregates(p: Problem) -> Problem:
+    """The same matrix with an aggregation-based C/F splitting: a sequential
+    greedy aggregation of A's graph (a point whose neighbours are all still
+    free seeds an aggregate with them; free points left join the aggregate of
+    their first aggregated neighbour, or seed a singleton).  Seeds become the
+    C-points, every other point an F-point; agg[j] = the seed of j's
+    aggregate.  The splitting is an input of the setup, like cf."""
+    n = p.n
+    rp, ci = p.row_ptr, p.col_idx
+    agg = np.full(n, -1, np.int64)
+    for i in range(n):
+        nb = ci[rp[i]:rp[i + 1]]
+        nb = nb[nb != i]
+        if agg[i] < 0 and np.all(agg[nb] < 0):
+            agg[i] = i
+            agg[nb] = i
+    for i in range(n):
+        if agg[i] < 0:
+            nb = ci[rp[i]:rp[i + 1]]
+            nb = nb[(nb != i) & (agg[nb] >= 0)]
+            agg[i] = agg[nb[0]] if len(nb) else i
+    cf = (agg == np.arange(n)).astype(np.int8)
+    return dataclasses.replace(p, name=p.name + "_agg", cf=cf, agg=agg.astype(np.int32))
