@@ -140,6 +140,24 @@ void clair_ctx_destroy(clair_ctx_t* ctx);
 int clair_build_R(const clair_csr_t* A, const int8_t* cf_marker, const double* B, int32_t ell,
                   clair_csr_out_t* R_out);
 
+/*
+ * clair_build_R_agg -- clair_build_R_batched with the aggregation-based base
+ * pattern (Section 3.1.3: with aggregation-based coarsening, T is the
+ * aggregation operator).  agg[k]: device int32[n], the root C-point of every
+ * point's aggregate, or -1; an F-point j belongs to root r = agg[k][j] when r
+ * is a C-point index in range (any other value: to no aggregate).  Row i of
+ * R starts from the F-points of i's aggregate and adds ell - 1 steps of the
+ * search (with the context's strength threshold); at ell = 1 it is the
+ * aggregate.  agg[k] may be NULL for a matrix that keeps the classical
+ * pattern.  Mixed precision only (CLAIR_PREC_FP64 returns
+ * CLAIR_ERR_UNSUPPORTED); plans and graphs take the classical pattern.
+ * Sizes and capacities as clair_build_R_batched (a synchronous call with too
+ * small capacities reports the sizes).
+ */
+int clair_build_R_agg(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf_marker,
+                      const int32_t* const* agg, const double* const* B, const int32_t* ell, clair_csr_out_t* R_out,
+                      const clair_opts_t* opts, clair_info_t* info);
+
 /* Same for one matrix with explicit context, options and info (info may be NULL). */
 int clair_build_R_ex(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_marker,
                      const double* B, int32_t ell, clair_csr_out_t* R_out, const clair_opts_t* opts,

@@ -30,7 +30,7 @@ EXPORTED = [
     "clair_ctx_create", "clair_ctx_destroy", "clair_build_R", "clair_build_R_ex", "clair_build_R_batched",
     "clair_ctx_info", "clair_size_R", "clair_ctx_stage_times", "clair_ctx_set_tuning", "clair_ctx_get_tuning",
     "clair_ctx_set_strength", "clair_ctx_get_strength", "clair_transpose", "clair_build_P",
-    "clair_spgemm", "clair_galerkin", "clair_smooth_B",
+    "clair_spgemm", "clair_galerkin", "clair_smooth_B", "clair_build_R_agg",
     "clair_autotune", "clair_graph_create", "clair_graph_launch", "clair_graph_destroy", "clair_graph_info",
     "clair_plan_create", "clair_plan_execute", "clair_plan_info", "clair_plan_destroy",
     "clair_strerror", "clair_last_error",
@@ -122,6 +122,9 @@ def load_library(path: str = LIB_PATH):
         "clair_galerkin": ([P, ctypes.POINTER(CsrIn), ctypes.POINTER(CsrIn), ctypes.POINTER(CsrIn), I32,
                             ctypes.POINTER(CsrOut), P], ctypes.c_int),
         "clair_smooth_B": ([P, ctypes.POINTER(CsrIn), P, P, P, I32, ctypes.c_double, I32, P], ctypes.c_int),
+        "clair_build_R_agg": ([P, I32, ctypes.POINTER(CsrIn), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
+                               ctypes.POINTER(I32), ctypes.POINTER(CsrOut), ctypes.POINTER(Opts),
+                               ctypes.POINTER(Info)], ctypes.c_int),
         "clair_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "clair_last_error": ([], ctypes.c_char_p),
     }
@@ -460,6 +463,43 @@ def clair_smooth_B(A: CSR, cf: torch.Tensor, B: torch.Tensor, iterations: int, o
     if st:
         raise ClairError(st, "clair_smooth_B")
     return out
+
+
+def clair_build_R_agg(As: Sequence[CSR], cfs, aggs, Bs, ells, *, ctx: Optional[Context] = None, stream=None,
+                      check: bool = True):
+    """Batched setup with the aggregation-based base pattern (aggs[k]: int32
+    root of every point's aggregate, or -1; None keeps the classical
+    pattern).  Returns (outs, infos, status); the sizes are read by a first
+    call with empty buffers."""
+    lib = load_library()
+    ctx = ctx or Context()
+    nmat = len(As)
+    for a in aggs:
+        if a is not None:
+            _check_dev(a, torch.int32, "agg")
+    aggp = (ctypes.c_void_p * nmat)(*[None if a is None else a.data_ptr() for a in aggs]) if nmat else None
+    o = Opts(_stream_ptr(stream), CLAIR_PREC_MIXED, 0, 0, 0)
+
+    def call(outs_c):
+        nm, Ac, cfp, Bp, ellv, _ = _batch_args(As, cfs, Bs, ells, [ROut(0, 0)] * nmat)
+        infos = (Info * nmat)()
+        st = lib.clair_build_R_agg(ctx.handle, nm, Ac, cfp, aggp, Bp, ellv, outs_c, ctypes.byref(o), infos)
+        return st, infos
+
+    probe = (CsrOut * nmat)()
+    st, infos = call(probe)
+    if st not in (CLAIR_OK, CLAIR_ERR_CAPACITY):
+        if check:
+            raise ClairError(st, "clair_build_R_agg")
+        return None, [i.as_dict() for i in infos], st
+    outs = [ROut(int(pr.n_rows), int(pr.nnz), device=As[0].row_ptr.device) for pr in probe]
+    outs_c = (CsrOut * nmat)(*[ob.c() for ob in outs])
+    st, infos = call(outs_c)
+    for ob, oc in zip(outs, outs_c):
+        ob.n_c, ob.nnz = int(oc.n_rows), int(oc.nnz)
+    if st and check:
+        raise ClairError(st, "clair_build_R_agg")
+    return outs, [i.as_dict() for i in infos], st
 
 
 def clair_autotune(ctx: Context, As, cfs, Bs, ells, outs, reps: int = 3, stream=None):

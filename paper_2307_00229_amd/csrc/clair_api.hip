@@ -71,12 +71,12 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
   size_t desc, st, cnt, chunk_nc, chunk_nnz, chunk_rbase, chunk_nzbase, chunk_mat, chunk_bins, row_block_chunk, clocal, lnz, dsum, rsum,
-      slotA, slotB, binC, bigq, big_size, ovf, cmax, total;
+      slotA, slotB, binC, bigq, big_size, ovf, cmax, agg_cnt, agg_rp, agg_list, agg_sums, total;
   size_t head_bytes;  // desc + st + counters (the uploaded head)
   int64_t capC;
 };
 
-Layout make_layout(int nmat, int nchunks, int64_t n_total, int GA) {
+Layout make_layout(int nmat, int nchunks, int64_t n_total, int GA, bool any_agg) {
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -111,6 +111,11 @@ Layout make_layout(int nmat, int nchunks, int64_t n_total, int GA) {
   L.big_size = take(sizeof(int32_t) * (n_total + 1));
   L.ovf = take(sizeof(int32_t) * (nchunks + 1));
   L.cmax = take(sizeof(double) * (n_total + 1));
+  const int64_t na = any_agg ? n_total : 0;
+  L.agg_cnt = take(sizeof(int32_t) * (na + 1));
+  L.agg_rp = take(sizeof(int32_t) * (na + 2));
+  L.agg_list = take(sizeof(int32_t) * (na + 1));
+  L.agg_sums = take(sizeof(int32_t) * (na / 1024 + 4));
   L.total = o;
   return L;
 }
@@ -233,6 +238,7 @@ struct Batch {
   int nchunks;
   int64_t n_total;
   bool any_B;
+  bool any_agg = false;
   Layout L;
   Work w;
 };
@@ -250,17 +256,20 @@ int check_args(int32_t nmat, const clair_csr_t* A, const int8_t* const* cf, cons
 }
 
 int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf,
-            const double* const* B, const int32_t* ell, const clair_csr_out_t* R, Batch* b) {
+            const double* const* B, const int32_t* ell, const clair_csr_out_t* R, Batch* b,
+            const int32_t* const* agg = nullptr) {
   b->nmat = nmat;
   b->nchunks = 0;
   b->n_total = 0;
   b->any_B = false;
+  b->any_agg = false;
   for (int m = 0; m < nmat; ++m) {
     b->nchunks += (A[m].n + c->chunk - 1) / c->chunk;
     b->n_total += A[m].n;
     b->any_B |= (B && B[m]);
+    b->any_agg |= (agg && agg[m]);
   }
-  b->L = make_layout(nmat, b->nchunks, b->n_total, c->group);
+  b->L = make_layout(nmat, b->nchunks, b->n_total, c->group, b->any_agg);
   HIPCHK(c->ws.ensure(b->L.total));
   HIPCHK(c->stage.ensure(b->L.head_bytes));
   HIPCHK(c->readback.ensure(b->L.head_bytes));
@@ -292,6 +301,10 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
   w.bigq = reinterpret_cast<int32_t*>(base + b->L.bigq);
   w.big_size = reinterpret_cast<int32_t*>(base + b->L.big_size);
   w.cmax = reinterpret_cast<double*>(base + b->L.cmax);
+  w.agg_cnt = reinterpret_cast<int32_t*>(base + b->L.agg_cnt);
+  w.agg_rp = reinterpret_cast<int32_t*>(base + b->L.agg_rp);
+  w.agg_list = reinterpret_cast<int32_t*>(base + b->L.agg_list);
+  w.agg_sums = reinterpret_cast<int32_t*>(base + b->L.agg_sums);
   w.scratch = static_cast<double*>(c->scratch.p);
   w.scratch_slots = c->scratch_slots;
   w.nmat = nmat;
@@ -326,6 +339,9 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
     d.fine0 = fine0;
     d.cmax = w.cmax + fine0;
     d.theta = c->theta;
+    d.agg = (agg && agg[m]) ? agg[m] : nullptr;
+    d.agg_rp = d.agg ? w.agg_rp + fine0 : nullptr;
+    d.agg_list = d.agg ? w.agg_list : nullptr;
     hd[m] = d;
     chunk0 += d.nchunks;
     fine0 += A[m].n;
@@ -418,6 +434,11 @@ int enqueue_symbolic(clair_ctx* c, Batch& b, hipStream_t s, bool validate, bool 
     HIPCHK(launch_validate(b.w, occupancy_blocks(c, 4), s));
     timing_mark(c, timing, s, "validate");
   }
+  if (b.any_agg) {
+    HIPCHK(launch_agg_lists(b.w, b.n_total, occupancy_blocks(c, 4), c->cus, s));
+    if (capture_check(c->capturing, s, "aggregate lists", __LINE__)) return CLAIR_ERR_HIP;
+    timing_mark(c, timing, s, "aggregates");
+  }
   if (c->theta > 0.0) {
     HIPCHK(launch_colmax(b.w, b.n_total, occupancy_blocks(c, 4), s));
     if (capture_check(c->capturing, s, "k_colmax", __LINE__)) return CLAIR_ERR_HIP;
@@ -463,13 +484,14 @@ int first_error(const MatStatus* hs, int nmat) {
 }
 
 int run_mixed(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf, const double* const* B,
-              const int32_t* ell, clair_csr_out_t* R, const clair_opts_t* o, clair_info_t* info) {
+              const int32_t* ell, clair_csr_out_t* R, const clair_opts_t* o, clair_info_t* info,
+              const int32_t* const* agg = nullptr) {
   const hipStream_t s = static_cast<hipStream_t>(o ? o->stream : nullptr);
   const bool async = o && o->async;
   const bool timing = o && o->timing;
   const bool validate = o && o->validate;
   Batch b;
-  int rc = prepare(c, nmat, A, cf, B, ell, R, &b);
+  int rc = prepare(c, nmat, A, cf, B, ell, R, &b, agg);
   if (rc) return rc;
   c->last_nmat = nmat;
   c->last_stream = s;
@@ -707,6 +729,23 @@ int clair_build_R_batched(clair_ctx_t* c, int32_t nmat, const clair_csr_t* A, co
   if (o && o->precision != CLAIR_PREC_MIXED) return CLAIR_ERR_INVALID;
   try {
     return run_mixed(c, nmat, A, cf, B, ell, R, o, info);
+  } catch (...) {
+    return CLAIR_ERR_NOMEM;
+  }
+}
+
+int clair_build_R_agg(clair_ctx_t* c, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf,
+                      const int32_t* const* agg, const double* const* B, const int32_t* ell, clair_csr_out_t* R,
+                      const clair_opts_t* o, clair_info_t* info) {
+  if (!c) return CLAIR_ERR_INVALID;
+  int rc = check_args(nmat, A, cf, ell, R);
+  if (rc) return rc;
+  if (nmat > 0 && !agg) return CLAIR_ERR_INVALID;
+  if (nmat == 0) return CLAIR_OK;
+  if (o && o->precision == CLAIR_PREC_FP64) return CLAIR_ERR_UNSUPPORTED;
+  if (o && o->precision != CLAIR_PREC_MIXED) return CLAIR_ERR_INVALID;
+  try {
+    return run_mixed(c, nmat, A, cf, B, ell, R, o, info, agg);
   } catch (...) {
     return CLAIR_ERR_NOMEM;
   }

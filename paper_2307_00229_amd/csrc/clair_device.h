@@ -41,6 +41,13 @@ struct MatDesc {
   int64_t fine0;    // offset of this matrix in fine-indexed workspaces
   const double* cmax;  // largest off-diagonal |a_wv| of column v (filled when theta > 0)
   double theta;        // strength threshold of the search (0: every stored nonzero)
+  // aggregation-based base pattern (null: classical, T = S_fc): the caller's
+  // root of every point's aggregate, and the member lists built from it
+  // (root c's F-members at agg_list[agg_rp[c] .. agg_rp[c+1]), agg_rp
+  // offset to the matrix)
+  const int32_t* agg;
+  const int32_t* agg_rp;
+  const int32_t* agg_list;
 };
 
 // Pointers into device (global) memory.  Pointers that kernels load from a
@@ -74,6 +81,9 @@ struct GDesc {
   int64_t fine0;
   gptr<const double> cmax;
   double theta;
+  gptr<const int32_t> agg;
+  gptr<const int32_t> agg_rp;
+  gptr<const int32_t> agg_list;
 };
 
 __device__ __forceinline__ GDesc gview(const MatDesc& m) {
@@ -96,6 +106,9 @@ __device__ __forceinline__ GDesc gview(const MatDesc& m) {
   g.fine0 = m.fine0;
   g.cmax = to_global(m.cmax);
   g.theta = m.theta;
+  g.agg = to_global(m.agg);
+  g.agg_rp = to_global(m.agg_rp);
+  g.agg_list = to_global(m.agg_list);
   return g;
 }
 
@@ -156,6 +169,10 @@ struct Work {
   int32_t* bigq;           // [capC] those rows, c * chunk + t
   int32_t* big_size;       // [n_total] their sizes, until the chunk's prefix is redone
   double* cmax;            // [n_total] column maxima for the strength test (theta > 0)
+  int32_t* agg_cnt;        // [n_total] aggregate sizes, then fill cursors (aggregates given)
+  int32_t* agg_rp;         // [n_total + 1] member-list offsets, batch-wide
+  int32_t* agg_list;       // [n_total] members (matrix-local indices), sorted per root
+  int32_t* agg_sums;       // scan scratch
   double* scratch;        // FP64 blocks for oversized rows: scratch_slots * kMaxBlock^2 (may be null)
   int64_t scratch_slots;
   int32_t nmat;
@@ -290,9 +307,14 @@ template <int SM>
 __device__ __forceinline__ int reg_bfs(RegSet<SM>& S, int n, int i, int ell, gptr<const int32_t> __restrict__ rp,
                                        gptr<const int32_t> __restrict__ ci, gptr<const double> __restrict__ va,
                                        gptr<const int8_t> __restrict__ cf, double theta,
-                                       gptr<const double> __restrict__ cmax) {
+                                       gptr<const double> __restrict__ cmax, gptr<const int32_t> __restrict__ mrp,
+                                       gptr<const int32_t> __restrict__ mem) {
   S.clear();
-  reg_expand(S, n, i, rp[i], rp[i + 1], 1, ci, va, cf, theta, cmax);
+  if (mrp) {  // aggregation-based: the aggregate's F-points (sorted, in range)
+    for (int e = mrp[i]; e < mrp[i + 1] && !S.ovf; ++e) S.insert(mem[e], 1);
+  } else {
+    reg_expand(S, n, i, rp[i], rp[i + 1], 1, ci, va, cf, theta, cmax);
+  }
   for (int L = 2; L <= ell && !S.ovf; ++L) {
     // expand the points found at level L-1 in ascending order (from a
     // snapshot: inserts move entries); only compile-time register indices.
@@ -396,9 +418,14 @@ template <int SM>
 __device__ __forceinline__ int regm_bfs(RegSetM<SM>& S, int n, int i, int ell, gptr<const int32_t> __restrict__ rp,
                                         gptr<const int32_t> __restrict__ ci, gptr<const double> __restrict__ va,
                                         gptr<const int8_t> __restrict__ cf, double theta,
-                                        gptr<const double> __restrict__ cmax) {
+                                        gptr<const double> __restrict__ cmax, gptr<const int32_t> __restrict__ mrp,
+                                        gptr<const int32_t> __restrict__ mem) {
   S.clear();
-  regm_expand(S, n, i, rp, ci, va, cf, theta, cmax);
+  if (mrp) {
+    for (int e = mrp[i]; e < mrp[i + 1] && !S.ovf; ++e) S.insert(mem[e]);
+  } else {
+    regm_expand(S, n, i, rp, ci, va, cf, theta, cmax);
+  }
   for (int L = 2; L <= ell && !S.ovf; ++L) {
     S.todo = S.cur;
     S.cur = 0;

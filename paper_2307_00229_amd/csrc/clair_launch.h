@@ -13,6 +13,8 @@ constexpr int kLdsBlockMax = 64;  // workgroup FP64 solver keeps blocks up to th
 // mixed (default) path
 hipError_t launch_clear_sums(const Work& w, int64_t n_total, int blocks, hipStream_t s);
 hipError_t launch_validate(const Work& w, int blocks, hipStream_t s);
+// member lists of the aggregates of the matrices given with them (w.agg_*)
+hipError_t launch_agg_lists(const Work& w, int64_t n_total, int blocks, int cus, hipStream_t s);
 // column maxima of every matrix with theta > 0 (w.cmax, batch-wide fine numbering)
 hipError_t launch_colmax(const Work& w, int64_t n_total, int blocks, hipStream_t s);
 hipError_t launch_count(const Work& w, hipStream_t s);

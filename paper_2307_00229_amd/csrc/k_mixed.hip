@@ -68,14 +68,29 @@ struct WideBuf {
 // (block-uniform).  Must be called by all kNT threads of the workgroup.
 __device__ int block_bfs(int n, int i, int ell, gptr<const int32_t> __restrict__ rp, gptr<const int32_t> __restrict__ ci,
                          gptr<const double> __restrict__ va, gptr<const int8_t> __restrict__ cf, double theta,
-                         gptr<const double> __restrict__ cmax, WideBuf& b, int** out) {
+                         gptr<const double> __restrict__ cmax, gptr<const int32_t> __restrict__ mrp,
+                         gptr<const int32_t> __restrict__ mem, WideBuf& b, int** out) {
   const int tid = threadIdx.x;
   constexpr int nt = kNT;
   int* cur = b.nb0;
   int* nxt = b.nb1;
   int s = 0;
   int fsz = 1;  // level-0 frontier is {i}
-  for (int depth = 1; depth <= ell && fsz > 0; ++depth) {
+  int d0 = 1;
+  if (mrp) {
+    // aggregation-based: level 1 is the aggregate's F-points (sorted)
+    const int a0 = mrp[i], na = mrp[i + 1] - a0;
+    if (na > kWN) return -1;
+    for (int t = tid; t < na; t += nt) {
+      cur[t] = mem[a0 + t];
+      b.fr[t] = mem[a0 + t];
+    }
+    __syncthreads();
+    s = na;
+    fsz = na;
+    d0 = 2;
+  }
+  for (int depth = d0; depth <= ell && fsz > 0; ++depth) {
     // row lengths of the frontier, prefix
     const int per = (fsz + nt - 1) / nt;
     const int t0 = tid * per, t1 = min(t0 + per, fsz);
@@ -367,13 +382,13 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
     // a row of seven or more entries (six or more neighbours) at ell >= 2
     // nearly always reaches more than 8 points: it goes straight to the
     // 32-point search below (either search gives the same set)
-    if (d.ell >= 2 && d.rp[s_rows[t] + 1] - d.rp[s_rows[t]] >= 7) {
+    if (!d.agg_rp && d.ell >= 2 && d.rp[s_rows[t] + 1] - d.rp[s_rows[t]] >= 7) {
       s_size[t] = -1;
       s_list[atomicAdd(&s_nlist, 1)] = t;
       continue;
     }
     RegSet<8> S;
-    const int sz = reg_bfs(S, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf, d.theta, d.cmax);
+    const int sz = reg_bfs(S, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf, d.theta, d.cmax, d.agg_rp, d.agg_list);
     if (sz >= 0) {
       s_size[t] = sz;
       ++inA;  // sz <= 8 <= lim
@@ -396,7 +411,8 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
     for (int k = tid; k < nl2; k += kNT) {
       const int t = s_list[k];
       RegSetM<32> S;
-      const int sz = regm_bfs(S, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf, d.theta, d.cmax);
+      const int sz = regm_bfs(S, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf, d.theta, d.cmax, d.agg_rp,
+                              d.agg_list);
       if (sz < 0) {
         s_size[t] = 0;
         w.clocal[base + t] = -(s_rows[t] + 1);
@@ -474,7 +490,7 @@ __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
     const int64_t base = d.fine0 + (int64_t)(c - d.chunk0) * w.chunk;
     const int i = -w.clocal[base + t] - 1;
     int* nl;
-    const int s = block_bfs(d.n, i, d.ell, d.rp, d.ci, d.va, d.cf, d.theta, d.cmax, bb, &nl);
+    const int s = block_bfs(d.n, i, d.ell, d.rp, d.ci, d.va, d.cf, d.theta, d.cmax, d.agg_rp, d.agg_list, bb, &nl);
     __syncthreads();
     if (tid == 0) {
       w.big_size[base + t] = s < 0 ? 0 : s;
@@ -1803,7 +1819,7 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
       const int i = ri.i;
       if (tid == 0) d.Rrp[ri.r] = ri.off;
       int* N;
-      const int s = block_bfs(d.n, i, d.ell, d.rp, d.ci, d.va, d.cf, d.theta, d.cmax, bb, &N);
+      const int s = block_bfs(d.n, i, d.ell, d.rp, d.ci, d.va, d.cf, d.theta, d.cmax, d.agg_rp, d.agg_list, bb, &N);
       __syncthreads();
       if (s != ri.s) {
         if (tid == 0) flag_row(st, s < 0 ? ST_UNSUPPORTED : ST_INVALID, i);
@@ -2062,6 +2078,62 @@ __global__ void k_colmax(Work w, int64_t n_total) {
   }
 }
 
+// Member lists of the aggregates (matrices given with aggregates only):
+// count per root, scan (host), scatter through cursors, sort per root.  An
+// F-point j joins root r = agg[j] when r is a C-point index in range.
+__device__ __forceinline__ int fine_matrix(const Work& w, int64_t g) {
+  int lo = 0, hi = w.nmat - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (w.desc[mid].fine0 <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int agg_root(const GDesc& d, int j) {
+  if (!d.agg || d.cf[j] != 0) return -1;
+  const int r = d.agg[j];
+  return ((unsigned)r < (unsigned)d.n && d.cf[r] != 0) ? r : -1;
+}
+
+__global__ void k_agg_count(Work w, int64_t n_total) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n_total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int m = fine_matrix(w, g);
+    const GDesc d = gview(w.desc[m]);
+    const int r = agg_root(d, (int)(g - d.fine0));
+    if (r >= 0) atomicAdd(&w.agg_cnt[d.fine0 + r], 1);
+  }
+}
+
+__global__ void k_agg_fill(Work w, int64_t n_total) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n_total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int m = fine_matrix(w, g);
+    const GDesc d = gview(w.desc[m]);
+    const int j = (int)(g - d.fine0);
+    const int r = agg_root(d, j);
+    if (r >= 0) w.agg_list[w.agg_rp[d.fine0 + r] + atomicAdd(&w.agg_cnt[d.fine0 + r], 1)] = j;
+  }
+}
+
+__global__ void k_agg_sort(Work w, int64_t n_total) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n_total; g += (int64_t)gridDim.x * blockDim.x) {
+    const int e0 = w.agg_rp[g], e1 = w.agg_rp[g + 1];
+    for (int a = e0 + 1; a < e1; ++a) {
+      const int k = w.agg_list[a];
+      int b = a - 1;
+      while (b >= e0 && w.agg_list[b] > k) {
+        w.agg_list[b + 1] = w.agg_list[b];
+        --b;
+      }
+      w.agg_list[b + 1] = k;
+    }
+  }
+}
+
+__global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) a[g] = v;
+}
+
 __global__ void k_clear_sums(Work w, int64_t n) {
   for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
     w.dsum[j] = 0.0;
@@ -2086,6 +2158,17 @@ hipError_t launch_clear_sums(const Work& w, int64_t n_total, int blocks, hipStre
 hipError_t launch_colmax(const Work& w, int64_t n_total, int blocks, hipStream_t s) {
   hipLaunchKernelGGL(k_colmax_clear, dim3(blocks), dim3(256), 0, s, w, n_total);
   hipLaunchKernelGGL(k_colmax, dim3(blocks), dim3(256), 0, s, w, n_total);
+  return hipGetLastError();
+}
+
+hipError_t launch_agg_lists(const Work& w, int64_t n_total, int blocks, int cus, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, s, w.agg_cnt, n_total, 0);
+  hipLaunchKernelGGL(k_agg_count, dim3(blocks), dim3(256), 0, s, w, n_total);
+  hipError_t e = launch_exclusive_scan(w.agg_cnt, (int)n_total, w.agg_rp, w.agg_sums, cus, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, s, w.agg_cnt, n_total, 0);
+  hipLaunchKernelGGL(k_agg_fill, dim3(blocks), dim3(256), 0, s, w, n_total);
+  hipLaunchKernelGGL(k_agg_sort, dim3(blocks), dim3(256), 0, s, w, n_total);
   return hipGetLastError();
 }
 
