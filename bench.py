@@ -206,6 +206,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--aggregates", action="store_true",
+                    help="C/F splitting and base pattern from greedy aggregates (clair_build_R_agg); "
+                         "direct launches only, no plain form, graph or plan")
     ap.add_argument("--theta", type=float, default=0.0,
                     help="strength threshold of the pattern (0: every stored nonzero)")
     ap.add_argument("--no-plan", action="store_true", help="skip the fixed-pattern (plan) measurement")
@@ -233,6 +236,10 @@ def main():
         import dataclasses
 
         problems = [dataclasses.replace(p, theta=args.theta) for p in problems]
+    if args.aggregates:
+        from paper_2307_00229_amd import problems as P
+
+        problems = [P.greedy_aggregates(p) for p in problems]
     As = [clair.CSR.from_problem(p, dev) for p in problems]
     cfs = [torch.from_numpy(p.cf).to(dev) for p in problems]
     Bs = [torch.from_numpy(p.B).to(dev) for p in problems]
@@ -240,18 +247,25 @@ def main():
     stream = torch.cuda.Stream()
     ctx = clair.Context()
     ctx.set_strength(args.theta)
+    aggs = [torch.from_numpy(p.agg).to(dev) for p in problems] if args.aggregates else None
     with torch.cuda.stream(stream):
-        n_c_list, nnz_list = clair.clair_size_R(As, cfs, ells, ctx=ctx, stream=stream)
+        if aggs is None:
+            n_c_list, nnz_list = clair.clair_size_R(As, cfs, ells, ctx=ctx, stream=stream)
+        else:
+            sized, _, _ = clair.clair_build_R_agg(As, cfs, aggs, Bs, ells, ctx=ctx, stream=stream)
+            n_c_list, nnz_list = [o.n_c for o in sized], [o.nnz for o in sized]
         outs = [clair.ROut(nc, nz, dev) for nc, nz in zip(n_c_list, nnz_list)]
-        if not args.no_autotune:
+        if not args.no_autotune and aggs is None:
             clair.clair_autotune(ctx, As, cfs, Bs, ells, outs, reps=3, stream=stream)
         tuning = ctx.get_tuning()
         rows = sum(n_c_list)
 
-        direct_step = clair.BatchedCall(ctx, As, cfs, Bs, ells, outs, async_=True, stream=stream)
+        direct_step = clair.BatchedCall(ctx, As, cfs, Bs, ells, outs, async_=True, stream=stream, aggs=aggs)
 
         graph, graph_error = None, None
         try:
+            if aggs is not None:
+                raise clair.ClairError(clair.CLAIR_ERR_UNSUPPORTED, "graphs take the classical pattern")
             # capture on a stream of its own: a failed capture must not leave
             # the measurement stream unusable
             cap_stream = torch.cuda.Stream()
@@ -293,27 +307,30 @@ def main():
 
         # dominant kernel: per-stage HIP events on the library's stream
         ctx.stage_times()
-        timed_step = clair.BatchedCall(ctx, As, cfs, Bs, ells, outs, async_=True, timing=True, stream=stream)
+        timed_step = clair.BatchedCall(ctx, As, cfs, Bs, ells, outs, async_=True, timing=True, stream=stream,
+                                       aggs=aggs)
         for _ in range(args.steps):
             timed_step()
         torch.cuda.synchronize()
         stages = {k: v / args.steps for k, v in ctx.stage_times().items()}
 
-        # plain FP64 per-row form on the same inputs
-        plain_ctx = clair.Context()
-        plain_ctx.set_strength(args.theta)
-        outs_p = [clair.ROut(nc, nz, dev) for nc, nz in zip(n_c_list, nnz_list)]
+        # plain FP64 per-row form on the same inputs (classical pattern only)
+        outs_p, t_plain = None, None
+        if aggs is None:
+            plain_ctx = clair.Context()
+            plain_ctx.set_strength(args.theta)
+            outs_p = [clair.ROut(nc, nz, dev) for nc, nz in zip(n_c_list, nnz_list)]
 
-        plain_step = clair.BatchedCall(plain_ctx, As, cfs, Bs, ells, outs_p, precision=clair.CLAIR_PREC_FP64,
-                                       async_=False, stream=stream)
+            plain_step = clair.BatchedCall(plain_ctx, As, cfs, Bs, ells, outs_p, precision=clair.CLAIR_PREC_FP64,
+                                           async_=False, stream=stream)
 
-        p_dev, p_wall = timed(plain_step, args.plain_steps, 2)
-        t_plain = p_wall / args.plain_steps
+            p_dev, p_wall = timed(plain_step, args.plain_steps, 2)
+            t_plain = p_wall / args.plain_steps
 
         # repeated setups on a fixed pattern: symbolic phase once (a plan),
         # numeric phase per step (reported beside the headline, not as it)
         plan_res = None
-        if not args.no_plan:
+        if not args.no_plan and aggs is None:
             outs_pl = [clair.ROut(nc, nz, dev) for nc, nz in zip(n_c_list, nnz_list)]
             plan = clair.Plan(ctx, As, cfs, ells, outs_pl, stream=stream)
 
@@ -330,7 +347,7 @@ def main():
         # the rest of a two-level setup on the first matrix (synchronous calls):
         # A^T, P = W(A), and A_c = R A P with the R measured above
         next_level = None
-        if not args.no_next_level:
+        if not args.no_next_level and aggs is None:
             next_level = time_next_level(clair, ctx, As[0], cfs[0], Bs[0], ells[0], outs[0], stream)
 
         if args.copy_probe_mib:
@@ -343,14 +360,14 @@ def main():
     gates = check_against_oracle(problems, outs)
     if plan_res is not None:
         plan_res["gates"] = check_against_oracle(problems, plan_res.pop("_outs"))
-    gates_plain = check_against_oracle(problems, outs_p)
+    gates_plain = check_against_oracle(problems, outs_p) if outs_p is not None else None
 
     whole_bytes, kern_bytes = algorithmic_bytes(problems, n_c_list, nnz_list)
     t_kern = stages.get("numeric", float("nan")) / 1e3
     achieved = kern_bytes / t_kern / 1e9 if t_kern > 0 else None
     src_hash = kernel_source_hash()
     # the committed counters were taken at theta = 0
-    traffic = read_traffic_profile(args.workload, src_hash) if args.theta == 0 else None
+    traffic = read_traffic_profile(args.workload, src_hash) if (args.theta == 0 and not args.aggregates) else None
     roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=(achieved / HBM_PEAK_GBS) if achieved else None, traffic=traffic,
                     kernel="k_numeric", kernel_ms=t_kern * 1e3, algorithmic_bytes_per_launch=kern_bytes,
@@ -375,11 +392,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}", "matrices": len(problems),
                    "R_rows": rows, "nnz_R": int(sum(nnz_list)), "launch": best, "tuning": tuning,
-                   "theta": args.theta,
+                   "theta": args.theta, "aggregates": bool(args.aggregates),
                    "parallelism": "single GPU"},
-        "plain_fp64": {"value": rows / t_plain, "unit": "rows/s", "ms_per_step": t_plain * 1e3,
-                       "gates": gates_plain},
-        "speedup_vs_plain_fp64": t_plain / t_mixed,
+        "plain_fp64": ({"value": rows / t_plain, "unit": "rows/s", "ms_per_step": t_plain * 1e3,
+                        "gates": gates_plain} if t_plain else None),
+        "speedup_vs_plain_fp64": (t_plain / t_mixed) if t_plain else None,
         "plan_numeric_only": plan_res,
         "next_level": next_level,
         "modes_ms_per_step": {k: v["wall_s"] / args.steps * 1e3 for k, v in results.items()},

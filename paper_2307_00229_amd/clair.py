@@ -345,19 +345,27 @@ class BatchedCall:
     calls on fixed buffers (benchmarks, solver setups on a fixed pattern)."""
 
     def __init__(self, ctx: Context, As, cfs, Bs, ells, outs, *, precision: int = CLAIR_PREC_MIXED,
-                 async_: bool = True, timing: bool = False, stream=None):
+                 async_: bool = True, timing: bool = False, stream=None, aggs=None):
         self._lib = load_library()
         self.ctx = ctx
         self.nmat, self._Ac, self._cfp, self._Bp, self._ellv, self._Rc = _batch_args(As, cfs, Bs, ells, outs)
         self._opts = Opts(_stream_ptr(stream), precision, 1 if async_ else 0, 0, 1 if timing else 0)
         self._inf = (Info * self.nmat)()
-        self._keep = (As, cfs, Bs, outs)
+        # aggregation-based pattern (clair_build_R_agg) when aggs is given
+        self._aggp = None
+        if aggs is not None:
+            self._aggp = (ctypes.c_void_p * self.nmat)(*[None if a is None else a.data_ptr() for a in aggs])
+        self._keep = (As, cfs, Bs, outs, aggs)
 
     def __call__(self) -> int:
-        st = self._lib.clair_build_R_batched(self.ctx.handle, self.nmat, self._Ac, self._cfp, self._Bp, self._ellv,
-                                             self._Rc, ctypes.byref(self._opts), self._inf)
+        if self._aggp is not None:
+            st = self._lib.clair_build_R_agg(self.ctx.handle, self.nmat, self._Ac, self._cfp, self._aggp, self._Bp,
+                                             self._ellv, self._Rc, ctypes.byref(self._opts), self._inf)
+        else:
+            st = self._lib.clair_build_R_batched(self.ctx.handle, self.nmat, self._Ac, self._cfp, self._Bp,
+                                                 self._ellv, self._Rc, ctypes.byref(self._opts), self._inf)
         if st:
-            raise ClairError(st, "clair_build_R_batched")
+            raise ClairError(st, "clair_build_R_agg" if self._aggp is not None else "clair_build_R_batched")
         return st
 
 
