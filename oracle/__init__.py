@@ -60,6 +60,8 @@ def _load():
         lib.orc_pattern_size.restype = ctypes.c_int
         lib.orc_build_R.argtypes = [i32, p, p, p, p, p, p, i32, f64, i32, p, p, p, i64, p, p]
         lib.orc_build_R.restype = ctypes.c_int
+        lib.orc_project_k.argtypes = [i32, i32, p, p, p, p, p, i32, f64, p]
+        lib.orc_project_k.restype = ctypes.c_int
         lib.orc_max_threads.argtypes = []
         lib.orc_max_threads.restype = ctypes.c_int
         _lib = lib
@@ -133,3 +135,24 @@ def build_R_problem(p, nthreads=0, B="problem", **kw):
     kw.setdefault("theta", getattr(p, "theta", 0.0))
     kw.setdefault("agg", getattr(p, "agg", None))
     return build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, Bv, p.ell, nthreads=nthreads, **kw)
+
+
+def project_constraints(o, cf, B, rcond=1e-12):
+    """R (an oracle result dict, built unconstrained) after imposing R^T B_c = B
+    for the k columns of B (n x k): a new dict; also n_uncovered."""
+    lib = _load()
+    Bm = np.ascontiguousarray(np.asarray(B, np.float64).reshape(len(cf), -1))
+    k = Bm.shape[1]
+    va = np.array(o["val"], np.float64, copy=True)
+    rp = np.ascontiguousarray(o["row_ptr"], np.int32)
+    ci = np.ascontiguousarray(o["col_idx"], np.int32)
+    cfa = np.ascontiguousarray(cf, np.int8)
+    unc = ctypes.c_int64(0)
+    rc = lib.orc_project_k(len(cfa), o["n_c"], _ptr(rp), _ptr(ci), _ptr(va), _ptr(cfa), _ptr(Bm), k, float(rcond),
+                           ctypes.byref(unc))
+    if rc:
+        raise OracleError(rc, f"oracle project_k failed ({rc})")
+    out = dict(o)
+    out["val"] = va
+    out["n_uncovered"] = unc.value
+    return out

@@ -467,4 +467,112 @@ int orc_build_R(int32_t n, const int32_t* rp, const int32_t* ci, const double* v
   return first_bad >= 0 ? ORC_ERR_SINGULAR : ORC_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* k constraint vectors (Section 2.3 allows a block of constraint vectors;    */
+/* Section 3.1's Q then has k rows per F-point).  B is n x k, row-major.      */
+/* For each F-column j with contributing rows I_j:                            */
+/*   G_j = sum_i B_i B_i^T (k x k),  r_j = sum_i z_ij B_i - B_j,              */
+/*   lambda_j = pinv(G_j) r_j,       z_ij -= B_i^T lambda_j,                  */
+/* the Euclidean projection onto {Q w = B_F}; Q Q^T is block diagonal with    */
+/* the G_j.  pinv drops eigenvalues <= rcond * the largest (symmetric         */
+/* Jacobi eigen-decomposition).  Applied in place to R's F-entries.           */
+/* ------------------------------------------------------------------------ */
+
+/* eigen-decomposition of the symmetric k x k matrix a (destroyed): values w,
+ * vectors in the columns of v (row-major k x k); cyclic Jacobi rotations */
+static void sym_eig(int k, double* a, double* w, double* v) {
+  for (int p = 0; p < k; ++p)
+    for (int q = 0; q < k; ++q) v[p * k + q] = (p == q) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int p = 0; p < k; ++p) {
+      diag += a[p * k + p] * a[p * k + p];
+      for (int q = p + 1; q < k; ++q) off += a[p * k + q] * a[p * k + q];
+    }
+    if (off <= 1e-40 * diag || off == 0.0) break;
+    for (int p = 0; p < k; ++p) {
+      for (int q = p + 1; q < k; ++q) {
+        const double apq = a[p * k + q];
+        if (apq == 0.0) continue;
+        /* rotation angle that zeroes a_pq */
+        const double theta = (a[q * k + q] - a[p * k + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+        for (int m = 0; m < k; ++m) { /* columns p, q */
+          const double amp = a[m * k + p], amq = a[m * k + q];
+          a[m * k + p] = c * amp - sn * amq;
+          a[m * k + q] = sn * amp + c * amq;
+        }
+        for (int m = 0; m < k; ++m) { /* rows p, q */
+          const double apm = a[p * k + m], aqm = a[q * k + m];
+          a[p * k + m] = c * apm - sn * aqm;
+          a[q * k + m] = sn * apm + c * aqm;
+        }
+        for (int m = 0; m < k; ++m) {
+          const double vmp = v[m * k + p], vmq = v[m * k + q];
+          v[m * k + p] = c * vmp - sn * vmq;
+          v[m * k + q] = sn * vmp + c * vmq;
+        }
+      }
+    }
+  }
+  for (int p = 0; p < k; ++p) w[p] = a[p * k + p];
+}
+
+int orc_project_k(int32_t n, int32_t n_c, const int32_t* R_rp, const int32_t* R_ci, double* R_va, const int8_t* cf,
+                  const double* B, int32_t k, double rcond, int64_t* n_uncovered) {
+  if (n < 0 || n_c < 0 || k < 1 || k > 8 || !(rcond >= 0.0)) return ORC_ERR_INVALID;
+  int32_t* clist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_c > 0 ? n_c : 1));
+  double* G = (double*)calloc((size_t)(n > 0 ? n : 1) * (size_t)(k * k), sizeof(double));
+  double* r = (double*)calloc((size_t)(n > 0 ? n : 1) * (size_t)k, sizeof(double));
+  char* cov = (char*)calloc((size_t)(n > 0 ? n : 1), 1);
+  if (!clist || !G || !r || !cov) { free(clist); free(G); free(r); free(cov); return ORC_ERR_NOMEM; }
+  for (int32_t j = 0, q = 0; j < n && q < n_c; ++j) if (cf[j]) clist[q++] = j;
+  for (int32_t q = 0; q < n_c; ++q) {
+    const double* bi = B + (int64_t)clist[q] * k;
+    for (int32_t e = R_rp[q]; e < R_rp[q + 1]; ++e) {
+      const int32_t j = R_ci[e];
+      if (cf[j]) continue;
+      cov[j] = 1;
+      for (int a = 0; a < k; ++a) {
+        r[(int64_t)j * k + a] += R_va[e] * bi[a];
+        for (int b = 0; b < k; ++b) G[(int64_t)j * k * k + a * k + b] += bi[a] * bi[b];
+      }
+    }
+  }
+  int64_t unc = 0;
+  double a[64], w[8], v[64], lam[8];
+  for (int32_t j = 0; j < n; ++j) {
+    if (cf[j]) continue;
+    if (!cov[j]) { ++unc; continue; }
+    double* rj = r + (int64_t)j * k;
+    for (int t = 0; t < k; ++t) rj[t] -= B[(int64_t)j * k + t];
+    memcpy(a, G + (int64_t)j * k * k, sizeof(double) * k * k);
+    sym_eig(k, a, w, v);
+    double wmax = 0.0;
+    for (int t = 0; t < k; ++t) wmax = fmax(wmax, fabs(w[t]));
+    for (int t = 0; t < k; ++t) lam[t] = 0.0;
+    for (int m = 0; m < k; ++m) {
+      if (!(fabs(w[m]) > rcond * wmax)) continue;
+      double proj = 0.0;
+      for (int t = 0; t < k; ++t) proj += v[t * k + m] * rj[t];
+      for (int t = 0; t < k; ++t) lam[t] += v[t * k + m] * proj / w[m];
+    }
+    memcpy(rj, lam, sizeof(double) * k); /* r_j now holds lambda_j */
+  }
+  for (int32_t q = 0; q < n_c; ++q) {
+    const double* bi = B + (int64_t)clist[q] * k;
+    for (int32_t e = R_rp[q]; e < R_rp[q + 1]; ++e) {
+      const int32_t j = R_ci[e];
+      if (cf[j]) continue;
+      double dz = 0.0;
+      for (int t = 0; t < k; ++t) dz += bi[t] * r[(int64_t)j * k + t];
+      R_va[e] -= dz;
+    }
+  }
+  if (n_uncovered) *n_uncovered = unc;
+  free(clist); free(G); free(r); free(cov);
+  return ORC_OK;
+}
+
 int orc_max_threads(void) { return set_threads(0); }

@@ -40,18 +40,19 @@ def algorithm1_R(A: np.ndarray, cf: np.ndarray, B: np.ndarray, ell: int, k: int 
         for f in nb[c]:
             slots.append((c, int(f)))
     nw = len(slots)
-    Bc = {c: B[c] for c in C}
+    Bm = np.asarray(B, dtype=np.float64).reshape(n, -1)  # k constraint vectors as columns
+    kc = Bm.shape[1]
+    Bc = {c: Bm[c] for c in C}
 
     # 1. tentative operator [-A_fc, I] of A^T on the expanded pattern
     wt = np.array([-At[f, c] for (c, f) in slots], dtype=np.float64)
 
-    # Q: one row per F-point f, entries B_c at the slots (c, f)
+    # Q: k rows per F-point f, entries B_c[t] at the slots (c, f)
     F = [int(f) for f in np.nonzero(cf == 0)[0]]
     frow = {f: r for r, f in enumerate(F)}
-    Q = np.zeros((len(F), nw))
+    Q = np.zeros((len(F) * kc, nw))
     for s, (c, f) in enumerate(slots):
-        Q[frow[f], s] = Bc[c]
-    BF = np.array([B[f] for f in F])
+        Q[frow[f] * kc:(frow[f] + 1) * kc, s] = Bc[c]
 
     # 2. enforce Q w^t = B|_F row by row: minimum-norm fit of each F-row
     if fit_constraint:
@@ -59,8 +60,8 @@ def algorithm1_R(A: np.ndarray, cf: np.ndarray, B: np.ndarray, ell: int, k: int 
             idx = [s for s in range(nw) if slots[s][1] == f]
             if not idx:
                 continue
-            bvec = np.array([Bc[slots[s][0]] for s in idx])
-            wt[idx] = np.linalg.pinv(bvec[None, :]) @ np.array([B[f]])
+            M = np.array([Bc[slots[s][0]] for s in idx]).T  # kc x |idx|
+            wt[idx] = np.linalg.pinv(M, rcond=1e-12) @ Bm[f]
 
     # 3. exact block inverses of A_ff^{(c)} (of A^T)
     blocks = {}
@@ -68,7 +69,7 @@ def algorithm1_R(A: np.ndarray, cf: np.ndarray, B: np.ndarray, ell: int, k: int 
         N = nb[c]
         blocks[c] = At[np.ix_(N, N)]
 
-    P = np.eye(nw) - Q.T @ np.linalg.pinv(Q @ Q.T) @ Q
+    P = np.eye(nw) - Q.T @ np.linalg.pinv(Q @ Q.T, rcond=1e-12) @ Q
     for _ in range(k):
         wbar = np.zeros(nw)
         for c in C:
