@@ -245,6 +245,27 @@ int clair_galerkin(clair_ctx_t* ctx, const clair_csr_t* R, const clair_csr_t* A,
 int clair_smooth_B(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_marker, const double* B_in,
                    double* B_out, int32_t iterations, double omega, int32_t transpose, void* stream);
 
+/*
+ * clair_project_constraints -- k constraint vectors (Section 2.3 allows a
+ * block of them; Section 3.1's Q then holds k rows per F-point): imposes
+ * R^T B_c = B, for every column of B, on an R built with B = NULL, in place.
+ * For each F-column j with contributing rows: G_j = sum_i B_i B_i^T (k x k),
+ * r_j = sum_i z_ij B_i - B_j, z_ij -= B_i^T pinv(G_j) r_j -- the Euclidean
+ * projection onto the constraints (k = 1 gives what clair_build_R computes
+ * with B).  pinv drops eigenvalues at or below rcond times the largest (a
+ * column reached by fewer rows than k gets the least-squares fit).
+ *   R          R from this library (n_rows = n_c, nnz, device arrays); its
+ *              values are updated
+ *   n, cf      fine size and the C/F marker R was built with
+ *   B          device float64[n * k], row-major (B[j * k + t])
+ *   k          1 <= k <= 4
+ * *n_uncovered (may be NULL): F-points no row reaches (left unchanged).
+ * A column index outside [0, n) gives CLAIR_ERR_INVALID (R may then be
+ * partly updated).  Synchronises `stream`.
+ */
+int clair_project_constraints(clair_ctx_t* ctx, clair_csr_out_t* R, int32_t n, const int8_t* cf_marker,
+                              const double* B, int32_t k, double rcond, int64_t* n_uncovered, void* stream);
+
 /* Results of the last call on ctx (synchronises its stream).  Fills nmat info
  * entries and the sizes in R_out (may be NULL).  Returns the first non-OK status. */
 int clair_ctx_info(clair_ctx_t* ctx, int32_t nmat, clair_csr_out_t* R_out, clair_info_t* info);

@@ -30,7 +30,7 @@ EXPORTED = [
     "clair_ctx_create", "clair_ctx_destroy", "clair_build_R", "clair_build_R_ex", "clair_build_R_batched",
     "clair_ctx_info", "clair_size_R", "clair_ctx_stage_times", "clair_ctx_set_tuning", "clair_ctx_get_tuning",
     "clair_ctx_set_strength", "clair_ctx_get_strength", "clair_transpose", "clair_build_P",
-    "clair_spgemm", "clair_galerkin", "clair_smooth_B", "clair_build_R_agg",
+    "clair_spgemm", "clair_galerkin", "clair_smooth_B", "clair_build_R_agg", "clair_project_constraints",
     "clair_autotune", "clair_graph_create", "clair_graph_launch", "clair_graph_destroy", "clair_graph_info",
     "clair_plan_create", "clair_plan_execute", "clair_plan_info", "clair_plan_destroy",
     "clair_strerror", "clair_last_error",
@@ -125,6 +125,8 @@ def load_library(path: str = LIB_PATH):
         "clair_build_R_agg": ([P, I32, ctypes.POINTER(CsrIn), ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
                                ctypes.POINTER(I32), ctypes.POINTER(CsrOut), ctypes.POINTER(Opts),
                                ctypes.POINTER(Info)], ctypes.c_int),
+        "clair_project_constraints": ([P, ctypes.POINTER(CsrOut), I32, P, P, I32, ctypes.c_double,
+                                       ctypes.POINTER(I64), P], ctypes.c_int),
         "clair_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "clair_last_error": ([], ctypes.c_char_p),
     }
@@ -508,6 +510,31 @@ def clair_build_R_agg(As: Sequence[CSR], cfs, aggs, Bs, ells, *, ctx: Optional[C
     if st and check:
         raise ClairError(st, "clair_build_R_agg")
     return outs, [i.as_dict() for i in infos], st
+
+
+def clair_project_constraints(R, n: int, cf: torch.Tensor, B: torch.Tensor, *, rcond: float = 1e-12,
+                              ctx: Optional[Context] = None, stream=None) -> int:
+    """Impose R^T B_c = B for the k columns of B (n x k) on R = (row_ptr,
+    col_idx, val) device tensors, in place (val changes); returns n_uncovered."""
+    lib = load_library()
+    ctx = ctx or Context()
+    rp, ci, va = R
+    _check_dev(rp, torch.int32, "row_ptr")
+    _check_dev(ci, torch.int32, "col_idx")
+    _check_dev(va, torch.float64, "val")
+    _check_dev(cf, torch.int8, "cf")
+    _check_dev(B, torch.float64, "B")
+    if cf.numel() != n or B.numel() % max(n, 1):
+        raise ValueError("cf must have n entries and B n x k")
+    Bm = B.reshape(n, -1)
+    n_c = rp.numel() - 1
+    oc = CsrOut(n_c, n, ci.numel(), n_c + 1, 0, ci.numel(), rp.data_ptr(), ci.data_ptr(), va.data_ptr())
+    unc = ctypes.c_int64(0)
+    st = lib.clair_project_constraints(ctx.handle, ctypes.byref(oc), int(n), cf.data_ptr(), Bm.data_ptr(),
+                                       int(Bm.shape[1]), float(rcond), ctypes.byref(unc), _stream_ptr(stream))
+    if st:
+        raise ClairError(st, "clair_project_constraints")
+    return int(unc.value)
 
 
 def clair_autotune(ctx: Context, As, cfs, Bs, ells, outs, reps: int = 3, stream=None):

@@ -169,6 +169,8 @@ struct clair_ctx {
   DevBuf g_rp, g_cnt, ap_rp, ap_ci, ap_va;
   // smoothing of B: two vectors and a flag
   DevBuf sm_x, sm_y, sm_flag;
+  // k constraint vectors: Gram matrices, right-hand sides, counts, a counter
+  DevBuf pk_scratch, pk_count;
 };
 
 namespace {
@@ -996,6 +998,30 @@ int clair_smooth_B(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf, const
     HIPCHK(hipStreamSynchronize(s));
     if (hf == 2) return CLAIR_ERR_INVALID;
     if (hf == 1) return CLAIR_ERR_SINGULAR;
+    return CLAIR_OK;
+  } catch (...) {
+    return CLAIR_ERR_NOMEM;
+  }
+}
+
+int clair_project_constraints(clair_ctx_t* c, clair_csr_out_t* R, int32_t n, const int8_t* cf, const double* B,
+                              int32_t k, double rcond, int64_t* n_uncovered, void* stream) {
+  if (!c || !R || n < 0 || k < 1 || k > 4 || !(rcond >= 0.0) || R->n_rows < 0 || R->nnz < 0) return CLAIR_ERR_INVALID;
+  if (n > 0 && (!cf || !B)) return CLAIR_ERR_INVALID;
+  if (R->n_rows > 0 && (!R->row_ptr || (R->nnz > 0 && (!R->col_idx || !R->val)))) return CLAIR_ERR_INVALID;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  try {
+    HIPCHK(c->pk_scratch.ensure(constraint_scratch_bytes(std::max(1, n))));
+    HIPCHK(c->pk_count.ensure(2 * sizeof(unsigned long long)));
+    unsigned long long* cnt = static_cast<unsigned long long*>(c->pk_count.p);
+    HIPCHK(hipMemsetAsync(cnt, 0, 2 * sizeof(unsigned long long), s));
+    HIPCHK(launch_project_k(n, R->n_rows, R->row_ptr, R->col_idx, R->val, cf, B, k, rcond, c->pk_scratch.p, cnt,
+                            c->cus, s));
+    unsigned long long h[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (h[1]) return CLAIR_ERR_INVALID;
+    if (n_uncovered) *n_uncovered = (int64_t)h[0];
     return CLAIR_OK;
   } catch (...) {
     return CLAIR_ERR_NOMEM;

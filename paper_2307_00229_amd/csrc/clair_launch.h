@@ -56,6 +56,14 @@ hipError_t launch_jacobi_sweep(int n, const int32_t* rp, const int32_t* ci, cons
                                int which_c, double omega, const double* x, double* y, int32_t* flag, int cus,
                                hipStream_t s);
 
+// k constraint vectors (k <= 4) imposed on an R built without constraints;
+// scratch of constraint_scratch_bytes(n); counters (device, zeroed by the
+// caller): [0] F-columns no row reaches, [1] column indices outside [0, n)
+size_t constraint_scratch_bytes(int n);
+hipError_t launch_project_k(int n, int n_c, const int32_t* rp, const int32_t* ci, double* va, const int8_t* cf,
+                            const double* B, int k, double rcond, void* scratch, unsigned long long* counters,
+                            int cus, hipStream_t s);
+
 // plain FP64 per-row form: one matrix, one thread per row, one kernel per stage
 struct PlainWork {
   const int32_t* rp;
