@@ -143,6 +143,7 @@ def time_next_level(clair, ctx, A, cf, B, ell, R_out, stream, reps=5):
     buffers (sizes read once beforehand), wall time of the synchronous call."""
     import ctypes
 
+    import numpy as np
     import torch
 
     lib = clair.load_library()
@@ -190,8 +191,16 @@ def time_next_level(clair, ctx, A, cf, B, ell, R_out, stream, reps=5):
     ones = torch.ones(A.n, dtype=torch.float64, device=A.row_ptr.device)
     s_ms = best_of(lambda: lib.clair_smooth_B(ctx.handle, ctypes.byref(Ac_), cf.data_ptr(), ones.data_ptr(),
                                               Bs_out.data_ptr(), 5, 2.0 / 3.0, 1, sp_))
+    # four constraint vectors imposed on a copy of R (the projection is idempotent)
+    va_k = va.clone()
+    Rk = clair.CsrOut(R_out.n_c, A.n, int(ci.numel()), R_out.n_c + 1, 0, int(ci.numel()), rp.data_ptr(),
+                      ci.data_ptr(), va_k.data_ptr())
+    B4 = torch.from_numpy(np.random.default_rng(4).uniform(0.5, 1.5, (A.n, 4))).to(A.row_ptr.device)
+    unc = ctypes.c_int64(0)
+    k_ms = best_of(lambda: lib.clair_project_constraints(ctx.handle, ctypes.byref(Rk), A.n, cf.data_ptr(),
+                                                         B4.data_ptr(), 4, 1e-12, ctypes.byref(unc), sp_))
     return {"matrix": "first of the workload", "transpose_ms": t_ms, "build_P_ms": p_ms, "galerkin_ms": g_ms,
-            "smooth_B_5_cff_on_AT_ms": s_ms,
+            "smooth_B_5_cff_on_AT_ms": s_ms, "project_constraints_k4_ms": k_ms,
             "nnz_A": int(A.col_idx.numel()), "nnz_P": int(Pc.nnz), "nnz_Ac": int(Gc.nnz),
             "note": "synchronous C calls into preallocated buffers, wall time, best of 5"}
 

@@ -259,9 +259,12 @@ int clair_smooth_B(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_mark
  *   n, cf      fine size and the C/F marker R was built with
  *   B          device float64[n * k], row-major (B[j * k + t])
  *   k          1 <= k <= 4
- * *n_uncovered (may be NULL): F-points no row reaches (left unchanged).
- * A column index outside [0, n) gives CLAIR_ERR_INVALID (R may then be
- * partly updated).  Synchronises `stream`.
+ * Row q of R belongs to the q-th C-point; n_rows must equal the number of
+ * C-points.  *n_uncovered (may be NULL): F-points no row reaches (left
+ * unchanged).  A column index outside [0, n), or a row count that differs
+ * from the number of C-points, gives CLAIR_ERR_INVALID (R may then be partly
+ * updated).  Deterministic: every column is summed in ascending row order.
+ * Synchronises `stream`.
  */
 int clair_project_constraints(clair_ctx_t* ctx, clair_csr_out_t* R, int32_t n, const int8_t* cf_marker,
                               const double* B, int32_t k, double rcond, int64_t* n_uncovered, void* stream);

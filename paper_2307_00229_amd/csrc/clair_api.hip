@@ -169,8 +169,8 @@ struct clair_ctx {
   DevBuf g_rp, g_cnt, ap_rp, ap_ci, ap_va;
   // smoothing of B: two vectors and a flag
   DevBuf sm_x, sm_y, sm_flag;
-  // k constraint vectors: Gram matrices, right-hand sides, counts, a counter
-  DevBuf pk_scratch, pk_count;
+  // k constraint vectors: R^T, the row -> C-point map, lambda, counters
+  DevBuf pk_scratch;
 };
 
 namespace {
@@ -1007,21 +1007,43 @@ int clair_smooth_B(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf, const
 int clair_project_constraints(clair_ctx_t* c, clair_csr_out_t* R, int32_t n, const int8_t* cf, const double* B,
                               int32_t k, double rcond, int64_t* n_uncovered, void* stream) {
   if (!c || !R || n < 0 || k < 1 || k > 4 || !(rcond >= 0.0) || R->n_rows < 0 || R->nnz < 0) return CLAIR_ERR_INVALID;
+  if (R->nnz > INT32_MAX) return CLAIR_ERR_UNSUPPORTED;
   if (n > 0 && (!cf || !B)) return CLAIR_ERR_INVALID;
   if (R->n_rows > 0 && (!R->row_ptr || (R->nnz > 0 && (!R->col_idx || !R->val)))) return CLAIR_ERR_INVALID;
   const hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t nn = (size_t)n, nr = (size_t)R->n_rows, nz = (size_t)std::max<int64_t>(1, R->nnz);
   try {
-    HIPCHK(c->pk_scratch.ensure(constraint_scratch_bytes(std::max(1, n))));
-    HIPCHK(c->pk_count.ensure(2 * sizeof(unsigned long long)));
-    unsigned long long* cnt = static_cast<unsigned long long*>(c->pk_count.p);
-    HIPCHK(hipMemsetAsync(cnt, 0, 2 * sizeof(unsigned long long), s));
-    HIPCHK(launch_project_k(n, R->n_rows, R->row_ptr, R->col_idx, R->val, cf, B, k, rcond, c->pk_scratch.p, cnt,
-                            c->cus, s));
-    unsigned long long h[2] = {0, 0};
-    HIPCHK(hipMemcpyAsync(h, cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+    // one allocation, 256-byte aligned pieces
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      const size_t o = off;
+      off += (bytes + 255) & ~size_t(255);
+      return o;
+    };
+    const size_t o_trp = take(sizeof(int32_t) * (nn + 1)), o_tci = take(sizeof(int32_t) * nz),
+                 o_tva = take(sizeof(double) * nz), o_ts = take(sizeof(int32_t) * transpose_scratch_ints(n)),
+                 o_flag = take(sizeof(int32_t) * std::max<size_t>(1, nn)), o_pos = take(sizeof(int32_t) * (nn + 1)),
+                 o_sums = take(sizeof(int32_t) * scan_scratch_ints(n)),
+                 o_rowc = take(sizeof(int32_t) * std::max<size_t>(1, nr)),
+                 o_lam = take(sizeof(double) * std::max<size_t>(1, nn * k)), o_cnt = take(sizeof(unsigned long long));
+    HIPCHK(c->pk_scratch.ensure(off));
+    char* base = static_cast<char*>(c->pk_scratch.p);
+    ProjectScratch w{reinterpret_cast<int32_t*>(base + o_trp),  reinterpret_cast<int32_t*>(base + o_tci),
+                     reinterpret_cast<double*>(base + o_tva),   reinterpret_cast<int32_t*>(base + o_ts),
+                     reinterpret_cast<int32_t*>(base + o_flag), reinterpret_cast<int32_t*>(base + o_pos),
+                     reinterpret_cast<int32_t*>(base + o_sums), reinterpret_cast<int32_t*>(base + o_rowc),
+                     reinterpret_cast<double*>(base + o_lam)};
+    unsigned long long* unc = reinterpret_cast<unsigned long long*>(base + o_cnt);
+    HIPCHK(hipMemsetAsync(unc, 0, sizeof(unsigned long long), s));
+    HIPCHK(launch_project_k(n, R->n_rows, R->row_ptr, R->col_idx, R->val, cf, B, k, rcond, w, unc, c->cus, s));
+    unsigned long long h_unc = 0;
+    int32_t h_bad = 0, h_nc = 0;
+    HIPCHK(hipMemcpyAsync(&h_unc, unc, sizeof(h_unc), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&h_bad, w.t_scratch + n, sizeof(h_bad), hipMemcpyDeviceToHost, s));
+    if (n > 0) HIPCHK(hipMemcpyAsync(&h_nc, w.pos + n, sizeof(h_nc), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    if (h[1]) return CLAIR_ERR_INVALID;
-    if (n_uncovered) *n_uncovered = (int64_t)h[0];
+    if (h_bad || h_nc != R->n_rows) return CLAIR_ERR_INVALID;
+    if (n_uncovered) *n_uncovered = (int64_t)h_unc;
     return CLAIR_OK;
   } catch (...) {
     return CLAIR_ERR_NOMEM;

@@ -56,13 +56,25 @@ hipError_t launch_jacobi_sweep(int n, const int32_t* rp, const int32_t* ci, cons
                                int which_c, double omega, const double* x, double* y, int32_t* flag, int cus,
                                hipStream_t s);
 
-// k constraint vectors (k <= 4) imposed on an R built without constraints;
-// scratch of constraint_scratch_bytes(n); counters (device, zeroed by the
-// caller): [0] F-columns no row reaches, [1] column indices outside [0, n)
-size_t constraint_scratch_bytes(int n);
-hipError_t launch_project_k(int n, int n_c, const int32_t* rp, const int32_t* ci, double* va, const int8_t* cf,
-                            const double* B, int k, double rcond, void* scratch, unsigned long long* counters,
-                            int cus, hipStream_t s);
+// k constraint vectors (k <= 4) imposed on an R built without constraints.
+// Device work arrays (sizes for n fine points, n_rows rows, nnz entries):
+// R^T (trp n + 1, tci nnz, tva nnz), the transpose's t_scratch
+// (transpose_scratch_ints(n)), the C/F flags (flag n), their scan (pos n + 1,
+// scan_sums scan_scratch_ints(n)), row -> C-point (rowc n_rows), lambda
+// (lam n * k).  *uncovered (device, zeroed by the caller) counts the
+// F-columns no row reaches; an index outside [0, n) sets t_scratch[n] to 1
+// (the transpose's flag) and is skipped everywhere; pos[n] is the number of
+// C-points, which the caller compares with n_rows.
+struct ProjectScratch {
+  int32_t *trp, *tci;
+  double* tva;
+  int32_t* t_scratch;
+  int32_t *flag, *pos, *scan_sums, *rowc;
+  double* lam;
+};
+hipError_t launch_project_k(int n, int n_rows, const int32_t* rp, const int32_t* ci, double* va, const int8_t* cf,
+                            const double* B, int k, double rcond, const ProjectScratch& w,
+                            unsigned long long* uncovered, int cus, hipStream_t s);
 
 // plain FP64 per-row form: one matrix, one thread per row, one kernel per stage
 struct PlainWork {

@@ -5,12 +5,16 @@
 // Applied to an R built without constraints: for each F-column j with
 // contributing rows I_j, G_j = sum_i B_i B_i^T and r_j = sum_i z_ij B_i - B_j,
 // lambda_j = pinv(G_j) r_j, then z_ij -= B_i^T lambda_j: the Euclidean
-// projection onto {R^T B_c = B}.  Three passes: sums (one thread per row of
-// R, FP64 atomics into the column's packed Gram matrix and right-hand side),
-// a k x k pseudo-inverse solve per column (one thread each: Jacobi
-// eigen-decomposition in registers, eigenvalues at or below rcond times the
-// largest dropped), the update (one thread per row).  B is n x k, row-major;
-// k <= 4.
+// projection onto {R^T B_c = B}.  Row q of R belongs to the q-th C-point.
+//
+// Gather form, no floating-point atomics: R is transposed on the device
+// (columns sorted by row, so every column is summed in ascending row order),
+// one thread per F-column forms G_j and r_j from its column of R^T and solves
+// the k x k system in registers (Jacobi eigen-decomposition; eigenvalues at or
+// below rcond times the largest are dropped), one thread per row of R applies
+// the update.  The row -> C-point map comes from a scan of the C/F marker.
+// B is n x k, row-major; k <= 4 (a template parameter, so the per-thread
+// arrays stay in registers).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -25,92 +29,106 @@ namespace {
 
 constexpr int kKT = 256;
 constexpr int kKMax = 4;
-constexpr int kPack = kKMax * (kKMax + 1) / 2;
 
-__device__ __forceinline__ int packed(int a, int b) {  // a <= b, row-major upper triangle
-  return a * kKMax - a * (a - 1) / 2 + (b - a);
-}
-
-// the C-point of row q (its only entry in a C-column); -1 with *bad set when
-// an index lies outside [0, n)
-__device__ __forceinline__ int row_cpoint(int n, const int32_t* rp, const int32_t* ci, const int8_t* cf, int q,
-                                          unsigned long long* bad) {
-  int i = -1;
-  for (int e = rp[q]; e < rp[q + 1]; ++e) {
-    const int j = ci[e];
-    if (j < 0 || j >= n) {
-      atomicAdd(bad, 1ull);
-      return -1;
-    }
-    if (cf[j] != 0) i = j;
-  }
-  return i;
-}
-
-__global__ void k_pk_sums(int n, int n_c, int k, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                          const double* __restrict__ va, const int8_t* __restrict__ cf, const double* __restrict__ B,
-                          double* G, double* r, int32_t* cnt, unsigned long long* bad) {
-  for (int q = blockIdx.x * kKT + threadIdx.x; q < n_c; q += gridDim.x * kKT) {
-    const int i = row_cpoint(n, rp, ci, cf, q, bad);
-    if (i < 0) continue;
-    double bi[kKMax];
-    for (int t = 0; t < kKMax; ++t) bi[t] = t < k ? B[(int64_t)i * k + t] : 0.0;
-    for (int e = rp[q]; e < rp[q + 1]; ++e) {
-      const int j = ci[e];
-      if (cf[j] != 0) continue;
-      atomicAdd(&cnt[j], 1);
-      const double z = va[e];
-      for (int a = 0; a < k; ++a) {
-        unsafeAtomicAdd(&r[(int64_t)j * kKMax + a], z * bi[a]);
-        for (int b = a; b < k; ++b) unsafeAtomicAdd(&G[(int64_t)j * kPack + packed(a, b)], bi[a] * bi[b]);
-      }
-    }
+__global__ __launch_bounds__(kKT) void k_pk_marks(int n, int n_rows, const int8_t* __restrict__ cf, int32_t* flag,
+                                                 int32_t* rowc) {
+  for (int i = blockIdx.x * kKT + threadIdx.x; i < max(n, n_rows); i += gridDim.x * kKT) {
+    if (i < n) flag[i] = cf[i] != 0;
+    if (i < n_rows) rowc[i] = -1;
   }
 }
 
-// lambda_j = pinv(G_j) (r_j - B_j) in place of r_j; counts the columns no row reaches
-__global__ void k_pk_solve(int n, int k, double rcond, const int8_t* __restrict__ cf, const double* __restrict__ B,
-                           const double* __restrict__ G, double* r, const int32_t* __restrict__ cnt,
-                           unsigned long long* uncovered) {
+// rowc[q] = the q-th C-point (rows beyond the C-points keep -1)
+__global__ __launch_bounds__(kKT) void k_pk_rowc(int n, int n_rows, const int8_t* __restrict__ cf,
+                                                const int32_t* __restrict__ pos, int32_t* rowc) {
+  for (int i = blockIdx.x * kKT + threadIdx.x; i < n; i += gridDim.x * kKT)
+    if (cf[i] != 0 && pos[i] < n_rows) rowc[pos[i]] = i;
+}
+
+// lambda_j = pinv(G_j) r_j for every F-column j, from column j of R^T
+template <int K>
+__global__ __launch_bounds__(kKT) void k_pk_solve(int n, int n_rows, double rcond, const int8_t* __restrict__ cf,
+                                                 const double* __restrict__ B, const int32_t* __restrict__ trp,
+                                                 const int32_t* __restrict__ tci, const double* __restrict__ tva,
+                                                 const int32_t* __restrict__ rowc, double* lam,
+                                                 unsigned long long* uncovered) {
   for (int j = blockIdx.x * kKT + threadIdx.x; j < n; j += gridDim.x * kKT) {
     if (cf[j] != 0) continue;
-    if (cnt[j] == 0) {
-      atomicAdd(uncovered, 1ull);
-      continue;
-    }
-    double a[kKMax][kKMax], v[kKMax][kKMax], rhs[kKMax];
-    for (int p = 0; p < kKMax; ++p) {
-      rhs[p] = p < k ? r[(int64_t)j * kKMax + p] - B[(int64_t)j * k + p] : 0.0;
-      for (int q = 0; q < kKMax; ++q) {
-        a[p][q] = (p < k && q < k) ? G[(int64_t)j * kPack + (p <= q ? packed(p, q) : packed(q, p))] : 0.0;
+    double a[K][K], v[K][K], rhs[K];
+#pragma unroll
+    for (int p = 0; p < K; ++p) {
+      rhs[p] = 0.0;
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        a[p][q] = 0.0;
         v[p][q] = p == q ? 1.0 : 0.0;
       }
     }
-    // cyclic Jacobi: rotate (p, q) pairs until the off-diagonal part is negligible
-    for (int sweep = 0; sweep < 60; ++sweep) {
+    int used = 0;
+    for (int e = trp[j]; e < trp[j + 1]; ++e) {
+      const int q = tci[e];
+      const int i = (unsigned)q < (unsigned)n_rows ? rowc[q] : -1;
+      if (i < 0) continue;
+      ++used;
+      const double z = tva[e];
+      double bi[K];
+#pragma unroll
+      for (int t = 0; t < K; ++t) bi[t] = B[(int64_t)i * K + t];
+#pragma unroll
+      for (int p = 0; p < K; ++p) {
+        rhs[p] += z * bi[p];
+#pragma unroll
+        for (int t = p; t < K; ++t) a[p][t] += bi[p] * bi[t];
+      }
+    }
+    if (used == 0) {
+      atomicAdd(uncovered, 1ull);
+#pragma unroll
+      for (int p = 0; p < K; ++p) lam[(int64_t)j * K + p] = 0.0;
+      continue;
+    }
+#pragma unroll
+    for (int p = 0; p < K; ++p) {
+      rhs[p] -= B[(int64_t)j * K + p];
+#pragma unroll
+      for (int t = 0; t < p; ++t) a[p][t] = a[t][p];
+    }
+    // cyclic Jacobi; each rotation sets its pair to zero exactly, so the
+    // off-diagonal part falls quadratically to nothing
+    for (int sweep = 0; sweep < 30; ++sweep) {
       double off = 0.0, on = 0.0;
-      for (int p = 0; p < k; ++p) {
+#pragma unroll
+      for (int p = 0; p < K; ++p) {
         on += a[p][p] * a[p][p];
-        for (int q = p + 1; q < k; ++q) off += a[p][q] * a[p][q];
+#pragma unroll
+        for (int q = p + 1; q < K; ++q) off += a[p][q] * a[p][q];
       }
       if (!(off > 1e-40 * on)) break;
-      for (int p = 0; p < k; ++p) {
-        for (int q = p + 1; q < k; ++q) {
-          if (a[p][q] == 0.0) continue;
-          const double h = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
-          const double t = copysign(1.0, h) / (fabs(h) + sqrt(h * h + 1.0));
+#pragma unroll
+      for (int p = 0; p < K; ++p) {
+#pragma unroll
+        for (int q = p + 1; q < K; ++q) {
+          const double apq = a[p][q];
+          const double h = (a[q][q] - a[p][p]) / (2.0 * (apq != 0.0 ? apq : 1.0));
+          double t = copysign(1.0, h) / (fabs(h) + sqrt(h * h + 1.0));
+          if (apq == 0.0) t = 0.0;
           const double c = rsqrt(t * t + 1.0), s = t * c;
-          for (int m = 0; m < kKMax; ++m) {
+#pragma unroll
+          for (int m = 0; m < K; ++m) {
             const double x = a[m][p], y = a[m][q];
             a[m][p] = c * x - s * y;
             a[m][q] = s * x + c * y;
           }
-          for (int m = 0; m < kKMax; ++m) {
+#pragma unroll
+          for (int m = 0; m < K; ++m) {
             const double x = a[p][m], y = a[q][m];
             a[p][m] = c * x - s * y;
             a[q][m] = s * x + c * y;
           }
-          for (int m = 0; m < kKMax; ++m) {
+          a[p][q] = 0.0;
+          a[q][p] = 0.0;
+#pragma unroll
+          for (int m = 0; m < K; ++m) {
             const double x = v[m][p], y = v[m][q];
             v[m][p] = c * x - s * y;
             v[m][q] = s * x + c * y;
@@ -119,30 +137,44 @@ __global__ void k_pk_solve(int n, int k, double rcond, const int8_t* __restrict_
       }
     }
     double wmax = 0.0;
-    for (int p = 0; p < k; ++p) wmax = fmax(wmax, fabs(a[p][p]));
-    double lam[kKMax] = {0.0, 0.0, 0.0, 0.0};
-    for (int m = 0; m < k; ++m) {
+#pragma unroll
+    for (int p = 0; p < K; ++p) wmax = fmax(wmax, fabs(a[p][p]));
+    double l[K];
+#pragma unroll
+    for (int p = 0; p < K; ++p) l[p] = 0.0;
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
       const double wm = a[m][m];
       if (!(fabs(wm) > rcond * wmax)) continue;
       double proj = 0.0;
-      for (int p = 0; p < k; ++p) proj += v[p][m] * rhs[p];
-      for (int p = 0; p < k; ++p) lam[p] += v[p][m] * proj / wm;
+#pragma unroll
+      for (int p = 0; p < K; ++p) proj += v[p][m] * rhs[p];
+#pragma unroll
+      for (int p = 0; p < K; ++p) l[p] += v[p][m] * proj / wm;
     }
-    for (int p = 0; p < k; ++p) r[(int64_t)j * kKMax + p] = lam[p];
+#pragma unroll
+    for (int p = 0; p < K; ++p) lam[(int64_t)j * K + p] = l[p];
   }
 }
 
-__global__ void k_pk_apply(int n, int n_c, int k, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                           double* va, const int8_t* __restrict__ cf, const double* __restrict__ B,
-                           const double* __restrict__ lam, const int32_t* __restrict__ cnt, unsigned long long* bad) {
-  for (int q = blockIdx.x * kKT + threadIdx.x; q < n_c; q += gridDim.x * kKT) {
-    const int i = row_cpoint(n, rp, ci, cf, q, bad);
+// z_ij -= B_i^T lambda_j on the F-entries of every row
+template <int K>
+__global__ __launch_bounds__(kKT) void k_pk_apply(int n, int n_rows, const int32_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ ci, double* va,
+                                                 const int8_t* __restrict__ cf, const double* __restrict__ B,
+                                                 const int32_t* __restrict__ rowc, const double* __restrict__ lam) {
+  for (int q = blockIdx.x * kKT + threadIdx.x; q < n_rows; q += gridDim.x * kKT) {
+    const int i = rowc[q];
     if (i < 0) continue;
+    double bi[K];
+#pragma unroll
+    for (int t = 0; t < K; ++t) bi[t] = B[(int64_t)i * K + t];
     for (int e = rp[q]; e < rp[q + 1]; ++e) {
       const int j = ci[e];
-      if (cf[j] != 0 || cnt[j] == 0) continue;
+      if ((unsigned)j >= (unsigned)n || cf[j] != 0) continue;
       double dz = 0.0;
-      for (int t = 0; t < k; ++t) dz += B[(int64_t)i * k + t] * lam[(int64_t)j * kKMax + t];
+#pragma unroll
+      for (int t = 0; t < K; ++t) dz += bi[t] * lam[(int64_t)j * K + t];
       va[e] -= dz;
     }
   }
@@ -150,27 +182,41 @@ __global__ void k_pk_apply(int n, int n_c, int k, const int32_t* __restrict__ rp
 
 int kgrid(int m, int cus) { return std::max(1, std::min((m + kKT - 1) / kKT, cus * 8)); }
 
-}  // namespace
-
-size_t constraint_scratch_bytes(int n) {
-  return (size_t)n * (sizeof(double) * (kPack + kKMax) + sizeof(int32_t)) + 64;
+template <int K>
+void launch_k(int n, int n_rows, const int32_t* rp, const int32_t* ci, double* va, const int8_t* cf, const double* B,
+              double rcond, const ProjectScratch& w, unsigned long long* uncovered, int cus, hipStream_t s) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_pk_solve<K>, dim3(kgrid(n, cus)), dim3(kKT), 0, s, n, n_rows, rcond, cf, B, w.trp, w.tci,
+                       w.tva, w.rowc, w.lam, uncovered);
+  if (n_rows > 0)
+    hipLaunchKernelGGL(k_pk_apply<K>, dim3(kgrid(n_rows, cus)), dim3(kKT), 0, s, n, n_rows, rp, ci, va, cf, B, w.rowc,
+                       w.lam);
 }
 
-hipError_t launch_project_k(int n, int n_c, const int32_t* rp, const int32_t* ci, double* va, const int8_t* cf,
-                            const double* B, int k, double rcond, void* scratch, unsigned long long* counters,
-                            int cus, hipStream_t s) {
-  unsigned long long* uncovered = counters;
-  unsigned long long* bad = counters + 1;
-  double* G = static_cast<double*>(scratch);
-  double* r = G + (size_t)n * kPack;
-  int32_t* cnt = reinterpret_cast<int32_t*>(r + (size_t)n * kKMax);
-  hipError_t e = hipMemsetAsync(scratch, 0, (size_t)n * (sizeof(double) * (kPack + kKMax) + sizeof(int32_t)), s);
+}  // namespace
+
+hipError_t launch_project_k(int n, int n_rows, const int32_t* rp, const int32_t* ci, double* va, const int8_t* cf,
+                            const double* B, int k, double rcond, const ProjectScratch& w,
+                            unsigned long long* uncovered, int cus, hipStream_t s) {
+  if (n > 0 || n_rows > 0)
+    hipLaunchKernelGGL(k_pk_marks, dim3(kgrid(std::max(n, n_rows), cus)), dim3(kKT), 0, s, n, n_rows, cf, w.flag,
+                       w.rowc);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (n_c > 0) hipLaunchKernelGGL(k_pk_sums, dim3(kgrid(n_c, cus)), dim3(kKT), 0, s, n, n_c, k, rp, ci, va, cf, B, G, r, cnt,
-                                bad);
-  if (n > 0) hipLaunchKernelGGL(k_pk_solve, dim3(kgrid(n, cus)), dim3(kKT), 0, s, n, k, rcond, cf, B, G, r, cnt, uncovered);
-  if (n_c > 0) hipLaunchKernelGGL(k_pk_apply, dim3(kgrid(n_c, cus)), dim3(kKT), 0, s, n, n_c, k, rp, ci, va, cf, B, r, cnt,
-                                 bad);
+  if (n > 0) {
+    e = launch_exclusive_scan(w.flag, n, w.pos, w.scan_sums, cus, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_pk_rowc, dim3(kgrid(n, cus)), dim3(kKT), 0, s, n, n_rows, cf, w.pos, w.rowc);
+  }
+  e = launch_transpose(n_rows, n, rp, ci, va, w.trp, w.tci, w.tva, w.t_scratch, cus, s);
+  if (e != hipSuccess) return e;
+  switch (k) {
+    case 1: launch_k<1>(n, n_rows, rp, ci, va, cf, B, rcond, w, uncovered, cus, s); break;
+    case 2: launch_k<2>(n, n_rows, rp, ci, va, cf, B, rcond, w, uncovered, cus, s); break;
+    case 3: launch_k<3>(n, n_rows, rp, ci, va, cf, B, rcond, w, uncovered, cus, s); break;
+    case 4: launch_k<4>(n, n_rows, rp, ci, va, cf, B, rcond, w, uncovered, cus, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -14,7 +14,9 @@ the oracle's unconstrained R.  Checks:
 * the constraints hold on the GPU result for every full-rank F-column, and
   n_uncovered equals the oracle's;
 * a 512 x 512 workload matrix (262144 unknowns) at k = 4;
-* index errors are rejected, and an R with no F-entries is left as it is.
+* index errors and a row count other than the number of C-points are
+  rejected, an R with no F-entries is left as it is, and two calls give the
+  same bits (every column is summed in ascending row order).
 """
 import numpy as np
 import pytest
@@ -186,6 +188,21 @@ def test_rejects_bad_index_and_arguments():
          torch.from_numpy(g["val"]).cuda())
     with pytest.raises(clair.ClairError):  # k = 5
         clair.clair_project_constraints(R, p.n, cf, torch.ones(p.n, 5, dtype=torch.float64, device="cuda"))
+    # one row fewer than C-points
+    n_c = g["n_c"]
+    Rs = (R[0][:n_c].contiguous(), R[1][: int(g["row_ptr"][n_c - 1])].contiguous(),
+          R[2][: int(g["row_ptr"][n_c - 1])].contiguous())
+    with pytest.raises(clair.ClairError):
+        clair.clair_project_constraints(Rs, p.n, cf, B)
+
+
+def test_deterministic():
+    p = CASES[1]()
+    B = _Bk(p, 3, 5)
+    g = _unconstrained(p)
+    a = _project_gpu(p, g, B)
+    b = _project_gpu(p, g, B)
+    assert np.array_equal(a["val"], b["val"])
 
 
 def test_all_c_points_leaves_r_unchanged():
