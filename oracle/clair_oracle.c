@@ -575,4 +575,120 @@ int orc_project_k(int32_t n, int32_t n_c, const int32_t* R_rp, const int32_t* R_
   return ORC_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Approximate block inverses (Section 3.1.2: a block-diagonal approximate     */
+/* inverse of A_ff^{(*)}, one block per C-point; the footnote of the           */
+/* comparison with root-node names the local diagonal inverse).  Algorithm 1  */
+/* with the diagonal block inverse, on the pattern of an R built beforehand:  */
+/*   tentative weights -a_ij on the pattern;                                   */
+/*   with B: each F-column j is replaced by the minimum-norm solution of its  */
+/*     constraint, z_ij = B_i B_j / d_j, d_j = sum_{i in I_j} B_i^2;          */
+/*   `iterations` times:                                                       */
+/*     residual of row i on its pattern: rho_ij = -(R A)_ij, j in N(i)        */
+/*       (R's row holds z on N(i) and 1 at i, so (R A)_ij = a_ij +            */
+/*       sum_{l in N(i)} z_il a_lj: the residual -a_i - A[N,N]^T z_i);        */
+/*     u_ij = rho_ij / a_jj (the diagonal of the block);                      */
+/*     with B: u_ij -= B_i (sum_i u_ij B_i) / d_j (the projection; Q Q^T is  */
+/*       diagonal);                                                            */
+/*     z += u.                                                                 */
+/* The residual is formed row by row: row i of R times the rows of A.         */
+/* Returns ORC_ERR_SINGULAR (bad_row = the smallest C-point whose row meets   */
+/* it) when a pattern column has no nonzero diagonal entry.                   */
+/* ------------------------------------------------------------------------ */
+int orc_iterate_diag(int32_t n, const int32_t* rp, const int32_t* ci, const double* va, const int8_t* cf,
+                     const double* B, int32_t n_c, const int32_t* R_rp, const int32_t* R_ci, double* R_va,
+                     int32_t iterations, int32_t* bad_row) {
+  if (iterations < 0 || check_csr(n, rp, ci)) return ORC_ERR_INVALID;
+  const size_t nn = (size_t)(n > 0 ? n : 1);
+  const int64_t nnz = R_rp[n_c];
+  int32_t* clist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_c > 0 ? n_c : 1));
+  double* diag = (double*)calloc(nn, sizeof(double));
+  double* d = (double*)calloc(nn, sizeof(double));
+  double* sj = (double*)calloc(nn, sizeof(double));
+  double* u = (double*)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+  if (!clist || !diag || !d || !sj || !u) {
+    free(clist); free(diag); free(d); free(sj); free(u);
+    return ORC_ERR_NOMEM;
+  }
+  int32_t nc_seen = 0;
+  for (int32_t j = 0; j < n; ++j)
+    if (cf[j]) {
+      if (nc_seen < n_c) clist[nc_seen] = j;
+      ++nc_seen;
+    }
+  if (nc_seen != n_c) {
+    free(clist); free(diag); free(d); free(sj); free(u);
+    return ORC_ERR_INVALID;
+  }
+  for (int32_t j = 0; j < n; ++j)
+    for (int32_t e = rp[j]; e < rp[j + 1]; ++e)
+      if (ci[e] == j) diag[j] += va[e];
+  int32_t first_bad = -1;
+  for (int32_t r = 0; r < n_c && first_bad < 0; ++r)
+    for (int32_t e = R_rp[r]; e < R_rp[r + 1]; ++e)
+      if (R_ci[e] != clist[r] && diag[R_ci[e]] == 0.0) { first_bad = clist[r]; break; }
+  if (first_bad >= 0) {
+    if (bad_row) *bad_row = first_bad;
+    free(clist); free(diag); free(d); free(sj); free(u);
+    return ORC_ERR_SINGULAR;
+  }
+  /* tentative weights, then the constraint fit */
+  for (int32_t r = 0; r < n_c; ++r) {
+    const int32_t i = clist[r];
+    for (int32_t e = R_rp[r]; e < R_rp[r + 1]; ++e) {
+      const int32_t j = R_ci[e];
+      if (j == i) { R_va[e] = 1.0; continue; }
+      double a = 0.0;
+      for (int32_t t = rp[i]; t < rp[i + 1]; ++t)
+        if (ci[t] == j) a += va[t];
+      R_va[e] = -a;
+      if (B) d[j] += B[i] * B[i];
+    }
+  }
+  if (B)
+    for (int32_t r = 0; r < n_c; ++r) {
+      const int32_t i = clist[r];
+      for (int32_t e = R_rp[r]; e < R_rp[r + 1]; ++e) {
+        const int32_t j = R_ci[e];
+        if (j == i) continue;
+        R_va[e] = d[j] > 0.0 ? B[i] * B[j] / d[j] : 0.0;
+      }
+    }
+  for (int32_t it = 0; it < iterations; ++it) {
+    /* u = D^{-1} (-(R A)) on the pattern, every row from the same R */
+    for (int32_t r = 0; r < n_c; ++r) {
+      const int32_t i = clist[r];
+      const int32_t e0 = R_rp[r], len = R_rp[r + 1] - e0;
+      for (int32_t e = e0; e < e0 + len; ++e) u[e] = 0.0;
+      for (int32_t e = e0; e < e0 + len; ++e) {
+        const int32_t l = R_ci[e];
+        const double zl = R_va[e];
+        for (int32_t t = rp[l]; t < rp[l + 1]; ++t) {
+          const int32_t p = find_sorted(R_ci + e0, len, ci[t]);
+          if (p >= 0) u[e0 + p] += zl * va[t];
+        }
+      }
+      for (int32_t e = e0; e < e0 + len; ++e) {
+        const int32_t j = R_ci[e];
+        u[e] = (j == i) ? 0.0 : -u[e] / diag[j];
+      }
+    }
+    if (B) {
+      memset(sj, 0, sizeof(double) * nn);
+      for (int32_t r = 0; r < n_c; ++r)
+        for (int32_t e = R_rp[r]; e < R_rp[r + 1]; ++e) sj[R_ci[e]] += u[e] * B[clist[r]];
+      for (int32_t r = 0; r < n_c; ++r) {
+        const int32_t i = clist[r];
+        for (int32_t e = R_rp[r]; e < R_rp[r + 1]; ++e) {
+          const int32_t j = R_ci[e];
+          if (j != i && d[j] > 0.0) u[e] -= B[i] * sj[j] / d[j];
+        }
+      }
+    }
+    for (int64_t e = 0; e < nnz; ++e) R_va[e] += u[e];
+  }
+  free(clist); free(diag); free(d); free(sj); free(u);
+  return ORC_OK;
+}
+
 int orc_max_threads(void) { return set_threads(0); }

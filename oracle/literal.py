@@ -8,7 +8,9 @@ operator formed explicitly as a dense matrix on tiny problems:
    on the expanded pattern (possibly zero entries);
 2. constraint fit: every F-row of W^t is replaced by the minimum-norm
    (pseudo-inverse) solution of  w B_c|_pattern = B_f;
-3. exact block inverses of the local blocks A_ff^{(c)} of A^T;
+3. block inverses of the local blocks A_ff^{(c)} of A^T: exact, or the
+   local diagonal inverse (Section 3.1.2's approximate block inverses; the
+   footnote of the comparison with root-node);
 4. k iterations of: residual update  w_bar = A_ff^{-1}(-a_fc - A_ff w^t);
    projection  w_bar <- (I - Q^T (Q Q^T)^+ Q) w_bar  with Q assembled entry by
    entry from B_c (Section 3.1, eq. Qdef) and the pseudo-inverse of Q Q^T;
@@ -25,9 +27,13 @@ import numpy as np
 from . import dense
 
 
-def algorithm1_R(A: np.ndarray, cf: np.ndarray, B: np.ndarray, ell: int, k: int = 1,
-                 fit_constraint: bool = True, theta: float = 0.0, agg=None):
-    """Dense R (n_c x n) from the literal Algorithm 1 on A^T (strength threshold theta)."""
+def algorithm1_R(A: np.ndarray, cf: np.ndarray, B, ell: int, k: int = 1,
+                 fit_constraint: bool = True, theta: float = 0.0, agg=None, inverse: str = "exact"):
+    """Dense R (n_c x n) from the literal Algorithm 1 on A^T (strength threshold theta).
+
+    inverse: "exact" (the block inverses of step 3) or "diag" (the local
+    diagonal inverse of each block).  B = None drops the constraint lines
+    (the fit of step 2 and the projection of step 4)."""
     n = A.shape[0]
     At = A.T
     C = [int(i) for i in np.nonzero(cf != 0)[0]]
@@ -40,6 +46,10 @@ def algorithm1_R(A: np.ndarray, cf: np.ndarray, B: np.ndarray, ell: int, k: int 
         for f in nb[c]:
             slots.append((c, int(f)))
     nw = len(slots)
+    constrained = B is not None
+    if not constrained:
+        B = np.zeros(n)
+        fit_constraint = False
     Bm = np.asarray(B, dtype=np.float64).reshape(n, -1)  # k constraint vectors as columns
     kc = Bm.shape[1]
     Bc = {c: Bm[c] for c in C}
@@ -63,13 +73,25 @@ def algorithm1_R(A: np.ndarray, cf: np.ndarray, B: np.ndarray, ell: int, k: int 
             M = np.array([Bc[slots[s][0]] for s in idx]).T  # kc x |idx|
             wt[idx] = np.linalg.pinv(M, rcond=1e-12) @ Bm[f]
 
-    # 3. exact block inverses of A_ff^{(c)} (of A^T)
+    # 3. exact or approximate block inverses of A_ff^{(c)} (of A^T)
     blocks = {}
+    inv = {}
     for c in C:
         N = nb[c]
         blocks[c] = At[np.ix_(N, N)]
+        if len(N) == 0:
+            continue
+        if inverse == "exact":
+            inv[c] = np.linalg.inv(blocks[c])
+        elif inverse == "diag":
+            inv[c] = np.diag(1.0 / np.diag(blocks[c]))
+        else:
+            raise ValueError(inverse)
 
-    P = np.eye(nw) - Q.T @ np.linalg.pinv(Q @ Q.T, rcond=1e-12) @ Q
+    if constrained:
+        P = np.eye(nw) - Q.T @ np.linalg.pinv(Q @ Q.T, rcond=1e-12) @ Q
+    else:
+        P = np.eye(nw)
     for _ in range(k):
         wbar = np.zeros(nw)
         for c in C:
@@ -80,7 +102,7 @@ def algorithm1_R(A: np.ndarray, cf: np.ndarray, B: np.ndarray, ell: int, k: int 
             w_c = wt[s0:s0 + len(N)]
             a_fc = At[N, c]
             res = -a_fc - blocks[c] @ w_c
-            wbar[s0:s0 + len(N)] = np.linalg.solve(blocks[c], res)
+            wbar[s0:s0 + len(N)] = inv[c] @ res
         wbar = P @ wbar
         wt = wt + wbar
 

@@ -1,0 +1,106 @@
+"""Oracle pins for Algorithm 1 with the diagonal block inverse (CPU).
+
+oracle.build_R_diag runs Algorithm 1's iteration with the local diagonal
+inverse of every block (Section 3.1.2's approximate block inverses; the
+diagonal one is the root-node-like variant of the footnote in the comparison
+with root-node) on the exact build's pattern, column by column.  Pinned
+against:
+* the literal Algorithm 1 (oracle/literal.py: Q assembled entry by entry,
+  pinv of Q Q^T, dense diagonal block inverses) for 0..4 iterations, with and
+  without constraints;
+* an exactness case: on a 5-point grid at distance 1 with C = (even, even),
+  the four neighbours of a C-point are not coupled to each other, every block
+  is diagonal, so the diagonal inverse is exact and one iteration gives the
+  closed form; more iterations change nothing (Remark 2);
+* the limit without constraints: the iteration is Jacobi on each local system,
+  which converges on these row-dominant matrices to the exact l-AIR rows;
+* feasibility: every iterate meets R^T B_c = B on the covered F-columns (the
+  start is a feasible point and every update is projected);
+* a zero diagonal on a pattern column is reported as singular.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import dense, literal
+from paper_2307_00229_amd import problems as P
+
+CASES = [
+    lambda: P.small_2d(10, stencil=9, eps=0.05, angle=1.0, k=3, ell=2),
+    lambda: P.small_2d(12, stencil=5, eps=0.1, angle=0.5, ell=2),
+    lambda: P.small_3d(5, eps=0.05, b=(1.0, 0.3, -0.2), ell=2),
+    lambda: P.random_sparse(50, 0.06, 5, ell=2),
+]
+
+
+def _dense_R(o, n):
+    return dense.csr_to_dense_R(o["row_ptr"], o["col_idx"], o["val"], n)
+
+
+@pytest.mark.parametrize("iters", [0, 1, 2, 4])
+@pytest.mark.parametrize("constrained", [True, False])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_equals_literal_algorithm1(case, constrained, iters):
+    p = CASES[case]()
+    B = p.B if constrained else None
+    got = oracle.build_R_diag(p.n, p.row_ptr, p.col_idx, p.val, p.cf, B, p.ell, iters)
+    A = dense.to_dense(p.n, p.row_ptr, p.col_idx, p.val)
+    Rl = literal.algorithm1_R(A, p.cf, B, p.ell, k=iters, inverse="diag")
+    R = _dense_R(got, p.n)
+    assert np.max(np.abs(Rl - R)) <= 1e-12 * max(1.0, np.max(np.abs(R)))
+
+
+def test_diagonal_blocks_make_one_iteration_exact():
+    p = P.cfg1()  # 32 x 32 5-point, distance 1, C = (even, even)
+    exact = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell)
+    for iters in (1, 3):
+        got = oracle.build_R_diag(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, iters)
+        assert np.array_equal(got["col_idx"], exact["col_idx"])
+        assert np.allclose(got["val"], exact["val"], rtol=0, atol=1e-14 * np.abs(exact["val"]).max())
+    # zero iterations is not the closed form: the start is the minimum-norm fit
+    got0 = oracle.build_R_diag(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, 0)
+    assert np.abs(got0["val"] - exact["val"]).max() > 1e-3
+
+
+@pytest.mark.parametrize("case", [1, 2, 3])
+def test_unconstrained_limit_is_exact_lair(case):
+    p = CASES[case]()
+    exact = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, None, p.ell)
+    got = oracle.build_R_diag(p.n, p.row_ptr, p.col_idx, p.val, p.cf, None, p.ell, 300)
+    assert np.array_equal(got["col_idx"], exact["col_idx"])
+    assert np.max(np.abs(got["val"] - exact["val"])) <= 1e-10 * np.abs(exact["val"]).max()
+    # and the error falls with the iteration count
+    errs = [np.abs(oracle.build_R_diag(p.n, p.row_ptr, p.col_idx, p.val, p.cf, None, p.ell, k)["val"]
+                   - exact["val"]).max() for k in (1, 4, 16)]
+    assert errs[0] > errs[1] > errs[2]
+
+
+@pytest.mark.parametrize("iters", [0, 1, 3])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_every_iterate_meets_the_constraint(case, iters):
+    p = CASES[case]()
+    got = oracle.build_R_diag(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, iters)
+    C = np.nonzero(p.cf)[0]
+    rows = np.repeat(np.arange(got["n_c"]), np.diff(got["row_ptr"]))
+    fm = got["col_idx"] != C[rows]
+    terms = got["val"][fm] * p.B[C[rows[fm]]]
+    S = np.zeros(p.n)
+    T = np.zeros(p.n)
+    np.add.at(S, got["col_idx"][fm], terms)
+    np.add.at(T, got["col_idx"][fm], np.abs(terms))
+    cov = np.zeros(p.n, bool)
+    cov[got["col_idx"][fm]] = True
+    res = np.abs(S[cov] - p.B[cov]) / (np.abs(p.B[cov]) + T[cov])
+    assert res.max() <= 1e-13
+
+
+def test_zero_diagonal_is_singular():
+    p = P.small_2d(10, stencil=5, eps=0.1, angle=0.5, ell=2)
+    va = p.val.copy()
+    F = np.nonzero(p.cf == 0)[0]
+    j = int(F[len(F) // 2])
+    for e in range(p.row_ptr[j], p.row_ptr[j + 1]):
+        if p.col_idx[e] == j:
+            va[e] = 0.0
+    with pytest.raises(oracle.OracleError):
+        oracle.build_R_diag(p.n, p.row_ptr, p.col_idx, va, p.cf, p.B, p.ell, 1)
