@@ -180,6 +180,32 @@ int clair_build_R_batched(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* A,
                           clair_csr_out_t* R_out, const clair_opts_t* opts, clair_info_t* info);
 
 /*
+ * clair_build_R_diag -- Algorithm 1 with approximate block inverses (Section
+ * 3.1.2): every local block A_ff^{(i)} replaced by its diagonal (the
+ * root-node-like variant of the footnote in the comparison with root-node),
+ * run for `iterations` steps.  Same pattern as clair_build_R (distance-ell
+ * F-neighbourhoods, the context's strength threshold), no local solves:
+ *   start: z_ij = -a_ij (the tentative operator); with B, every F-column is
+ *          replaced by the minimum-norm solution of its constraint,
+ *          z_ij = B_i B_j / d_j with d_j = sum over the column's rows of B_i^2;
+ *   each iteration: u_ij = -(R A)_ij / a_jj on the F-entries (the block
+ *          residual scaled by the block's diagonal), projected with B
+ *          (u_ij -= B_i sum_i(u_ij B_i) / d_j), then z += u.
+ * Every iterate meets the constraint where B is given.  With exact inverses
+ * one iteration gives clair_build_R's result (Remark 2); with the diagonal
+ * it does when every block is diagonal.  FP64 throughout; per-column sums by
+ * FP64 atomics (rounding order not fixed).
+ *   R_out     as for clair_build_R (n_rows, n_cols, nnz set; too small
+ *             capacities return CLAIR_ERR_CAPACITY, a size query)
+ *   info      n_c, nnz, max_block, n_uncovered (with B), first_bad_row
+ * A pattern F-column j with a_jj = 0 returns CLAIR_ERR_SINGULAR, first_bad_row
+ * = the smallest C-point whose row meets one.  Blocks above 64 points return
+ * CLAIR_ERR_UNSUPPORTED.  Synchronises `stream`.
+ */
+int clair_build_R_diag(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_marker, const double* B,
+                       int32_t ell, int32_t iterations, clair_csr_out_t* R_out, clair_info_t* info, void* stream);
+
+/*
  * clair_transpose -- AT = A^T for an A of A->n rows and ncol columns (sorted
  * CSR in, sorted CSR out; values copied exactly).  AT_out: n_rows = ncol,
  * n_cols = A->n, nnz = A->nnz are set; with too small capacities (row_ptr

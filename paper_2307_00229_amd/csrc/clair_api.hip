@@ -171,6 +171,8 @@ struct clair_ctx {
   DevBuf sm_x, sm_y, sm_flag;
   // k constraint vectors: R^T, the row -> C-point map, lambda, counters
   DevBuf pk_scratch;
+  // diagonal block inverse: diagonal, column sums, updates, row of each entry
+  DevBuf ap_ws;
 };
 
 namespace {
@@ -543,8 +545,11 @@ int run_mixed(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* co
 // ---------------------------------------------------------------------------
 // plain FP64 per-row form
 // ---------------------------------------------------------------------------
+// pattern_only: stop after R's row_ptr and col_idx; *clist_out then points to
+// the C-point list in the workspace (valid until the next plain-form call)
 int run_plain_one(clair_ctx* c, const clair_csr_t& A, const int8_t* cf, const double* B, int ell,
-                  clair_csr_out_t* R, hipStream_t s, clair_info_t* info) {
+                  clair_csr_out_t* R, hipStream_t s, clair_info_t* info, bool pattern_only = false,
+                  const int32_t** clist_out = nullptr) {
   const int n = A.n;
   const int nb = (n + 255) / 256;
   // workspace: blk_cnt[nb+1] clist[n] sizes[n+1] scan_tmp[nb+2] dsum[n] rsum[n] flags[8]
@@ -619,6 +624,11 @@ int run_plain_one(clair_ctx* c, const clair_csr_t& A, const int8_t* cf, const do
     return in.status;
   }
   HIPCHK(plain_fill(p, n_c, s));
+  if (pattern_only) {
+    if (clist_out) *clist_out = p.clist;
+    if (info) *info = in;
+    return CLAIR_OK;
+  }
   const int smax = std::max(1, hflags[2]);
   const size_t kb = (size_t)n_c * ((size_t)smax * smax + smax) * sizeof(double);
   if (c->plain_k.ensure(std::max<size_t>(kb, 64)) != hipSuccess) return CLAIR_ERR_NOMEM;
@@ -1044,6 +1054,91 @@ int clair_project_constraints(clair_ctx_t* c, clair_csr_out_t* R, int32_t n, con
     HIPCHK(hipStreamSynchronize(s));
     if (h_bad || h_nc != R->n_rows) return CLAIR_ERR_INVALID;
     if (n_uncovered) *n_uncovered = (int64_t)h_unc;
+    return CLAIR_OK;
+  } catch (...) {
+    return CLAIR_ERR_NOMEM;
+  }
+}
+
+int clair_build_R_diag(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf, const double* B, int32_t ell,
+                       int32_t iterations, clair_csr_out_t* R, clair_info_t* info, void* stream) {
+  if (!c || !R || !cf || ell < 1 || ell > 64 || iterations < 0 || check_csr_args(A)) return CLAIR_ERR_INVALID;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const int32_t n = A->n;
+  try {
+    // the pattern (strength threshold of the context), no local solves
+    clair_info_t in{};
+    const int32_t* clist = nullptr;
+    int rc = run_plain_one(c, *A, cf, B, ell, R, s, &in, true, &clist);
+    if (info) *info = in;
+    if (rc) return rc;
+    const int32_t n_c = R->n_rows;
+    const int64_t nnz = R->nnz;
+    // A^T for the column gathers of the residual
+    HIPCHK(c->t_rp.ensure(sizeof(int32_t) * ((size_t)n + 1)));
+    HIPCHK(c->t_ci.ensure(sizeof(int32_t) * std::max<size_t>(1, (size_t)A->nnz)));
+    HIPCHK(c->t_va.ensure(sizeof(double) * std::max<size_t>(1, (size_t)A->nnz)));
+    rc = transpose_into(c, *A, n, static_cast<int32_t*>(c->t_rp.p), static_cast<int32_t*>(c->t_ci.p),
+                        static_cast<double*>(c->t_va.p), s);
+    if (rc) return rc;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      const size_t o = off;
+      off += (bytes + 255) & ~size_t(255);
+      return o;
+    };
+    const size_t nn = std::max<size_t>(1, (size_t)n), nz = std::max<size_t>(1, (size_t)nnz);
+    const size_t o_diag = take(sizeof(double) * nn), o_d = take(sizeof(double) * nn), o_sj = take(sizeof(double) * nn),
+                 o_u = take(sizeof(double) * nz), o_cnt = take(sizeof(int32_t) * nn),
+                 o_erow = take(sizeof(int32_t) * nz), o_flags = take(64);
+    HIPCHK(c->ap_ws.ensure(off));
+    char* base = static_cast<char*>(c->ap_ws.p);
+    DiagWork w{};
+    w.n = n;
+    w.n_c = n_c;
+    w.nnz = nnz;
+    w.cus = c->cus;
+    w.rp = A->row_ptr;
+    w.ci = A->col_idx;
+    w.va = A->val;
+    w.trp = static_cast<const int32_t*>(c->t_rp.p);
+    w.tci = static_cast<const int32_t*>(c->t_ci.p);
+    w.tva = static_cast<const double*>(c->t_va.p);
+    w.cf = cf;
+    w.B = B;
+    w.Rrp = R->row_ptr;
+    w.Rci = R->col_idx;
+    w.Rva = R->val;
+    w.clist = clist;
+    w.diag = reinterpret_cast<double*>(base + o_diag);
+    w.d = reinterpret_cast<double*>(base + o_d);
+    w.sj = reinterpret_cast<double*>(base + o_sj);
+    w.u = reinterpret_cast<double*>(base + o_u);
+    w.cnt = reinterpret_cast<int32_t*>(base + o_cnt);
+    w.erow = reinterpret_cast<int32_t*>(base + o_erow);
+    w.bad_row = reinterpret_cast<int32_t*>(base + o_flags);
+    w.uncovered = reinterpret_cast<unsigned long long*>(base + o_flags + 8);
+    HIPCHK(hipMemsetAsync(w.d, 0, sizeof(double) * nn, s));
+    HIPCHK(hipMemsetAsync(w.cnt, 0, sizeof(int32_t) * nn, s));
+    const int32_t hinit[4] = {INT32_MAX, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(w.bad_row, hinit, sizeof(hinit), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_diag_start(w, s));
+    int32_t hbad[4] = {0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(hbad, w.bad_row, sizeof(hbad), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hbad[0] != INT32_MAX) {
+      in.status = CLAIR_ERR_SINGULAR;
+      in.first_bad_row = hbad[0];
+      if (info) *info = in;
+      return CLAIR_ERR_SINGULAR;
+    }
+    for (int32_t it = 0; it < iterations; ++it) HIPCHK(launch_diag_iteration(w, s));
+    unsigned long long unc = 0;
+    HIPCHK(hipMemcpyAsync(&unc, w.uncovered, sizeof(unc), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    in.n_uncovered = B ? (int64_t)unc : 0;
+    in.first_bad_row = -1;
+    if (info) *info = in;
     return CLAIR_OK;
   } catch (...) {
     return CLAIR_ERR_NOMEM;

@@ -76,6 +76,29 @@ hipError_t launch_project_k(int n, int n_rows, const int32_t* rp, const int32_t*
                             const double* B, int k, double rcond, const ProjectScratch& w,
                             unsigned long long* uncovered, int cus, hipStream_t s);
 
+// Algorithm 1 with the diagonal block inverse, on R's pattern (rows sorted,
+// the C-point's own entry included).  A^T in trp/tci/tva; clist[q] = the
+// C-point of row q; work arrays: diag, d, sj (n), cnt (n, zeroed), u and erow
+// (nnz), *bad_row (INT32_MAX beforehand), *uncovered (zeroed).
+struct DiagWork {
+  int n, n_c;
+  int64_t nnz;
+  int cus;
+  const int32_t *rp, *ci;
+  const double* va;
+  const int32_t *trp, *tci;
+  const double* tva;
+  const int8_t* cf;
+  const double* B;
+  const int32_t *Rrp, *Rci, *clist;
+  double* Rva;
+  double *diag, *d, *sj, *u;
+  int32_t *cnt, *erow, *bad_row;
+  unsigned long long* uncovered;
+};
+hipError_t launch_diag_start(const DiagWork& w, hipStream_t s);
+hipError_t launch_diag_iteration(const DiagWork& w, hipStream_t s);
+
 // plain FP64 per-row form: one matrix, one thread per row, one kernel per stage
 struct PlainWork {
   const int32_t* rp;
