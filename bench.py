@@ -199,8 +199,17 @@ def time_next_level(clair, ctx, A, cf, B, ell, R_out, stream, reps=5):
     unc = ctypes.c_int64(0)
     k_ms = best_of(lambda: lib.clair_project_constraints(ctx.handle, ctypes.byref(Rk), A.n, cf.data_ptr(),
                                                          B4.data_ptr(), 4, 1e-12, ctypes.byref(unc), sp_))
+    # Algorithm 1 with the diagonal block inverse, three iterations
+    info_d = clair.Info()
+    probe = clair.CsrOut()
+    lib.clair_build_R_diag(ctx.handle, ctypes.byref(Ac_), cf.data_ptr(), clair._ptr(B), ell, 3, ctypes.byref(probe),
+                           ctypes.byref(info_d), sp_)
+    Dout = clair.ROut(int(probe.n_rows), int(probe.nnz), device=A.row_ptr.device)
+    Dc = Dout.c()
+    d_ms = best_of(lambda: lib.clair_build_R_diag(ctx.handle, ctypes.byref(Ac_), cf.data_ptr(), clair._ptr(B), ell,
+                                                  3, ctypes.byref(Dc), ctypes.byref(info_d), sp_))
     return {"matrix": "first of the workload", "transpose_ms": t_ms, "build_P_ms": p_ms, "galerkin_ms": g_ms,
-            "smooth_B_5_cff_on_AT_ms": s_ms, "project_constraints_k4_ms": k_ms,
+            "smooth_B_5_cff_on_AT_ms": s_ms, "project_constraints_k4_ms": k_ms, "build_R_diag_3_iterations_ms": d_ms,
             "nnz_A": int(A.col_idx.numel()), "nnz_P": int(Pc.nnz), "nnz_Ac": int(Gc.nnz),
             "note": "synchronous C calls into preallocated buffers, wall time, best of 5"}
 
