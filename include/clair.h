@@ -200,7 +200,8 @@ int clair_build_R_batched(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* A,
  *   info      n_c, nnz, max_block, n_uncovered (with B), first_bad_row
  * A pattern F-column j with a_jj = 0 returns CLAIR_ERR_SINGULAR, first_bad_row
  * = the smallest C-point whose row meets one.  Blocks above 64 points return
- * CLAIR_ERR_UNSUPPORTED.  Synchronises `stream`.
+ * CLAIR_ERR_UNSUPPORTED.  cf_marker may be NULL only when A->n = 0.
+ * Synchronises `stream`.
  */
 int clair_build_R_diag(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_marker, const double* B,
                        int32_t ell, int32_t iterations, clair_csr_out_t* R_out, clair_info_t* info, void* stream);

@@ -177,7 +177,10 @@ def project_constraints(o, cf, B, rcond=1e-12):
     """R (an oracle result dict, built unconstrained) after imposing R^T B_c = B
     for the k columns of B (n x k): a new dict; also n_uncovered."""
     lib = _load()
-    Bm = np.ascontiguousarray(np.asarray(B, np.float64).reshape(len(cf), -1))
+    Bm = np.asarray(B, np.float64)
+    Bm = np.ascontiguousarray(Bm if Bm.ndim == 2 else Bm.reshape(-1, 1))
+    if Bm.shape[0] != len(cf):
+        raise ValueError("B must be n x k")
     k = Bm.shape[1]
     va = np.array(o["val"], np.float64, copy=True)
     rp = np.ascontiguousarray(o["row_ptr"], np.int32)

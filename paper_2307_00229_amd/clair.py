@@ -558,9 +558,9 @@ def clair_project_constraints(R, n: int, cf: torch.Tensor, B: torch.Tensor, *, r
     _check_dev(va, torch.float64, "val")
     _check_dev(cf, torch.int8, "cf")
     _check_dev(B, torch.float64, "B")
-    if cf.numel() != n or B.numel() % max(n, 1):
+    Bm = B if B.dim() == 2 else B.reshape(-1, 1)
+    if cf.numel() != n or Bm.shape[0] != n:
         raise ValueError("cf must have n entries and B n x k")
-    Bm = B.reshape(n, -1)
     n_c = rp.numel() - 1
     oc = CsrOut(n_c, n, ci.numel(), n_c + 1, 0, ci.numel(), rp.data_ptr(), ci.data_ptr(), va.data_ptr())
     unc = ctypes.c_int64(0)

@@ -1062,7 +1062,8 @@ int clair_project_constraints(clair_ctx_t* c, clair_csr_out_t* R, int32_t n, con
 
 int clair_build_R_diag(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf, const double* B, int32_t ell,
                        int32_t iterations, clair_csr_out_t* R, clair_info_t* info, void* stream) {
-  if (!c || !R || !cf || ell < 1 || ell > 64 || iterations < 0 || check_csr_args(A)) return CLAIR_ERR_INVALID;
+  if (!c || !R || ell < 1 || ell > 64 || iterations < 0 || check_csr_args(A)) return CLAIR_ERR_INVALID;
+  if (!cf && A->n > 0) return CLAIR_ERR_INVALID;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   const int32_t n = A->n;
   try {

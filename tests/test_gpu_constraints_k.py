@@ -216,3 +216,17 @@ def test_all_c_points_leaves_r_unchanged():
     unc = clair.clair_project_constraints((rp, ci, va), n, cf, torch.rand(n, 3, dtype=torch.float64, device="cuda"))
     assert unc == 0
     assert torch.equal(va, torch.ones_like(va))
+
+
+@pytest.mark.parametrize("idx", [0, 2, 3])
+def test_degenerate_inputs(idx):
+    # no C-points (every F-point uncovered), a C-point with no F-neighbour, n = 0
+    from .test_oracle_approx import _edge_problems
+
+    p = _edge_problems()[idx]
+    print(f"[gpu] constraints degenerate {p.name} n={p.n}", flush=True)
+    B = _Bk(p, 2, 7) if p.n else np.zeros((0, 2))
+    g = _project_gpu(p, _unconstrained(p), B)
+    o = oracle.project_constraints(oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, None, p.ell), p.cf, B)
+    assert g["n_uncovered"] == o["n_uncovered"]
+    assert np.allclose(g["val"], o["val"], rtol=0, atol=1e-14)

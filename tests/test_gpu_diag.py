@@ -130,3 +130,18 @@ def test_zero_diagonal_is_singular():
                                             1, check=False)
     assert st == clair.CLAIR_ERR_SINGULAR
     assert info["first_bad_row"] == expect
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_degenerate_inputs(idx):
+    # no C-points, all C-points, a C-point with no F-neighbour, n = 0
+    from .test_oracle_approx import _edge_problems
+
+    p = _edge_problems()[idx]
+    print(f"[gpu] diag degenerate {p.name} n={p.n} n_c={int((p.cf != 0).sum())}", flush=True)
+    g, info = _gpu_diag(p, p.B, 2)
+    o = oracle.build_R_diag(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, 2)
+    assert g["n_c"] == o["n_c"]
+    assert np.array_equal(g["row_ptr"], o["row_ptr"]) and np.array_equal(g["col_idx"], o["col_idx"])
+    assert np.allclose(g["val"], o["val"], rtol=0, atol=1e-14)
+    assert info["n_uncovered"] == o["n_uncovered"]

@@ -104,3 +104,33 @@ def test_zero_diagonal_is_singular():
             va[e] = 0.0
     with pytest.raises(oracle.OracleError):
         oracle.build_R_diag(p.n, p.row_ptr, p.col_idx, va, p.cf, p.B, p.ell, 1)
+
+
+def _edge_problems():
+    p0 = P.small_2d(12, ell=2)
+    p0.cf = np.zeros(p0.n, np.int8)
+    p1 = P.small_2d(12, ell=2)
+    p1.cf = np.ones(p1.n, np.int8)
+    iso = P.Problem("iso", 3, np.array([0, 2, 4, 6], np.int32), np.array([0, 1, 0, 1, 1, 2], np.int32),
+                    np.array([2.0, -1.0, -1.0, 2.0, -1.0, 2.0]), np.array([1, 1, 0], np.int8), np.ones(3), 2)
+    empty = P.Problem("empty", 0, np.array([0], np.int32), np.zeros(0, np.int32), np.zeros(0),
+                      np.zeros(0, np.int8), np.zeros(0), 1)
+    return [p0, p1, iso, empty]
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_degenerate_inputs(idx):
+    # no C-points, all C-points, a C-point with no F-neighbour, n = 0
+    p = _edge_problems()[idx]
+    got = oracle.build_R_diag(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, 2)
+    n_c = int((p.cf != 0).sum())
+    assert got["n_c"] == n_c
+    exact = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell)
+    assert np.array_equal(got["row_ptr"], exact["row_ptr"]) and np.array_equal(got["col_idx"], exact["col_idx"])
+    assert got["n_uncovered"] == exact["n_uncovered"]
+    if idx in (1, 2):  # every row is a bare injection
+        C = np.nonzero(p.cf)[0]
+        rows = np.repeat(np.arange(n_c), np.diff(got["row_ptr"]))
+        assert np.all(got["val"][got["col_idx"] == C[rows]] == 1.0)
+    if idx == 0:
+        assert got["n_uncovered"] == p.n
