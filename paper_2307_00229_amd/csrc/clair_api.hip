@@ -871,9 +871,10 @@ int clair_build_P(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf, const 
 namespace {
 
 // Symbolic phase of C = X Y (X: X.n rows, k columns; Y: k rows, ny columns):
-// row pointers into c->g_rp (X.n + 1 entries) and nnz(C).  Synchronous.
+// row pointers into c->g_rp (X.n + 1 entries), nnz(C) and the hash-table size
+// the numeric phase takes.  Synchronous.
 int spgemm_symbolic(clair_ctx* c, const clair_csr_t& X, int32_t k, const clair_csr_t& Y, int32_t ny, int64_t* nnz,
-                    hipStream_t s) {
+                    int* lg, hipStream_t s) {
   const int m = X.n;
   HIPCHK(c->g_rp.ensure(sizeof(int32_t) * ((size_t)m + 1)));
   HIPCHK(c->g_cnt.ensure(sizeof(int32_t) * ((size_t)m + 4 + scan_scratch_ints(m))));
@@ -882,7 +883,7 @@ int spgemm_symbolic(clair_ctx* c, const clair_csr_t& X, int32_t k, const clair_c
   int32_t* sums = flags + 4;
   int32_t* crp = static_cast<int32_t*>(c->g_rp.p);
   HIPCHK(hipMemsetAsync(flags, 0, sizeof(int32_t) * 4, s));
-  HIPCHK(launch_spgemm_count(m, X.row_ptr, X.col_idx, k, Y.row_ptr, Y.col_idx, ny, cnt, flags, c->cus, s));
+  HIPCHK(launch_spgemm_count(m, X.row_ptr, X.col_idx, k, Y.row_ptr, Y.col_idx, ny, cnt, flags, lg, c->cus, s));
   HIPCHK(launch_exclusive_scan(cnt, m, crp, sums, c->cus, s));
   int32_t hf[2] = {0, 0};
   int32_t total = 0;
@@ -901,12 +902,13 @@ int check_product_args(const clair_csr_t* X, int32_t x_cols, const clair_csr_t* 
 }
 
 // C = X Y into C (capacities already checked); symbolic phase done (g_rp)
-int spgemm_numeric(clair_ctx* c, const clair_csr_t& X, const clair_csr_t& Y, int32_t* crp, int32_t* cci, double* cva,
-                   hipStream_t s) {
+int spgemm_numeric(clair_ctx* c, const clair_csr_t& X, const clair_csr_t& Y, int lg, int32_t* crp, int32_t* cci,
+                   double* cva, hipStream_t s) {
   const int m = X.n;
   if (crp != c->g_rp.p)
     HIPCHK(hipMemcpyAsync(crp, c->g_rp.p, sizeof(int32_t) * ((size_t)m + 1), hipMemcpyDeviceToDevice, s));
-  HIPCHK(launch_spgemm_fill(m, X.row_ptr, X.col_idx, X.val, Y.row_ptr, Y.col_idx, Y.val, crp, cci, cva, c->cus, s));
+  HIPCHK(launch_spgemm_fill(m, X.row_ptr, X.col_idx, X.val, Y.row_ptr, Y.col_idx, Y.val, crp, cci, cva, lg, c->cus,
+                            s));
   HIPCHK(hipStreamSynchronize(s));
   return CLAIR_OK;
 }
@@ -923,13 +925,14 @@ int clair_spgemm(clair_ctx_t* c, const clair_csr_t* X, int32_t x_cols, const cla
   const hipStream_t s = static_cast<hipStream_t>(stream);
   try {
     int64_t nnz = 0;
-    int rc = spgemm_symbolic(c, *X, x_cols, *Y, y_cols, &nnz, s);
+    int lg = 6;
+    int rc = spgemm_symbolic(c, *X, x_cols, *Y, y_cols, &nnz, &lg, s);
     C->n_rows = X->n;
     C->n_cols = y_cols;
     C->nnz = nnz;
     if (rc) return rc;
     if (!fits(C, X->n, nnz)) return CLAIR_ERR_CAPACITY;
-    return spgemm_numeric(c, *X, *Y, C->row_ptr, C->col_idx, C->val, s);
+    return spgemm_numeric(c, *X, *Y, lg, C->row_ptr, C->col_idx, C->val, s);
   } catch (...) {
     return CLAIR_ERR_NOMEM;
   }
@@ -943,26 +946,27 @@ int clair_galerkin(clair_ctx_t* c, const clair_csr_t* R, const clair_csr_t* A, c
   try {
     // A P (n x n_c) in library buffers
     int64_t nnz_ap = 0;
-    int rc = spgemm_symbolic(c, *A, A->n, *P, n_c, &nnz_ap, s);
+    int lg = 6;
+    int rc = spgemm_symbolic(c, *A, A->n, *P, n_c, &nnz_ap, &lg, s);
     if (rc) return rc;
     if (nnz_ap > INT32_MAX) return CLAIR_ERR_UNSUPPORTED;
     HIPCHK(c->ap_rp.ensure(sizeof(int32_t) * ((size_t)A->n + 1)));
     HIPCHK(c->ap_ci.ensure(sizeof(int32_t) * std::max<int64_t>(1, nnz_ap)));
     HIPCHK(c->ap_va.ensure(sizeof(double) * std::max<int64_t>(1, nnz_ap)));
-    rc = spgemm_numeric(c, *A, *P, static_cast<int32_t*>(c->ap_rp.p), static_cast<int32_t*>(c->ap_ci.p),
+    rc = spgemm_numeric(c, *A, *P, lg, static_cast<int32_t*>(c->ap_rp.p), static_cast<int32_t*>(c->ap_ci.p),
                         static_cast<double*>(c->ap_va.p), s);
     if (rc) return rc;
     const clair_csr_t AP{A->n, (int32_t)nnz_ap, static_cast<int32_t*>(c->ap_rp.p), static_cast<int32_t*>(c->ap_ci.p),
                          static_cast<double*>(c->ap_va.p)};
     // R (A P)
     int64_t nnz = 0;
-    rc = spgemm_symbolic(c, *R, A->n, AP, n_c, &nnz, s);
+    rc = spgemm_symbolic(c, *R, A->n, AP, n_c, &nnz, &lg, s);
     Ac->n_rows = n_c;
     Ac->n_cols = n_c;
     Ac->nnz = nnz;
     if (rc) return rc;
     if (!fits(Ac, n_c, nnz)) return CLAIR_ERR_CAPACITY;
-    return spgemm_numeric(c, *R, AP, Ac->row_ptr, Ac->col_idx, Ac->val, s);
+    return spgemm_numeric(c, *R, AP, lg, Ac->row_ptr, Ac->col_idx, Ac->val, s);
   } catch (...) {
     return CLAIR_ERR_NOMEM;
   }

@@ -40,15 +40,19 @@ size_t scan_scratch_ints(int n);
 hipError_t launch_exclusive_scan(const int32_t* cnt, int n, int32_t* out, int32_t* sums, int cus, hipStream_t s);
 
 // sparse product C = X Y (X: m rows, Y: k x ny), one wavefront per row of C.
-// Symbolic: cnt[i] = distinct columns of row i; flags[0] = 1 for a row above
-// kSpgemmMaxRow columns, flags[1] = 1 for an index out of range.  Numeric:
-// sorted rows at crp[i] (crp from the scan of cnt).
+// Symbolic: cnt[i] = distinct columns of row i; flags (4 ints, zeroed by the
+// caller): [0] = 1 for a row above kSpgemmMaxRow columns, [1] = 1 for an index
+// out of range, [2] the largest product count of a row.  It synchronises the
+// stream once (to size the hash tables) and returns the table size in
+// *lg_out, which the numeric pass takes.  Numeric: sorted rows at crp[i]
+// (crp from the scan of cnt).
 constexpr int kSpgemmMaxRow = 1536;
 hipError_t launch_spgemm_count(int m, const int32_t* xrp, const int32_t* xci, int k, const int32_t* yrp,
-                               const int32_t* yci, int ny, int32_t* cnt, int32_t* flags, int cus, hipStream_t s);
+                               const int32_t* yci, int ny, int32_t* cnt, int32_t* flags, int* lg_out, int cus,
+                               hipStream_t s);
 hipError_t launch_spgemm_fill(int m, const int32_t* xrp, const int32_t* xci, const double* xva, const int32_t* yrp,
                               const int32_t* yci, const double* yva, const int32_t* crp, int32_t* cci, double* cva,
-                              int cus, hipStream_t s);
+                              int lg, int cus, hipStream_t s);
 
 // one weighted Jacobi sweep for M x = 0 on the points with (cf != 0) == which_c
 // (M's rows given); flag: 1 = zero diagonal on a swept row, 2 = bad index

@@ -4,10 +4,13 @@
 //
 // One wavefront per output row.  The row's products x_ij y_jc are gathered
 // into an open-addressing hash table in LDS (keys inserted with LDS
-// compare-and-swap, values summed with LDS FP64 atomics).  The table has up
-// to 2048 slots per wavefront; a row uses the smallest power of two (at least
-// 64) that is twice its number of products, so short rows clear and scan
-// only a few slots.
+// compare-and-swap, values summed with LDS FP64 atomics).  A row uses the
+// smallest power of two (at least 64) that is twice its number of products,
+// so short rows clear and scan only a few slots.  The kernels are compiled
+// for tables of 2^6 .. 2^11 slots per wavefront; the launch takes the size
+// the longest row of the product needs (a first pass finds the largest
+// product count), so LDS does not cap the number of wavefronts per CU when
+// every row is short.
 // then the occupied slots are compacted in place and every entry is written
 // at its rank among the row's columns, so rows come out sorted.  A symbolic
 // pass counts the columns of every row first; the caller scans the counts
@@ -26,10 +29,11 @@ namespace clair {
 
 namespace {
 
-constexpr int kSW = 2;      // wavefronts per workgroup
 constexpr int kLgH = 11;    // log2 of the largest table
-constexpr int kH = 1 << kLgH;  // hash slots per wavefront
+constexpr int kH = 1 << kLgH;  // hash slots per wavefront at most
 static_assert(kSpgemmMaxRow <= kH * 3 / 4, "row bound below the table size");
+// wavefronts per workgroup for a table of 2^LG slots
+constexpr int waves_for(int LG) { return LG <= 8 ? 4 : 2; }
 
 // Inserts key c into a table of 2^lg slots; returns its slot, or -1 when the
 // table holds its bound of keys already (the probe sequence is bounded by
@@ -51,7 +55,9 @@ __device__ __forceinline__ int hash_insert(int* keys, int* count, int c, int lg,
 }
 
 // Table size of row i: the smallest power of two >= max(64, 2 * products),
-// capped at kH; *bound = the keys it may hold
+// capped at 2^LG; *bound = the keys it may hold (below the cap a row never
+// reaches it: it has at most half as many columns as slots)
+template <int LG>
 __device__ __forceinline__ int table_lg(const int32_t* __restrict__ xrp, const int32_t* __restrict__ xci, int k,
                                         const int32_t* __restrict__ yrp, int i, int* bound) {
   const int lane = threadIdx.x & 63;
@@ -63,23 +69,39 @@ __device__ __forceinline__ int table_lg(const int32_t* __restrict__ xrp, const i
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) prod += __shfl_xor(prod, o, 64);
   int lg = 6;
-  while (lg < kLgH && (1ll << lg) < 2 * prod) ++lg;
+  while (lg < LG && (1ll << lg) < 2 * prod) ++lg;
   *bound = (lg == kLgH) ? kSpgemmMaxRow : (1 << lg);
   return lg;
 }
 
-__global__ __launch_bounds__(64 * kSW) void k_sg_count(int m, const int32_t* __restrict__ xrp,
-                                                         const int32_t* __restrict__ xci, int k,
-                                                         const int32_t* __restrict__ yrp,
-                                                         const int32_t* __restrict__ yci, int ny, int32_t* cnt,
-                                                         int32_t* flags) {
-  __shared__ int keys[kSW][kH];
+// largest number of products of a row (indices out of range skipped; the
+// count pass reports them), into *maxprod
+__global__ void k_sg_maxprod(int m, const int32_t* __restrict__ xrp, const int32_t* __restrict__ xci, int k,
+                             const int32_t* __restrict__ yrp, int32_t* maxprod) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < m; i += gridDim.x * 256) {
+    long long prod = 0;
+    for (int e = xrp[i]; e < xrp[i + 1]; ++e) {
+      const int j = xci[e];
+      if ((unsigned)j < (unsigned)k) prod += yrp[j + 1] - yrp[j];
+    }
+    atomicMax(maxprod, (int32_t)min(prod, (long long)(1 << 30)));
+  }
+}
+
+template <int LG>
+__global__ __launch_bounds__(64 * waves_for(LG)) void k_sg_count(int m, const int32_t* __restrict__ xrp,
+                                                                   const int32_t* __restrict__ xci, int k,
+                                                                   const int32_t* __restrict__ yrp,
+                                                                   const int32_t* __restrict__ yci, int ny,
+                                                                   int32_t* cnt, int32_t* flags) {
+  constexpr int kSW = waves_for(LG);
+  __shared__ int keys[kSW][1 << LG];
   __shared__ int count[kSW];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int* kt = keys[wv];
   for (int i = blockIdx.x * kSW + wv; i < m; i += gridDim.x * kSW) {
     int bound;
-    const int lg = table_lg(xrp, xci, k, yrp, i, &bound);
+    const int lg = table_lg<LG>(xrp, xci, k, yrp, i, &bound);
     for (int t = lane; t < (1 << lg); t += 64) kt[t] = -1;
     if (lane == 0) count[wv] = 0;
     wave_sync();
@@ -104,15 +126,18 @@ __global__ __launch_bounds__(64 * kSW) void k_sg_count(int m, const int32_t* __r
   }
 }
 
-__global__ __launch_bounds__(64 * kSW) void k_sg_fill(int m, const int32_t* __restrict__ xrp,
-                                                        const int32_t* __restrict__ xci,
-                                                        const double* __restrict__ xva,
-                                                        const int32_t* __restrict__ yrp,
-                                                        const int32_t* __restrict__ yci,
-                                                        const double* __restrict__ yva,
-                                                        const int32_t* __restrict__ crp, int32_t* cci, double* cva) {
-  __shared__ int keys[kSW][kH];
-  __shared__ double vals[kSW][kH];
+template <int LG>
+__global__ __launch_bounds__(64 * waves_for(LG)) void k_sg_fill(int m, const int32_t* __restrict__ xrp,
+                                                                  const int32_t* __restrict__ xci,
+                                                                  const double* __restrict__ xva,
+                                                                  const int32_t* __restrict__ yrp,
+                                                                  const int32_t* __restrict__ yci,
+                                                                  const double* __restrict__ yva,
+                                                                  const int32_t* __restrict__ crp, int32_t* cci,
+                                                                  double* cva) {
+  constexpr int kSW = waves_for(LG);
+  __shared__ int keys[kSW][1 << LG];
+  __shared__ double vals[kSW][1 << LG];
   __shared__ int count[kSW];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   int* kt = keys[wv];
@@ -121,7 +146,7 @@ __global__ __launch_bounds__(64 * kSW) void k_sg_fill(int m, const int32_t* __re
     const int c0 = crp[i], c1 = crp[i + 1];
     if (c1 == c0) continue;  // empty row (or one the symbolic pass rejected)
     int bound;
-    const int lg = table_lg(xrp, xci, 0x7fffffff, yrp, i, &bound);
+    const int lg = table_lg<LG>(xrp, xci, 0x7fffffff, yrp, i, &bound);
     const int size = 1 << lg;
     for (int t = lane; t < size; t += 64) { kt[t] = -1; vt[t] = 0.0; }
     if (lane == 0) count[wv] = 0;
@@ -162,22 +187,65 @@ __global__ __launch_bounds__(64 * kSW) void k_sg_fill(int m, const int32_t* __re
   }
 }
 
-int sg_grid(int m, int cus) { return std::max(1, std::min((m + kSW - 1) / kSW, cus * 8)); }
+int sg_grid(int m, int waves, int cus) { return std::max(1, std::min((m + waves - 1) / waves, cus * 8)); }
+
+template <int LG>
+void launch_count_lg(int m, const int32_t* xrp, const int32_t* xci, int k, const int32_t* yrp, const int32_t* yci,
+                     int ny, int32_t* cnt, int32_t* flags, int cus, hipStream_t s) {
+  constexpr int W = waves_for(LG);
+  hipLaunchKernelGGL(k_sg_count<LG>, dim3(sg_grid(m, W, cus)), dim3(64 * W), 0, s, m, xrp, xci, k, yrp, yci, ny, cnt,
+                     flags);
+}
+
+template <int LG>
+void launch_fill_lg(int m, const int32_t* xrp, const int32_t* xci, const double* xva, const int32_t* yrp,
+                    const int32_t* yci, const double* yva, const int32_t* crp, int32_t* cci, double* cva, int cus,
+                    hipStream_t s) {
+  constexpr int W = waves_for(LG);
+  hipLaunchKernelGGL(k_sg_fill<LG>, dim3(sg_grid(m, W, cus)), dim3(64 * W), 0, s, m, xrp, xci, xva, yrp, yci, yva,
+                     crp, cci, cva);
+}
 
 }  // namespace
 
 hipError_t launch_spgemm_count(int m, const int32_t* xrp, const int32_t* xci, int k, const int32_t* yrp,
-                               const int32_t* yci, int ny, int32_t* cnt, int32_t* flags, int cus, hipStream_t s) {
-  if (m > 0) hipLaunchKernelGGL(k_sg_count, dim3(sg_grid(m, cus)), dim3(64 * kSW), 0, s, m, xrp, xci, k, yrp, yci, ny,
-                                cnt, flags);
+                               const int32_t* yci, int ny, int32_t* cnt, int32_t* flags, int* lg_out, int cus,
+                               hipStream_t s) {
+  *lg_out = 6;
+  if (m <= 0) return hipSuccess;
+  // the table size: twice the largest product count, as a power of two
+  hipLaunchKernelGGL(k_sg_maxprod, dim3(std::max(1, std::min((m + 255) / 256, cus * 8))), dim3(256), 0, s, m, xrp,
+                     xci, k, yrp, flags + 2);
+  int32_t maxprod = 0;
+  hipError_t e = hipMemcpyAsync(&maxprod, flags + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  int lg = 6;
+  while (lg < kLgH && (1ll << lg) < 2ll * maxprod) ++lg;
+  *lg_out = lg;
+  switch (lg) {
+    case 6: launch_count_lg<6>(m, xrp, xci, k, yrp, yci, ny, cnt, flags, cus, s); break;
+    case 7: launch_count_lg<7>(m, xrp, xci, k, yrp, yci, ny, cnt, flags, cus, s); break;
+    case 8: launch_count_lg<8>(m, xrp, xci, k, yrp, yci, ny, cnt, flags, cus, s); break;
+    case 9: launch_count_lg<9>(m, xrp, xci, k, yrp, yci, ny, cnt, flags, cus, s); break;
+    case 10: launch_count_lg<10>(m, xrp, xci, k, yrp, yci, ny, cnt, flags, cus, s); break;
+    default: launch_count_lg<11>(m, xrp, xci, k, yrp, yci, ny, cnt, flags, cus, s); break;
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_spgemm_fill(int m, const int32_t* xrp, const int32_t* xci, const double* xva, const int32_t* yrp,
                               const int32_t* yci, const double* yva, const int32_t* crp, int32_t* cci, double* cva,
-                              int cus, hipStream_t s) {
-  if (m > 0) hipLaunchKernelGGL(k_sg_fill, dim3(sg_grid(m, cus)), dim3(64 * kSW), 0, s, m, xrp, xci, xva, yrp, yci,
-                                yva, crp, cci, cva);
+                              int lg, int cus, hipStream_t s) {
+  if (m <= 0) return hipSuccess;
+  switch (lg) {
+    case 6: launch_fill_lg<6>(m, xrp, xci, xva, yrp, yci, yva, crp, cci, cva, cus, s); break;
+    case 7: launch_fill_lg<7>(m, xrp, xci, xva, yrp, yci, yva, crp, cci, cva, cus, s); break;
+    case 8: launch_fill_lg<8>(m, xrp, xci, xva, yrp, yci, yva, crp, cci, cva, cus, s); break;
+    case 9: launch_fill_lg<9>(m, xrp, xci, xva, yrp, yci, yva, crp, cci, cva, cus, s); break;
+    case 10: launch_fill_lg<10>(m, xrp, xci, xva, yrp, yci, yva, crp, cci, cva, cus, s); break;
+    default: launch_fill_lg<11>(m, xrp, xci, xva, yrp, yci, yva, crp, cci, cva, cus, s); break;
+  }
   return hipGetLastError();
 }
 
