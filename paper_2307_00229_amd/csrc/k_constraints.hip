@@ -28,7 +28,6 @@ namespace clair {
 namespace {
 
 constexpr int kKT = 256;
-constexpr int kKMax = 4;
 
 __global__ __launch_bounds__(kKT) void k_pk_marks(int n, int n_rows, const int8_t* __restrict__ cf, int32_t* flag,
                                                  int32_t* rowc) {

@@ -2,7 +2,8 @@
 // CSR), for the Galerkin coarse operator A_c = R A P (Section 1: the coarse
 // level of the hierarchy; Section 4.2 forms P and R separately).
 //
-// One wavefront per output row.  The row's products x_ij y_jc are gathered
+// A group of lanes per output row (16 for short rows, else a wavefront), one
+// lane per entry x_ij of X's row (that lane walks row j of Y).  The row's products x_ij y_jc are gathered
 // into an open-addressing hash table in LDS (keys inserted with LDS
 // compare-and-swap, values summed with LDS FP64 atomics).  A row uses the
 // smallest power of two (at least 64) that is twice its number of products,
@@ -54,20 +55,12 @@ __device__ __forceinline__ int hash_insert(int* keys, int* count, int c, int lg,
   return -1;
 }
 
-// Table size of row i: the smallest power of two >= max(64, 2 * products),
-// capped at 2^LG; *bound = the keys it may hold (below the cap a row never
-// reaches it: it has at most half as many columns as slots)
+// Table size for a row of `prod` products: the smallest power of two
+// >= max(64, 2 * prod), capped at 2^LG; *bound = the keys it may hold (below
+// the cap a row never reaches it: it has at most half as many columns as
+// slots)
 template <int LG>
-__device__ __forceinline__ int table_lg(const int32_t* __restrict__ xrp, const int32_t* __restrict__ xci, int k,
-                                        const int32_t* __restrict__ yrp, int i, int* bound) {
-  const int lane = threadIdx.x & 63;
-  long long prod = 0;
-  for (int e = xrp[i] + lane; e < xrp[i + 1]; e += 64) {
-    const int j = xci[e];
-    if ((unsigned)j < (unsigned)k) prod += yrp[j + 1] - yrp[j];
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) prod += __shfl_xor(prod, o, 64);
+__device__ __forceinline__ int table_lg(long long prod, int* bound) {
   int lg = 6;
   while (lg < LG && (1ll << lg) < 2 * prod) ++lg;
   *bound = (lg == kLgH) ? kSpgemmMaxRow : (1 << lg);
@@ -78,47 +71,91 @@ __device__ __forceinline__ int table_lg(const int32_t* __restrict__ xrp, const i
 // count pass reports them), into *maxprod
 __global__ void k_sg_maxprod(int m, const int32_t* __restrict__ xrp, const int32_t* __restrict__ xci, int k,
                              const int32_t* __restrict__ yrp, int32_t* maxprod) {
+  int best = 0;
   for (int i = blockIdx.x * 256 + threadIdx.x; i < m; i += gridDim.x * 256) {
     long long prod = 0;
-    for (int e = xrp[i]; e < xrp[i + 1]; ++e) {
-      const int j = xci[e];
-      if ((unsigned)j < (unsigned)k) prod += yrp[j + 1] - yrp[j];
+    const int x1 = xrp[i + 1];
+    for (int e0 = xrp[i]; e0 < x1; e0 += 8) {  // eight entries' loads in flight together
+      int j[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) j[t] = e0 + t < x1 ? xci[e0 + t] : -1;
+#pragma unroll
+      for (int t = 0; t < 8; ++t)
+        if ((unsigned)j[t] < (unsigned)k) prod += yrp[j[t] + 1] - yrp[j[t]];
     }
-    atomicMax(maxprod, (int32_t)min(prod, (long long)(1 << 30)));
+    best = max(best, (int)min(prod, (long long)(1 << 30)));
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) best = max(best, __shfl_xor(best, o, 64));
+  if ((threadIdx.x & 63) == 0 && best > 0) atomicMax(maxprod, best);
 }
 
+// lanes per row: a quarter wavefront for tables of up to 128 slots (short
+// rows), the whole wavefront above
+constexpr int lanes_for(int LG) { return LG <= 7 ? 16 : 64; }
+
+// Symbolic pass: groups of GL lanes, one row each (lane t of a group takes X
+// entries t, t + GL, ...; the first one's column and Y row bounds stay in
+// registers); the wavefront's loop over its rows is uniform, so the ballots
+// see every group
 template <int LG>
 __global__ __launch_bounds__(64 * waves_for(LG)) void k_sg_count(int m, const int32_t* __restrict__ xrp,
                                                                    const int32_t* __restrict__ xci, int k,
                                                                    const int32_t* __restrict__ yrp,
                                                                    const int32_t* __restrict__ yci, int ny,
                                                                    int32_t* cnt, int32_t* flags) {
-  constexpr int kSW = waves_for(LG);
-  __shared__ int keys[kSW][1 << LG];
-  __shared__ int count[kSW];
+  constexpr int kSW = waves_for(LG), GL = lanes_for(LG), GPW = 64 / GL, NG = kSW * GPW;
+  constexpr uint64_t gmask = GL == 64 ? ~0ull : ((1ull << GL) - 1);
+  __shared__ int keys[NG][1 << LG];
+  __shared__ int count[NG];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int* kt = keys[wv];
-  for (int i = blockIdx.x * kSW + wv; i < m; i += gridDim.x * kSW) {
-    int bound;
-    const int lg = table_lg<LG>(xrp, xci, k, yrp, i, &bound);
-    for (int t = lane; t < (1 << lg); t += 64) kt[t] = -1;
-    if (lane == 0) count[wv] = 0;
-    wave_sync();
-    bool over = false;
-    for (int e = xrp[i]; e < xrp[i + 1]; ++e) {
+  const int g = lane / GL, tl = lane % GL, grp = wv * GPW + g;
+  int* kt = keys[grp];
+  for (int i0 = (blockIdx.x * kSW + wv) * GPW; i0 < m; i0 += gridDim.x * NG) {
+    const int i = i0 + g;
+    const bool live = i < m;
+    const int x0 = live ? xrp[i] : 0, x1 = live ? xrp[i + 1] : 0;
+    const bool mine = x0 + tl < x1;
+    int j0 = -1, ya = 0, yb = 0;
+    long long prod = 0;
+    if (mine) {
+      j0 = xci[x0 + tl];
+      if ((unsigned)j0 < (unsigned)k) { ya = yrp[j0]; yb = yrp[j0 + 1]; prod = yb - ya; }
+    }
+    for (int e = x0 + GL + tl; e < x1; e += GL) {
       const int j = xci[e];
-      if ((unsigned)j >= (unsigned)k) { if (lane == 0) atomicExch(&flags[1], 1); continue; }
-      for (int f = yrp[j] + lane; f < yrp[j + 1]; f += 64) {
+      if ((unsigned)j < (unsigned)k) prod += yrp[j + 1] - yrp[j];
+    }
+#pragma unroll
+    for (int o = GL / 2; o > 0; o >>= 1) prod += __shfl_xor(prod, o, 64);
+    int bound;
+    const int lg = table_lg<LG>(prod, &bound);
+    for (int t = tl; t < (1 << lg); t += GL) kt[t] = -1;
+    if (tl == 0) count[grp] = 0;
+    wave_sync();
+    bool over = false, bad = false;
+    if (mine) {
+      if ((unsigned)j0 >= (unsigned)k) bad = true;
+      for (int f = ya; f < yb; ++f) {
         const int c = yci[f];
-        if ((unsigned)c >= (unsigned)ny) { atomicExch(&flags[1], 1); continue; }
-        if (hash_insert(kt, &count[wv], c, lg, bound) < 0) over = true;
+        if ((unsigned)c >= (unsigned)ny) bad = true;
+        else if (hash_insert(kt, &count[grp], c, lg, bound) < 0) over = true;
       }
     }
+    for (int e = x0 + GL + tl; e < x1; e += GL) {
+      const int j = xci[e];
+      if ((unsigned)j >= (unsigned)k) { bad = true; continue; }
+      for (int f = yrp[j]; f < yrp[j + 1]; ++f) {
+        const int c = yci[f];
+        if ((unsigned)c >= (unsigned)ny) bad = true;
+        else if (hash_insert(kt, &count[grp], c, lg, bound) < 0) over = true;
+      }
+    }
+    if (bad) atomicExch(&flags[1], 1);
     wave_sync();
-    const int n = count[wv];
-    const bool any_over = __ballot(over) != 0 || n > bound;
-    if (lane == 0) {
+    const int n = count[grp];
+    const bool any_over = ((__ballot(over) >> (g * GL)) & gmask) != 0 || n > bound;
+    if (live && tl == 0) {
       cnt[i] = any_over ? 0 : n;
       if (any_over) atomicExch(&flags[0], 1);
     }
@@ -126,6 +163,10 @@ __global__ __launch_bounds__(64 * waves_for(LG)) void k_sg_count(int m, const in
   }
 }
 
+// Numeric pass, the same groups: products into the row's table, then the
+// occupied slots compacted in place (a slot moves only to an index at or
+// below its own, after the group has read the whole run of GL slots) and
+// every entry written at its rank among the row's columns
 template <int LG>
 __global__ __launch_bounds__(64 * waves_for(LG)) void k_sg_fill(int m, const int32_t* __restrict__ xrp,
                                                                   const int32_t* __restrict__ xci,
@@ -135,48 +176,69 @@ __global__ __launch_bounds__(64 * waves_for(LG)) void k_sg_fill(int m, const int
                                                                   const double* __restrict__ yva,
                                                                   const int32_t* __restrict__ crp, int32_t* cci,
                                                                   double* cva) {
-  constexpr int kSW = waves_for(LG);
-  __shared__ int keys[kSW][1 << LG];
-  __shared__ double vals[kSW][1 << LG];
-  __shared__ int count[kSW];
+  constexpr int kSW = waves_for(LG), GL = lanes_for(LG), GPW = 64 / GL, NG = kSW * GPW;
+  constexpr uint64_t gmask = GL == 64 ? ~0ull : ((1ull << GL) - 1);
+  __shared__ int keys[NG][1 << LG];
+  __shared__ double vals[NG][1 << LG];
+  __shared__ int count[NG];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int* kt = keys[wv];
-  double* vt = vals[wv];
-  for (int i = blockIdx.x * kSW + wv; i < m; i += gridDim.x * kSW) {
-    const int c0 = crp[i], c1 = crp[i + 1];
-    if (c1 == c0) continue;  // empty row (or one the symbolic pass rejected)
+  const int g = lane / GL, tl = lane % GL, grp = wv * GPW + g;
+  int* kt = keys[grp];
+  double* vt = vals[grp];
+  for (int i0 = (blockIdx.x * kSW + wv) * GPW; i0 < m; i0 += gridDim.x * NG) {
+    const int i = i0 + g;
+    const int c0 = i < m ? crp[i] : 0, c1 = i < m ? crp[i + 1] : 0;
+    const bool act = c1 > c0;  // empty rows, and rows the symbolic pass rejected, are skipped
+    const int x0 = act ? xrp[i] : 0, x1 = act ? xrp[i + 1] : 0;
+    const bool mine = x0 + tl < x1;
+    int ya = 0, yb = 0;
+    double xv = 0.0;
+    if (mine) {
+      const int j = xci[x0 + tl];
+      xv = xva[x0 + tl];
+      ya = yrp[j];
+      yb = yrp[j + 1];
+    }
+    long long prod = yb - ya;
+    for (int e = x0 + GL + tl; e < x1; e += GL) {
+      const int j = xci[e];
+      prod += yrp[j + 1] - yrp[j];
+    }
+#pragma unroll
+    for (int o = GL / 2; o > 0; o >>= 1) prod += __shfl_xor(prod, o, 64);
     int bound;
-    const int lg = table_lg<LG>(xrp, xci, 0x7fffffff, yrp, i, &bound);
-    const int size = 1 << lg;
-    for (int t = lane; t < size; t += 64) { kt[t] = -1; vt[t] = 0.0; }
-    if (lane == 0) count[wv] = 0;
+    const int lg = table_lg<LG>(prod, &bound);
+    const int size = act ? 1 << lg : 0;
+    for (int t = tl; t < size; t += GL) { kt[t] = -1; vt[t] = 0.0; }
+    if (tl == 0) count[grp] = 0;
     wave_sync();
-    for (int e = xrp[i]; e < xrp[i + 1]; ++e) {
+    for (int f = ya; f < yb; ++f) {
+      const int h = hash_insert(kt, &count[grp], yci[f], lg, bound);
+      if (h >= 0) atomicAdd(&vt[h], xv * yva[f]);
+    }
+    for (int e = x0 + GL + tl; e < x1; e += GL) {
       const int j = xci[e];
       const double x = xva[e];
-      for (int f = yrp[j] + lane; f < yrp[j + 1]; f += 64) {
-        const int h = hash_insert(kt, &count[wv], yci[f], lg, bound);
+      for (int f = yrp[j]; f < yrp[j + 1]; ++f) {
+        const int h = hash_insert(kt, &count[grp], yci[f], lg, bound);
         if (h >= 0) atomicAdd(&vt[h], x * yva[f]);
       }
     }
     wave_sync();
-    // compact the occupied slots in place (a slot moves only to an index at
-    // or below its own, after the whole run of 64 slots has been read)
     int base = 0;
-    for (int t0 = 0; t0 < size; t0 += 64) {
-      const int key = kt[t0 + lane];
-      const double val = vt[t0 + lane];
+    for (int t0 = 0; t0 < size; t0 += GL) {
+      const int key = kt[t0 + tl];
+      const double val = vt[t0 + tl];
       const bool occ = key >= 0;
-      const uint64_t mask = __ballot(occ);
-      const int pos = base + __popcll(mask & ((1ull << lane) - 1));
+      const uint64_t bits = (__ballot(occ) >> (g * GL)) & gmask;
+      const int pos = base + __popcll(bits & ((1ull << tl) - 1));
       wave_sync();
       if (occ) { kt[pos] = key; vt[pos] = val; }
-      base += __popcll(mask);
+      base += __popcll(bits);
       wave_sync();
     }
-    // every entry at its rank among the row's columns
     const int n = min(base, c1 - c0);
-    for (int q = lane; q < n; q += 64) {
+    for (int q = tl; q < n; q += GL) {
       const int key = kt[q];
       int rank = 0;
       for (int s2 = 0; s2 < n; ++s2) rank += kt[s2] < key ? 1 : 0;
@@ -187,14 +249,15 @@ __global__ __launch_bounds__(64 * waves_for(LG)) void k_sg_fill(int m, const int
   }
 }
 
-int sg_grid(int m, int waves, int cus) { return std::max(1, std::min((m + waves - 1) / waves, cus * 8)); }
+// workgroups for m rows at `rows` rows per workgroup
+int sg_grid(int m, int rows, int cus) { return std::max(1, std::min((m + rows - 1) / rows, cus * 8)); }
 
 template <int LG>
 void launch_count_lg(int m, const int32_t* xrp, const int32_t* xci, int k, const int32_t* yrp, const int32_t* yci,
                      int ny, int32_t* cnt, int32_t* flags, int cus, hipStream_t s) {
   constexpr int W = waves_for(LG);
-  hipLaunchKernelGGL(k_sg_count<LG>, dim3(sg_grid(m, W, cus)), dim3(64 * W), 0, s, m, xrp, xci, k, yrp, yci, ny, cnt,
-                     flags);
+  hipLaunchKernelGGL(k_sg_count<LG>, dim3(sg_grid(m, W * (64 / lanes_for(LG)), cus)), dim3(64 * W), 0, s, m, xrp,
+                     xci, k, yrp, yci, ny, cnt, flags);
 }
 
 template <int LG>
@@ -202,8 +265,8 @@ void launch_fill_lg(int m, const int32_t* xrp, const int32_t* xci, const double*
                     const int32_t* yci, const double* yva, const int32_t* crp, int32_t* cci, double* cva, int cus,
                     hipStream_t s) {
   constexpr int W = waves_for(LG);
-  hipLaunchKernelGGL(k_sg_fill<LG>, dim3(sg_grid(m, W, cus)), dim3(64 * W), 0, s, m, xrp, xci, xva, yrp, yci, yva,
-                     crp, cci, cva);
+  hipLaunchKernelGGL(k_sg_fill<LG>, dim3(sg_grid(m, W * (64 / lanes_for(LG)), cus)), dim3(64 * W), 0, s, m, xrp,
+                     xci, xva, yrp, yci, yva, crp, cci, cva);
 }
 
 }  // namespace
