@@ -17,9 +17,9 @@ Modules
                     constraint fit, residual update, explicit projection), for
                     any number k of iterations.
 ``smoothing``    -- CFF-weighted-Jacobi smoothing of the constraint vector.
-``build_R_diag`` -- Algorithm 1 with the diagonal block inverse and any
-                    number of iterations (C oracle, on the exact build's
-                    pattern).
+``build_R_approx`` -- Algorithm 1 with approximate block inverses (diagonal
+                    or ILU(0)) and any number of iterations (C oracle, on the
+                    exact build's pattern); ``build_R_diag`` the diagonal one.
 """
 from __future__ import annotations
 
@@ -65,8 +65,8 @@ def _load():
         lib.orc_build_R.restype = ctypes.c_int
         lib.orc_project_k.argtypes = [i32, i32, p, p, p, p, p, i32, f64, p]
         lib.orc_project_k.restype = ctypes.c_int
-        lib.orc_iterate_diag.argtypes = [i32, p, p, p, p, p, i32, p, p, p, i32, p]
-        lib.orc_iterate_diag.restype = ctypes.c_int
+        lib.orc_iterate_approx.argtypes = [i32, p, p, p, p, p, i32, p, p, p, i32, i32, p]
+        lib.orc_iterate_approx.restype = ctypes.c_int
         lib.orc_max_threads.argtypes = []
         lib.orc_max_threads.restype = ctypes.c_int
         _lib = lib
@@ -143,9 +143,15 @@ def build_R_problem(p, nthreads=0, B="problem", **kw):
 
 
 def build_R_diag(n, row_ptr, col_idx, val, cf, B, ell, iterations, theta=0.0, agg=None):
-    """Algorithm 1 with the diagonal block inverse and `iterations` steps, on
-    the pattern of the exact build (the pattern does not depend on the
-    inverse).  Returns the same dict as build_R (n_uncovered as there)."""
+    """Algorithm 1 with the diagonal block inverse (see build_R_approx)."""
+    return build_R_approx(n, row_ptr, col_idx, val, cf, B, ell, iterations, "diag", theta=theta, agg=agg)
+
+
+def build_R_approx(n, row_ptr, col_idx, val, cf, B, ell, iterations, inverse, theta=0.0, agg=None):
+    """Algorithm 1 with approximate block inverses ("diag": the diagonal of
+    each block; "ilu0": its incomplete LU factorisation without fill) and
+    `iterations` steps, on the pattern of the exact build (the pattern does
+    not depend on the inverse).  Returns the same dict as build_R."""
     lib = _load()
     o = build_R(n, row_ptr, col_idx, val, cf, None, ell, allow_singular=True, theta=theta, agg=agg)
     rp = np.ascontiguousarray(row_ptr, np.int32)
@@ -155,11 +161,12 @@ def build_R_diag(n, row_ptr, col_idx, val, cf, B, ell, iterations, theta=0.0, ag
     Ba = None if B is None else np.ascontiguousarray(B, np.float64)
     Rva = np.zeros(max(o["nnz"], 1), np.float64)
     bad = ctypes.c_int32(-1)
-    rc = lib.orc_iterate_diag(n, _ptr(rp), _ptr(ci), _ptr(va), _ptr(cfa), _ptr(Ba), o["n_c"], _ptr(o["row_ptr"]),
-                              _ptr(np.ascontiguousarray(o["col_idx"], np.int32)), _ptr(Rva), int(iterations),
-                              ctypes.byref(bad))
+    kind = {"diag": 1, "ilu0": 2}[inverse]
+    rc = lib.orc_iterate_approx(n, _ptr(rp), _ptr(ci), _ptr(va), _ptr(cfa), _ptr(Ba), o["n_c"], _ptr(o["row_ptr"]),
+                                _ptr(np.ascontiguousarray(o["col_idx"], np.int32)), _ptr(Rva), kind, int(iterations),
+                                ctypes.byref(bad))
     if rc:
-        raise OracleError(rc, f"oracle iterate_diag failed ({rc}), bad_row={bad.value}")
+        raise OracleError(rc, f"oracle iterate_approx failed ({rc}), bad_row={bad.value}")
     out = dict(o)
     out["val"] = Rva[: o["nnz"]]
     out["bad_row"] = -1

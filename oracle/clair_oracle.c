@@ -577,9 +577,10 @@ int orc_project_k(int32_t n, int32_t n_c, const int32_t* R_rp, const int32_t* R_
 
 /* ------------------------------------------------------------------------ */
 /* Approximate block inverses (Section 3.1.2: a block-diagonal approximate     */
-/* inverse of A_ff^{(*)}, one block per C-point; the footnote of the           */
-/* comparison with root-node names the local diagonal inverse).  Algorithm 1  */
-/* with the diagonal block inverse, on the pattern of an R built beforehand:  */
+/* inverse of A_ff^{(*)}, one block per C-point, e.g. diagonal or ILU; the    */
+/* footnote of the comparison with root-node names the local diagonal         */
+/* inverse).  Algorithm 1 with such inverses, on the pattern of an R built    */
+/* beforehand:                                                                 */
 /*   tentative weights -a_ij on the pattern;                                   */
 /*   with B: each F-column j is replaced by the minimum-norm solution of its  */
 /*     constraint, z_ij = B_i B_j / d_j, d_j = sum_{i in I_j} B_i^2;          */
@@ -587,18 +588,50 @@ int orc_project_k(int32_t n, int32_t n_c, const int32_t* R_rp, const int32_t* R_
 /*     residual of row i on its pattern: rho_ij = -(R A)_ij, j in N(i)        */
 /*       (R's row holds z on N(i) and 1 at i, so (R A)_ij = a_ij +            */
 /*       sum_{l in N(i)} z_il a_lj: the residual -a_i - A[N,N]^T z_i);        */
-/*     u_ij = rho_ij / a_jj (the diagonal of the block);                      */
+/*     u_i = Khat_i^{-1} rho_i with K_i = A[N,N]^T: inverse = 1 takes the     */
+/*       diagonal (u_ij = rho_ij / a_jj), inverse = 2 the incomplete LU       */
+/*       factorisation of K_i without fill (ILU(0): the factors keep K_i's    */
+/*       nonzero pattern; row-oriented elimination, unit lower factor);       */
 /*     with B: u_ij -= B_i (sum_i u_ij B_i) / d_j (the projection; Q Q^T is  */
 /*       diagonal);                                                            */
 /*     z += u.                                                                 */
 /* The residual is formed row by row: row i of R times the rows of A.         */
-/* Returns ORC_ERR_SINGULAR (bad_row = the smallest C-point whose row meets   */
-/* it) when a pattern column has no nonzero diagonal entry.                   */
+/* Returns ORC_ERR_SINGULAR (bad_row = the smallest C-point concerned) when a */
+/* pattern column has no nonzero diagonal entry (diagonal) or a pivot of the  */
+/* incomplete factorisation is zero (ILU(0)).                                 */
 /* ------------------------------------------------------------------------ */
-int orc_iterate_diag(int32_t n, const int32_t* rp, const int32_t* ci, const double* va, const int8_t* cf,
-                     const double* B, int32_t n_c, const int32_t* R_rp, const int32_t* R_ci, double* R_va,
-                     int32_t iterations, int32_t* bad_row) {
-  if (iterations < 0 || check_csr(n, rp, ci)) return ORC_ERR_INVALID;
+/* ILU(0) of the s x s matrix K (row-major) in place: multipliers below the
+   diagonal (unit lower factor), U on and above; only positions where K is
+   nonzero on entry are updated.  Returns 1 on a zero pivot. */
+static int ilu0(double* K, int32_t s, unsigned char* mask) {
+  for (int64_t t = 0; t < (int64_t)s * s; ++t) mask[t] = K[t] != 0.0;
+  for (int32_t a = 0; a < s; ++a) {
+    for (int32_t b = 0; b < a; ++b) {
+      if (!mask[(int64_t)a * s + b]) continue;
+      K[(int64_t)a * s + b] /= K[(int64_t)b * s + b];
+      const double m = K[(int64_t)a * s + b];
+      for (int32_t c = b + 1; c < s; ++c)
+        if (mask[(int64_t)a * s + c]) K[(int64_t)a * s + c] -= m * K[(int64_t)b * s + c];
+    }
+    if (K[(int64_t)a * s + a] == 0.0) return 1;
+  }
+  return 0;
+}
+
+/* x = (L U)^{-1} x with the factors of ilu0 */
+static void ilu0_solve(const double* K, int32_t s, double* x) {
+  for (int32_t a = 0; a < s; ++a)
+    for (int32_t b = 0; b < a; ++b) x[a] -= K[(int64_t)a * s + b] * x[b];
+  for (int32_t a = s - 1; a >= 0; --a) {
+    for (int32_t c = a + 1; c < s; ++c) x[a] -= K[(int64_t)a * s + c] * x[c];
+    x[a] /= K[(int64_t)a * s + a];
+  }
+}
+
+int orc_iterate_approx(int32_t n, const int32_t* rp, const int32_t* ci, const double* va, const int8_t* cf,
+                       const double* B, int32_t n_c, const int32_t* R_rp, const int32_t* R_ci, double* R_va,
+                       int32_t inverse, int32_t iterations, int32_t* bad_row) {
+  if (iterations < 0 || (inverse != 1 && inverse != 2) || check_csr(n, rp, ci)) return ORC_ERR_INVALID;
   const size_t nn = (size_t)(n > 0 ? n : 1);
   const int64_t nnz = R_rp[n_c];
   int32_t* clist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_c > 0 ? n_c : 1));
@@ -624,14 +657,59 @@ int orc_iterate_diag(int32_t n, const int32_t* rp, const int32_t* ci, const doub
     for (int32_t e = rp[j]; e < rp[j + 1]; ++e)
       if (ci[e] == j) diag[j] += va[e];
   int32_t first_bad = -1;
-  for (int32_t r = 0; r < n_c && first_bad < 0; ++r)
-    for (int32_t e = R_rp[r]; e < R_rp[r + 1]; ++e)
-      if (R_ci[e] != clist[r] && diag[R_ci[e]] == 0.0) { first_bad = clist[r]; break; }
+  if (inverse == 1)
+    for (int32_t r = 0; r < n_c && first_bad < 0; ++r)
+      for (int32_t e = R_rp[r]; e < R_rp[r + 1]; ++e)
+        if (R_ci[e] != clist[r] && diag[R_ci[e]] == 0.0) { first_bad = clist[r]; break; }
+  /* ILU(0) factors of every block K_i = A[N,N]^T (N = the row's F-columns) */
+  double* fac = NULL;
+  int64_t* foff = NULL;
+  if (inverse == 2 && first_bad < 0) {
+    foff = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_c + 1));
+    if (!foff) { free(clist); free(diag); free(d); free(sj); free(u); return ORC_ERR_NOMEM; }
+    foff[0] = 0;
+    int32_t smax = 0;
+    for (int32_t r = 0; r < n_c; ++r) {
+      const int32_t sr = R_rp[r + 1] - R_rp[r] - 1;
+      foff[r + 1] = foff[r] + (int64_t)sr * sr;
+      if (sr > smax) smax = sr;
+    }
+    fac = (double*)calloc((size_t)(foff[n_c] > 0 ? foff[n_c] : 1), sizeof(double));
+    int32_t* N = (int32_t*)malloc(sizeof(int32_t) * (size_t)(smax > 0 ? smax : 1));
+    unsigned char* mask = (unsigned char*)malloc((size_t)smax * smax + 1);
+    if (!fac || !N || !mask) {
+      free(fac); free(foff); free(N); free(mask); free(clist); free(diag); free(d); free(sj); free(u);
+      return ORC_ERR_NOMEM;
+    }
+    for (int32_t r = 0; r < n_c && first_bad < 0; ++r) {
+      const int32_t i = clist[r];
+      int32_t sr = 0;
+      for (int32_t e = R_rp[r]; e < R_rp[r + 1]; ++e)
+        if (R_ci[e] != i) N[sr++] = R_ci[e];
+      double* K = fac + foff[r];
+      /* K[q][p] = a_{N_p, N_q} */
+      for (int32_t p2 = 0; p2 < sr; ++p2) {
+        const int32_t row = N[p2];
+        for (int32_t e = rp[row]; e < rp[row + 1]; ++e) {
+          const int32_t q = find_sorted(N, sr, ci[e]);
+          if (q >= 0) K[(int64_t)q * sr + p2] += va[e];
+        }
+      }
+      if (sr > 0 && ilu0(K, sr, mask)) first_bad = i;
+    }
+    free(N);
+    free(mask);
+  }
   if (first_bad >= 0) {
     if (bad_row) *bad_row = first_bad;
-    free(clist); free(diag); free(d); free(sj); free(u);
+    free(fac); free(foff); free(clist); free(diag); free(d); free(sj); free(u);
     return ORC_ERR_SINGULAR;
   }
+  int32_t maxlen = 1;
+  for (int32_t r = 0; r < n_c; ++r)
+    if (R_rp[r + 1] - R_rp[r] > maxlen) maxlen = R_rp[r + 1] - R_rp[r];
+  double* xs = (double*)malloc(sizeof(double) * (size_t)maxlen);
+  if (!xs) { free(fac); free(foff); free(clist); free(diag); free(d); free(sj); free(u); return ORC_ERR_NOMEM; }
   /* tentative weights, then the constraint fit */
   for (int32_t r = 0; r < n_c; ++r) {
     const int32_t i = clist[r];
@@ -668,9 +746,19 @@ int orc_iterate_diag(int32_t n, const int32_t* rp, const int32_t* ci, const doub
           if (p >= 0) u[e0 + p] += zl * va[t];
         }
       }
-      for (int32_t e = e0; e < e0 + len; ++e) {
-        const int32_t j = R_ci[e];
-        u[e] = (j == i) ? 0.0 : -u[e] / diag[j];
+      if (inverse == 1) {
+        for (int32_t e = e0; e < e0 + len; ++e) {
+          const int32_t j = R_ci[e];
+          u[e] = (j == i) ? 0.0 : -u[e] / diag[j];
+        }
+      } else {
+        /* the row's F-entries in order, then (L U)^{-1} */
+        int32_t sr = 0;
+        for (int32_t e = e0; e < e0 + len; ++e)
+          if (R_ci[e] != i) xs[sr++] = -u[e];
+        ilu0_solve(fac + foff[r], sr, xs);
+        sr = 0;
+        for (int32_t e = e0; e < e0 + len; ++e) u[e] = (R_ci[e] == i) ? 0.0 : xs[sr++];
       }
     }
     if (B) {
@@ -687,7 +775,7 @@ int orc_iterate_diag(int32_t n, const int32_t* rp, const int32_t* ci, const doub
     }
     for (int64_t e = 0; e < nnz; ++e) R_va[e] += u[e];
   }
-  free(clist); free(diag); free(d); free(sj); free(u);
+  free(xs); free(fac); free(foff); free(clist); free(diag); free(d); free(sj); free(u);
   return ORC_OK;
 }
 

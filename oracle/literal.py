@@ -27,12 +27,33 @@ import numpy as np
 from . import dense
 
 
+def _ilu0(K: np.ndarray):
+    """Incomplete LU of K without fill: L unit lower, U upper, both on K's
+    nonzero pattern; L U agrees with K on that pattern (the defining property,
+    Saad, Iterative Methods for Sparse Linear Systems, Section 10.3)."""
+    s = K.shape[0]
+    P = K != 0
+    W = K.astype(np.float64).copy()
+    for a in range(1, s):
+        for b in range(a):
+            if not P[a, b]:
+                continue
+            W[a, b] /= W[b, b]
+            for c in range(b + 1, s):
+                if P[a, c]:
+                    W[a, c] -= W[a, b] * W[b, c]
+    L = np.tril(W, -1) + np.eye(s)
+    U = np.triu(W)
+    return L, U
+
+
 def algorithm1_R(A: np.ndarray, cf: np.ndarray, B, ell: int, k: int = 1,
                  fit_constraint: bool = True, theta: float = 0.0, agg=None, inverse: str = "exact"):
     """Dense R (n_c x n) from the literal Algorithm 1 on A^T (strength threshold theta).
 
-    inverse: "exact" (the block inverses of step 3) or "diag" (the local
-    diagonal inverse of each block).  B = None drops the constraint lines
+    inverse: "exact" (the block inverses of step 3), "diag" (the local
+    diagonal inverse of each block) or "ilu0" (the inverse of each block's
+    incomplete LU factors without fill).  B = None drops the constraint lines
     (the fit of step 2 and the projection of step 4)."""
     n = A.shape[0]
     At = A.T
@@ -85,6 +106,9 @@ def algorithm1_R(A: np.ndarray, cf: np.ndarray, B, ell: int, k: int = 1,
             inv[c] = np.linalg.inv(blocks[c])
         elif inverse == "diag":
             inv[c] = np.diag(1.0 / np.diag(blocks[c]))
+        elif inverse == "ilu0":
+            L, U = _ilu0(blocks[c])
+            inv[c] = np.linalg.inv(U) @ np.linalg.inv(L)
         else:
             raise ValueError(inverse)
 

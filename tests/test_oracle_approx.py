@@ -134,3 +134,98 @@ def test_degenerate_inputs(idx):
         assert np.all(got["val"][got["col_idx"] == C[rows]] == 1.0)
     if idx == 0:
         assert got["n_uncovered"] == p.n
+
+
+# ---------------------------------------------------------------- ILU(0) ---
+def _tridiag_1d(n=60, eps=0.1, b=1.0):
+    """1D upwind advection-diffusion on n interior nodes, every third node C."""
+    h = 1.0 / (n + 1)
+    rp, ci, va = [0], [], []
+    for r in range(n):
+        row = []
+        if r > 0:
+            row.append((r - 1, -eps / h**2 - b / h))
+        row.append((r, 2 * eps / h**2 + b / h))
+        if r < n - 1:
+            row.append((r + 1, -eps / h**2))
+        for c_, v in row:
+            ci.append(c_)
+            va.append(v)
+        rp.append(len(ci))
+    cf = np.array([1 if r % 3 == 0 else 0 for r in range(n)], np.int8)
+    return P.Problem("tridiag1d", n, np.array(rp, np.int32), np.array(ci, np.int32), np.array(va), cf,
+                     np.ones(n), 2)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_ilu0_factors_agree_with_the_block_on_its_pattern(seed):
+    # the defining property of ILU(0): L U = K at every nonzero of K, with L
+    # (unit lower) and U (upper) supported on K's pattern
+    rng = np.random.default_rng(seed)
+    s = 3 + seed * 3
+    K = np.where(rng.random((s, s)) < 0.35, -rng.uniform(0.1, 1.0, (s, s)), 0.0)
+    np.fill_diagonal(K, np.abs(K).sum(axis=1) + rng.uniform(0.5, 1.5, s))
+    L, U = literal._ilu0(K)
+    Pm = K != 0
+    assert np.allclose((L @ U)[Pm], K[Pm], rtol=1e-13, atol=1e-13 * np.abs(K).max())
+    assert np.all((np.tril(L, -1) != 0) <= Pm) and np.all((U != 0) <= Pm)
+    assert np.allclose(np.diag(L), 1.0)
+
+
+@pytest.mark.parametrize("iters", [0, 1, 3])
+@pytest.mark.parametrize("constrained", [True, False])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_ilu0_equals_literal_algorithm1(case, constrained, iters):
+    p = CASES[case]()
+    B = p.B if constrained else None
+    got = oracle.build_R_approx(p.n, p.row_ptr, p.col_idx, p.val, p.cf, B, p.ell, iters, "ilu0")
+    A = dense.to_dense(p.n, p.row_ptr, p.col_idx, p.val)
+    Rl = literal.algorithm1_R(A, p.cf, B, p.ell, k=iters, inverse="ilu0")
+    R = _dense_R(got, p.n)
+    assert np.max(np.abs(Rl - R)) <= 1e-12 * max(1.0, np.max(np.abs(R)))
+
+
+def test_ilu0_exact_on_tridiagonal_blocks():
+    # 1D, distance 2, every third node C: each block is two uncoupled 2 x 2
+    # pairs, which have no fill, so ILU(0) is the exact inverse and one
+    # iteration gives the closed form; the diagonal inverse does not
+    p = _tridiag_1d()
+    exact = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell)
+    for iters in (1, 2):
+        got = oracle.build_R_approx(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, iters, "ilu0")
+        assert np.array_equal(got["col_idx"], exact["col_idx"])
+        assert np.allclose(got["val"], exact["val"], rtol=0, atol=1e-13 * np.abs(exact["val"]).max())
+    diag = oracle.build_R_approx(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, 1, "diag")
+    assert np.abs(diag["val"] - exact["val"]).max() > 1e-3 * np.abs(exact["val"]).max()
+
+
+@pytest.mark.parametrize("case", [1, 2, 3])
+def test_ilu0_unconstrained_limit_is_exact_lair(case):
+    # on these M-matrices ILU(0) is a convergent splitting of every block
+    p = CASES[case]()
+    exact = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, None, p.ell)
+    got = oracle.build_R_approx(p.n, p.row_ptr, p.col_idx, p.val, p.cf, None, p.ell, 100, "ilu0")
+    assert np.max(np.abs(got["val"] - exact["val"])) <= 1e-10 * np.abs(exact["val"]).max()
+    # and it gets there faster than the diagonal
+    e_ilu = np.abs(oracle.build_R_approx(p.n, p.row_ptr, p.col_idx, p.val, p.cf, None, p.ell, 3, "ilu0")["val"]
+                   - exact["val"]).max()
+    e_dia = np.abs(oracle.build_R_approx(p.n, p.row_ptr, p.col_idx, p.val, p.cf, None, p.ell, 3, "diag")["val"]
+                   - exact["val"]).max()
+    assert e_ilu < e_dia
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_ilu0_iterates_meet_the_constraint(case):
+    p = CASES[case]()
+    got = oracle.build_R_approx(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, 2, "ilu0")
+    C = np.nonzero(p.cf)[0]
+    rows = np.repeat(np.arange(got["n_c"]), np.diff(got["row_ptr"]))
+    fm = got["col_idx"] != C[rows]
+    terms = got["val"][fm] * p.B[C[rows[fm]]]
+    S = np.zeros(p.n)
+    T = np.zeros(p.n)
+    np.add.at(S, got["col_idx"][fm], terms)
+    np.add.at(T, got["col_idx"][fm], np.abs(terms))
+    cov = np.zeros(p.n, bool)
+    cov[got["col_idx"][fm]] = True
+    assert (np.abs(S[cov] - p.B[cov]) / (np.abs(p.B[cov]) + T[cov])).max() <= 1e-13
