@@ -180,29 +180,43 @@ int clair_build_R_batched(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* A,
                           clair_csr_out_t* R_out, const clair_opts_t* opts, clair_info_t* info);
 
 /*
- * clair_build_R_diag -- Algorithm 1 with approximate block inverses (Section
- * 3.1.2): every local block A_ff^{(i)} replaced by its diagonal (the
- * root-node-like variant of the footnote in the comparison with root-node),
- * run for `iterations` steps.  Same pattern as clair_build_R (distance-ell
- * F-neighbourhoods, the context's strength threshold), no local solves:
+ * clair_build_R_approx -- Algorithm 1 with approximate block inverses
+ * (Section 3.1.2 allows a diagonal, GMRES or ILU approximation of each block
+ * A_ff^{(i)}; the footnote of the comparison with root-node names the
+ * diagonal one), run for `iterations` steps.  Same pattern as clair_build_R
+ * (distance-ell F-neighbourhoods, the context's strength threshold), no exact
+ * local solves.  With K_i = A[N,N]^T the block of C-point i:
+ *   inverse = CLAIR_INVERSE_DIAG: K_i replaced by its diagonal (a_jj);
+ *   inverse = CLAIR_INVERSE_ILU0: by its incomplete LU factors without fill
+ *             (ILU(0): unit lower L and upper U on K_i's nonzero pattern,
+ *             L U = K_i there; row-oriented elimination).
  *   start: z_ij = -a_ij (the tentative operator); with B, every F-column is
  *          replaced by the minimum-norm solution of its constraint,
  *          z_ij = B_i B_j / d_j with d_j = sum over the column's rows of B_i^2;
- *   each iteration: u_ij = -(R A)_ij / a_jj on the F-entries (the block
- *          residual scaled by the block's diagonal), projected with B
+ *   each iteration: rho_i = -(R A) on row i's F-entries (the block
+ *          residual), u_i = Khat_i^{-1} rho_i, projected with B
  *          (u_ij -= B_i sum_i(u_ij B_i) / d_j), then z += u.
- * Every iterate meets the constraint where B is given.  With exact inverses
- * one iteration gives clair_build_R's result (Remark 2); with the diagonal
- * it does when every block is diagonal.  FP64 throughout; per-column sums by
+ * Every iterate meets the constraint where B is given.  One iteration gives
+ * clair_build_R's result when the approximate inverse is exact for every
+ * block (Remark 2): diagonal blocks for the diagonal, blocks whose
+ * factorisation has no fill for ILU(0).  FP64 throughout; per-column sums by
  * FP64 atomics (rounding order not fixed).
  *   R_out     as for clair_build_R (n_rows, n_cols, nnz set; too small
  *             capacities return CLAIR_ERR_CAPACITY, a size query)
  *   info      n_c, nnz, max_block, n_uncovered (with B), first_bad_row
- * A pattern F-column j with a_jj = 0 returns CLAIR_ERR_SINGULAR, first_bad_row
- * = the smallest C-point whose row meets one.  Blocks above 64 points return
- * CLAIR_ERR_UNSUPPORTED.  cf_marker may be NULL only when A->n = 0.
- * Synchronises `stream`.
+ * A zero diagonal on a pattern F-column (diagonal) or a zero pivot (ILU(0))
+ * returns CLAIR_ERR_SINGULAR, first_bad_row = the smallest C-point concerned.
+ * Blocks above 64 points return CLAIR_ERR_UNSUPPORTED; an unknown `inverse`
+ * CLAIR_ERR_INVALID.  cf_marker may be NULL only when A->n = 0.  ILU(0)
+ * keeps n_c x (s^2 + s) doubles of factors (s the largest block) in the
+ * context.  Synchronises `stream`.
  */
+enum { CLAIR_INVERSE_DIAG = 1, CLAIR_INVERSE_ILU0 = 2 };
+int clair_build_R_approx(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_marker, const double* B,
+                         int32_t ell, int32_t inverse, int32_t iterations, clair_csr_out_t* R_out, clair_info_t* info,
+                         void* stream);
+
+/* clair_build_R_diag -- clair_build_R_approx with CLAIR_INVERSE_DIAG. */
 int clair_build_R_diag(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_marker, const double* B,
                        int32_t ell, int32_t iterations, clair_csr_out_t* R_out, clair_info_t* info, void* stream);
 

@@ -30,7 +30,8 @@ EXPORTED = [
     "clair_ctx_create", "clair_ctx_destroy", "clair_build_R", "clair_build_R_ex", "clair_build_R_batched",
     "clair_ctx_info", "clair_size_R", "clair_ctx_stage_times", "clair_ctx_set_tuning", "clair_ctx_get_tuning",
     "clair_ctx_set_strength", "clair_ctx_get_strength", "clair_transpose", "clair_build_P",
-    "clair_spgemm", "clair_galerkin", "clair_smooth_B", "clair_build_R_agg", "clair_project_constraints", "clair_build_R_diag",
+    "clair_spgemm", "clair_galerkin", "clair_smooth_B", "clair_build_R_agg", "clair_project_constraints",
+    "clair_build_R_diag", "clair_build_R_approx",
     "clair_autotune", "clair_graph_create", "clair_graph_launch", "clair_graph_destroy", "clair_graph_info",
     "clair_plan_create", "clair_plan_execute", "clair_plan_info", "clair_plan_destroy",
     "clair_strerror", "clair_last_error",
@@ -129,6 +130,8 @@ def load_library(path: str = LIB_PATH):
                                        ctypes.POINTER(I64), P], ctypes.c_int),
         "clair_build_R_diag": ([P, ctypes.POINTER(CsrIn), P, P, I32, I32, ctypes.POINTER(CsrOut),
                                 ctypes.POINTER(Info), P], ctypes.c_int),
+        "clair_build_R_approx": ([P, ctypes.POINTER(CsrIn), P, P, I32, I32, I32, ctypes.POINTER(CsrOut),
+                                  ctypes.POINTER(Info), P], ctypes.c_int),
         "clair_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "clair_last_error": ([], ctypes.c_char_p),
     }
@@ -514,9 +517,19 @@ def clair_build_R_agg(As: Sequence[CSR], cfs, aggs, Bs, ells, *, ctx: Optional[C
     return outs, [i.as_dict() for i in infos], st
 
 
-def clair_build_R_diag(A: CSR, cf: torch.Tensor, B: Optional[torch.Tensor], ell: int, iterations: int, *,
-                       ctx: Optional[Context] = None, stream=None, check: bool = True):
+CLAIR_INVERSE_DIAG, CLAIR_INVERSE_ILU0 = 1, 2
+
+
+def clair_build_R_diag(A: CSR, cf: torch.Tensor, B: Optional[torch.Tensor], ell: int, iterations: int, **kw):
     """Algorithm 1 with the diagonal block inverse: ((row_ptr, col_idx, val), info, status)."""
+    return clair_build_R_approx(A, cf, B, ell, iterations, inverse=CLAIR_INVERSE_DIAG, **kw)
+
+
+def clair_build_R_approx(A: CSR, cf: torch.Tensor, B: Optional[torch.Tensor], ell: int, iterations: int, *,
+                         inverse: int = CLAIR_INVERSE_DIAG, ctx: Optional[Context] = None, stream=None,
+                         check: bool = True):
+    """Algorithm 1 with approximate block inverses (CLAIR_INVERSE_DIAG or
+    CLAIR_INVERSE_ILU0): ((row_ptr, col_idx, val), info, status)."""
     lib = load_library()
     ctx = ctx or Context()
     _check_dev(cf, torch.int8, "cf")
@@ -527,20 +540,20 @@ def clair_build_R_diag(A: CSR, cf: torch.Tensor, B: Optional[torch.Tensor], ell:
     Ac = A.c()
 
     def call(o):
-        return lib.clair_build_R_diag(ctx.handle, ctypes.byref(Ac), cf.data_ptr(), _ptr(B), int(ell),
-                                      int(iterations), ctypes.byref(o), ctypes.byref(info), sp_)
+        return lib.clair_build_R_approx(ctx.handle, ctypes.byref(Ac), cf.data_ptr(), _ptr(B), int(ell), int(inverse),
+                                        int(iterations), ctypes.byref(o), ctypes.byref(info), sp_)
 
     probe = CsrOut()
     st = call(probe)
     if st not in (CLAIR_OK, CLAIR_ERR_CAPACITY):
         if check:
-            raise ClairError(st, "clair_build_R_diag")
+            raise ClairError(st, "clair_build_R_approx")
         return None, info.as_dict(), st
     out = ROut(int(probe.n_rows), int(probe.nnz), device=A.row_ptr.device)
     oc = out.c()
     st = call(oc)
     if st and check:
-        raise ClairError(st, "clair_build_R_diag")
+        raise ClairError(st, "clair_build_R_approx")
     out.n_c = int(oc.n_rows)
     out.nnz = int(oc.nnz)
     return out.trimmed(), info.as_dict(), st

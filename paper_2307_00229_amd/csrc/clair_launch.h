@@ -80,11 +80,16 @@ hipError_t launch_project_k(int n, int n_rows, const int32_t* rp, const int32_t*
                             const double* B, int k, double rcond, const ProjectScratch& w,
                             unsigned long long* uncovered, int cus, hipStream_t s);
 
-// Algorithm 1 with the diagonal block inverse, on R's pattern (rows sorted,
+// Algorithm 1 with approximate block inverses, on R's pattern (rows sorted,
 // the C-point's own entry included).  A^T in trp/tci/tva; clist[q] = the
 // C-point of row q; work arrays: diag, d, sj (n), cnt (n, zeroed), u and erow
-// (nnz), *bad_row (INT32_MAX beforehand), *uncovered (zeroed).
+// (nnz), *bad_row (INT32_MAX beforehand), *uncovered (zeroed).  ilu: ILU(0)
+// of every block instead of its diagonal, factors at fac + q * fstride
+// (fstride >= s^2 + s doubles for the largest block s <= 64).
 struct DiagWork {
+  int ilu;
+  double* fac;
+  int64_t fstride;
   int n, n_c;
   int64_t nnz;
   int cus;

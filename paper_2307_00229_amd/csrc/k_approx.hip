@@ -1,15 +1,20 @@
-// k_approx.hip -- Algorithm 1 with the diagonal block inverse (Section 3.1.2:
-// a block-diagonal approximate inverse of A_ff^{(*)}; the footnote of the
-// comparison with root-node names the local diagonal inverse), run for a given
-// number of iterations on a pattern built beforehand.
+// k_approx.hip -- Algorithm 1 with approximate block inverses (Section 3.1.2:
+// a block-diagonal approximate inverse of A_ff^{(*)}, e.g. diagonal or ILU;
+// the footnote of the comparison with root-node names the local diagonal
+// inverse), run for a given number of iterations on a pattern built
+// beforehand.  Two inverses: the diagonal of each block K_i = A[N,N]^T, or
+// its incomplete LU factorisation without fill (ILU(0)).
 //
 // One thread per entry of R (row q, C-point i = clist[q], column j):
 //   start: -a_ij (the tentative operator), or with B the minimum-norm fit of
 //          each F-column's constraint, z_ij = B_i B_j / d_j;
 //   per iteration:
-//     u_ij = -(R A)_ij / a_jj on the F-entries: column j of A is read from
-//            A^T and each a_lj is paired with R's entry (q, l), found by a
-//            binary search of row q (sorted; it holds the C-point's 1 too);
+//     rho_ij = -(R A)_ij on the F-entries: column j of A is read from A^T
+//            and each a_lj is paired with R's entry (q, l), found by a binary
+//            search of row q (sorted; it holds the C-point's 1 too);
+//     u_i = Khat_i^{-1} rho_i: rho_ij / a_jj (diagonal, same kernel), or the
+//            two triangular solves with the row's ILU(0) factors (one thread
+//            per row, in place on the row's entries);
 //            with B, s_j += u_ij B_i (FP64 atomics);
 //     z_ij += u_ij - B_i s_j / d_j (the projection; Q Q^T is diagonal).
 // The residual reads only the old R, so each iteration is one residual
@@ -61,7 +66,7 @@ __global__ __launch_bounds__(kAT) void k_ap_start(int64_t nnz, const int32_t* __
       Rva[e] = 1.0;
       continue;
     }
-    if (diag[j] == 0.0) atomicMin(bad_row, i);
+    if (bad_row && diag[j] == 0.0) atomicMin(bad_row, i);
     atomicAdd(&cnt[j], 1);
     if (B) {
       unsafeAtomicAdd(&d[j], B[i] * B[i]);
@@ -92,7 +97,7 @@ __global__ __launch_bounds__(kAT) void k_ap_resid(int64_t nnz, const int32_t* __
                                                  const int32_t* __restrict__ Rci, const double* __restrict__ Rva,
                                                  const int32_t* __restrict__ trp, const int32_t* __restrict__ tci,
                                                  const double* __restrict__ tva, const double* __restrict__ diag,
-                                                 const double* __restrict__ B, double* u, double* sj) {
+                                                 const double* __restrict__ B, double* u, double* sj, int scale) {
   for (int64_t e = blockIdx.x * (int64_t)kAT + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * kAT) {
     const int q = erow[e];
     const int i = clist[q];
@@ -112,9 +117,13 @@ __global__ __launch_bounds__(kAT) void k_ap_resid(int64_t nnz, const int32_t* __
       }
       if (lo < len && Rci[r0 + lo] == l) acc += Rva[r0 + lo] * tva[t];
     }
-    const double x = -acc / diag[j];
-    u[e] = x;
-    if (B) unsafeAtomicAdd(&sj[j], x * B[i]);
+    if (scale) {  // the diagonal inverse
+      const double x = -acc / diag[j];
+      u[e] = x;
+      if (B) unsafeAtomicAdd(&sj[j], x * B[i]);
+    } else {
+      u[e] = -acc;
+    }
   }
 }
 
@@ -130,6 +139,102 @@ __global__ __launch_bounds__(kAT) void k_ap_update(int64_t nnz, const int32_t* _
     double x = u[e];
     if (B && d[j] > 0.0) x -= B[i] * sj[j] / d[j];
     Rva[e] += x;
+  }
+}
+
+// ILU(0) of every row's block K = A[N,N]^T (N = the row's F-columns, in
+// order): K at fac + r * stride (s x s, row-major), then s 64-bit masks of
+// K's nonzero pattern (bit b of mask a: K[a][b] != 0 before elimination);
+// row-oriented elimination touching only pattern positions, unit lower
+// factor.  A zero pivot reports the row's C-point.
+__global__ __launch_bounds__(kAT) void k_ap_ilu_factor(int n_c, const int32_t* __restrict__ Rrp,
+                                                      const int32_t* __restrict__ Rci,
+                                                      const int32_t* __restrict__ clist,
+                                                      const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                      const double* __restrict__ va, double* fac, int64_t stride,
+                                                      int32_t* bad_row) {
+  for (int r = blockIdx.x * kAT + threadIdx.x; r < n_c; r += gridDim.x * kAT) {
+    const int i = clist[r];
+    const int e0 = Rrp[r], len = Rrp[r + 1] - e0;
+    const int s = len - 1;
+    if (s <= 0) continue;
+    double* K = fac + (int64_t)r * stride;
+    uint64_t* mk = reinterpret_cast<uint64_t*>(K + (int64_t)s * s);
+    for (int t = 0; t < s * s; ++t) K[t] = 0.0;
+    // F-entry p of the row is R entry e0 + p before the C-point, e0 + p + 1 after
+    int pc = 0;
+    while (pc < len && Rci[e0 + pc] != i) ++pc;
+    for (int p2 = 0; p2 < s; ++p2) {
+      const int row = Rci[e0 + p2 + (p2 >= pc ? 1 : 0)];
+      for (int t = rp[row]; t < rp[row + 1]; ++t) {
+        const int col = ci[t];
+        int lo = 0, hi = len;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (Rci[e0 + mid] < col) lo = mid + 1; else hi = mid;
+        }
+        if (lo < len && Rci[e0 + lo] == col && col != i) {
+          const int q = col > i ? lo - 1 : lo;
+          K[(int64_t)q * s + p2] += va[t];
+        }
+      }
+    }
+    for (int a = 0; a < s; ++a) {
+      uint64_t m = 0;
+      for (int b = 0; b < s; ++b)
+        if (K[(int64_t)a * s + b] != 0.0) m |= 1ull << b;
+      mk[a] = m;
+    }
+    bool zero = false;
+    for (int a = 0; a < s && !zero; ++a) {
+      const uint64_t ma = mk[a];
+      for (int b = 0; b < a; ++b) {
+        if (!((ma >> b) & 1ull)) continue;
+        const double mult = K[(int64_t)a * s + b] / K[(int64_t)b * s + b];
+        K[(int64_t)a * s + b] = mult;
+        for (int c = b + 1; c < s; ++c)
+          if ((ma >> c) & 1ull) K[(int64_t)a * s + c] -= mult * K[(int64_t)b * s + c];
+      }
+      zero = K[(int64_t)a * s + a] == 0.0;
+    }
+    if (zero) atomicMin(bad_row, i);
+  }
+}
+
+// u_i = (L U)^{-1} rho_i on the row's F-entries, in place; with B the column
+// sums s_j += u_ij B_i
+__global__ __launch_bounds__(kAT) void k_ap_ilu_solve(int n_c, const int32_t* __restrict__ Rrp,
+                                                     const int32_t* __restrict__ Rci,
+                                                     const int32_t* __restrict__ clist,
+                                                     const double* __restrict__ fac, int64_t stride,
+                                                     const double* __restrict__ B, double* u, double* sj) {
+  for (int r = blockIdx.x * kAT + threadIdx.x; r < n_c; r += gridDim.x * kAT) {
+    const int i = clist[r];
+    const int e0 = Rrp[r], len = Rrp[r + 1] - e0;
+    const int s = len - 1;
+    if (s <= 0) continue;
+    // the C-point's position in the row; F-entry a is u[e0 + a + (a >= pc)]
+    int pc = 0;
+    while (pc < len && Rci[e0 + pc] != i) ++pc;
+    double* x = u + e0;
+    const double* K = fac + (int64_t)r * stride;
+    for (int a = 1; a < s; ++a) {
+      double v = x[a + (a >= pc)];
+      for (int b = 0; b < a; ++b) v -= K[(int64_t)a * s + b] * x[b + (b >= pc)];
+      x[a + (a >= pc)] = v;
+    }
+    for (int a = s - 1; a >= 0; --a) {
+      double v = x[a + (a >= pc)];
+      for (int c = a + 1; c < s; ++c) v -= K[(int64_t)a * s + c] * x[c + (c >= pc)];
+      x[a + (a >= pc)] = v / K[(int64_t)a * s + a];
+    }
+    if (B) {
+      const double bi = B[i];
+      for (int a = 0; a < s; ++a) {
+        const int e = e0 + a + (a >= pc);
+        unsafeAtomicAdd(&sj[Rci[e]], x[a + (a >= pc)] * bi);
+      }
+    }
   }
 }
 
@@ -149,7 +254,10 @@ hipError_t launch_diag_start(const DiagWork& w, hipStream_t s) {
                        w.Rrp, w.erow);
   if (w.nnz > 0) {
     hipLaunchKernelGGL(k_ap_start, dim3(agrid(w.nnz, w.cus)), dim3(kAT), 0, s, w.nnz, w.erow, w.clist, w.Rci, w.Rva,
-                       w.rp, w.ci, w.va, w.B, w.diag, w.d, w.cnt, w.bad_row);
+                       w.rp, w.ci, w.va, w.B, w.diag, w.d, w.cnt, w.ilu ? nullptr : w.bad_row);
+    if (w.ilu)
+      hipLaunchKernelGGL(k_ap_ilu_factor, dim3(agrid(w.n_c, w.cus)), dim3(kAT), 0, s, w.n_c, w.Rrp, w.Rci, w.clist,
+                         w.rp, w.ci, w.va, w.fac, w.fstride, w.bad_row);
     if (w.B)
       hipLaunchKernelGGL(k_ap_fit, dim3(agrid(w.nnz, w.cus)), dim3(kAT), 0, s, w.nnz, w.erow, w.clist, w.Rci, w.Rva,
                          w.B, w.d);
@@ -166,7 +274,10 @@ hipError_t launch_diag_iteration(const DiagWork& w, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_ap_resid, dim3(agrid(w.nnz, w.cus)), dim3(kAT), 0, s, w.nnz, w.erow, w.clist, w.Rrp, w.Rci,
-                     w.Rva, w.trp, w.tci, w.tva, w.diag, w.B, w.u, w.sj);
+                     w.Rva, w.trp, w.tci, w.tva, w.diag, w.B, w.u, w.sj, w.ilu ? 0 : 1);
+  if (w.ilu)
+    hipLaunchKernelGGL(k_ap_ilu_solve, dim3(agrid(w.n_c, w.cus)), dim3(kAT), 0, s, w.n_c, w.Rrp, w.Rci, w.clist, w.fac,
+                       w.fstride, w.B, w.u, w.sj);
   hipLaunchKernelGGL(k_ap_update, dim3(agrid(w.nnz, w.cus)), dim3(kAT), 0, s, w.nnz, w.erow, w.clist, w.Rci, w.Rva,
                      w.u, w.B, w.d, w.sj);
   return hipGetLastError();

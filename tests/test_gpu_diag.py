@@ -145,3 +145,85 @@ def test_degenerate_inputs(idx):
     assert np.array_equal(g["row_ptr"], o["row_ptr"]) and np.array_equal(g["col_idx"], o["col_idx"])
     assert np.allclose(g["val"], o["val"], rtol=0, atol=1e-14)
     assert info["n_uncovered"] == o["n_uncovered"]
+
+
+# ---------------------------------------------------------------- ILU(0) ---
+def _gpu_approx(p, B, iters, inverse, theta=0.0, check=True):
+    from paper_2307_00229_amd import clair
+
+    ctx = clair.Context()
+    if theta:
+        ctx.set_strength(theta)
+    A = clair.CSR.from_problem(p, "cuda")
+    cf = torch.from_numpy(p.cf).cuda()
+    Bt = None if B is None else torch.from_numpy(np.ascontiguousarray(B)).cuda()
+    out, info, st = clair.clair_build_R_approx(A, cf, Bt, p.ell, iters, inverse=inverse, ctx=ctx, check=check)
+    torch.cuda.synchronize()
+    if out is None or st:
+        return None, info, st
+    rp, ci, va = out
+    return dict(row_ptr=rp.cpu().numpy(), col_idx=ci.cpu().numpy(), val=va.cpu().numpy(), n_c=info["n_c"],
+                nnz=info["nnz"]), info, st
+
+
+def _compare_ilu(p, B, iters, theta=0.0):
+    from paper_2307_00229_amd import clair
+
+    g, info, _ = _gpu_approx(p, B, iters, clair.CLAIR_INVERSE_ILU0, theta)
+    o = oracle.build_R_approx(p.n, p.row_ptr, p.col_idx, p.val, p.cf, B, p.ell, iters, "ilu0", theta=theta)
+    assert np.array_equal(g["row_ptr"], o["row_ptr"]) and np.array_equal(g["col_idx"], o["col_idx"])
+    err, _, _ = row_errors(p, g, o)
+    print(f"[gpu] ilu0 {p.name} B={'yes' if B is not None else 'no'} iters={iters} theta={theta}: "
+          f"row error {err.max():.2e}", flush=True)
+    assert err.max() <= 1e-10
+    if B is not None:
+        assert info["n_uncovered"] == o["n_uncovered"]
+        res, _ = constraint_residual(p, g)
+        assert res <= 1e-12, res
+    return g, o
+
+
+@pytest.mark.parametrize("iters", [0, 1, 3])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_ilu0_matches_oracle(case, iters):
+    p = CASES[case]()
+    _compare_ilu(p, p.B, iters)
+    _compare_ilu(p, None, iters)
+
+
+def test_ilu0_strength_and_workload_matrix():
+    _compare_ilu(CASES[0](), CASES[0]().B, 2, theta=0.25)
+    p = P.cfg2()[0]
+    _compare_ilu(p, p.B, 2)
+
+
+def test_ilu0_one_iteration_exact_on_fill_free_blocks():
+    from .test_oracle_approx import _tridiag_1d
+
+    p = _tridiag_1d()
+    from paper_2307_00229_amd import clair
+
+    g, _, _ = _gpu_approx(p, p.B, 1, clair.CLAIR_INVERSE_ILU0)
+    ex, infos, st = gpu_build([p])
+    assert st == 0, infos
+    err, _, _ = row_errors(p, g, ex[0])
+    assert err.max() <= 1e-10, err.max()
+
+
+def test_ilu0_zero_pivot_is_singular():
+    from paper_2307_00229_amd import clair
+
+    p = P.small_2d(10, stencil=5, eps=0.1, angle=0.5, ell=2)
+    va = p.val.copy()
+    F = np.nonzero(p.cf == 0)[0]
+    j = int(F[0])  # the first F-point: its diagonal is the first pivot of every block holding it first
+    for e in range(p.row_ptr[j], p.row_ptr[j + 1]):
+        if p.col_idx[e] == j:
+            va[e] = 0.0
+    q = P.Problem(p.name, p.n, p.row_ptr, p.col_idx, va, p.cf, p.B, p.ell)
+    with pytest.raises(oracle.OracleError) as exc:
+        oracle.build_R_approx(q.n, q.row_ptr, q.col_idx, q.val, q.cf, q.B, q.ell, 1, "ilu0")
+    expect = int(str(exc.value).split("bad_row=")[1])
+    _, info, st = _gpu_approx(q, q.B, 1, clair.CLAIR_INVERSE_ILU0, check=False)
+    assert st == clair.CLAIR_ERR_SINGULAR
+    assert info["first_bad_row"] == expect
