@@ -208,8 +208,8 @@ int clair_build_R_batched(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* A,
  * returns CLAIR_ERR_SINGULAR, first_bad_row = the smallest C-point concerned.
  * Blocks above 64 points return CLAIR_ERR_UNSUPPORTED; an unknown `inverse`
  * CLAIR_ERR_INVALID.  cf_marker may be NULL only when A->n = 0.  ILU(0)
- * keeps n_c x (s^2 + s) doubles of factors (s the largest block) in the
- * context.  Synchronises `stream`.
+ * keeps n_c x s^2 doubles of factors (s the largest block) in the context.
+ * Synchronises `stream`.
  */
 enum { CLAIR_INVERSE_DIAG = 1, CLAIR_INVERSE_ILU0 = 2 };
 int clair_build_R_approx(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_marker, const double* B,

@@ -1101,7 +1101,7 @@ int clair_build_R_approx(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf,
     const size_t nn = std::max<size_t>(1, (size_t)n), nz = std::max<size_t>(1, (size_t)nnz);
     const bool ilu = inverse == CLAIR_INVERSE_ILU0;
     const int smax = std::max(1, in.max_block);
-    const int64_t fstride = (int64_t)smax * smax + smax;  // K, then one mask per row of K
+    const int64_t fstride = (int64_t)smax * smax;  // per row: K
     const size_t o_diag = take(sizeof(double) * nn), o_d = take(sizeof(double) * nn), o_sj = take(sizeof(double) * nn),
                  o_u = take(sizeof(double) * nz), o_cnt = take(sizeof(int32_t) * nn),
                  o_erow = take(sizeof(int32_t) * nz), o_flags = take(64),
@@ -1111,7 +1111,7 @@ int clair_build_R_approx(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf,
     DiagWork w{};
     w.ilu = ilu ? 1 : 0;
     w.fac = reinterpret_cast<double*>(base + o_fac);
-    w.fstride = fstride;
+    w.smax = smax;
     w.n = n;
     w.n_c = n_c;
     w.nnz = nnz;

@@ -84,12 +84,12 @@ hipError_t launch_project_k(int n, int n_rows, const int32_t* rp, const int32_t*
 // the C-point's own entry included).  A^T in trp/tci/tva; clist[q] = the
 // C-point of row q; work arrays: diag, d, sj (n), cnt (n, zeroed), u and erow
 // (nnz), *bad_row (INT32_MAX beforehand), *uncovered (zeroed).  ilu: ILU(0)
-// of every block instead of its diagonal, factors at fac + q * fstride
-// (fstride >= s^2 + s doubles for the largest block s <= 64).
+// of every block instead of its diagonal; fac holds smax^2 * n_c doubles
+// (smax >= the largest block, <= 64), interleaved over rows.
 struct DiagWork {
   int ilu;
   double* fac;
-  int64_t fstride;
+  int smax;
   int n, n_c;
   int64_t nnz;
   int cus;

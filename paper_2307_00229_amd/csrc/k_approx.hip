@@ -143,24 +143,26 @@ __global__ __launch_bounds__(kAT) void k_ap_update(int64_t nnz, const int32_t* _
 }
 
 // ILU(0) of every row's block K = A[N,N]^T (N = the row's F-columns, in
-// order): K at fac + r * stride (s x s, row-major), then s 64-bit masks of
-// K's nonzero pattern (bit b of mask a: K[a][b] != 0 before elimination);
-// row-oriented elimination touching only pattern positions, unit lower
-// factor.  A zero pivot reports the row's C-point.
+// order), interleaved over rows so that the lanes of a wavefront touch
+// consecutive addresses: K[a][b] of row r at fac[(a * smax + b) * n_c + r].
+// Row-oriented elimination touching only pattern positions, unit lower
+// factor: row a is eliminated against the final rows above it, and its
+// pattern (a bit mask, s <= 64) is read just before, while it still holds K's
+// values.  A zero pivot reports the row's C-point.
 __global__ __launch_bounds__(kAT) void k_ap_ilu_factor(int n_c, const int32_t* __restrict__ Rrp,
                                                       const int32_t* __restrict__ Rci,
                                                       const int32_t* __restrict__ clist,
                                                       const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                                      const double* __restrict__ va, double* fac, int64_t stride,
+                                                      const double* __restrict__ va, double* fac, int smax,
                                                       int32_t* bad_row) {
   for (int r = blockIdx.x * kAT + threadIdx.x; r < n_c; r += gridDim.x * kAT) {
     const int i = clist[r];
     const int e0 = Rrp[r], len = Rrp[r + 1] - e0;
     const int s = len - 1;
     if (s <= 0) continue;
-    double* K = fac + (int64_t)r * stride;
-    uint64_t* mk = reinterpret_cast<uint64_t*>(K + (int64_t)s * s);
-    for (int t = 0; t < s * s; ++t) K[t] = 0.0;
+    auto K = [&](int a, int b) -> double& { return fac[((int64_t)a * smax + b) * n_c + r]; };
+    for (int a = 0; a < s; ++a)
+      for (int b = 0; b < s; ++b) K(a, b) = 0.0;
     // F-entry p of the row is R entry e0 + p before the C-point, e0 + p + 1 after
     int pc = 0;
     while (pc < len && Rci[e0 + pc] != i) ++pc;
@@ -175,27 +177,23 @@ __global__ __launch_bounds__(kAT) void k_ap_ilu_factor(int n_c, const int32_t* _
         }
         if (lo < len && Rci[e0 + lo] == col && col != i) {
           const int q = col > i ? lo - 1 : lo;
-          K[(int64_t)q * s + p2] += va[t];
+          K(q, p2) += va[t];
         }
       }
     }
-    for (int a = 0; a < s; ++a) {
-      uint64_t m = 0;
-      for (int b = 0; b < s; ++b)
-        if (K[(int64_t)a * s + b] != 0.0) m |= 1ull << b;
-      mk[a] = m;
-    }
     bool zero = false;
     for (int a = 0; a < s && !zero; ++a) {
-      const uint64_t ma = mk[a];
+      uint64_t ma = 0;
+      for (int b = 0; b < s; ++b)
+        if (K(a, b) != 0.0) ma |= 1ull << b;
       for (int b = 0; b < a; ++b) {
         if (!((ma >> b) & 1ull)) continue;
-        const double mult = K[(int64_t)a * s + b] / K[(int64_t)b * s + b];
-        K[(int64_t)a * s + b] = mult;
+        const double mult = K(a, b) / K(b, b);
+        K(a, b) = mult;
         for (int c = b + 1; c < s; ++c)
-          if ((ma >> c) & 1ull) K[(int64_t)a * s + c] -= mult * K[(int64_t)b * s + c];
+          if ((ma >> c) & 1ull) K(a, c) -= mult * K(b, c);
       }
-      zero = K[(int64_t)a * s + a] == 0.0;
+      zero = K(a, a) == 0.0;
     }
     if (zero) atomicMin(bad_row, i);
   }
@@ -206,7 +204,7 @@ __global__ __launch_bounds__(kAT) void k_ap_ilu_factor(int n_c, const int32_t* _
 __global__ __launch_bounds__(kAT) void k_ap_ilu_solve(int n_c, const int32_t* __restrict__ Rrp,
                                                      const int32_t* __restrict__ Rci,
                                                      const int32_t* __restrict__ clist,
-                                                     const double* __restrict__ fac, int64_t stride,
+                                                     const double* __restrict__ fac, int smax,
                                                      const double* __restrict__ B, double* u, double* sj) {
   for (int r = blockIdx.x * kAT + threadIdx.x; r < n_c; r += gridDim.x * kAT) {
     const int i = clist[r];
@@ -217,16 +215,16 @@ __global__ __launch_bounds__(kAT) void k_ap_ilu_solve(int n_c, const int32_t* __
     int pc = 0;
     while (pc < len && Rci[e0 + pc] != i) ++pc;
     double* x = u + e0;
-    const double* K = fac + (int64_t)r * stride;
+    auto K = [&](int a, int b) { return fac[((int64_t)a * smax + b) * n_c + r]; };
     for (int a = 1; a < s; ++a) {
       double v = x[a + (a >= pc)];
-      for (int b = 0; b < a; ++b) v -= K[(int64_t)a * s + b] * x[b + (b >= pc)];
+      for (int b = 0; b < a; ++b) v -= K(a, b) * x[b + (b >= pc)];
       x[a + (a >= pc)] = v;
     }
     for (int a = s - 1; a >= 0; --a) {
       double v = x[a + (a >= pc)];
-      for (int c = a + 1; c < s; ++c) v -= K[(int64_t)a * s + c] * x[c + (c >= pc)];
-      x[a + (a >= pc)] = v / K[(int64_t)a * s + a];
+      for (int c = a + 1; c < s; ++c) v -= K(a, c) * x[c + (c >= pc)];
+      x[a + (a >= pc)] = v / K(a, a);
     }
     if (B) {
       const double bi = B[i];
@@ -257,7 +255,7 @@ hipError_t launch_diag_start(const DiagWork& w, hipStream_t s) {
                        w.rp, w.ci, w.va, w.B, w.diag, w.d, w.cnt, w.ilu ? nullptr : w.bad_row);
     if (w.ilu)
       hipLaunchKernelGGL(k_ap_ilu_factor, dim3(agrid(w.n_c, w.cus)), dim3(kAT), 0, s, w.n_c, w.Rrp, w.Rci, w.clist,
-                         w.rp, w.ci, w.va, w.fac, w.fstride, w.bad_row);
+                         w.rp, w.ci, w.va, w.fac, w.smax, w.bad_row);
     if (w.B)
       hipLaunchKernelGGL(k_ap_fit, dim3(agrid(w.nnz, w.cus)), dim3(kAT), 0, s, w.nnz, w.erow, w.clist, w.Rci, w.Rva,
                          w.B, w.d);
@@ -277,7 +275,7 @@ hipError_t launch_diag_iteration(const DiagWork& w, hipStream_t s) {
                      w.Rva, w.trp, w.tci, w.tva, w.diag, w.B, w.u, w.sj, w.ilu ? 0 : 1);
   if (w.ilu)
     hipLaunchKernelGGL(k_ap_ilu_solve, dim3(agrid(w.n_c, w.cus)), dim3(kAT), 0, s, w.n_c, w.Rrp, w.Rci, w.clist, w.fac,
-                       w.fstride, w.B, w.u, w.sj);
+                       w.smax, w.B, w.u, w.sj);
   hipLaunchKernelGGL(k_ap_update, dim3(agrid(w.nnz, w.cus)), dim3(kAT), 0, s, w.nnz, w.erow, w.clist, w.Rci, w.Rva,
                      w.u, w.B, w.d, w.sj);
   return hipGetLastError();
