@@ -17,8 +17,8 @@ Modules
                     constraint fit, residual update, explicit projection), for
                     any number k of iterations.
 ``smoothing``    -- CFF-weighted-Jacobi smoothing of the constraint vector.
-``build_R_approx`` -- Algorithm 1 with approximate block inverses (diagonal
-                    or ILU(0)) and any number of iterations (C oracle, on the
+``build_R_approx`` -- Algorithm 1 with approximate block inverses (diagonal,
+                    ILU(0) or GMRES) and any number of iterations (C oracle, on the
                     exact build's pattern); ``build_R_diag`` the diagonal one.
 """
 from __future__ import annotations
@@ -65,7 +65,7 @@ def _load():
         lib.orc_build_R.restype = ctypes.c_int
         lib.orc_project_k.argtypes = [i32, i32, p, p, p, p, p, i32, f64, p]
         lib.orc_project_k.restype = ctypes.c_int
-        lib.orc_iterate_approx.argtypes = [i32, p, p, p, p, p, i32, p, p, p, i32, i32, p]
+        lib.orc_iterate_approx.argtypes = [i32, p, p, p, p, p, i32, p, p, p, i32, i32, i32, p]
         lib.orc_iterate_approx.restype = ctypes.c_int
         lib.orc_max_threads.argtypes = []
         lib.orc_max_threads.restype = ctypes.c_int
@@ -147,9 +147,10 @@ def build_R_diag(n, row_ptr, col_idx, val, cf, B, ell, iterations, theta=0.0, ag
     return build_R_approx(n, row_ptr, col_idx, val, cf, B, ell, iterations, "diag", theta=theta, agg=agg)
 
 
-def build_R_approx(n, row_ptr, col_idx, val, cf, B, ell, iterations, inverse, theta=0.0, agg=None):
+def build_R_approx(n, row_ptr, col_idx, val, cf, B, ell, iterations, inverse, theta=0.0, agg=None, krylov=0):
     """Algorithm 1 with approximate block inverses ("diag": the diagonal of
-    each block; "ilu0": its incomplete LU factorisation without fill) and
+    each block; "ilu0": its incomplete LU factorisation without fill;
+    "gmres": `krylov` steps of GMRES on each local system from zero) and
     `iterations` steps, on the pattern of the exact build (the pattern does
     not depend on the inverse).  Returns the same dict as build_R."""
     lib = _load()
@@ -161,10 +162,10 @@ def build_R_approx(n, row_ptr, col_idx, val, cf, B, ell, iterations, inverse, th
     Ba = None if B is None else np.ascontiguousarray(B, np.float64)
     Rva = np.zeros(max(o["nnz"], 1), np.float64)
     bad = ctypes.c_int32(-1)
-    kind = {"diag": 1, "ilu0": 2}[inverse]
+    kind = {"diag": 1, "ilu0": 2, "gmres": 3}[inverse]
     rc = lib.orc_iterate_approx(n, _ptr(rp), _ptr(ci), _ptr(va), _ptr(cfa), _ptr(Ba), o["n_c"], _ptr(o["row_ptr"]),
-                                _ptr(np.ascontiguousarray(o["col_idx"], np.int32)), _ptr(Rva), kind, int(iterations),
-                                ctypes.byref(bad))
+                                _ptr(np.ascontiguousarray(o["col_idx"], np.int32)), _ptr(Rva), kind, int(krylov),
+                                int(iterations), ctypes.byref(bad))
     if rc:
         raise OracleError(rc, f"oracle iterate_approx failed ({rc}), bad_row={bad.value}")
     out = dict(o)

@@ -591,7 +591,11 @@ int orc_project_k(int32_t n, int32_t n_c, const int32_t* R_rp, const int32_t* R_
 /*     u_i = Khat_i^{-1} rho_i with K_i = A[N,N]^T: inverse = 1 takes the     */
 /*       diagonal (u_ij = rho_ij / a_jj), inverse = 2 the incomplete LU       */
 /*       factorisation of K_i without fill (ILU(0): the factors keep K_i's    */
-/*       nonzero pattern; row-oriented elimination, unit lower factor);       */
+/*       nonzero pattern; row-oriented elimination, unit lower factor),       */
+/*       inverse = 3 `krylov` steps of GMRES on K_i u = rho_i from u = 0      */
+/*       (the minimal residual over the Krylov space; Arnoldi with modified   */
+/*       Gram-Schmidt, Givens rotations; it stops early when the new basis    */
+/*       vector's norm is at most 1e-12 of the vector it came from);          */
 /*     with B: u_ij -= B_i (sum_i u_ij B_i) / d_j (the projection; Q Q^T is  */
 /*       diagonal);                                                            */
 /*     z += u.                                                                 */
@@ -628,10 +632,76 @@ static void ilu0_solve(const double* K, int32_t s, double* x) {
   }
 }
 
+/* x = the GMRES(m) approximation of K^{-1} b from x = 0 (K s x s row-major);
+   work: (m + 1) * s + (m + 1) * m + 3 * (m + 1) doubles */
+static void gmres_apply(const double* K, int32_t s, int32_t m, const double* b, double* x, double* work) {
+  double* V = work;                      /* (m + 1) x s, rows are basis vectors */
+  double* H = V + (int64_t)(m + 1) * s;  /* (m + 1) x m, column j = step j */
+  double* cs = H + (int64_t)(m + 1) * m;
+  double* sn = cs + (m + 1);
+  double* g = sn + (m + 1);
+  for (int32_t a = 0; a < s; ++a) x[a] = 0.0;
+  double beta = 0.0;
+  for (int32_t a = 0; a < s; ++a) beta += b[a] * b[a];
+  beta = sqrt(beta);
+  if (beta == 0.0 || m == 0) return;
+  for (int32_t a = 0; a < s; ++a) V[a] = b[a] / beta;
+  for (int32_t t = 0; t <= m; ++t) g[t] = 0.0;
+  g[0] = beta;
+  int32_t k = 0;
+  for (int32_t j = 0; j < m; ++j) {
+    double* w = V + (int64_t)(j + 1) * s;
+    for (int32_t a = 0; a < s; ++a) {
+      double acc = 0.0;
+      for (int32_t c = 0; c < s; ++c) acc += K[(int64_t)a * s + c] * V[(int64_t)j * s + c];
+      w[a] = acc;
+    }
+    double w0 = 0.0;
+    for (int32_t a = 0; a < s; ++a) w0 += w[a] * w[a];
+    w0 = sqrt(w0);
+    for (int32_t i = 0; i <= j; ++i) {
+      double h = 0.0;
+      for (int32_t a = 0; a < s; ++a) h += w[a] * V[(int64_t)i * s + a];
+      H[(int64_t)i * m + j] = h;
+      for (int32_t a = 0; a < s; ++a) w[a] -= h * V[(int64_t)i * s + a];
+    }
+    double hn = 0.0;
+    for (int32_t a = 0; a < s; ++a) hn += w[a] * w[a];
+    hn = sqrt(hn);
+    /* earlier rotations on column j, then the one that zeroes H[j+1][j] */
+    for (int32_t i = 0; i < j; ++i) {
+      const double h0 = H[(int64_t)i * m + j], h1 = H[(int64_t)(i + 1) * m + j];
+      H[(int64_t)i * m + j] = cs[i] * h0 + sn[i] * h1;
+      H[(int64_t)(i + 1) * m + j] = -sn[i] * h0 + cs[i] * h1;
+    }
+    const double hjj = H[(int64_t)j * m + j];
+    const double rr = sqrt(hjj * hjj + hn * hn);
+    cs[j] = rr > 0.0 ? hjj / rr : 1.0;
+    sn[j] = rr > 0.0 ? hn / rr : 0.0;
+    H[(int64_t)j * m + j] = rr;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    k = j + 1;
+    if (!(hn > 1e-12 * w0)) break; /* the Krylov space is invariant: exact */
+    for (int32_t a = 0; a < s; ++a) w[a] /= hn;
+  }
+  /* H[0..k)[0..k) y = g[0..k), then x = V y */
+  double* y = g; /* solved in place */
+  for (int32_t i = k - 1; i >= 0; --i) {
+    double v = y[i];
+    for (int32_t c = i + 1; c < k; ++c) v -= H[(int64_t)i * m + c] * y[c];
+    y[i] = H[(int64_t)i * m + i] != 0.0 ? v / H[(int64_t)i * m + i] : 0.0;
+  }
+  for (int32_t i = 0; i < k; ++i)
+    for (int32_t a = 0; a < s; ++a) x[a] += y[i] * V[(int64_t)i * s + a];
+}
+
 int orc_iterate_approx(int32_t n, const int32_t* rp, const int32_t* ci, const double* va, const int8_t* cf,
                        const double* B, int32_t n_c, const int32_t* R_rp, const int32_t* R_ci, double* R_va,
-                       int32_t inverse, int32_t iterations, int32_t* bad_row) {
-  if (iterations < 0 || (inverse != 1 && inverse != 2) || check_csr(n, rp, ci)) return ORC_ERR_INVALID;
+                       int32_t inverse, int32_t krylov, int32_t iterations, int32_t* bad_row) {
+  if (iterations < 0 || inverse < 1 || inverse > 3 || (inverse == 3 && (krylov < 1 || krylov > 64)) ||
+      check_csr(n, rp, ci))
+    return ORC_ERR_INVALID;
   const size_t nn = (size_t)(n > 0 ? n : 1);
   const int64_t nnz = R_rp[n_c];
   int32_t* clist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_c > 0 ? n_c : 1));
@@ -664,7 +734,7 @@ int orc_iterate_approx(int32_t n, const int32_t* rp, const int32_t* ci, const do
   /* ILU(0) factors of every block K_i = A[N,N]^T (N = the row's F-columns) */
   double* fac = NULL;
   int64_t* foff = NULL;
-  if (inverse == 2 && first_bad < 0) {
+  if (inverse >= 2 && first_bad < 0) {
     foff = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_c + 1));
     if (!foff) { free(clist); free(diag); free(d); free(sj); free(u); return ORC_ERR_NOMEM; }
     foff[0] = 0;
@@ -695,7 +765,7 @@ int orc_iterate_approx(int32_t n, const int32_t* rp, const int32_t* ci, const do
           if (q >= 0) K[(int64_t)q * sr + p2] += va[e];
         }
       }
-      if (sr > 0 && ilu0(K, sr, mask)) first_bad = i;
+      if (inverse == 2 && sr > 0 && ilu0(K, sr, mask)) first_bad = i;
     }
     free(N);
     free(mask);
@@ -708,8 +778,14 @@ int orc_iterate_approx(int32_t n, const int32_t* rp, const int32_t* ci, const do
   int32_t maxlen = 1;
   for (int32_t r = 0; r < n_c; ++r)
     if (R_rp[r + 1] - R_rp[r] > maxlen) maxlen = R_rp[r + 1] - R_rp[r];
-  double* xs = (double*)malloc(sizeof(double) * (size_t)maxlen);
-  if (!xs) { free(fac); free(foff); free(clist); free(diag); free(d); free(sj); free(u); return ORC_ERR_NOMEM; }
+  double* xs = (double*)malloc(sizeof(double) * (size_t)maxlen * 2);
+  const int32_t km = inverse == 3 ? krylov : 0;
+  const size_t gsize = (size_t)(km + 1) * (size_t)maxlen + (size_t)(km + 1) * km + 3 * (size_t)(km + 1);
+  double* gw = (double*)malloc(sizeof(double) * gsize);
+  if (!xs || !gw) {
+    free(xs); free(gw); free(fac); free(foff); free(clist); free(diag); free(d); free(sj); free(u);
+    return ORC_ERR_NOMEM;
+  }
   /* tentative weights, then the constraint fit */
   for (int32_t r = 0; r < n_c; ++r) {
     const int32_t i = clist[r];
@@ -756,7 +832,12 @@ int orc_iterate_approx(int32_t n, const int32_t* rp, const int32_t* ci, const do
         int32_t sr = 0;
         for (int32_t e = e0; e < e0 + len; ++e)
           if (R_ci[e] != i) xs[sr++] = -u[e];
-        ilu0_solve(fac + foff[r], sr, xs);
+        if (inverse == 2) {
+          ilu0_solve(fac + foff[r], sr, xs);
+        } else {
+          memcpy(xs + maxlen, xs, sizeof(double) * (size_t)sr);
+          gmres_apply(fac + foff[r], sr, km, xs + maxlen, xs, gw);
+        }
         sr = 0;
         for (int32_t e = e0; e < e0 + len; ++e) u[e] = (R_ci[e] == i) ? 0.0 : xs[sr++];
       }
@@ -775,7 +856,7 @@ int orc_iterate_approx(int32_t n, const int32_t* rp, const int32_t* ci, const do
     }
     for (int64_t e = 0; e < nnz; ++e) R_va[e] += u[e];
   }
-  free(xs); free(fac); free(foff); free(clist); free(diag); free(d); free(sj); free(u);
+  free(xs); free(gw); free(fac); free(foff); free(clist); free(diag); free(d); free(sj); free(u);
   return ORC_OK;
 }
 

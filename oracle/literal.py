@@ -47,13 +47,36 @@ def _ilu0(K: np.ndarray):
     return L, U
 
 
+def _gmres(K: np.ndarray, r: np.ndarray, m: int) -> np.ndarray:
+    """The vector of the Krylov space span{r, K r, ..., K^{m-1} r} that
+    minimises ||r - K x|| (what m steps of GMRES from x = 0 return), by an
+    orthonormal basis of the space (QR of the Krylov matrix, cut where the
+    space stops growing) and a least-squares fit."""
+    if not np.any(r):
+        return np.zeros_like(r)
+    cols = [r / np.linalg.norm(r)]
+    for _ in range(m - 1):
+        v = K @ cols[-1]
+        cols.append(v / np.linalg.norm(v) if np.any(v) else v)
+    Q, Rq = np.linalg.qr(np.array(cols).T)
+    d = np.abs(np.diag(Rq))
+    k = 1
+    while k < len(d) and d[k] > 1e-10 * d[0]:
+        k += 1
+    V = Q[:, :k]
+    y = np.linalg.lstsq(K @ V, r, rcond=None)[0]
+    return V @ y
+
+
 def algorithm1_R(A: np.ndarray, cf: np.ndarray, B, ell: int, k: int = 1,
-                 fit_constraint: bool = True, theta: float = 0.0, agg=None, inverse: str = "exact"):
+                 fit_constraint: bool = True, theta: float = 0.0, agg=None, inverse: str = "exact",
+                 krylov: int = 1):
     """Dense R (n_c x n) from the literal Algorithm 1 on A^T (strength threshold theta).
 
     inverse: "exact" (the block inverses of step 3), "diag" (the local
-    diagonal inverse of each block) or "ilu0" (the inverse of each block's
-    incomplete LU factors without fill).  B = None drops the constraint lines
+    diagonal inverse of each block), "ilu0" (the inverse of each block's
+    incomplete LU factors without fill) or "gmres" (`krylov` steps of GMRES
+    on each local system from zero).  B = None drops the constraint lines
     (the fit of step 2 and the projection of step 4)."""
     n = A.shape[0]
     At = A.T
@@ -109,6 +132,8 @@ def algorithm1_R(A: np.ndarray, cf: np.ndarray, B, ell: int, k: int = 1,
         elif inverse == "ilu0":
             L, U = _ilu0(blocks[c])
             inv[c] = np.linalg.inv(U) @ np.linalg.inv(L)
+        elif inverse == "gmres":
+            inv[c] = None  # applied to each residual below (not a linear map)
         else:
             raise ValueError(inverse)
 
@@ -126,7 +151,10 @@ def algorithm1_R(A: np.ndarray, cf: np.ndarray, B, ell: int, k: int = 1,
             w_c = wt[s0:s0 + len(N)]
             a_fc = At[N, c]
             res = -a_fc - blocks[c] @ w_c
-            wbar[s0:s0 + len(N)] = inv[c] @ res
+            if inverse == "gmres":
+                wbar[s0:s0 + len(N)] = _gmres(blocks[c], res, krylov)
+            else:
+                wbar[s0:s0 + len(N)] = inv[c] @ res
         wbar = P @ wbar
         wt = wt + wbar
 

@@ -229,3 +229,70 @@ def test_ilu0_iterates_meet_the_constraint(case):
     cov = np.zeros(p.n, bool)
     cov[got["col_idx"][fm]] = True
     assert (np.abs(S[cov] - p.B[cov]) / (np.abs(p.B[cov]) + T[cov])).max() <= 1e-13
+
+
+# ----------------------------------------------------------------- GMRES ---
+@pytest.mark.parametrize("krylov", [1, 2, 3])
+@pytest.mark.parametrize("constrained", [True, False])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_gmres_equals_literal_algorithm1(case, constrained, krylov):
+    # Arnoldi with Givens rotations (C oracle) against a least-squares fit over
+    # an orthonormal basis of the Krylov space (literal)
+    p = CASES[case]()
+    B = p.B if constrained else None
+    for iters in (1, 2):
+        got = oracle.build_R_approx(p.n, p.row_ptr, p.col_idx, p.val, p.cf, B, p.ell, iters, "gmres", krylov=krylov)
+        A = dense.to_dense(p.n, p.row_ptr, p.col_idx, p.val)
+        Rl = literal.algorithm1_R(A, p.cf, B, p.ell, k=iters, inverse="gmres", krylov=krylov)
+        R = _dense_R(got, p.n)
+        assert np.max(np.abs(Rl - R)) <= 1e-10 * max(1.0, np.max(np.abs(R)))
+
+
+def test_gmres_one_step_is_the_minimal_residual_multiple():
+    # one GMRES step: u = alpha rho with alpha = (rho . K rho) / |K rho|^2
+    p = CASES[1]()
+    A = dense.to_dense(p.n, p.row_ptr, p.col_idx, p.val)
+    got = oracle.build_R_approx(p.n, p.row_ptr, p.col_idx, p.val, p.cf, None, p.ell, 1, "gmres", krylov=1)
+    R = _dense_R(got, p.n)
+    nb = dense.neighbourhoods(A, p.cf, p.ell)
+    for r, c in enumerate(np.nonzero(p.cf)[0]):
+        N = nb[c]
+        if len(N) == 0:
+            continue
+        K = A[np.ix_(N, N)].T
+        z0 = -A[c, N]
+        rho = -A[c, N] - K @ z0
+        Kr = K @ rho
+        alpha = (rho @ Kr) / (Kr @ Kr) if np.any(Kr) else 0.0
+        assert np.allclose(R[r, N], z0 + alpha * rho, rtol=0, atol=1e-12 * max(1.0, np.abs(R[r]).max()))
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_gmres_with_a_full_krylov_space_is_exact(case):
+    # with as many steps as the block has points GMRES solves the block exactly,
+    # so one iteration gives the closed form (Remark 2)
+    p = CASES[case]()
+    exact = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell)
+    got = oracle.build_R_approx(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, 1, "gmres", krylov=64)
+    assert np.array_equal(got["col_idx"], exact["col_idx"])
+    assert np.max(np.abs(got["val"] - exact["val"])) <= 1e-10 * np.abs(exact["val"]).max()
+
+
+@pytest.mark.parametrize("case", [1, 2, 3])
+def test_gmres_unconstrained_limit_and_feasibility(case):
+    p = CASES[case]()
+    exact = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, None, p.ell)
+    got = oracle.build_R_approx(p.n, p.row_ptr, p.col_idx, p.val, p.cf, None, p.ell, 40, "gmres", krylov=2)
+    assert np.max(np.abs(got["val"] - exact["val"])) <= 1e-10 * np.abs(exact["val"]).max()
+    g = oracle.build_R_approx(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, 2, "gmres", krylov=3)
+    C = np.nonzero(p.cf)[0]
+    rows = np.repeat(np.arange(g["n_c"]), np.diff(g["row_ptr"]))
+    fm = g["col_idx"] != C[rows]
+    terms = g["val"][fm] * p.B[C[rows[fm]]]
+    S = np.zeros(p.n)
+    T = np.zeros(p.n)
+    np.add.at(S, g["col_idx"][fm], terms)
+    np.add.at(T, g["col_idx"][fm], np.abs(terms))
+    cov = np.zeros(p.n, bool)
+    cov[g["col_idx"][fm]] = True
+    assert (np.abs(S[cov] - p.B[cov]) / (np.abs(p.B[cov]) + T[cov])).max() <= 1e-13
