@@ -189,7 +189,11 @@ int clair_build_R_batched(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* A,
  *   inverse = CLAIR_INVERSE_DIAG: K_i replaced by its diagonal (a_jj);
  *   inverse = CLAIR_INVERSE_ILU0: by its incomplete LU factors without fill
  *             (ILU(0): unit lower L and upper U on K_i's nonzero pattern,
- *             L U = K_i there; row-oriented elimination).
+ *             L U = K_i there; row-oriented elimination);
+ *   inverse = CLAIR_INVERSE_GMRES: u_i = `krylov` (1..32) steps of GMRES on
+ *             K_i u = rho_i from u = 0 (the least residual over the Krylov
+ *             space; it stops early once the space is invariant, a new basis
+ *             vector at most 1e-12 of K v_j).  krylov is ignored otherwise.
  *   start: z_ij = -a_ij (the tentative operator); with B, every F-column is
  *          replaced by the minimum-norm solution of its constraint,
  *          z_ij = B_i B_j / d_j with d_j = sum over the column's rows of B_i^2;
@@ -199,7 +203,7 @@ int clair_build_R_batched(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* A,
  * Every iterate meets the constraint where B is given.  One iteration gives
  * clair_build_R's result when the approximate inverse is exact for every
  * block (Remark 2): diagonal blocks for the diagonal, blocks whose
- * factorisation has no fill for ILU(0).  FP64 throughout; per-column sums by
+ * factorisation has no fill for ILU(0), krylov >= the block size for GMRES.  FP64 throughout; per-column sums by
  * FP64 atomics (rounding order not fixed).
  *   R_out     as for clair_build_R (n_rows, n_cols, nnz set; too small
  *             capacities return CLAIR_ERR_CAPACITY, a size query)
@@ -207,14 +211,16 @@ int clair_build_R_batched(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* A,
  * A zero diagonal on a pattern F-column (diagonal) or a zero pivot (ILU(0))
  * returns CLAIR_ERR_SINGULAR, first_bad_row = the smallest C-point concerned.
  * Blocks above 64 points return CLAIR_ERR_UNSUPPORTED; an unknown `inverse`
- * CLAIR_ERR_INVALID.  cf_marker may be NULL only when A->n = 0.  ILU(0)
- * keeps n_c x s^2 doubles of factors (s the largest block) in the context.
+ * or krylov outside 1..32 for GMRES CLAIR_ERR_INVALID.  cf_marker may be NULL
+ * only when A->n = 0.  ILU(0) and GMRES keep n_c x s^2 doubles of blocks (s
+ * the largest block) in the context, GMRES n_c x (krylov + 1)(s + krylov + 3)
+ * more.
  * Synchronises `stream`.
  */
-enum { CLAIR_INVERSE_DIAG = 1, CLAIR_INVERSE_ILU0 = 2 };
+enum { CLAIR_INVERSE_DIAG = 1, CLAIR_INVERSE_ILU0 = 2, CLAIR_INVERSE_GMRES = 3 };
 int clair_build_R_approx(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_marker, const double* B,
-                         int32_t ell, int32_t inverse, int32_t iterations, clair_csr_out_t* R_out, clair_info_t* info,
-                         void* stream);
+                         int32_t ell, int32_t inverse, int32_t krylov, int32_t iterations, clair_csr_out_t* R_out,
+                         clair_info_t* info, void* stream);
 
 /* clair_build_R_diag -- clair_build_R_approx with CLAIR_INVERSE_DIAG. */
 int clair_build_R_diag(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_marker, const double* B,

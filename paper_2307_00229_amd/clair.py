@@ -130,7 +130,7 @@ def load_library(path: str = LIB_PATH):
                                        ctypes.POINTER(I64), P], ctypes.c_int),
         "clair_build_R_diag": ([P, ctypes.POINTER(CsrIn), P, P, I32, I32, ctypes.POINTER(CsrOut),
                                 ctypes.POINTER(Info), P], ctypes.c_int),
-        "clair_build_R_approx": ([P, ctypes.POINTER(CsrIn), P, P, I32, I32, I32, ctypes.POINTER(CsrOut),
+        "clair_build_R_approx": ([P, ctypes.POINTER(CsrIn), P, P, I32, I32, I32, I32, ctypes.POINTER(CsrOut),
                                   ctypes.POINTER(Info), P], ctypes.c_int),
         "clair_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "clair_last_error": ([], ctypes.c_char_p),
@@ -517,7 +517,7 @@ def clair_build_R_agg(As: Sequence[CSR], cfs, aggs, Bs, ells, *, ctx: Optional[C
     return outs, [i.as_dict() for i in infos], st
 
 
-CLAIR_INVERSE_DIAG, CLAIR_INVERSE_ILU0 = 1, 2
+CLAIR_INVERSE_DIAG, CLAIR_INVERSE_ILU0, CLAIR_INVERSE_GMRES = 1, 2, 3
 
 
 def clair_build_R_diag(A: CSR, cf: torch.Tensor, B: Optional[torch.Tensor], ell: int, iterations: int, **kw):
@@ -526,10 +526,11 @@ def clair_build_R_diag(A: CSR, cf: torch.Tensor, B: Optional[torch.Tensor], ell:
 
 
 def clair_build_R_approx(A: CSR, cf: torch.Tensor, B: Optional[torch.Tensor], ell: int, iterations: int, *,
-                         inverse: int = CLAIR_INVERSE_DIAG, ctx: Optional[Context] = None, stream=None,
-                         check: bool = True):
-    """Algorithm 1 with approximate block inverses (CLAIR_INVERSE_DIAG or
-    CLAIR_INVERSE_ILU0): ((row_ptr, col_idx, val), info, status)."""
+                         inverse: int = CLAIR_INVERSE_DIAG, krylov: int = 0, ctx: Optional[Context] = None,
+                         stream=None, check: bool = True):
+    """Algorithm 1 with approximate block inverses (CLAIR_INVERSE_DIAG,
+    CLAIR_INVERSE_ILU0, or CLAIR_INVERSE_GMRES with `krylov` steps):
+    ((row_ptr, col_idx, val), info, status)."""
     lib = load_library()
     ctx = ctx or Context()
     _check_dev(cf, torch.int8, "cf")
@@ -541,7 +542,7 @@ def clair_build_R_approx(A: CSR, cf: torch.Tensor, B: Optional[torch.Tensor], el
 
     def call(o):
         return lib.clair_build_R_approx(ctx.handle, ctypes.byref(Ac), cf.data_ptr(), _ptr(B), int(ell), int(inverse),
-                                        int(iterations), ctypes.byref(o), ctypes.byref(info), sp_)
+                                        int(krylov), int(iterations), ctypes.byref(o), ctypes.byref(info), sp_)
 
     probe = CsrOut()
     st = call(probe)

@@ -1066,13 +1066,16 @@ int clair_project_constraints(clair_ctx_t* c, clair_csr_out_t* R, int32_t n, con
 
 int clair_build_R_diag(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf, const double* B, int32_t ell,
                        int32_t iterations, clair_csr_out_t* R, clair_info_t* info, void* stream) {
-  return clair_build_R_approx(c, A, cf, B, ell, CLAIR_INVERSE_DIAG, iterations, R, info, stream);
+  return clair_build_R_approx(c, A, cf, B, ell, CLAIR_INVERSE_DIAG, 0, iterations, R, info, stream);
 }
 
 int clair_build_R_approx(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf, const double* B, int32_t ell,
-                         int32_t inverse, int32_t iterations, clair_csr_out_t* R, clair_info_t* info, void* stream) {
+                         int32_t inverse, int32_t krylov, int32_t iterations, clair_csr_out_t* R, clair_info_t* info,
+                         void* stream) {
   if (!c || !R || ell < 1 || ell > 64 || iterations < 0 || check_csr_args(A)) return CLAIR_ERR_INVALID;
-  if (inverse != CLAIR_INVERSE_DIAG && inverse != CLAIR_INVERSE_ILU0) return CLAIR_ERR_INVALID;
+  if (inverse != CLAIR_INVERSE_DIAG && inverse != CLAIR_INVERSE_ILU0 && inverse != CLAIR_INVERSE_GMRES)
+    return CLAIR_ERR_INVALID;
+  if (inverse == CLAIR_INVERSE_GMRES && (krylov < 1 || krylov > 32)) return CLAIR_ERR_INVALID;
   if (!cf && A->n > 0) return CLAIR_ERR_INVALID;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   const int32_t n = A->n;
@@ -1099,17 +1102,24 @@ int clair_build_R_approx(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf,
       return o;
     };
     const size_t nn = std::max<size_t>(1, (size_t)n), nz = std::max<size_t>(1, (size_t)nnz);
-    const bool ilu = inverse == CLAIR_INVERSE_ILU0;
+    const bool ilu = inverse == CLAIR_INVERSE_ILU0, gmres = inverse == CLAIR_INVERSE_GMRES;
+    const int km = gmres ? krylov : 0;
     const int smax = std::max(1, in.max_block);
     const int64_t fstride = (int64_t)smax * smax;  // per row: K
     const size_t o_diag = take(sizeof(double) * nn), o_d = take(sizeof(double) * nn), o_sj = take(sizeof(double) * nn),
                  o_u = take(sizeof(double) * nz), o_cnt = take(sizeof(int32_t) * nn),
                  o_erow = take(sizeof(int32_t) * nz), o_flags = take(64),
-                 o_fac = take(ilu ? sizeof(double) * (size_t)fstride * std::max<size_t>(1, (size_t)n_c) : 8);
+                 o_fac = take((ilu || gmres) ? sizeof(double) * (size_t)fstride * std::max<size_t>(1, (size_t)n_c) : 8),
+                 o_gw = take(gmres ? sizeof(double) * (size_t)(km + 1) * (size_t)(smax + km + 3) *
+                                         std::max<size_t>(1, (size_t)n_c)
+                                   : 8);
     HIPCHK(c->ap_ws.ensure(off));
     char* base = static_cast<char*>(c->ap_ws.p);
     DiagWork w{};
     w.ilu = ilu ? 1 : 0;
+    w.gmres = gmres ? 1 : 0;
+    w.krylov = km;
+    w.gw = reinterpret_cast<double*>(base + o_gw);
     w.fac = reinterpret_cast<double*>(base + o_fac);
     w.smax = smax;
     w.n = n;

@@ -84,11 +84,13 @@ hipError_t launch_project_k(int n, int n_rows, const int32_t* rp, const int32_t*
 // the C-point's own entry included).  A^T in trp/tci/tva; clist[q] = the
 // C-point of row q; work arrays: diag, d, sj (n), cnt (n, zeroed), u and erow
 // (nnz), *bad_row (INT32_MAX beforehand), *uncovered (zeroed).  ilu: ILU(0)
-// of every block instead of its diagonal; fac holds smax^2 * n_c doubles
-// (smax >= the largest block, <= 64), interleaved over rows.
+// of every block instead of its diagonal; gmres: `krylov` GMRES steps on
+// every local system; fac holds the blocks (factors for ILU(0)), smax^2 * n_c
+// doubles (smax >= the largest block, <= 64), interleaved over rows; gw the
+// GMRES work, ((krylov + 1) (smax + krylov + 3)) * n_c doubles.
 struct DiagWork {
-  int ilu;
-  double* fac;
+  int ilu, gmres, krylov;
+  double *fac, *gw;
   int smax;
   int n, n_c;
   int64_t nnz;

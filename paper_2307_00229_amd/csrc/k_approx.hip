@@ -2,8 +2,9 @@
 // a block-diagonal approximate inverse of A_ff^{(*)}, e.g. diagonal or ILU;
 // the footnote of the comparison with root-node names the local diagonal
 // inverse), run for a given number of iterations on a pattern built
-// beforehand.  Two inverses: the diagonal of each block K_i = A[N,N]^T, or
-// its incomplete LU factorisation without fill (ILU(0)).
+// beforehand.  Three inverses: the diagonal of each block K_i = A[N,N]^T,
+// its incomplete LU factorisation without fill (ILU(0)), or m steps of GMRES
+// on the local system from zero.
 //
 // One thread per entry of R (row q, C-point i = clist[q], column j):
 //   start: -a_ij (the tentative operator), or with B the minimum-norm fit of
@@ -12,9 +13,10 @@
 //     rho_ij = -(R A)_ij on the F-entries: column j of A is read from A^T
 //            and each a_lj is paired with R's entry (q, l), found by a binary
 //            search of row q (sorted; it holds the C-point's 1 too);
-//     u_i = Khat_i^{-1} rho_i: rho_ij / a_jj (diagonal, same kernel), or the
-//            two triangular solves with the row's ILU(0) factors (one thread
-//            per row, in place on the row's entries);
+//     u_i = Khat_i^{-1} rho_i: rho_ij / a_jj (diagonal, same kernel), the
+//            two triangular solves with the row's ILU(0) factors, or GMRES
+//            with the row's block (one thread per row, in place on the row's
+//            entries);
 //            with B, s_j += u_ij B_i (FP64 atomics);
 //     z_ij += u_ij - B_i s_j / d_j (the projection; Q Q^T is diagonal).
 // The residual reads only the old R, so each iteration is one residual
@@ -149,12 +151,12 @@ __global__ __launch_bounds__(kAT) void k_ap_update(int64_t nnz, const int32_t* _
 // factor: row a is eliminated against the final rows above it, and its
 // pattern (a bit mask, s <= 64) is read just before, while it still holds K's
 // values.  A zero pivot reports the row's C-point.
-__global__ __launch_bounds__(kAT) void k_ap_ilu_factor(int n_c, const int32_t* __restrict__ Rrp,
-                                                      const int32_t* __restrict__ Rci,
-                                                      const int32_t* __restrict__ clist,
-                                                      const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
-                                                      const double* __restrict__ va, double* fac, int smax,
-                                                      int32_t* bad_row) {
+// (factor = 0: the block only, for GMRES)
+__global__ __launch_bounds__(kAT) void k_ap_block(int n_c, const int32_t* __restrict__ Rrp,
+                                                 const int32_t* __restrict__ Rci, const int32_t* __restrict__ clist,
+                                                 const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                 const double* __restrict__ va, double* fac, int smax, int factor,
+                                                 int32_t* bad_row) {
   for (int r = blockIdx.x * kAT + threadIdx.x; r < n_c; r += gridDim.x * kAT) {
     const int i = clist[r];
     const int e0 = Rrp[r], len = Rrp[r + 1] - e0;
@@ -181,6 +183,7 @@ __global__ __launch_bounds__(kAT) void k_ap_ilu_factor(int n_c, const int32_t* _
         }
       }
     }
+    if (!factor) continue;
     bool zero = false;
     for (int a = 0; a < s && !zero; ++a) {
       uint64_t ma = 0;
@@ -236,6 +239,97 @@ __global__ __launch_bounds__(kAT) void k_ap_ilu_solve(int n_c, const int32_t* __
   }
 }
 
+// GMRES(m) on the row's block from zero: u_i = the vector of the Krylov space
+// span{rho, K rho, ..., K^{m-1} rho} with the least residual |rho - K u|
+// (Arnoldi with modified Gram-Schmidt, Givens rotations; it stops when the
+// new basis vector's norm is at most 1e-12 of K v_j's).  Basis V ((m + 1) x
+// smax), Hessenberg H ((m + 1) x m), rotations and right-hand side g (3 (m +
+// 1)) per row, interleaved over rows in gw; with B the column sums
+// s_j += u_ij B_i.
+__global__ __launch_bounds__(kAT) void k_ap_gmres(int n_c, const int32_t* __restrict__ Rrp,
+                                                 const int32_t* __restrict__ Rci, const int32_t* __restrict__ clist,
+                                                 const double* __restrict__ fac, int smax, int m, double* gw,
+                                                 const double* __restrict__ B, double* u, double* sj) {
+  const int64_t nc = n_c;
+  double* Vb = gw;
+  double* Hb = Vb + (int64_t)(m + 1) * smax * nc;
+  double* cb = Hb + (int64_t)(m + 1) * m * nc;
+  double* sb = cb + (int64_t)(m + 1) * nc;
+  double* gb = sb + (int64_t)(m + 1) * nc;
+  for (int r = blockIdx.x * kAT + threadIdx.x; r < n_c; r += gridDim.x * kAT) {
+    const int i = clist[r];
+    const int e0 = Rrp[r], len = Rrp[r + 1] - e0;
+    const int s = len - 1;
+    if (s <= 0) continue;
+    int pc = 0;
+    while (pc < len && Rci[e0 + pc] != i) ++pc;
+    double* x = u + e0;  // rho in, u out; F-entry a at x[a + (a >= pc)]
+    auto X = [&](int a) -> double& { return x[a + (a >= pc)]; };
+    auto K = [&](int a, int c) { return fac[((int64_t)a * smax + c) * nc + r]; };
+    auto V = [&](int k, int a) -> double& { return Vb[((int64_t)k * smax + a) * nc + r]; };
+    auto H = [&](int a, int c) -> double& { return Hb[((int64_t)a * m + c) * nc + r]; };
+    auto CS = [&](int k) -> double& { return cb[(int64_t)k * nc + r]; };
+    auto SN = [&](int k) -> double& { return sb[(int64_t)k * nc + r]; };
+    auto G = [&](int k) -> double& { return gb[(int64_t)k * nc + r]; };
+    double beta = 0.0;
+    for (int a = 0; a < s; ++a) beta += X(a) * X(a);
+    beta = sqrt(beta);
+    if (beta == 0.0) continue;  // u = 0
+    for (int a = 0; a < s; ++a) V(0, a) = X(a) / beta;
+    for (int t = 0; t <= m; ++t) G(t) = 0.0;
+    G(0) = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      for (int a = 0; a < s; ++a) {
+        double acc = 0.0;
+        for (int c = 0; c < s; ++c) acc += K(a, c) * V(j, c);
+        V(j + 1, a) = acc;
+      }
+      double w0 = 0.0;
+      for (int a = 0; a < s; ++a) w0 += V(j + 1, a) * V(j + 1, a);
+      w0 = sqrt(w0);
+      for (int q = 0; q <= j; ++q) {
+        double h = 0.0;
+        for (int a = 0; a < s; ++a) h += V(j + 1, a) * V(q, a);
+        H(q, j) = h;
+        for (int a = 0; a < s; ++a) V(j + 1, a) -= h * V(q, a);
+      }
+      double hn = 0.0;
+      for (int a = 0; a < s; ++a) hn += V(j + 1, a) * V(j + 1, a);
+      hn = sqrt(hn);
+      for (int q = 0; q < j; ++q) {
+        const double h0 = H(q, j), h1 = H(q + 1, j);
+        H(q, j) = CS(q) * h0 + SN(q) * h1;
+        H(q + 1, j) = -SN(q) * h0 + CS(q) * h1;
+      }
+      const double hjj = H(j, j);
+      const double rr = sqrt(hjj * hjj + hn * hn);
+      CS(j) = rr > 0.0 ? hjj / rr : 1.0;
+      SN(j) = rr > 0.0 ? hn / rr : 0.0;
+      H(j, j) = rr;
+      G(j + 1) = -SN(j) * G(j);
+      G(j) = CS(j) * G(j);
+      k = j + 1;
+      if (!(hn > 1e-12 * w0)) break;  // the Krylov space is invariant: exact
+      for (int a = 0; a < s; ++a) V(j + 1, a) /= hn;
+    }
+    for (int q = k - 1; q >= 0; --q) {
+      double v = G(q);
+      for (int c = q + 1; c < k; ++c) v -= H(q, c) * G(c);
+      G(q) = H(q, q) != 0.0 ? v / H(q, q) : 0.0;
+    }
+    for (int a = 0; a < s; ++a) {
+      double v = 0.0;
+      for (int q = 0; q < k; ++q) v += G(q) * V(q, a);
+      X(a) = v;
+    }
+    if (B) {
+      const double bi = B[i];
+      for (int a = 0; a < s; ++a) unsafeAtomicAdd(&sj[Rci[e0 + a + (a >= pc)]], X(a) * bi);
+    }
+  }
+}
+
 // F-points no row reaches
 __global__ __launch_bounds__(kAT) void k_ap_uncovered(int n, const int8_t* __restrict__ cf,
                                                      const int32_t* __restrict__ cnt, unsigned long long* out) {
@@ -252,10 +346,10 @@ hipError_t launch_diag_start(const DiagWork& w, hipStream_t s) {
                        w.Rrp, w.erow);
   if (w.nnz > 0) {
     hipLaunchKernelGGL(k_ap_start, dim3(agrid(w.nnz, w.cus)), dim3(kAT), 0, s, w.nnz, w.erow, w.clist, w.Rci, w.Rva,
-                       w.rp, w.ci, w.va, w.B, w.diag, w.d, w.cnt, w.ilu ? nullptr : w.bad_row);
-    if (w.ilu)
-      hipLaunchKernelGGL(k_ap_ilu_factor, dim3(agrid(w.n_c, w.cus)), dim3(kAT), 0, s, w.n_c, w.Rrp, w.Rci, w.clist,
-                         w.rp, w.ci, w.va, w.fac, w.smax, w.bad_row);
+                       w.rp, w.ci, w.va, w.B, w.diag, w.d, w.cnt, (w.ilu || w.gmres) ? nullptr : w.bad_row);
+    if (w.ilu || w.gmres)
+      hipLaunchKernelGGL(k_ap_block, dim3(agrid(w.n_c, w.cus)), dim3(kAT), 0, s, w.n_c, w.Rrp, w.Rci, w.clist, w.rp,
+                         w.ci, w.va, w.fac, w.smax, w.ilu, w.bad_row);
     if (w.B)
       hipLaunchKernelGGL(k_ap_fit, dim3(agrid(w.nnz, w.cus)), dim3(kAT), 0, s, w.nnz, w.erow, w.clist, w.Rci, w.Rva,
                          w.B, w.d);
@@ -272,10 +366,13 @@ hipError_t launch_diag_iteration(const DiagWork& w, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_ap_resid, dim3(agrid(w.nnz, w.cus)), dim3(kAT), 0, s, w.nnz, w.erow, w.clist, w.Rrp, w.Rci,
-                     w.Rva, w.trp, w.tci, w.tva, w.diag, w.B, w.u, w.sj, w.ilu ? 0 : 1);
+                     w.Rva, w.trp, w.tci, w.tva, w.diag, w.B, w.u, w.sj, (w.ilu || w.gmres) ? 0 : 1);
   if (w.ilu)
     hipLaunchKernelGGL(k_ap_ilu_solve, dim3(agrid(w.n_c, w.cus)), dim3(kAT), 0, s, w.n_c, w.Rrp, w.Rci, w.clist, w.fac,
                        w.smax, w.B, w.u, w.sj);
+  if (w.gmres)
+    hipLaunchKernelGGL(k_ap_gmres, dim3(agrid(w.n_c, w.cus)), dim3(kAT), 0, s, w.n_c, w.Rrp, w.Rci, w.clist, w.fac,
+                       w.smax, w.krylov, w.gw, w.B, w.u, w.sj);
   hipLaunchKernelGGL(k_ap_update, dim3(agrid(w.nnz, w.cus)), dim3(kAT), 0, s, w.nnz, w.erow, w.clist, w.Rci, w.Rva,
                      w.u, w.B, w.d, w.sj);
   return hipGetLastError();

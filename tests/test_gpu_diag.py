@@ -148,7 +148,7 @@ def test_degenerate_inputs(idx):
 
 
 # ---------------------------------------------------------------- ILU(0) ---
-def _gpu_approx(p, B, iters, inverse, theta=0.0, check=True):
+def _gpu_approx(p, B, iters, inverse, theta=0.0, check=True, krylov=0):
     from paper_2307_00229_amd import clair
 
     ctx = clair.Context()
@@ -157,7 +157,8 @@ def _gpu_approx(p, B, iters, inverse, theta=0.0, check=True):
     A = clair.CSR.from_problem(p, "cuda")
     cf = torch.from_numpy(p.cf).cuda()
     Bt = None if B is None else torch.from_numpy(np.ascontiguousarray(B)).cuda()
-    out, info, st = clair.clair_build_R_approx(A, cf, Bt, p.ell, iters, inverse=inverse, ctx=ctx, check=check)
+    out, info, st = clair.clair_build_R_approx(A, cf, Bt, p.ell, iters, inverse=inverse, krylov=krylov, ctx=ctx,
+                                               check=check)
     torch.cuda.synchronize()
     if out is None or st:
         return None, info, st
@@ -227,3 +228,60 @@ def test_ilu0_zero_pivot_is_singular():
     _, info, st = _gpu_approx(q, q.B, 1, clair.CLAIR_INVERSE_ILU0, check=False)
     assert st == clair.CLAIR_ERR_SINGULAR
     assert info["first_bad_row"] == expect
+
+
+# ----------------------------------------------------------------- GMRES ---
+def _compare_gmres(p, B, iters, krylov, theta=0.0):
+    from paper_2307_00229_amd import clair
+
+    g, info, _ = _gpu_approx(p, B, iters, clair.CLAIR_INVERSE_GMRES, theta, krylov=krylov)
+    o = oracle.build_R_approx(p.n, p.row_ptr, p.col_idx, p.val, p.cf, B, p.ell, iters, "gmres", theta=theta,
+                              krylov=krylov)
+    assert np.array_equal(g["row_ptr"], o["row_ptr"]) and np.array_equal(g["col_idx"], o["col_idx"])
+    err, _, _ = row_errors(p, g, o)
+    print(f"[gpu] gmres({krylov}) {p.name} B={'yes' if B is not None else 'no'} iters={iters}: "
+          f"row error {err.max():.2e}", flush=True)
+    assert err.max() <= 1e-10
+    if B is not None:
+        assert info["n_uncovered"] == o["n_uncovered"]
+        res, _ = constraint_residual(p, g)
+        assert res <= 1e-12, res
+    return g
+
+
+@pytest.mark.parametrize("krylov", [1, 3])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_gmres_matches_oracle(case, krylov):
+    p = CASES[case]()
+    for iters in (1, 2):
+        _compare_gmres(p, p.B, iters, krylov)
+        _compare_gmres(p, None, iters, krylov)
+
+
+def test_gmres_workload_matrix_and_strength():
+    p = P.cfg2()[0]
+    _compare_gmres(p, p.B, 2, 3)
+    _compare_gmres(CASES[2](), CASES[2]().B, 2, 2, theta=0.25)
+
+
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_gmres_full_krylov_space_is_exact(case):
+    # every block of these matrices has at most 32 points
+    from paper_2307_00229_amd import clair
+
+    p = CASES[case]()
+    g, _, _ = _gpu_approx(p, p.B, 1, clair.CLAIR_INVERSE_GMRES, krylov=32)
+    ex, infos, st = gpu_build([p])
+    assert st == 0, infos
+    err, _, _ = row_errors(p, g, ex[0])
+    print(f"[gpu] gmres(32) {p.name} vs exact build: row error {err.max():.2e}", flush=True)
+    assert err.max() <= 1e-10, err.max()
+
+
+def test_gmres_bad_krylov_rejected():
+    from paper_2307_00229_amd import clair
+
+    p = CASES[1]()
+    for m in (0, 33):
+        _, _, st = _gpu_approx(p, p.B, 1, clair.CLAIR_INVERSE_GMRES, krylov=m, check=False)
+        assert st == clair.CLAIR_ERR_INVALID
