@@ -17,6 +17,8 @@ Modules
                     constraint fit, residual update, explicit projection), for
                     any number k of iterations.
 ``smoothing``    -- CFF-weighted-Jacobi smoothing of the constraint vector.
+``kkt``          -- the exact minimiser in the normal-equations metric (the
+                    KKT system of Section 3.1.1), for comparison.
 ``build_R_approx`` -- Algorithm 1 with approximate block inverses (diagonal,
                     ILU(0) or GMRES) and any number of iterations (C oracle, on the
                     exact build's pattern); ``build_R_diag`` the diagonal one.
