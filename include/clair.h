@@ -222,6 +222,29 @@ int clair_build_R_approx(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* c
                          int32_t ell, int32_t inverse, int32_t krylov, int32_t iterations, clair_csr_out_t* R_out,
                          clair_info_t* info, void* stream);
 
+/*
+ * clair_build_R_kkt -- for comparison with Algorithm 1: the exact solution of
+ * Section 3.1.1's constrained problem in the normal-equations metric (its
+ * KKT system has the (1,1) block A_ff^T A_ff; Algorithm 1 projects in the
+ * Euclidean norm instead).  For restriction, row i (C-point i, F-columns N)
+ * has K_i = A[N,N]^T, a_i = A[i,N]^T and the energy |a_i + K_i z_i|^2; R
+ * minimises the sum over the rows subject to R^T B_c = B.  Same pattern as
+ * clair_build_R (the context's strength threshold).  Computed as
+ * z_i = z0_i - Abar_i^{-1} B_i lambda|_N with z0 the exact unconstrained rows,
+ * Abar_i = K_i^T K_i (Cholesky per row) and lambda from conjugate gradients
+ * on Q Abar^{-1} Q^T lambda = Q z0 - B_F (SPD over the covered F-points;
+ * stopped at a residual of 1e-14 of the right-hand side, at most 10000
+ * steps).  B = NULL gives the unconstrained rows.
+ *   R_out     as for clair_build_R (a size query with too small capacities)
+ *   info      as clair_build_R's; refine_iters_max = the CG steps taken
+ * An Abar_i that is not positive definite returns CLAIR_ERR_SINGULAR with
+ * first_bad_row = the smallest such C-point; blocks above 64 points
+ * CLAIR_ERR_UNSUPPORTED.  cf_marker may be NULL only when A->n = 0.
+ * Synchronises `stream` (two host reads per CG step).
+ */
+int clair_build_R_kkt(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_marker, const double* B,
+                      int32_t ell, clair_csr_out_t* R_out, clair_info_t* info, void* stream);
+
 /* clair_build_R_diag -- clair_build_R_approx with CLAIR_INVERSE_DIAG. */
 int clair_build_R_diag(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_marker, const double* B,
                        int32_t ell, int32_t iterations, clair_csr_out_t* R_out, clair_info_t* info, void* stream);

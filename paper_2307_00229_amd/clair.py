@@ -31,7 +31,7 @@ EXPORTED = [
     "clair_ctx_info", "clair_size_R", "clair_ctx_stage_times", "clair_ctx_set_tuning", "clair_ctx_get_tuning",
     "clair_ctx_set_strength", "clair_ctx_get_strength", "clair_transpose", "clair_build_P",
     "clair_spgemm", "clair_galerkin", "clair_smooth_B", "clair_build_R_agg", "clair_project_constraints",
-    "clair_build_R_diag", "clair_build_R_approx",
+    "clair_build_R_diag", "clair_build_R_approx", "clair_build_R_kkt",
     "clair_autotune", "clair_graph_create", "clair_graph_launch", "clair_graph_destroy", "clair_graph_info",
     "clair_plan_create", "clair_plan_execute", "clair_plan_info", "clair_plan_destroy",
     "clair_strerror", "clair_last_error",
@@ -130,6 +130,8 @@ def load_library(path: str = LIB_PATH):
                                        ctypes.POINTER(I64), P], ctypes.c_int),
         "clair_build_R_diag": ([P, ctypes.POINTER(CsrIn), P, P, I32, I32, ctypes.POINTER(CsrOut),
                                 ctypes.POINTER(Info), P], ctypes.c_int),
+        "clair_build_R_kkt": ([P, ctypes.POINTER(CsrIn), P, P, I32, ctypes.POINTER(CsrOut), ctypes.POINTER(Info), P],
+                              ctypes.c_int),
         "clair_build_R_approx": ([P, ctypes.POINTER(CsrIn), P, P, I32, I32, I32, I32, ctypes.POINTER(CsrOut),
                                   ctypes.POINTER(Info), P], ctypes.c_int),
         "clair_strerror": ([ctypes.c_int], ctypes.c_char_p),
@@ -555,6 +557,39 @@ def clair_build_R_approx(A: CSR, cf: torch.Tensor, B: Optional[torch.Tensor], el
     st = call(oc)
     if st and check:
         raise ClairError(st, "clair_build_R_approx")
+    out.n_c = int(oc.n_rows)
+    out.nnz = int(oc.nnz)
+    return out.trimmed(), info.as_dict(), st
+
+
+def clair_build_R_kkt(A: CSR, cf: torch.Tensor, B: Optional[torch.Tensor], ell: int, *,
+                      ctx: Optional[Context] = None, stream=None, check: bool = True):
+    """The normal-equations (KKT) minimiser: ((row_ptr, col_idx, val), info, status);
+    info["refine_iters_max"] holds the conjugate-gradient steps."""
+    lib = load_library()
+    ctx = ctx or Context()
+    _check_dev(cf, torch.int8, "cf")
+    if B is not None:
+        _check_dev(B, torch.float64, "B")
+    info = Info()
+    sp_ = _stream_ptr(stream)
+    Ac = A.c()
+
+    def call(o):
+        return lib.clair_build_R_kkt(ctx.handle, ctypes.byref(Ac), cf.data_ptr(), _ptr(B), int(ell), ctypes.byref(o),
+                                     ctypes.byref(info), sp_)
+
+    probe = CsrOut()
+    st = call(probe)
+    if st not in (CLAIR_OK, CLAIR_ERR_CAPACITY):
+        if check:
+            raise ClairError(st, "clair_build_R_kkt")
+        return None, info.as_dict(), st
+    out = ROut(int(probe.n_rows), int(probe.nnz), device=A.row_ptr.device)
+    oc = out.c()
+    st = call(oc)
+    if st and check:
+        raise ClairError(st, "clair_build_R_kkt")
     out.n_c = int(oc.n_rows)
     out.nnz = int(oc.nnz)
     return out.trimmed(), info.as_dict(), st

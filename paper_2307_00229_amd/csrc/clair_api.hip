@@ -173,6 +173,8 @@ struct clair_ctx {
   DevBuf pk_scratch;
   // diagonal block inverse: diagonal, column sums, updates, row of each entry
   DevBuf ap_ws;
+  // normal-equations minimiser: blocks, Cholesky factors, CG vectors
+  DevBuf kkt_ws;
 };
 
 namespace {
@@ -1166,6 +1168,119 @@ int clair_build_R_approx(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf,
     HIPCHK(hipStreamSynchronize(s));
     in.n_uncovered = B ? (int64_t)unc : 0;
     in.first_bad_row = -1;
+    if (info) *info = in;
+    return CLAIR_OK;
+  } catch (...) {
+    return CLAIR_ERR_NOMEM;
+  }
+}
+
+int clair_build_R_kkt(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf, const double* B, int32_t ell,
+                      clair_csr_out_t* R, clair_info_t* info, void* stream) {
+  if (!c || !R || ell < 1 || ell > 64 || check_csr_args(A)) return CLAIR_ERR_INVALID;
+  if (!cf && A->n > 0) return CLAIR_ERR_INVALID;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  try {
+    // the unconstrained minimiser: the exact l-AIR rows
+    clair_opts_t o{};
+    o.stream = stream;
+    o.precision = CLAIR_PREC_MIXED;
+    clair_info_t in{};
+    int rc = clair_build_R_ex(c, A, cf, nullptr, ell, R, &o, &in);
+    if (info) *info = in;
+    if (rc || !B) return rc;
+    const int32_t n = A->n, n_rows = R->n_rows;
+    const int smax = std::max(1, in.max_block);
+    if (smax > 64) return CLAIR_ERR_UNSUPPORTED;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      const size_t o2 = off;
+      off += (bytes + 255) & ~size_t(255);
+      return o2;
+    };
+    const size_t nn = std::max<size_t>(1, (size_t)n), nr = std::max<size_t>(1, (size_t)n_rows);
+    const size_t o_flag = take(sizeof(int32_t) * nn), o_pos = take(sizeof(int32_t) * (nn + 1)),
+                 o_sums = take(sizeof(int32_t) * scan_scratch_ints(n)), o_rowc = take(sizeof(int32_t) * nr),
+                 o_cnt = take(sizeof(int32_t) * nn), o_bad = take(64),
+                 o_K = take(sizeof(double) * (size_t)smax * smax * nr), o_L = take(sizeof(double) * (size_t)smax * smax * nr),
+                 o_T = take(sizeof(double) * (size_t)smax * nr), o_rhs = take(sizeof(double) * nn),
+                 o_res = take(sizeof(double) * nn), o_p = take(sizeof(double) * nn), o_x = take(sizeof(double) * nn),
+                 o_Ap = take(sizeof(double) * nn), o_dot = take(64);
+    HIPCHK(c->kkt_ws.ensure(off));
+    char* base = static_cast<char*>(c->kkt_ws.p);
+    KktWork w{};
+    w.n = n;
+    w.n_rows = n_rows;
+    w.smax = smax;
+    w.cus = c->cus;
+    w.rp = A->row_ptr;
+    w.ci = A->col_idx;
+    w.va = A->val;
+    w.cf = cf;
+    w.B = B;
+    w.Rrp = R->row_ptr;
+    w.Rci = R->col_idx;
+    w.Rva = R->val;
+    w.flag = reinterpret_cast<int32_t*>(base + o_flag);
+    w.pos = reinterpret_cast<int32_t*>(base + o_pos);
+    w.scan_sums = reinterpret_cast<int32_t*>(base + o_sums);
+    w.rowc = reinterpret_cast<int32_t*>(base + o_rowc);
+    w.cnt = reinterpret_cast<int32_t*>(base + o_cnt);
+    w.bad = reinterpret_cast<int32_t*>(base + o_bad);
+    w.K = reinterpret_cast<double*>(base + o_K);
+    w.L = reinterpret_cast<double*>(base + o_L);
+    w.T = reinterpret_cast<double*>(base + o_T);
+    w.rhs = reinterpret_cast<double*>(base + o_rhs);
+    w.res = reinterpret_cast<double*>(base + o_res);
+    w.p = reinterpret_cast<double*>(base + o_p);
+    w.x = reinterpret_cast<double*>(base + o_x);
+    w.Ap = reinterpret_cast<double*>(base + o_Ap);
+    double* dot = reinterpret_cast<double*>(base + o_dot);
+    HIPCHK(hipMemsetAsync(w.cnt, 0, sizeof(int32_t) * nn, s));
+    HIPCHK(hipMemsetAsync(w.rhs, 0, sizeof(double) * nn, s));
+    const int32_t hbad0[2] = {0, INT32_MAX};
+    HIPCHK(hipMemcpyAsync(w.bad, hbad0, sizeof(hbad0), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_kkt_setup(w, s));
+    int32_t hbad[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(hbad, w.bad, sizeof(hbad), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (hbad[0]) return CLAIR_ERR_INVALID;
+    if (hbad[1] != INT32_MAX) {
+      in.status = CLAIR_ERR_SINGULAR;
+      in.first_bad_row = hbad[1];
+      if (info) *info = in;
+      return CLAIR_ERR_SINGULAR;
+    }
+    // conjugate gradients on M lambda = Q z0 - B_F (M SPD), from lambda = 0
+    auto dotp = [&](const double* x, const double* y, double* out) -> int {
+      HIPCHK(hipMemsetAsync(dot, 0, sizeof(double), s));
+      HIPCHK(launch_kkt_dot(w, x, y, dot, s));
+      HIPCHK(hipMemcpyAsync(out, dot, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      return CLAIR_OK;
+    };
+    double rr = 0.0;
+    rc = dotp(w.res, w.res, &rr);
+    if (rc) return rc;
+    const double stop = rr * 1e-28;  // |res| <= 1e-14 |rhs|
+    int it = 0;
+    for (; it < 10000 && rr > stop && rr > 0.0; ++it) {
+      HIPCHK(hipMemsetAsync(w.Ap, 0, sizeof(double) * nn, s));
+      HIPCHK(launch_kkt_matvec(w, s));
+      double pAp = 0.0;
+      rc = dotp(w.p, w.Ap, &pAp);
+      if (rc) return rc;
+      if (!(pAp > 0.0)) break;
+      HIPCHK(launch_kkt_axpy(w, rr / pAp, s));
+      double rr_new = 0.0;
+      rc = dotp(w.res, w.res, &rr_new);
+      if (rc) return rc;
+      HIPCHK(launch_kkt_dir(w, rr_new / rr, s));
+      rr = rr_new;
+    }
+    HIPCHK(launch_kkt_apply(w, s));
+    HIPCHK(hipStreamSynchronize(s));
+    in.refine_iters_max = it;
     if (info) *info = in;
     return CLAIR_OK;
   } catch (...) {

@@ -110,6 +110,29 @@ struct DiagWork {
 hipError_t launch_diag_start(const DiagWork& w, hipStream_t s);
 hipError_t launch_diag_iteration(const DiagWork& w, hipStream_t s);
 
+// the normal-equations (KKT) minimiser on an unconstrained R (rows sorted,
+// the C-point's entry included; n_rows = the number of C-points).  Device
+// arrays: flag (n), pos (n + 1), scan_sums (scan_scratch_ints(n)), rowc
+// (n_rows), K and L (smax^2 * n_rows), T (smax * n_rows), rhs, res, p, x, Ap
+// (n), cnt (n, zeroed), rhs zeroed, bad (2 ints: 0 and INT32_MAX).
+struct KktWork {
+  int n, n_rows, smax, cus;
+  const int32_t *rp, *ci;
+  const double* va;
+  const int8_t* cf;
+  const double* B;
+  const int32_t *Rrp, *Rci;
+  double* Rva;
+  int32_t *flag, *pos, *scan_sums, *rowc, *cnt, *bad;
+  double *K, *L, *T, *rhs, *res, *p, *x, *Ap;
+};
+hipError_t launch_kkt_setup(const KktWork& w, hipStream_t s);
+hipError_t launch_kkt_matvec(const KktWork& w, hipStream_t s);  // Ap += M p
+hipError_t launch_kkt_dot(const KktWork& w, const double* x, const double* y, double* out, hipStream_t s);
+hipError_t launch_kkt_axpy(const KktWork& w, double alpha, hipStream_t s);  // x += alpha p, res -= alpha Ap
+hipError_t launch_kkt_dir(const KktWork& w, double beta, hipStream_t s);    // p = res + beta p
+hipError_t launch_kkt_apply(const KktWork& w, hipStream_t s);               // z -= B_i Abar^{-1} x|_N
+
 // plain FP64 per-row form: one matrix, one thread per row, one kernel per stage
 struct PlainWork {
   const int32_t* rp;
