@@ -1251,33 +1251,28 @@ int clair_build_R_kkt(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf, co
       if (info) *info = in;
       return CLAIR_ERR_SINGULAR;
     }
-    // conjugate gradients on M lambda = Q z0 - B_F (M SPD), from lambda = 0
-    auto dotp = [&](const double* x, const double* y, double* out) -> int {
-      HIPCHK(hipMemsetAsync(dot, 0, sizeof(double), s));
-      HIPCHK(launch_kkt_dot(w, x, y, dot, s));
-      HIPCHK(hipMemcpyAsync(out, dot, sizeof(double), hipMemcpyDeviceToHost, s));
+    // conjugate gradients on M lambda = Q z0 - B_F (M SPD), from lambda = 0;
+    // the scalars stay on the device, the host reads the flag every 8 steps
+    w.sc = dot;
+    w.done = reinterpret_cast<int32_t*>(dot + 6);
+    w.steps = w.done + 1;
+    HIPCHK(hipMemsetAsync(dot, 0, 64, s));
+    HIPCHK(launch_kkt_dot(w, w.res, w.res, w.sc, s));
+    double rr0 = 0.0;
+    HIPCHK(hipMemcpyAsync(&rr0, w.sc, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double stop = rr0 * 1e-28;  // |res| <= 1e-14 |rhs|
+    HIPCHK(hipMemcpyAsync(w.sc + 3, &stop, sizeof(double), hipMemcpyHostToDevice, s));
+    int32_t hs[2] = {rr0 > 0.0 ? 0 : 1, 0};
+    HIPCHK(hipMemcpyAsync(w.done, hs, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    int queued = 0;
+    while (!hs[0] && queued < 10000) {
+      for (int k = 0; k < 8; ++k) HIPCHK(launch_kkt_step(w, s));
+      queued += 8;
+      HIPCHK(hipMemcpyAsync(hs, w.done, sizeof(hs), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      return CLAIR_OK;
-    };
-    double rr = 0.0;
-    rc = dotp(w.res, w.res, &rr);
-    if (rc) return rc;
-    const double stop = rr * 1e-28;  // |res| <= 1e-14 |rhs|
-    int it = 0;
-    for (; it < 10000 && rr > stop && rr > 0.0; ++it) {
-      HIPCHK(hipMemsetAsync(w.Ap, 0, sizeof(double) * nn, s));
-      HIPCHK(launch_kkt_matvec(w, s));
-      double pAp = 0.0;
-      rc = dotp(w.p, w.Ap, &pAp);
-      if (rc) return rc;
-      if (!(pAp > 0.0)) break;
-      HIPCHK(launch_kkt_axpy(w, rr / pAp, s));
-      double rr_new = 0.0;
-      rc = dotp(w.res, w.res, &rr_new);
-      if (rc) return rc;
-      HIPCHK(launch_kkt_dir(w, rr_new / rr, s));
-      rr = rr_new;
     }
+    const int it = hs[1];
     HIPCHK(launch_kkt_apply(w, s));
     HIPCHK(hipStreamSynchronize(s));
     in.refine_iters_max = it;

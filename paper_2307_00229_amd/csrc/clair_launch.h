@@ -114,8 +114,12 @@ hipError_t launch_diag_iteration(const DiagWork& w, hipStream_t s);
 // the C-point's entry included; n_rows = the number of C-points).  Device
 // arrays: flag (n), pos (n + 1), scan_sums (scan_scratch_ints(n)), rowc
 // (n_rows), K and L (smax^2 * n_rows), T (smax * n_rows), rhs, res, p, x, Ap
-// (n), cnt (n, zeroed), rhs zeroed, bad (2 ints: 0 and INT32_MAX).
+// (n), cnt (n, zeroed), rhs zeroed, bad (2 ints: 0 and INT32_MAX); CG state
+// sc (5 doubles: res.res, p.Ap, new res.res, stop level, beta), done and
+// steps (ints, zeroed).
 struct KktWork {
+  double* sc;
+  int32_t *done, *steps;
   int n, n_rows, smax, cus;
   const int32_t *rp, *ci;
   const double* va;
@@ -127,10 +131,10 @@ struct KktWork {
   double *K, *L, *T, *rhs, *res, *p, *x, *Ap;
 };
 hipError_t launch_kkt_setup(const KktWork& w, hipStream_t s);
-hipError_t launch_kkt_matvec(const KktWork& w, hipStream_t s);  // Ap += M p
+// *out += x . y (skipped once done)
 hipError_t launch_kkt_dot(const KktWork& w, const double* x, const double* y, double* out, hipStream_t s);
-hipError_t launch_kkt_axpy(const KktWork& w, double alpha, hipStream_t s);  // x += alpha p, res -= alpha Ap
-hipError_t launch_kkt_dir(const KktWork& w, double beta, hipStream_t s);    // p = res + beta p
+// one CG step with the scalars on the device; a no-op once *done
+hipError_t launch_kkt_step(const KktWork& w, hipStream_t s);
 hipError_t launch_kkt_apply(const KktWork& w, hipStream_t s);               // z -= B_i Abar^{-1} x|_N
 
 // plain FP64 per-row form: one matrix, one thread per row, one kernel per stage

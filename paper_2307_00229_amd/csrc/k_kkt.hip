@@ -12,7 +12,10 @@
 // interleaved over rows so a wavefront's accesses are consecutive), then
 // conjugate gradients on M applied matrix-free (gather lambda on N, two
 // triangular solves, scatter B_i^2 times the result with FP64 atomics), then
-// the correction of every row.
+// the correction of every row.  The CG scalars stay on the device: the step
+// lengths are read from device memory, a one-thread kernel tests convergence
+// and sets a flag after which every step kernel returns at once, so the host
+// can queue several steps between reads.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -168,7 +171,8 @@ __global__ __launch_bounds__(kQT) void k_q_matvec(int n_rows, const int32_t* __r
                                                  const int32_t* __restrict__ Rci, const int32_t* __restrict__ rowc,
                                                  const double* __restrict__ Lb, int smax, double* Tb,
                                                  const double* __restrict__ B, const double* __restrict__ p,
-                                                 double* y) {
+                                                 double* y, const int32_t* __restrict__ done) {
+  if (*done) return;
   const int64_t nr = n_rows;
   for (int r = blockIdx.x * kQT + threadIdx.x; r < n_rows; r += gridDim.x * kQT) {
     const int i = rowc[r];
@@ -186,8 +190,9 @@ __global__ __launch_bounds__(kQT) void k_q_matvec(int n_rows, const int32_t* __r
 
 // *out += x . y
 __global__ __launch_bounds__(kQT) void k_q_dot(int n, const double* __restrict__ x, const double* __restrict__ y,
-                                              double* out) {
+                                              double* out, const int32_t* __restrict__ done) {
   __shared__ double part[kQT / 64];
+  if (done && *done) return;
   double acc = 0.0;
   for (int j = blockIdx.x * kQT + threadIdx.x; j < n; j += gridDim.x * kQT) acc += x[j] * y[j];
 #pragma unroll
@@ -201,16 +206,47 @@ __global__ __launch_bounds__(kQT) void k_q_dot(int n, const double* __restrict__
   }
 }
 
-__global__ __launch_bounds__(kQT) void k_q_axpy(int n, double alpha, const double* __restrict__ p,
-                                               const double* __restrict__ Ap, double* x, double* res) {
+// sc: [0] res.res, [1] p.Ap, [2] the new res.res, [3] the stop level,
+// [4] beta; *done set once the step cannot or need not go on
+__global__ __launch_bounds__(kQT) void k_q_axpy(int n, const double* __restrict__ sc, const double* __restrict__ p,
+                                               const double* __restrict__ Ap, double* x, double* res, int32_t* done) {
+  if (*done) return;
+  if (!(sc[1] > 0.0)) {  // breakdown (lambda is as good as it gets)
+    if (blockIdx.x == 0 && threadIdx.x == 0) *done = 1;
+    return;
+  }
+  const double alpha = sc[0] / sc[1];
   for (int j = blockIdx.x * kQT + threadIdx.x; j < n; j += gridDim.x * kQT) {
     x[j] += alpha * p[j];
     res[j] -= alpha * Ap[j];
   }
 }
 
-__global__ __launch_bounds__(kQT) void k_q_dir(int n, double beta, const double* __restrict__ res, double* p) {
+// one thread: convergence test, beta, the step count; clears [1] and [2] for
+// the next step
+__global__ void k_q_scalars(double* sc, int32_t* done, int32_t* steps) {
+  if (*done) return;
+  *steps += 1;
+  if (!(sc[2] > sc[3])) {
+    *done = 1;
+    return;
+  }
+  sc[4] = sc[2] / sc[0];
+  sc[0] = sc[2];
+  sc[1] = 0.0;
+  sc[2] = 0.0;
+}
+
+__global__ __launch_bounds__(kQT) void k_q_dir(int n, const double* __restrict__ sc, const double* __restrict__ res,
+                                              double* p, const int32_t* __restrict__ done) {
+  if (*done) return;
+  const double beta = sc[4];
   for (int j = blockIdx.x * kQT + threadIdx.x; j < n; j += gridDim.x * kQT) p[j] = res[j] + beta * p[j];
+}
+
+__global__ __launch_bounds__(kQT) void k_q_zero(int n, double* y, const int32_t* __restrict__ done) {
+  if (*done) return;
+  for (int j = blockIdx.x * kQT + threadIdx.x; j < n; j += gridDim.x * kQT) y[j] = 0.0;
 }
 
 // z_ij -= B_i (Abar^{-1} lambda|_N)_j
@@ -259,28 +295,27 @@ hipError_t launch_kkt_setup(const KktWork& w, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_kkt_matvec(const KktWork& w, hipStream_t s) {
-  if (w.n_rows > 0)
-    hipLaunchKernelGGL(k_q_matvec, dim3(qgrid(w.n_rows, w.cus)), dim3(kQT), 0, s, w.n_rows, w.Rrp, w.Rci, w.rowc,
-                       w.L, w.smax, w.T, w.B, w.p, w.Ap);
-  return hipGetLastError();
-}
-
 hipError_t launch_kkt_dot(const KktWork& w, const double* x, const double* y, double* out, hipStream_t s) {
   if (w.n > 0)
     hipLaunchKernelGGL(k_q_dot, dim3(std::max(1, std::min((w.n + kQT - 1) / kQT, w.cus * 4))), dim3(kQT), 0, s,
-                       w.n, x, y, out);
+                       w.n, x, y, out, w.done);
   return hipGetLastError();
 }
 
-hipError_t launch_kkt_axpy(const KktWork& w, double alpha, hipStream_t s) {
-  if (w.n > 0)
-    hipLaunchKernelGGL(k_q_axpy, dim3(qgrid(w.n, w.cus)), dim3(kQT), 0, s, w.n, alpha, w.p, w.Ap, w.x, w.res);
-  return hipGetLastError();
-}
-
-hipError_t launch_kkt_dir(const KktWork& w, double beta, hipStream_t s) {
-  if (w.n > 0) hipLaunchKernelGGL(k_q_dir, dim3(qgrid(w.n, w.cus)), dim3(kQT), 0, s, w.n, beta, w.res, w.p);
+hipError_t launch_kkt_step(const KktWork& w, hipStream_t s) {
+  if (w.n <= 0) return hipSuccess;
+  const int g = qgrid(w.n, w.cus);
+  hipLaunchKernelGGL(k_q_zero, dim3(g), dim3(kQT), 0, s, w.n, w.Ap, w.done);
+  if (w.n_rows > 0)
+    hipLaunchKernelGGL(k_q_matvec, dim3(qgrid(w.n_rows, w.cus)), dim3(kQT), 0, s, w.n_rows, w.Rrp, w.Rci, w.rowc,
+                       w.L, w.smax, w.T, w.B, w.p, w.Ap, w.done);
+  hipError_t e = launch_kkt_dot(w, w.p, w.Ap, w.sc + 1, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_q_axpy, dim3(g), dim3(kQT), 0, s, w.n, w.sc, w.p, w.Ap, w.x, w.res, w.done);
+  e = launch_kkt_dot(w, w.res, w.res, w.sc + 2, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_q_scalars, dim3(1), dim3(1), 0, s, w.sc, w.done, w.steps);
+  hipLaunchKernelGGL(k_q_dir, dim3(g), dim3(kQT), 0, s, w.n, w.sc, w.res, w.p, w.done);
   return hipGetLastError();
 }
 
