@@ -240,7 +240,8 @@ int clair_build_R_approx(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* c
  * An Abar_i that is not positive definite returns CLAIR_ERR_SINGULAR with
  * first_bad_row = the smallest such C-point; blocks above 64 points
  * CLAIR_ERR_UNSUPPORTED.  cf_marker may be NULL only when A->n = 0.
- * Synchronises `stream` (two host reads per CG step).
+ * Synchronises `stream` (the host reads the CG convergence flag every 8
+ * steps; the step scalars stay on the device).
  */
 int clair_build_R_kkt(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_marker, const double* B,
                       int32_t ell, clair_csr_out_t* R_out, clair_info_t* info, void* stream);
