@@ -65,6 +65,8 @@ def _load():
         lib.orc_pattern_size.restype = ctypes.c_int
         lib.orc_build_R.argtypes = [i32, p, p, p, p, p, p, i32, f64, i32, p, p, p, i64, p, p]
         lib.orc_build_R.restype = ctypes.c_int
+        lib.orc_build_R_g.argtypes = [i32, p, p, p, p, p, p, p, p, p, i32, f64, i32, p, p, p, i64, p, p]
+        lib.orc_build_R_g.restype = ctypes.c_int
         lib.orc_project_k.argtypes = [i32, i32, p, p, p, p, p, i32, f64, p]
         lib.orc_project_k.restype = ctypes.c_int
         lib.orc_iterate_approx.argtypes = [i32, p, p, p, p, p, i32, p, p, p, i32, i32, i32, p]
@@ -109,9 +111,13 @@ def pattern_size(n, row_ptr, col_idx, val, cf, ell, nthreads=0, theta=0.0, agg=N
     return n_c.value, nnz.value, sizes[: n_c.value]
 
 
-def build_R(n, row_ptr, col_idx, val, cf, B, ell, nthreads=0, allow_singular=False, theta=0.0, agg=None):
+def build_R(n, row_ptr, col_idx, val, cf, B, ell, nthreads=0, allow_singular=False, theta=0.0, agg=None,
+            strength=None):
     """FP64 oracle R (CSR arrays) plus statistics.  theta: strength threshold
-    of the pattern (0 keeps every stored nonzero).
+    of the pattern (0 keeps every stored nonzero).  strength: an optional n x n
+    CSR (row_ptr, col_idx, val) whose stored entries u -> v are the edges of
+    the neighbourhood search instead of A's (theta then filters its entries);
+    the local systems always use A.
 
     Returns dict(row_ptr, col_idx, val, n_c, nnz, n_uncovered, bad_row).
     """
@@ -122,14 +128,21 @@ def build_R(n, row_ptr, col_idx, val, cf, B, ell, nthreads=0, allow_singular=Fal
     cfa = np.ascontiguousarray(cf, np.int8)
     Ba = None if B is None else np.ascontiguousarray(B, np.float64)
     ag = None if agg is None else np.ascontiguousarray(agg, np.int32)
-    n_c, nnz, _ = pattern_size(n, rp, ci, va, cfa, ell, nthreads, theta=theta, agg=ag)
+    if strength is None:
+        grp, gci, gva = rp, ci, va
+    else:
+        grp = np.ascontiguousarray(strength[0], np.int32)
+        gci = np.ascontiguousarray(strength[1], np.int32)
+        gva = np.ascontiguousarray(strength[2], np.float64)
+    n_c, nnz, _ = pattern_size(n, grp, gci, gva, cfa, ell, nthreads, theta=theta, agg=ag)
     Rrp = np.zeros(n_c + 1, np.int32)
     Rci = np.zeros(max(nnz, 1), np.int32)
     Rva = np.zeros(max(nnz, 1), np.float64)
     unc = ctypes.c_int64(0)
     bad = ctypes.c_int32(-1)
-    rc = lib.orc_build_R(n, _ptr(rp), _ptr(ci), _ptr(va), _ptr(cfa), _ptr(ag), _ptr(Ba), ell, float(theta), nthreads,
-                         _ptr(Rrp), _ptr(Rci), _ptr(Rva), nnz, ctypes.byref(unc), ctypes.byref(bad))
+    rc = lib.orc_build_R_g(n, _ptr(rp), _ptr(ci), _ptr(va), _ptr(grp), _ptr(gci), _ptr(gva), _ptr(cfa), _ptr(ag),
+                           _ptr(Ba), ell, float(theta), nthreads, _ptr(Rrp), _ptr(Rci), _ptr(Rva), nnz,
+                           ctypes.byref(unc), ctypes.byref(bad))
     if rc and not (rc == ORC_ERR_SINGULAR and allow_singular):
         raise OracleError(rc, f"oracle build_R failed ({rc}), bad_row={bad.value}")
     return dict(row_ptr=Rrp, col_idx=Rci[:nnz], val=Rva[:nnz], n_c=n_c, nnz=nnz,

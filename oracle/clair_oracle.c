@@ -259,9 +259,15 @@ static int build_agg_lists(int32_t n, const int8_t* cf, const int32_t* agg, int3
 
 /* Number of C-points and nnz(R) = sum_i (|N(i)| + 1).  Also the per-row sizes
  * when `sizes` (length n_c) is given. */
-int orc_pattern_size(int32_t n, const int32_t* rp, const int32_t* ci, const double* va,
-                     const int8_t* cf, const int32_t* agg, int32_t ell, double theta, int32_t nthreads,
-                     int32_t* n_c_out, int64_t* nnz_out, int32_t* sizes) {
+/* The search runs on the graph G (g_rp, g_ci, g_va: n x n CSR): A itself, or
+   a strength matrix the caller gives, whose stored entries u -> v are the
+   edges (filtered by theta against G's column maxima, as for A). */
+int orc_pattern_size_g(int32_t n, const int32_t* g_rp, const int32_t* g_ci, const double* g_va,
+                       const int8_t* cf, const int32_t* agg, int32_t ell, double theta, int32_t nthreads,
+                       int32_t* n_c_out, int64_t* nnz_out, int32_t* sizes) {
+  const int32_t* rp = g_rp;
+  const int32_t* ci = g_ci;
+  const double* va = g_va;
   if (ell < 1 || !(theta >= 0.0 && theta <= 1.0) || check_csr(n, rp, ci)) return ORC_ERR_INVALID;
   double* cmax = NULL;
   if (theta > 0.0) {
@@ -318,30 +324,52 @@ int orc_pattern_size(int32_t n, const int32_t* rp, const int32_t* ci, const doub
   return ORC_OK;
 }
 
+int orc_pattern_size(int32_t n, const int32_t* rp, const int32_t* ci, const double* va,
+                     const int8_t* cf, const int32_t* agg, int32_t ell, double theta, int32_t nthreads,
+                     int32_t* n_c_out, int64_t* nnz_out, int32_t* sizes) {
+  return orc_pattern_size_g(n, rp, ci, va, cf, agg, ell, theta, nthreads, n_c_out, nnz_out, sizes);
+}
+
 /*
  * Build R.  B may be NULL (unconstrained: plain l-AIR rows, Remark 1).
  * R_rp has n_c+1 entries; R_ci/R_va have `cap` entries.  Statistics (may be
  * NULL): n_uncovered = F-points with d_j = 0 (only when B is given);
  * bad_row = fine index of the first C-row whose local block is singular.
  */
+int orc_build_R_g(int32_t n, const int32_t* rp, const int32_t* ci, const double* va, const int32_t* g_rp,
+                  const int32_t* g_ci, const double* g_va, const int8_t* cf, const int32_t* agg, const double* B,
+                  int32_t ell, double theta, int32_t nthreads, int32_t* R_rp, int32_t* R_ci, double* R_va,
+                  int64_t cap, int64_t* n_uncovered, int32_t* bad_row);
+
 int orc_build_R(int32_t n, const int32_t* rp, const int32_t* ci, const double* va, const int8_t* cf,
                 const int32_t* agg, const double* B, int32_t ell, double theta, int32_t nthreads, int32_t* R_rp,
                 int32_t* R_ci, double* R_va, int64_t cap, int64_t* n_uncovered, int32_t* bad_row) {
-  if (ell < 1 || !(theta >= 0.0 && theta <= 1.0) || check_csr(n, rp, ci)) return ORC_ERR_INVALID;
+  return orc_build_R_g(n, rp, ci, va, rp, ci, va, cf, agg, B, ell, theta, nthreads, R_rp, R_ci, R_va, cap,
+                       n_uncovered, bad_row);
+}
+
+/* The same with the search on the graph G (A, or a strength matrix); the
+   local systems always use A. */
+int orc_build_R_g(int32_t n, const int32_t* rp, const int32_t* ci, const double* va, const int32_t* g_rp,
+                  const int32_t* g_ci, const double* g_va, const int8_t* cf, const int32_t* agg, const double* B,
+                  int32_t ell, double theta, int32_t nthreads, int32_t* R_rp, int32_t* R_ci, double* R_va,
+                  int64_t cap, int64_t* n_uncovered, int32_t* bad_row) {
+  if (ell < 1 || !(theta >= 0.0 && theta <= 1.0) || check_csr(n, rp, ci) || check_csr(n, g_rp, g_ci))
+    return ORC_ERR_INVALID;
   int32_t n_c = 0;
   int64_t nnz = 0;
   for (int32_t j = 0; j < n; ++j) n_c += (cf[j] != 0);
   int32_t* sizes = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_c > 0 ? n_c : 1));
   int32_t* clist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_c > 0 ? n_c : 1));
   if (!sizes || !clist) { free(sizes); free(clist); return ORC_ERR_NOMEM; }
-  int rc = orc_pattern_size(n, rp, ci, va, cf, agg, ell, theta, nthreads, &n_c, &nnz, sizes);
+  int rc = orc_pattern_size_g(n, g_rp, g_ci, g_va, cf, agg, ell, theta, nthreads, &n_c, &nnz, sizes);
   if (rc) { free(sizes); free(clist); return rc; }
   if (nnz > cap) { free(sizes); free(clist); return ORC_ERR_CAPACITY; }
   double* cmax = NULL;
   if (theta > 0.0) {
     cmax = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     if (!cmax) { free(sizes); free(clist); return ORC_ERR_NOMEM; }
-    column_max(n, rp, ci, va, cmax);
+    column_max(n, g_rp, g_ci, g_va, cmax);
   }
   agg_lists ag = {NULL, NULL};
   if (agg) {
@@ -373,7 +401,7 @@ int orc_build_R(int32_t n, const int32_t* rp, const int32_t* ci, const double* v
 #pragma omp for schedule(dynamic, 64)
       for (int32_t r = 0; r < n_c; ++r) {
         int32_t i = clist[r];
-        int32_t s = neighbourhood(i, ell, rp, ci, va, cf, theta, cmax, agg ? &ag : NULL, &w);
+        int32_t s = neighbourhood(i, ell, g_rp, g_ci, g_va, cf, theta, cmax, agg ? &ag : NULL, &w);
         if (s < 0) {
 #pragma omp atomic write
           err = 1;

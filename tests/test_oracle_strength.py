@@ -157,3 +157,46 @@ def test_invalid_theta_rejected():
     for bad in (-0.1, 1.5, float("nan")):
         with pytest.raises(oracle.OracleError):
             oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, None, 2, theta=bad)
+
+
+# --------------------------------------------- a strength matrix as input ---
+def _csr(M):
+    import scipy.sparse as sp
+
+    M = sp.csr_matrix(M)
+    M.sort_indices()
+    return M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64)
+
+
+def test_strength_matrix_equal_to_A_changes_nothing():
+    p = P.small_2d(14, stencil=9, eps=0.05, angle=1.0, k=3, ell=2)
+    a = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell)
+    b = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, strength=(p.row_ptr, p.col_idx, p.val))
+    assert np.array_equal(a["col_idx"], b["col_idx"]) and np.array_equal(a["val"], b["val"])
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_strength_matrix_is_the_search_graph(seed):
+    # a random graph that drops some of A's couplings and adds others: the
+    # pattern is dense reachability on S (F-interiors), the rows still solve
+    # the systems of A on that pattern
+    import scipy.sparse as sp
+
+    p = P.random_sparse(60, 0.06, 10 + seed, ell=2)
+    A = dense.to_dense(p.n, p.row_ptr, p.col_idx, p.val)
+    rng = np.random.default_rng(seed)
+    S = np.where((A != 0) & (rng.random(A.shape) < 0.7), 1.0, 0.0)
+    S += np.where(rng.random(A.shape) < 0.01, 1.0, 0.0)
+    np.fill_diagonal(S, 1.0)
+    srp, sci, sva = _csr(S)
+    got = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, None, p.ell, strength=(srp, sci, sva))
+    nb = dense.neighbourhoods(S, p.cf, p.ell)
+    C = np.nonzero(p.cf)[0]
+    for r, i in enumerate(C):
+        e = np.arange(got["row_ptr"][r], got["row_ptr"][r + 1])
+        cols = got["col_idx"][e]
+        N = np.asarray(nb[int(i)], int)
+        assert np.array_equal(cols[cols != i], N)
+        if len(N):
+            z = np.linalg.solve(A[np.ix_(N, N)].T, -A[i, N])
+            assert np.allclose(got["val"][e][cols != i], z, rtol=0, atol=1e-12 * max(1.0, np.abs(z).max()))
