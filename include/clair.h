@@ -380,6 +380,25 @@ int clair_ctx_get_tuning(clair_ctx_t* ctx, int32_t* group, int32_t* wg_threads, 
  * theta outside [0, 1], or NaN, returns CLAIR_ERR_INVALID and changes nothing.
  */
 int clair_ctx_set_strength(clair_ctx_t* ctx, double theta);
+
+/*
+ * A strength matrix of the caller's as the graph of the neighbourhood search
+ * (Algorithm 1 takes the strength matrix S as an input, Section 3.1.3): one n
+ * x n CSR per matrix of the batches that follow (device arrays, rows sorted,
+ * same n as the matrix; the arrays must stay valid while ctx uses them).  The
+ * search then steps u -> v along S's stored nonzero entries u != v instead of
+ * A's, in A's orientation (row u of S lists the v that u reaches), and theta
+ * filters S's entries against S's column maxima; the local systems always use
+ * A.  nmat = 0 or S = NULL returns to A's graph.  The setting applies to
+ * clair_size_R, clair_build_R / _ex / _batched (both precisions), clair_build_R_agg,
+ * clair_autotune, clair_build_R_approx and clair_build_R_kkt (one matrix),
+ * graphs and plans created after it; a batch whose size or matrix sizes
+ * differ returns CLAIR_ERR_INVALID, and clair_build_P (which would need a
+ * strength matrix of A^T) CLAIR_ERR_UNSUPPORTED.  With opts->validate the
+ * mixed path checks S's order and index range as well; otherwise indices
+ * outside [0, n) are skipped by the search.
+ */
+int clair_ctx_set_graph(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* S);
 int clair_ctx_get_strength(clair_ctx_t* ctx, double* theta);
 int clair_autotune(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf_marker,
                    const double* const* B, const int32_t* ell, clair_csr_out_t* R_out, void* stream,

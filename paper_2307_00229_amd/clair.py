@@ -31,7 +31,7 @@ EXPORTED = [
     "clair_ctx_info", "clair_size_R", "clair_ctx_stage_times", "clair_ctx_set_tuning", "clair_ctx_get_tuning",
     "clair_ctx_set_strength", "clair_ctx_get_strength", "clair_transpose", "clair_build_P",
     "clair_spgemm", "clair_galerkin", "clair_smooth_B", "clair_build_R_agg", "clair_project_constraints",
-    "clair_build_R_diag", "clair_build_R_approx", "clair_build_R_kkt",
+    "clair_build_R_diag", "clair_build_R_approx", "clair_build_R_kkt", "clair_ctx_set_graph",
     "clair_autotune", "clair_graph_create", "clair_graph_launch", "clair_graph_destroy", "clair_graph_info",
     "clair_plan_create", "clair_plan_execute", "clair_plan_info", "clair_plan_destroy",
     "clair_strerror", "clair_last_error",
@@ -130,6 +130,7 @@ def load_library(path: str = LIB_PATH):
                                        ctypes.POINTER(I64), P], ctypes.c_int),
         "clair_build_R_diag": ([P, ctypes.POINTER(CsrIn), P, P, I32, I32, ctypes.POINTER(CsrOut),
                                 ctypes.POINTER(Info), P], ctypes.c_int),
+        "clair_ctx_set_graph": ([P, I32, P], ctypes.c_int),
         "clair_build_R_kkt": ([P, ctypes.POINTER(CsrIn), P, P, I32, ctypes.POINTER(CsrOut), ctypes.POINTER(Info), P],
                               ctypes.c_int),
         "clair_build_R_approx": ([P, ctypes.POINTER(CsrIn), P, P, I32, I32, I32, I32, ctypes.POINTER(CsrOut),
@@ -254,6 +255,20 @@ class Context:
         st = self._lib.clair_ctx_set_strength(self._h, float(theta))
         if st:
             raise ClairError(st, "clair_ctx_set_strength")
+
+    def set_graph(self, graphs):
+        """Strength matrices (CSR, one per matrix of the batches that follow)
+        as the neighbourhood search's graph; None returns to A's graph.  The
+        tensors are kept alive by the context object."""
+        if not graphs:
+            self._graph_keep = None
+            st = self._lib.clair_ctx_set_graph(self._h, 0, None)
+        else:
+            arr = (CsrIn * len(graphs))(*[g.c() for g in graphs])
+            self._graph_keep = (list(graphs), arr)
+            st = self._lib.clair_ctx_set_graph(self._h, len(graphs), arr)
+        if st:
+            raise ClairError(st, "clair_ctx_set_graph")
 
     def get_strength(self) -> float:
         t = ctypes.c_double()

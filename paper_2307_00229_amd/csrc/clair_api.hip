@@ -136,6 +136,7 @@ struct clair_ctx {
   // tuning
   int group = 8;  // lanes per row of the small solver: 1, 4 or 8 (|N| <= 8), 16/32 (|N| <= group)
   double theta = 0.0;  // strength threshold of the neighbourhood search
+  std::vector<clair_csr_t> graph;  // strength matrices of the search, one per matrix (empty: A's graph)
   int binB_max = 32;  // largest block of the last batch whose sizes were read back (9..32)
   int last_maxb = 0;  // the same, unclamped (0: none read back yet)
   int wg_threads = 256;
@@ -264,6 +265,11 @@ int check_args(int32_t nmat, const clair_csr_t* A, const int8_t* const* cf, cons
 int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf,
             const double* const* B, const int32_t* ell, const clair_csr_out_t* R, Batch* b,
             const int32_t* const* agg = nullptr) {
+  if (!c->graph.empty()) {  // the context's strength matrices must match the batch
+    if ((int32_t)c->graph.size() != nmat) return CLAIR_ERR_INVALID;
+    for (int m = 0; m < nmat; ++m)
+      if (c->graph[m].n != A[m].n) return CLAIR_ERR_INVALID;
+  }
   b->nmat = nmat;
   b->nchunks = 0;
   b->n_total = 0;
@@ -330,6 +336,9 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
     d.rp = A[m].row_ptr;
     d.ci = A[m].col_idx;
     d.va = A[m].val;
+    d.grp = c->graph.empty() ? A[m].row_ptr : c->graph[m].row_ptr;
+    d.gci = c->graph.empty() ? A[m].col_idx : c->graph[m].col_idx;
+    d.gva = c->graph.empty() ? A[m].val : c->graph[m].val;
     d.cf = cf[m];
     d.B = B ? B[m] : nullptr;
     d.Rrp = R[m].row_ptr;
@@ -551,7 +560,7 @@ int run_mixed(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* co
 // the C-point list in the workspace (valid until the next plain-form call)
 int run_plain_one(clair_ctx* c, const clair_csr_t& A, const int8_t* cf, const double* B, int ell,
                   clair_csr_out_t* R, hipStream_t s, clair_info_t* info, bool pattern_only = false,
-                  const int32_t** clist_out = nullptr) {
+                  const int32_t** clist_out = nullptr, const clair_csr_t* graph = nullptr) {
   const int n = A.n;
   const int nb = (n + 255) / 256;
   // workspace: blk_cnt[nb+1] clist[n] sizes[n+1] scan_tmp[nb+2] dsum[n] rsum[n] flags[8]
@@ -571,6 +580,9 @@ int run_plain_one(clair_ctx* c, const clair_csr_t& A, const int8_t* cf, const do
   p.rp = A.row_ptr;
   p.ci = A.col_idx;
   p.va = A.val;
+  p.grp = graph ? graph->row_ptr : A.row_ptr;
+  p.gci = graph ? graph->col_idx : A.col_idx;
+  p.gva = graph ? graph->val : A.val;
   p.cf = cf;
   p.B = B;
   p.n = n;
@@ -667,7 +679,9 @@ int run_plain(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* co
   }
   for (int m = 0; m < nmat; ++m) {
     clair_info_t in{};
-    int rc = run_plain_one(c, A[m], cf[m], B ? B[m] : nullptr, ell[m], &R[m], s, &in);
+    if (!c->graph.empty() && ((int32_t)c->graph.size() != nmat || c->graph[m].n != A[m].n)) return CLAIR_ERR_INVALID;
+    int rc = run_plain_one(c, A[m], cf[m], B ? B[m] : nullptr, ell[m], &R[m], s, &in, false, nullptr,
+                           c->graph.empty() ? nullptr : &c->graph[m]);
     if (rc == CLAIR_ERR_HIP || rc == CLAIR_ERR_NOMEM) return rc;
     in.status = rc;
     c->plain_info[m] = in;
@@ -822,6 +836,7 @@ int clair_transpose(clair_ctx_t* c, const clair_csr_t* A, int32_t ncol, clair_cs
 int clair_build_P(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf, const double* B, int32_t ell,
                   clair_csr_out_t* P, const clair_opts_t* o, clair_info_t* info) {
   if (!c || !P || !cf || ell < 1 || ell > 64 || check_csr_args(A)) return CLAIR_ERR_INVALID;
+  if (!c->graph.empty()) return CLAIR_ERR_UNSUPPORTED;  // a strength matrix of A^T would be needed
   if (o && o->precision != CLAIR_PREC_MIXED && o->precision != CLAIR_PREC_FP64) return CLAIR_ERR_INVALID;
   const hipStream_t s = static_cast<hipStream_t>(o ? o->stream : nullptr);
   const int32_t n = A->n;
@@ -1085,7 +1100,8 @@ int clair_build_R_approx(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf,
     // the pattern (strength threshold of the context), no local solves
     clair_info_t in{};
     const int32_t* clist = nullptr;
-    int rc = run_plain_one(c, *A, cf, B, ell, R, s, &in, true, &clist);
+    if (!c->graph.empty() && (c->graph.size() != 1 || c->graph[0].n != A->n)) return CLAIR_ERR_INVALID;
+    int rc = run_plain_one(c, *A, cf, B, ell, R, s, &in, true, &clist, c->graph.empty() ? nullptr : &c->graph[0]);
     if (info) *info = in;
     if (rc) return rc;
     const int32_t n_c = R->n_rows;
@@ -1392,6 +1408,22 @@ int clair_ctx_set_tuning(clair_ctx_t* c, int32_t group, int32_t wg_threads, int3
   return CLAIR_OK;
 }
 
+int clair_ctx_set_graph(clair_ctx_t* c, int32_t nmat, const clair_csr_t* S) {
+  if (!c || nmat < 0) return CLAIR_ERR_INVALID;
+  if (nmat == 0 || !S) {
+    c->graph.clear();
+    return CLAIR_OK;
+  }
+  for (int m = 0; m < nmat; ++m)
+    if (check_csr_args(&S[m])) return CLAIR_ERR_INVALID;
+  try {
+    c->graph.assign(S, S + nmat);
+  } catch (...) {
+    return CLAIR_ERR_NOMEM;
+  }
+  return CLAIR_OK;
+}
+
 int clair_ctx_set_strength(clair_ctx_t* c, double theta) {
   if (!c || !(theta >= 0.0 && theta <= 1.0)) return CLAIR_ERR_INVALID;
   c->theta = theta;
@@ -1487,6 +1519,7 @@ int clair_graph_create(clair_ctx_t* parent, int32_t nmat, const clair_csr_t* A, 
   g->ctx->wg_threads = parent->wg_threads;
   g->ctx->chunk = parent->chunk;
   g->ctx->theta = parent->theta;
+  g->ctx->graph = parent->graph;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   clair_opts_t o{};
   o.stream = stream;
@@ -1570,6 +1603,7 @@ int clair_plan_create(clair_ctx_t* parent, int32_t nmat, const clair_csr_t* A, c
     c->wg_threads = parent->wg_threads;
     c->chunk = parent->chunk;
     c->theta = parent->theta;
+    c->graph = parent->graph;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     Batch& b = pl->b;
     rc = prepare(c, nmat, A, cf, nullptr, ell, R, &b);
@@ -1645,6 +1679,11 @@ int clair_plan_execute(clair_plan_t* pl, int32_t nmat, const clair_csr_t* A, con
     hd[m].rp = A[m].row_ptr;
     hd[m].ci = A[m].col_idx;
     hd[m].va = A[m].val;
+    if (pl->ctx->graph.empty()) {  // the search (workgroup rows re-run it) follows the new A
+      hd[m].grp = A[m].row_ptr;
+      hd[m].gci = A[m].col_idx;
+      hd[m].gva = A[m].val;
+    }
     hd[m].B = B ? B[m] : nullptr;
     hd[m].Rrp = R[m].row_ptr;
     hd[m].Rci = R[m].col_idx;

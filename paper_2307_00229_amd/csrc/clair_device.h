@@ -48,6 +48,12 @@ struct MatDesc {
   const int32_t* agg;
   const int32_t* agg_rp;
   const int32_t* agg_list;
+  // the graph of the neighbourhood search: A itself, or a strength matrix
+  // the caller gives (n x n CSR; its stored entries u -> v are the edges,
+  // theta filters them against its own column maxima)
+  const int32_t* grp;
+  const int32_t* gci;
+  const double* gva;
 };
 
 // Pointers into device (global) memory.  Pointers that kernels load from a
@@ -84,6 +90,9 @@ struct GDesc {
   gptr<const int32_t> agg;
   gptr<const int32_t> agg_rp;
   gptr<const int32_t> agg_list;
+  gptr<const int32_t> grp;
+  gptr<const int32_t> gci;
+  gptr<const double> gva;
 };
 
 __device__ __forceinline__ GDesc gview(const MatDesc& m) {
@@ -108,6 +117,9 @@ __device__ __forceinline__ GDesc gview(const MatDesc& m) {
   g.theta = m.theta;
   g.agg = to_global(m.agg);
   g.agg_rp = to_global(m.agg_rp);
+  g.grp = to_global(m.grp);
+  g.gci = to_global(m.gci);
+  g.gva = to_global(m.gva);
   g.agg_list = to_global(m.agg_list);
   return g;
 }

@@ -142,6 +142,10 @@ struct PlainWork {
   const int32_t* rp;
   const int32_t* ci;
   const double* va;
+  // the graph of the neighbourhood search (A, or a strength matrix)
+  const int32_t* grp;
+  const int32_t* gci;
+  const double* gva;
   const int8_t* cf;
   const double* B;
   int32_t n;

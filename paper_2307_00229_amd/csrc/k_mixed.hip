@@ -317,6 +317,14 @@ __global__ void k_validate(Work w) {
         const int k = d.ci[e];
         bad = (k < 0 || k >= d.n || (e > e0 && k <= d.ci[e - 1]));
       }
+      if (d.grp != d.rp) {  // a strength matrix: sorted rows, indices in range
+        const int g0 = d.grp[r], g1 = d.grp[r + 1];
+        bad = bad || g1 < g0 || g0 < 0 || (r == 0 && g0 != 0);
+        for (int e = g0; e < g1 && !bad; ++e) {
+          const int k = d.gci[e];
+          bad = (k < 0 || k >= d.n || (e > g0 && k <= d.gci[e - 1]));
+        }
+      }
       if (bad) flag_row(&w.st[m], ST_INVALID, r);
     }
   }
@@ -382,13 +390,14 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
     // a row of seven or more entries (six or more neighbours) at ell >= 2
     // nearly always reaches more than 8 points: it goes straight to the
     // 32-point search below (either search gives the same set)
-    if (!d.agg_rp && d.ell >= 2 && d.rp[s_rows[t] + 1] - d.rp[s_rows[t]] >= 7) {
+    if (!d.agg_rp && d.ell >= 2 && d.grp[s_rows[t] + 1] - d.grp[s_rows[t]] >= 7) {
       s_size[t] = -1;
       s_list[atomicAdd(&s_nlist, 1)] = t;
       continue;
     }
     RegSet<8> S;
-    const int sz = reg_bfs(S, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf, d.theta, d.cmax, d.agg_rp, d.agg_list);
+    const int sz = reg_bfs(S, d.n, s_rows[t], d.ell, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax, d.agg_rp,
+                           d.agg_list);
     if (sz >= 0) {
       s_size[t] = sz;
       ++inA;  // sz <= 8 <= lim
@@ -411,7 +420,7 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
     for (int k = tid; k < nl2; k += kNT) {
       const int t = s_list[k];
       RegSetM<32> S;
-      const int sz = regm_bfs(S, d.n, s_rows[t], d.ell, d.rp, d.ci, d.va, d.cf, d.theta, d.cmax, d.agg_rp,
+      const int sz = regm_bfs(S, d.n, s_rows[t], d.ell, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax, d.agg_rp,
                               d.agg_list);
       if (sz < 0) {
         s_size[t] = 0;
@@ -490,7 +499,7 @@ __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
     const int64_t base = d.fine0 + (int64_t)(c - d.chunk0) * w.chunk;
     const int i = -w.clocal[base + t] - 1;
     int* nl;
-    const int s = block_bfs(d.n, i, d.ell, d.rp, d.ci, d.va, d.cf, d.theta, d.cmax, d.agg_rp, d.agg_list, bb, &nl);
+    const int s = block_bfs(d.n, i, d.ell, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax, d.agg_rp, d.agg_list, bb, &nl);
     __syncthreads();
     if (tid == 0) {
       w.big_size[base + t] = s < 0 ? 0 : s;
@@ -1819,7 +1828,8 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
       const int i = ri.i;
       if (tid == 0) d.Rrp[ri.r] = ri.off;
       int* N;
-      const int s = block_bfs(d.n, i, d.ell, d.rp, d.ci, d.va, d.cf, d.theta, d.cmax, d.agg_rp, d.agg_list, bb, &N);
+      const int s = block_bfs(d.n, i, d.ell, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax, d.agg_rp, d.agg_list, bb,
+                              &N);
       __syncthreads();
       if (s != ri.s) {
         if (tid == 0) flag_row(st, s < 0 ? ST_UNSUPPORTED : ST_INVALID, i);
@@ -2069,11 +2079,11 @@ __global__ void k_colmax(Work w, int64_t n_total) {
     const GDesc d = gview(w.desc[lo]);
     if (d.theta == 0.0 || !matrix_live(w.st[lo])) continue;
     const int u = (int)(g - d.fine0);
-    for (int e = d.rp[u]; e < d.rp[u + 1]; ++e) {
-      const int v = d.ci[e];
+    for (int e = d.grp[u]; e < d.grp[u + 1]; ++e) {  // column maxima of the search graph
+      const int v = d.gci[e];
       if (v == u || (unsigned)v >= (unsigned)d.n) continue;
       atomicMax(reinterpret_cast<unsigned long long*>(w.cmax + d.fine0 + v),
-                (unsigned long long)__double_as_longlong(fabs(d.va[e])));
+                (unsigned long long)__double_as_longlong(fabs(d.gva[e])));
     }
   }
 }

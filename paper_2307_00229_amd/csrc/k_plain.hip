@@ -35,10 +35,10 @@ __device__ int plain_bfs(const PlainWork& p, int i, int* N) {
     const int uhi = (depth == 1) ? 1 : hi;
     for (int t = ulo; t < uhi; ++t) {
       const int u = (depth == 1) ? i : N[t];
-      for (int e = p.rp[u]; e < p.rp[u + 1]; ++e) {
-        const int k = p.ci[e];
-        if (k == u || p.va[e] == 0.0 || p.cf[k] != 0) continue;
-        if (p.theta != 0.0 && !(fabs(p.va[e]) >= p.theta * p.cmax[k])) continue;  // strength of A^T
+      for (int e = p.grp[u]; e < p.grp[u + 1]; ++e) {  // the search graph: A or a strength matrix
+        const int k = p.gci[e];
+        if (k == u || (unsigned)k >= (unsigned)p.n || p.gva[e] == 0.0 || p.cf[k] != 0) continue;
+        if (p.theta != 0.0 && !(fabs(p.gva[e]) >= p.theta * p.cmax[k])) continue;  // strength of A^T
         bool seen = false;
         for (int q = 0; q < s && !seen; ++q) seen = (N[q] == k);
         if (seen) continue;
@@ -69,11 +69,11 @@ __global__ void k_p_colmax_clear(PlainWork p) {
 __global__ void k_p_colmax(PlainWork p) {
   const int u = blockIdx.x * kPT + threadIdx.x;
   if (u >= p.n) return;
-  for (int e = p.rp[u]; e < p.rp[u + 1]; ++e) {
-    const int v = p.ci[e];
+  for (int e = p.grp[u]; e < p.grp[u + 1]; ++e) {
+    const int v = p.gci[e];
     if (v != u && (unsigned)v < (unsigned)p.n)
       atomicMax(reinterpret_cast<unsigned long long*>(p.cmax + v),
-                          (unsigned long long)__double_as_longlong(fabs(p.va[e])));
+                          (unsigned long long)__double_as_longlong(fabs(p.gva[e])));
   }
 }
 
