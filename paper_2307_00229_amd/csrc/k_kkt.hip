@@ -156,13 +156,14 @@ __global__ __launch_bounds__(kQT) void k_q_rhs(int n, int n_rows, const int32_t*
 // every other point holds 0
 __global__ __launch_bounds__(kQT) void k_q_rhs_fin(int n, const int8_t* __restrict__ cf,
                                                   const double* __restrict__ B, const int32_t* __restrict__ cnt,
-                                                  double* rhs, double* res, double* p, double* x) {
+                                                  double* rhs, double* res, double* p, double* x, double* Ap) {
   for (int j = blockIdx.x * kQT + threadIdx.x; j < n; j += gridDim.x * kQT) {
     const double v = (cf[j] == 0 && cnt[j] > 0) ? rhs[j] - B[j] : 0.0;
     rhs[j] = v;
     res[j] = v;
     p[j] = v;
     x[j] = 0.0;
+    Ap[j] = 0.0;
   }
 }
 
@@ -237,16 +238,15 @@ __global__ void k_q_scalars(double* sc, int32_t* done, int32_t* steps) {
   sc[2] = 0.0;
 }
 
+// p = res + beta p, and Ap cleared for the next step's product
 __global__ __launch_bounds__(kQT) void k_q_dir(int n, const double* __restrict__ sc, const double* __restrict__ res,
-                                              double* p, const int32_t* __restrict__ done) {
+                                              double* p, double* Ap, const int32_t* __restrict__ done) {
   if (*done) return;
   const double beta = sc[4];
-  for (int j = blockIdx.x * kQT + threadIdx.x; j < n; j += gridDim.x * kQT) p[j] = res[j] + beta * p[j];
-}
-
-__global__ __launch_bounds__(kQT) void k_q_zero(int n, double* y, const int32_t* __restrict__ done) {
-  if (*done) return;
-  for (int j = blockIdx.x * kQT + threadIdx.x; j < n; j += gridDim.x * kQT) y[j] = 0.0;
+  for (int j = blockIdx.x * kQT + threadIdx.x; j < n; j += gridDim.x * kQT) {
+    p[j] = res[j] + beta * p[j];
+    Ap[j] = 0.0;
+  }
 }
 
 // z_ij -= B_i (Abar^{-1} lambda|_N)_j
@@ -291,21 +291,20 @@ hipError_t launch_kkt_setup(const KktWork& w, hipStream_t s) {
   }
   if (w.n > 0)
     hipLaunchKernelGGL(k_q_rhs_fin, dim3(qgrid(w.n, w.cus)), dim3(kQT), 0, s, w.n, w.cf, w.B, w.cnt, w.rhs, w.res,
-                       w.p, w.x);
+                       w.p, w.x, w.Ap);
   return hipGetLastError();
 }
 
 hipError_t launch_kkt_dot(const KktWork& w, const double* x, const double* y, double* out, hipStream_t s) {
   if (w.n > 0)
-    hipLaunchKernelGGL(k_q_dot, dim3(std::max(1, std::min((w.n + kQT - 1) / kQT, w.cus * 4))), dim3(kQT), 0, s,
-                       w.n, x, y, out, w.done);
+    hipLaunchKernelGGL(k_q_dot, dim3(std::max(1, std::min((w.n + kQT - 1) / kQT, w.cus))), dim3(kQT), 0, s, w.n, x,
+                       y, out, w.done);  // one workgroup per CU: few atomics on the one sum
   return hipGetLastError();
 }
 
 hipError_t launch_kkt_step(const KktWork& w, hipStream_t s) {
   if (w.n <= 0) return hipSuccess;
   const int g = qgrid(w.n, w.cus);
-  hipLaunchKernelGGL(k_q_zero, dim3(g), dim3(kQT), 0, s, w.n, w.Ap, w.done);
   if (w.n_rows > 0)
     hipLaunchKernelGGL(k_q_matvec, dim3(qgrid(w.n_rows, w.cus)), dim3(kQT), 0, s, w.n_rows, w.Rrp, w.Rci, w.rowc,
                        w.L, w.smax, w.T, w.B, w.p, w.Ap, w.done);
@@ -315,7 +314,7 @@ hipError_t launch_kkt_step(const KktWork& w, hipStream_t s) {
   e = launch_kkt_dot(w, w.res, w.res, w.sc + 2, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_q_scalars, dim3(1), dim3(1), 0, s, w.sc, w.done, w.steps);
-  hipLaunchKernelGGL(k_q_dir, dim3(g), dim3(kQT), 0, s, w.n, w.sc, w.res, w.p, w.done);
+  hipLaunchKernelGGL(k_q_dir, dim3(g), dim3(kQT), 0, s, w.n, w.sc, w.res, w.p, w.Ap, w.done);
   return hipGetLastError();
 }
 
