@@ -84,3 +84,17 @@ def test_without_B_is_the_unconstrained_build():
     ex, infos, st = gpu_build([dataclasses.replace(p, B=None)])
     assert st == 0, infos
     assert np.array_equal(g["val"], ex[0]["val"])
+
+
+@pytest.mark.parametrize("idx", range(4))
+def test_degenerate_inputs(idx):
+    # no C-points, all C-points, a C-point with no F-neighbour, n = 0
+    from .test_oracle_approx import _edge_problems
+
+    p = _edge_problems()[idx]
+    print(f"[gpu] kkt degenerate {p.name} n={p.n}", flush=True)
+    g, _ = _gpu_kkt(p, p.B)
+    o = kkt.kkt_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell)
+    assert g["n_c"] == o["n_c"]
+    assert np.array_equal(g["row_ptr"], o["row_ptr"]) and np.array_equal(g["col_idx"], o["col_idx"])
+    assert np.allclose(g["val"], o["val"], rtol=0, atol=1e-14)
