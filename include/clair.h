@@ -255,7 +255,10 @@ int clair_build_R_diag(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_
  * CSR in, sorted CSR out; values copied exactly).  AT_out: n_rows = ncol,
  * n_cols = A->n, nnz = A->nnz are set; with too small capacities (row_ptr
  * needs ncol + 1 entries) nothing else is written and CLAIR_ERR_CAPACITY is
- * returned.  A column index outside [0, ncol) returns CLAIR_ERR_INVALID.
+ * returned.  A column index outside [0, ncol), or A->row_ptr[0] != 0 or
+ * A->row_ptr[A->n] != A->nnz (read from the device), returns
+ * CLAIR_ERR_INVALID; the calls built on the transpose (clair_build_P,
+ * clair_smooth_B on A^T, clair_build_R_approx) check the same.
  * Synchronises `stream`.
  */
 int clair_transpose(clair_ctx_t* ctx, const clair_csr_t* A, int32_t ncol, clair_csr_out_t* AT_out, void* stream);
@@ -332,9 +335,9 @@ int clair_smooth_B(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_mark
  *   k          1 <= k <= 4
  * Row q of R belongs to the q-th C-point; n_rows must equal the number of
  * C-points.  *n_uncovered (may be NULL): F-points no row reaches (left
- * unchanged).  A column index outside [0, n), or a row count that differs
- * from the number of C-points, gives CLAIR_ERR_INVALID (R may then be partly
- * updated).  Deterministic: every column is summed in ascending row order.
+ * unchanged).  A column index outside [0, n), a row count that differs
+ * from the number of C-points, or R's row_ptr[0] != 0 or row_ptr[n_rows] !=
+ * nnz gives CLAIR_ERR_INVALID (R may then be partly updated).  Deterministic: every column is summed in ascending row order.
  * Synchronises `stream`.
  */
 int clair_project_constraints(clair_ctx_t* ctx, clair_csr_out_t* R, int32_t n, const int8_t* cf_marker,

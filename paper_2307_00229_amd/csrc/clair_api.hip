@@ -797,8 +797,20 @@ int clair_build_R(const clair_csr_t* A, const int8_t* cf, const double* B, int32
 namespace {
 
 // B = A^T (A: m x ncol) into device arrays of sufficient size; synchronous
+// row_ptr[0] == 0 and row_ptr[m] == nnz on the device (the buffers that
+// follow are sized from nnz, the kernels follow row_ptr); synchronous
+int check_row_ptr_ends(const int32_t* rp, int32_t m, int64_t nnz, hipStream_t s) {
+  if (m <= 0) return nnz == 0 ? CLAIR_OK : CLAIR_ERR_INVALID;
+  int32_t ends[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(&ends[0], rp, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&ends[1], rp + m, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return (ends[0] == 0 && (int64_t)ends[1] == nnz) ? CLAIR_OK : CLAIR_ERR_INVALID;
+}
+
 int transpose_into(clair_ctx* c, const clair_csr_t& A, int32_t ncol, int32_t* trp, int32_t* tci, double* tva,
                    hipStream_t s) {
+  if (int rc = check_row_ptr_ends(A.row_ptr, A.n, A.nnz, s)) return rc;
   const size_t ints = transpose_scratch_ints(ncol);
   HIPCHK(c->t_scratch.ensure(sizeof(int32_t) * ints));
   int32_t* scr = static_cast<int32_t*>(c->t_scratch.p);
@@ -1042,6 +1054,7 @@ int clair_project_constraints(clair_ctx_t* c, clair_csr_out_t* R, int32_t n, con
   if (n > 0 && (!cf || !B)) return CLAIR_ERR_INVALID;
   if (R->n_rows > 0 && (!R->row_ptr || (R->nnz > 0 && (!R->col_idx || !R->val)))) return CLAIR_ERR_INVALID;
   const hipStream_t s = static_cast<hipStream_t>(stream);
+  if (int rc = check_row_ptr_ends(R->row_ptr, R->n_rows, R->nnz, s)) return rc;
   const size_t nn = (size_t)n, nr = (size_t)R->n_rows, nz = (size_t)std::max<int64_t>(1, R->nnz);
   try {
     // one allocation, 256-byte aligned pieces

@@ -230,3 +230,17 @@ def test_degenerate_inputs(idx):
     o = oracle.project_constraints(oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, None, p.ell), p.cf, B)
     assert g["n_uncovered"] == o["n_uncovered"]
     assert np.allclose(g["val"], o["val"], rtol=0, atol=1e-14)
+
+
+def test_rejects_nnz_that_disagrees_with_row_ptr():
+    from paper_2307_00229_amd import clair
+
+    p = CASES[0]()
+    g = _unconstrained(p)
+    R = (torch.from_numpy(g["row_ptr"]).cuda(),
+         torch.from_numpy(np.concatenate([g["col_idx"], [0]]).astype(np.int32)).cuda(),
+         torch.from_numpy(np.concatenate([g["val"], [0.0]])).cuda())
+    with pytest.raises(clair.ClairError) as ei:
+        clair.clair_project_constraints(R, p.n, torch.from_numpy(p.cf).cuda(),
+                                        torch.ones(p.n, 2, dtype=torch.float64, device="cuda"))
+    assert ei.value.status == clair.CLAIR_ERR_INVALID

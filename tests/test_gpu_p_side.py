@@ -137,3 +137,18 @@ def test_build_P_capacity_and_bad_arguments():
     assert st == clair.CLAIR_ERR_CAPACITY and probe.n_rows == p.n and probe.nnz > 0
     st = lib.clair_build_P(ctx.handle, A.c(), cf.data_ptr(), None, 0, probe, None, info)
     assert st == clair.CLAIR_ERR_INVALID
+
+
+def test_transpose_rejects_nnz_that_disagrees_with_row_ptr():
+    # output buffers are sized from nnz and the kernels follow row_ptr: the
+    # two must agree
+    from paper_2307_00229_amd import clair
+
+    M = sp.random(50, 40, density=0.1, random_state=5, format="csr")
+    M.sort_indices()
+    rp = torch.from_numpy(M.indptr.astype(np.int32)).cuda()
+    ci = torch.from_numpy(np.concatenate([M.indices, [0, 1, 2]]).astype(np.int32)).cuda()
+    va = torch.from_numpy(np.concatenate([M.data, [1.0, 2.0, 3.0]])).cuda()
+    with pytest.raises(clair.ClairError) as ei:
+        clair.clair_transpose(clair.CSR(rp, ci, va, n=50), 40)
+    assert ei.value.status == clair.CLAIR_ERR_INVALID
