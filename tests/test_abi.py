@@ -12,6 +12,16 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "clair.h")
 
 
+@pytest.fixture(scope="module", autouse=True)
+def _library_built():
+    """Build libclair.so with hipcc if this tree has none yet (a fresh
+    checkout: the library is not kept in version control)."""
+    from paper_2307_00229_amd import build
+
+    if not os.path.exists(build.LIB):
+        build.build()
+
+
 def _declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
