@@ -245,3 +245,44 @@ def test_strength_matrix_checks():
     ctx.set_graph(None)
     _, infos, st = gpu_build([p], ctx=ctx)
     assert st == 0
+
+
+def test_strength_matrix_graph_replay_and_plan():
+    # graphs and plans created after clair_ctx_set_graph search the strength
+    # matrices; replays and plan executes match the oracle on that graph
+    from paper_2307_00229_amd import clair
+
+    ps = _mixed_cases()[:3]
+    graphs = [_random_graph(p, 21 + k) for k, p in enumerate(ps)]
+    refs = [oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, strength=g) for p, g in zip(ps, graphs)]
+    As, cfs, Bs, ells = to_device(ps)
+    ctx = clair.Context()
+    ctx.set_graph([_dev_csr(*g, n=p.n) for g, p in zip(graphs, ps)])
+    eager, _, st = clair.clair_build_R_batched(As, cfs, Bs, ells, ctx=ctx)
+    assert st == 0
+    outs = [clair.ROut(o.n_c, o.nnz) for o in eager]
+    s = torch.cuda.Stream()
+    g = clair.Graph(ctx, As, cfs, Bs, ells, outs, stream=s)
+    for _ in range(3):
+        for o in outs:
+            o.val.fill_(-7.0)
+        torch.cuda.synchronize()
+        g.launch(s)
+        s.synchronize()
+        st, infos = g.info()
+        assert st == 0, infos
+        clair.clair_build_R_batched(As, cfs, Bs, ells, ctx=ctx)  # eager work between replays
+        for p, o, inf, ref in zip(ps, outs, infos, refs):
+            rp, ci, va = o.trimmed()
+            gres = dict(row_ptr=rp.cpu().numpy(), col_idx=ci.cpu().numpy(), val=va.cpu().numpy(),
+                        n_c=o.n_c, nnz=o.nnz)
+            assert_matches_oracle(p, gres, ref, inf)
+    g.close()
+    plan = clair.Plan(ctx, As, cfs, ells, outs)
+    infos, st = plan.execute(As, Bs)
+    assert st == 0
+    for p, o, inf, ref in zip(ps, outs, infos, refs):
+        rp, ci, va = o.trimmed()
+        gres = dict(row_ptr=rp.cpu().numpy(), col_idx=ci.cpu().numpy(), val=va.cpu().numpy(), n_c=o.n_c, nnz=o.nnz)
+        assert_matches_oracle(p, gres, ref, inf)
+    plan.close()
