@@ -162,14 +162,16 @@ def build_R_diag(n, row_ptr, col_idx, val, cf, B, ell, iterations, theta=0.0, ag
     return build_R_approx(n, row_ptr, col_idx, val, cf, B, ell, iterations, "diag", theta=theta, agg=agg)
 
 
-def build_R_approx(n, row_ptr, col_idx, val, cf, B, ell, iterations, inverse, theta=0.0, agg=None, krylov=0):
+def build_R_approx(n, row_ptr, col_idx, val, cf, B, ell, iterations, inverse, theta=0.0, agg=None, krylov=0,
+                   strength=None):
     """Algorithm 1 with approximate block inverses ("diag": the diagonal of
     each block; "ilu0": its incomplete LU factorisation without fill;
     "gmres": `krylov` steps of GMRES on each local system from zero) and
     `iterations` steps, on the pattern of the exact build (the pattern does
     not depend on the inverse).  Returns the same dict as build_R."""
     lib = _load()
-    o = build_R(n, row_ptr, col_idx, val, cf, None, ell, allow_singular=True, theta=theta, agg=agg)
+    o = build_R(n, row_ptr, col_idx, val, cf, None, ell, allow_singular=True, theta=theta, agg=agg,
+                strength=strength)
     rp = np.ascontiguousarray(row_ptr, np.int32)
     ci = np.ascontiguousarray(col_idx, np.int32)
     va = np.ascontiguousarray(val, np.float64)

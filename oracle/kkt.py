@@ -25,11 +25,11 @@ import scipy.sparse.linalg as spla
 from . import build_R
 
 
-def kkt_R(n, row_ptr, col_idx, val, cf, B, ell, theta=0.0):
+def kkt_R(n, row_ptr, col_idx, val, cf, B, ell, theta=0.0, strength=None):
     """R (dict as build_R returns) minimising the normal-equations energy
     under R^T B_c = B; also "lam" (n entries, 0 off the covered F-points) and
     "energy" (sum_i |a_i + K_i z_i|^2)."""
-    o = build_R(n, row_ptr, col_idx, val, cf, None, ell, theta=theta)
+    o = build_R(n, row_ptr, col_idx, val, cf, None, ell, theta=theta, strength=strength)
     A = sp.csr_matrix((np.asarray(val, np.float64), np.asarray(col_idx), np.asarray(row_ptr)), shape=(n, n))
     cfa = np.asarray(cf)
     C = np.nonzero(cfa)[0]

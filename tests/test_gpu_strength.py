@@ -286,3 +286,35 @@ def test_strength_matrix_graph_replay_and_plan():
         gres = dict(row_ptr=rp.cpu().numpy(), col_idx=ci.cpu().numpy(), val=va.cpu().numpy(), n_c=o.n_c, nnz=o.nnz)
         assert_matches_oracle(p, gres, ref, inf)
     plan.close()
+
+
+def test_strength_matrix_in_the_approximate_and_kkt_builds():
+    from oracle import kkt
+
+    from paper_2307_00229_amd import clair
+
+    from ._util import row_errors
+
+    p = P.small_2d(30, stencil=9, eps=0.05, angle=1.0, k=3, ell=2)
+    gr = _random_graph(p, 33)
+    ctx = clair.Context()
+    ctx.set_graph([_dev_csr(*gr, n=p.n)])
+    A = clair.CSR.from_problem(p, "cuda")
+    cf = torch.from_numpy(p.cf).cuda()
+    B = torch.from_numpy(p.B).cuda()
+
+    def as_dict(out, info):
+        rp, ci, va = out
+        return dict(row_ptr=rp.cpu().numpy(), col_idx=ci.cpu().numpy(), val=va.cpu().numpy(), n_c=info["n_c"],
+                    nnz=info["nnz"])
+
+    out, info, _ = clair.clair_build_R_approx(A, cf, B, p.ell, 2, inverse=clair.CLAIR_INVERSE_ILU0, ctx=ctx)
+    g = as_dict(out, info)
+    o = oracle.build_R_approx(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, 2, "ilu0", strength=gr)
+    assert np.array_equal(g["col_idx"], o["col_idx"])
+    assert row_errors(p, g, o)[0].max() <= 1e-10
+    out, info, _ = clair.clair_build_R_kkt(A, cf, B, p.ell, ctx=ctx)
+    g = as_dict(out, info)
+    o = kkt.kkt_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, strength=gr)
+    assert np.array_equal(g["col_idx"], o["col_idx"])
+    assert row_errors(p, g, o)[0].max() <= 1e-10
