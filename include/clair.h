@@ -332,7 +332,7 @@ int clair_smooth_B(clair_ctx_t* ctx, const clair_csr_t* A, const int8_t* cf_mark
  *              values are updated
  *   n, cf      fine size and the C/F marker R was built with
  *   B          device float64[n * k], row-major (B[j * k + t])
- *   k          1 <= k <= 4
+ *   k          1 <= k <= 8
  * Row q of R belongs to the q-th C-point; n_rows must equal the number of
  * C-points.  *n_uncovered (may be NULL): F-points no row reaches (left
  * unchanged).  A column index outside [0, n), a row count that differs

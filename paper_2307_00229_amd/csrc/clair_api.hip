@@ -1049,7 +1049,7 @@ int clair_smooth_B(clair_ctx_t* c, const clair_csr_t* A, const int8_t* cf, const
 
 int clair_project_constraints(clair_ctx_t* c, clair_csr_out_t* R, int32_t n, const int8_t* cf, const double* B,
                               int32_t k, double rcond, int64_t* n_uncovered, void* stream) {
-  if (!c || !R || n < 0 || k < 1 || k > 4 || !(rcond >= 0.0) || R->n_rows < 0 || R->nnz < 0) return CLAIR_ERR_INVALID;
+  if (!c || !R || n < 0 || k < 1 || k > 8 || !(rcond >= 0.0) || R->n_rows < 0 || R->nnz < 0) return CLAIR_ERR_INVALID;
   if (R->nnz > INT32_MAX) return CLAIR_ERR_UNSUPPORTED;
   if (n > 0 && (!cf || !B)) return CLAIR_ERR_INVALID;
   if (R->n_rows > 0 && (!R->row_ptr || (R->nnz > 0 && (!R->col_idx || !R->val)))) return CLAIR_ERR_INVALID;

@@ -13,8 +13,9 @@
 // the k x k system in registers (Jacobi eigen-decomposition; eigenvalues at or
 // below rcond times the largest are dropped), one thread per row of R applies
 // the update.  The row -> C-point map comes from a scan of the C/F marker.
-// B is n x k, row-major; k <= 4 (a template parameter, so the per-thread
-// arrays stay in registers).
+// B is n x k, row-major; k <= 8, a template parameter: up to 4 the k x k
+// matrices of a thread stay in registers, from 5 to 8 they live in LDS (64
+// threads per workgroup, thread index fastest, so the banks do not clash).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -156,6 +157,99 @@ __global__ __launch_bounds__(kKT) void k_pk_solve(int n, int n_rows, double rcon
   }
 }
 
+// the same for K = 5..8 with the two K x K matrices of each thread in LDS
+constexpr int kKL = 64;
+template <int K>
+__global__ __launch_bounds__(kKL) void k_pk_solve_lds(int n, int n_rows, double rcond, const int8_t* __restrict__ cf,
+                                                     const double* __restrict__ B, const int32_t* __restrict__ trp,
+                                                     const int32_t* __restrict__ tci, const double* __restrict__ tva,
+                                                     const int32_t* __restrict__ rowc, double* lam,
+                                                     unsigned long long* uncovered) {
+  __shared__ double sa[K * K * kKL], sv[K * K * kKL];
+  const int tid = threadIdx.x;
+  auto a = [&](int p, int q) -> double& { return sa[(p * K + q) * kKL + tid]; };
+  auto v = [&](int p, int q) -> double& { return sv[(p * K + q) * kKL + tid]; };
+  for (int j = blockIdx.x * kKL + tid; j < n; j += gridDim.x * kKL) {
+    if (cf[j] != 0) continue;
+    double rhs[K];
+    for (int p = 0; p < K; ++p) {
+      rhs[p] = 0.0;
+      for (int q = 0; q < K; ++q) {
+        a(p, q) = 0.0;
+        v(p, q) = p == q ? 1.0 : 0.0;
+      }
+    }
+    int used = 0;
+    for (int e = trp[j]; e < trp[j + 1]; ++e) {
+      const int q = tci[e];
+      const int i = (unsigned)q < (unsigned)n_rows ? rowc[q] : -1;
+      if (i < 0) continue;
+      ++used;
+      const double z = tva[e];
+      for (int p = 0; p < K; ++p) {
+        const double bp = B[(int64_t)i * K + p];
+        rhs[p] += z * bp;
+        for (int t = p; t < K; ++t) a(p, t) += bp * B[(int64_t)i * K + t];
+      }
+    }
+    if (used == 0) {
+      atomicAdd(uncovered, 1ull);
+      for (int p = 0; p < K; ++p) lam[(int64_t)j * K + p] = 0.0;
+      continue;
+    }
+    for (int p = 0; p < K; ++p) {
+      rhs[p] -= B[(int64_t)j * K + p];
+      for (int t = 0; t < p; ++t) a(p, t) = a(t, p);
+    }
+    for (int sweep = 0; sweep < 30; ++sweep) {
+      double off = 0.0, on = 0.0;
+      for (int p = 0; p < K; ++p) {
+        on += a(p, p) * a(p, p);
+        for (int q = p + 1; q < K; ++q) off += a(p, q) * a(p, q);
+      }
+      if (!(off > 1e-40 * on)) break;
+      for (int p = 0; p < K; ++p) {
+        for (int q = p + 1; q < K; ++q) {
+          const double apq = a(p, q);
+          const double h = (a(q, q) - a(p, p)) / (2.0 * (apq != 0.0 ? apq : 1.0));
+          double t = copysign(1.0, h) / (fabs(h) + sqrt(h * h + 1.0));
+          if (apq == 0.0) t = 0.0;
+          const double c = rsqrt(t * t + 1.0), sn = t * c;
+          for (int m = 0; m < K; ++m) {
+            const double x = a(m, p), y = a(m, q);
+            a(m, p) = c * x - sn * y;
+            a(m, q) = sn * x + c * y;
+          }
+          for (int m = 0; m < K; ++m) {
+            const double x = a(p, m), y = a(q, m);
+            a(p, m) = c * x - sn * y;
+            a(q, m) = sn * x + c * y;
+          }
+          a(p, q) = 0.0;
+          a(q, p) = 0.0;
+          for (int m = 0; m < K; ++m) {
+            const double x = v(m, p), y = v(m, q);
+            v(m, p) = c * x - sn * y;
+            v(m, q) = sn * x + c * y;
+          }
+        }
+      }
+    }
+    double wmax = 0.0;
+    for (int p = 0; p < K; ++p) wmax = fmax(wmax, fabs(a(p, p)));
+    double l[K];
+    for (int p = 0; p < K; ++p) l[p] = 0.0;
+    for (int m = 0; m < K; ++m) {
+      const double wm = a(m, m);
+      if (!(fabs(wm) > rcond * wmax)) continue;
+      double proj = 0.0;
+      for (int p = 0; p < K; ++p) proj += v(p, m) * rhs[p];
+      for (int p = 0; p < K; ++p) l[p] += v(p, m) * proj / wm;
+    }
+    for (int p = 0; p < K; ++p) lam[(int64_t)j * K + p] = l[p];
+  }
+}
+
 // z_ij -= B_i^T lambda_j on the F-entries of every row
 template <int K>
 __global__ __launch_bounds__(kKT) void k_pk_apply(int n, int n_rows, const int32_t* __restrict__ rp,
@@ -184,9 +278,15 @@ int kgrid(int m, int cus) { return std::max(1, std::min((m + kKT - 1) / kKT, cus
 template <int K>
 void launch_k(int n, int n_rows, const int32_t* rp, const int32_t* ci, double* va, const int8_t* cf, const double* B,
               double rcond, const ProjectScratch& w, unsigned long long* uncovered, int cus, hipStream_t s) {
-  if (n > 0)
-    hipLaunchKernelGGL(k_pk_solve<K>, dim3(kgrid(n, cus)), dim3(kKT), 0, s, n, n_rows, rcond, cf, B, w.trp, w.tci,
-                       w.tva, w.rowc, w.lam, uncovered);
+  if constexpr (K <= 4) {
+    if (n > 0)
+      hipLaunchKernelGGL(k_pk_solve<K>, dim3(kgrid(n, cus)), dim3(kKT), 0, s, n, n_rows, rcond, cf, B, w.trp, w.tci,
+                         w.tva, w.rowc, w.lam, uncovered);
+  } else {
+    if (n > 0)
+      hipLaunchKernelGGL(k_pk_solve_lds<K>, dim3(std::max(1, std::min((n + kKL - 1) / kKL, cus * 16))), dim3(kKL), 0,
+                         s, n, n_rows, rcond, cf, B, w.trp, w.tci, w.tva, w.rowc, w.lam, uncovered);
+  }
   if (n_rows > 0)
     hipLaunchKernelGGL(k_pk_apply<K>, dim3(kgrid(n_rows, cus)), dim3(kKT), 0, s, n, n_rows, rp, ci, va, cf, B, w.rowc,
                        w.lam);
@@ -214,6 +314,10 @@ hipError_t launch_project_k(int n, int n_rows, const int32_t* rp, const int32_t*
     case 2: launch_k<2>(n, n_rows, rp, ci, va, cf, B, rcond, w, uncovered, cus, s); break;
     case 3: launch_k<3>(n, n_rows, rp, ci, va, cf, B, rcond, w, uncovered, cus, s); break;
     case 4: launch_k<4>(n, n_rows, rp, ci, va, cf, B, rcond, w, uncovered, cus, s); break;
+    case 5: launch_k<5>(n, n_rows, rp, ci, va, cf, B, rcond, w, uncovered, cus, s); break;
+    case 6: launch_k<6>(n, n_rows, rp, ci, va, cf, B, rcond, w, uncovered, cus, s); break;
+    case 7: launch_k<7>(n, n_rows, rp, ci, va, cf, B, rcond, w, uncovered, cus, s); break;
+    case 8: launch_k<8>(n, n_rows, rp, ci, va, cf, B, rcond, w, uncovered, cus, s); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
