@@ -90,3 +90,24 @@ def test_fp64_form_rejects_aggregates():
     o = clair.Opts(None, clair.CLAIR_PREC_FP64, 0, 0, 0)
     st = lib.clair_build_R_agg(clair.Context().handle, 1, Ac, cfp, aggp, Bp, ellv, Rc, ctypes.byref(o), None)
     assert st == clair.CLAIR_ERR_UNSUPPORTED
+
+
+def test_aggregation_with_a_strength_matrix():
+    # aggregates give T, a strength matrix of the caller's gives the expansion
+    from paper_2307_00229_amd import clair
+
+    from .test_gpu_strength import _dev_csr, _random_graph
+
+    ps = _cases(2)[:2]
+    graphs = [_random_graph(p, 51 + k) for k, p in enumerate(ps)]
+    ctx = clair.Context()
+    ctx.set_graph([_dev_csr(*g, n=p.n) for g, p in zip(graphs, ps)])
+    As, cfs, Bs, ells = to_device(ps)
+    aggs = [torch.from_numpy(p.agg).cuda() for p in ps]
+    outs, infos, st = clair.clair_build_R_agg(As, cfs, aggs, Bs, ells, ctx=ctx)
+    assert st == 0, infos
+    for p, o, inf, g in zip(ps, outs, infos, graphs):
+        rp, ci, va = o.trimmed()
+        got = dict(row_ptr=rp.cpu().numpy(), col_idx=ci.cpu().numpy(), val=va.cpu().numpy(), n_c=o.n_c, nnz=o.nnz)
+        ref = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, agg=p.agg, strength=g)
+        assert_matches_oracle(p, got, ref, inf)
