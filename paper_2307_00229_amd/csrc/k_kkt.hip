@@ -209,17 +209,31 @@ __global__ __launch_bounds__(kQT) void k_q_dot(int n, const double* __restrict__
 
 // sc: [0] res.res, [1] p.Ap, [2] the new res.res, [3] the stop level,
 // [4] beta; *done set once the step cannot or need not go on
-__global__ __launch_bounds__(kQT) void k_q_axpy(int n, const double* __restrict__ sc, const double* __restrict__ p,
+// x += alpha p, res -= alpha Ap, and the new res.res into sc[2]
+__global__ __launch_bounds__(kQT) void k_q_axpy(int n, double* sc, const double* __restrict__ p,
                                                const double* __restrict__ Ap, double* x, double* res, int32_t* done) {
+  __shared__ double part[kQT / 64];
   if (*done) return;
   if (!(sc[1] > 0.0)) {  // breakdown (lambda is as good as it gets)
     if (blockIdx.x == 0 && threadIdx.x == 0) *done = 1;
     return;
   }
   const double alpha = sc[0] / sc[1];
+  double acc = 0.0;
   for (int j = blockIdx.x * kQT + threadIdx.x; j < n; j += gridDim.x * kQT) {
     x[j] += alpha * p[j];
-    res[j] -= alpha * Ap[j];
+    const double r = res[j] - alpha * Ap[j];
+    res[j] = r;
+    acc += r * r;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kQT / 64; ++w) t += part[w];
+    unsafeAtomicAdd(&sc[2], t);
   }
 }
 
@@ -310,9 +324,9 @@ hipError_t launch_kkt_step(const KktWork& w, hipStream_t s) {
                        w.L, w.smax, w.T, w.B, w.p, w.Ap, w.done);
   hipError_t e = launch_kkt_dot(w, w.p, w.Ap, w.sc + 1, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_q_axpy, dim3(g), dim3(kQT), 0, s, w.n, w.sc, w.p, w.Ap, w.x, w.res, w.done);
-  e = launch_kkt_dot(w, w.res, w.res, w.sc + 2, s);
-  if (e != hipSuccess) return e;
+  // one workgroup per CU: few atomics on the residual's sum
+  hipLaunchKernelGGL(k_q_axpy, dim3(std::max(1, std::min((w.n + kQT - 1) / kQT, w.cus))), dim3(kQT), 0, s, w.n, w.sc,
+                     w.p, w.Ap, w.x, w.res, w.done);
   hipLaunchKernelGGL(k_q_scalars, dim3(1), dim3(1), 0, s, w.sc, w.done, w.steps);
   hipLaunchKernelGGL(k_q_dir, dim3(g), dim3(kQT), 0, s, w.n, w.sc, w.res, w.p, w.Ap, w.done);
   return hipGetLastError();
