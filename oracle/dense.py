@@ -63,6 +63,26 @@ def neighbourhoods(A: np.ndarray, cf: np.ndarray, ell: int, theta: float = 0.0, 
     return out
 
 
+def neighbourhoods_literal(A: np.ndarray, cf: np.ndarray, ell: int, theta: float = 0.0):
+    """dict C-point -> sorted F-points of column c of pattern((S^{ell-1} T)|_F)
+    taken literally (Algorithm 1's pattern expansion): S the strength matrix
+    of A^T with its diagonal, T = [S_fc, I], boolean products.  C-points may
+    be interior vertices of a walk here; the searches of this library keep
+    F-points only, and the two agree for ell <= 2."""
+    n = A.shape[0]
+    S = strength_transposed(A, theta) | np.eye(n, dtype=bool)
+    F = cf == 0
+    C = np.nonzero(cf != 0)[0]
+    T = np.zeros((n, n), dtype=bool)
+    T[np.ix_(F, C)] = S[np.ix_(F, C)]
+    T[C, C] = True
+    X = T.astype(np.int64)
+    Si = S.astype(np.int64)
+    for _ in range(ell - 1):
+        X = ((Si @ X) > 0).astype(np.int64)
+    return {int(c): np.nonzero((X[:, c] > 0) & F)[0] for c in C}
+
+
 def lair_rows(A: np.ndarray, cf: np.ndarray, ell: int, theta: float = 0.0, agg=None):
     """Unconstrained rows: dict C-point -> (N, z) with (A[N,N])^T z = -A[i,N]^T."""
     nb = neighbourhoods(A, cf, ell, theta, agg)

@@ -200,3 +200,27 @@ def test_strength_matrix_is_the_search_graph(seed):
         if len(N):
             z = np.linalg.solve(A[np.ix_(N, N)].T, -A[i, N])
             assert np.allclose(got["val"][e][cols != i], z, rtol=0, atol=1e-12 * max(1.0, np.abs(z).max()))
+
+
+# ------------------------------------- the literal S^{ell-1} T pattern ---
+@pytest.mark.parametrize("theta", [0.0, 0.25])
+def test_literal_pattern_agrees_up_to_distance_2_and_not_beyond(theta):
+    # Algorithm 1 expands T = [S_fc, I] by S^{ell-1}, which lets C-points be
+    # interior vertices; the searches here keep F-points only.  Both give the
+    # same pattern for ell <= 2 (every workload), and from ell = 3 on the
+    # literal one can be larger
+    cases = [P.small_2d(12, stencil=9, eps=0.05, angle=1.0, k=3), P.small_2d(14, stencil=5, eps=0.1, angle=0.5),
+             P.small_3d(5, eps=0.05, b=(1.0, 0.3, -0.2)), P.random_sparse(60, 0.06, 5)]
+    larger = 0
+    for p in cases:
+        A = dense.to_dense(p.n, p.row_ptr, p.col_idx, p.val)
+        for ell in (1, 2, 3):
+            ours = dense.neighbourhoods(A, p.cf, ell, theta)
+            lit = dense.neighbourhoods_literal(A, p.cf, ell, theta)
+            for c in ours:
+                assert set(ours[c]) <= set(lit[c])
+                if ell <= 2:
+                    assert np.array_equal(ours[c], lit[c]), (p.name, ell, c)
+                else:
+                    larger += len(lit[c]) > len(ours[c])
+    assert larger > 0
