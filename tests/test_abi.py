@@ -104,3 +104,28 @@ def test_product_path_does_not_import_oracle():
     for fn in os.listdir(os.path.join(pkg, "csrc")):
         text = open(os.path.join(pkg, "csrc", fn)).read()
         assert "oracle" not in text.lower(), fn
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    # no CPU fallback: without the HIP library the binding raises
+    from paper_2307_00229_amd import clair
+
+    saved = clair._lib
+    clair._lib = None
+    try:
+        with pytest.raises(RuntimeError, match="not built"):
+            clair.load_library(str(tmp_path / "libclair.so"))
+    finally:
+        clair._lib = saved
+
+
+def test_product_code_does_not_use_the_oracle():
+    # only tests, the smoke check and the benchmark's CPU baseline may load
+    # oracle/; the package and the kernels never do
+    pkg = os.path.join(ROOT, "paper_2307_00229_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert not re.search(r"^\s*(import oracle|from oracle)", text, flags=re.M), fn
+                assert "clair_oracle" not in text, fn
