@@ -65,7 +65,9 @@ def _load():
         lib.orc_pattern_size.restype = ctypes.c_int
         lib.orc_build_R.argtypes = [i32, p, p, p, p, p, p, i32, f64, i32, p, p, p, i64, p, p]
         lib.orc_build_R.restype = ctypes.c_int
-        lib.orc_build_R_g.argtypes = [i32, p, p, p, p, p, p, p, p, p, i32, f64, i32, p, p, p, i64, p, p]
+        lib.orc_build_R_g.argtypes = [i32, p, p, p, p, p, p, p, p, p, i32, f64, i32, i32, p, p, p, i64, p, p]
+        lib.orc_pattern_size_g.argtypes = [i32, p, p, p, p, p, i32, f64, i32, i32, p, p, p]
+        lib.orc_pattern_size_g.restype = ctypes.c_int
         lib.orc_build_R_g.restype = ctypes.c_int
         lib.orc_project_k.argtypes = [i32, i32, p, p, p, p, p, i32, f64, p]
         lib.orc_project_k.restype = ctypes.c_int
@@ -91,7 +93,7 @@ def max_threads() -> int:
     return int(_load().orc_max_threads())
 
 
-def pattern_size(n, row_ptr, col_idx, val, cf, ell, nthreads=0, theta=0.0, agg=None):
+def pattern_size(n, row_ptr, col_idx, val, cf, ell, nthreads=0, theta=0.0, agg=None, literal=False):
     """(n_c, nnz_R, sizes[n_c]) with sizes[r] = |N(i_r)|.  theta: strength
     threshold; agg: root C-point of every point's aggregate (or -1), for the
     aggregation-based base pattern."""
@@ -104,20 +106,22 @@ def pattern_size(n, row_ptr, col_idx, val, cf, ell, nthreads=0, theta=0.0, agg=N
     n_c = ctypes.c_int32(0)
     nnz = ctypes.c_int64(0)
     sizes = np.zeros(int((cf != 0).sum()) or 1, np.int32)
-    rc = lib.orc_pattern_size(n, _ptr(rp), _ptr(ci), _ptr(va), _ptr(cf), _ptr(ag), ell, float(theta), nthreads,
-                              ctypes.byref(n_c), ctypes.byref(nnz), _ptr(sizes))
+    rc = lib.orc_pattern_size_g(n, _ptr(rp), _ptr(ci), _ptr(va), _ptr(cf), _ptr(ag), ell, float(theta),
+                                int(bool(literal)), nthreads, ctypes.byref(n_c), ctypes.byref(nnz), _ptr(sizes))
     if rc:
         raise OracleError(rc, f"oracle pattern_size failed ({rc})")
     return n_c.value, nnz.value, sizes[: n_c.value]
 
 
 def build_R(n, row_ptr, col_idx, val, cf, B, ell, nthreads=0, allow_singular=False, theta=0.0, agg=None,
-            strength=None):
+            strength=None, literal=False):
     """FP64 oracle R (CSR arrays) plus statistics.  theta: strength threshold
     of the pattern (0 keeps every stored nonzero).  strength: an optional n x n
     CSR (row_ptr, col_idx, val) whose stored entries u -> v are the edges of
     the neighbourhood search instead of A's (theta then filters its entries);
-    the local systems always use A.
+    the local systems always use A.  literal: the pattern of S^{ell-1} T
+    taken literally (C-points may be interior vertices of a walk; the same
+    as the default for ell <= 2).
 
     Returns dict(row_ptr, col_idx, val, n_c, nnz, n_uncovered, bad_row).
     """
@@ -134,14 +138,15 @@ def build_R(n, row_ptr, col_idx, val, cf, B, ell, nthreads=0, allow_singular=Fal
         grp = np.ascontiguousarray(strength[0], np.int32)
         gci = np.ascontiguousarray(strength[1], np.int32)
         gva = np.ascontiguousarray(strength[2], np.float64)
-    n_c, nnz, _ = pattern_size(n, grp, gci, gva, cfa, ell, nthreads, theta=theta, agg=ag)
+    n_c, nnz, _ = pattern_size(n, grp, gci, gva, cfa, ell, nthreads, theta=theta, agg=ag, literal=literal)
     Rrp = np.zeros(n_c + 1, np.int32)
     Rci = np.zeros(max(nnz, 1), np.int32)
     Rva = np.zeros(max(nnz, 1), np.float64)
     unc = ctypes.c_int64(0)
     bad = ctypes.c_int32(-1)
     rc = lib.orc_build_R_g(n, _ptr(rp), _ptr(ci), _ptr(va), _ptr(grp), _ptr(gci), _ptr(gva), _ptr(cfa), _ptr(ag),
-                           _ptr(Ba), ell, float(theta), nthreads, _ptr(Rrp), _ptr(Rci), _ptr(Rva), nnz,
+                           _ptr(Ba), ell, float(theta), int(bool(literal)), nthreads, _ptr(Rrp), _ptr(Rci),
+                           _ptr(Rva), nnz,
                            ctypes.byref(unc), ctypes.byref(bad))
     if rc and not (rc == ORC_ERR_SINGULAR and allow_singular):
         raise OracleError(rc, f"oracle build_R failed ({rc}), bad_row={bad.value}")

@@ -117,15 +117,38 @@ typedef struct {
   const int32_t* mem;
 } agg_lists;
 
-/* Returns s = |N(i)| (>= 0), N(i) sorted ascending in w->list[0..s), or -1 on OOM. */
+/* Returns s = |N(i)| (>= 0), N(i) sorted ascending in w->list[0..s), or -1 on OOM.
+ * literal != 0: the pattern of S^{ell-1} T taken literally, where C-points
+ * may be interior vertices: the first step (T = [S_fc, I]) reaches i's
+ * F-neighbours and i itself, every later step any vertex; only F-points join
+ * N(i).  The same as the default for ell <= 2. */
 static int32_t neighbourhood(int32_t i, int ell, const int32_t* rp, const int32_t* ci,
                              const double* va, const int8_t* cf, double theta, const double* cmax,
-                             const agg_lists* ag, bfs_ws* w) {
+                             const agg_lists* ag, bfs_ws* w, int literal) {
   w->stamp++;
   w->mark[i] = w->stamp;
   int32_t len = 0;
   int32_t lo = 0, hi = 0; /* current frontier = list[lo..hi); level 0 frontier is {i} */
   for (int depth = 1; depth <= ell; ++depth) {
+    if (literal && depth >= 2) {
+      /* the frontier holds F- and C-points; at depth 2 it also holds i (T's
+         identity part), whose C-neighbours become interior vertices */
+      int32_t before = len;
+      for (int32_t t = (depth == 2 ? lo - 1 : lo); t < hi; ++t) {
+        int32_t u = (t < lo) ? i : w->list[t];
+        for (int32_t e = rp[u]; e < rp[u + 1]; ++e) {
+          int32_t k = ci[e];
+          if (!is_edge(u, e, ci, va, theta, cmax) || w->mark[k] == w->stamp) continue;
+          w->mark[k] = w->stamp;
+          if (ws_push(w, len, k)) return -1;
+          ++len;
+        }
+      }
+      lo = before;
+      hi = len;
+      if (lo == hi) break;
+      continue;
+    }
     int32_t before = len;
     if (depth == 1 && ag) {
       /* the aggregate's F-points */
@@ -159,6 +182,12 @@ static int32_t neighbourhood(int32_t i, int ell, const int32_t* rp, const int32_
     lo = before;
     hi = len;
     if (lo == hi) break;
+  }
+  if (literal) { /* C-points were interior vertices only */
+    int32_t m = 0;
+    for (int32_t t = 0; t < len; ++t)
+      if (cf[w->list[t]] == 0) w->list[m++] = w->list[t];
+    len = m;
   }
   qsort(w->list, (size_t)len, sizeof(int32_t), cmp_i32);
   return len;
@@ -263,8 +292,8 @@ static int build_agg_lists(int32_t n, const int8_t* cf, const int32_t* agg, int3
    a strength matrix the caller gives, whose stored entries u -> v are the
    edges (filtered by theta against G's column maxima, as for A). */
 int orc_pattern_size_g(int32_t n, const int32_t* g_rp, const int32_t* g_ci, const double* g_va,
-                       const int8_t* cf, const int32_t* agg, int32_t ell, double theta, int32_t nthreads,
-                       int32_t* n_c_out, int64_t* nnz_out, int32_t* sizes) {
+                       const int8_t* cf, const int32_t* agg, int32_t ell, double theta, int32_t literal,
+                       int32_t nthreads, int32_t* n_c_out, int64_t* nnz_out, int32_t* sizes) {
   const int32_t* rp = g_rp;
   const int32_t* ci = g_ci;
   const double* va = g_va;
@@ -301,7 +330,7 @@ int orc_pattern_size_g(int32_t n, const int32_t* g_rp, const int32_t* g_ci, cons
     } else {
 #pragma omp for schedule(static)
       for (int32_t r = 0; r < n_c; ++r) {
-        int32_t s = neighbourhood(clist[r], ell, rp, ci, va, cf, theta, cmax, agg ? &ag : NULL, &w);
+        int32_t s = neighbourhood(clist[r], ell, rp, ci, va, cf, theta, cmax, agg ? &ag : NULL, &w, literal);
         if (s < 0) {
 #pragma omp atomic write
           err = 1;
@@ -327,7 +356,7 @@ int orc_pattern_size_g(int32_t n, const int32_t* g_rp, const int32_t* g_ci, cons
 int orc_pattern_size(int32_t n, const int32_t* rp, const int32_t* ci, const double* va,
                      const int8_t* cf, const int32_t* agg, int32_t ell, double theta, int32_t nthreads,
                      int32_t* n_c_out, int64_t* nnz_out, int32_t* sizes) {
-  return orc_pattern_size_g(n, rp, ci, va, cf, agg, ell, theta, nthreads, n_c_out, nnz_out, sizes);
+  return orc_pattern_size_g(n, rp, ci, va, cf, agg, ell, theta, 0, nthreads, n_c_out, nnz_out, sizes);
 }
 
 /*
@@ -338,13 +367,13 @@ int orc_pattern_size(int32_t n, const int32_t* rp, const int32_t* ci, const doub
  */
 int orc_build_R_g(int32_t n, const int32_t* rp, const int32_t* ci, const double* va, const int32_t* g_rp,
                   const int32_t* g_ci, const double* g_va, const int8_t* cf, const int32_t* agg, const double* B,
-                  int32_t ell, double theta, int32_t nthreads, int32_t* R_rp, int32_t* R_ci, double* R_va,
-                  int64_t cap, int64_t* n_uncovered, int32_t* bad_row);
+                  int32_t ell, double theta, int32_t literal, int32_t nthreads, int32_t* R_rp, int32_t* R_ci,
+                  double* R_va, int64_t cap, int64_t* n_uncovered, int32_t* bad_row);
 
 int orc_build_R(int32_t n, const int32_t* rp, const int32_t* ci, const double* va, const int8_t* cf,
                 const int32_t* agg, const double* B, int32_t ell, double theta, int32_t nthreads, int32_t* R_rp,
                 int32_t* R_ci, double* R_va, int64_t cap, int64_t* n_uncovered, int32_t* bad_row) {
-  return orc_build_R_g(n, rp, ci, va, rp, ci, va, cf, agg, B, ell, theta, nthreads, R_rp, R_ci, R_va, cap,
+  return orc_build_R_g(n, rp, ci, va, rp, ci, va, cf, agg, B, ell, theta, 0, nthreads, R_rp, R_ci, R_va, cap,
                        n_uncovered, bad_row);
 }
 
@@ -352,8 +381,8 @@ int orc_build_R(int32_t n, const int32_t* rp, const int32_t* ci, const double* v
    local systems always use A. */
 int orc_build_R_g(int32_t n, const int32_t* rp, const int32_t* ci, const double* va, const int32_t* g_rp,
                   const int32_t* g_ci, const double* g_va, const int8_t* cf, const int32_t* agg, const double* B,
-                  int32_t ell, double theta, int32_t nthreads, int32_t* R_rp, int32_t* R_ci, double* R_va,
-                  int64_t cap, int64_t* n_uncovered, int32_t* bad_row) {
+                  int32_t ell, double theta, int32_t literal, int32_t nthreads, int32_t* R_rp, int32_t* R_ci,
+                  double* R_va, int64_t cap, int64_t* n_uncovered, int32_t* bad_row) {
   if (ell < 1 || !(theta >= 0.0 && theta <= 1.0) || check_csr(n, rp, ci) || check_csr(n, g_rp, g_ci))
     return ORC_ERR_INVALID;
   int32_t n_c = 0;
@@ -362,7 +391,7 @@ int orc_build_R_g(int32_t n, const int32_t* rp, const int32_t* ci, const double*
   int32_t* sizes = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_c > 0 ? n_c : 1));
   int32_t* clist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n_c > 0 ? n_c : 1));
   if (!sizes || !clist) { free(sizes); free(clist); return ORC_ERR_NOMEM; }
-  int rc = orc_pattern_size_g(n, g_rp, g_ci, g_va, cf, agg, ell, theta, nthreads, &n_c, &nnz, sizes);
+  int rc = orc_pattern_size_g(n, g_rp, g_ci, g_va, cf, agg, ell, theta, literal, nthreads, &n_c, &nnz, sizes);
   if (rc) { free(sizes); free(clist); return rc; }
   if (nnz > cap) { free(sizes); free(clist); return ORC_ERR_CAPACITY; }
   double* cmax = NULL;
@@ -401,7 +430,7 @@ int orc_build_R_g(int32_t n, const int32_t* rp, const int32_t* ci, const double*
 #pragma omp for schedule(dynamic, 64)
       for (int32_t r = 0; r < n_c; ++r) {
         int32_t i = clist[r];
-        int32_t s = neighbourhood(i, ell, g_rp, g_ci, g_va, cf, theta, cmax, agg ? &ag : NULL, &w);
+        int32_t s = neighbourhood(i, ell, g_rp, g_ci, g_va, cf, theta, cmax, agg ? &ag : NULL, &w, literal);
         if (s < 0) {
 #pragma omp atomic write
           err = 1;

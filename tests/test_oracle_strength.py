@@ -224,3 +224,24 @@ def test_literal_pattern_agrees_up_to_distance_2_and_not_beyond(theta):
                 else:
                     larger += len(lit[c]) > len(ours[c])
     assert larger > 0
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.25])
+def test_literal_search_equals_the_boolean_products(theta):
+    # the C oracle's literal search (C-points as interior vertices) against
+    # pattern((S^{ell-1} T)|_F) formed by boolean matrix products, ell = 1..4
+    cases = [P.small_2d(12, stencil=9, eps=0.05, angle=1.0, k=3), P.small_2d(14, stencil=5, eps=0.1, angle=0.5),
+             P.small_3d(5, eps=0.05, b=(1.0, 0.3, -0.2)), P.random_sparse(60, 0.06, 5)]
+    for p in cases:
+        A = dense.to_dense(p.n, p.row_ptr, p.col_idx, p.val)
+        for ell in (1, 2, 3, 4):
+            lit = dense.neighbourhoods_literal(A, p.cf, ell, theta)
+            o = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, None, ell, theta=theta, literal=True,
+                               allow_singular=True)
+            C = np.nonzero(p.cf)[0]
+            for r, c in enumerate(C):
+                cols = o["col_idx"][o["row_ptr"][r]:o["row_ptr"][r + 1]]
+                assert np.array_equal(cols[cols != c], lit[int(c)]), (p.name, ell, int(c))
+            if ell <= 2:
+                d = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, None, ell, theta=theta)
+                assert np.array_equal(d["col_idx"], o["col_idx"]) and np.array_equal(d["val"], o["val"])
