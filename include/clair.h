@@ -66,7 +66,7 @@ typedef enum clair_status {
   CLAIR_ERR_CAPACITY = 2,    /* R does not fit: required sizes are in clair_info_t / R_out */
   CLAIR_ERR_SINGULAR = 3,    /* a local block is singular (first fine row in info.first_bad_row) */
   CLAIR_ERR_HIP = 4,         /* a HIP runtime call failed */
-  CLAIR_ERR_UNSUPPORTED = 5, /* a neighbourhood exceeds CLAIR_MAX_BLOCK */
+  CLAIR_ERR_UNSUPPORTED = 5, /* a neighbourhood exceeds CLAIR_MAX_BLOCK, or an input or option the entry point does not take */
   CLAIR_ERR_NOMEM = 6        /* workspace allocation failed */
 } clair_status;
 
@@ -402,6 +402,23 @@ int clair_ctx_set_strength(clair_ctx_t* ctx, double theta);
  * outside [0, n) are skipped by the search.
  */
 int clair_ctx_set_graph(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* S);
+
+/*
+ * on = 1: the pattern of Algorithm 1's expansion S^{ell-1} T taken literally
+ * (T = [S_fc, I]): C-points may then be interior vertices of a walk (the
+ * first step reaches i's F-neighbours and i itself, every later step any
+ * vertex; only F-points join N(i)).  The default (on = 0) keeps F-points as
+ * interior vertices; the two agree for ell <= 2.  With on = 1 the per-row
+ * FP64 form (CLAIR_PREC_FP64, clair_build_R_approx) searches literally for
+ * any ell, clair_size_R sizes those rows with it, and every mixed-precision
+ * entry point returns CLAIR_ERR_UNSUPPORTED for a matrix with ell >= 3 (at
+ * ell <= 2 it builds as usual).  The FP64 form's search holds 64 vertices;
+ * with on = 1 the C-points it passes through before the last step count
+ * against that too, and a row that does not fit fails as an oversized
+ * neighbourhood does.  The classical base pattern only (not the
+ * aggregation-based one).  on outside {0, 1} returns CLAIR_ERR_INVALID.
+ */
+int clair_ctx_set_literal_pattern(clair_ctx_t* ctx, int32_t on);
 int clair_ctx_get_strength(clair_ctx_t* ctx, double* theta);
 int clair_autotune(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf_marker,
                    const double* const* B, const int32_t* ell, clair_csr_out_t* R_out, void* stream,

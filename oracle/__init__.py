@@ -168,7 +168,7 @@ def build_R_diag(n, row_ptr, col_idx, val, cf, B, ell, iterations, theta=0.0, ag
 
 
 def build_R_approx(n, row_ptr, col_idx, val, cf, B, ell, iterations, inverse, theta=0.0, agg=None, krylov=0,
-                   strength=None):
+                   strength=None, literal=False):
     """Algorithm 1 with approximate block inverses ("diag": the diagonal of
     each block; "ilu0": its incomplete LU factorisation without fill;
     "gmres": `krylov` steps of GMRES on each local system from zero) and
@@ -176,7 +176,7 @@ def build_R_approx(n, row_ptr, col_idx, val, cf, B, ell, iterations, inverse, th
     not depend on the inverse).  Returns the same dict as build_R."""
     lib = _load()
     o = build_R(n, row_ptr, col_idx, val, cf, None, ell, allow_singular=True, theta=theta, agg=agg,
-                strength=strength)
+                strength=strength, literal=literal)
     rp = np.ascontiguousarray(row_ptr, np.int32)
     ci = np.ascontiguousarray(col_idx, np.int32)
     va = np.ascontiguousarray(val, np.float64)

@@ -32,6 +32,7 @@ EXPORTED = [
     "clair_ctx_set_strength", "clair_ctx_get_strength", "clair_transpose", "clair_build_P",
     "clair_spgemm", "clair_galerkin", "clair_smooth_B", "clair_build_R_agg", "clair_project_constraints",
     "clair_build_R_diag", "clair_build_R_approx", "clair_build_R_kkt", "clair_ctx_set_graph",
+    "clair_ctx_set_literal_pattern",
     "clair_autotune", "clair_graph_create", "clair_graph_launch", "clair_graph_destroy", "clair_graph_info",
     "clair_plan_create", "clair_plan_execute", "clair_plan_info", "clair_plan_destroy",
     "clair_strerror", "clair_last_error",
@@ -131,6 +132,7 @@ def load_library(path: str = LIB_PATH):
         "clair_build_R_diag": ([P, ctypes.POINTER(CsrIn), P, P, I32, I32, ctypes.POINTER(CsrOut),
                                 ctypes.POINTER(Info), P], ctypes.c_int),
         "clair_ctx_set_graph": ([P, I32, P], ctypes.c_int),
+        "clair_ctx_set_literal_pattern": ([P, I32], ctypes.c_int),
         "clair_build_R_kkt": ([P, ctypes.POINTER(CsrIn), P, P, I32, ctypes.POINTER(CsrOut), ctypes.POINTER(Info), P],
                               ctypes.c_int),
         "clair_build_R_approx": ([P, ctypes.POINTER(CsrIn), P, P, I32, I32, I32, I32, ctypes.POINTER(CsrOut),
@@ -269,6 +271,12 @@ class Context:
             st = self._lib.clair_ctx_set_graph(self._h, len(graphs), arr)
         if st:
             raise ClairError(st, "clair_ctx_set_graph")
+
+    def set_literal_pattern(self, on: bool):
+        """The literal S^{ell-1} T pattern (C-points as interior vertices)."""
+        st = self._lib.clair_ctx_set_literal_pattern(self._h, 1 if on else 0)
+        if st:
+            raise ClairError(st, "clair_ctx_set_literal_pattern")
 
     def get_strength(self) -> float:
         t = ctypes.c_double()

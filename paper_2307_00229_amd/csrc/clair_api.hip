@@ -137,6 +137,7 @@ struct clair_ctx {
   int group = 8;  // lanes per row of the small solver: 1, 4 or 8 (|N| <= 8), 16/32 (|N| <= group)
   double theta = 0.0;  // strength threshold of the neighbourhood search
   std::vector<clair_csr_t> graph;  // strength matrices of the search, one per matrix (empty: A's graph)
+  int literal = 0;  // the literal S^{ell-1} T pattern (the per-row FP64 form; a no-op at ell <= 2)
   int binB_max = 32;  // largest block of the last batch whose sizes were read back (9..32)
   int last_maxb = 0;  // the same, unclamped (0: none read back yet)
   int wg_threads = 256;
@@ -270,6 +271,9 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
     for (int m = 0; m < nmat; ++m)
       if (c->graph[m].n != A[m].n) return CLAIR_ERR_INVALID;
   }
+  if (c->literal)  // the literal pattern differs from the searches here only from distance 3 on
+    for (int m = 0; m < nmat; ++m)
+      if (ell[m] >= 3) return CLAIR_ERR_UNSUPPORTED;
   b->nmat = nmat;
   b->nchunks = 0;
   b->n_total = 0;
@@ -580,6 +584,7 @@ int run_plain_one(clair_ctx* c, const clair_csr_t& A, const int8_t* cf, const do
   p.rp = A.row_ptr;
   p.ci = A.col_idx;
   p.va = A.val;
+  p.literal = c->literal;
   p.grp = graph ? graph->row_ptr : A.row_ptr;
   p.gci = graph ? graph->col_idx : A.col_idx;
   p.gva = graph ? graph->val : A.val;
@@ -1347,6 +1352,22 @@ int clair_size_R(clair_ctx_t* c, int32_t nmat, const clair_csr_t* A, const int8_
   if (rc) return rc;
   if (nmat == 0) return CLAIR_OK;
   const hipStream_t s = static_cast<hipStream_t>(stream);
+  bool lit3 = false;
+  for (int m = 0; m < nmat; ++m) lit3 |= c->literal && ell[m] >= 3;
+  if (lit3) {  // the literal pattern at distance 3 or more: the per-row form's sizes
+    if (!c->graph.empty() && (int32_t)c->graph.size() != nmat) return CLAIR_ERR_INVALID;
+    for (int m = 0; m < nmat; ++m) {
+      if (!c->graph.empty() && c->graph[m].n != A[m].n) return CLAIR_ERR_INVALID;
+      clair_csr_out_t probe{};
+      clair_info_t in{};
+      rc = run_plain_one(c, A[m], cf[m], nullptr, ell[m], &probe, s, &in, true, nullptr,
+                         c->graph.empty() ? nullptr : &c->graph[m]);
+      if (rc && rc != CLAIR_ERR_CAPACITY) return rc;
+      n_c[m] = probe.n_rows;
+      nnz[m] = probe.nnz;
+    }
+    return CLAIR_OK;
+  }
   Batch b;
   rc = prepare(c, nmat, A, cf, nullptr, ell, R.data(), &b);
   if (rc) return rc;
@@ -1418,6 +1439,12 @@ int clair_ctx_set_tuning(clair_ctx_t* c, int32_t group, int32_t wg_threads, int3
   if (group) c->group = group;
   if (wg_threads) c->wg_threads = wg_threads;
   if (chunk) c->chunk = chunk;
+  return CLAIR_OK;
+}
+
+int clair_ctx_set_literal_pattern(clair_ctx_t* c, int32_t on) {
+  if (!c || (on != 0 && on != 1)) return CLAIR_ERR_INVALID;
+  c->literal = on;
   return CLAIR_OK;
 }
 
@@ -1533,6 +1560,7 @@ int clair_graph_create(clair_ctx_t* parent, int32_t nmat, const clair_csr_t* A, 
   g->ctx->chunk = parent->chunk;
   g->ctx->theta = parent->theta;
   g->ctx->graph = parent->graph;
+  g->ctx->literal = parent->literal;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   clair_opts_t o{};
   o.stream = stream;
@@ -1617,6 +1645,7 @@ int clair_plan_create(clair_ctx_t* parent, int32_t nmat, const clair_csr_t* A, c
     c->chunk = parent->chunk;
     c->theta = parent->theta;
     c->graph = parent->graph;
+    c->literal = parent->literal;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     Batch& b = pl->b;
     rc = prepare(c, nmat, A, cf, nullptr, ell, R, &b);
@@ -1768,7 +1797,7 @@ const char* clair_strerror(int st) {
     case CLAIR_ERR_CAPACITY: return "output capacity too small (required sizes reported)";
     case CLAIR_ERR_SINGULAR: return "singular local block";
     case CLAIR_ERR_HIP: return "HIP runtime error";
-    case CLAIR_ERR_UNSUPPORTED: return "neighbourhood larger than CLAIR_MAX_BLOCK";
+    case CLAIR_ERR_UNSUPPORTED: return "unsupported: a neighbourhood larger than CLAIR_MAX_BLOCK, or an input or option this entry point does not take";
     case CLAIR_ERR_NOMEM: return "workspace allocation failed";
     default: return "unknown status";
   }

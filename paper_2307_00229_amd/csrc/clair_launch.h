@@ -146,6 +146,7 @@ struct PlainWork {
   const int32_t* grp;
   const int32_t* gci;
   const double* gva;
+  int32_t literal;  // 1: the pattern of S^{ell-1} T taken literally (C-points as interior vertices)
   const int8_t* cf;
   const double* B;
   int32_t n;

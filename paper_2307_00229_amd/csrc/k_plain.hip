@@ -26,18 +26,25 @@ __device__ void pflag(int32_t* flags, int code, int row) {
   atomicMin(&flags[PF_FIRST_BAD], row);
 }
 
-// breadth-first search into a private array; returns |N(i)| (sorted) or -1
+// breadth-first search into a private array; returns |N(i)| (sorted) or -1.
+// With p.literal the pattern of S^{ell-1} T is taken literally: from the
+// second step on C-points may be interior vertices (those reached before the
+// last step wait in the array with the F-points, counting against its
+// capacity, and are dropped at the end), and the second step also expands i
+// itself (T's identity part).
 __device__ int plain_bfs(const PlainWork& p, int i, int* N) {
   int s = 0, lo = 0, hi = 0;
   for (int depth = 1; depth <= p.ell; ++depth) {
     const int start = s;
-    const int ulo = (depth == 1) ? 0 : lo;
+    const bool lit = p.literal && depth >= 2;
+    const int ulo = (depth == 1) ? 0 : (lit && depth == 2 ? lo - 1 : lo);
     const int uhi = (depth == 1) ? 1 : hi;
     for (int t = ulo; t < uhi; ++t) {
-      const int u = (depth == 1) ? i : N[t];
+      const int u = (depth == 1 || t < lo) ? i : N[t];
       for (int e = p.grp[u]; e < p.grp[u + 1]; ++e) {  // the search graph: A or a strength matrix
         const int k = p.gci[e];
-        if (k == u || (unsigned)k >= (unsigned)p.n || p.gva[e] == 0.0 || p.cf[k] != 0) continue;
+        if (k == u || k == i || (unsigned)k >= (unsigned)p.n || p.gva[e] == 0.0) continue;
+        if (p.cf[k] != 0 && !(lit && depth < p.ell)) continue;  // a C-point is kept only to be expanded
         if (p.theta != 0.0 && !(fabs(p.gva[e]) >= p.theta * p.cmax[k])) continue;  // strength of A^T
         bool seen = false;
         for (int q = 0; q < s && !seen; ++q) seen = (N[q] == k);
@@ -49,6 +56,12 @@ __device__ int plain_bfs(const PlainWork& p, int i, int* N) {
     lo = start;
     hi = s;
     if (lo == hi) break;
+  }
+  if (p.literal) {  // C-points were interior vertices only
+    int m = 0;
+    for (int a = 0; a < s; ++a)
+      if (p.cf[N[a]] == 0) N[m++] = N[a];
+    s = m;
   }
   for (int a = 1; a < s; ++a) {  // insertion sort
     const int v = N[a];

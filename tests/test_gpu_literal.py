@@ -1,0 +1,98 @@
+"""GPU: the literal S^{ell-1} T pattern (clair_ctx_set_literal_pattern).
+
+Algorithm 1 expands T = [S_fc, I] by S^{ell-1}; taken literally, C-points can
+be interior vertices of a walk from distance 3 on (the oracle's literal
+search is pinned against boolean matrix products in
+tests/test_oracle_strength.py).  The per-row FP64 form searches literally
+for any ell: pattern identical and row error <= 1e-10 against the oracle at
+ell = 3, where the literal patterns are larger; the size query agrees; the
+approximate-inverse build (which uses that form's pattern) too.  The mixed
+path builds as usual at ell <= 2 (where the readings agree) and reports
+CLAIR_ERR_UNSUPPORTED at ell >= 3.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_00229_amd import problems as P
+
+from ._util import assert_matches_oracle, gpu_build, row_errors, to_device
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2307_00229_amd import clair
+
+    clair.load_library()
+
+
+def _cases(ell):
+    return [P.small_2d(40, stencil=5, eps=0.1, angle=0.5, ell=ell),
+            P.small_3d(9, eps=0.05, b=(1.0, 0.3, -0.2), ell=ell),
+            P.random_sparse(300, 0.01, 5, ell=ell)]
+
+
+def _ctx():
+    from paper_2307_00229_amd import clair
+
+    ctx = clair.Context()
+    ctx.set_literal_pattern(True)
+    return ctx
+
+
+def test_fp64_form_searches_literally_at_distance_3():
+    from paper_2307_00229_amd import clair
+
+    ps = _cases(3)
+    ctx = _ctx()
+    print(f"[gpu] literal pattern, FP64 form, ell=3 {[p.name for p in ps]}", flush=True)
+    res, infos, st = gpu_build(ps, ctx=ctx, precision=clair.CLAIR_PREC_FP64)
+    assert st == 0, infos
+    larger = 0
+    for p, g, inf in zip(ps, res, infos):
+        o = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, literal=True)
+        assert_matches_oracle(p, g, o, inf)
+        larger += o["nnz"] > oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell)["nnz"]
+    assert larger > 0
+    As, cfs, _, ells = to_device(ps)
+    ncs, nzs = clair.clair_size_R(As, cfs, ells, ctx=ctx)
+    assert list(nzs) == [i["nnz"] for i in infos]
+
+
+def test_mixed_path_agrees_at_distance_2_and_declines_beyond():
+    from paper_2307_00229_amd import clair
+
+    ps = _cases(2)
+    a, _, st = gpu_build(ps, ctx=_ctx())
+    assert st == 0
+    b, _, st = gpu_build(ps)
+    assert st == 0
+    for x, y in zip(a, b):  # the projection's column sums are atomic: equal up to their rounding
+        assert np.array_equal(x["row_ptr"], y["row_ptr"]) and np.array_equal(x["col_idx"], y["col_idx"])
+        assert np.abs(x["val"] - y["val"]).max() <= 1e-13 * np.abs(y["val"]).max()
+    As, cfs, Bs, ells = to_device(_cases(3)[:1])
+    _, _, st = clair.clair_build_R_batched(As, cfs, Bs, ells, ctx=_ctx(), check=False)
+    assert st == clair.CLAIR_ERR_UNSUPPORTED
+
+
+def test_approximate_inverse_build_with_the_literal_pattern():
+    from paper_2307_00229_amd import clair
+
+    p = _cases(3)[0]
+    A = clair.CSR.from_problem(p, "cuda")
+    out, info, _ = clair.clair_build_R_approx(A, torch.from_numpy(p.cf).cuda(), torch.from_numpy(p.B).cuda(),
+                                              p.ell, 2, inverse=clair.CLAIR_INVERSE_DIAG, ctx=_ctx())
+    rp, ci, va = out
+    g = dict(row_ptr=rp.cpu().numpy(), col_idx=ci.cpu().numpy(), val=va.cpu().numpy(), n_c=info["n_c"],
+             nnz=info["nnz"])
+    o = oracle.build_R_approx(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, 2, "diag", literal=True)
+    assert np.array_equal(g["col_idx"], o["col_idx"])
+    assert row_errors(p, g, o)[0].max() <= 1e-10
