@@ -438,7 +438,7 @@ int enqueue_numeric(clair_ctx* c, Batch& b, hipStream_t s, bool timing, const Co
   timing_mark(c, timing, s, "rows_wg");
   if (b.any_B) {
     // rows of up to 8 points: one thread per row; longer rows: eight lanes each
-    HIPCHK(launch_project(b.w, occupancy_blocks(c, 4), c->last_maxb > 8 ? 8 : 1, s));
+    HIPCHK(launch_project(b.w, occupancy_blocks(c, 4), occupancy_blocks(c, 4), c->last_maxb > 8 ? 8 : 1, s));
     if (capture_check(c->capturing, s, "k_project", __LINE__)) return CLAIR_ERR_HIP;
     timing_mark(c, timing, s, "project");
   }

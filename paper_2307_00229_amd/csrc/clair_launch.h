@@ -26,7 +26,7 @@ hipError_t launch_numeric(const Work& w, int which, int group, int sm, int wg_th
 hipError_t launch_quad8(const Work& w, int wg_threads, int cus, hipStream_t s);
 hipError_t launch_rows8(const Work& w, int wg_threads, int cus, hipStream_t s);
 hipError_t launch_rows_wg(const Work& w, int blocks, hipStream_t s);
-hipError_t launch_project(const Work& w, int blocks, int lanes_per_row, hipStream_t s);
+hipError_t launch_project(const Work& w, int blocks, int unc_blocks, int lanes_per_row, hipStream_t s);
 
 // CSR transpose of an m x ncol matrix: trp[ncol+1], tci/tva[nnz]; scratch of
 // transpose_scratch_ints(ncol) ints (column cursors, a flag set to 1 for an

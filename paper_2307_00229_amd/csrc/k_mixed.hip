@@ -282,11 +282,12 @@ struct ChunkCursor {
 // round-robin (block b runs on XCD b % 8).  Give each XCD a contiguous range
 // of logical indices, so the rows one XCD works on are neighbours in the grid
 // and share its L2.
-__device__ __forceinline__ int xcd_logical_block() {
-  const int b = blockIdx.x, nb = gridDim.x;
+__device__ __forceinline__ int xcd_logical_block(int nb) {
+  const int b = blockIdx.x;
   const int x = b % 8, q = nb / 8, r = nb % 8;
   return x * q + min(x, r) + b / 8;
 }
+__device__ __forceinline__ int xcd_logical_block() { return xcd_logical_block(gridDim.x); }
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
@@ -1960,10 +1961,34 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
 // ---------------------------------------------------------------------------
 // LPR = 1: one thread per row (short rows: a wavefront covers 64
 // consecutive rows, a contiguous run of R).  LPR = 8: eight lanes per row,
-// entry by entry (long rows).
+// entry by entry (long rows).  Workgroups [0, nproj) project (nproj a
+// multiple of 8); the rest count the uncovered F-points at the same time.
 template <int LPR>
-__global__ __launch_bounds__(256) void k_project(Work w) {
+__global__ __launch_bounds__(256) void k_project(Work w, int nproj) {
   const int tid = threadIdx.x;
+  if ((int)blockIdx.x >= nproj) {
+    // uncovered F-points: one global atomic per workgroup and matrix
+    __shared__ int s_unc;
+    const int nu = gridDim.x - nproj, bu = blockIdx.x - nproj;
+    for (int m = 0; m < w.nmat; ++m) {
+      const GDesc d = gview(w.desc[m]);
+      if (!d.B || !matrix_live(w.st[m])) continue;  // uniform
+      if (tid == 0) s_unc = 0;
+      __syncthreads();
+      int cnt = 0;
+      for (int j = bu * blockDim.x + tid; j < d.n; j += nu * blockDim.x) {
+        const int8_t cj = d.cf[j];  // both loads issued before either is used
+        const double sj = w.dsum[d.fine0 + j];
+        cnt += (cj == 0 && !(sj > 0.0)) ? 1 : 0;
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+      if ((tid & 63) == 0 && cnt) atomicAdd(&s_unc, cnt);
+      __syncthreads();
+      if (tid == 0 && s_unc) atomicAdd((unsigned long long*)&w.st[m].n_uncovered, (unsigned long long)s_unc);
+    }
+    return;
+  }
   if constexpr (LPR == 1) {
   // one thread per row: a wavefront covers 64 consecutive rows, i.e. a
   // contiguous run of R; a row's entries are read eight at a time and all
@@ -1971,8 +1996,8 @@ __global__ __launch_bounds__(256) void k_project(Work w) {
   // looked up once per wavefront and chunk (wavefront-uniform values).
   const int lane = tid & 63;
   const int total = w.cnt->total_rows;
-  const int lb = xcd_logical_block();
-  const int per = (total + gridDim.x - 1) / gridDim.x;
+  const int lb = xcd_logical_block(nproj);
+  const int per = (total + nproj - 1) / nproj;
   const int r0 = lb * per;
   const int r1 = min(total, r0 + per);
   ChunkCursor cc;
@@ -2018,8 +2043,8 @@ __global__ __launch_bounds__(256) void k_project(Work w) {
     const int grp = tid / LPR;
     constexpr int NG = 256 / LPR;
     const int total = w.cnt->total_rows;
-    const int lb = xcd_logical_block();
-    const int per = (total + gridDim.x - 1) / gridDim.x;
+    const int lb = xcd_logical_block(nproj);
+    const int per = (total + nproj - 1) / nproj;
     const int r0 = lb * per;
     const int r1 = min(total, r0 + per);
     ChunkCursor cc;
@@ -2039,22 +2064,6 @@ __global__ __launch_bounds__(256) void k_project(Work w) {
         if (dj > 0.0) d.Rva[e] -= bi * (w.rsum[cc.fine0 + j] - d.B[j]) / dj;
       }
     }
-  }
-  // uncovered F-points: one global atomic per workgroup and matrix
-  __shared__ int s_unc;
-  for (int m = 0; m < w.nmat; ++m) {
-    const GDesc d = gview(w.desc[m]);
-    if (!d.B || !matrix_live(w.st[m])) continue;  // uniform
-    if (tid == 0) s_unc = 0;
-    __syncthreads();
-    int cnt = 0;
-    for (int j = blockIdx.x * blockDim.x + tid; j < d.n; j += gridDim.x * blockDim.x)
-      cnt += (d.cf[j] == 0 && !(w.dsum[d.fine0 + j] > 0.0)) ? 1 : 0;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-    if ((tid & 63) == 0 && cnt) atomicAdd(&s_unc, cnt);
-    __syncthreads();
-    if (tid == 0 && s_unc) atomicAdd((unsigned long long*)&w.st[m].n_uncovered, (unsigned long long)s_unc);
   }
 }
 
@@ -2271,12 +2280,13 @@ hipError_t launch_rows_wg(const Work& w, int blocks, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_project(const Work& w, int blocks, int lanes_per_row, hipStream_t s) {
+hipError_t launch_project(const Work& w, int blocks, int unc_blocks, int lanes_per_row, hipStream_t s) {
   blocks = (blocks + 7) / 8 * 8;
+  const int grid = blocks + (unc_blocks < 1 ? 1 : unc_blocks);
   if (lanes_per_row == 1)
-    hipLaunchKernelGGL(k_project<1>, dim3(blocks), dim3(256), 0, s, w);
+    hipLaunchKernelGGL(k_project<1>, dim3(grid), dim3(256), 0, s, w, blocks);
   else
-    hipLaunchKernelGGL(k_project<8>, dim3(blocks), dim3(256), 0, s, w);
+    hipLaunchKernelGGL(k_project<8>, dim3(grid), dim3(256), 0, s, w, blocks);
   return hipGetLastError();
 }
 
