@@ -96,3 +96,33 @@ def test_approximate_inverse_build_with_the_literal_pattern():
     o = oracle.build_R_approx(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, 2, "diag", literal=True)
     assert np.array_equal(g["col_idx"], o["col_idx"])
     assert row_errors(p, g, o)[0].max() <= 1e-10
+
+
+def test_literal_pattern_with_a_strength_threshold():
+    from paper_2307_00229_amd import clair
+
+    p = P.small_2d(40, stencil=5, eps=0.1, angle=0.5, ell=3)
+    ctx = _ctx()
+    ctx.set_strength(0.25)
+    print("[gpu] literal pattern, theta=0.25, ell=3, FP64 form", flush=True)
+    res, infos, st = gpu_build([p], ctx=ctx, precision=clair.CLAIR_PREC_FP64)
+    assert st == 0, infos
+    o = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, theta=0.25, literal=True)
+    assert_matches_oracle(p, res[0], o, infos[0])
+
+
+def test_literal_pattern_on_a_strength_matrix():
+    from paper_2307_00229_amd import clair
+
+    from .test_gpu_strength import _dev_csr, _random_graph
+
+    ps = [P.random_sparse(300, 0.01, 41, ell=3), P.small_2d(40, stencil=9, eps=1e-2, angle=0.7, k=3, ell=3)]
+    graphs = [_random_graph(p, 7 + k) for k, p in enumerate(ps)]
+    ctx = _ctx()
+    ctx.set_graph([_dev_csr(*g, n=p.n) for g, p in zip(graphs, ps)])
+    print("[gpu] literal pattern on strength matrices, ell=3, FP64 form", flush=True)
+    res, infos, st = gpu_build(ps, ctx=ctx, precision=clair.CLAIR_PREC_FP64)
+    assert st == 0, infos
+    for p, g, gr, inf in zip(ps, res, graphs, infos):
+        o = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, strength=gr, literal=True)
+        assert_matches_oracle(p, g, o, inf)
