@@ -126,3 +126,22 @@ def test_literal_pattern_on_a_strength_matrix():
     for p, g, gr, inf in zip(ps, res, graphs, infos):
         o = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, strength=gr, literal=True)
         assert_matches_oracle(p, g, o, inf)
+
+
+def test_flag_values_and_switching_back():
+    from paper_2307_00229_amd import clair
+
+    lib = clair.load_library()
+    ctx = clair.Context()
+    for bad in (2, -1):
+        assert lib.clair_ctx_set_literal_pattern(ctx.handle, bad) == clair.CLAIR_ERR_INVALID
+    assert lib.clair_ctx_set_literal_pattern(None, 1) == clair.CLAIR_ERR_INVALID
+    ps = _cases(3)[:1]
+    _, _, st = gpu_build(ps, ctx=ctx, check=False)  # rejected values left the default
+    assert st == 0
+    ctx.set_literal_pattern(True)
+    _, _, st = gpu_build(ps, ctx=ctx, check=False)
+    assert st == clair.CLAIR_ERR_UNSUPPORTED
+    ctx.set_literal_pattern(False)
+    _, _, st = gpu_build(ps, ctx=ctx, check=False)
+    assert st == 0
