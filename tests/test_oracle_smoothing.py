@@ -75,3 +75,50 @@ def test_sweep_touches_only_its_subset_and_hand_value():
     # the same on A^T: (M^T x)_0 = 2 - 4 = -2, x_0 <- 1 + 0.5 * 2 / 2 = 1.5
     xt = S.jacobi_subset(M.T, np.ones(2), np.array([True, False]), 0.5)
     assert xt.tolist() == [1.5, 1.0]
+
+
+def _read_cff_cases():
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "cff_jacobi_hand.txt")
+    cases, cur = [], None
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        key, _, rest = line.partition(" ")
+        if key == "case":
+            cur = {"name": rest}
+            cases.append(cur)
+        elif key == "A":
+            cur["A"] = np.array([[float(v) for v in r.split()] for r in rest.split(";")])
+        elif key in ("cf",):
+            cur[key] = np.array([int(v) for v in rest.split()], dtype=np.int8)
+        elif key in ("B", "x"):
+            cur[key] = np.array([float(v) for v in rest.split()])
+        elif key in ("iterations", "transpose"):
+            cur[key] = int(rest)
+        else:
+            cur[key] = float(rest)
+    return cases
+
+
+def test_cff_order_hand_example():
+    """Hand-worked CFF iterations on non-diagonal 3x3 matrices (every value a
+    dyadic fraction, so exact in FP64): the sweep order C, F, F of Section 4's
+    smoother is pinned, and the orders F, F, C and F, C, F miss the values."""
+    cases = _read_cff_cases()
+    assert [c["name"] for c in cases] == ["sym", "ns_T", "sym2"]
+    for c in cases:
+        A = sp.csr_matrix(c["A"])
+        x = S.cff_jacobi(A, c["cf"], c["B"], c["iterations"], c["omega"], bool(c["transpose"]))
+        assert x.tolist() == c["x"].tolist(), c["name"]
+        # the same iteration with the sweeps reordered differs from the hand values
+        M = sp.csr_matrix(A.T if c["transpose"] else A)
+        Cm = c["cf"] != 0
+        for order in ((~Cm, ~Cm, Cm), (~Cm, Cm, ~Cm)):
+            y = c["B"].copy()
+            for _ in range(c["iterations"]):
+                for mask in order:
+                    y = S.jacobi_subset(M, y, mask, c["omega"])
+            assert y.tolist() != c["x"].tolist(), c["name"]
