@@ -181,7 +181,9 @@ static int32_t neighbourhood(int32_t i, int ell, const int32_t* rp, const int32_
     }
     lo = before;
     hi = len;
-    if (lo == hi) break;
+    /* literal: the second step also expands i itself (T's identity part),
+       so an empty first level does not end the search */
+    if (lo == hi && !(literal && depth == 1)) break;
   }
   if (literal) { /* C-points were interior vertices only */
     int32_t m = 0;

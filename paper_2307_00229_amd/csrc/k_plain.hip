@@ -55,7 +55,9 @@ __device__ int plain_bfs(const PlainWork& p, int i, int* N) {
     }
     lo = start;
     hi = s;
-    if (lo == hi) break;
+    // literal: the second step also expands i itself (T's identity part), so
+    // an empty first level does not end the search
+    if (lo == hi && !(p.literal && depth == 1)) break;
   }
   if (p.literal) {  // C-points were interior vertices only
     int m = 0;

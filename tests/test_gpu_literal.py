@@ -145,3 +145,21 @@ def test_flag_values_and_switching_back():
     ctx.set_literal_pattern(False)
     _, _, st = gpu_build(ps, ctx=ctx, check=False)
     assert st == 0
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.3])
+def test_literal_pattern_c_points_without_f_neighbours(theta):
+    # many C-points, so that some have no (strong) F-neighbour: T's identity
+    # part still lets the second step expand them; FP64 form against the
+    # oracle's literal search (pinned against boolean products) at ell = 3
+    from paper_2307_00229_amd import clair
+
+    ps = [P.random_sparse(300, 0.01, 60 + k, c_frac=0.55, ell=3) for k in range(2)]
+    ctx = _ctx()
+    ctx.set_strength(theta)
+    print(f"[gpu] literal pattern, dense C-points, theta={theta}, ell=3, FP64 form", flush=True)
+    res, infos, st = gpu_build(ps, ctx=ctx, precision=clair.CLAIR_PREC_FP64)
+    assert st == 0, infos
+    for p, g, inf in zip(ps, res, infos):
+        o = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, theta=theta, literal=True)
+        assert_matches_oracle(p, g, o, inf)

@@ -245,3 +245,69 @@ def test_literal_search_equals_the_boolean_products(theta):
             if ell <= 2:
                 d = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, None, ell, theta=theta)
                 assert np.array_equal(d["col_idx"], o["col_idx"]) and np.array_equal(d["val"], o["val"])
+
+
+def _lit_cols(p_n, rp, ci, va, cf, ell, theta):
+    o = oracle.build_R(p_n, rp, ci, va, cf, None, ell, theta=theta, literal=True, allow_singular=True)
+    C = np.nonzero(cf)[0]
+    out = {}
+    for r, c in enumerate(C):
+        cols = o["col_idx"][o["row_ptr"][r]:o["row_ptr"][r + 1]]
+        out[int(c)] = cols[cols != c]
+    return out
+
+
+def test_literal_search_c_point_without_f_neighbours():
+    # T = [S_fc, I] puts the C-point itself in T's column, so the first step
+    # of S^{ell-1} expands it even when it has no (strong) F-neighbour: its
+    # C-neighbours become interior vertices.  1D Laplacian, n = 6,
+    # C = {0, 1, 4}: C-point 0 reaches 2 through 1 at distance 3 (by hand:
+    # T's column 0 is {0}; S steps give {0, 1}, then {0, 1, 2}; F part {2})
+    n = 6
+    A = np.diag(np.full(n, 2.0)) - np.diag(np.ones(n - 1), 1) - np.diag(np.ones(n - 1), -1)
+    cf = np.array([1, 1, 0, 0, 1, 0], dtype=np.int8)
+    rp, ci, va = _csr(A)
+    for ell in (1, 2, 3, 4):
+        got = _lit_cols(n, rp, ci, va, cf, ell, 0.0)
+        want = dense.neighbourhoods_literal(A, cf, ell)
+        for c in want:
+            assert np.array_equal(got[c], want[c]), (ell, c)
+    assert _lit_cols(n, rp, ci, va, cf, 3, 0.0)[0].tolist() == [2]
+    assert _lit_cols(n, rp, ci, va, cf, 2, 0.0)[0].tolist() == []
+    # a C-point whose only F-neighbour is weak at theta = 0.5: C-point 0 has
+    # F-neighbour 1 (|a_01| = 0.1 against column 1's largest off-diagonal 1)
+    # and C-neighbour 2 (strong); through 2 it reaches F-point 3 at distance 3
+    B = np.zeros((6, 6))
+    for u, v, a in [(0, 1, 0.1), (0, 2, 1.0), (1, 0, 1.0), (1, 3, 1.0), (2, 0, 1.0), (2, 3, 1.0), (3, 1, 1.0),
+                    (3, 2, 1.0), (3, 4, 1.0), (4, 3, 1.0), (4, 5, 1.0), (5, 4, 1.0)]:
+        B[u, v] = -a
+    np.fill_diagonal(B, 4.0)
+    cf2 = np.array([1, 0, 1, 0, 0, 1], dtype=np.int8)
+    rp, ci, va = _csr(B)
+    for ell in (1, 2, 3, 4):
+        got = _lit_cols(6, rp, ci, va, cf2, ell, 0.5)
+        want = dense.neighbourhoods_literal(B, cf2, ell, 0.5)
+        for c in want:
+            assert np.array_equal(got[c], want[c]), (ell, c)
+    assert _lit_cols(6, rp, ci, va, cf2, 3, 0.5)[0].tolist() == [3]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_literal_search_dense_c_points(seed):
+    # many C-points, so that some have no F-neighbour or only weak ones: the
+    # literal search against the boolean products, ell = 1..4
+    rng = np.random.default_rng(100 + seed)
+    p = P.random_sparse(50, 0.08, 20 + seed, ell=2)
+    A = dense.to_dense(p.n, p.row_ptr, p.col_idx, p.val)
+    cf = (rng.random(p.n) < 0.55).astype(np.int8)
+    lacking = 0
+    for theta in (0.0, 0.3):
+        S = dense.strength_transposed(A, theta)
+        for c in np.nonzero(cf)[0]:
+            lacking += not np.any(S[:, c] & (cf == 0))
+        for ell in (1, 2, 3, 4):
+            got = _lit_cols(p.n, p.row_ptr, p.col_idx, p.val, cf, ell, theta)
+            want = dense.neighbourhoods_literal(A, cf, ell, theta)
+            for c in want:
+                assert np.array_equal(got[c], want[c]), (theta, ell, c)
+    assert lacking > 0
