@@ -368,6 +368,13 @@ int clair_ctx_stage_times(clair_ctx_t* ctx, const char** names, float* ms, int32
 int clair_ctx_set_tuning(clair_ctx_t* ctx, int32_t group, int32_t wg_threads, int32_t chunk);
 int clair_ctx_get_tuning(clair_ctx_t* ctx, int32_t* group, int32_t* wg_threads, int32_t* chunk);
 
+/* Bytes of device memory ctx holds for the FP64 blocks of rows above 64
+ * points (one slot per workgroup of the FP64 solver, each the square of the
+ * largest block a synchronous call has read back, rounded up to a multiple
+ * of 8 points; 0 until such a row occurs).  Grows, never shrinks, until
+ * clair_ctx_destroy.  NULL arguments return CLAIR_ERR_INVALID. */
+int clair_ctx_scratch_bytes(clair_ctx_t* ctx, int64_t* bytes);
+
 /*
  * Strength threshold theta of the neighbourhood search.  Algorithm 1
  * (Section 3.1.3) grows the pattern from a classical strength-of-connection

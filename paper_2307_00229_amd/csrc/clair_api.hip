@@ -146,6 +146,7 @@ struct clair_ctx {
   DevBuf ws;
   DevBuf scratch;  // FP64 blocks of oversized rows
   int64_t scratch_slots = 0;
+  int64_t scratch_stride = 0;  // doubles per slot (the largest block sized for, squared)
   HostPinned stage;     // descriptor/status upload
   HostPinned readback;  // status download
   hipEvent_t upload_done = nullptr;
@@ -323,6 +324,7 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
   w.agg_sums = reinterpret_cast<int32_t*>(base + b->L.agg_sums);
   w.scratch = static_cast<double*>(c->scratch.p);
   w.scratch_slots = c->scratch_slots;
+  w.scratch_stride = c->scratch_stride;
   w.nmat = nmat;
   w.nchunks = b->nchunks;
   w.chunk = c->chunk;
@@ -395,11 +397,22 @@ const MatStatus* host_status(clair_ctx* c, const Batch& b) {
 
 int occupancy_blocks(clair_ctx* c, int per_cu) { return std::max(8, c->cus * per_cu); }
 
-int ensure_scratch(clair_ctx* c, int slots) {
-  if (c->scratch_slots >= slots) return CLAIR_OK;
-  const size_t bytes = (size_t)slots * kMaxBlock * kMaxBlock * sizeof(double);
-  if (c->scratch.ensure(bytes) != hipSuccess) return CLAIR_ERR_NOMEM;
-  c->scratch_slots = slots;
+// one slot per workgroup of the FP64 solver, each holding a block of the
+// largest size read back (rounded up to a multiple of 8 points)
+int ensure_scratch(clair_ctx* c, int slots, int maxb) {
+  const int64_t side = std::min<int64_t>(kMaxBlock, ((int64_t)std::max(maxb, 1) + 7) / 8 * 8);
+  const int64_t stride = side * side;
+  if (c->scratch_slots >= slots && c->scratch_stride >= stride) return CLAIR_OK;
+  const int64_t want_slots = std::max<int64_t>(slots, c->scratch_slots);
+  const int64_t want_stride = std::max(stride, c->scratch_stride);
+  const size_t bytes = (size_t)want_slots * (size_t)want_stride * sizeof(double);
+  if (c->scratch.ensure(bytes) != hipSuccess) {
+    c->scratch_slots = 0;  // the old buffer is gone too
+    c->scratch_stride = 0;
+    return CLAIR_ERR_NOMEM;
+  }
+  c->scratch_slots = want_slots;
+  c->scratch_stride = want_stride;
   return CLAIR_OK;
 }
 
@@ -413,6 +426,7 @@ const Counters* host_counters(clair_ctx* c, const Batch& b) {
 int enqueue_numeric(clair_ctx* c, Batch& b, hipStream_t s, bool timing, const Counters* known) {
   b.w.scratch = static_cast<double*>(c->scratch.p);
   b.w.scratch_slots = c->scratch_slots;
+  b.w.scratch_stride = c->scratch_stride;
   if (!known || known->nA > 0) {
     if (c->group == 1) {
       HIPCHK(launch_rows8(b.w, c->wg_threads, c->cus, s));
@@ -540,7 +554,7 @@ int run_mixed(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* co
     c->binB_max = std::max(9, std::min(32, maxb));
     c->last_maxb = maxb;
     if (maxb > kLdsBlockMax) {
-      rc = ensure_scratch(c, std::max(1, c->cus));
+      rc = ensure_scratch(c, std::max(1, c->cus), maxb);
       if (rc) return rc;
     }
   }
@@ -1476,6 +1490,12 @@ int clair_ctx_get_strength(clair_ctx_t* c, double* theta) {
   return CLAIR_OK;
 }
 
+int clair_ctx_scratch_bytes(clair_ctx_t* c, int64_t* bytes) {
+  if (!c || !bytes) return CLAIR_ERR_INVALID;
+  *bytes = c->scratch.p ? c->scratch_slots * c->scratch_stride * (int64_t)sizeof(double) : 0;
+  return CLAIR_OK;
+}
+
 int clair_ctx_get_tuning(clair_ctx_t* c, int32_t* group, int32_t* wg_threads, int32_t* chunk) {
   if (!c) return CLAIR_ERR_INVALID;
   if (group) *group = c->group;
@@ -1667,7 +1687,7 @@ int clair_plan_create(clair_ctx_t* parent, int32_t nmat, const clair_csr_t* A, c
     c->binB_max = std::max(9, std::min(32, maxb));
     c->last_maxb = maxb;
     if (maxb > kLdsBlockMax) {
-      rc = ensure_scratch(c, std::max(1, c->cus));
+      rc = ensure_scratch(c, std::max(1, c->cus), maxb);
       if (rc) {
         clair_plan_destroy(pl);
         return rc;

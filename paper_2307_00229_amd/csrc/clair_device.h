@@ -185,8 +185,9 @@ struct Work {
   int32_t* agg_rp;         // [n_total + 1] member-list offsets, batch-wide
   int32_t* agg_list;       // [n_total] members (matrix-local indices), sorted per root
   int32_t* agg_sums;       // scan scratch
-  double* scratch;        // FP64 blocks for oversized rows: scratch_slots * kMaxBlock^2 (may be null)
+  double* scratch;        // FP64 blocks for oversized rows: scratch_slots slots of scratch_stride doubles (may be null)
   int64_t scratch_slots;
+  int64_t scratch_stride; // doubles per slot: the square of the largest block the host sized it for
   int32_t nmat;
   int32_t nchunks;
   int32_t chunk;

@@ -1847,8 +1847,15 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
           atomicMax(&st->refine_max, itm);
         __syncthreads();
       } else {
+      if (big && (int64_t)s * s > w.scratch_stride) {
+        // the scratch was sized for smaller blocks (an asynchronous call
+        // after a smaller batch): report the row instead of solving it
+        if (tid == 0) flag_row(st, ST_UNSUPPORTED, i);
+        __syncthreads();
+        continue;
+      }
       const int ld = big ? s : (kLdsBlockMax + 1);
-      double* K = big ? (w.scratch + (int64_t)blockIdx.x * kMaxBlock * kMaxBlock) : sK;
+      double* K = big ? (w.scratch + (int64_t)blockIdx.x * w.scratch_stride) : sK;
       for (int t = tid; t < s * ld; t += kWT) K[t] = 0.0;
       for (int t = tid; t < s; t += kWT) sf[t] = 0.0;
       __syncthreads();

@@ -99,15 +99,33 @@ def test_cfg3_shape_ell3_workgroup_mixed_path():
 
 
 def test_cfg3_shape_ell5_scratch_path():
+    from paper_2307_00229_amd import clair
+
+    # the FP64 scratch is sized to the largest block read back (108 points,
+    # rounded up to 112): one slot of 112^2 doubles per workgroup
+    ctx = clair.Context()
     p = P.cfg3(N=150, ell=5)
-    res, infos = _check([p], precision=0)
+    res, infos = _check([p], precision=0, ctx=ctx)
     assert infos[0]["max_block"] == 108
+    sb = ctx.scratch_bytes()
+    assert 0 < sb <= 128 * 2 ** 20, sb
+    assert sb % (112 * 112 * 8) == 0, sb
 
 
 def test_cfg5_shape_ell4_scratch_path():
+    from paper_2307_00229_amd import clair
+
+    ctx = clair.Context()
     p = P.cfg5(N=24, ell=4)
-    res, infos = _check([p], precision=0)
+    res, infos = _check([p], precision=0, ctx=ctx)
     assert infos[0]["max_block"] == 98
+    sb = ctx.scratch_bytes()
+    assert 0 < sb <= 128 * 2 ** 20 and sb % (104 * 104 * 8) == 0, sb
+    # a batch with a larger block afterwards grows the slots (112^2) and solves
+    q = P.cfg3(N=150, ell=5)
+    _check([q], precision=0, ctx=ctx)
+    sb2 = ctx.scratch_bytes()
+    assert sb < sb2 <= 128 * 2 ** 20 and sb2 % (112 * 112 * 8) == 0, sb2
 
 
 @pytest.mark.parametrize("group,wg,chunk", [(1, 256, 2048), (1, 64, 512), (4, 256, 1024), (4, 64, 2048),
