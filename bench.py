@@ -3,15 +3,18 @@
 
 One step = the whole setup (neighbourhood search, C/F indexing, block gather,
 FP32 factorisation + FP64 refinement, R write, constraint projection) for
-every matrix of the workload, inputs resident in HBM.  Default workload: three
-512x512 5-point upwind advection-diffusion matrices (eps = 1e-6, 1e-2, 1),
-C-points every 2nd node, ell = 2, B = 1, set up in one batched pass.
+every matrix of the workload, inputs resident in HBM.  Default workload: the
+batch of 64 5-point upwind advection-diffusion matrices (sides drawn from
+64..768, eps log-uniform in [1e-6, 1], random flow angle, ell 1 or 2, seed 0;
+3,189,226 rows of R), the largest workload, set up in one batched pass.
 
 Prints one JSON line.  Besides the contract fields it carries
 * the plain FP64 per-row form measured on the same inputs and the ratio;
 * accuracy gates of the measured result against the FP64 oracle;
-* "roofline" for the dominant kernel (HIP events on the library's stream);
-* "cpu_baseline": the oracle on the host cores;
+* "roofline" for the dominant kernel: the stage with the largest time per
+  step (HIP events on the library's stream), with the whole step's fraction
+  and a measured device-copy bandwidth beside the 8 TB/s peak;
+* "cpu_baseline": the oracle on all host cores, and on one core;
 * "plan_numeric_only": repeated setups on a fixed pattern (symbolic phase
   once, numeric phase per step), beside the headline, never as it.
 """
@@ -60,10 +63,10 @@ def algorithmic_bytes(problems, n_c_list, nnz_list):
     return whole, kernel
 
 
-def read_traffic_profile(workload, kernel_src_hash):
-    """Counter bytes per launch of the numeric kernel from a committed rocprofv3
+def read_traffic_profile(workload, stage, kernel_src_hash):
+    """Counter bytes per launch of a stage's kernel from a committed rocprofv3
     summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"k_numeric_{workload}_counters.json")
+    path = os.path.join(ROOT, "profiles", f"{stage}_{workload}_counters.json")
     if not os.path.exists(path):
         return None
     try:
@@ -75,6 +78,49 @@ def read_traffic_profile(workload, kernel_src_hash):
     return d.get("traffic_bytes_per_launch")
 
 
+def bin_rows(outs, tuning):
+    """Rows of R in each size bin of the mixed path: (A) |N| up to the small
+    solver's bound, (B) up to 32 points, (C) beyond (the workgroup solver)."""
+    import numpy as np
+
+    g = tuning["group"]
+    lim = 8 if g <= 4 else g
+    a = b = c = 0
+    for o in outs:
+        s = np.diff(o.trimmed()[0].cpu().numpy()) - 1
+        a += int(np.count_nonzero(s <= lim))
+        b += int(np.count_nonzero((s > lim) & (s <= 32)))
+        c += int(np.count_nonzero(s > 32))
+    return a, b, c
+
+
+def stage_kernel_name(stage, tuning):
+    g = tuning["group"]
+    small = {1: "k_rows8", 4: "k_quad8"}.get(g, f"k_numeric<{g},...> (bin A)")
+    return {"count": "k_count", "count_big": "k_count_big", "scan": "k_scan", "numeric": small,
+            "numeric32": "k_numeric<16|32,128,SM> (bin B)", "rows_wg": "k_rows_wg", "project": "k_project",
+            "upload": "descriptor upload"}.get(stage, stage)
+
+
+def measure_copy_bandwidth(torch, dev, stream, mib=1024, reps=5):
+    """GB/s of a device-to-device copy of `mib` MiB (bytes read + written)."""
+    n = mib * 2 ** 20 // 4
+    x = torch.ones(n, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    best = float("inf")
+    with torch.cuda.stream(stream):
+        y.copy_(x)
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            y.copy_(x)
+            e1.record(stream)
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1) / 1e3)
+    del x, y
+    return 2 * n * 4 / best / 1e9
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for fn in ("k_mixed.hip", "clair_device.h"):
@@ -83,7 +129,20 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(problems, budget_s):
+    """The oracle as it stands: the whole workload repeated on all host
+    threads for about budget_s, then on one thread over the matrices in turn
+    for about budget_s (a bounded sample of the same workload)."""
     import oracle
 
     nthreads = oracle.max_threads()
@@ -98,8 +157,20 @@ def cpu_baseline(problems, budget_s):
         el = time.perf_counter() - t0
         if el >= budget_s:
             break
+    rows1, n1 = 0, 0
+    t1 = time.perf_counter()
+    while True:
+        p = problems[n1 % len(problems)]
+        rows1 += oracle.build_R_problem(p, nthreads=1)["n_c"]
+        n1 += 1
+        el1 = time.perf_counter() - t1
+        if el1 >= budget_s:
+            break
     return dict(value=rows / el, unit="rows/s", cores=nthreads, kind="oracle",
-                sample=f"full workload x{reps} ({rows} R rows, {el:.1f} s, OpenMP over rows)")
+                sample=f"full workload x{reps} ({rows} R rows, {el:.1f} s, OpenMP over rows)",
+                single_core={"value": rows1 / el1, "unit": "rows/s", "cores": 1,
+                             "sample": f"{n1} matrices of the workload in order ({rows1} R rows, {el1:.1f} s)"},
+                cpu_model=cpu_model(), host_threads=os.cpu_count())
 
 
 def check_against_oracle(problems, outs):
@@ -229,7 +300,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="cfg4", choices=sorted(WORKLOADS))
     ap.add_argument("--plain-steps", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -385,21 +456,40 @@ def main():
             y.copy_(x)
             torch.cuda.synchronize()
 
+        # achievable HBM bandwidth on this device: a 1 GiB device-to-device
+        # copy (read + write), best of 5, events on the same stream
+        copy_gbs = measure_copy_bandwidth(torch, dev, stream)
+
     gates = check_against_oracle(problems, outs)
     if plan_res is not None:
         plan_res["gates"] = check_against_oracle(problems, plan_res.pop("_outs"))
     gates_plain = check_against_oracle(problems, outs_p) if outs_p is not None else None
 
-    whole_bytes, kern_bytes = algorithmic_bytes(problems, n_c_list, nnz_list)
-    t_kern = stages.get("numeric", float("nan")) / 1e3
+    whole_bytes, _ = algorithmic_bytes(problems, n_c_list, nnz_list)
+    # units per launch: the rows each stage processes (the solvers take the
+    # rows of their size bin; every other stage passes over all rows)
+    bins = bin_rows(outs, tuning)
+    per_row = whole_bytes / rows
+    stage_units = {"numeric": bins[0], "numeric32": bins[1], "rows_wg": bins[2], "count_big": bins[2]}
+    dom = max(stages, key=stages.get) if stages else None
+    t_kern = stages[dom] / 1e3 if dom else float("nan")
+    units = stage_units.get(dom, rows)
+    kern_bytes = per_row * units
     achieved = kern_bytes / t_kern / 1e9 if t_kern > 0 else None
     src_hash = kernel_source_hash()
     # the committed counters were taken at theta = 0
-    traffic = read_traffic_profile(args.workload, src_hash) if (args.theta == 0 and not args.aggregates) else None
+    traffic = (read_traffic_profile(args.workload, dom, src_hash)
+               if (dom and args.theta == 0 and not args.aggregates) else None)
     roofline = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=(achieved / HBM_PEAK_GBS) if achieved else None, traffic=traffic,
-                    kernel="k_numeric", kernel_ms=t_kern * 1e3, algorithmic_bytes_per_launch=kern_bytes,
-                    step_GBps=whole_bytes / t_mixed / 1e9, stage_ms=stages)
+                    kernel=stage_kernel_name(dom, tuning), stage=dom, kernel_ms=t_kern * 1e3,
+                    rows_per_launch=units, algorithmic_bytes_per_row=per_row,
+                    algorithmic_bytes_per_launch=kern_bytes,
+                    step_algorithmic_bytes=whole_bytes, step_GBps=whole_bytes / t_mixed / 1e9,
+                    step_frac=whole_bytes / t_mixed / 1e9 / HBM_PEAK_GBS,
+                    measured_copy_GBps=copy_gbs,
+                    step_frac_of_measured_copy=(whole_bytes / t_mixed / 1e9 / copy_gbs) if copy_gbs else None,
+                    rows_by_bin=dict(A=bins[0], B=bins[1], C=bins[2]), stage_ms=stages)
 
     cpu = None
     if not args.no_cpu_baseline:
