@@ -368,6 +368,18 @@ int clair_ctx_stage_times(clair_ctx_t* ctx, const char** names, float* ms, int32
 int clair_ctx_set_tuning(clair_ctx_t* ctx, int32_t group, int32_t wg_threads, int32_t chunk);
 int clair_ctx_get_tuning(clair_ctx_t* ctx, int32_t* group, int32_t* wg_threads, int32_t* chunk);
 
+/*
+ * Lane layout of the bin-B solver (rows whose |N| lies above the bin-A bound
+ * and at most 32): binB_lanes = 8, 16 or 32 lanes per row, each lane holding
+ * ceil(b / binB_lanes) rows of the block, where b = 16, 20, 24 or 32 is the
+ * smallest bound that holds the largest block the last synchronous call read
+ * back (8 lanes become 16 at b = 32, 32 lanes become 16 at b = 16).  0 keeps
+ * the current value; default 32.  Other values return CLAIR_ERR_INVALID and
+ * change nothing.
+ */
+int clair_ctx_set_bin_shape(clair_ctx_t* ctx, int32_t binB_lanes);
+int clair_ctx_get_bin_shape(clair_ctx_t* ctx, int32_t* binB_lanes);
+
 /* Bytes of device memory ctx holds for the FP64 blocks of rows above 64
  * points (one slot per workgroup of the FP64 solver, each the square of the
  * largest block a synchronous call has read back, rounded up to a multiple

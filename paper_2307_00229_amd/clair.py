@@ -32,7 +32,7 @@ EXPORTED = [
     "clair_ctx_set_strength", "clair_ctx_get_strength", "clair_transpose", "clair_build_P",
     "clair_spgemm", "clair_galerkin", "clair_smooth_B", "clair_build_R_agg", "clair_project_constraints",
     "clair_build_R_diag", "clair_build_R_approx", "clair_build_R_kkt", "clair_ctx_set_graph",
-    "clair_ctx_set_literal_pattern", "clair_ctx_scratch_bytes",
+    "clair_ctx_set_literal_pattern", "clair_ctx_scratch_bytes", "clair_ctx_set_bin_shape", "clair_ctx_get_bin_shape",
     "clair_autotune", "clair_graph_create", "clair_graph_launch", "clair_graph_destroy", "clair_graph_info",
     "clair_plan_create", "clair_plan_execute", "clair_plan_info", "clair_plan_destroy",
     "clair_strerror", "clair_last_error",
@@ -102,6 +102,8 @@ def load_library(path: str = LIB_PATH):
         "clair_ctx_set_tuning": ([P, I32, I32, I32], ctypes.c_int),
         "clair_ctx_get_tuning": ([P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)], ctypes.c_int),
         "clair_ctx_scratch_bytes": ([P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+        "clair_ctx_set_bin_shape": ([P, I32], ctypes.c_int),
+        "clair_ctx_get_bin_shape": ([P, ctypes.POINTER(I32)], ctypes.c_int),
         "clair_ctx_set_strength": ([P, ctypes.c_double], ctypes.c_int),
         "clair_ctx_get_strength": ([P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "clair_autotune": ([P, I32, ctypes.POINTER(CsrIn), ctypes.POINTER(P), ctypes.POINTER(P),
@@ -288,6 +290,16 @@ class Context:
         g, t, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         self._lib.clair_ctx_get_tuning(self._h, ctypes.byref(g), ctypes.byref(t), ctypes.byref(c))
         return dict(group=g.value, wg_threads=t.value, chunk=c.value)
+
+    def set_bin_shape(self, binB_lanes: int):
+        st = self._lib.clair_ctx_set_bin_shape(self._h, binB_lanes)
+        if st:
+            raise ClairError(st, f"clair_ctx_set_bin_shape({binB_lanes})")
+
+    def get_bin_shape(self) -> int:
+        g = ctypes.c_int32()
+        self._lib.clair_ctx_get_bin_shape(self._h, ctypes.byref(g))
+        return g.value
 
     def scratch_bytes(self) -> int:
         b = ctypes.c_int64()

@@ -70,7 +70,7 @@ struct HostPinned {
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-  size_t desc, st, cnt, chunk_nc, chunk_nnz, chunk_rbase, chunk_nzbase, chunk_mat, chunk_bins, row_block_chunk, clocal, lnz, dsum, rsum,
+  size_t desc, st, cnt, chunk_nc, chunk_nnz, chunk_rbase, chunk_nzbase, chunk_mat, chunk_bins, row_block_chunk, clocal, lnz, chead,
       slotA, slotB, binC, bigq, big_size, ovf, cmax, agg_cnt, agg_rp, agg_list, agg_sums, total;
   size_t head_bytes;  // desc + st + counters (the uploaded head)
   int64_t capC;
@@ -101,8 +101,7 @@ Layout make_layout(int nmat, int nchunks, int64_t n_total, int GA, bool any_agg)
   L.row_block_chunk = take(sizeof(int32_t) * (n_total / 256 + 2));
   L.clocal = take(sizeof(int32_t) * (n_total + 1));
   L.lnz = take(sizeof(int32_t) * (n_total + 1));
-  L.dsum = take(sizeof(double) * (n_total + 1));
-  L.rsum = take(sizeof(double) * (n_total + 1));
+  L.chead = take(sizeof(int32_t) * (n_total + 1));
   const int SA = GA <= 4 ? 8 : GA;  // slot stride of bin A
   L.slotA = take(sizeof(int32_t) * (SA ? (n_total + 1) * SA : 1));
   L.slotB = take(sizeof(int32_t) * (n_total + 1) * (GA < 32 ? 32 : 1));
@@ -139,11 +138,14 @@ struct clair_ctx {
   std::vector<clair_csr_t> graph;  // strength matrices of the search, one per matrix (empty: A's graph)
   int literal = 0;  // the literal S^{ell-1} T pattern (the per-row FP64 form; a no-op at ell <= 2)
   int binB_max = 32;  // largest block of the last batch whose sizes were read back (9..32)
+  int binB_lanes = 32;  // lanes per row of the bin-B solver (8, 16 or 32)
   int last_maxb = 0;  // the same, unclamped (0: none read back yet)
   int wg_threads = 256;
   int chunk = 1024;
   // memory
   DevBuf ws;
+  DevBuf links;    // the projection's column lists: one int2 per R entry of a batch
+  int64_t link_cap = 0;
   DevBuf scratch;  // FP64 blocks of oversized rows
   int64_t scratch_slots = 0;
   int64_t scratch_stride = 0;  // doubles per slot (the largest block sized for, squared)
@@ -246,6 +248,7 @@ struct Batch {
   int nmat;
   int nchunks;
   int64_t n_total;
+  int64_t cap_sum = 0;  // R capacities summed over the batch (bounds the R entries of an asynchronous call)
   bool any_B;
   bool any_agg = false;
   Layout L;
@@ -280,9 +283,11 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
   b->n_total = 0;
   b->any_B = false;
   b->any_agg = false;
+  b->cap_sum = 0;
   for (int m = 0; m < nmat; ++m) {
     b->nchunks += (A[m].n + c->chunk - 1) / c->chunk;
     b->n_total += A[m].n;
+    b->cap_sum += std::max<int64_t>(0, R[m].nnz_capacity);
     b->any_B |= (B && B[m]);
     b->any_agg |= (agg && agg[m]);
   }
@@ -309,8 +314,9 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
   w.row_block_chunk = reinterpret_cast<int32_t*>(base + b->L.row_block_chunk);
   w.clocal = reinterpret_cast<int32_t*>(base + b->L.clocal);
   w.lnz = reinterpret_cast<int32_t*>(base + b->L.lnz);
-  w.dsum = reinterpret_cast<double*>(base + b->L.dsum);
-  w.rsum = reinterpret_cast<double*>(base + b->L.rsum);
+  w.chead = reinterpret_cast<int32_t*>(base + b->L.chead);
+  w.clink = static_cast<int2*>(c->links.p);
+  w.link_cap = c->link_cap;
   w.slotA = reinterpret_cast<int32_t*>(base + b->L.slotA);
   w.slotB = reinterpret_cast<int32_t*>(base + b->L.slotB);
   w.binC = reinterpret_cast<int32_t*>(base + b->L.binC);
@@ -337,8 +343,11 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
   Counters* hc = reinterpret_cast<Counters*>(h + (b->L.cnt - b->L.desc));
   int chunk0 = 0;
   int64_t fine0 = 0;
+  int64_t link0 = 0;
   for (int m = 0; m < nmat; ++m) {
     MatDesc d{};
+    d.link_base = link0;
+    link0 += std::max<int64_t>(0, R[m].nnz_capacity);
     d.rp = A[m].row_ptr;
     d.ci = A[m].col_idx;
     d.va = A[m].val;
@@ -416,6 +425,24 @@ int ensure_scratch(clair_ctx* c, int slots, int maxb) {
   return CLAIR_OK;
 }
 
+// Column lists of the projection: one int2 per R entry the caller's
+// capacities allow, numbered through the batch (int32 numbers).
+int ensure_links(clair_ctx* c, Batch& b) {
+  if (!b.any_B) return CLAIR_OK;
+  const int64_t entries = b.cap_sum;
+  if (entries > INT32_MAX) return CLAIR_ERR_UNSUPPORTED;
+  if (c->link_cap < entries) {
+    if (c->links.ensure(sizeof(int2) * (size_t)std::max<int64_t>(entries, 1)) != hipSuccess) {
+      c->link_cap = 0;
+      return CLAIR_ERR_NOMEM;
+    }
+    c->link_cap = entries;
+  }
+  b.w.clink = static_cast<int2*>(c->links.p);
+  b.w.link_cap = c->link_cap;
+  return CLAIR_OK;
+}
+
 const Counters* host_counters(clair_ctx* c, const Batch& b) {
   return reinterpret_cast<const Counters*>(static_cast<char*>(c->readback.p) + (b.L.cnt - b.L.desc));
 }
@@ -441,9 +468,18 @@ int enqueue_numeric(clair_ctx* c, Batch& b, hipStream_t s, bool timing, const Co
   if (c->group < 32 && (!known || known->nB > 0)) {
     // bin B: the smallest block bound that holds the largest block seen (rows
     // beyond it go to the workgroup solver, so any bound is correct)
-    const int bg = c->binB_max <= 16 ? 16 : 32;
+    // block bound 16, 20, 24 or 32 (the smallest that holds the largest
+    // block read back).  binB_lanes = 32: one lane per block row (16 lanes at
+    // the bound 16); 8 or 16: ceil(bound / lanes) block rows per lane (8
+    // lanes at 32 points would need more LDS than a workgroup has: 16 then)
     const int bsm = c->binB_max <= 16 ? 16 : c->binB_max <= 20 ? 20 : c->binB_max <= 24 ? 24 : 32;
-    HIPCHK(launch_numeric(b.w, 1, bg, bsm, 128, c->cus, s));
+    if (c->binB_lanes == 32) {
+      HIPCHK(launch_numeric(b.w, 1, bsm == 16 ? 16 : 32, bsm, 128, c->cus, s));
+    } else {
+      const int bg = (bsm == 32 && c->binB_lanes == 8) ? 16 : c->binB_lanes;
+      const int br = (bsm + bg - 1) / bg;
+      HIPCHK(launch_lanes(b.w, 1, bg, br, bsm, 64, c->cus, s));
+    }
     if (capture_check(c->capturing, s, "k_numeric32", __LINE__)) return CLAIR_ERR_HIP;
     timing_mark(c, timing, s, "numeric32");
   }
@@ -452,7 +488,7 @@ int enqueue_numeric(clair_ctx* c, Batch& b, hipStream_t s, bool timing, const Co
   timing_mark(c, timing, s, "rows_wg");
   if (b.any_B) {
     // rows of up to 8 points: one thread per row; longer rows: eight lanes each
-    HIPCHK(launch_project(b.w, occupancy_blocks(c, 4), occupancy_blocks(c, 4), c->last_maxb > 8 ? 8 : 1, s));
+    HIPCHK(launch_project(b.w, s));
     if (capture_check(c->capturing, s, "k_project", __LINE__)) return CLAIR_ERR_HIP;
     timing_mark(c, timing, s, "project");
   }
@@ -558,6 +594,8 @@ int run_mixed(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* co
       if (rc) return rc;
     }
   }
+  rc = ensure_links(c, b);
+  if (rc) return rc;
   Counters known{};
   if (!async) known = *host_counters(c, b);
   rc = enqueue_numeric(c, b, s, timing, async ? nullptr : &known);
@@ -754,6 +792,7 @@ void clair_ctx_destroy(clair_ctx_t* c) {
   (void)hipDeviceSynchronize();
   c->ws.release();
   c->scratch.release();
+  c->links.release();
   c->plain_ws.release();
   c->plain_k.release();
   c->stage.release();
@@ -1490,6 +1529,18 @@ int clair_ctx_get_strength(clair_ctx_t* c, double* theta) {
   return CLAIR_OK;
 }
 
+int clair_ctx_set_bin_shape(clair_ctx_t* c, int32_t binB_lanes) {
+  if (!c || !(binB_lanes == 0 || binB_lanes == 8 || binB_lanes == 16 || binB_lanes == 32)) return CLAIR_ERR_INVALID;
+  if (binB_lanes) c->binB_lanes = binB_lanes;
+  return CLAIR_OK;
+}
+
+int clair_ctx_get_bin_shape(clair_ctx_t* c, int32_t* binB_lanes) {
+  if (!c || !binB_lanes) return CLAIR_ERR_INVALID;
+  *binB_lanes = c->binB_lanes;
+  return CLAIR_OK;
+}
+
 int clair_ctx_scratch_bytes(clair_ctx_t* c, int64_t* bytes) {
   if (!c || !bytes) return CLAIR_ERR_INVALID;
   *bytes = c->scratch.p ? c->scratch_slots * c->scratch_stride * (int64_t)sizeof(double) : 0;
@@ -1581,6 +1632,7 @@ int clair_graph_create(clair_ctx_t* parent, int32_t nmat, const clair_csr_t* A, 
   g->ctx->theta = parent->theta;
   g->ctx->graph = parent->graph;
   g->ctx->literal = parent->literal;
+  g->ctx->binB_lanes = parent->binB_lanes;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   clair_opts_t o{};
   o.stream = stream;
@@ -1666,6 +1718,7 @@ int clair_plan_create(clair_ctx_t* parent, int32_t nmat, const clair_csr_t* A, c
     c->theta = parent->theta;
     c->graph = parent->graph;
     c->literal = parent->literal;
+    c->binB_lanes = parent->binB_lanes;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     Batch& b = pl->b;
     rc = prepare(c, nmat, A, cf, nullptr, ell, R, &b);
@@ -1737,7 +1790,10 @@ int clair_plan_execute(clair_plan_t* pl, int32_t nmat, const clair_csr_t* A, con
   std::memcpy(h, pl->head.data(), pl->head.size());
   MatDesc* hd = reinterpret_cast<MatDesc*>(h);
   b.any_B = false;
+  b.cap_sum = 0;
   for (int m = 0; m < nmat; ++m) {
+    hd[m].link_base = b.cap_sum;
+    b.cap_sum += R[m].nnz_capacity;
     hd[m].rp = A[m].row_ptr;
     hd[m].ci = A[m].col_idx;
     hd[m].va = A[m].val;
@@ -1767,11 +1823,13 @@ int clair_plan_execute(clair_plan_t* pl, int32_t nmat, const clair_csr_t* A, con
   rc = upload(c, b, s);
   if (rc) return rc;
   timing_mark(c, timing, s, "upload");
-  // zero projection sums (k_count did that in a full call) and R.row_ptr[n_c]
-  // of the (possibly new) R buffers
+  // empty the projection's column lists (k_count does that in a full call)
+  // and write R.row_ptr[n_c] of the (possibly new) R buffers
   HIPCHK(launch_clear_sums(b.w, b.n_total, occupancy_blocks(c, 4), s));
   if (capture_check(c->capturing, s, "k_clear_sums", __LINE__)) return CLAIR_ERR_HIP;
   timing_mark(c, timing, s, "clear");
+  rc = ensure_links(c, b);
+  if (rc) return rc;
   const Counters* known = async ? nullptr : reinterpret_cast<const Counters*>(pl->head.data() + (b.L.cnt - b.L.desc));
   rc = enqueue_numeric(c, b, s, timing, known);
   if (rc) return rc;

@@ -9,7 +9,9 @@
 //   clocal / lnz      per chunk, the C-points of the chunk in ascending order
 //                     and the exclusive prefix of (|N(i)|+1) inside the chunk,
 //                     stored at the chunk's own fine offsets
-//   dsum / rsum       FP64 column accumulators of the projection, per fine point
+//   chead / clink     the projection's column lists: per fine point the last R
+//                     entry of its column, per R entry the previous one and
+//                     the C-point of its row (a list per F-column, in no order)
 //   slots A / B       sorted neighbourhoods of rows small enough for the
 //                     lane-group solvers, per fine point
 //   bin C             rows queued for the workgroup-per-row solver
@@ -54,6 +56,7 @@ struct MatDesc {
   const int32_t* grp;
   const int32_t* gci;
   const double* gva;
+  int64_t link_base;   // first entry of this matrix in the projection's column lists (capacities summed)
 };
 
 // Pointers into device (global) memory.  Pointers that kernels load from a
@@ -93,6 +96,7 @@ struct GDesc {
   gptr<const int32_t> grp;
   gptr<const int32_t> gci;
   gptr<const double> gva;
+  int64_t link_base;
 };
 
 __device__ __forceinline__ GDesc gview(const MatDesc& m) {
@@ -121,6 +125,7 @@ __device__ __forceinline__ GDesc gview(const MatDesc& m) {
   g.gci = to_global(m.gci);
   g.gva = to_global(m.gva);
   g.agg_list = to_global(m.agg_list);
+  g.link_base = m.link_base;
   return g;
 }
 
@@ -172,8 +177,9 @@ struct Work {
   int32_t* row_block_chunk;  // [n_total / 256 + 2] chunk holding global row 256 b
   int32_t* clocal;        // [n_total] chunk-local C-points (negative while unsized)
   int32_t* lnz;           // [n_total] chunk-local prefix of |N(i)|+1
-  double* dsum;           // [n_total]
-  double* rsum;           // [n_total]
+  int32_t* chead;         // [n_total] projection lists: the last R entry (batch-wide number) of each F-column, -1 = none
+  int2* clink;            // [link_cap] per R entry (matrix m's entry p at desc[m].link_base + p): the column's
+                          // previous entry and the row's C-point
   int32_t* slotA;         // [n_total * GA]
   int32_t* slotB;         // [n_total * 32]
   int32_t* binC;          // [capC] rows for the workgroup solver
@@ -188,6 +194,7 @@ struct Work {
   double* scratch;        // FP64 blocks for oversized rows: scratch_slots slots of scratch_stride doubles (may be null)
   int64_t scratch_slots;
   int64_t scratch_stride; // doubles per slot: the square of the largest block the host sized it for
+  int64_t link_cap;       // entries of clink (the R capacities summed over the batch when any B is given)
   int32_t nmat;
   int32_t nchunks;
   int32_t chunk;

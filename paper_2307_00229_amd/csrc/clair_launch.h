@@ -11,6 +11,7 @@ constexpr int kMaxChunk = 2048;   // fine points per symbolic-pass workgroup (up
 constexpr int kLdsBlockMax = 64;  // workgroup FP64 solver keeps blocks up to this size in LDS
 
 // mixed (default) path
+// empties the projection's column lists and writes R.row_ptr[n_c] (plan execute)
 hipError_t launch_clear_sums(const Work& w, int64_t n_total, int blocks, hipStream_t s);
 hipError_t launch_validate(const Work& w, int blocks, hipStream_t s);
 // member lists of the aggregates of the matrices given with them (w.agg_*)
@@ -22,11 +23,15 @@ hipError_t launch_count_big(const Work& w, int blocks, hipStream_t s);
 hipError_t launch_scan(const Work& w, hipStream_t s);
 // which = 0: bin A with group = GA; which = 1: bin B with group = 32
 hipError_t launch_numeric(const Work& w, int which, int group, int sm, int wg_threads, int cus, hipStream_t s);
+// group lanes per row with rows_per_lane block rows each (bins A and B)
+hipError_t launch_lanes(const Work& w, int which, int group, int rows_per_lane, int sm, int wg_threads, int cus,
+                        hipStream_t s);
 // one thread per row with |N| <= 8 (GA == 1); four lanes per row (GA == 4)
 hipError_t launch_quad8(const Work& w, int wg_threads, int cus, hipStream_t s);
 hipError_t launch_rows8(const Work& w, int wg_threads, int cus, hipStream_t s);
 hipError_t launch_rows_wg(const Work& w, int blocks, hipStream_t s);
-hipError_t launch_project(const Work& w, int blocks, int unc_blocks, int lanes_per_row, hipStream_t s);
+// the constraint projection over the column lists (one workgroup per chunk)
+hipError_t launch_project(const Work& w, hipStream_t s);
 
 // CSR transpose of an m x ncol matrix: trp[ncol+1], tci/tva[nnz]; scratch of
 // transpose_scratch_ints(ncol) ints (column cursors, a flag set to 1 for an

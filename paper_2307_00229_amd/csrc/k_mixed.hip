@@ -34,6 +34,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <utility>
 
 #include "clair_device.h"
 #include "clair_launch.h"
@@ -233,6 +234,22 @@ __device__ __forceinline__ bool matrix_live(const MatStatus& st) {
   return st.status != ST_CAPACITY && st.status != ST_INVALID;
 }
 
+// F-entry (i, j) of R at position pos of its matrix: the value, and with a
+// constraint vector the entry joins the list of column j for the projection
+// (list entry link_base + pos, below the matrix's R capacity; one atomic
+// exchange on the list head; the projection orders each list itself, so the
+// exchange order does not matter)
+__device__ __forceinline__ void put_f_entry(const Work& w, const GDesc& d, int64_t fine0, int pos, int j, int i,
+                                            double z) {
+  d.Rci[pos] = j;
+  d.Rva[pos] = z;
+  if (d.B) {
+    const int64_t eg = d.link_base + pos;
+    const int prev = atomicExch(&w.chead[fine0 + j], (int32_t)eg);
+    w.clink[eg] = make_int2(prev, i);
+  }
+}
+
 // Per-lane cache of the chunk a run of consecutive rows lies in: reloaded only
 // when the row index crosses into another chunk, so a row costs one level of
 // (coalesced) per-row loads instead of the chunk -> matrix -> descriptor chain.
@@ -364,9 +381,9 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
     return;
   }
 
-  // clear the projection accumulators of this chunk's fine points
+  // empty the projection's column lists of this chunk's fine points
   if (d.B) {
-    for (int j = f0 + tid; j < f1; j += kNT) { w.dsum[d.fine0 + j] = 0.0; w.rsum[d.fine0 + j] = 0.0; }
+    for (int j = f0 + tid; j < f1; j += kNT) w.chead[d.fine0 + j] = -1;
   }
 
   // compaction of the chunk's C-points, ascending
@@ -658,7 +675,7 @@ struct NumGroupBuf {
 // pattern is an immediate, so k must fold to a constant (unrolled loops).
 template <int G>
 __device__ __forceinline__ int gbi(int v, int k) {
-  static_assert(G == 8 || G == 16 || G == 32, "group size");
+  static_assert(G == 2 || G == 4 || G == 8 || G == 16 || G == 32, "group size");
 #define CLAIR_SWZ(K) \
   case K: return __builtin_amdgcn_ds_swizzle(v, (32 - G) | ((K) << 5));
   switch (k) {
@@ -694,7 +711,7 @@ __device__ __forceinline__ double gpartd(double v) {
 template <int G>
 __device__ __forceinline__ float group_maxf(float v) {
   v = fmaxf(v, __int_as_float(gpart<1>(__float_as_int(v))));
-  v = fmaxf(v, __int_as_float(gpart<2>(__float_as_int(v))));
+  if constexpr (G >= 4) v = fmaxf(v, __int_as_float(gpart<2>(__float_as_int(v))));
   if constexpr (G >= 8) v = fmaxf(v, __int_as_float(gpart<4>(__float_as_int(v))));
   if constexpr (G >= 16) v = fmaxf(v, __int_as_float(gpart<8>(__float_as_int(v))));
   if constexpr (G >= 32) v = fmaxf(v, __int_as_float(gpart<16>(__float_as_int(v))));
@@ -703,7 +720,7 @@ __device__ __forceinline__ float group_maxf(float v) {
 template <int G>
 __device__ __forceinline__ double group_maxd(double v) {
   v = fmax(v, gpartd<1>(v));
-  v = fmax(v, gpartd<2>(v));
+  if constexpr (G >= 4) v = fmax(v, gpartd<2>(v));
   if constexpr (G >= 8) v = fmax(v, gpartd<4>(v));
   if constexpr (G >= 16) v = fmax(v, gpartd<8>(v));
   if constexpr (G >= 32) v = fmax(v, gpartd<16>(v));
@@ -712,7 +729,7 @@ __device__ __forceinline__ double group_maxd(double v) {
 template <int G>
 __device__ __forceinline__ int group_ori(int v) {
   v |= gpart<1>(v);
-  v |= gpart<2>(v);
+  if constexpr (G >= 4) v |= gpart<2>(v);
   if constexpr (G >= 8) v |= gpart<4>(v);
   if constexpr (G >= 16) v |= gpart<8>(v);
   if constexpr (G >= 32) v |= gpart<16>(v);
@@ -969,16 +986,7 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
     }
 
     // ---- R row: F-entries of N(i) around the injected C-point ----
-    if (lane < s) {
-      const int pos = ri.off + lane + (lane >= dpos ? 1 : 0);
-      d.Rci[pos] = myN;
-      d.Rva[pos] = z;
-      if (d.B) {
-        const double bi = d.B[i];
-        unsafeAtomicAdd(&w.dsum[ri.fine0 + myN], bi * bi);
-        unsafeAtomicAdd(&w.rsum[ri.fine0 + myN], z * bi);
-      }
-    }
+    if (lane < s) put_f_entry(w, d, ri.fine0, ri.off + lane + (lane >= dpos ? 1 : 0), myN, i, z);
     if (lane == 0) {
       d.Rci[ri.off + dpos] = i;
       d.Rva[ri.off + dpos] = 1.0;
@@ -987,6 +995,372 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
   __syncthreads();
   if (tid == 0 && s_itmax > __hip_atomic_load(&w.st[m0].refine_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
     atomicMax(&w.st[m0].refine_max, s_itmax);
+}
+
+// ---------------------------------------------------------------------------
+// numeric pass, G lanes per row with R block rows per lane: block row q lives
+// in lane q % G, register slot q / G.  Every lane works on R rows of the
+// block, so a wavefront solves 64 / G rows at a time with no lane idle when
+// G R = |N|, and each Gauss-Jordan step broadcasts the pivot row once for
+// the R rows of a lane (the lane-per-row kernel above broadcasts it once per
+// block row and leaves G - |N| lanes idle).
+// ---------------------------------------------------------------------------
+constexpr int pow2_at_least(int x) { return x <= 1 ? 1 : 2 * pow2_at_least((x + 1) / 2); }
+
+// LDS of one row of k_lanes: blocks of up to SM points
+// (f, zb and nb hold a slot for every lane row, dummies included, so that
+// no store or load on them depends on the lane)
+template <int SM, int RS>
+struct LaneRowsBuf {
+  double K[SM * SM];                 // FP64 block, row q = row q of (A[N,N])^T
+  double f[RS];                      // -A[i,N], 0 beyond |N|
+  double zb[RS];                     // broadcast buffer: z (FP64), or a correction's right-hand side (FP32)
+  int nb[pow2_at_least(SM)];         // sorted N(i), INT32_MAX beyond |N|
+};
+
+// y_q = sum_p Kinv[q][p] v_p for the R rows q of a lane (v = scale * x in
+// FP32): v goes through LDS once, then every lane reads all of it
+template <int G, int R, int SM>
+__device__ __forceinline__ void lanes_apply_inv(const float (&kf)[R][SM], float* yb, int lane, const double (&x)[R],
+                                                double scale, float (&y)[R]) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) yb[lane + G * r] = (float)(x[r] * scale);  // dummy rows write past SM, unread
+  wave_sync();
+  float vs[SM];
+#pragma unroll
+  for (int p = 0; p < SM; ++p) vs[p] = yb[p];
+  wave_sync();  // the buffer is reused next
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    float acc = 0.f;
+#pragma unroll
+    for (int p = 0; p < SM; ++p) acc = fmaf(kf[r][p], vs[p], acc);
+    y[r] = acc;
+  }
+}
+
+// One Gauss-Jordan step of k_lanes, K a compile-time constant (the swizzle
+// pattern is an immediate; a loop over K is not always unrolled in full).
+template <int G, int R, int SM, int K>
+__device__ __forceinline__ void lanes_gj_step(float (&kf)[R][SM], int lane, int& bad) {
+  constexpr int src = K % G, slot = K / G;
+  float u[SM];
+#pragma unroll
+  for (int p = 0; p < SM; ++p)
+    u[p] = __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(kf[slot][p]), (32 - G) | (src << 5)));
+  // FP32 factors only precondition the FP64 refinement: the hardware
+  // reciprocal (1 ulp) is accurate enough
+  const float pinv = __builtin_amdgcn_rcpf(u[K]);
+  bad |= !(fabsf(u[K]) >= 0x1p-24f);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const bool pl = (r == slot) && (lane == src);
+    const float lk = kf[r][K] * pinv;
+    const float l = pl ? 1.f - pinv : lk;
+#pragma unroll
+    for (int p = 0; p < SM; ++p)
+      if (p != K) kf[r][p] = fmaf(-l, u[p], kf[r][p]);
+    kf[r][K] = pl ? pinv : -lk;
+  }
+  // keep the scheduler from interleaving steps (that multiplies live rows)
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+template <int G, int R, int SM, int... Ks>
+__device__ __forceinline__ void lanes_gj(float (&kf)[R][SM], int lane, int& bad, std::integer_sequence<int, Ks...>) {
+  (lanes_gj_step<G, R, SM, Ks>(kf, lane, bad), ...);
+}
+
+template <int G, int R, int SM, int NT>
+__global__ __launch_bounds__(NT) void k_lanes(Work w, int which) {
+  static_assert(SM <= G * R && SM > G * (R - 1), "block bound");
+  static_assert(NT % 64 == 0 && 64 % G == 0, "shape");
+  constexpr int NG = NT / G;
+  constexpr int NBP = pow2_at_least(SM);
+  __shared__ LaneRowsBuf<SM, G * R> sb[NG];
+
+  const int tid = threadIdx.x;
+  const int grp = tid / G;
+  const int lane = tid % G;
+  LaneRowsBuf<SM, G * R>& gb = sb[grp];
+  const uint64_t gmask = (G >= 64) ? ~0ull : (((1ull << G) - 1ull) << ((threadIdx.x & 63) - lane));
+  // block rows of this lane: q_r = lane + G r; rows at or beyond SM are dummies
+  bool rowl[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) rowl[r] = lane + G * r < SM;
+
+  if ((which ? w.cnt->nB : w.cnt->nA) == 0) return;
+  const int smin = which ? small_limit(w.GA) + 1 : 0;
+  const int32_t* slots = which ? w.slotB : w.slotA;
+  const int sstride = which ? 32 : slot_stride(w.GA);
+  const int total = w.cnt->total_rows;
+  const int lb = xcd_logical_block();
+  const int per = (total + gridDim.x - 1) / gridDim.x;
+  const int r0 = lb * per;
+  const int r1 = min(total, r0 + per);
+  if (r0 >= r1) return;
+  // most refinement steps of the group's rows of its first matrix (one
+  // atomic per group at the end); rows of later matrices go straight out
+  const int m0 = w.chunk_mat[row_chunk_fast(w, r0)];
+  int itmax = 0;
+  ChunkCursor cc;
+  // one row ahead, as in k_numeric: chunk data, slot entries and A-row bounds
+  // of row g + NG are loaded while row g is solved
+  int nx_t = 0, nx_i = 0, nx_off = 0, nx_s = -1, nx_f0 = 0, nx_f1 = 0;
+  int nx_N[R], nx_e0[R], nx_e1[R];
+  bool ahead = false;
+
+  for (int gbase = r0; gbase < r1; gbase += NG) {
+    const int g = gbase + grp;
+    if (g >= r1) break;  // group-uniform
+    int t, i, off, s, fe0, fe1;
+    int myN0[R], ae0[R], ae1[R];
+    if (ahead) {
+      t = nx_t; i = nx_i; off = nx_off; s = nx_s; fe0 = nx_f0; fe1 = nx_f1;
+#pragma unroll
+      for (int r = 0; r < R; ++r) { myN0[r] = nx_N[r]; ae0[r] = nx_e0[r]; ae1[r] = nx_e1[r]; }
+    } else {
+      cc.seek(w, g);
+      cc.row(w, g, &t, &i, &off, &s);
+      fe0 = 0; fe1 = 0;
+      const bool ok = s >= smin && s <= SM && cc.live;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int q = lane + G * r;
+        myN0[r] = slots[(cc.fbase + t) * sstride + min(q, sstride - 1)];
+        ae0[r] = 0; ae1[r] = 0;
+        if (ok && q < s) { ae0[r] = cc.md.rp[myN0[r]]; ae1[r] = cc.md.rp[myN0[r] + 1]; }
+      }
+      if (ok) { fe0 = cc.md.rp[i]; fe1 = cc.md.rp[i + 1]; }
+    }
+    const int gn = g + NG;
+    ahead = gn < r1 && gn < cc.re;
+    if (ahead) {
+      cc.row(w, gn, &nx_t, &nx_i, &nx_off, &nx_s);
+#pragma unroll
+      for (int r = 0; r < R; ++r) nx_N[r] = slots[(cc.fbase + nx_t) * sstride + min(lane + G * r, sstride - 1)];
+    }
+    const bool mine = s >= smin && s <= SM && cc.live;  // group-uniform
+    const bool nx_mine = ahead && nx_s >= smin && nx_s <= SM && cc.live;
+    if (!mine) {
+      if (which && s > SM && s <= 32 && cc.live && lane == 0) {
+        const int qc = atomicAdd(&w.cnt->nC, 1);
+        if (qc < w.capC) w.binC[qc] = cc.c * w.chunk + t;
+        else flag_row(&w.st[cc.m], ST_UNSUPPORTED, i);
+      }
+      if (nx_mine) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          nx_e0[r] = 0; nx_e1[r] = 0;
+          if (lane + G * r < nx_s) { nx_e0[r] = cc.md.rp[nx_N[r]]; nx_e1[r] = cc.md.rp[nx_N[r] + 1]; }
+        }
+        nx_f0 = cc.md.rp[nx_i];
+        nx_f1 = cc.md.rp[nx_i + 1];
+      }
+      continue;
+    }
+    const int entry = cc.c * w.chunk + t;
+    const GDesc& d = cc.md;
+    MatStatus* st = &w.st[cc.m];
+    const int rr = g - cc.rbase_m;
+    if (lane == 0) d.Rrp[rr] = off;
+    int myN[R];
+    int below = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int q = lane + G * r;
+      myN[r] = (q < s) ? myN0[r] : 0x7fffffff;
+      gb.nb[q] = myN[r];
+      gb.f[q] = 0.0;
+      below += __popcll(__ballot(q < s && myN[r] < i) & gmask);
+    }
+    if constexpr (G * R < NBP) {
+      for (int q = G * R + lane; q < NBP; q += G) gb.nb[q] = 0x7fffffff;
+    }
+    const int dpos = below;
+
+    // ---- gather: K = (A[N,N])^T (identity on the padding), f = -A[i,N] ----
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int q = lane + G * r;
+      if (q < SM) {
+#pragma unroll
+        for (int p = 0; p < SM; ++p) gb.K[q * SM + p] = (p == q && q >= s) ? 1.0 : 0.0;
+      }
+    }
+    wave_sync();
+    {
+      int len = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) len = max(len, ae1[r] - ae0[r]);
+      for (int o = 0; o < len; o += 4) {
+        int k[R][4];
+        double v[R][4];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            k[r][j] = -1;
+            v[r][j] = 0.0;
+            if (ae0[r] + o + j < ae1[r]) { k[r][j] = d.ci[ae0[r] + o + j]; v[r][j] = d.va[ae0[r] + o + j]; }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int qq = find_pos<NBP>(gb.nb, k[r][j]);
+            if (qq >= 0) gb.K[qq * SM + lane + G * r] = v[r][j];
+          }
+        }
+      }
+    }
+    for (int e = fe0 + lane; e < fe1; e += G) {
+      const int qq = find_pos<NBP>(gb.nb, d.ci[e]);
+      if (qq >= 0) gb.f[qq] = -d.va[e];
+    }
+    wave_sync();
+    if (nx_mine) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        nx_e0[r] = 0; nx_e1[r] = 0;
+        if (lane + G * r < nx_s) { nx_e0[r] = d.rp[nx_N[r]]; nx_e1[r] = d.rp[nx_N[r] + 1]; }
+      }
+      nx_f0 = d.rp[nx_i];
+      nx_f1 = d.rp[nx_i + 1];
+    }
+
+    // ---- FP32 inverse of the scaled block ----
+    // (loops over columns that index no register array stay rolled, so the
+    // compiler does not hoist every LDS load of the block at once)
+    float amax = 0.f;
+    double knorm = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      // a dummy row (beyond SM) reads the last row and is ignored
+      const double* kr = gb.K + min(lane + G * r, SM - 1) * SM;
+      double rs = 0.0;
+#pragma unroll 4
+      for (int p = 0; p < SM; ++p) {
+        const double v = (lane + G * r < s) ? fabs(kr[p]) : 0.0;  // the identity padding does not count
+        amax = fmaxf(amax, (float)v);
+        rs += v;
+      }
+      knorm = fmax(knorm, rs);
+    }
+    amax = group_maxf<G>(amax);
+    knorm = group_maxd<G>(knorm);
+    int ex = 0;
+    frexpf(amax, &ex);
+    const double scale = ldexp(1.0, -ex);
+    float kf[R][SM];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+      for (int p = 0; p < SM; ++p) {
+        const float x = (float)(gb.K[min(lane + G * r, SM - 1) * SM + p] * scale);
+        // padding rows keep a unit pivot whatever the scale (they are
+        // decoupled from the block, and their z stays 0)
+        kf[r][p] = !rowl[r] ? 0.f : (lane + G * r >= s) ? (p == lane + G * r ? 1.f : 0.f) : x;
+        if ((p & 7) == 7) __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    int bad = !(amax > 0.f) || !(amax < 3.0e38f);
+    // Gauss-Jordan in place without pivoting (as in k_numeric): step k
+    // broadcasts pivot row k from lane k % G, slot k / G, once for all R rows
+    // of every lane
+    lanes_gj<G, R, SM>(kf, lane, bad, std::make_integer_sequence<int, SM>{});
+    bad = group_ori<G>(bad);
+
+    // ---- solve and refine in FP64 ----
+    double fq[R], z[R];
+    double fmaxv = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      fq[r] = gb.f[lane + G * r];  // 0 on padding and dummy rows
+      fmaxv = fmax(fmaxv, fabs(fq[r]));
+      z[r] = 0.0;
+    }
+    const double fnorm = group_maxd<G>(fmaxv);
+    int it = 0;
+    bool conv = false;
+    // Every group runs the solve, also one whose factorisation is not
+    // trusted (its result is then discarded): a branch on `bad` here lets the
+    // compiler sink the last elimination steps into it, which keeps the
+    // broadcasts of many steps alive at once and spills.
+    {
+      {
+        float y[R];
+        lanes_apply_inv<G, R, SM>(kf, reinterpret_cast<float*>(gb.zb), lane, fq, scale, y);
+#pragma unroll
+        for (int r = 0; r < R; ++r) z[r] = (double)y[r];
+      }
+      for (it = 1; it <= kRefineMax; ++it) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) gb.zb[lane + G * r] = z[r];  // dummy rows write past SM, unread
+        wave_sync();
+        double res[R];
+        double rmax = 0.0, zmax = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) res[r] = fq[r];
+        // (a dummy row, beyond SM, reads the last row and is ignored: no
+        // branch on the lane inside the loop)
+#pragma unroll 2
+        for (int p = 0; p < SM; ++p) {
+          const double zp = gb.zb[p];
+#pragma unroll
+          for (int r = 0; r < R; ++r) res[r] = fma(-gb.K[min(lane + G * r, SM - 1) * SM + p], zp, res[r]);
+        }
+        wave_sync();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          rmax = fmax(rmax, rowl[r] ? fabs(res[r]) : 0.0);
+          zmax = fmax(zmax, rowl[r] ? fabs(z[r]) : 0.0);
+        }
+        // the FP32 solution is never accurate to FP64 rounding: the first
+        // correction is applied unchecked
+        if (bad) break;  // group-uniform: the FP64 solver takes the row
+        if (it > 1) {
+          const double rn = group_maxd<G>(rmax);
+          const double zn = group_maxd<G>(zmax);
+          if (rn <= 0x1p-47 * (knorm * zn + fnorm)) { conv = true; break; }
+        }
+        float y[R];
+        lanes_apply_inv<G, R, SM>(kf, reinterpret_cast<float*>(gb.zb), lane, res, scale, y);
+#pragma unroll
+        for (int r = 0; r < R; ++r) z[r] += (double)y[r];
+      }
+      bool nan = false;
+#pragma unroll
+      for (int r = 0; r < R; ++r) nan |= !(z[r] == z[r]);
+      if (nan || bad) conv = false;
+      conv = group_ori<G>(conv ? 0 : 1) == 0;
+    }
+    if (!conv) {
+      // FP32 factorisation not trusted: the workgroup solver redoes the row in FP64
+      if (lane == 0) {
+        const int qc = atomicAdd(&w.cnt->nC, 1);
+        if (qc < w.capC) w.binC[qc] = entry;
+        else flag_row(st, ST_UNSUPPORTED, i);
+      }
+      continue;
+    }
+    if (cc.m == m0) itmax = max(itmax, it);
+    else if (lane == 0) atomicMax(&st->refine_max, it);
+
+    // ---- R row: F-entries of N(i) around the injected C-point ----
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int q = lane + G * r;
+      if (q < s) put_f_entry(w, d, cc.fine0, off + q + (q >= dpos ? 1 : 0), myN[r], i, z[r]);
+    }
+    if (lane == 0) {
+      d.Rci[off + dpos] = i;
+      d.Rva[off + dpos] = 1.0;
+    }
+  }
+  if (lane == 0 && itmax > __hip_atomic_load(&w.st[m0].refine_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    atomicMax(&w.st[m0].refine_max, itmax);
 }
 
 // ---------------------------------------------------------------------------
@@ -1250,21 +1624,10 @@ __global__ __launch_bounds__(NT) void k_quad8(Work w) {
     const int dpos_l = (n0 < i ? 1 : 0) + (n1 < i ? 1 : 0);
     const int dpos = dpos_l + __builtin_amdgcn_mov_dpp(dpos_l, 0xB1, 0xF, 0xF, false);
     const int dposq = dpos + __builtin_amdgcn_mov_dpp(dpos, 0x4E, 0xF, 0xF, false);
-    const double bi = d.B ? d.B[i] : 0.0;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int p = q0 + h;
-      if (p < s) {
-        const int np = h ? n1 : n0;
-        const double zp = h ? z1 : z0;
-        const int pos = ri.off + p + (p >= dposq ? 1 : 0);
-        d.Rci[pos] = np;
-        d.Rva[pos] = zp;
-        if (d.B) {
-          unsafeAtomicAdd(&w.dsum[ri.fine0 + np], bi * bi);
-          unsafeAtomicAdd(&w.rsum[ri.fine0 + np], zp * bi);
-        }
-      }
+      if (p < s) put_f_entry(w, d, ri.fine0, ri.off + p + (p >= dposq ? 1 : 0), h ? n1 : n0, i, h ? z1 : z0);
     }
     if (ql == 0) {
       d.Rci[ri.off + dposq] = i;
@@ -1517,19 +1880,9 @@ __global__ __launch_bounds__(NT) void k_rows8(Work w) {
       int dpos = 0;
 #pragma unroll
       for (int p = 0; p < kS8; ++p) dpos += (N[p] < i) ? 1 : 0;
-      const double bi = d.B ? d.B[i] : 0.0;
 #pragma unroll
-      for (int p = 0; p < kS8; ++p) {
-        if (p < s) {
-          const int pos = off + p + (p >= dpos ? 1 : 0);
-          d.Rci[pos] = N[p];
-          d.Rva[pos] = z[p];
-          if (d.B) {
-            unsafeAtomicAdd(&w.dsum[cc.fine0 + N[p]], bi * bi);
-            unsafeAtomicAdd(&w.rsum[cc.fine0 + N[p]], z[p] * bi);
-          }
-        }
-      }
+      for (int p = 0; p < kS8; ++p)
+        if (p < s) put_f_entry(w, d, cc.fine0, off + p + (p >= dpos ? 1 : 0), N[p], i, z[p]);
       d.Rci[off + dpos] = i;
       d.Rva[off + dpos] = 1.0;
     }
@@ -1643,7 +1996,7 @@ __device__ __forceinline__ void mf_lu_solve(const float* K, int lda, int S, floa
 // floats; f, z, r: LDS FP64 vectors of kMfmaMax; y: LDS FP32 vector of
 // kMfmaMax.
 __device__ __forceinline__ bool mixed_big_row(const GDesc& d, int i, const int* N, int s, float* K, double* f, double* z,
-                              double* r, float* y, double* shv, int* s_flag, int* it_out) {
+                              double* r, float* y, double* shv, int* s_flag, int* it_out, int* bnd) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int S = (s + 31) & ~31;
@@ -1747,17 +2100,28 @@ __device__ __forceinline__ bool mixed_big_row(const GDesc& d, int i, const int* 
   mf_lu_solve(K, lda, S, y);
   for (int t = tid; t < s; t += kWT) z[t] = y[t];
   __syncthreads();
+  // row bounds of the rows of N, for the residual's searches
+  for (int p = tid; p < s; p += kWT) { bnd[2 * p] = d.rp[N[p]]; bnd[2 * p + 1] = d.rp[N[p] + 1]; }
+  __syncthreads();
   for (int it = 1; it <= kRefineMax; ++it) {
-    // r = f - K z with the FP64 entries of A: row N_p adds -a_{N_p, N_q} z_p to r_q
-    for (int t = tid; t < s; t += kWT) r[t] = f[t];
-    __syncthreads();
-    for (int p = tid; p < s; p += kWT) {
-      const int u = N[p];
-      const double zp = z[p];
-      for (int ee = d.rp[u]; ee < d.rp[u + 1]; ++ee) {
-        const int q = find_sorted(N, s, d.ci[ee]);
-        if (q >= 0) atomicAdd(&r[q], -d.va[ee] * zp);
+    // r = f - K z with the FP64 entries of A: r_q = f_q - sum_p a_{N_p, N_q} z_p,
+    // summed in ascending p (the same bits on every run): thread q finds N_q
+    // in each row N_p by bisection
+    for (int q = tid; q < s; q += kWT) {
+      const int col = N[q];
+      double acc = f[q];
+#pragma unroll 4
+      for (int p = 0; p < s; ++p) {
+        int lo = bnd[2 * p];
+        const int e1 = bnd[2 * p + 1];
+        int hi = e1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (d.ci[mid] < col) lo = mid + 1; else hi = mid;
+        }
+        if (lo < e1 && d.ci[lo] == col) acc = fma(-d.va[lo], z[p], acc);
       }
+      r[q] = acc;
     }
     __syncthreads();
     if (it > 1) {
@@ -1840,7 +2204,7 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
       // blocks above 32 points: the mixed solver first
       int itm = 0;
       const bool mixed_ok = s > 32 && s <= kMfmaMax &&
-                            mixed_big_row(d, i, N, s, sK32, sf, s_z, s_r, s_y, shv, &s_mflag, &itm);
+                            mixed_big_row(d, i, N, s, sK32, sf, s_z, s_r, s_y, shv, &s_mflag, &itm, bb.dp);
       if (mixed_ok) {
         for (int t = tid; t < s; t += kWT) sf[t] = s_z[t];
         if (tid == 0 && itm > __hip_atomic_load(&st->refine_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
@@ -1943,16 +2307,7 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
         dpos = shi[0];
         __syncthreads();
       }
-      for (int p = tid; p < s; p += kWT) {
-        const int pos = ri.off + p + (p >= dpos ? 1 : 0);
-        d.Rci[pos] = N[p];
-        d.Rva[pos] = sf[p];
-        if (d.B) {
-          const double bi = d.B[i];
-          unsafeAtomicAdd(&w.dsum[ri.fine0 + N[p]], bi * bi);
-          unsafeAtomicAdd(&w.rsum[ri.fine0 + N[p]], sf[p] * bi);
-        }
-      }
+      for (int p = tid; p < s; p += kWT) put_f_entry(w, d, ri.fine0, ri.off + p + (p >= dpos ? 1 : 0), N[p], i, sf[p]);
       if (tid == 0) {
         d.Rci[ri.off + dpos] = i;
         d.Rva[ri.off + dpos] = 1.0;
@@ -1970,108 +2325,127 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
 // consecutive rows, a contiguous run of R).  LPR = 8: eight lanes per row,
 // entry by entry (long rows).  Workgroups [0, nproj) project (nproj a
 // multiple of 8); the rest count the uncovered F-points at the same time.
-template <int LPR>
-__global__ __launch_bounds__(256) void k_project(Work w, int nproj) {
+// Constraint projection, one workgroup per chunk of fine points, one thread
+// per F-point j (the survey's exchange step: Algorithm 1's projection applied
+// per F-column, QQ^T being diagonal): the entries of column j are those
+// linked into its list by the solvers; the thread orders them by R position
+// (ascending row, so the sums are the same on every run), forms
+// d_j = sum B_i^2 and r_j = sum z_ij B_i - B_j in that order and sets
+// z_ij -= B_i r_j / d_j.  A column with d_j = 0 is left alone and counted as
+// uncovered.  Lists of up to kPL entries are ordered in registers; a longer
+// list is taken kPL entries at a time, each pass keeping the smallest
+// positions above the last one summed.
+constexpr int kPL = 8;
+
+struct ColEntry {
+  int e[kPL];     // batch-wide R entry, INT32_MAX when empty
+  int ci[kPL];    // the row's C-point
+  double z[kPL];  // the entry's value before the projection
+  int n;
+
+  __device__ __forceinline__ void clear() {
+#pragma unroll
+    for (int k = 0; k < kPL; ++k) { e[k] = INT32_MAX; ci[k] = 0; z[k] = 0.0; }
+    n = 0;
+  }
+  // keep the kPL smallest positions (sorted); returns false when an entry
+  // had to be dropped
+  __device__ __forceinline__ bool insert(int ee, int ii, double zz) {
+    int pos = 0;
+#pragma unroll
+    for (int k = 0; k < kPL; ++k) pos += (e[k] < ee) ? 1 : 0;
+    const bool full = n == kPL;
+    if (pos >= kPL) return false;
+#pragma unroll
+    for (int k = kPL - 1; k > 0; --k)
+      if (k > pos) { e[k] = e[k - 1]; ci[k] = ci[k - 1]; z[k] = z[k - 1]; }
+#pragma unroll
+    for (int k = 0; k < kPL; ++k)
+      if (k == pos) { e[k] = ee; ci[k] = ii; z[k] = zz; }
+    n = full ? kPL : n + 1;
+    return !full;
+  }
+};
+
+__global__ __launch_bounds__(256) void k_colproj(Work w) {
+  __shared__ int s_unc;
+  const int c = xcd_logical_block();
   const int tid = threadIdx.x;
-  if ((int)blockIdx.x >= nproj) {
-    // uncovered F-points: one global atomic per workgroup and matrix
-    __shared__ int s_unc;
-    const int nu = gridDim.x - nproj, bu = blockIdx.x - nproj;
-    for (int m = 0; m < w.nmat; ++m) {
-      const GDesc d = gview(w.desc[m]);
-      if (!d.B || !matrix_live(w.st[m])) continue;  // uniform
-      if (tid == 0) s_unc = 0;
-      __syncthreads();
-      int cnt = 0;
-      for (int j = bu * blockDim.x + tid; j < d.n; j += nu * blockDim.x) {
-        const int8_t cj = d.cf[j];  // both loads issued before either is used
-        const double sj = w.dsum[d.fine0 + j];
-        cnt += (cj == 0 && !(sj > 0.0)) ? 1 : 0;
+  const int m = w.chunk_mat[c];
+  const GDesc d = gview(w.desc[m]);
+  if (!d.B || !matrix_live(w.st[m])) return;
+  const int64_t nzb = d.link_base;  // list entry of R position p: nzb + p
+  const int f0 = (c - d.chunk0) * w.chunk;
+  const int f1 = min(f0 + w.chunk, d.n);
+  if (tid == 0) s_unc = 0;
+  __syncthreads();
+  int unc = 0;
+  for (int j = f0 + tid; j < f1; j += blockDim.x) {
+    const int8_t cj = d.cf[j];
+    const int head = w.chead[d.fine0 + j];
+    if (cj != 0) continue;
+    if (head < 0) { ++unc; continue; }
+    // first pass: the kPL smallest positions of the list
+    ColEntry L;
+    L.clear();
+    bool more = false;
+    for (int e = head; e >= 0;) {
+      const int2 lk = w.clink[e];
+      const double zv = d.Rva[e - nzb];
+      more |= !L.insert(e, lk.y, zv);
+      e = lk.x;
+    }
+    double dsum = 0.0, rsum = 0.0;
+#pragma unroll
+    for (int k = 0; k < kPL; ++k) {
+      if (k < L.n) {
+        const double bi = d.B[L.ci[k]];
+        dsum = fma(bi, bi, dsum);
+        rsum = fma(L.z[k], bi, rsum);
+      }
+    }
+    // longer lists: further passes, each over the positions above the last
+    // one taken
+    int last = L.e[kPL - 1];
+    while (more) {
+      ColEntry M;
+      M.clear();
+      more = false;
+      for (int e = head; e >= 0;) {
+        const int2 lk = w.clink[e];
+        if (e > last) more |= !M.insert(e, lk.y, d.Rva[e - nzb]);
+        e = lk.x;
       }
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-      if ((tid & 63) == 0 && cnt) atomicAdd(&s_unc, cnt);
-      __syncthreads();
-      if (tid == 0 && s_unc) atomicAdd((unsigned long long*)&w.st[m].n_uncovered, (unsigned long long)s_unc);
-    }
-    return;
-  }
-  if constexpr (LPR == 1) {
-  // one thread per row: a wavefront covers 64 consecutive rows, i.e. a
-  // contiguous run of R; a row's entries are read eight at a time and all
-  // their column sums are gathered before any is used.  The chunk data is
-  // looked up once per wavefront and chunk (wavefront-uniform values).
-  const int lane = tid & 63;
-  const int total = w.cnt->total_rows;
-  const int lb = xcd_logical_block(nproj);
-  const int per = (total + nproj - 1) / nproj;
-  const int r0 = lb * per;
-  const int r1 = min(total, r0 + per);
-  ChunkCursor cc;
-  for (int gw = r0 + (tid & ~63); gw < r1; gw += blockDim.x) {
-    const int g = gw + lane;
-    const int gend = min(gw + 64, r1);
-    for (int gc = gw; gc < gend;) {  // wavefront-uniform
-      cc.seek(w, __builtin_amdgcn_readfirstlane(gc));
-      const int cend = min(gend, cc.re);
-      if (g >= gc && g < cend && cc.live && cc.md.B) {
-        int t, i, off, sz;
-        cc.row(w, g, &t, &i, &off, &sz);
-        const GDesc& d = cc.md;
-        const double bi = d.B[i];
-        const int64_t f0 = cc.fine0;
-        const int e1 = off + sz + 1;
-        for (int e0 = off; e0 < e1; e0 += 8) {
-          int j[8];
-          double z[8], dj[8], rj[8], bj[8];
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            j[k] = -1;
-            z[k] = 0.0;
-            if (e0 + k < e1) { j[k] = d.Rci[e0 + k]; z[k] = d.Rva[e0 + k]; }
-          }
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            dj[k] = 0.0;
-            rj[k] = 0.0;
-            bj[k] = 0.0;
-            if (j[k] >= 0 && j[k] != i) { dj[k] = w.dsum[f0 + j[k]]; rj[k] = w.rsum[f0 + j[k]]; bj[k] = d.B[j[k]]; }
-          }
-#pragma unroll
-          for (int k = 0; k < 8; ++k)
-            if (dj[k] > 0.0) d.Rva[e0 + k] = z[k] - bi * (rj[k] - bj[k]) / dj[k];
+      for (int k = 0; k < kPL; ++k) {
+        if (k < M.n) {
+          const double bi = d.B[M.ci[k]];
+          dsum = fma(bi, bi, dsum);
+          rsum = fma(M.z[k], bi, rsum);
         }
       }
-      gc = cend;
+      last = M.e[kPL - 1];
     }
-  }
-  } else {
-    const int lane = tid % LPR;
-    const int grp = tid / LPR;
-    constexpr int NG = 256 / LPR;
-    const int total = w.cnt->total_rows;
-    const int lb = xcd_logical_block(nproj);
-    const int per = (total + nproj - 1) / nproj;
-    const int r0 = lb * per;
-    const int r1 = min(total, r0 + per);
-    ChunkCursor cc;
-    for (int gbase = r0; gbase < r1; gbase += NG) {
-      const int g = gbase + grp;
-      if (g >= r1) break;
-      cc.seek(w, g);
-      if (!cc.live || !cc.md.B) continue;
-      int t, i, off, sz;
-      cc.row(w, g, &t, &i, &off, &sz);
-      const GDesc& d = cc.md;
-      const double bi = d.B[i];
-      for (int e = off + lane; e <= off + sz; e += LPR) {
-        const int j = d.Rci[e];
-        if (j == i) continue;
-        const double dj = w.dsum[cc.fine0 + j];
-        if (dj > 0.0) d.Rva[e] -= bi * (w.rsum[cc.fine0 + j] - d.B[j]) / dj;
+    if (!(dsum > 0.0)) { ++unc; continue; }
+    const double q = (rsum - d.B[j]) / dsum;
+    if (L.n < kPL || L.e[kPL - 1] == last) {
+      // the whole list is in registers
+#pragma unroll
+      for (int k = 0; k < kPL; ++k)
+        if (k < L.n) d.Rva[L.e[k] - nzb] = L.z[k] - d.B[L.ci[k]] * q;
+    } else {
+      for (int e = head; e >= 0;) {
+        const int2 lk = w.clink[e];
+        d.Rva[e - nzb] -= d.B[lk.y] * q;
+        e = lk.x;
       }
     }
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) unc += __shfl_xor(unc, o, 64);
+  if ((tid & 63) == 0 && unc) atomicAdd(&s_unc, unc);
+  __syncthreads();
+  if (tid == 0 && s_unc) atomicAdd((unsigned long long*)&w.st[m].n_uncovered, (unsigned long long)s_unc);
 }
 
 // a numeric pass without the symbolic pass before it: projection sums of all
@@ -2161,10 +2535,8 @@ __global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
 }
 
 __global__ void k_clear_sums(Work w, int64_t n) {
-  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-    w.dsum[j] = 0.0;
-    w.rsum[j] = 0.0;
-  }
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+    w.chead[j] = -1;
   if (blockIdx.x == 0) {
     for (int m = threadIdx.x; m < w.nmat; m += blockDim.x) {
       const MatStatus& st = w.st[m];
@@ -2248,6 +2620,37 @@ hipError_t launch_numeric(const Work& w, int which, int group, int sm, int wg_th
   return hipErrorInvalidValue;
 }
 
+// G lanes per row, R block rows per lane, blocks of up to SM points, one
+// wavefront per workgroup; persistent grid as for k_numeric
+hipError_t launch_lanes(const Work& w, int which, int group, int rows_per_lane, int sm, int wg_threads, int cus,
+                        hipStream_t s) {
+#define CLAIR_LR(GG, RR, SMM, NTT)                                                                          \
+  if (group == GG && rows_per_lane == RR && sm == SMM && wg_threads == NTT) {                               \
+    int per = 0;                                                                                            \
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_lanes<GG, RR, SMM, NTT>, NTT, 0);   \
+    if (e != hipSuccess) return e;                                                                          \
+    const int blocks = (std::max(1, per) * cus + 7) / 8 * 8;                                               \
+    hipLaunchKernelGGL((k_lanes<GG, RR, SMM, NTT>), dim3(blocks), dim3(NTT), 0, s, w, which);               \
+    return hipGetLastError();                                                                               \
+  }
+  CLAIR_LR(8, 2, 16, 64)
+  CLAIR_LR(8, 3, 20, 64)
+  CLAIR_LR(8, 3, 24, 64)
+  CLAIR_LR(16, 1, 16, 64)
+  CLAIR_LR(16, 2, 20, 64)
+  CLAIR_LR(16, 2, 24, 64)
+  CLAIR_LR(16, 2, 32, 64)
+  CLAIR_LR(32, 1, 20, 64)
+  CLAIR_LR(32, 1, 24, 64)
+  CLAIR_LR(32, 1, 32, 64)
+  CLAIR_LR(4, 2, 8, 64)
+  CLAIR_LR(4, 2, 8, 128)
+  CLAIR_LR(2, 4, 8, 64)
+  CLAIR_LR(2, 4, 8, 128)
+#undef CLAIR_LR
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_rows8(const Work& w, int wg_threads, int cus, hipStream_t s) {
 #define CLAIR_R8(NTT)                                                                       \
   if (wg_threads == NTT) {                                                                  \
@@ -2287,13 +2690,8 @@ hipError_t launch_rows_wg(const Work& w, int blocks, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_project(const Work& w, int blocks, int unc_blocks, int lanes_per_row, hipStream_t s) {
-  blocks = (blocks + 7) / 8 * 8;
-  const int grid = blocks + (unc_blocks < 1 ? 1 : unc_blocks);
-  if (lanes_per_row == 1)
-    hipLaunchKernelGGL(k_project<1>, dim3(grid), dim3(256), 0, s, w, blocks);
-  else
-    hipLaunchKernelGGL(k_project<8>, dim3(grid), dim3(256), 0, s, w, blocks);
+hipError_t launch_project(const Work& w, hipStream_t s) {
+  hipLaunchKernelGGL(k_colproj, dim3(w.nchunks), dim3(256), 0, s, w);
   return hipGetLastError();
 }
 

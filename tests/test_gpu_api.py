@@ -199,16 +199,35 @@ def test_stage_timing_and_autotune():
     assert all(v >= 0 for v in t.values())
 
 
-def test_repeat_runs_identical_pattern_and_close_values():
+@pytest.mark.parametrize("which", ["cfg1", "mixed_bins", "cfg2_eps1e-2"])
+def test_repeat_runs_bitwise_identical(which):
+    # the projection orders every column's entries by row before summing
+    # (Algorithm 1's projection step, one F-column at a time): repeat runs give
+    # the same bits, also with random B, rows in several size bins and
+    # columns of more than eight rows (the distance-3 random pattern)
     from paper_2307_00229_amd import clair
 
-    p = P.cfg1()
-    As, cfs, Bs, ells = to_device([p])
-    a = _fetch(clair.clair_build_R_batched(As, cfs, Bs, ells)[0][0])
-    b = _fetch(clair.clair_build_R_batched(As, cfs, Bs, ells)[0][0])
-    assert np.array_equal(a["col_idx"], b["col_idx"])
-    # the projection sums use FP64 atomics: only the last bits may differ
-    np.testing.assert_allclose(a["val"], b["val"], rtol=1e-14, atol=1e-16)
+    if which == "cfg1":
+        ps = [P.cfg1()]
+    elif which == "mixed_bins":
+        ps = _cases() + [P.random_sparse(400, 0.012, 77, ell=3)]
+        rng = np.random.default_rng(5)
+        for q in ps:
+            q.B = rng.uniform(0.5, 1.5, q.n)
+    else:
+        ps = [P.cfg2(eps_list=(1e-2,))[0]]
+    As, cfs, Bs, ells = to_device(ps)
+    runs = []
+    for _ in range(3):
+        outs, infos, st = clair.clair_build_R_batched(As, cfs, Bs, ells, ctx=clair.Context())
+        assert st == 0, infos
+        runs.append([_fetch(o) for o in outs])
+    for other in runs[1:]:
+        for a, b in zip(runs[0], other):
+            assert np.array_equal(a["row_ptr"], b["row_ptr"]) and np.array_equal(a["col_idx"], b["col_idx"])
+            assert np.array_equal(a["val"].view(np.int64), b["val"].view(np.int64))
+    for q, g in zip(ps, runs[0]):
+        assert_matches_oracle(q, g, oracle.build_R_problem(q))
 
 
 # ---------------------------------------------------------------------------

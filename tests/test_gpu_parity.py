@@ -217,3 +217,36 @@ def test_scaling_extremes():
         p = P.small_2d(64, stencil=5, eps=1e-2, angle=0.3, ell=2)
         p.val = p.val * alpha
         _check([p], precision=0)
+
+
+@pytest.mark.parametrize("lanes", [8, 16, 32])
+def test_binB_lane_layouts(lanes):
+    # the bin-B solver with 8, 16 or 32 lanes per row (each lane holding
+    # ceil(b / lanes) block rows) at the block bounds b = 16, 20, 24 and 32
+    from paper_2307_00229_amd import clair
+
+    cases = [(P.small_2d(97, stencil=9, eps=1e-3, angle=0.4, k=3, ell=2), 24),
+             (P.small_3d(21, eps=0.01, b=(0.3, -0.6, 0.7), ell=2), 18),
+             (P.greedy_aggregates(P.small_2d(64, stencil=5, eps=0.1, angle=0.5, ell=2)), None),
+             (P.random_sparse(400, 0.012, 77, ell=3), None)]
+    for p, want in cases:
+        ctx = clair.Context()
+        ctx.set_tuning(4, 0, 0)
+        ctx.set_bin_shape(lanes)
+        assert ctx.get_bin_shape() == lanes
+        if p.agg is not None:
+            from ._util import assert_matches_oracle
+
+            A = clair.CSR.from_problem(p, "cuda")
+            outs, infos, st = clair.clair_build_R_agg([A], [torch.from_numpy(p.cf).cuda()],
+                                                      [torch.from_numpy(p.agg).cuda()],
+                                                      [torch.from_numpy(p.B).cuda()], [p.ell], ctx=ctx)
+            assert st == 0, infos
+            rp, ci, va = outs[0].trimmed()
+            g = dict(row_ptr=rp.cpu().numpy(), col_idx=ci.cpu().numpy(), val=va.cpu().numpy(), n_c=outs[0].n_c,
+                     nnz=outs[0].nnz)
+            assert_matches_oracle(p, g, oracle.build_R_problem(p), infos[0])
+            continue
+        res, infos = _check([p], precision=0, ctx=ctx)
+        if want is not None:
+            assert infos[0]["max_block"] == want
