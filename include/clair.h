@@ -380,6 +380,29 @@ int clair_ctx_get_tuning(clair_ctx_t* ctx, int32_t* group, int32_t* wg_threads, 
 int clair_ctx_set_bin_shape(clair_ctx_t* ctx, int32_t binB_lanes);
 int clair_ctx_get_bin_shape(clair_ctx_t* ctx, int32_t* binB_lanes);
 
+/*
+ * clair_build_R_noalloc -- clair_build_R_ex for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): one matrix, mixed precision, default tuning, synchronous on
+ * `stream` (NULL = null stream), allocating no device or host memory.  The
+ * whole workspace sits in a static device array of
+ * CLAIR_NOALLOC_SCRATCH_BYTES (64 MiB), one copy per device the library runs
+ * on, held until the process ends: the descriptors, per-point arrays of about
+ * 200 bytes per fine point of A, and the projection's column lists (8 bytes
+ * per entry of R_out's nnz capacity when B != NULL), which fit a 512 x 512
+ * five-point matrix.  An input that does not fit returns
+ * CLAIR_ERR_UNSUPPORTED (clair_last_error states the sizes) before any device
+ * work; rows whose neighbourhood exceeds 64 points are reported the same way
+ * (first_bad_row).  Arguments, size query and results as clair_build_R_ex.
+ * Every call on one device shares that device's array and host staging, so
+ * calls that overlap on one device (other threads, other streams) race; the
+ * array keeps the last call's contents, and every call re-initialises what it
+ * reads.
+ */
+#define CLAIR_NOALLOC_SCRATCH_BYTES (64 * 1024 * 1024)
+int clair_build_R_noalloc(const clair_csr_t* A, const int8_t* cf_marker, const double* B, int32_t ell,
+                          clair_csr_out_t* R_out, void* stream, clair_info_t* info);
+
 /* Bytes of device memory ctx holds for the FP64 blocks of rows above 64
  * points (one slot per workgroup of the FP64 solver, each the square of the
  * largest block a synchronous call has read back, rounded up to a multiple

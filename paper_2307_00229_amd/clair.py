@@ -33,6 +33,7 @@ EXPORTED = [
     "clair_spgemm", "clair_galerkin", "clair_smooth_B", "clair_build_R_agg", "clair_project_constraints",
     "clair_build_R_diag", "clair_build_R_approx", "clair_build_R_kkt", "clair_ctx_set_graph",
     "clair_ctx_set_literal_pattern", "clair_ctx_scratch_bytes", "clair_ctx_set_bin_shape", "clair_ctx_get_bin_shape",
+    "clair_build_R_noalloc",
     "clair_autotune", "clair_graph_create", "clair_graph_launch", "clair_graph_destroy", "clair_graph_info",
     "clair_plan_create", "clair_plan_execute", "clair_plan_info", "clair_plan_destroy",
     "clair_strerror", "clair_last_error",
@@ -103,6 +104,8 @@ def load_library(path: str = LIB_PATH):
         "clair_ctx_get_tuning": ([P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)], ctypes.c_int),
         "clair_ctx_scratch_bytes": ([P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "clair_ctx_set_bin_shape": ([P, I32], ctypes.c_int),
+        "clair_build_R_noalloc": ([ctypes.POINTER(CsrIn), P, P, I32, ctypes.POINTER(CsrOut), P, ctypes.POINTER(Info)],
+                                  ctypes.c_int),
         "clair_ctx_get_bin_shape": ([P, ctypes.POINTER(I32)], ctypes.c_int),
         "clair_ctx_set_strength": ([P, ctypes.c_double], ctypes.c_int),
         "clair_ctx_get_strength": ([P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),

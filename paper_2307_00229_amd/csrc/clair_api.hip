@@ -120,6 +120,8 @@ Layout make_layout(int nmat, int nchunks, int64_t n_total, int GA, bool any_agg)
 }
 
 constexpr int kMaxStages = 12;
+constexpr int kNoAllocDevices = 64;      // devices the fixed-memory entry point serves
+constexpr int kNoAllocHostBytes = 8192;  // its host staging per device (descriptor upload + status read-back)
 
 struct StageEvents {
   hipEvent_t ev[kMaxStages + 1];
@@ -144,6 +146,14 @@ struct clair_ctx {
   int chunk = 1024;
   // memory
   DevBuf ws;
+  // fixed memory (clair_build_R_noalloc): the workspace and the column lists
+  // in the library's static device array, host staging in a static host
+  // array; nothing is allocated or grown
+  bool fixed = false;
+  char* fixed_dev = nullptr;
+  size_t fixed_dev_bytes = 0;
+  char* fixed_host = nullptr;
+  size_t fixed_host_bytes = 0;
   DevBuf links;    // the projection's column lists: one int2 per R entry of a batch
   int64_t link_cap = 0;
   DevBuf scratch;  // FP64 blocks of oversized rows
@@ -255,6 +265,13 @@ struct Batch {
   Work w;
 };
 
+// device workspace, host staging (upload) and host read-back area
+char* ws_base(clair_ctx* c) { return c->fixed ? c->fixed_dev : static_cast<char*>(c->ws.p); }
+char* stage_base(clair_ctx* c) { return c->fixed ? c->fixed_host : static_cast<char*>(c->stage.p); }
+char* readback_base(clair_ctx* c) {
+  return c->fixed ? c->fixed_host + c->fixed_host_bytes / 2 : static_cast<char*>(c->readback.p);
+}
+
 int check_args(int32_t nmat, const clair_csr_t* A, const int8_t* const* cf, const int32_t* ell,
                clair_csr_out_t* R) {
   if (nmat < 0 || (nmat > 0 && (!A || !cf || !ell || !R))) return CLAIR_ERR_INVALID;
@@ -292,15 +309,24 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
     b->any_agg |= (agg && agg[m]);
   }
   b->L = make_layout(nmat, b->nchunks, b->n_total, c->group, b->any_agg);
-  HIPCHK(c->ws.ensure(b->L.total));
-  HIPCHK(c->stage.ensure(b->L.head_bytes));
-  HIPCHK(c->readback.ensure(b->L.head_bytes));
+  if (c->fixed) {
+    if (b->L.total > c->fixed_dev_bytes || b->L.head_bytes > c->fixed_host_bytes / 2) {
+      snprintf(g_last_error, sizeof(g_last_error),
+               "clair_build_R_noalloc: the workspace of %lld fine points needs %zu bytes, above the %zu-byte "
+               "static scratch", (long long)b->n_total, b->L.total, c->fixed_dev_bytes);
+      return CLAIR_ERR_UNSUPPORTED;
+    }
+  } else {
+    HIPCHK(c->ws.ensure(b->L.total));
+    HIPCHK(c->stage.ensure(b->L.head_bytes));
+    HIPCHK(c->readback.ensure(b->L.head_bytes));
+  }
   // the previous upload must have left the staging buffer before it is rewritten
   if (c->upload_pending) {
     HIPCHK(hipEventSynchronize(c->upload_done));
     c->upload_pending = false;
   }
-  char* base = static_cast<char*>(c->ws.p);
+  char* base = ws_base(c);
   Work& w = b->w;
   w.desc = reinterpret_cast<MatDesc*>(base + b->L.desc);
   w.st = reinterpret_cast<MatStatus*>(base + b->L.st);
@@ -337,7 +363,7 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
   w.GA = c->group;
   w.capC = (int32_t)std::min<int64_t>(b->L.capC, INT32_MAX);
 
-  char* h = static_cast<char*>(c->stage.p);
+  char* h = stage_base(c);
   MatDesc* hd = reinterpret_cast<MatDesc*>(h);
   MatStatus* hs = reinterpret_cast<MatStatus*>(h + (b->L.st - b->L.desc));
   Counters* hc = reinterpret_cast<Counters*>(h + (b->L.cnt - b->L.desc));
@@ -384,6 +410,12 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
 }
 
 int upload(clair_ctx* c, const Batch& b, hipStream_t s) {
+  if (c->fixed) {
+    // the calls of the fixed-memory entry point end with a stream
+    // synchronisation, so the staging area is free again at the next call
+    HIPCHK(hipMemcpyAsync(b.w.desc, stage_base(c), b.L.head_bytes, hipMemcpyHostToDevice, s));
+    return CLAIR_OK;
+  }
   if (!c->upload_done) HIPCHK(hipEventCreateWithFlags(&c->upload_done, hipEventDisableTiming));
   HIPCHK(hipMemcpyAsync(b.w.desc, c->stage.p, b.L.head_bytes, hipMemcpyHostToDevice, s));
   if (capture_check(c->capturing, s, "descriptor upload", __LINE__)) return CLAIR_ERR_HIP;
@@ -395,13 +427,13 @@ int upload(clair_ctx* c, const Batch& b, hipStream_t s) {
 }
 
 int read_status(clair_ctx* c, const Batch& b, hipStream_t s) {
-  HIPCHK(hipMemcpyAsync(c->readback.p, b.w.desc, b.L.head_bytes, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(readback_base(c), b.w.desc, b.L.head_bytes, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   return CLAIR_OK;
 }
 
 const MatStatus* host_status(clair_ctx* c, const Batch& b) {
-  return reinterpret_cast<const MatStatus*>(static_cast<char*>(c->readback.p) + (b.L.st - b.L.desc));
+  return reinterpret_cast<const MatStatus*>(readback_base(c) + (b.L.st - b.L.desc));
 }
 
 int occupancy_blocks(clair_ctx* c, int per_cu) { return std::max(8, c->cus * per_cu); }
@@ -409,6 +441,7 @@ int occupancy_blocks(clair_ctx* c, int per_cu) { return std::max(8, c->cus * per
 // one slot per workgroup of the FP64 solver, each holding a block of the
 // largest size read back (rounded up to a multiple of 8 points)
 int ensure_scratch(clair_ctx* c, int slots, int maxb) {
+  if (c->fixed) return CLAIR_OK;  // no FP64 scratch: the solver reports rows above 64 points
   const int64_t side = std::min<int64_t>(kMaxBlock, ((int64_t)std::max(maxb, 1) + 7) / 8 * 8);
   const int64_t stride = side * side;
   if (c->scratch_slots >= slots && c->scratch_stride >= stride) return CLAIR_OK;
@@ -431,6 +464,20 @@ int ensure_links(clair_ctx* c, Batch& b) {
   if (!b.any_B) return CLAIR_OK;
   const int64_t entries = b.cap_sum;
   if (entries > INT32_MAX) return CLAIR_ERR_UNSUPPORTED;
+  if (c->fixed) {  // after the workspace in the static scratch
+    const size_t at = align_up(b.L.total, 256);
+    const int64_t room = at < c->fixed_dev_bytes ? (int64_t)((c->fixed_dev_bytes - at) / sizeof(int2)) : 0;
+    if (entries > room) {
+      snprintf(g_last_error, sizeof(g_last_error),
+               "clair_build_R_noalloc: %lld R entries of capacity need %lld bytes of column lists beyond the "
+               "workspace; the %zu-byte static scratch leaves %lld", (long long)entries,
+               (long long)(entries * (int64_t)sizeof(int2)), c->fixed_dev_bytes, (long long)(room * sizeof(int2)));
+      return CLAIR_ERR_UNSUPPORTED;
+    }
+    b.w.clink = reinterpret_cast<int2*>(c->fixed_dev + at);
+    b.w.link_cap = entries;
+    return CLAIR_OK;
+  }
   if (c->link_cap < entries) {
     if (c->links.ensure(sizeof(int2) * (size_t)std::max<int64_t>(entries, 1)) != hipSuccess) {
       c->link_cap = 0;
@@ -444,7 +491,7 @@ int ensure_links(clair_ctx* c, Batch& b) {
 }
 
 const Counters* host_counters(clair_ctx* c, const Batch& b) {
-  return reinterpret_cast<const Counters*>(static_cast<char*>(c->readback.p) + (b.L.cnt - b.L.desc));
+  return reinterpret_cast<const Counters*>(readback_base(c) + (b.L.cnt - b.L.desc));
 }
 
 // enqueue the numeric half (after the symbolic pass).  `known` holds the queue
@@ -1527,6 +1574,50 @@ int clair_ctx_get_strength(clair_ctx_t* c, double* theta) {
   if (!c || !theta) return CLAIR_ERR_INVALID;
   *theta = c->theta;
   return CLAIR_OK;
+}
+
+// clair_build_R_noalloc: the whole workspace of one setup (descriptors,
+// chunk arrays, neighbourhood slots, queues, column lists) lives in this
+// static device array, one copy per device the library runs on, kept until
+// the process ends.  Kernels get its device address (hipGetSymbolAddress,
+// once per device), never the name, which in host code is only a stand-in.
+static __device__ __align__(256) char scratch[CLAIR_NOALLOC_SCRATCH_BYTES];
+
+int clair_build_R_noalloc(const clair_csr_t* A, const int8_t* cf_marker, const double* B, int32_t ell,
+                          clair_csr_out_t* R_out, void* stream, clair_info_t* info) {
+  static std::mutex mu;
+  static char* dev_ptr[kNoAllocDevices];
+  static clair_ctx ctx_of[kNoAllocDevices];
+  alignas(256) static char host_stage[kNoAllocDevices][kNoAllocHostBytes];
+  if (!A || !R_out) return CLAIR_ERR_INVALID;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocDevices) return CLAIR_ERR_UNSUPPORTED;
+  clair_ctx* c = &ctx_of[dev];
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (!dev_ptr[dev]) {
+      // set-up on this device's first call, with the device current
+      char* p = nullptr;
+      HIPCHK(hipGetSymbolAddress(reinterpret_cast<void**>(&p), HIP_SYMBOL(scratch)));
+      int cus = 0;
+      HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+      c->device = dev;
+      c->cus = cus > 0 ? cus : 256;
+      c->fixed = true;
+      c->fixed_dev = p;
+      c->fixed_dev_bytes = CLAIR_NOALLOC_SCRATCH_BYTES;
+      c->fixed_host = host_stage[dev];
+      c->fixed_host_bytes = kNoAllocHostBytes;
+      dev_ptr[dev] = p;
+    }
+  }
+  clair_opts_t o{};
+  o.stream = stream;
+  const int8_t* cfs[1] = {cf_marker};
+  const double* Bs[1] = {B};
+  const int32_t ells[1] = {ell};
+  return run_mixed(c, 1, A, cfs, Bs, ells, R_out, &o, info);
 }
 
 int clair_ctx_set_bin_shape(clair_ctx_t* c, int32_t binB_lanes) {
