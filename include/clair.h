@@ -386,9 +386,9 @@ int clair_ctx_get_bin_shape(clair_ctx_t* ctx, int32_t* binB_lanes);
  * hipMalloc): one matrix, mixed precision, default tuning, synchronous on
  * `stream` (NULL = null stream), allocating no device or host memory.  The
  * whole workspace sits in a static device array of
- * CLAIR_NOALLOC_SCRATCH_BYTES (64 MiB), one copy per device the library runs
+ * CLAIR_NOALLOC_SCRATCH_BYTES (96 MiB), one copy per device the library runs
  * on, held until the process ends: the descriptors, per-point arrays of about
- * 200 bytes per fine point of A, and the projection's column lists (8 bytes
+ * 270 bytes per fine point of A, and the projection's listed records (8 bytes
  * per entry of R_out's nnz capacity when B != NULL), which fit a 512 x 512
  * five-point matrix.  An input that does not fit returns
  * CLAIR_ERR_UNSUPPORTED (clair_last_error states the sizes) before any device
@@ -399,7 +399,7 @@ int clair_ctx_get_bin_shape(clair_ctx_t* ctx, int32_t* binB_lanes);
  * array keeps the last call's contents, and every call re-initialises what it
  * reads.
  */
-#define CLAIR_NOALLOC_SCRATCH_BYTES (64 * 1024 * 1024)
+#define CLAIR_NOALLOC_SCRATCH_BYTES (96 * 1024 * 1024)
 int clair_build_R_noalloc(const clair_csr_t* A, const int8_t* cf_marker, const double* B, int32_t ell,
                           clair_csr_out_t* R_out, void* stream, clair_info_t* info);
 
@@ -462,9 +462,24 @@ int clair_ctx_set_graph(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* S);
  */
 int clair_ctx_set_literal_pattern(clair_ctx_t* ctx, int32_t on);
 int clair_ctx_get_strength(clair_ctx_t* ctx, double* theta);
+/*
+ * clair_autotune -- picks the tuning (clair_ctx_set_tuning) and the bin-B
+ * layout (clair_ctx_set_bin_shape) for a batch by timing candidates on it
+ * (reps setups each, after one warm-up), and stores them in ctx.  The
+ * candidates follow the batch's histogram of block sizes (read back after
+ * one synchronous setup): bin-A bounds of 16 and 32 are tried only when rows
+ * above 8 (16) points exist, the bin-B layouts only when rows fall between
+ * the bin-A bound and 32.  The pick is cached per process by (device,
+ * histogram signature, the number of matrices, the strength setting): a
+ * batch whose histogram has, size by size, the same binary order of
+ * magnitude of rows reuses it with no timing runs.  Leaves R_out as one
+ * setup with the chosen tuning writes it.
+ */
 int clair_autotune(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf_marker,
                    const double* const* B, const int32_t* ell, clair_csr_out_t* R_out, void* stream,
                    int32_t reps);
+/* Timing runs of the last clair_autotune on ctx (0 when the cache held it). */
+int clair_ctx_autotune_runs(clair_ctx_t* ctx, int32_t* timed);
 
 /* hipGraph replay of a batched setup on fixed buffers (values of A and B may
  * change between launches; the pattern may change as long as R still fits).

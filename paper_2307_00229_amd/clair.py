@@ -33,7 +33,7 @@ EXPORTED = [
     "clair_spgemm", "clair_galerkin", "clair_smooth_B", "clair_build_R_agg", "clair_project_constraints",
     "clair_build_R_diag", "clair_build_R_approx", "clair_build_R_kkt", "clair_ctx_set_graph",
     "clair_ctx_set_literal_pattern", "clair_ctx_scratch_bytes", "clair_ctx_set_bin_shape", "clair_ctx_get_bin_shape",
-    "clair_build_R_noalloc",
+    "clair_build_R_noalloc", "clair_ctx_autotune_runs",
     "clair_autotune", "clair_graph_create", "clair_graph_launch", "clair_graph_destroy", "clair_graph_info",
     "clair_plan_create", "clair_plan_execute", "clair_plan_info", "clair_plan_destroy",
     "clair_strerror", "clair_last_error",
@@ -104,6 +104,7 @@ def load_library(path: str = LIB_PATH):
         "clair_ctx_get_tuning": ([P, ctypes.POINTER(I32), ctypes.POINTER(I32), ctypes.POINTER(I32)], ctypes.c_int),
         "clair_ctx_scratch_bytes": ([P, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "clair_ctx_set_bin_shape": ([P, I32], ctypes.c_int),
+        "clair_ctx_autotune_runs": ([P, ctypes.POINTER(I32)], ctypes.c_int),
         "clair_build_R_noalloc": ([ctypes.POINTER(CsrIn), P, P, I32, ctypes.POINTER(CsrOut), P, ctypes.POINTER(Info)],
                                   ctypes.c_int),
         "clair_ctx_get_bin_shape": ([P, ctypes.POINTER(I32)], ctypes.c_int),
@@ -293,6 +294,11 @@ class Context:
         g, t, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         self._lib.clair_ctx_get_tuning(self._h, ctypes.byref(g), ctypes.byref(t), ctypes.byref(c))
         return dict(group=g.value, wg_threads=t.value, chunk=c.value)
+
+    def autotune_runs(self) -> int:
+        t = ctypes.c_int32()
+        self._lib.clair_ctx_autotune_runs(self._h, ctypes.byref(t))
+        return t.value
 
     def set_bin_shape(self, binB_lanes: int):
         st = self._lib.clair_ctx_set_bin_shape(self._h, binB_lanes)
@@ -671,7 +677,7 @@ def clair_autotune(ctx: Context, As, cfs, Bs, ells, outs, reps: int = 3, stream=
     st = load_library().clair_autotune(ctx.handle, nmat, Ac, cfp, Bp, ellv, Rc, _stream_ptr(stream), reps)
     if st:
         raise ClairError(st, "clair_autotune")
-    return ctx.get_tuning()
+    return dict(ctx.get_tuning(), binB_lanes=ctx.get_bin_shape(), timing_runs=ctx.autotune_runs())
 
 
 class Graph:

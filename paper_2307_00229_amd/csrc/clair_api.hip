@@ -10,6 +10,7 @@
 #include <climits>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <string>
@@ -141,6 +142,7 @@ struct clair_ctx {
   int literal = 0;  // the literal S^{ell-1} T pattern (the per-row FP64 form; a no-op at ell <= 2)
   int binB_max = 32;  // largest block of the last batch whose sizes were read back (9..32)
   int binB_lanes = 32;  // lanes per row of the bin-B solver (8, 16 or 32)
+  int tune_timed = 0;   // timing runs of the last clair_autotune (0: the cache held the histogram)
   int last_maxb = 0;  // the same, unclamped (0: none read back yet)
   int wg_threads = 256;
   int chunk = 1024;
@@ -1646,57 +1648,164 @@ int clair_ctx_get_tuning(clair_ctx_t* c, int32_t* group, int32_t* wg_threads, in
   return CLAIR_OK;
 }
 
+// The autotuner's cache: the tuning picked for a block-size histogram, per
+// device and search setting.  The histogram counts the rows of each block
+// size 0..32 and above 32 over the whole batch; its signature keeps, per size,
+// the binary order of magnitude of the count (so batches of the same shape
+// and similar size share an entry).
+struct TuneKey {
+  int device;
+  int nmat_class;  // 1, 2..7, 8..63, 64+ matrices
+  double theta;
+  int literal, graph, agg;
+  uint8_t hist[34];
+  bool operator<(const TuneKey& o) const {
+    if (device != o.device) return device < o.device;
+    if (nmat_class != o.nmat_class) return nmat_class < o.nmat_class;
+    if (theta != o.theta) return theta < o.theta;
+    if (literal != o.literal) return literal < o.literal;
+    if (graph != o.graph) return graph < o.graph;
+    if (agg != o.agg) return agg < o.agg;
+    return std::memcmp(hist, o.hist, sizeof(hist)) < 0;
+  }
+};
+struct TuneVal {
+  int group, wg_threads, chunk, binB_lanes;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune_cache;
+
 int clair_autotune(clair_ctx_t* c, int32_t nmat, const clair_csr_t* A, const int8_t* const* cf,
                    const double* const* B, const int32_t* ell, clair_csr_out_t* R, void* stream, int32_t reps) {
   if (!c || reps < 1) return CLAIR_ERR_INVALID;
   const hipStream_t s = static_cast<hipStream_t>(stream);
-  // block-size histogram bound: the largest block decides which groups can hold most rows
+  // one synchronous setup: sizes, validity, and R's row pointers for the
+  // histogram of block sizes
   std::vector<clair_info_t> info(nmat);
   clair_opts_t o{};
   o.stream = stream;
   int rc = clair_build_R_batched(c, nmat, A, cf, B, ell, R, &o, info.data());
   if (rc) return rc;
-  const int groups[5] = {1, 4, 8, 16, 32};
-  const int threads[3] = {64, 128, 256};
-  const int chunks[3] = {512, 1024, 2048};
+  int64_t hist[34] = {0};
+  for (int m = 0; m < nmat; ++m) {
+    const int nc = info[m].n_c;
+    if (nc <= 0) continue;
+    std::vector<int32_t> rp((size_t)nc + 1);
+    HIPCHK(hipMemcpy(rp.data(), R[m].row_ptr, sizeof(int32_t) * rp.size(), hipMemcpyDeviceToHost));
+    for (int r = 0; r < nc; ++r) {
+      const int sz = rp[r + 1] - rp[r] - 1;
+      hist[sz < 0 ? 0 : sz > 32 ? 33 : sz] += 1;
+    }
+  }
+  TuneKey key{};
+  key.device = c->device;
+  key.nmat_class = nmat <= 1 ? 0 : nmat < 8 ? 1 : nmat < 64 ? 2 : 3;
+  key.theta = c->theta;
+  key.literal = c->literal;
+  key.graph = c->graph.empty() ? 0 : 1;
+  key.agg = 0;
+  for (int k = 0; k < 34; ++k) {
+    int mag = 0;
+    for (int64_t v = hist[k]; v > 0; v >>= 1) ++mag;
+    key.hist[k] = (uint8_t)mag;
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      c->group = it->second.group;
+      c->wg_threads = it->second.wg_threads;
+      c->chunk = it->second.chunk;
+      c->binB_lanes = it->second.binB_lanes;
+      c->tune_timed = 0;
+      o.async = 0;
+      return clair_build_R_batched(c, nmat, A, cf, B, ell, R, &o, nullptr);
+    }
+  }
+  int maxs = 0;
+  int64_t above8 = 0, above16 = 0, binB_rows = 0;
+  for (int k = 0; k < 34; ++k) {
+    if (hist[k]) maxs = k;
+    if (k > 8) above8 += hist[k];
+    if (k > 16) above16 += hist[k];
+  }
+  // candidates for the bin-A bound, from the histogram: 16 and 32 lanes per
+  // row only when rows above 8 (16) points exist
+  std::vector<int> groups = {1, 4, 8};
+  if (above8) groups.push_back(16);
+  if (above16) groups.push_back(32);
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  float best = 1e30f;
-  int bg = c->group, bt = c->wg_threads, bc = c->chunk;
+  int timed = 0;
+  auto time_one = [&](float* ms) -> int {
+    int r2 = clair_build_R_batched(c, nmat, A, cf, B, ell, R, &o, nullptr);  // warm-up
+    if (r2) return r2;
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps && !r2; ++r) r2 = clair_build_R_batched(c, nmat, A, cf, B, ell, R, &o, nullptr);
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    (void)hipEventElapsedTime(ms, e0, e1);
+    ++timed;
+    return r2;
+  };
+  TuneVal best{c->group, c->wg_threads, c->chunk, c->binB_lanes};
+  float best_ms = 1e30f;
   o.async = 1;
+  // stage 1: bin-A lanes and workgroup size (chunk 1024)
   for (int g : groups) {
-    for (int t : threads) {
+    for (int t : {64, 128, 256}) {
       if (g == 32 && t == 256) continue;
-      for (int ch : chunks) {
-        c->group = g;
-        c->wg_threads = t;
-        c->chunk = ch;
-        rc = clair_build_R_batched(c, nmat, A, cf, B, ell, R, &o, nullptr);  // warm-up
-        if (rc) break;
-        (void)hipEventRecord(e0, s);
-        for (int r = 0; r < reps && !rc; ++r) rc = clair_build_R_batched(c, nmat, A, cf, B, ell, R, &o, nullptr);
-        (void)hipEventRecord(e1, s);
-        (void)hipEventSynchronize(e1);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (!rc && ms < best) {
-          best = ms;
-          bg = g;
-          bt = t;
-          bc = ch;
-        }
-      }
+      c->group = g;
+      c->wg_threads = t;
+      c->chunk = 1024;
+      float ms = 0.f;
+      if (!time_one(&ms) && ms < best_ms) { best_ms = ms; best = {g, t, 1024, c->binB_lanes}; }
+    }
+  }
+  // stage 2: the symbolic pass's chunk
+  for (int ch : {512, 2048}) {
+    c->group = best.group;
+    c->wg_threads = best.wg_threads;
+    c->chunk = ch;
+    float ms = 0.f;
+    if (!time_one(&ms) && ms < best_ms) { best_ms = ms; best.chunk = ch; }
+  }
+  // stage 3: the bin-B layout, when rows fall between the bin-A bound and 32
+  const int abound = best.group <= 8 ? 8 : best.group;
+  for (int k = abound + 1; k <= 32; ++k) binB_rows += hist[k];
+  if (binB_rows) {
+    for (int lanes : {8, 16, 32}) {
+      if (lanes == best.binB_lanes) continue;
+      c->group = best.group;
+      c->wg_threads = best.wg_threads;
+      c->chunk = best.chunk;
+      c->binB_lanes = lanes;
+      float ms = 0.f;
+      if (!time_one(&ms) && ms < best_ms) { best_ms = ms; best.binB_lanes = lanes; }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  c->group = bg;
-  c->wg_threads = bt;
-  c->chunk = bc;
+  (void)maxs;
+  c->group = best.group;
+  c->wg_threads = best.wg_threads;
+  c->chunk = best.chunk;
+  c->binB_lanes = best.binB_lanes;
+  c->tune_timed = timed;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = best;
+  }
   // leave R consistent with the chosen shape
   o.async = 0;
   return clair_build_R_batched(c, nmat, A, cf, B, ell, R, &o, nullptr);
+}
+
+int clair_ctx_autotune_runs(clair_ctx_t* c, int32_t* timed) {
+  if (!c || !timed) return CLAIR_ERR_INVALID;
+  *timed = c->tune_timed;
+  return CLAIR_OK;
 }
 
 struct clair_graph {

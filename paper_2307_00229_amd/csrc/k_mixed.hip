@@ -306,6 +306,53 @@ __device__ __forceinline__ int xcd_logical_block(int nb) {
 }
 __device__ __forceinline__ int xcd_logical_block() { return xcd_logical_block(gridDim.x); }
 
+// Rows of the persistent numeric kernels: XCD x (= blockIdx.x % 8, the
+// hardware deals workgroups round-robin) owns a contiguous eighth of all
+// rows, and its workgroups take blocks of nb rows from it in turn.  The rows
+// in flight on one XCD at any time are then neighbours, whose blocks share A
+// rows in that XCD's L2 (with a contiguous range per workgroup they would be
+// as many separate streams through A as there are workgroups).
+struct RowBlocks {
+  int xb, xe, k, nx, nb;
+  __device__ __forceinline__ RowBlocks(int total, int nb_) {
+    const int x = blockIdx.x % 8;
+    const int per = (total + 7) / 8;
+    xb = min(total, x * per);
+    xe = min(total, xb + per);
+    nx = (int)gridDim.x / 8 + ((int)(gridDim.x % 8) > x ? 1 : 0);
+    k = blockIdx.x / 8;
+    nb = nb_;
+  }
+  // the j-th block of this workgroup: rows [*b, *e); false past the end
+  __device__ __forceinline__ bool block(int j, int* b, int* e) const {
+    const int64_t s0 = xb + ((int64_t)k + (int64_t)j * nx) * nb;
+    if (s0 >= xe) return false;
+    *b = (int)s0;
+    *e = min(xe, (int)s0 + nb);
+    return true;
+  }
+};
+
+// Most refinement steps of the rows a thread (lane 0 of a group) finished,
+// per matrix: gathered in registers and sent with one global atomic when the
+// thread moves on to another matrix or ends (one atomic per row would meet
+// at a handful of addresses in a batch of many matrices).
+struct RefineMax {
+  int m = -1, v = 0;
+  __device__ __forceinline__ void flush(const Work& w) {
+    if (m >= 0 && v > __hip_atomic_load(&w.st[m].refine_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(&w.st[m].refine_max, v);
+  }
+  __device__ __forceinline__ void add(const Work& w, int mm, int it) {
+    if (mm != m) {
+      flush(w);
+      m = mm;
+      v = 0;
+    }
+    v = max(v, it);
+  }
+};
+
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
 // wave-aggregated queue append: every lane with `want` gets a distinct slot
@@ -773,7 +820,6 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
   constexpr int NG = NT / G;
   constexpr int LD = SM + 1;
   __shared__ NumGroupBuf<G, SM> sb[NG];
-  __shared__ int s_itmax;
 
   const int tid = threadIdx.x;
   const int grp = tid / G;
@@ -787,16 +833,10 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
   const int32_t* slots = which ? w.slotB : w.slotA;
   const int sstride = which ? 32 : w.GA;
   const int total = w.cnt->total_rows;
-  const int lb = xcd_logical_block();
-  const int per = (total + gridDim.x - 1) / gridDim.x;
-  const int r0 = lb * per;
-  const int r1 = min(total, r0 + per);
-  if (r0 >= r1) return;
-  // statistics of the workgroup's first matrix gather in LDS (one global
-  // atomic per workgroup); rows of later matrices in the range go straight out
-  const int m0 = w.chunk_mat[row_chunk_fast(w, r0)];
-  if (tid == 0) s_itmax = 0;
-  __syncthreads();
+  const RowBlocks rbk(total, 4 * NG);
+  int r0, r1;
+  if (!rbk.block(0, &r0, &r1)) return;
+  RefineMax rmx;
   ChunkCursor cc;
   // The group works one row ahead: while row g is solved, the chunk-local
   // data, the slot entry and the A-row bounds of row g + NG (same chunk) are
@@ -804,6 +844,8 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
   int nx_t = 0, nx_i = 0, nx_off = 0, nx_s = -1, nx_N = 0, nx_e0 = 0, nx_e1 = 0, nx_f0 = 0, nx_f1 = 0;
   bool ahead = false;
 
+  for (int jb = 0; rbk.block(jb, &r0, &r1); ++jb) {
+  ahead = false;
   for (int gbase = r0; gbase < r1; gbase += NG) {
     const int g = gbase + grp;
     if (g >= r1) break;  // group-uniform
@@ -980,10 +1022,7 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
       }
       continue;
     }
-    if (lane == 0) {
-      if (ri.m == m0) atomicMax(&s_itmax, it);
-      else atomicMax(&st->refine_max, it);
-    }
+    if (lane == 0) rmx.add(w, ri.m, it);
 
     // ---- R row: F-entries of N(i) around the injected C-point ----
     if (lane < s) put_f_entry(w, d, ri.fine0, ri.off + lane + (lane >= dpos ? 1 : 0), myN, i, z);
@@ -992,9 +1031,8 @@ __global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
       d.Rva[ri.off + dpos] = 1.0;
     }
   }
-  __syncthreads();
-  if (tid == 0 && s_itmax > __hip_atomic_load(&w.st[m0].refine_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-    atomicMax(&w.st[m0].refine_max, s_itmax);
+  }
+  if (lane == 0) rmx.flush(w);
 }
 
 // ---------------------------------------------------------------------------
@@ -1094,15 +1132,10 @@ __global__ __launch_bounds__(NT) void k_lanes(Work w, int which) {
   const int32_t* slots = which ? w.slotB : w.slotA;
   const int sstride = which ? 32 : slot_stride(w.GA);
   const int total = w.cnt->total_rows;
-  const int lb = xcd_logical_block();
-  const int per = (total + gridDim.x - 1) / gridDim.x;
-  const int r0 = lb * per;
-  const int r1 = min(total, r0 + per);
-  if (r0 >= r1) return;
-  // most refinement steps of the group's rows of its first matrix (one
-  // atomic per group at the end); rows of later matrices go straight out
-  const int m0 = w.chunk_mat[row_chunk_fast(w, r0)];
-  int itmax = 0;
+  const RowBlocks rbk(total, 4 * NG);
+  int r0, r1;
+  if (!rbk.block(0, &r0, &r1)) return;
+  RefineMax rmx;
   ChunkCursor cc;
   // one row ahead, as in k_numeric: chunk data, slot entries and A-row bounds
   // of row g + NG are loaded while row g is solved
@@ -1110,6 +1143,8 @@ __global__ __launch_bounds__(NT) void k_lanes(Work w, int which) {
   int nx_N[R], nx_e0[R], nx_e1[R];
   bool ahead = false;
 
+  for (int jb = 0; rbk.block(jb, &r0, &r1); ++jb) {
+  ahead = false;
   for (int gbase = r0; gbase < r1; gbase += NG) {
     const int g = gbase + grp;
     if (g >= r1) break;  // group-uniform
@@ -1345,8 +1380,7 @@ __global__ __launch_bounds__(NT) void k_lanes(Work w, int which) {
       }
       continue;
     }
-    if (cc.m == m0) itmax = max(itmax, it);
-    else if (lane == 0) atomicMax(&st->refine_max, it);
+    if (lane == 0) rmx.add(w, cc.m, it);
 
     // ---- R row: F-entries of N(i) around the injected C-point ----
 #pragma unroll
@@ -1359,8 +1393,8 @@ __global__ __launch_bounds__(NT) void k_lanes(Work w, int which) {
       d.Rva[off + dpos] = 1.0;
     }
   }
-  if (lane == 0 && itmax > __hip_atomic_load(&w.st[m0].refine_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-    atomicMax(&w.st[m0].refine_max, itmax);
+  }
+  if (lane == 0) rmx.flush(w);
 }
 
 // ---------------------------------------------------------------------------
@@ -1421,24 +1455,20 @@ template <int NT>
 __global__ __launch_bounds__(NT) void k_quad8(Work w) {
   constexpr int NQ = NT / 4;
   __shared__ QuadBuf qbuf[NQ];
-  __shared__ int s_itmax;
   const int tid = threadIdx.x;
   const int qd = tid >> 2;
   const int ql = tid & 3;
   QuadBuf& B = qbuf[qd];
   if (w.cnt->nA == 0) return;
   const int total = w.cnt->total_rows;
-  const int lb = xcd_logical_block();
-  const int per = (total + gridDim.x - 1) / gridDim.x;
-  const int r0 = lb * per;
-  const int r1 = min(total, r0 + per);
-  if (r0 >= r1) return;
-  const int m0 = w.chunk_mat[row_chunk_fast(w, r0)];
-  if (tid == 0) s_itmax = 0;
-  __syncthreads();
+  const RowBlocks rbk(total, 4 * NQ);
+  int r0, r1;
+  if (!rbk.block(0, &r0, &r1)) return;
+  RefineMax rmx;
   const int q0 = 2 * ql, q1 = 2 * ql + 1;  // this lane's rows of K
   ChunkCursor cc;
 
+  for (int jb = 0; rbk.block(jb, &r0, &r1); ++jb) {
   for (int g = r0 + qd; g < r1; g += NQ) {  // quad-uniform
     cc.seek(w, g);
     int t, i, off, s;
@@ -1616,10 +1646,7 @@ __global__ __launch_bounds__(NT) void k_quad8(Work w) {
       }
       continue;
     }
-    if (ql == 0) {
-      if (ri.m == m0) atomicMax(&s_itmax, it);
-      else atomicMax(&st->refine_max, it);
-    }
+    if (ql == 0) rmx.add(w, ri.m, it);
     // R row
     const int dpos_l = (n0 < i ? 1 : 0) + (n1 < i ? 1 : 0);
     const int dpos = dpos_l + __builtin_amdgcn_mov_dpp(dpos_l, 0xB1, 0xF, 0xF, false);
@@ -1634,9 +1661,8 @@ __global__ __launch_bounds__(NT) void k_quad8(Work w) {
       d.Rva[ri.off + dposq] = 1.0;
     }
   }
-  __syncthreads();
-  if (tid == 0 && s_itmax > __hip_atomic_load(&w.st[m0].refine_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-    atomicMax(&w.st[m0].refine_max, s_itmax);
+  }
+  if (ql == 0) rmx.flush(w);
 }
 
 // ---------------------------------------------------------------------------
@@ -1717,21 +1743,17 @@ __device__ __forceinline__ void gather8_pair(gptr<const int32_t> __restrict__ ci
 
 template <int NT>
 __global__ __launch_bounds__(NT) void k_rows8(Work w) {
-  __shared__ int s_itmax;
   if (w.cnt->nA == 0) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int total = w.cnt->total_rows;
-  const int lb = xcd_logical_block();
-  const int per = (total + gridDim.x - 1) / gridDim.x;
-  const int r0 = lb * per;
-  const int r1 = min(total, r0 + per);
-  if (r0 >= r1) return;
-  const int m0 = w.chunk_mat[row_chunk_fast(w, r0)];
-  if (tid == 0) s_itmax = 0;
-  __syncthreads();
+  const RowBlocks rbk(total, 4 * NT);
+  int r0, r1;
+  if (!rbk.block(0, &r0, &r1)) return;
+  RefineMax rmx;
   ChunkCursor cc;
 
+  for (int jb = 0; rbk.block(jb, &r0, &r1); ++jb) {
   for (int gw = r0 + (tid & ~63); gw < r1; gw += NT) {
     const int g = gw + lane;
     const int gend = min(gw + 64, r1);
@@ -1873,8 +1895,7 @@ __global__ __launch_bounds__(NT) void k_rows8(Work w) {
         else flag_row(st, ST_UNSUPPORTED, i);
         continue;
       }
-      if (cc.m == m0) atomicMax(&s_itmax, it);
-      else atomicMax(&st->refine_max, it);
+      rmx.add(w, cc.m, it);
 
       // R row: the F-entries of N(i) around the injected C-point
       int dpos = 0;
@@ -1887,9 +1908,8 @@ __global__ __launch_bounds__(NT) void k_rows8(Work w) {
       d.Rva[off + dpos] = 1.0;
     }
   }
-  __syncthreads();
-  if (tid == 0 && s_itmax > __hip_atomic_load(&w.st[m0].refine_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-    atomicMax(&w.st[m0].refine_max, s_itmax);
+  }
+  rmx.flush(w);
 }
 
 // ---------------------------------------------------------------------------

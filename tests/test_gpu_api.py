@@ -319,3 +319,30 @@ def test_plan_with_workgroup_rows_and_bad_arguments():
     assert st == clair.CLAIR_ERR_INVALID
     infos, st = plan.execute(As, Bs, [clair.ROut(ncs[0], nzs[0] - 1)], check=False)
     assert st == clair.CLAIR_ERR_CAPACITY
+
+
+def test_autotune_cache_by_histogram():
+    # the pick is cached by (device, block-size histogram signature): a second
+    # autotune on the same inputs (another context) makes no timing runs and
+    # returns the same tuning; another histogram is timed
+    from paper_2307_00229_amd import clair
+
+    ps = [P.small_2d(143, stencil=9, eps=2e-3, angle=1.3, k=3, ell=2), P.small_3d(17, eps=0.02, ell=2)]
+    As, cfs, Bs, ells = to_device(ps)
+    ncs, nzs = clair.clair_size_R(As, cfs, ells)
+    outs = [clair.ROut(a, b) for a, b in zip(ncs, nzs)]
+    t1 = clair.clair_autotune(clair.Context(), As, cfs, Bs, ells, outs, reps=1)
+    assert t1["timing_runs"] > 0
+    ctx2 = clair.Context()
+    t2 = clair.clair_autotune(ctx2, As, cfs, Bs, ells, outs, reps=1)
+    assert t2["timing_runs"] == 0
+    assert {k: t1[k] for k in ("group", "wg_threads", "chunk", "binB_lanes")} == \
+        {k: t2[k] for k in ("group", "wg_threads", "chunk", "binB_lanes")}
+    for p, o in zip(ps, outs):
+        assert_matches_oracle(p, _fetch(o), oracle.build_R_problem(p))
+    q = [P.small_2d(61, stencil=5, eps=1e-5, angle=4.0, ell=1)]
+    Aq, cq, Bq, eq = to_device(q)
+    nq, zq = clair.clair_size_R(Aq, cq, eq)
+    oq = [clair.ROut(a, b) for a, b in zip(nq, zq)]
+    t3 = clair.clair_autotune(ctx2, Aq, cq, Bq, eq, oq, reps=1)
+    assert t3["timing_runs"] > 0
