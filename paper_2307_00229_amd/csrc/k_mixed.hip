@@ -2355,7 +2355,7 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
 // uncovered.  Lists of up to kPL entries are ordered in registers; a longer
 // list is taken kPL entries at a time, each pass keeping the smallest
 // positions above the last one summed.
-constexpr int kPL = 8;
+constexpr int kPL = 4;
 
 struct ColEntry {
   int e[kPL];     // batch-wide R entry, INT32_MAX when empty
@@ -2387,6 +2387,72 @@ struct ColEntry {
   }
 };
 
+// One F-column of any length (the general path of k_colproj): returns true
+// when the column is uncovered (d_j = 0)
+__device__ bool project_column(const Work& w, const GDesc& d, int64_t nzb, int j, int head) {
+  // first pass: the kPL smallest positions of the list
+  ColEntry L;
+  L.clear();
+  bool more = false;
+  for (int e = head; e >= 0;) {
+    const int2 lk = w.clink[e];
+    const double zv = d.Rva[e - nzb];
+    more |= !L.insert(e, lk.y, zv);
+    e = lk.x;
+  }
+  double dsum = 0.0, rsum = 0.0;
+#pragma unroll
+  for (int k = 0; k < kPL; ++k) {
+    if (k < L.n) {
+      const double bi = d.B[L.ci[k]];
+      dsum = fma(bi, bi, dsum);
+      rsum = fma(L.z[k], bi, rsum);
+    }
+  }
+  // longer lists: further passes, each over the positions above the last
+  // one taken
+  int last = L.e[kPL - 1];
+  while (more) {
+    ColEntry M;
+    M.clear();
+    more = false;
+    for (int e = head; e >= 0;) {
+      const int2 lk = w.clink[e];
+      if (e > last) more |= !M.insert(e, lk.y, d.Rva[e - nzb]);
+      e = lk.x;
+    }
+#pragma unroll
+    for (int k = 0; k < kPL; ++k) {
+      if (k < M.n) {
+        const double bi = d.B[M.ci[k]];
+        dsum = fma(bi, bi, dsum);
+        rsum = fma(M.z[k], bi, rsum);
+      }
+    }
+    last = M.e[kPL - 1];
+  }
+  if (!(dsum > 0.0)) return true;
+  const double q = (rsum - d.B[j]) / dsum;
+  if (L.n < kPL || L.e[kPL - 1] == last) {
+    // the whole list is in registers
+#pragma unroll
+    for (int k = 0; k < kPL; ++k)
+      if (k < L.n) d.Rva[L.e[k] - nzb] = L.z[k] - d.B[L.ci[k]] * q;
+  } else {
+    for (int e = head; e >= 0;) {
+      const int2 lk = w.clink[e];
+      d.Rva[e - nzb] -= d.B[lk.y] * q;
+      e = lk.x;
+    }
+  }
+  return false;
+}
+
+// Constraint projection kernel: IC F-points per thread walked together (their
+// list loads in flight at once), each list of up to kPI records in
+// registers; a longer list takes the general path.
+constexpr int kIC = 4, kPI = 4;
+
 __global__ __launch_bounds__(256) void k_colproj(Work w) {
   __shared__ int s_unc;
   const int c = xcd_logical_block();
@@ -2400,65 +2466,76 @@ __global__ __launch_bounds__(256) void k_colproj(Work w) {
   if (tid == 0) s_unc = 0;
   __syncthreads();
   int unc = 0;
-  for (int j = f0 + tid; j < f1; j += blockDim.x) {
-    const int8_t cj = d.cf[j];
-    const int head = w.chead[d.fine0 + j];
-    if (cj != 0) continue;
-    if (head < 0) { ++unc; continue; }
-    // first pass: the kPL smallest positions of the list
-    ColEntry L;
-    L.clear();
-    bool more = false;
-    for (int e = head; e >= 0;) {
-      const int2 lk = w.clink[e];
-      const double zv = d.Rva[e - nzb];
-      more |= !L.insert(e, lk.y, zv);
-      e = lk.x;
-    }
-    double dsum = 0.0, rsum = 0.0;
+  for (int jb = f0 + tid; jb < f1; jb += blockDim.x * kIC) {
+    int j[kIC], e[kIC], head[kIC], n[kIC];
+    int re[kIC][kPI], ri[kIC][kPI];
+    double rz[kIC][kPI];
 #pragma unroll
-    for (int k = 0; k < kPL; ++k) {
-      if (k < L.n) {
-        const double bi = d.B[L.ci[k]];
-        dsum = fma(bi, bi, dsum);
-        rsum = fma(L.z[k], bi, rsum);
-      }
-    }
-    // longer lists: further passes, each over the positions above the last
-    // one taken
-    int last = L.e[kPL - 1];
-    while (more) {
-      ColEntry M;
-      M.clear();
-      more = false;
-      for (int e = head; e >= 0;) {
-        const int2 lk = w.clink[e];
-        if (e > last) more |= !M.insert(e, lk.y, d.Rva[e - nzb]);
-        e = lk.x;
-      }
-#pragma unroll
-      for (int k = 0; k < kPL; ++k) {
-        if (k < M.n) {
-          const double bi = d.B[M.ci[k]];
-          dsum = fma(bi, bi, dsum);
-          rsum = fma(M.z[k], bi, rsum);
+    for (int q = 0; q < kIC; ++q) {
+      j[q] = jb + q * (int)blockDim.x;
+      head[q] = -1;
+      n[q] = 0;
+      if (j[q] < f1) {
+        const int8_t cj = d.cf[j[q]];
+        const int h = w.chead[d.fine0 + j[q]];
+        if (cj == 0) {
+          head[q] = h;
+          if (h < 0) ++unc;
         }
       }
-      last = M.e[kPL - 1];
+      e[q] = head[q];
     }
-    if (!(dsum > 0.0)) { ++unc; continue; }
-    const double q = (rsum - d.B[j]) / dsum;
-    if (L.n < kPL || L.e[kPL - 1] == last) {
-      // the whole list is in registers
+    // walk the lists together, kPI steps
 #pragma unroll
-      for (int k = 0; k < kPL; ++k)
-        if (k < L.n) d.Rva[L.e[k] - nzb] = L.z[k] - d.B[L.ci[k]] * q;
-    } else {
-      for (int e = head; e >= 0;) {
-        const int2 lk = w.clink[e];
-        d.Rva[e - nzb] -= d.B[lk.y] * q;
-        e = lk.x;
+    for (int k = 0; k < kPI; ++k) {
+#pragma unroll
+      for (int q = 0; q < kIC; ++q) {
+        re[q][k] = INT32_MAX;
+        ri[q][k] = 0;
+        rz[q][k] = 0.0;
+        if (e[q] >= 0) {
+          const int2 lk = w.clink[e[q]];
+          re[q][k] = e[q];
+          ri[q][k] = lk.y;
+          rz[q][k] = d.Rva[e[q] - nzb];
+          e[q] = lk.x;
+          ++n[q];
+        }
       }
+    }
+#pragma unroll
+    for (int q = 0; q < kIC; ++q) {
+      if (head[q] < 0) continue;
+      if (e[q] >= 0) {  // more than kPI records
+        unc += project_column(w, d, nzb, j[q], head[q]) ? 1 : 0;
+        continue;
+      }
+      // order the records by R position (a sorting network on kPI = 4)
+#define CLAIR_CS(A, B)                                                   \
+  if (re[q][B] < re[q][A]) {                                            \
+    const int te = re[q][A]; re[q][A] = re[q][B]; re[q][B] = te;         \
+    const int ti = ri[q][A]; ri[q][A] = ri[q][B]; ri[q][B] = ti;         \
+    const double tz = rz[q][A]; rz[q][A] = rz[q][B]; rz[q][B] = tz;      \
+  }
+      CLAIR_CS(0, 1) CLAIR_CS(2, 3) CLAIR_CS(0, 2) CLAIR_CS(1, 3) CLAIR_CS(1, 2)
+#undef CLAIR_CS
+      double bi[kPI];
+#pragma unroll
+      for (int k = 0; k < kPI; ++k) bi[k] = (k < n[q]) ? d.B[ri[q][k]] : 0.0;
+      const double bj = d.B[j[q]];
+      double dsum = 0.0, rsum = 0.0;
+#pragma unroll
+      for (int k = 0; k < kPI; ++k) {
+        if (k < n[q]) {
+          dsum = fma(bi[k], bi[k], dsum);
+          rsum = fma(rz[q][k], bi[k], rsum);
+        }
+      }
+      if (!(dsum > 0.0)) { ++unc; continue; }
+      const double qq = (rsum - bj) / dsum;
+#pragma unroll
+      for (int k = 0; k < kPI; ++k)
+        if (k < n[q]) d.Rva[re[q][k] - nzb] = rz[q][k] - bi[k] * qq;
     }
   }
 #pragma unroll
