@@ -97,7 +97,7 @@ def bin_rows(outs, tuning):
 def stage_kernel_name(stage, tuning):
     g = tuning["group"]
     small = {1: "k_rows8", 4: "k_quad8"}.get(g, f"k_numeric<{g},...> (bin A)")
-    return {"count": "k_count", "count_big": "k_count_big", "scan": "k_scan", "numeric": small,
+    return {"adj": "k_adj", "count": "k_count", "count_mid": "k_count_mid", "count_big": "k_count_big", "scan": "k_scan", "numeric": small,
             "numeric32": "k_numeric<16|32,128,SM> (bin B)", "rows_wg": "k_rows_wg", "project": "k_project",
             "upload": "descriptor upload"}.get(stage, stage)
 
@@ -305,6 +305,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tuning", default=None,
+                    help="fixed tuning GROUP,WG_THREADS,CHUNK[,BINB_LANES] instead of the autotuner's pick")
     ap.add_argument("--aggregates", action="store_true",
                     help="C/F splitting and base pattern from greedy aggregates (clair_build_R_agg); "
                          "direct launches only, no plain form, graph or plan")
@@ -354,7 +356,12 @@ def main():
             sized, _, _ = clair.clair_build_R_agg(As, cfs, aggs, Bs, ells, ctx=ctx, stream=stream)
             n_c_list, nnz_list = [o.n_c for o in sized], [o.nnz for o in sized]
         outs = [clair.ROut(nc, nz, dev) for nc, nz in zip(n_c_list, nnz_list)]
-        if not args.no_autotune and aggs is None:
+        if args.tuning:
+            t = [int(x) for x in args.tuning.split(",")]
+            ctx.set_tuning(*t[:3])
+            if len(t) > 3:
+                ctx.set_bin_shape(t[3])
+        elif not args.no_autotune and aggs is None:
             clair.clair_autotune(ctx, As, cfs, Bs, ells, outs, reps=3, stream=stream)
         tuning = ctx.get_tuning()
         rows = sum(n_c_list)

@@ -427,6 +427,24 @@ int clair_ctx_scratch_bytes(clair_ctx_t* ctx, int64_t* bytes);
 int clair_ctx_set_strength(clair_ctx_t* ctx, double theta);
 
 /*
+ * How the symbolic phase of the mixed form finds N(i) (Section 3.1.3, the
+ * pattern of Algorithm 1) for matrices with ell >= 2.  By default (mode -1) a
+ * prepass first lists, for every point u, the F-points that one step from u
+ * reaches (the edge test above), in 4 slots per point when every such matrix
+ * has at most five stored entries per row on average, else 8; the search then
+ * takes each level's whole frontier from that list in one round of loads.
+ * Points with more such neighbours than slots are expanded from the rows of
+ * A (or of the strength matrix), as are matrices with more than nine stored
+ * entries per row on average, aggregates and every call of
+ * clair_build_R_noalloc.  Mode 0 searches every row from A directly; 4 or 8
+ * forces that width.  The pattern and R are identical in every mode; the
+ * setting changes only the work (mode 4 on a nine-point stencil sends most
+ * points down the row path).  Any other mode returns CLAIR_ERR_INVALID.
+ * Applies to later calls on ctx, graphs captured and plans created after it.
+ */
+int clair_ctx_set_search_adjacency(clair_ctx_t* ctx, int32_t mode);
+
+/*
  * A strength matrix of the caller's as the graph of the neighbourhood search
  * (Algorithm 1 takes the strength matrix S as an input, Section 3.1.3): one n
  * x n CSR per matrix of the batches that follow (device arrays, rows sorted,

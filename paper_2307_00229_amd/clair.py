@@ -29,7 +29,7 @@ CLAIR_MAX_BLOCK = 1024
 EXPORTED = [
     "clair_ctx_create", "clair_ctx_destroy", "clair_build_R", "clair_build_R_ex", "clair_build_R_batched",
     "clair_ctx_info", "clair_size_R", "clair_ctx_stage_times", "clair_ctx_set_tuning", "clair_ctx_get_tuning",
-    "clair_ctx_set_strength", "clair_ctx_get_strength", "clair_transpose", "clair_build_P",
+    "clair_ctx_set_strength", "clair_ctx_get_strength", "clair_ctx_set_search_adjacency", "clair_transpose", "clair_build_P",
     "clair_spgemm", "clair_galerkin", "clair_smooth_B", "clair_build_R_agg", "clair_project_constraints",
     "clair_build_R_diag", "clair_build_R_approx", "clair_build_R_kkt", "clair_ctx_set_graph",
     "clair_ctx_set_literal_pattern", "clair_ctx_scratch_bytes", "clair_ctx_set_bin_shape", "clair_ctx_get_bin_shape",
@@ -109,6 +109,7 @@ def load_library(path: str = LIB_PATH):
                                   ctypes.c_int),
         "clair_ctx_get_bin_shape": ([P, ctypes.POINTER(I32)], ctypes.c_int),
         "clair_ctx_set_strength": ([P, ctypes.c_double], ctypes.c_int),
+        "clair_ctx_set_search_adjacency": ([P, I32], ctypes.c_int),
         "clair_ctx_get_strength": ([P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "clair_autotune": ([P, I32, ctypes.POINTER(CsrIn), ctypes.POINTER(P), ctypes.POINTER(P),
                             ctypes.POINTER(I32), ctypes.POINTER(CsrOut), P, I32], ctypes.c_int),
@@ -264,6 +265,13 @@ class Context:
         st = self._lib.clair_ctx_set_strength(self._h, float(theta))
         if st:
             raise ClairError(st, "clair_ctx_set_strength")
+
+    def set_search_adjacency(self, mode: int):
+        """The symbolic phase's compact adjacency: -1 automatic width, 0 off,
+        4 or 8 forced width (the pattern is the same in every mode)."""
+        st = self._lib.clair_ctx_set_search_adjacency(self._h, int(mode))
+        if st:
+            raise ClairError(st, "clair_ctx_set_search_adjacency")
 
     def set_graph(self, graphs):
         """Strength matrices (CSR, one per matrix of the batches that follow)

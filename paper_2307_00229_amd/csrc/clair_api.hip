@@ -72,12 +72,12 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
   size_t desc, st, cnt, chunk_nc, chunk_nnz, chunk_rbase, chunk_nzbase, chunk_mat, chunk_bins, row_block_chunk, clocal, lnz, chead,
-      slotA, slotB, binC, bigq, big_size, ovf, cmax, agg_cnt, agg_rp, agg_list, agg_sums, total;
+      slotA, slotB, binC, bigq, big_size, ovf, cmax, agg_cnt, agg_rp, agg_list, agg_sums, fadj, total;
   size_t head_bytes;  // desc + st + counters (the uploaded head)
   int64_t capC;
 };
 
-Layout make_layout(int nmat, int nchunks, int64_t n_total, int GA, bool any_agg) {
+Layout make_layout(int nmat, int nchunks, int64_t n_total, int GA, bool any_agg, int adj_w) {
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -116,11 +116,12 @@ Layout make_layout(int nmat, int nchunks, int64_t n_total, int GA, bool any_agg)
   L.agg_rp = take(sizeof(int32_t) * (na + 2));
   L.agg_list = take(sizeof(int32_t) * (na + 1));
   L.agg_sums = take(sizeof(int32_t) * (na / 1024 + 4));
+  L.fadj = take(sizeof(int32_t) * (adj_w ? n_total * adj_w : 1));
   L.total = o;
   return L;
 }
 
-constexpr int kMaxStages = 12;
+constexpr int kMaxStages = 16;
 constexpr int kNoAllocDevices = 64;      // devices the fixed-memory entry point serves
 constexpr int kNoAllocHostBytes = 8192;  // its host staging per device (descriptor upload + status read-back)
 
@@ -138,6 +139,7 @@ struct clair_ctx {
   // tuning
   int group = 8;  // lanes per row of the small solver: 1, 4 or 8 (|N| <= 8), 16/32 (|N| <= group)
   double theta = 0.0;  // strength threshold of the neighbourhood search
+  int adj_mode = -1;   // the search's compact adjacency: -1 automatic width, 0 off, 4 or 8 forced width
   std::vector<clair_csr_t> graph;  // strength matrices of the search, one per matrix (empty: A's graph)
   int literal = 0;  // the literal S^{ell-1} T pattern (the per-row FP64 form; a no-op at ell <= 2)
   int binB_max = 32;  // largest block of the last batch whose sizes were read back (9..32)
@@ -263,6 +265,7 @@ struct Batch {
   int64_t cap_sum = 0;  // R capacities summed over the batch (bounds the R entries of an asynchronous call)
   bool any_B;
   bool any_agg = false;
+  int adj_w = 0;  // slots per point of the search's compact adjacency (0: not built)
   Layout L;
   Work w;
 };
@@ -310,7 +313,24 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
     b->any_B |= (B && B[m]);
     b->any_agg |= (agg && agg[m]);
   }
-  b->L = make_layout(nmat, b->nchunks, b->n_total, c->group, b->any_agg);
+  // the compact adjacency serves the searches of distance 2 and more on
+  // sparse graphs: width 4 when every such graph has at most five stored
+  // entries per row on average, else 8 (points beyond it are searched from
+  // the rows); denser graphs, aggregates and the fixed-memory entry point go
+  // without
+  std::vector<char> use_adj(nmat, 0);
+  b->adj_w = 0;
+  if (!c->fixed && c->adj_mode != 0) {
+    int w_need = 0;
+    for (int m = 0; m < nmat; ++m) {
+      const int64_t gnnz = c->graph.empty() ? A[m].nnz : c->graph[m].nnz;
+      if (ell[m] < 2 || A[m].n <= 0 || (agg && agg[m]) || gnnz > 9 * (int64_t)A[m].n) continue;
+      use_adj[m] = 1;
+      w_need = std::max(w_need, gnnz <= 5 * (int64_t)A[m].n ? 4 : 8);
+    }
+    b->adj_w = c->adj_mode > 0 ? (w_need ? c->adj_mode : 0) : w_need;
+  }
+  b->L = make_layout(nmat, b->nchunks, b->n_total, c->group, b->any_agg, b->adj_w);
   if (c->fixed) {
     if (b->L.total > c->fixed_dev_bytes || b->L.head_bytes > c->fixed_host_bytes / 2) {
       snprintf(g_last_error, sizeof(g_last_error),
@@ -364,6 +384,8 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
   w.chunk = c->chunk;
   w.GA = c->group;
   w.capC = (int32_t)std::min<int64_t>(b->L.capC, INT32_MAX);
+  w.adj_w = b->adj_w;
+  w.fadj = reinterpret_cast<int32_t*>(base + b->L.fadj);
 
   char* h = stage_base(c);
   MatDesc* hd = reinterpret_cast<MatDesc*>(h);
@@ -400,6 +422,7 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
     d.agg = (agg && agg[m]) ? agg[m] : nullptr;
     d.agg_rp = d.agg ? w.agg_rp + fine0 : nullptr;
     d.agg_list = d.agg ? w.agg_list : nullptr;
+    d.fadj = (b->adj_w && use_adj[m]) ? w.fadj + fine0 * b->adj_w : nullptr;
     hd[m] = d;
     chunk0 += d.nchunks;
     fine0 += A[m].n;
@@ -562,9 +585,17 @@ int enqueue_symbolic(clair_ctx* c, Batch& b, hipStream_t s, bool validate, bool 
     if (capture_check(c->capturing, s, "k_colmax", __LINE__)) return CLAIR_ERR_HIP;
     timing_mark(c, timing, s, "colmax");
   }
+  if (b.adj_w) {
+    HIPCHK(launch_adj(b.w, s));
+    if (capture_check(c->capturing, s, "k_adj", __LINE__)) return CLAIR_ERR_HIP;
+    timing_mark(c, timing, s, "adj");
+  }
   HIPCHK(launch_count(b.w, s));
   if (capture_check(c->capturing, s, "k_count", __LINE__)) return CLAIR_ERR_HIP;
   timing_mark(c, timing, s, "count");
+  HIPCHK(launch_count_mid(b.w, s));
+  if (capture_check(c->capturing, s, "k_count_mid", __LINE__)) return CLAIR_ERR_HIP;
+  timing_mark(c, timing, s, "count_mid");
   HIPCHK(launch_count_big(b.w, std::max(8, c->cus * 2), s));
   if (capture_check(c->capturing, s, "k_count_big", __LINE__)) return CLAIR_ERR_HIP;
   timing_mark(c, timing, s, "count_big");
@@ -1569,6 +1600,12 @@ int clair_ctx_set_graph(clair_ctx_t* c, int32_t nmat, const clair_csr_t* S) {
 int clair_ctx_set_strength(clair_ctx_t* c, double theta) {
   if (!c || !(theta >= 0.0 && theta <= 1.0)) return CLAIR_ERR_INVALID;
   c->theta = theta;
+  return CLAIR_OK;
+}
+
+int clair_ctx_set_search_adjacency(clair_ctx_t* c, int32_t mode) {
+  if (!c || !(mode == -1 || mode == 0 || mode == 4 || mode == 8)) return CLAIR_ERR_INVALID;
+  c->adj_mode = mode;
   return CLAIR_OK;
 }
 

@@ -57,6 +57,9 @@ struct MatDesc {
   const int32_t* gci;
   const double* gva;
   int64_t link_base;   // first entry of this matrix in the projection's column lists (capacities summed)
+  // the compact adjacency of the search graph (null: the search reads the
+  // graph's rows): adj_w slots per point, matrix-local indices
+  const int32_t* fadj;
 };
 
 // Pointers into device (global) memory.  Pointers that kernels load from a
@@ -97,6 +100,7 @@ struct GDesc {
   gptr<const int32_t> gci;
   gptr<const double> gva;
   int64_t link_base;
+  gptr<const int32_t> fadj;
 };
 
 __device__ __forceinline__ GDesc gview(const MatDesc& m) {
@@ -126,6 +130,7 @@ __device__ __forceinline__ GDesc gview(const MatDesc& m) {
   g.gva = to_global(m.gva);
   g.agg_list = to_global(m.agg_list);
   g.link_base = m.link_base;
+  g.fadj = to_global(m.fadj);
   return g;
 }
 
@@ -200,7 +205,8 @@ struct Work {
   int32_t chunk;
   int32_t GA;             // lane-group size of the small solver (8, 16 or 32)
   int32_t capC;
-  int32_t pad0;
+  int32_t adj_w;          // slots per point of the compact adjacency (0: none built)
+  int32_t* fadj;          // [n_total * adj_w]
 };
 
 // status codes (mirror clair_status)
@@ -459,6 +465,163 @@ __device__ __forceinline__ int regm_bfs(RegSetM<SM>& S, int n, int i, int ell, g
       for (int j = 0; j < SM; ++j)
         if (j == j0) u = S.v[j];
       regm_expand(S, n, u, rp, ci, va, cf, theta, cmax);
+    }
+  }
+  return S.ovf ? -1 : S.s;
+}
+
+// ---------------------------------------------------------------------------
+// Compact adjacency of the search graph.  Expanding a point u adds the points
+// v of its row that pass the search's edge test (stored nonzero, v != u,
+// strong_edge, v an F-point).  A prepass writes that list once per point, in
+// W int32 slots (ascending, padded with -1; kAdjOverflow in slot 0 when u has
+// more than W), so that a search takes a whole level's frontier in one round
+// of loads instead of reading row bounds, entries and C/F markers point by
+// point.  Points that overflow are expanded from the graph's rows.
+// ---------------------------------------------------------------------------
+constexpr int kAdjOverflow = -2;
+typedef int adj_v4 __attribute__((ext_vector_type(4)));
+
+template <int W>
+__device__ __forceinline__ void adj_load(gptr<const int32_t> __restrict__ adj, int u, int* o) {
+  static_assert(W % 4 == 0, "adjacency rows are read as int4");
+  const gptr<const adj_v4> p = (gptr<const adj_v4>)(adj + (int64_t)u * W);
+#pragma unroll
+  for (int q = 0; q < W / 4; ++q) {
+    const adj_v4 t = p[q];
+    o[4 * q] = t.x;
+    o[4 * q + 1] = t.y;
+    o[4 * q + 2] = t.z;
+    o[4 * q + 3] = t.w;
+  }
+}
+
+// frontier points whose adjacency rows are loaded together (32 slots)
+template <int W>
+constexpr int adj_group() { return 32 / W; }
+
+// reg_bfs over the compact adjacency: the same set (and levels)
+template <int SM, int W>
+__device__ __forceinline__ int reg_bfs_adj(RegSet<SM>& S, int n, int i, int ell, gptr<const int32_t> __restrict__ adj,
+                                           gptr<const int32_t> __restrict__ rp, gptr<const int32_t> __restrict__ ci,
+                                           gptr<const double> __restrict__ va, gptr<const int8_t> __restrict__ cf,
+                                           double theta, gptr<const double> __restrict__ cmax) {
+  constexpr int FG = adj_group<W>() < SM ? adj_group<W>() : SM;
+  static_assert(SM % FG == 0, "frontier groups tile the set");
+  S.clear();
+  {
+    int a[W];
+    adj_load<W>(adj, i, a);
+    if (a[0] == kAdjOverflow) {
+      reg_expand(S, n, i, rp[i], rp[i + 1], 1, ci, va, cf, theta, cmax);
+    } else {
+#pragma unroll
+      for (int q = 0; q < W; ++q)
+        if (a[q] >= 0) S.insert(a[q], 1);
+    }
+  }
+  for (int L = 2; L <= ell && !S.ovf; ++L) {
+    // the level-(L-1) points, from a snapshot (inserts move entries)
+    int fv[SM];
+    bool fr[SM];
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < SM; ++j) {
+      fv[j] = S.v[j];
+      fr[j] = S.lev[j] == L - 1;
+      any |= fr[j];
+    }
+    if (!any) break;
+#pragma unroll
+    for (int g = 0; g < SM; g += FG) {
+      int a[FG][W];
+#pragma unroll
+      for (int jj = 0; jj < FG; ++jj) {
+        if (fr[g + jj]) {
+          adj_load<W>(adj, fv[g + jj], a[jj]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < W; ++q) a[jj][q] = -1;
+        }
+      }
+#pragma unroll
+      for (int jj = 0; jj < FG; ++jj) {
+        if (!fr[g + jj]) continue;
+        if (a[jj][0] == kAdjOverflow) {
+          const int u = fv[g + jj];
+          reg_expand(S, n, u, rp[u], rp[u + 1], L, ci, va, cf, theta, cmax);
+        } else {
+#pragma unroll
+          for (int q = 0; q < W; ++q)
+            if (a[jj][q] >= 0) S.insert(a[jj][q], L);
+        }
+      }
+      if (S.ovf) break;
+    }
+  }
+  return S.ovf ? -1 : S.s;
+}
+
+// regm_bfs over the compact adjacency: the same set
+template <int SM, int W>
+__device__ __forceinline__ int regm_bfs_adj(RegSetM<SM>& S, int n, int i, int ell, gptr<const int32_t> __restrict__ adj,
+                                            gptr<const int32_t> __restrict__ rp, gptr<const int32_t> __restrict__ ci,
+                                            gptr<const double> __restrict__ va, gptr<const int8_t> __restrict__ cf,
+                                            double theta, gptr<const double> __restrict__ cmax) {
+  constexpr int FG = adj_group<W>();
+  S.clear();
+  {
+    int a[W];
+    adj_load<W>(adj, i, a);
+    if (a[0] == kAdjOverflow) {
+      regm_expand(S, n, i, rp, ci, va, cf, theta, cmax);
+    } else {
+#pragma unroll
+      for (int q = 0; q < W; ++q)
+        if (a[q] >= 0) S.insert(a[q]);
+    }
+  }
+  for (int L = 2; L <= ell && !S.ovf; ++L) {
+    S.todo = S.cur;
+    S.cur = 0;
+    if (!S.todo) break;
+    while (S.todo && !S.ovf) {
+      // up to FG of the smallest points still to expand
+      int u[FG];
+#pragma unroll
+      for (int g = 0; g < FG; ++g) {
+        u[g] = -1;
+        if (S.todo) {
+          const int j0 = __builtin_ctzll(S.todo);
+          S.todo &= S.todo - 1;
+          int x = 0;
+#pragma unroll
+          for (int j = 0; j < SM; ++j)
+            if (j == j0) x = S.v[j];
+          u[g] = x;
+        }
+      }
+      int a[FG][W];
+#pragma unroll
+      for (int g = 0; g < FG; ++g) {
+        if (u[g] >= 0) {
+          adj_load<W>(adj, u[g], a[g]);
+        } else {
+#pragma unroll
+          for (int q = 0; q < W; ++q) a[g][q] = -1;
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < FG; ++g) {
+        if (u[g] < 0) continue;
+        if (a[g][0] == kAdjOverflow) {
+          regm_expand(S, n, u[g], rp, ci, va, cf, theta, cmax);
+        } else {
+#pragma unroll
+          for (int q = 0; q < W; ++q)
+            if (a[g][q] >= 0) S.insert(a[g][q]);
+        }
+      }
     }
   }
   return S.ovf ? -1 : S.s;

@@ -1,12 +1,18 @@
 // k_mixed.hip -- the batched, mixed-precision restriction setup.
 //
 // Stages (one launch each, over all matrices of a batch):
+//   k_adj        the compact adjacency of the search graph (ell >= 2, sparse
+//                graphs): for every point, the F-points one step reaches.
 //   k_count      symbolic pass per chunk of fine points: the C-points of the
-//                chunk, the neighbourhood N(i) of each (one thread per row,
-//                up to 8 points in registers, then up to 32 for the rows that
-//                overflowed) kept in a per-row slot, the chunk-local prefix of
-//                |N(i)|+1; clears the projection accumulators of the chunk.
-//                Rows of more than 32 points are queued, unsized.
+//                chunk; rows at ell = 1 (up to 8 entries) and at ell = 2 over
+//                a width-4 adjacency sized by one thread each from a sorted
+//                candidate list and written to their slot; a chunk with every
+//                row sized gets its chunk-local prefix of |N(i)|+1 here;
+//                clears the projection's column lists of the chunk.
+//   k_count_mid  the other rows of unfinished chunks: one thread per row, up
+//                to 32 points in registers (over the adjacency when built),
+//                then the chunk's prefix.  Rows of more than 32 points are
+//                queued, unsized.
 //   k_count_big  one workgroup per queued row: a workgroup-wide search sizes
 //                it (queued for the workgroup solver); the last row of a chunk
 //                to be sized redoes the chunk's prefix.
@@ -405,14 +411,221 @@ __device__ __forceinline__ int small_limit(int GA) { return GA <= 4 ? 8 : GA; }
 // stride of a row's slot in slotA
 __device__ __forceinline__ int slot_stride(int GA) { return GA <= 4 ? 8 : GA; }
 
+// The compact adjacency of the matrices whose descriptor carries one: the
+// workgroup of logical block b takes 256 points of chunk b / (chunk / 256),
+// one thread per point (the chunk's XCD is the one k_count gives it).
+template <int W>
+__global__ __launch_bounds__(256) void k_adj(Work w) {
+  const int per = w.chunk / 256;
+  const int b = xcd_logical_block();
+  const int c = b / per;
+  const int m = chunk_matrix(w.desc, w.nmat, c);
+  const GDesc d = gview(w.desc[m]);
+  if (!d.fadj) return;
+  const int u = (c - d.chunk0) * w.chunk + (b - c * per) * 256 + (int)threadIdx.x;
+  if (u >= d.n) return;
+  int o[W];
+#pragma unroll
+  for (int q = 0; q < W; ++q) o[q] = -1;
+  int cnt = 0;
+  const int e1 = d.grp[u + 1];
+  for (int e = d.grp[u]; e < e1 && cnt <= W; e += 8) {
+    int k[8];
+    double x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      k[j] = u;
+      x[j] = 0.0;
+      if (e + j < e1) { k[j] = d.gci[e + j]; x[j] = d.gva[e + j]; }
+    }
+    int8_t c8[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) c8[j] = ((unsigned)k[j] < (unsigned)d.n) ? d.cf[k[j]] : (int8_t)1;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (k[j] != u && x[j] != 0.0 && c8[j] == 0 && strong_edge(x[j], k[j], d.theta, d.cmax)) {
+#pragma unroll
+        for (int q = 0; q < W; ++q)
+          if (q == cnt) o[q] = k[j];
+        ++cnt;
+      }
+    }
+  }
+  if (cnt > W) o[0] = kAdjOverflow;
+  gptr<adj_v4> dst = (gptr<adj_v4>)(to_global(w.fadj) + (d.fine0 + u) * W);
+#pragma unroll
+  for (int q = 0; q < W / 4; ++q) {
+    adj_v4 t;
+    t.x = o[4 * q];
+    t.y = o[4 * q + 1];
+    t.z = o[4 * q + 2];
+    t.w = o[4 * q + 3];
+    dst[q] = t;
+  }
+}
+
+// Sorting network over P (a power of two) registers, ascending; compile-time
+// indices only.
+template <int P>
+__device__ __forceinline__ void bitonic_sort(int (&v)[P]) {
+#pragma unroll
+  for (int k = 2; k <= P; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+      for (int q = 0; q < P; ++q) {
+        const int l = q ^ j;
+        if (l > q) {
+          const int a = v[q], b = v[l];
+          const bool up = (q & k) == 0;
+          v[q] = up ? min(a, b) : max(a, b);
+          v[l] = up ? max(a, b) : min(a, b);
+        }
+      }
+    }
+  }
+}
+
+// The distinct values of v (sorted, INT32_MAX = none) into the row's slot:
+// bin A's (stride SA) when there are at most lim of them, else bin B's.
+// Returns their number (at most P <= 32).
+template <int P>
+__device__ __forceinline__ int emit_distinct(const int (&v)[P], const Work& w, int64_t row, int SA, int lim) {
+  static_assert(P <= 32, "bin B slots hold 32 points");
+  int sz = 0;
+#pragma unroll
+  for (int q = 0; q < P; ++q) sz += (v[q] != 0x7fffffff && (q == 0 || v[q] != v[q - 1])) ? 1 : 0;
+  gptr<int32_t> dst = sz <= lim ? to_global(w.slotA) + row * SA : to_global(w.slotB) + row * 32;
+  int pos = 0;
+#pragma unroll
+  for (int q = 0; q < P; ++q) {
+    const bool u = v[q] != 0x7fffffff && (q == 0 || v[q] != v[q - 1]);
+    if (u) dst[pos] = v[q];
+    pos += u ? 1 : 0;
+  }
+  return sz;
+}
+
+// N(i) at ell = 2 from the compact adjacency of width 4: the four slots of
+// i and the four of each of them, sorted, duplicates dropped.  -1 when a
+// point overflows its slots (the row is left to k_count_mid).
+__device__ __forceinline__ int count_adj4_ell2(const Work& w, const GDesc& d, int i, int64_t row, int SA, int lim) {
+  int a[4];
+  adj_load<4>(d.fadj, i, a);
+  if (a[0] == kAdjOverflow) return -1;
+  int b[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (a[q] >= 0) {
+      adj_load<4>(d.fadj, a[q], b[q]);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) b[q][r] = -1;
+    }
+  }
+  int v[32];
+  bool ovf = false;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    ovf |= b[q][0] == kAdjOverflow;
+    v[q] = a[q] >= 0 ? a[q] : 0x7fffffff;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) v[4 + 4 * q + r] = b[q][r] >= 0 ? b[q][r] : 0x7fffffff;
+  }
+  if (ovf) return -1;
+#pragma unroll
+  for (int q = 20; q < 32; ++q) v[q] = 0x7fffffff;
+  bitonic_sort<32>(v);
+  return emit_distinct<32>(v, w, row, SA, lim);
+}
+
+// N(i) at ell = 1 from row i of the search graph (at most 8 stored entries;
+// -1 otherwise, the row is left to k_count_mid)
+__device__ __forceinline__ int count_row_ell1(const Work& w, const GDesc& d, int i, int64_t row, int SA, int lim) {
+  const int e0 = d.grp[i], e1 = d.grp[i + 1];
+  if (e1 - e0 > 8) return -1;
+  int k[8];
+  double x[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    k[j] = i;
+    x[j] = 0.0;
+    if (e0 + j < e1) { k[j] = d.gci[e0 + j]; x[j] = d.gva[e0 + j]; }
+  }
+  int v[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int8_t c8 = ((unsigned)k[j] < (unsigned)d.n) ? d.cf[k[j]] : (int8_t)1;
+    v[j] = (k[j] != i && x[j] != 0.0 && c8 == 0 && strong_edge(x[j], k[j], d.theta, d.cmax)) ? k[j] : 0x7fffffff;
+  }
+  bitonic_sort<8>(v);
+  return emit_distinct<8>(v, w, row, SA, lim);
+}
+
+// The chunk's bookkeeping once every row is sized (s_size; the rows left to
+// k_count_big have size 0, a negative s_rows entry and their index in
+// s_unres[0..nunres)): bin counts, the queue of k_count_big, the chunk-local
+// exclusive prefix of |N(i)|+1, the chunk totals.
+__device__ __forceinline__ void finish_chunk(const Work& w, int c, int m, MatStatus* st, int64_t base, int nc,
+                                             const int* s_rows, const int16_t* s_size, const int16_t* s_unres,
+                                             int nunres, int* s_scan, int* s_flag, int* s_qbase) {
+  const int tid = threadIdx.x;
+  const int lim = small_limit(w.GA);
+  if (nunres) {
+    if (tid == 0) *s_qbase = atomicAdd(&w.cnt->nbig, nunres);
+    __syncthreads();
+    for (int k = tid; k < nunres; k += kNT) {
+      const int q = *s_qbase + k;
+      if (q < w.capC) w.bigq[q] = c * w.chunk + s_unres[k];
+      else flag_row(st, ST_UNSUPPORTED, -s_rows[s_unres[k]] - 1);
+    }
+  }
+  const int per2 = (nc + kNT - 1) / kNT;
+  const int t0 = tid * per2;
+  int mysum = 0, mymax = 0, inA = 0, inB = 0;
+  for (int t = t0; t < min(t0 + per2, nc); ++t) {
+    const int sz = s_size[t];
+    mysum += sz + 1;
+    mymax = max(mymax, sz);
+    if (s_rows[t] >= 0) {
+      inA += sz <= lim ? 1 : 0;
+      inB += sz > lim ? 1 : 0;
+    }
+  }
+  int tot;
+  int pre = block_exclusive_scan(mysum, s_scan, &tot);
+  for (int t = t0; t < min(t0 + per2, nc); ++t) { w.lnz[base + t] = pre; pre += s_size[t] + 1; }
+  if (mymax) atomicMax(&s_flag[0], mymax);
+  if (inA) atomicAdd(&s_flag[2], inA);
+  if (inB) atomicAdd(&s_flag[3], inB);
+  __syncthreads();
+  if (tid == 0) {
+    w.chunk_nc[c] = nc;
+    w.chunk_nnz[c] = tot;
+    w.chunk_mat[c] = m;
+    // bin sizes per chunk (summed by k_scan); the largest block only when it
+    // grows, so that few workgroups meet at one address
+    w.chunk_bins[c] = make_int2(s_flag[2], s_flag[3]);
+    if (s_flag[0] > __hip_atomic_load(&st->max_block, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(&st->max_block, s_flag[0]);
+    w.chunk_unsized[c] = nunres;
+  }
+}
+
+// Symbolic pass, first part: one workgroup per chunk of fine points.  The
+// chunk's C-points are compacted; rows at ell = 1 with at most 8 stored
+// entries, and rows at ell = 2 of matrices with a width-4 compact adjacency,
+// are sized by one thread each from a sorted candidate list (no search
+// state); a chunk whose rows are all sized is finished here.  Other rows
+// (larger stencils, ell >= 3, aggregates, overflowing points) are marked -1
+// in lnz and left, with the chunk's bookkeeping, to k_count_mid.
+template <int W>
 __global__ __launch_bounds__(kNT) void k_count(Work w) {
   __shared__ int s_rows[kMaxChunk];
   __shared__ int16_t s_size[kMaxChunk];
   __shared__ int s_scan[kNT];
-  __shared__ int s_flag[4];  // max |N|, unresolved rows, rows in bin A, rows in bin B
-  __shared__ int16_t s_list[kMaxChunk];   // rows with more than 8 points
-  __shared__ int16_t s_unres[kMaxChunk];  // rows with more than 32 points
-  __shared__ int s_nlist, s_qbase;
+  __shared__ int s_flag[4];  // max |N|, -, rows in bin A, rows in bin B
+  __shared__ int s_ndef, s_qbase;
 
   const int c = xcd_logical_block();
   const int tid = threadIdx.x;
@@ -443,105 +656,105 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
   for (int j = j0; j < min(j0 + per, f1); ++j) {
     if (d.cf[j] != 0) { s_rows[rank] = j; w.clocal[base + rank] = j; ++rank; }
   }
-  if (tid == 0) { s_flag[0] = 0; s_flag[1] = 0; s_flag[2] = 0; s_flag[3] = 0; s_nlist = 0; }
+  if (tid == 0) { s_flag[0] = 0; s_flag[1] = 0; s_flag[2] = 0; s_flag[3] = 0; s_ndef = 0; }
   __syncthreads();
 
   const int SA = slot_stride(w.GA);
-  int inA = 0, inB = 0;
-
-  // one thread per C-row, neighbourhoods of up to 8 points in registers; the
-  // larger ones are left unsized for k_count_big
+  const int lim = small_limit(w.GA);
+  int ndef = 0;
   for (int t = tid; t < nc; t += kNT) {
-    // a row of seven or more entries (six or more neighbours) at ell >= 2
-    // nearly always reaches more than 8 points: it goes straight to the
-    // 32-point search below (either search gives the same set)
-    if (!d.agg_rp && d.ell >= 2 && d.grp[s_rows[t] + 1] - d.grp[s_rows[t]] >= 7) {
-      s_size[t] = -1;
-      s_list[atomicAdd(&s_nlist, 1)] = t;
-      continue;
-    }
-    RegSet<8> S;
-    const int sz = reg_bfs(S, d.n, s_rows[t], d.ell, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax, d.agg_rp,
-                           d.agg_list);
-    if (sz >= 0) {
-      s_size[t] = sz;
-      ++inA;  // sz <= 8 <= lim
-      if (SA) {
-#pragma unroll
-        for (int p = 0; p < 8; ++p)
-          if (p < sz) w.slotA[(base + t) * SA + p] = S.v[p];
+    int sz = -1;
+    if (!d.agg_rp) {
+      if constexpr (W == 4) {
+        if (d.fadj && d.ell == 2) sz = count_adj4_ell2(w, d, s_rows[t], base + t, SA, lim);
       }
-    } else {
-      s_size[t] = -1;
-      s_list[atomicAdd(&s_nlist, 1)] = t;
+      if (d.ell == 1) sz = count_row_ell1(w, d, s_rows[t], base + t, SA, lim);
     }
+    s_size[t] = (int16_t)sz;
+    ndef += sz < 0 ? 1 : 0;
   }
+  if (ndef) atomicAdd(&s_ndef, ndef);
   __syncthreads();
-  // rows with more than 8 points: one thread per row, up to 32 points in
-  // registers (slot of bin A or B); larger rows are left unsized for k_count_big
-  {
-    const int lim = small_limit(w.GA);
-    const int nl2 = s_nlist;
-    for (int k = tid; k < nl2; k += kNT) {
-      const int t = s_list[k];
-      RegSetM<32> S;
-      const int sz = regm_bfs(S, d.n, s_rows[t], d.ell, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax, d.agg_rp,
-                              d.agg_list);
-      if (sz < 0) {
-        s_size[t] = 0;
-        w.clocal[base + t] = -(s_rows[t] + 1);
-        s_unres[atomicAdd(&s_flag[1], 1)] = t;
-      } else if (sz <= lim) {
-        s_size[t] = sz;
-        ++inA;
-#pragma unroll
-        for (int p = 0; p < 32; ++p)
-          if (p < sz) w.slotA[(base + t) * SA + p] = S.v[p];
-      } else {
-        s_size[t] = sz;
-        ++inB;
-#pragma unroll
-        for (int p = 0; p < 32; ++p)
-          if (p < sz) w.slotB[(base + t) * 32 + p] = S.v[p];
-      }
-    }
+  if (s_ndef == 0) {
+    finish_chunk(w, c, m, st, base, nc, s_rows, s_size, nullptr, 0, s_scan, s_flag, &s_qbase);
+    return;
   }
-  if (inA) atomicAdd(&s_flag[2], inA);
-  if (inB) atomicAdd(&s_flag[3], inB);
-  __syncthreads();
-  // rows of more than 32 points: one queue entry each for k_count_big
-  const int nunres = s_flag[1];
-  if (nunres) {
-    if (tid == 0) s_qbase = atomicAdd(&w.cnt->nbig, nunres);
-    __syncthreads();
-    for (int k = tid; k < nunres; k += kNT) {
-      const int q = s_qbase + k;
-      if (q < w.capC) w.bigq[q] = c * w.chunk + s_unres[k];
-      else flag_row(st, ST_UNSUPPORTED, s_rows[s_unres[k]]);
-    }
-  }
-
-  // chunk-local exclusive prefix of (s+1)
-  const int per2 = (nc + kNT - 1) / kNT;
-  const int t0 = tid * per2;
-  int mysum = 0, mymax = 0;
-  for (int t = t0; t < min(t0 + per2, nc); ++t) { mysum += s_size[t] + 1; mymax = max(mymax, s_size[t]); }
-  int tot;
-  int pre = block_exclusive_scan(mysum, s_scan, &tot);
-  for (int t = t0; t < min(t0 + per2, nc); ++t) { w.lnz[base + t] = pre; pre += s_size[t] + 1; }
-  atomicMax(&s_flag[0], mymax);
-  __syncthreads();
+  // left to k_count_mid: the sizes so far (-1 = not sized)
+  for (int t = tid; t < nc; t += kNT) w.lnz[base + t] = s_size[t];
   if (tid == 0) {
     w.chunk_nc[c] = nc;
-    w.chunk_nnz[c] = tot;
     w.chunk_mat[c] = m;
-    // bin sizes per chunk (summed by k_scan); the largest block only when it
-    // grows, so that few workgroups meet at one address
-    w.chunk_bins[c] = make_int2(s_flag[2], s_flag[3]);
-    if (s_flag[0] > __hip_atomic_load(&st->max_block, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-      atomicMax(&st->max_block, s_flag[0]);
-    w.chunk_unsized[c] = nunres;
+    w.chunk_nnz[c] = -1;
   }
+}
+
+// Symbolic pass, second part: the chunks k_count left unfinished (one
+// workgroup per chunk; the others return at once).  One thread per row not
+// yet sized searches up to 32 points in registers (over the compact
+// adjacency when the matrix has one); larger rows are left unsized for
+// k_count_big.  Then the chunk's bookkeeping.
+template <int W>
+__global__ __launch_bounds__(kNT) void k_count_mid(Work w) {
+  __shared__ int s_rows[kMaxChunk];
+  __shared__ int16_t s_size[kMaxChunk];
+  __shared__ int s_scan[kNT];
+  __shared__ int s_flag[4];  // max |N|, rows left unsized, rows in bin A, rows in bin B
+  __shared__ int16_t s_list[kMaxChunk];   // rows to size here
+  __shared__ int16_t s_unres[kMaxChunk];  // rows with more than 32 points
+  __shared__ int s_nlist, s_qbase;
+
+  const int c = xcd_logical_block();
+  if (w.chunk_nnz[c] >= 0) return;  // finished by k_count
+  const int tid = threadIdx.x;
+  const int m = w.chunk_mat[c];
+  const GDesc d = gview(w.desc[m]);
+  MatStatus* st = &w.st[m];
+  const int64_t base = d.fine0 + (int64_t)(c - d.chunk0) * w.chunk;
+  const int nc = w.chunk_nc[c];
+  if (tid == 0) { s_flag[0] = 0; s_flag[1] = 0; s_flag[2] = 0; s_flag[3] = 0; s_nlist = 0; }
+  __syncthreads();
+  for (int t = tid; t < nc; t += kNT) {
+    s_rows[t] = w.clocal[base + t];
+    const int sz = w.lnz[base + t];
+    s_size[t] = (int16_t)sz;
+    if (sz < 0) s_list[atomicAdd(&s_nlist, 1)] = (int16_t)t;
+  }
+  __syncthreads();
+  const int SA = slot_stride(w.GA);
+  const int lim = small_limit(w.GA);
+  const int nl = s_nlist;
+  for (int k = tid; k < nl; k += kNT) {
+    const int t = s_list[k];
+    const int i = s_rows[t];
+    RegSetM<32> S;
+    int sz;
+    if constexpr (W > 0) {
+      if (d.fadj)
+        sz = regm_bfs_adj<32, W>(S, d.n, i, d.ell, d.fadj, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax);
+      else
+        sz = regm_bfs(S, d.n, i, d.ell, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax, d.agg_rp, d.agg_list);
+    } else {
+      sz = regm_bfs(S, d.n, i, d.ell, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax, d.agg_rp, d.agg_list);
+    }
+    if (sz < 0) {
+      s_size[t] = 0;
+      s_rows[t] = -(i + 1);
+      w.clocal[base + t] = -(i + 1);
+      s_unres[atomicAdd(&s_flag[1], 1)] = (int16_t)t;
+    } else if (sz <= lim) {
+      s_size[t] = (int16_t)sz;
+#pragma unroll
+      for (int p = 0; p < 32; ++p)
+        if (p < sz) w.slotA[(base + t) * SA + p] = S.v[p];
+    } else {
+      s_size[t] = (int16_t)sz;
+#pragma unroll
+      for (int p = 0; p < 32; ++p)
+        if (p < sz) w.slotB[(base + t) * 32 + p] = S.v[p];
+    }
+  }
+  __syncthreads();
+  finish_chunk(w, c, m, st, base, nc, s_rows, s_size, s_unres, s_flag[1], s_scan, s_flag, &s_qbase);
 }
 
 // Rows with more than 32 points, one workgroup per row (grid-stride over the
@@ -2672,9 +2885,32 @@ hipError_t launch_validate(const Work& w, int blocks, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t launch_adj(const Work& w, hipStream_t s) {
+  if (w.nchunks == 0 || w.adj_w == 0) return hipSuccess;
+  if (w.chunk % 256) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)w.nchunks * (unsigned)(w.chunk / 256));
+  if (w.adj_w == 4) hipLaunchKernelGGL(k_adj<4>, grid, dim3(256), 0, s, w);
+  else if (w.adj_w == 8) hipLaunchKernelGGL(k_adj<8>, grid, dim3(256), 0, s, w);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 hipError_t launch_count(const Work& w, hipStream_t s) {
   if (w.nchunks == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_count, dim3(w.nchunks), dim3(kNT), 0, s, w);
+  const dim3 grid(w.nchunks), block(kNT);
+  if (w.adj_w == 4) hipLaunchKernelGGL(k_count<4>, grid, block, 0, s, w);
+  else if (w.adj_w == 0 || w.adj_w == 8) hipLaunchKernelGGL(k_count<0>, grid, block, 0, s, w);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_count_mid(const Work& w, hipStream_t s) {
+  if (w.nchunks == 0) return hipSuccess;
+  const dim3 grid(w.nchunks), block(kNT);
+  if (w.adj_w == 0) hipLaunchKernelGGL(k_count_mid<0>, grid, block, 0, s, w);
+  else if (w.adj_w == 4) hipLaunchKernelGGL(k_count_mid<4>, grid, block, 0, s, w);
+  else if (w.adj_w == 8) hipLaunchKernelGGL(k_count_mid<8>, grid, block, 0, s, w);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -250,3 +250,31 @@ def test_binB_lane_layouts(lanes):
         res, infos = _check([p], precision=0, ctx=ctx)
         if want is not None:
             assert infos[0]["max_block"] == want
+
+
+@pytest.mark.parametrize("mode", [-1, 0, 4, 8])
+def test_search_adjacency_modes(mode):
+    # the symbolic pass with the compact adjacency at its automatic width,
+    # without it, and at widths 4 and 8 forced (width 4 on the nine-point and
+    # random graphs sends many points down the row path): the same pattern and
+    # the same values in every mode
+    from paper_2307_00229_amd import clair
+
+    ps = [P.small_2d(97, stencil=9, eps=1e-3, angle=0.4, k=3, ell=2),
+          P.small_3d(21, eps=0.01, b=(0.3, -0.6, 0.7), ell=2),
+          P.small_2d(130, stencil=5, eps=0.5, angle=2.0, ell=2),
+          P.random_sparse(300, 0.012, 91, ell=3),
+          P.small_2d(61, stencil=5, eps=1e-5, angle=4.0, ell=1)]
+    ref_ctx = clair.Context()
+    ref_ctx.set_search_adjacency(0)
+    ref, _, st = gpu_build(ps, precision=0, ctx=ref_ctx)
+    assert st == 0
+    ctx = clair.Context()
+    ctx.set_search_adjacency(mode)
+    res, _ = _check(ps, precision=0, ctx=ctx)
+    for a, b in zip(res, ref):
+        assert np.array_equal(a["row_ptr"], b["row_ptr"])
+        assert np.array_equal(a["col_idx"], b["col_idx"])
+        assert np.array_equal(a["val"], b["val"])
+    with pytest.raises(clair.ClairError):
+        ctx.set_search_adjacency(3)
