@@ -261,213 +261,26 @@ __device__ __forceinline__ int find_sorted(const int* a, int len, int key) {
   return (p < len && a[p] == key) ? p : -1;
 }
 
-// Register-resident neighbourhood search of one thread, for neighbourhoods of
-// at most SM points.  N(i) = the F-points reachable from C-point i by a walk
-// of at most ell edges (u -> v with u != v, a stored nonzero a_uv and
-// strong_edge) whose
-// interior vertices are F-points; kept sorted in v[0..s) (empty slots hold
-// INT32_MAX).  Returns s, or -1 when more than SM points are found.
-template <int SM>
-struct RegSet {
-  int v[SM];    // sorted points
-  int lev[SM];  // the level (hop count) at which each point was found
-  int s;
-  bool ovf;
-
-  __device__ __forceinline__ void clear() {
+// Sorting network over P (a power of two) registers, ascending; compile-time
+// indices only.
+template <int P>
+__device__ __forceinline__ void bitonic_sort(int (&v)[P]) {
 #pragma unroll
-    for (int j = 0; j < SM; ++j) { v[j] = 0x7fffffff; lev[j] = 0; }
-    s = 0;
-    ovf = false;
-  }
-  __device__ __forceinline__ void insert(int k, int L) {
-    bool present = false;
-    int pos = 0;
+  for (int k = 2; k <= P; k <<= 1) {
 #pragma unroll
-    for (int j = 0; j < SM; ++j) {
-      present |= (v[j] == k);
-      pos += (v[j] < k) ? 1 : 0;
-    }
-    if (present) return;
-    if (s == SM) { ovf = true; return; }
+    for (int j = k >> 1; j > 0; j >>= 1) {
 #pragma unroll
-    for (int j = SM - 1; j > 0; --j) {
-      if (j > pos) { v[j] = v[j - 1]; lev[j] = lev[j - 1]; }
-    }
-#pragma unroll
-    for (int j = 0; j < SM; ++j) {
-      if (j == pos) { v[j] = k; lev[j] = L; }
-    }
-    ++s;
-  }
-};
-
-// the F-neighbours of u (edges with a stored nonzero; row u of A is entries
-// [e0, e1)), added at level L; entries are read eight at a time (one batch
-// for most stencil rows)
-template <int SM>
-__device__ __forceinline__ void reg_expand(RegSet<SM>& S, int n, int u, int e0, int e1, int L,
-                                           gptr<const int32_t> __restrict__ ci, gptr<const double> __restrict__ va,
-                                           gptr<const int8_t> __restrict__ cf, double theta,
-                                           gptr<const double> __restrict__ cmax) {
-  for (int e = e0; e < e1 && !S.ovf; e += 8) {
-    int k[8];
-    double v[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      k[j] = u;
-      v[j] = 0.0;
-      if (e + j < e1) { k[j] = ci[e + j]; v[j] = va[e + j]; }
-    }
-    int8_t c8[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) c8[j] = ((unsigned)k[j] < (unsigned)n) ? cf[k[j]] : (int8_t)1;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      if (k[j] != u && v[j] != 0.0 && c8[j] == 0 && strong_edge(v[j], k[j], theta, cmax)) S.insert(k[j], L);
+      for (int q = 0; q < P; ++q) {
+        const int l = q ^ j;
+        if (l > q) {
+          const int a = v[q], b = v[l];
+          const bool up = (q & k) == 0;
+          v[q] = up ? min(a, b) : max(a, b);
+          v[l] = up ? max(a, b) : min(a, b);
+        }
+      }
     }
   }
-}
-
-template <int SM>
-__device__ __forceinline__ int reg_bfs(RegSet<SM>& S, int n, int i, int ell, gptr<const int32_t> __restrict__ rp,
-                                       gptr<const int32_t> __restrict__ ci, gptr<const double> __restrict__ va,
-                                       gptr<const int8_t> __restrict__ cf, double theta,
-                                       gptr<const double> __restrict__ cmax, gptr<const int32_t> __restrict__ mrp,
-                                       gptr<const int32_t> __restrict__ mem) {
-  S.clear();
-  if (mrp) {  // aggregation-based: the aggregate's F-points (sorted, in range)
-    for (int e = mrp[i]; e < mrp[i + 1] && !S.ovf; ++e) S.insert(mem[e], 1);
-  } else {
-    reg_expand(S, n, i, rp[i], rp[i + 1], 1, ci, va, cf, theta, cmax);
-  }
-  for (int L = 2; L <= ell && !S.ovf; ++L) {
-    // expand the points found at level L-1 in ascending order (from a
-    // snapshot: inserts move entries); only compile-time register indices.
-    // The row bounds of the whole level are loaded first, all in flight
-    // together, so each expansion waits for its entries only.
-    int fv[SM], fl[SM], b0[SM], b1[SM];
-#pragma unroll
-    for (int j = 0; j < SM; ++j) {
-      fv[j] = S.v[j];
-      fl[j] = S.lev[j];
-      b0[j] = 0;
-      b1[j] = 0;
-      if (fl[j] == L - 1) { b0[j] = rp[fv[j]]; b1[j] = rp[fv[j] + 1]; }
-    }
-    int last = -1;
-    bool any = false;
-    while (!S.ovf) {
-      int u = 0x7fffffff, e0 = 0, e1 = 0;
-#pragma unroll
-      for (int j = 0; j < SM; ++j)
-        if (fl[j] == L - 1 && fv[j] > last && fv[j] < u) { u = fv[j]; e0 = b0[j]; e1 = b1[j]; }
-      if (u == 0x7fffffff) break;
-      reg_expand(S, n, u, e0, e1, L, ci, va, cf, theta, cmax);
-      last = u;
-      any = true;
-    }
-    if (!any) break;
-  }
-  return S.ovf ? -1 : S.s;
-}
-
-// The same search for neighbourhoods of up to SM <= 32 points with less
-// register state: instead of a level per slot, bit masks over the slots mark
-// the points found at the current level and the previous level's points not
-// yet expanded; every sorted insert moves the mask bits with the entries.
-template <int SM>
-struct RegSetM {
-  int v[SM];      // sorted points, INT32_MAX beyond s
-  uint64_t cur;   // slots found at the current level
-  uint64_t todo;  // slots of the previous level still to expand
-  int s;
-  bool ovf;
-
-  __device__ __forceinline__ void clear() {
-#pragma unroll
-    for (int j = 0; j < SM; ++j) v[j] = 0x7fffffff;
-    cur = 0;
-    todo = 0;
-    s = 0;
-    ovf = false;
-  }
-  __device__ __forceinline__ void insert(int k) {
-    bool present = false;
-    int pos = 0;
-#pragma unroll
-    for (int j = 0; j < SM; ++j) {
-      present |= (v[j] == k);
-      pos += (v[j] < k) ? 1 : 0;
-    }
-    if (present) return;
-    if (s == SM) { ovf = true; return; }
-#pragma unroll
-    for (int j = SM - 1; j > 0; --j)
-      if (j > pos) v[j] = v[j - 1];
-#pragma unroll
-    for (int j = 0; j < SM; ++j)
-      if (j == pos) v[j] = k;
-    const uint64_t low = (1ull << pos) - 1;
-    todo = (todo & low) | ((todo & ~low) << 1);
-    cur = (cur & low) | ((cur & ~low) << 1) | (1ull << pos);
-    ++s;
-  }
-};
-
-// F-neighbours of u (stored nonzero, u excluded), eight entries per batch
-template <int SM>
-__device__ __forceinline__ void regm_expand(RegSetM<SM>& S, int n, int u, gptr<const int32_t> __restrict__ rp,
-                                            gptr<const int32_t> __restrict__ ci, gptr<const double> __restrict__ va,
-                                            gptr<const int8_t> __restrict__ cf, double theta,
-                                            gptr<const double> __restrict__ cmax) {
-  const int e1 = rp[u + 1];
-  for (int e = rp[u]; e < e1 && !S.ovf; e += 8) {
-    int k[8];
-    double x[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      k[j] = u;
-      x[j] = 0.0;
-      if (e + j < e1) { k[j] = ci[e + j]; x[j] = va[e + j]; }
-    }
-    int8_t c8[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) c8[j] = ((unsigned)k[j] < (unsigned)n) ? cf[k[j]] : (int8_t)1;
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-      if (k[j] != u && x[j] != 0.0 && c8[j] == 0 && strong_edge(x[j], k[j], theta, cmax)) S.insert(k[j]);
-  }
-}
-
-template <int SM>
-__device__ __forceinline__ int regm_bfs(RegSetM<SM>& S, int n, int i, int ell, gptr<const int32_t> __restrict__ rp,
-                                        gptr<const int32_t> __restrict__ ci, gptr<const double> __restrict__ va,
-                                        gptr<const int8_t> __restrict__ cf, double theta,
-                                        gptr<const double> __restrict__ cmax, gptr<const int32_t> __restrict__ mrp,
-                                        gptr<const int32_t> __restrict__ mem) {
-  S.clear();
-  if (mrp) {
-    for (int e = mrp[i]; e < mrp[i + 1] && !S.ovf; ++e) S.insert(mem[e]);
-  } else {
-    regm_expand(S, n, i, rp, ci, va, cf, theta, cmax);
-  }
-  for (int L = 2; L <= ell && !S.ovf; ++L) {
-    S.todo = S.cur;
-    S.cur = 0;
-    if (!S.todo) break;
-    while (S.todo && !S.ovf) {
-      // the lowest slot still to expand (the smallest such point)
-      const int j0 = __builtin_ctzll(S.todo);
-      S.todo &= S.todo - 1;
-      int u = 0;
-#pragma unroll
-      for (int j = 0; j < SM; ++j)
-        if (j == j0) u = S.v[j];
-      regm_expand(S, n, u, rp, ci, va, cf, theta, cmax);
-    }
-  }
-  return S.ovf ? -1 : S.s;
 }
 
 // ---------------------------------------------------------------------------
@@ -496,135 +309,138 @@ __device__ __forceinline__ void adj_load(gptr<const int32_t> __restrict__ adj, i
   }
 }
 
-// frontier points whose adjacency rows are loaded together (32 slots)
-template <int W>
-constexpr int adj_group() { return 32 / W; }
+// Register-resident neighbourhood search of one thread, for neighbourhoods of
+// at most SM <= 32 points.  N(i) = the F-points reachable from C-point i by a
+// walk of at most ell edges (u -> v with u != v, a stored nonzero a_uv and
+// strong_edge) whose interior vertices are F-points.  Points are appended in
+// the order found, so the points first reached at one distance form a run
+// [lo, hi) that the next level expands; an insert is a membership test and
+// one slot write, and the set is sorted once at the end.
+template <int SM>
+struct RegSetA {
+  static_assert(SM <= 32 && (SM & (SM - 1)) == 0, "a power of two up to 32");
+  int v[SM];  // points in the order found, INT32_MAX beyond s
+  int s;
+  bool ovf;
 
-// reg_bfs over the compact adjacency: the same set (and levels)
-template <int SM, int W>
-__device__ __forceinline__ int reg_bfs_adj(RegSet<SM>& S, int n, int i, int ell, gptr<const int32_t> __restrict__ adj,
-                                           gptr<const int32_t> __restrict__ rp, gptr<const int32_t> __restrict__ ci,
-                                           gptr<const double> __restrict__ va, gptr<const int8_t> __restrict__ cf,
-                                           double theta, gptr<const double> __restrict__ cmax) {
-  constexpr int FG = adj_group<W>() < SM ? adj_group<W>() : SM;
-  static_assert(SM % FG == 0, "frontier groups tile the set");
-  S.clear();
-  {
-    int a[W];
-    adj_load<W>(adj, i, a);
-    if (a[0] == kAdjOverflow) {
-      reg_expand(S, n, i, rp[i], rp[i + 1], 1, ci, va, cf, theta, cmax);
-    } else {
+  __device__ __forceinline__ void clear() {
 #pragma unroll
-      for (int q = 0; q < W; ++q)
-        if (a[q] >= 0) S.insert(a[q], 1);
-    }
+    for (int j = 0; j < SM; ++j) v[j] = 0x7fffffff;
+    s = 0;
+    ovf = false;
   }
-  for (int L = 2; L <= ell && !S.ovf; ++L) {
-    // the level-(L-1) points, from a snapshot (inserts move entries)
-    int fv[SM];
-    bool fr[SM];
-    bool any = false;
+  __device__ __forceinline__ void insert(int k) {
+    bool present = false;
 #pragma unroll
-    for (int j = 0; j < SM; ++j) {
-      fv[j] = S.v[j];
-      fr[j] = S.lev[j] == L - 1;
-      any |= fr[j];
-    }
-    if (!any) break;
+    for (int j = 0; j < SM; ++j) present |= (v[j] == k);
+    if (present) return;
+    if (s == SM) { ovf = true; return; }
 #pragma unroll
-    for (int g = 0; g < SM; g += FG) {
-      int a[FG][W];
-#pragma unroll
-      for (int jj = 0; jj < FG; ++jj) {
-        if (fr[g + jj]) {
-          adj_load<W>(adj, fv[g + jj], a[jj]);
-        } else {
-#pragma unroll
-          for (int q = 0; q < W; ++q) a[jj][q] = -1;
-        }
-      }
-#pragma unroll
-      for (int jj = 0; jj < FG; ++jj) {
-        if (!fr[g + jj]) continue;
-        if (a[jj][0] == kAdjOverflow) {
-          const int u = fv[g + jj];
-          reg_expand(S, n, u, rp[u], rp[u + 1], L, ci, va, cf, theta, cmax);
-        } else {
-#pragma unroll
-          for (int q = 0; q < W; ++q)
-            if (a[jj][q] >= 0) S.insert(a[jj][q], L);
-        }
-      }
-      if (S.ovf) break;
-    }
+    for (int j = 0; j < SM; ++j)
+      if (j == s) v[j] = k;
+    ++s;
   }
-  return S.ovf ? -1 : S.s;
+  __device__ __forceinline__ int get(int p) const {
+    int x = 0;
+#pragma unroll
+    for (int j = 0; j < SM; ++j)
+      if (j == p) x = v[j];
+    return x;
+  }
+};
+
+// the F-neighbours of u from row u of the graph, eight entries per batch
+template <int SM>
+__device__ __forceinline__ void rowa_expand(RegSetA<SM>& S, int n, int u, gptr<const int32_t> __restrict__ rp,
+                                            gptr<const int32_t> __restrict__ ci, gptr<const double> __restrict__ va,
+                                            gptr<const int8_t> __restrict__ cf, double theta,
+                                            gptr<const double> __restrict__ cmax) {
+  const int e1 = rp[u + 1];
+  for (int e = rp[u]; e < e1 && !S.ovf; e += 8) {
+    int k[8];
+    double x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      k[j] = u;
+      x[j] = 0.0;
+      if (e + j < e1) { k[j] = ci[e + j]; x[j] = va[e + j]; }
+    }
+    int8_t c8[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) c8[j] = ((unsigned)k[j] < (unsigned)n) ? cf[k[j]] : (int8_t)1;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (k[j] != u && x[j] != 0.0 && c8[j] == 0 && strong_edge(x[j], k[j], theta, cmax)) S.insert(k[j]);
+  }
 }
 
-// regm_bfs over the compact adjacency: the same set
+// The search.  W = 4 or 8: expansions read the compact adjacency adj (the
+// rows of points that overflow it are read instead), 32 / W frontier points
+// at a time; W = 0: every expansion reads the graph's rows.  mrp/mem (may be
+// null): the aggregate members that replace the first step.  Returns |N(i)|
+// with S.v[0..s) ascending, or -1 when more than SM points are found.
 template <int SM, int W>
-__device__ __forceinline__ int regm_bfs_adj(RegSetM<SM>& S, int n, int i, int ell, gptr<const int32_t> __restrict__ adj,
-                                            gptr<const int32_t> __restrict__ rp, gptr<const int32_t> __restrict__ ci,
-                                            gptr<const double> __restrict__ va, gptr<const int8_t> __restrict__ cf,
-                                            double theta, gptr<const double> __restrict__ cmax) {
-  constexpr int FG = adj_group<W>();
+__device__ __forceinline__ int rega_bfs(RegSetA<SM>& S, int n, int i, int ell, gptr<const int32_t> __restrict__ adj,
+                                        gptr<const int32_t> __restrict__ rp, gptr<const int32_t> __restrict__ ci,
+                                        gptr<const double> __restrict__ va, gptr<const int8_t> __restrict__ cf,
+                                        double theta, gptr<const double> __restrict__ cmax,
+                                        gptr<const int32_t> __restrict__ mrp, gptr<const int32_t> __restrict__ mem) {
   S.clear();
-  {
+  if (mrp) {
+    for (int e = mrp[i]; e < mrp[i + 1] && !S.ovf; ++e) S.insert(mem[e]);
+  } else if constexpr (W > 0) {
     int a[W];
     adj_load<W>(adj, i, a);
     if (a[0] == kAdjOverflow) {
-      regm_expand(S, n, i, rp, ci, va, cf, theta, cmax);
+      rowa_expand(S, n, i, rp, ci, va, cf, theta, cmax);
     } else {
 #pragma unroll
       for (int q = 0; q < W; ++q)
         if (a[q] >= 0) S.insert(a[q]);
     }
+  } else {
+    rowa_expand(S, n, i, rp, ci, va, cf, theta, cmax);
   }
+  int lo = 0;
   for (int L = 2; L <= ell && !S.ovf; ++L) {
-    S.todo = S.cur;
-    S.cur = 0;
-    if (!S.todo) break;
-    while (S.todo && !S.ovf) {
-      // up to FG of the smallest points still to expand
-      int u[FG];
+    const int hi = S.s;
+    if (lo == hi) break;
+    if constexpr (W > 0) {
+      constexpr int FG = 32 / W;
+      for (int p = lo; p < hi && !S.ovf; p += FG) {
+        int u[FG];
+        int a[FG][W];
 #pragma unroll
-      for (int g = 0; g < FG; ++g) {
-        u[g] = -1;
-        if (S.todo) {
-          const int j0 = __builtin_ctzll(S.todo);
-          S.todo &= S.todo - 1;
-          int x = 0;
+        for (int g = 0; g < FG; ++g) u[g] = (p + g < hi) ? S.get(p + g) : -1;
 #pragma unroll
-          for (int j = 0; j < SM; ++j)
-            if (j == j0) x = S.v[j];
-          u[g] = x;
+        for (int g = 0; g < FG; ++g) {
+          if (u[g] >= 0) {
+            adj_load<W>(adj, u[g], a[g]);
+          } else {
+#pragma unroll
+            for (int q = 0; q < W; ++q) a[g][q] = -1;
+          }
+        }
+#pragma unroll
+        for (int g = 0; g < FG; ++g) {
+          if (u[g] < 0) continue;
+          if (a[g][0] == kAdjOverflow) {
+            rowa_expand(S, n, u[g], rp, ci, va, cf, theta, cmax);
+          } else {
+#pragma unroll
+            for (int q = 0; q < W; ++q)
+              if (a[g][q] >= 0) S.insert(a[g][q]);
+          }
         }
       }
-      int a[FG][W];
-#pragma unroll
-      for (int g = 0; g < FG; ++g) {
-        if (u[g] >= 0) {
-          adj_load<W>(adj, u[g], a[g]);
-        } else {
-#pragma unroll
-          for (int q = 0; q < W; ++q) a[g][q] = -1;
-        }
-      }
-#pragma unroll
-      for (int g = 0; g < FG; ++g) {
-        if (u[g] < 0) continue;
-        if (a[g][0] == kAdjOverflow) {
-          regm_expand(S, n, u[g], rp, ci, va, cf, theta, cmax);
-        } else {
-#pragma unroll
-          for (int q = 0; q < W; ++q)
-            if (a[g][q] >= 0) S.insert(a[g][q]);
-        }
-      }
+    } else {
+      for (int p = lo; p < hi && !S.ovf; ++p) rowa_expand(S, n, S.get(p), rp, ci, va, cf, theta, cmax);
     }
+    lo = hi;
   }
-  return S.ovf ? -1 : S.s;
+  if (S.ovf) return -1;
+  bitonic_sort<SM>(S.v);
+  return S.s;
 }
 
 // matrix owning global chunk c (desc[].chunk0 ascending)

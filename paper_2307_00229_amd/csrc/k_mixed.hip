@@ -55,7 +55,7 @@ constexpr int kWN = kMaxBlock;
 constexpr int kWC = 4096;
 
 // Workgroup-wide neighbourhood search for rows of any size up to kWN points:
-// the same set as reg_bfs (F-points reachable from C-point i by at most ell
+// the same set as rega_bfs (F-points reachable from C-point i by at most ell
 // edges with F-points inside the walk).  The entries of a level's frontier
 // rows are taken in windows of kWC: each window is sorted (bitonic, in LDS),
 // reduced to points that are new (first of their run, not yet in N, not yet
@@ -464,28 +464,6 @@ __global__ __launch_bounds__(256) void k_adj(Work w) {
   }
 }
 
-// Sorting network over P (a power of two) registers, ascending; compile-time
-// indices only.
-template <int P>
-__device__ __forceinline__ void bitonic_sort(int (&v)[P]) {
-#pragma unroll
-  for (int k = 2; k <= P; k <<= 1) {
-#pragma unroll
-    for (int j = k >> 1; j > 0; j >>= 1) {
-#pragma unroll
-      for (int q = 0; q < P; ++q) {
-        const int l = q ^ j;
-        if (l > q) {
-          const int a = v[q], b = v[l];
-          const bool up = (q & k) == 0;
-          v[q] = up ? min(a, b) : max(a, b);
-          v[l] = up ? max(a, b) : min(a, b);
-        }
-      }
-    }
-  }
-}
-
 // The distinct values of v (sorted, INT32_MAX = none) into the row's slot:
 // bin A's (stride SA) when there are at most lim of them, else bin B's.
 // Returns their number (at most P <= 32).
@@ -726,15 +704,17 @@ __global__ __launch_bounds__(kNT) void k_count_mid(Work w) {
   for (int k = tid; k < nl; k += kNT) {
     const int t = s_list[k];
     const int i = s_rows[t];
-    RegSetM<32> S;
+    RegSetA<32> S;
     int sz;
     if constexpr (W > 0) {
       if (d.fadj)
-        sz = regm_bfs_adj<32, W>(S, d.n, i, d.ell, d.fadj, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax);
+        sz = rega_bfs<32, W>(S, d.n, i, d.ell, d.fadj, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax, nullptr, nullptr);
       else
-        sz = regm_bfs(S, d.n, i, d.ell, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax, d.agg_rp, d.agg_list);
+        sz = rega_bfs<32, 0>(S, d.n, i, d.ell, nullptr, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax, d.agg_rp,
+                             d.agg_list);
     } else {
-      sz = regm_bfs(S, d.n, i, d.ell, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax, d.agg_rp, d.agg_list);
+      sz = rega_bfs<32, 0>(S, d.n, i, d.ell, nullptr, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax, d.agg_rp,
+                           d.agg_list);
     }
     if (sz < 0) {
       s_size[t] = 0;
