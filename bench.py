@@ -98,7 +98,7 @@ def stage_kernel_name(stage, tuning):
     g = tuning["group"]
     small = {1: "k_rows8", 4: "k_quad8"}.get(g, f"k_numeric<{g},...> (bin A)")
     return {"adj": "k_adj", "count": "k_count", "count_mid": "k_count_mid", "count_big": "k_count_big", "scan": "k_scan", "numeric": small,
-            "numeric32": "k_numeric<16|32,128,SM> (bin B)", "rows_wg": "k_rows_wg", "project": "k_project",
+            "numeric32": "k_numeric<16|32,128,SM> (bin B)", "rows_wg": "k_rows_wg", "project": "k_colproj",
             "upload": "descriptor upload"}.get(stage, stage)
 
 
