@@ -624,15 +624,23 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
     for (int j = f0 + tid; j < f1; j += kNT) w.chead[d.fine0 + j] = -1;
   }
 
-  // compaction of the chunk's C-points, ascending
+  // compaction of the chunk's C-points, ascending: each thread's run of up
+  // to 8 markers is read once, all loads in flight together
+  static_assert(kMaxChunk <= 8 * kNT, "a thread's run of markers fits one byte mask");
   const int per = (w.chunk + kNT - 1) / kNT;
   const int j0 = f0 + tid * per;
-  int myc = 0;
-  for (int j = j0; j < min(j0 + per, f1); ++j) myc += d.cf[j] != 0;
+  const int j1 = min(j0 + per, f1);
+  uint32_t cbits = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (j0 + k < j1 && d.cf[j0 + k] != 0) cbits |= 1u << k;
   int nc;
-  int rank = block_exclusive_scan(myc, s_scan, &nc);
-  for (int j = j0; j < min(j0 + per, f1); ++j) {
-    if (d.cf[j] != 0) { s_rows[rank] = j; w.clocal[base + rank] = j; ++rank; }
+  int rank = block_exclusive_scan(__popc(cbits), s_scan, &nc);
+  for (uint32_t b = cbits; b; b &= b - 1) {
+    const int j = j0 + __ffs(b) - 1;
+    s_rows[rank] = j;
+    w.clocal[base + rank] = j;
+    ++rank;
   }
   if (tid == 0) { s_flag[0] = 0; s_flag[1] = 0; s_flag[2] = 0; s_flag[3] = 0; s_ndef = 0; }
   __syncthreads();
@@ -810,57 +818,92 @@ __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
 // writes R.row_ptr[n_c].  Per-matrix R offsets are the global ones minus the
 // matrix's base.
 __global__ __launch_bounds__(1024) void k_scan(Work w) {
-  __shared__ long long s_wr[16], s_wz[16];
-  __shared__ int s_wa[16], s_wb[16];
+  __shared__ long long s_wr[17], s_wz[17];
+  __shared__ int s_wa[17], s_wb[17];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wid = tid >> 6;
   const int nch = w.nchunks;
-  const int per = (nch + 1023) / 1024;
-  const int c0 = min(nch, tid * per), c1 = min(nch, c0 + per);
-  long long sr = 0, sz = 0;
-  int ba = 0, bb = 0;
-  for (int c = c0; c < c1; ++c) {
-    sr += w.chunk_nc[c];
-    sz += w.chunk_nnz[c];
-    const int2 bn = w.chunk_bins[c];
-    ba += bn.x;
-    bb += bn.y;
-  }
-  // inclusive scans inside each wavefront, then across the 16 wavefronts
-  long long xr = sr, xz = sz;
-  int xa = ba, xb = bb;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const long long yr = __shfl_up(xr, o, 64);
-    const long long yz = __shfl_up(xz, o, 64);
-    const int ya = __shfl_up(xa, o, 64);
-    const int yb = __shfl_up(xb, o, 64);
-    if (lane >= o) { xr += yr; xz += yz; xa += ya; xb += yb; }
-  }
-  if (lane == 63) { s_wr[wid] = xr; s_wz[wid] = xz; s_wa[wid] = xa; s_wb[wid] = xb; }
-  __syncthreads();
-  long long br = 0, bz = 0, rows_total = 0, nnz_total = 0;
+  // tiles of 4096 consecutive chunks, four per thread (their loads in flight
+  // together), scanned in order with the running totals carried over
+  constexpr int CPT = 4;
+  long long carry_r = 0, carry_z = 0;
   int na = 0, nb = 0;
-  for (int k = 0; k < 16; ++k) {
-    const long long r = s_wr[k], z = s_wz[k];
-    if (k < wid) { br += r; bz += z; }
-    rows_total += r;
-    nnz_total += z;
-    na += s_wa[k];
-    nb += s_wb[k];
+  for (int t0 = 0; t0 < nch; t0 += 1024 * CPT) {
+    const int cb = t0 + tid * CPT;
+    int ncs[CPT];
+    long long nzs[CPT];
+    int nc = 0, a = 0, bbin = 0;
+    long long nz = 0;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      ncs[k] = 0;
+      nzs[k] = 0;
+      if (cb + k < nch) {
+        ncs[k] = w.chunk_nc[cb + k];
+        nzs[k] = w.chunk_nnz[cb + k];
+        const int2 bn = w.chunk_bins[cb + k];
+        a += bn.x;
+        bbin += bn.y;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) { nc += ncs[k]; nz += nzs[k]; }
+    // inclusive scans inside each wavefront, then across the 16 wavefronts
+    long long xr = nc, xz = nz;
+    int xa = a, xb = bbin;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const long long yr = __shfl_up(xr, o, 64);
+      const long long yz = __shfl_up(xz, o, 64);
+      const int ya = __shfl_up(xa, o, 64);
+      const int yb = __shfl_up(xb, o, 64);
+      if (lane >= o) { xr += yr; xz += yz; xa += ya; xb += yb; }
+    }
+    if (lane == 63) { s_wr[wid] = xr; s_wz[wid] = xz; s_wa[wid] = xa; s_wb[wid] = xb; }
+    __syncthreads();
+    // the first wavefront scans the 16 wavefront totals: exclusive prefixes
+    // in place, the tile's totals in slot 16
+    if (wid == 0) {
+      const long long r0 = lane < 16 ? s_wr[lane] : 0, z0 = lane < 16 ? s_wz[lane] : 0;
+      const int a0 = lane < 16 ? s_wa[lane] : 0, b0 = lane < 16 ? s_wb[lane] : 0;
+      long long r = r0, z = z0;
+      int a1 = a0, b1 = b0;
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        const long long yr = __shfl_up(r, o, 64);
+        const long long yz = __shfl_up(z, o, 64);
+        const int ya = __shfl_up(a1, o, 64);
+        const int yb = __shfl_up(b1, o, 64);
+        if (lane >= o) { r += yr; z += yz; a1 += ya; b1 += yb; }
+      }
+      if (lane < 16) { s_wr[lane] = r - r0; s_wz[lane] = z - z0; }
+      if (lane == 15) { s_wr[16] = r; s_wz[16] = z; s_wa[16] = a1; s_wb[16] = b1; }
+    }
+    __syncthreads();
+    const long long br = s_wr[wid], bz = s_wz[wid], tr = s_wr[16], tz = s_wz[16];
+    const int ta = s_wa[16], tb = s_wb[16];
+    __syncthreads();  // read before the next tile writes them
+    long long rr = carry_r + br + xr - nc;
+    long long zz = carry_z + bz + xz - nz;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const int c = cb + k;
+      if (c < nch) {
+        w.chunk_rbase[c] = (int32_t)rr;
+        w.chunk_nzglob[c] = zz;
+        // row blocks whose first row lies in this chunk
+        for (long long b = (rr + (1 << kRowBlockLog) - 1) >> kRowBlockLog; (b << kRowBlockLog) < rr + ncs[k]; ++b)
+          w.row_block_chunk[b] = c;
+      }
+      rr += ncs[k];
+      zz += nzs[k];
+    }
+    carry_r += tr;
+    carry_z += tz;
+    na += ta;
+    nb += tb;
   }
-  long long rr = br + xr - sr;
-  long long zz = bz + xz - sz;
-  for (int c = c0; c < c1; ++c) {
-    w.chunk_rbase[c] = (int32_t)rr;
-    w.chunk_nzglob[c] = zz;
-    const int nc = w.chunk_nc[c];
-    // row blocks whose first row lies in this chunk
-    for (long long b = (rr + (1 << kRowBlockLog) - 1) >> kRowBlockLog; (b << kRowBlockLog) < rr + nc; ++b)
-      w.row_block_chunk[b] = c;
-    rr += nc;
-    zz += w.chunk_nnz[c];
-  }
+  const long long rows_total = carry_r, nnz_total = carry_z;
   __syncthreads();
   for (int m = tid; m < w.nmat; m += 1024) {
     const GDesc d = gview(w.desc[m]);
@@ -1636,7 +1679,7 @@ __device__ __forceinline__ int qori(int v) {
 }
 
 struct QuadBuf {
-  double K[8 * 9];  // gathered block, row q of K at stride 9
+  double K[8 * 8];  // gathered block, row q of K at stride 8
   double f[8];
   int nb[8];
 };
@@ -1645,7 +1688,7 @@ struct QuadBuf {
 #define QB_ROW(arr0, arr1, k, p) ((k) & 1 ? qb(arr1[p], (k) / 2) : qb(arr0[p], (k) / 2))
 
 template <int NT>
-__global__ __launch_bounds__(NT) void k_quad8(Work w) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_quad8(Work w) {
   constexpr int NQ = NT / 4;
   __shared__ QuadBuf qbuf[NQ];
   const int tid = threadIdx.x;
@@ -1685,9 +1728,9 @@ __global__ __launch_bounds__(NT) void k_quad8(Work w) {
     B.nb[q0] = n0;
     B.nb[q1] = n1;
 #pragma unroll
-    for (int u = 0; u < 18; ++u) {  // zero the block, identity on the padding
-      const int idx = ql * 18 + u;
-      const int rq = idx / 9, cp = idx % 9;
+    for (int u = 0; u < 16; ++u) {  // zero the block, identity on the padding
+      const int idx = ql * 16 + u;
+      const int rq = idx / 8, cp = idx % 8;
       B.K[idx] = (rq == cp && rq >= s) ? 1.0 : 0.0;
     }
     B.f[q0] = 0.0;
@@ -1715,8 +1758,8 @@ __global__ __launch_bounds__(NT) void k_quad8(Work w) {
         for (int j = 0; j < 4; ++j) {
           const int qa = find_pos<8>(B.nb, ka[j]);
           const int qb_ = find_pos<8>(B.nb, kb[j]);
-          if (qa >= 0) B.K[qa * 9 + q0] = va_[j];
-          if (qb_ >= 0) B.K[qb_ * 9 + q1] = vb_[j];
+          if (qa >= 0) B.K[qa * 8 + q0] = va_[j];
+          if (qb_ >= 0) B.K[qb_ * 8 + q1] = vb_[j];
         }
       }
     }
@@ -1734,8 +1777,8 @@ __global__ __launch_bounds__(NT) void k_quad8(Work w) {
     double rs0 = 0.0, rs1 = 0.0;
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
-      k0[p] = B.K[q0 * 9 + p];
-      k1[p] = B.K[q1 * 9 + p];
+      k0[p] = B.K[q0 * 8 + p];
+      k1[p] = B.K[q1 * 8 + p];
       amax = fmaxf(amax, fmaxf((float)fabs(k0[p]), (float)fabs(k1[p])));
       rs0 += fabs(k0[p]);
       rs1 += fabs(k1[p]);
@@ -1810,14 +1853,13 @@ __global__ __launch_bounds__(NT) void k_quad8(Work w) {
       z1 = y1;
       for (it = 1; it <= kRefineMax; ++it) {
         // r = f - K z in FP64: all of z broadcast in the quad
-        double zall[8];
-#pragma unroll
-        for (int p = 0; p < 8; ++p) zall[p] = (p & 1) ? qbd(z1, p / 2) : qbd(z0, p / 2);
+        // (the FP64 rows are read from LDS again rather than kept live)
         double r0 = f0, r1 = f1;
 #pragma unroll
         for (int p = 0; p < 8; ++p) {
-          r0 = fma(-k0[p], zall[p], r0);
-          r1 = fma(-k1[p], zall[p], r1);
+          const double zp = (p & 1) ? qbd(z1, p / 2) : qbd(z0, p / 2);
+          r0 = fma(-B.K[q0 * 8 + p], zp, r0);
+          r1 = fma(-B.K[q1 * 8 + p], zp, r1);
         }
         const double rn = qmaxd(fmax(fabs(r0), fabs(r1)));
         const double zn = qmaxd(fmax(fabs(z0), fabs(z1)));
