@@ -1050,8 +1050,10 @@ constexpr int kRefineMax = 5;
 // G lanes per row, blocks of up to SM <= G points.  which = 0: bin A
 // (|N| <= G = GA); which = 1: bin B (GA < |N| <= 32), rows with |N| > SM are
 // handed to the workgroup solver.
+// (at SM = 20 the registers fit four wavefronts per SIMD without spilling;
+// the other shapes are held to fewer by their LDS or would spill)
 template <int G, int NT, int SM>
-__global__ __launch_bounds__(NT) void k_numeric(Work w, int which) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(SM == 20 ? 4 : 1))) void k_numeric(Work w, int which) {
   static_assert(SM <= G, "block bound");
   constexpr int NG = NT / G;
   constexpr int LD = SM + 1;
@@ -2688,7 +2690,7 @@ __device__ bool project_column(const Work& w, const GDesc& d, int64_t nzb, int j
 // registers; a longer list takes the general path.
 constexpr int kIC = 4, kPI = 4;
 
-__global__ __launch_bounds__(256) void k_colproj(Work w) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_colproj(Work w) {
   __shared__ int s_unc;
   const int c = xcd_logical_block();
   const int tid = threadIdx.x;
