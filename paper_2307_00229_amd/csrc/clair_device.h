@@ -443,14 +443,21 @@ __device__ __forceinline__ int rega_bfs(RegSetA<SM>& S, int n, int i, int ell, g
   return S.s;
 }
 
-// matrix owning global chunk c (desc[].chunk0 ascending)
+// matrix owning global chunk c (desc[].chunk0 ascending): the last matrix
+// whose first chunk is at or before c.  For a wavefront whose 64 lanes all
+// ask for the same c, with every lane active: lane l reads the first chunk
+// of matrix b + l for blocks of 64 matrices and a ballot counts them, one
+// round of loads per 64 matrices instead of a dependent binary search.
 __device__ __forceinline__ int chunk_matrix(const MatDesc* desc, int nmat, int c) {
-  int lo = 0, hi = nmat - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (desc[mid].chunk0 <= c) lo = mid; else hi = mid - 1;
+  const int lane = threadIdx.x & 63;
+  int cnt = 0;
+  for (int b = 0; b < nmat; b += 64) {
+    const int k = b + lane;
+    const uint64_t bal = __ballot(k < nmat && desc[k].chunk0 <= c);
+    cnt += __popcll(bal);
+    if (bal != ~0ull) break;  // ascending: no later matrix starts at or before c
   }
-  return lo;
+  return cnt > 0 ? cnt - 1 : 0;
 }
 
 __device__ __forceinline__ void flag_row(MatStatus* st, int32_t code, int fine_row) {

@@ -412,55 +412,85 @@ __device__ __forceinline__ int small_limit(int GA) { return GA <= 4 ? 8 : GA; }
 __device__ __forceinline__ int slot_stride(int GA) { return GA <= 4 ? 8 : GA; }
 
 // The compact adjacency of the matrices whose descriptor carries one: the
-// workgroup of logical block b takes 256 points of chunk b / (chunk / 256),
-// one thread per point (the chunk's XCD is the one k_count gives it).
+// workgroup of logical block b takes 256 * kAdjPP points of chunk
+// b / ceil(chunk / (256 * kAdjPP)) (the chunk's XCD is the one k_count gives
+// it), kAdjPP points per thread with their loads in flight together (two per
+// thread were slower than one: 98 VGPRs instead of 44 halve the wavefronts).
+constexpr int kAdjPP = 1;
+
 template <int W>
 __global__ __launch_bounds__(256) void k_adj(Work w) {
-  const int per = w.chunk / 256;
+  const int per = (w.chunk + 256 * kAdjPP - 1) / (256 * kAdjPP);
   const int b = xcd_logical_block();
   const int c = b / per;
   const int m = chunk_matrix(w.desc, w.nmat, c);
   const GDesc d = gview(w.desc[m]);
   if (!d.fadj) return;
-  const int u = (c - d.chunk0) * w.chunk + (b - c * per) * 256 + (int)threadIdx.x;
-  if (u >= d.n) return;
-  int o[W];
+  const int f0 = (c - d.chunk0) * w.chunk;
+  const int f1 = min(f0 + w.chunk, d.n);
+  const int ub = f0 + (b - c * per) * 256 * kAdjPP + (int)threadIdx.x;
+  int u[kAdjPP], e0[kAdjPP], e1[kAdjPP], cnt[kAdjPP];
+  int o[kAdjPP][W];
 #pragma unroll
-  for (int q = 0; q < W; ++q) o[q] = -1;
-  int cnt = 0;
-  const int e1 = d.grp[u + 1];
-  for (int e = d.grp[u]; e < e1 && cnt <= W; e += 8) {
-    int k[8];
-    double x[8];
+  for (int p = 0; p < kAdjPP; ++p) {
+    u[p] = ub + 256 * p;
+    e0[p] = 0;
+    e1[p] = 0;
+    cnt[p] = 0;
+    if (u[p] < f1) { e0[p] = d.grp[u[p]]; e1[p] = d.grp[u[p] + 1]; }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      k[j] = u;
-      x[j] = 0.0;
-      if (e + j < e1) { k[j] = d.gci[e + j]; x[j] = d.gva[e + j]; }
+    for (int q = 0; q < W; ++q) o[p][q] = -1;
+  }
+  for (int e = 0;; e += 8) {
+    bool any = false;
+#pragma unroll
+    for (int p = 0; p < kAdjPP; ++p) any |= e0[p] + e < e1[p] && cnt[p] <= W;
+    if (!any) break;
+    int k[kAdjPP][8];
+    double x[kAdjPP][8];
+#pragma unroll
+    for (int p = 0; p < kAdjPP; ++p) {
+      const bool go = cnt[p] <= W;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        k[p][j] = u[p];
+        x[p][j] = 0.0;
+        if (go && e0[p] + e + j < e1[p]) { k[p][j] = d.gci[e0[p] + e + j]; x[p][j] = d.gva[e0[p] + e + j]; }
+      }
     }
-    int8_t c8[8];
+    int8_t c8[kAdjPP][8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) c8[j] = ((unsigned)k[j] < (unsigned)d.n) ? d.cf[k[j]] : (int8_t)1;
+    for (int p = 0; p < kAdjPP; ++p)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      if (k[j] != u && x[j] != 0.0 && c8[j] == 0 && strong_edge(x[j], k[j], d.theta, d.cmax)) {
+      for (int j = 0; j < 8; ++j)
+        c8[p][j] = ((unsigned)k[p][j] < (unsigned)d.n) ? d.cf[k[p][j]] : (int8_t)1;
 #pragma unroll
-        for (int q = 0; q < W; ++q)
-          if (q == cnt) o[q] = k[j];
-        ++cnt;
+    for (int p = 0; p < kAdjPP; ++p) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (k[p][j] != u[p] && x[p][j] != 0.0 && c8[p][j] == 0 && strong_edge(x[p][j], k[p][j], d.theta, d.cmax)) {
+#pragma unroll
+          for (int q = 0; q < W; ++q)
+            if (q == cnt[p]) o[p][q] = k[p][j];
+          ++cnt[p];
+        }
       }
     }
   }
-  if (cnt > W) o[0] = kAdjOverflow;
-  gptr<adj_v4> dst = (gptr<adj_v4>)(to_global(w.fadj) + (d.fine0 + u) * W);
 #pragma unroll
-  for (int q = 0; q < W / 4; ++q) {
-    adj_v4 t;
-    t.x = o[4 * q];
-    t.y = o[4 * q + 1];
-    t.z = o[4 * q + 2];
-    t.w = o[4 * q + 3];
-    dst[q] = t;
+  for (int p = 0; p < kAdjPP; ++p) {
+    if (u[p] >= f1) continue;
+    if (cnt[p] > W) o[p][0] = kAdjOverflow;
+    gptr<adj_v4> dst = (gptr<adj_v4>)(to_global(w.fadj) + (d.fine0 + u[p]) * W);
+#pragma unroll
+    for (int q = 0; q < W / 4; ++q) {
+      adj_v4 t;
+      t.x = o[p][4 * q];
+      t.y = o[p][4 * q + 1];
+      t.z = o[p][4 * q + 2];
+      t.w = o[p][4 * q + 3];
+      dst[q] = t;
+    }
   }
 }
 
@@ -1744,6 +1774,18 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
       int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
       if (q0 < s) { a0 = d.rp[n0]; a1 = d.rp[n0 + 1]; }
       if (q1 < s) { b0 = d.rp[n1]; b1 = d.rp[n1 + 1]; }
+      // row i's bounds and its first eight entries (two per lane) go out with
+      // the block rows' loads
+      const int i0 = d.rp[i], i1 = d.rp[i + 1];
+      int kf[2];
+      double vf[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int e = i0 + ql + 4 * h;
+        kf[h] = -1;
+        vf[h] = 0.0;
+        if (e < i1) { kf[h] = d.ci[e]; vf[h] = d.va[e]; }
+      }
       for (int o = 0; a0 + o < a1 || b0 + o < b1; o += 4) {
         int ka[4], kb[4];
         double va_[4], vb_[4];
@@ -1764,10 +1806,12 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
           if (qb_ >= 0) B.K[qb_ * 8 + q1] = vb_[j];
         }
       }
-    }
-    {
-      const int e1 = d.rp[i + 1];
-      for (int e = d.rp[i] + ql; e < e1; e += 4) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int qq = find_pos<8>(B.nb, kf[h]);
+        if (qq >= 0) B.f[qq] = -vf[h];
+      }
+      for (int e = i0 + ql + 8; e < i1; e += 4) {  // rows of more than eight entries
         const int qq = find_pos<8>(B.nb, d.ci[e]);
         if (qq >= 0) B.f[qq] = -d.va[e];
       }
@@ -2911,8 +2955,8 @@ hipError_t launch_validate(const Work& w, int blocks, hipStream_t s) {
 
 hipError_t launch_adj(const Work& w, hipStream_t s) {
   if (w.nchunks == 0 || w.adj_w == 0) return hipSuccess;
-  if (w.chunk % 256) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)w.nchunks * (unsigned)(w.chunk / 256));
+  const int per = (w.chunk + 256 * kAdjPP - 1) / (256 * kAdjPP);
+  const dim3 grid((unsigned)w.nchunks * (unsigned)per);
   if (w.adj_w == 4) hipLaunchKernelGGL(k_adj<4>, grid, dim3(256), 0, s, w);
   else if (w.adj_w == 8) hipLaunchKernelGGL(k_adj<8>, grid, dim3(256), 0, s, w);
   else return hipErrorInvalidValue;
