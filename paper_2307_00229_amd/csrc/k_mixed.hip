@@ -1710,6 +1710,8 @@ __device__ __forceinline__ int qori(int v) {
   return v;
 }
 
+constexpr int kQG = 5;  // entries per gather round of k_quad8
+
 struct QuadBuf {
   double K[8 * 8];  // gathered block, row q of K at stride 8
   double f[8];
@@ -1769,7 +1771,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     B.f[q1] = 0.0;
     wave_sync();
     // gather: lane l walks rows N_{2l}, N_{2l+1} of A (columns 2l, 2l+1 of
-    // K) side by side, four entries of each at a time
+    // K) side by side, kQG entries of each at a time (a five-point row in
+    // one round)
     {
       int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
       if (q0 < s) { a0 = d.rp[n0]; a1 = d.rp[n0 + 1]; }
@@ -1786,11 +1789,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         vf[h] = 0.0;
         if (e < i1) { kf[h] = d.ci[e]; vf[h] = d.va[e]; }
       }
-      for (int o = 0; a0 + o < a1 || b0 + o < b1; o += 4) {
-        int ka[4], kb[4];
-        double va_[4], vb_[4];
+      for (int o = 0; a0 + o < a1 || b0 + o < b1; o += kQG) {
+        int ka[kQG], kb[kQG];
+        double va_[kQG], vb_[kQG];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < kQG; ++j) {
           ka[j] = -1;
           kb[j] = -1;
           va_[j] = 0.0;
@@ -1799,7 +1802,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
           if (b0 + o + j < b1) { kb[j] = d.ci[b0 + o + j]; vb_[j] = d.va[b0 + o + j]; }
         }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < kQG; ++j) {
           const int qa = find_pos<8>(B.nb, ka[j]);
           const int qb_ = find_pos<8>(B.nb, kb[j]);
           if (qa >= 0) B.K[qa * 8 + q0] = va_[j];
