@@ -1083,7 +1083,7 @@ constexpr int kRefineMax = 5;
 // (at SM = 20 the registers fit four wavefronts per SIMD without spilling;
 // the other shapes are held to fewer by their LDS or would spill)
 template <int G, int NT, int SM>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(SM == 20 ? 4 : 1))) void k_numeric(Work w, int which) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((SM == 20 || SM == 24) ? 4 : 1))) void k_numeric(Work w, int which) {
   static_assert(SM <= G, "block bound");
   constexpr int NG = NT / G;
   constexpr int LD = SM + 1;
