@@ -44,7 +44,14 @@
  *   until the FP64 backward error is at rounding level; the projection is
  *   FP64.  Rows whose FP32 factorisation is unreliable are redone in FP64.
  *   CLAIR_PREC_FP64 is the plain per-row FP64 form (one thread per row, one
- *   kernel per stage, one matrix at a time).
+ *   kernel per stage, one matrix at a time).  CLAIR_PREC_MIXED_BF16 is the
+ *   mixed form whose workgroup solver (blocks of 33 to 128 points) takes the
+ *   L21 and U12 tiles of its blocked LU's trailing updates rounded to
+ *   bfloat16 (matrix cores, FP32 accumulation), refines in FP64 for up to 10
+ *   steps, and redoes a row that does not converge with FP32 updates
+ *   (clair_info_t.n_bf16_retries); smaller blocks are solved as in
+ *   CLAIR_PREC_MIXED.  clair_build_R_batched / _ex and clair_build_R_agg
+ *   accept it; graphs and plans use CLAIR_PREC_MIXED.
  * - Errors: every entry point returns a clair_status (0 = CLAIR_OK).  Nothing
  *   aborts and no C++ exception crosses the ABI.  Per-matrix details land in
  *   clair_info_t.
@@ -70,7 +77,7 @@ typedef enum clair_status {
   CLAIR_ERR_NOMEM = 6        /* workspace allocation failed */
 } clair_status;
 
-enum { CLAIR_PREC_MIXED = 0, CLAIR_PREC_FP64 = 1 };
+enum { CLAIR_PREC_MIXED = 0, CLAIR_PREC_FP64 = 1, CLAIR_PREC_MIXED_BF16 = 2 };
 
 /* Largest local block (|N(i)|) any path accepts. */
 #define CLAIR_MAX_BLOCK 1024
@@ -107,12 +114,15 @@ typedef struct clair_info {
   int64_t n_uncovered;      /* F-points no row reaches (only when B != NULL) */
   int32_t refine_iters_max; /* most FP64 refinement steps any row needed (mixed) */
   int32_t n_fp64_rows;      /* rows solved by the FP64 fallback (mixed) */
+  int32_t n_bf16_retries;   /* rows of more than 32 points whose BF16-update factorisation did not
+                               converge and was redone with FP32 updates (CLAIR_PREC_MIXED_BF16) */
+  int32_t reserved;         /* 0 */
 } clair_info_t;
 
 /* Options for the _ex entry points.  Zero-initialised = defaults. */
 typedef struct clair_opts {
   void* stream;       /* hipStream_t to run on; NULL = null stream */
-  int32_t precision;  /* CLAIR_PREC_MIXED (0) or CLAIR_PREC_FP64 (1) */
+  int32_t precision;  /* CLAIR_PREC_MIXED (0), CLAIR_PREC_FP64 (1) or CLAIR_PREC_MIXED_BF16 (2) */
   int32_t async;      /* 1: only enqueue; read results later with clair_ctx_info */
   int32_t validate;   /* 1: check CSR order / index range on the device first */
   int32_t timing;     /* 1: record per-stage HIP events (see clair_ctx_stage_times) */

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libclair.so")
 
 CLAIR_OK, CLAIR_ERR_INVALID, CLAIR_ERR_CAPACITY, CLAIR_ERR_SINGULAR = 0, 1, 2, 3
 CLAIR_ERR_HIP, CLAIR_ERR_UNSUPPORTED, CLAIR_ERR_NOMEM = 4, 5, 6
-CLAIR_PREC_MIXED, CLAIR_PREC_FP64 = 0, 1
+CLAIR_PREC_MIXED, CLAIR_PREC_FP64, CLAIR_PREC_MIXED_BF16 = 0, 1, 2
 CLAIR_MAX_BLOCK = 1024
 
 EXPORTED = [
@@ -54,7 +54,8 @@ class CsrOut(ctypes.Structure):
 class Info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("first_bad_row", ctypes.c_int32), ("n_c", ctypes.c_int32),
                 ("max_block", ctypes.c_int32), ("nnz", ctypes.c_int64), ("n_uncovered", ctypes.c_int64),
-                ("refine_iters_max", ctypes.c_int32), ("n_fp64_rows", ctypes.c_int32)]
+                ("refine_iters_max", ctypes.c_int32), ("n_fp64_rows", ctypes.c_int32),
+                ("n_bf16_retries", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

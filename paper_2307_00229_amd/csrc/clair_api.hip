@@ -386,6 +386,8 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
   w.capC = (int32_t)std::min<int64_t>(b->L.capC, INT32_MAX);
   w.adj_w = b->adj_w;
   w.fadj = reinterpret_cast<int32_t*>(base + b->L.fadj);
+  w.bf16 = 0;
+  w.pad1 = 0;
 
   char* h = stage_base(c);
   MatDesc* hd = reinterpret_cast<MatDesc*>(h);
@@ -622,6 +624,8 @@ void fill_results(const MatStatus* hs, int nmat, clair_csr_out_t* R, clair_info_
       in.n_uncovered = hs[m].n_uncovered;
       in.refine_iters_max = hs[m].refine_max;
       in.n_fp64_rows = hs[m].n_fp64;
+      in.n_bf16_retries = hs[m].n_retry;
+      in.reserved = 0;
     }
   }
 }
@@ -642,6 +646,7 @@ int run_mixed(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* co
   Batch b;
   int rc = prepare(c, nmat, A, cf, B, ell, R, &b, agg);
   if (rc) return rc;
+  b.w.bf16 = (o && o->precision == CLAIR_PREC_MIXED_BF16) ? 1 : 0;
   c->last_nmat = nmat;
   c->last_stream = s;
   c->last_layout = b.L;
@@ -892,7 +897,7 @@ int clair_build_R_batched(clair_ctx_t* c, int32_t nmat, const clair_csr_t* A, co
   if (rc) return rc;
   if (nmat == 0) return CLAIR_OK;
   if (o && o->precision == CLAIR_PREC_FP64) return run_plain(c, nmat, A, cf, B, ell, R, o, info);
-  if (o && o->precision != CLAIR_PREC_MIXED) return CLAIR_ERR_INVALID;
+  if (o && o->precision != CLAIR_PREC_MIXED && o->precision != CLAIR_PREC_MIXED_BF16) return CLAIR_ERR_INVALID;
   try {
     return run_mixed(c, nmat, A, cf, B, ell, R, o, info);
   } catch (...) {
@@ -909,7 +914,7 @@ int clair_build_R_agg(clair_ctx_t* c, int32_t nmat, const clair_csr_t* A, const 
   if (nmat > 0 && !agg) return CLAIR_ERR_INVALID;
   if (nmat == 0) return CLAIR_OK;
   if (o && o->precision == CLAIR_PREC_FP64) return CLAIR_ERR_UNSUPPORTED;
-  if (o && o->precision != CLAIR_PREC_MIXED) return CLAIR_ERR_INVALID;
+  if (o && o->precision != CLAIR_PREC_MIXED && o->precision != CLAIR_PREC_MIXED_BF16) return CLAIR_ERR_INVALID;
   try {
     return run_mixed(c, nmat, A, cf, B, ell, R, o, info, agg);
   } catch (...) {

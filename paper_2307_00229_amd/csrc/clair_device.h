@@ -152,7 +152,7 @@ struct MatStatus {
   int32_t refine_max;
   int32_t n_fp64;
   int32_t row_base;    // first global row of this matrix
-  int32_t pad0;
+  int32_t n_retry;     // rows whose BF16-update factorisation was redone with FP32 updates
   int64_t nz_base;     // first global R entry of this matrix (batch-wide numbering)
 };
 
@@ -207,6 +207,8 @@ struct Work {
   int32_t capC;
   int32_t adj_w;          // slots per point of the compact adjacency (0: none built)
   int32_t* fadj;          // [n_total * adj_w]
+  int32_t bf16;           // 1: the workgroup solver's trailing updates take bfloat16 inputs
+  int32_t pad1;
 };
 
 // status codes (mirror clair_status)

@@ -2229,7 +2229,16 @@ __device__ __forceinline__ void block_argmax(double v, int idx, double* shv, int
 // the row to the FP64 solver with partial pivoting.
 // ---------------------------------------------------------------------------
 constexpr int kMfmaMax = 128;
+constexpr int kRefineMaxBf16 = 10;  // refinement steps of the BF16-update factorisation
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+
+// x rounded to bfloat16 (nearest, ties to even), as its 16 bits; x finite
+__device__ __forceinline__ short to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
 
 // max of v over the workgroup (all threads call; result to all)
 __device__ __forceinline__ double block_maxd(double v, double* shv) {
@@ -2298,9 +2307,22 @@ __device__ __forceinline__ void mf_lu_solve(const float* K, int lda, int S, floa
 // Returns true with the solution in z[0..s) when the row converged.
 // N: sorted neighbourhood (LDS); K: LDS buffer of (kMfmaMax+1)*kMfmaMax
 // floats; f, z, r: LDS FP64 vectors of kMfmaMax; y: LDS FP32 vector of
-// kMfmaMax.
+// kMfmaMax.  bf16: the trailing updates take their L21 and U12 tiles
+// rounded to bfloat16 (v_mfma_f32_32x32x8bf16_1k, FP32 accumulation), and
+// the refinement may take up to kRefineMaxBf16 steps.
+// LDS scratch of the residual's column lists (see below)
+struct ResidLists {
+  int* cnt;  // [kMfmaMax + 1]
+  int* off;  // [kMfmaMax + 1]
+  int* pp;   // [cap] block row p of each entry
+  int* pe;   // [cap] its entry in A
+  int* bnd;  // [2 kMfmaMax] row bounds, for rows whose lists exceed cap
+  int cap;
+};
+
 __device__ __forceinline__ bool mixed_big_row(const GDesc& d, int i, const int* N, int s, float* K, double* f, double* z,
-                              double* r, float* y, double* shv, int* s_flag, int* it_out, int* bnd) {
+                              double* r, float* y, double* shv, int* s_flag, int* it_out, const ResidLists& rl,
+                              bool bf16) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int S = (s + 31) & ~31;
@@ -2376,12 +2398,27 @@ __device__ __forceinline__ bool mixed_big_row(const GDesc& d, int i, const int* 
         const int row = i0 + 8 * (rr / 4) + 4 * (lane / 32) + (rr % 4);
         acc[rr] = K[row * lda + j0 + (lane % 32)];
       }
+      if (bf16) {
+        // lane l supplies A[l % 32][4 (l / 32) + j] and B[4 (l / 32) + j][l % 32], j < 4
 #pragma unroll
-      for (int kk = 0; kk < 16; ++kk) {
-        const int kc = P0 + 2 * kk + lane / 32;
-        const float a = -K[(i0 + lane % 32) * lda + kc];
-        const float b = K[kc * lda + j0 + lane % 32];
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        for (int kk = 0; kk < 4; ++kk) {
+          const int kc = P0 + 8 * kk + 4 * (lane / 32);
+          bf16x4 a, b;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            a[j] = to_bf16(-K[(i0 + lane % 32) * lda + kc + j]);
+            b[j] = to_bf16(K[(kc + j) * lda + j0 + lane % 32]);
+          }
+          acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, acc, 0, 0, 0);
+        }
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+          const int kc = P0 + 2 * kk + lane / 32;
+          const float a = -K[(i0 + lane % 32) * lda + kc];
+          const float b = K[kc * lda + j0 + lane % 32];
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+        }
       }
 #pragma unroll
       for (int rr = 0; rr < 16; ++rr) {
@@ -2404,26 +2441,86 @@ __device__ __forceinline__ bool mixed_big_row(const GDesc& d, int i, const int* 
   mf_lu_solve(K, lda, S, y);
   for (int t = tid; t < s; t += kWT) z[t] = y[t];
   __syncthreads();
-  // row bounds of the rows of N, for the residual's searches
-  for (int p = tid; p < s; p += kWT) { bnd[2 * p] = d.rp[N[p]]; bnd[2 * p + 1] = d.rp[N[p] + 1]; }
+  // The residual r_q = f_q - sum_p a_{N_p, N_q} z_p reads, for each q, the
+  // entries of column N_q in the rows N_p: lists built once per row (counted,
+  // placed, then each ordered by p), so every residual sums in ascending p
+  // (the same bits on every run) with independent loads.  Rows whose lists
+  // exceed the scratch search each row N_p by bisection instead.
+  int* cnt = rl.cnt;
+  int* off = rl.off;
+  for (int q = tid; q <= s; q += kWT) cnt[q] = 0;
   __syncthreads();
-  for (int it = 1; it <= kRefineMax; ++it) {
-    // r = f - K z with the FP64 entries of A: r_q = f_q - sum_p a_{N_p, N_q} z_p,
-    // summed in ascending p (the same bits on every run): thread q finds N_q
-    // in each row N_p by bisection
-    for (int q = tid; q < s; q += kWT) {
-      const int col = N[q];
-      double acc = f[q];
-#pragma unroll 4
-      for (int p = 0; p < s; ++p) {
-        int lo = bnd[2 * p];
-        const int e1 = bnd[2 * p + 1];
-        int hi = e1;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (d.ci[mid] < col) lo = mid + 1; else hi = mid;
+  for (int p = tid; p < s; p += kWT) {
+    const int u = N[p];
+    const int e1 = d.rp[u + 1];
+    for (int e = d.rp[u]; e < e1; ++e) {
+      const int q = find_sorted(N, s, d.ci[e]);
+      if (q >= 0) atomicAdd(&cnt[q], 1);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int o = 0;
+    for (int q = 0; q < s; ++q) {
+      off[q] = o;
+      o += cnt[q];
+      cnt[q] = 0;
+    }
+    off[s] = o;
+  }
+  __syncthreads();
+  const bool lists = off[s] <= rl.cap;  // workgroup-uniform
+  if (lists) {
+    for (int p = tid; p < s; p += kWT) {
+      const int u = N[p];
+      const int e1 = d.rp[u + 1];
+      for (int e = d.rp[u]; e < e1; ++e) {
+        const int q = find_sorted(N, s, d.ci[e]);
+        if (q >= 0) {
+          const int k = off[q] + atomicAdd(&cnt[q], 1);
+          rl.pp[k] = p;
+          rl.pe[k] = e;
         }
-        if (lo < e1 && d.ci[lo] == col) acc = fma(-d.va[lo], z[p], acc);
+      }
+    }
+    __syncthreads();
+    for (int q = tid; q < s; q += kWT) {  // insertion sort of list q by p
+      for (int k = off[q] + 1; k < off[q + 1]; ++k) {
+        const int kp = rl.pp[k], ke = rl.pe[k];
+        int m = k - 1;
+        while (m >= off[q] && rl.pp[m] > kp) {
+          rl.pp[m + 1] = rl.pp[m];
+          rl.pe[m + 1] = rl.pe[m];
+          --m;
+        }
+        rl.pp[m + 1] = kp;
+        rl.pe[m + 1] = ke;
+      }
+    }
+  } else {
+    for (int p = tid; p < s; p += kWT) { rl.bnd[2 * p] = d.rp[N[p]]; rl.bnd[2 * p + 1] = d.rp[N[p] + 1]; }
+  }
+  __syncthreads();
+  const int itmax = bf16 ? kRefineMaxBf16 : kRefineMax;
+  for (int it = 1; it <= itmax; ++it) {
+    // r = f - K z with the FP64 entries of A, summed in ascending p
+    for (int q = tid; q < s; q += kWT) {
+      double acc = f[q];
+      if (lists) {
+        const int k1 = off[q + 1];
+        for (int k = off[q]; k < k1; ++k) acc = fma(-d.va[rl.pe[k]], z[rl.pp[k]], acc);
+      } else {
+        const int col = N[q];
+        for (int p = 0; p < s; ++p) {
+          int lo = rl.bnd[2 * p];
+          const int e1 = rl.bnd[2 * p + 1];
+          int hi = e1;
+          while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (d.ci[mid] < col) lo = mid + 1; else hi = mid;
+          }
+          if (lo < e1 && d.ci[lo] == col) acc = fma(-d.va[lo], z[p], acc);
+        }
       }
       r[q] = acc;
     }
@@ -2507,8 +2604,17 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
       }
       // blocks above 32 points: the mixed solver first
       int itm = 0;
-      const bool mixed_ok = s > 32 && s <= kMfmaMax &&
-                            mixed_big_row(d, i, N, s, sK32, sf, s_z, s_r, s_y, shv, &s_mflag, &itm, bb.dp);
+      bool mixed_ok = false;
+      if (s > 32 && s <= kMfmaMax) {
+        static_assert(kWN >= kMfmaMax + 1 && kWN + 1 >= 2 * kMfmaMax, "the residual's lists fit the search's buffers");
+        const ResidLists rl{bb.fr, bb.nl, bb.cand, bb.kb, bb.dp, kWC};
+        mixed_ok = mixed_big_row(d, i, N, s, sK32, sf, s_z, s_r, s_y, shv, &s_mflag, &itm, rl, w.bf16 != 0);
+        if (!mixed_ok && w.bf16) {
+          // the BF16-update factorisation did not converge: FP32 updates next
+          if (tid == 0) atomicAdd(&st->n_retry, 1);
+          mixed_ok = mixed_big_row(d, i, N, s, sK32, sf, s_z, s_r, s_y, shv, &s_mflag, &itm, rl, false);
+        }
+      }
       if (mixed_ok) {
         for (int t = tid; t < s; t += kWT) sf[t] = s_z[t];
         if (tid == 0 && itm > __hip_atomic_load(&st->refine_max, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))

@@ -65,7 +65,7 @@ int main(void) {
   printf("clair_info_t %zu\n", sizeof(clair_info_t));
   printf("clair_opts_t %zu\n", sizeof(clair_opts_t));
   P(clair_csr_t, val) P(clair_csr_out_t, nnz_capacity) P(clair_csr_out_t, val)
-  P(clair_info_t, n_uncovered) P(clair_info_t, n_fp64_rows) P(clair_opts_t, timing)
+  P(clair_info_t, n_uncovered) P(clair_info_t, n_fp64_rows) P(clair_info_t, n_bf16_retries) P(clair_opts_t, timing)
   return 0;
 }
 '''
@@ -86,6 +86,7 @@ int main(void) {
     assert vals["clair_csr_out_t.val"] == clair.CsrOut.val.offset
     assert vals["clair_info_t.n_uncovered"] == clair.Info.n_uncovered.offset
     assert vals["clair_info_t.n_fp64_rows"] == clair.Info.n_fp64_rows.offset
+    assert vals["clair_info_t.n_bf16_retries"] == clair.Info.n_bf16_retries.offset
     assert vals["clair_opts_t.timing"] == clair.Opts.timing.offset
 
 

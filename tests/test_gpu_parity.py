@@ -278,3 +278,20 @@ def test_search_adjacency_modes(mode):
         assert np.array_equal(a["val"], b["val"])
     with pytest.raises(clair.ClairError):
         ctx.set_search_adjacency(3)
+
+
+@pytest.mark.parametrize("which", ["2048-type l=5", "128cube-type l=4"])
+def test_bf16_trailing_updates(which):
+    # CLAIR_PREC_MIXED_BF16: the workgroup solver's trailing updates take
+    # bfloat16 tiles (FP32 accumulation); FP64 refinement brings every row to
+    # the same gates as the FP32 form, with no row left to the FP64 solver
+    from paper_2307_00229_amd import clair
+
+    p = P.cfg3(N=150, ell=5) if which.startswith("2048") else P.cfg5(N=24, ell=4)
+    res, infos = _check([p], precision=clair.CLAIR_PREC_MIXED_BF16)
+    inf = infos[0]
+    print(f"[gpu] {which}: bf16 retries {inf['n_bf16_retries']}, refine max {inf['refine_iters_max']}", flush=True)
+    assert inf["n_fp64_rows"] == 0
+    assert inf["max_block"] > 32
+    big = int(np.count_nonzero(np.diff(res[0]["row_ptr"]) - 1 > 32))
+    assert inf["n_bf16_retries"] <= big // 10, (inf["n_bf16_retries"], big)
