@@ -478,15 +478,16 @@ int clair_ctx_set_graph(clair_ctx_t* ctx, int32_t nmat, const clair_csr_t* S);
  * (T = [S_fc, I]): C-points may then be interior vertices of a walk (the
  * first step reaches i's F-neighbours and i itself, every later step any
  * vertex; only F-points join N(i)).  The default (on = 0) keeps F-points as
- * interior vertices; the two agree for ell <= 2.  With on = 1 the per-row
- * FP64 form (CLAIR_PREC_FP64, clair_build_R_approx) searches literally for
- * any ell, clair_size_R sizes those rows with it, and every mixed-precision
- * entry point returns CLAIR_ERR_UNSUPPORTED for a matrix with ell >= 3 (at
- * ell <= 2 it builds as usual).  The FP64 form's search holds 64 vertices;
- * with on = 1 the C-points it passes through before the last step count
- * against that too, and a row that does not fit fails as an oversized
- * neighbourhood does.  The classical base pattern only (not the
- * aggregation-based one).  on outside {0, 1} returns CLAIR_ERR_INVALID.
+ * interior vertices; the two agree for ell <= 2.  Both forms, the size
+ * query, graphs, plans and the approximate-inverse build follow the setting
+ * for any ell.  The searches hold the C-points they pass through before the
+ * last step too: the mixed form's register search moves a row to its
+ * workgroup search beyond 32 such vertices, which holds up to
+ * CLAIR_MAX_BLOCK; the FP64 form's search holds 64, and a row that does not
+ * fit fails as an oversized neighbourhood does.  The mixed form builds no
+ * compact adjacency for such matrices at ell >= 3.  The classical base
+ * pattern only (not the aggregation-based one).  on outside {0, 1} returns
+ * CLAIR_ERR_INVALID.
  */
 int clair_ctx_set_literal_pattern(clair_ctx_t* ctx, int32_t on);
 int clair_ctx_get_strength(clair_ctx_t* ctx, double* theta);

@@ -141,7 +141,7 @@ struct clair_ctx {
   double theta = 0.0;  // strength threshold of the neighbourhood search
   int adj_mode = -1;   // the search's compact adjacency: -1 automatic width, 0 off, 4 or 8 forced width
   std::vector<clair_csr_t> graph;  // strength matrices of the search, one per matrix (empty: A's graph)
-  int literal = 0;  // the literal S^{ell-1} T pattern (the per-row FP64 form; a no-op at ell <= 2)
+  int literal = 0;  // the literal S^{ell-1} T pattern (both forms; the same pattern as the default at ell <= 2)
   int binB_max = 32;  // largest block of the last batch whose sizes were read back (9..32)
   int binB_lanes = 32;  // lanes per row of the bin-B solver (8, 16 or 32)
   int tune_timed = 0;   // timing runs of the last clair_autotune (0: the cache held the histogram)
@@ -297,9 +297,6 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
     for (int m = 0; m < nmat; ++m)
       if (c->graph[m].n != A[m].n) return CLAIR_ERR_INVALID;
   }
-  if (c->literal)  // the literal pattern differs from the searches here only from distance 3 on
-    for (int m = 0; m < nmat; ++m)
-      if (ell[m] >= 3) return CLAIR_ERR_UNSUPPORTED;
   b->nmat = nmat;
   b->nchunks = 0;
   b->n_total = 0;
@@ -324,7 +321,11 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
     int w_need = 0;
     for (int m = 0; m < nmat; ++m) {
       const int64_t gnnz = c->graph.empty() ? A[m].nnz : c->graph[m].nnz;
-      if (ell[m] < 2 || A[m].n <= 0 || (agg && agg[m]) || gnnz > 9 * (int64_t)A[m].n) continue;
+      // (the literal reading from distance 3 on walks through C-points, which
+      // the adjacency leaves out)
+      if (ell[m] < 2 || A[m].n <= 0 || (agg && agg[m]) || gnnz > 9 * (int64_t)A[m].n ||
+          (c->literal && ell[m] >= 3))
+        continue;
       use_adj[m] = 1;
       w_need = std::max(w_need, gnnz <= 5 * (int64_t)A[m].n ? 4 : 8);
     }
@@ -425,6 +426,8 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
     d.agg_rp = d.agg ? w.agg_rp + fine0 : nullptr;
     d.agg_list = d.agg ? w.agg_list : nullptr;
     d.fadj = (b->adj_w && use_adj[m]) ? w.fadj + fine0 * b->adj_w : nullptr;
+    d.literal = (c->literal && !d.agg) ? 1 : 0;
+    d.pad = 0;
     hd[m] = d;
     chunk0 += d.nchunks;
     fine0 += A[m].n;
@@ -1490,22 +1493,6 @@ int clair_size_R(clair_ctx_t* c, int32_t nmat, const clair_csr_t* A, const int8_
   if (rc) return rc;
   if (nmat == 0) return CLAIR_OK;
   const hipStream_t s = static_cast<hipStream_t>(stream);
-  bool lit3 = false;
-  for (int m = 0; m < nmat; ++m) lit3 |= c->literal && ell[m] >= 3;
-  if (lit3) {  // the literal pattern at distance 3 or more: the per-row form's sizes
-    if (!c->graph.empty() && (int32_t)c->graph.size() != nmat) return CLAIR_ERR_INVALID;
-    for (int m = 0; m < nmat; ++m) {
-      if (!c->graph.empty() && c->graph[m].n != A[m].n) return CLAIR_ERR_INVALID;
-      clair_csr_out_t probe{};
-      clair_info_t in{};
-      rc = run_plain_one(c, A[m], cf[m], nullptr, ell[m], &probe, s, &in, true, nullptr,
-                         c->graph.empty() ? nullptr : &c->graph[m]);
-      if (rc && rc != CLAIR_ERR_CAPACITY) return rc;
-      n_c[m] = probe.n_rows;
-      nnz[m] = probe.nnz;
-    }
-    return CLAIR_OK;
-  }
   Batch b;
   rc = prepare(c, nmat, A, cf, nullptr, ell, R.data(), &b);
   if (rc) return rc;

@@ -60,6 +60,8 @@ struct MatDesc {
   // the compact adjacency of the search graph (null: the search reads the
   // graph's rows): adj_w slots per point, matrix-local indices
   const int32_t* fadj;
+  int32_t literal;  // 1: the pattern of S^{ell-1} T taken literally (C-points may be interior vertices)
+  int32_t pad;
 };
 
 // Pointers into device (global) memory.  Pointers that kernels load from a
@@ -101,6 +103,7 @@ struct GDesc {
   gptr<const double> gva;
   int64_t link_base;
   gptr<const int32_t> fadj;
+  int32_t literal;
 };
 
 __device__ __forceinline__ GDesc gview(const MatDesc& m) {
@@ -131,6 +134,7 @@ __device__ __forceinline__ GDesc gview(const MatDesc& m) {
   g.agg_list = to_global(m.agg_list);
   g.link_base = m.link_base;
   g.fadj = to_global(m.fadj);
+  g.literal = m.literal;
   return g;
 }
 
@@ -443,6 +447,81 @@ __device__ __forceinline__ int rega_bfs(RegSetA<SM>& S, int n, int i, int ell, g
   if (S.ovf) return -1;
   bitonic_sort<SM>(S.v);
   return S.s;
+}
+
+// The literal reading of Algorithm 1's pattern S^{ell-1} T, T = [S_fc, I]:
+// the first step reaches i's F-neighbours; the second step expands i itself
+// (T's identity part) and those points; from the second step on, C-points
+// may be interior vertices of a walk (they stay in the set until the last
+// step and are dropped at the end); i never enters.  The graph's rows only
+// (the compact adjacency lists F-points alone).  Returns |N(i)| with
+// S.v[0..s) ascending, or -1 when more than SM points (C-points included)
+// are met.
+template <int SM>
+__device__ __forceinline__ void rowa_expand_literal(RegSetA<SM>& S, int n, int u, int i, bool allow_c,
+                                                    gptr<const int32_t> __restrict__ rp,
+                                                    gptr<const int32_t> __restrict__ ci,
+                                                    gptr<const double> __restrict__ va,
+                                                    gptr<const int8_t> __restrict__ cf, double theta,
+                                                    gptr<const double> __restrict__ cmax) {
+  const int e1 = rp[u + 1];
+  for (int e = rp[u]; e < e1 && !S.ovf; e += 8) {
+    int k[8];
+    double x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      k[j] = u;
+      x[j] = 0.0;
+      if (e + j < e1) { k[j] = ci[e + j]; x[j] = va[e + j]; }
+    }
+    bool in[8];
+    int8_t c8[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      in[j] = (unsigned)k[j] < (unsigned)n;
+      c8[j] = in[j] ? cf[k[j]] : (int8_t)0;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (in[j] && k[j] != u && k[j] != i && x[j] != 0.0 && (c8[j] == 0 || allow_c) &&
+          strong_edge(x[j], k[j], theta, cmax))
+        S.insert(k[j]);
+  }
+}
+
+template <int SM>
+__device__ __forceinline__ int rega_bfs_literal(RegSetA<SM>& S, int n, int i, int ell,
+                                                gptr<const int32_t> __restrict__ rp,
+                                                gptr<const int32_t> __restrict__ ci,
+                                                gptr<const double> __restrict__ va,
+                                                gptr<const int8_t> __restrict__ cf, double theta,
+                                                gptr<const double> __restrict__ cmax) {
+  S.clear();
+  rowa_expand_literal(S, n, i, i, false, rp, ci, va, cf, theta, cmax);
+  int lo = 0;
+  for (int L = 2; L <= ell && !S.ovf; ++L) {
+    const int hi = S.s;
+    const bool allow_c = L < ell;
+    if (L == 2) rowa_expand_literal(S, n, i, i, allow_c, rp, ci, va, cf, theta, cmax);
+    else if (lo == hi) break;
+    for (int p = lo; p < hi && !S.ovf; ++p)
+      rowa_expand_literal(S, n, S.get(p), i, allow_c, rp, ci, va, cf, theta, cmax);
+    lo = hi;
+  }
+  if (S.ovf) return -1;
+  // the C-points were interior vertices only
+  int8_t c8[SM];
+#pragma unroll
+  for (int j = 0; j < SM; ++j) c8[j] = (S.v[j] != 0x7fffffff) ? cf[S.v[j]] : (int8_t)0;
+  int f = 0;
+#pragma unroll
+  for (int j = 0; j < SM; ++j) {
+    if (c8[j] != 0) S.v[j] = 0x7fffffff;
+    f += S.v[j] != 0x7fffffff ? 1 : 0;
+  }
+  bitonic_sort<SM>(S.v);
+  S.s = f;
+  return f;
 }
 
 // matrix owning global chunk c (desc[].chunk0 ascending): the last matrix

@@ -76,7 +76,7 @@ struct WideBuf {
 __device__ int block_bfs(int n, int i, int ell, gptr<const int32_t> __restrict__ rp, gptr<const int32_t> __restrict__ ci,
                          gptr<const double> __restrict__ va, gptr<const int8_t> __restrict__ cf, double theta,
                          gptr<const double> __restrict__ cmax, gptr<const int32_t> __restrict__ mrp,
-                         gptr<const int32_t> __restrict__ mem, WideBuf& b, int** out) {
+                         gptr<const int32_t> __restrict__ mem, WideBuf& b, int** out, bool literal = false) {
   const int tid = threadIdx.x;
   constexpr int nt = kNT;
   int* cur = b.nb0;
@@ -97,23 +97,30 @@ __device__ int block_bfs(int n, int i, int ell, gptr<const int32_t> __restrict__
     fsz = na;
     d0 = 2;
   }
-  for (int depth = d0; depth <= ell && fsz > 0; ++depth) {
+  // literal reading (S^{ell-1} T taken as written): the second step also
+  // expands i itself, C-points may be interior vertices until the last step
+  // (and are dropped at the end), and i never enters
+  for (int depth = d0; depth <= ell && (fsz > 0 || (literal && depth == 2)); ++depth) {
+    const bool with_i = literal && depth == 2;  // frontier slot fsz is i
+    const int fn = fsz + (with_i ? 1 : 0);
+    const bool allow_c = literal && depth >= 2 && depth < ell;
+    auto fu = [&](int t) { return (depth == 1 || (with_i && t == fsz)) ? i : b.fr[t]; };
     // row lengths of the frontier, prefix
-    const int per = (fsz + nt - 1) / nt;
-    const int t0 = tid * per, t1 = min(t0 + per, fsz);
+    const int per = (fn + nt - 1) / nt;
+    const int t0 = tid * per, t1 = min(t0 + per, fn);
     int sum = 0;
     for (int t = t0; t < t1; ++t) {
-      const int u = (depth == 1) ? i : b.fr[t];
+      const int u = fu(t);
       sum += rp[u + 1] - rp[u];
     }
     int E;
     int pre = block_exclusive_scan(sum, b.sh, &E);
     for (int t = t0; t < t1; ++t) {
-      const int u = (depth == 1) ? i : b.fr[t];
+      const int u = fu(t);
       b.dp[t] = pre;
       pre += rp[u + 1] - rp[u];
     }
-    if (tid == 0) b.dp[fsz] = E;
+    if (tid == 0) b.dp[fn] = E;
     __syncthreads();
     int nnl = 0;
     for (int w0 = 0; w0 < E; w0 += kWC) {
@@ -124,15 +131,15 @@ __device__ int block_bfs(int n, int i, int ell, gptr<const int32_t> __restrict__
         int k = INT32_MAX;
         if (t < wn) {
           const int ef = w0 + t;
-          int lo = 0, hi = fsz - 1;  // last frontier vertex with dp <= ef
+          int lo = 0, hi = fn - 1;  // last frontier vertex with dp <= ef
           while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (b.dp[mid] <= ef) lo = mid; else hi = mid - 1;
           }
-          const int u = (depth == 1) ? i : b.fr[lo];
+          const int u = fu(lo);
           const int e = rp[u] + (ef - b.dp[lo]);
           const int kk = ci[e];
-          if (kk != u && (unsigned)kk < (unsigned)n && va[e] != 0.0 && cf[kk] == 0 &&
+          if (kk != u && kk != i && (unsigned)kk < (unsigned)n && va[e] != 0.0 && (cf[kk] == 0 || allow_c) &&
               strong_edge(va[e], kk, theta, cmax))
             k = kk;
         }
@@ -187,6 +194,19 @@ __device__ int block_bfs(int n, int i, int ell, gptr<const int32_t> __restrict__
     nxt = tmp;
     s += nnl;
     fsz = nnl;
+  }
+  if (literal) {  // the C-points were interior vertices only: keep the F-points, in order
+    const int per = (s + nt - 1) / nt;
+    const int t0 = tid * per, t1 = min(t0 + per, s);
+    int kf = 0;
+    for (int t = t0; t < t1; ++t) kf += cf[cur[t]] == 0 ? 1 : 0;
+    int f;
+    int pos = block_exclusive_scan(kf, b.sh, &f);
+    for (int t = t0; t < t1; ++t)
+      if (cf[cur[t]] == 0) nxt[pos++] = cur[t];
+    __syncthreads();
+    *out = nxt;
+    return f;
   }
   *out = cur;
   return s;
@@ -744,7 +764,9 @@ __global__ __launch_bounds__(kNT) void k_count_mid(Work w) {
     const int i = s_rows[t];
     RegSetA<32> S;
     int sz;
-    if constexpr (W > 0) {
+    if (d.literal && d.ell >= 3) {
+      sz = rega_bfs_literal<32>(S, d.n, i, d.ell, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax);
+    } else if constexpr (W > 0) {
       if (d.fadj)
         sz = rega_bfs<32, W>(S, d.n, i, d.ell, d.fadj, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax, nullptr, nullptr);
       else
@@ -795,8 +817,21 @@ __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
     const int64_t base = d.fine0 + (int64_t)(c - d.chunk0) * w.chunk;
     const int i = -w.clocal[base + t] - 1;
     int* nl;
-    const int s = block_bfs(d.n, i, d.ell, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax, d.agg_rp, d.agg_list, bb, &nl);
+    const int s = block_bfs(d.n, i, d.ell, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax, d.agg_rp, d.agg_list, bb, &nl,
+                            d.literal != 0);
     __syncthreads();
+    // A row the register search gave up on may still hold at most 32 points
+    // (the literal reading counts the C-points a walk passes through): it
+    // then joins its size bin, whose solvers take every row of that size,
+    // and not the workgroup solver as well.
+    const int lim = small_limit(w.GA);
+    const bool toA = s >= 0 && s <= lim, toB = s > lim && s <= 32;
+    if (toA) {
+      const int SA = slot_stride(w.GA);
+      for (int p = tid; p < s; p += kNT) w.slotA[(base + t) * SA + p] = nl[p];
+    } else if (toB) {
+      for (int p = tid; p < s; p += kNT) w.slotB[(base + t) * 32 + p] = nl[p];
+    }
     if (tid == 0) {
       w.big_size[base + t] = s < 0 ? 0 : s;
       if (s < 0) {
@@ -804,9 +839,13 @@ __global__ __launch_bounds__(kNT) void k_count_big(Work w) {
       } else {
         if (s > __hip_atomic_load(&st->max_block, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
           atomicMax(&st->max_block, s);
-        const int q = atomicAdd(&w.cnt->nC, 1);
-        if (q < w.capC) w.binC[q] = e;
-        else flag_row(st, ST_UNSUPPORTED, i);
+        if (toA || toB) {
+          atomicAdd(reinterpret_cast<int*>(&w.chunk_bins[c]) + (toA ? 0 : 1), 1);
+        } else {
+          const int q = atomicAdd(&w.cnt->nC, 1);
+          if (q < w.capC) w.binC[q] = e;
+          else flag_row(st, ST_UNSUPPORTED, i);
+        }
       }
       __threadfence();  // the size is visible before the count drops
       s_last = atomicSub(&w.chunk_unsized[c], 1) == 1;
@@ -2595,7 +2634,7 @@ __global__ __launch_bounds__(kWT) void k_rows_wg(Work w) {
       if (tid == 0) d.Rrp[ri.r] = ri.off;
       int* N;
       const int s = block_bfs(d.n, i, d.ell, d.grp, d.gci, d.gva, d.cf, d.theta, d.cmax, d.agg_rp, d.agg_list, bb,
-                              &N);
+                              &N, d.literal != 0);
       __syncthreads();
       if (s != ri.s) {
         if (tid == 0) flag_row(st, s < 0 ? ST_UNSUPPORTED : ST_INVALID, i);
@@ -2780,15 +2819,20 @@ struct ColEntry {
 // One F-column of any length (the general path of k_colproj): returns true
 // when the column is uncovered (d_j = 0)
 __device__ bool project_column(const Work& w, const GDesc& d, int64_t nzb, int j, int head) {
+  // A list holds at most one record per row, so a walk of more than n steps
+  // means a record linked twice (a cycle): the column is then left as
+  // written and counted as uncovered rather than walked for ever.
   // first pass: the kPL smallest positions of the list
   ColEntry L;
   L.clear();
   bool more = false;
+  int steps = 0;
   for (int e = head; e >= 0;) {
     const int2 lk = w.clink[e];
     const double zv = d.Rva[e - nzb];
     more |= !L.insert(e, lk.y, zv);
     e = lk.x;
+    if (++steps > d.n) return true;
   }
   double dsum = 0.0, rsum = 0.0;
 #pragma unroll
@@ -2810,7 +2854,7 @@ __device__ bool project_column(const Work& w, const GDesc& d, int64_t nzb, int j
       const int2 lk = w.clink[e];
       if (e > last) more |= !M.insert(e, lk.y, d.Rva[e - nzb]);
       e = lk.x;
-    }
+    }  // (the first walk ended, so this one does)
 #pragma unroll
     for (int k = 0; k < kPL; ++k) {
       if (k < M.n) {
@@ -2829,7 +2873,7 @@ __device__ bool project_column(const Work& w, const GDesc& d, int64_t nzb, int j
     for (int k = 0; k < kPL; ++k)
       if (k < L.n) d.Rva[L.e[k] - nzb] = L.z[k] - d.B[L.ci[k]] * q;
   } else {
-    for (int e = head; e >= 0;) {
+    for (int e = head; e >= 0;) {  // the walk ended above, so no cycle here
       const int2 lk = w.clink[e];
       d.Rva[e - nzb] -= d.B[lk.y] * q;
       e = lk.x;

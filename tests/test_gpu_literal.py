@@ -7,8 +7,9 @@ tests/test_oracle_strength.py).  The per-row FP64 form searches literally
 for any ell: pattern identical and row error <= 1e-10 against the oracle at
 ell = 3, where the literal patterns are larger; the size query agrees; the
 approximate-inverse build (which uses that form's pattern) too.  The mixed
-path builds as usual at ell <= 2 (where the readings agree) and reports
-CLAIR_ERR_UNSUPPORTED at ell >= 3.
+path gives the same bits as the default reading at ell <= 2 (where the
+readings agree) and matches the oracle's literal pattern at ell = 3 and 4,
+through its register search, its workgroup search and its workgroup solver.
 """
 import dataclasses
 
@@ -67,20 +68,68 @@ def test_fp64_form_searches_literally_at_distance_3():
     assert list(nzs) == [i["nnz"] for i in infos]
 
 
-def test_mixed_path_agrees_at_distance_2_and_declines_beyond():
-    from paper_2307_00229_amd import clair
-
+def test_mixed_path_agrees_at_distance_2():
     ps = _cases(2)
     a, _, st = gpu_build(ps, ctx=_ctx())
     assert st == 0
     b, _, st = gpu_build(ps)
     assert st == 0
-    for x, y in zip(a, b):  # the projection's column sums are atomic: equal up to their rounding
+    for x, y in zip(a, b):  # the same pattern, and the same bits (every sum has a fixed order)
         assert np.array_equal(x["row_ptr"], y["row_ptr"]) and np.array_equal(x["col_idx"], y["col_idx"])
-        assert np.abs(x["val"] - y["val"]).max() <= 1e-13 * np.abs(y["val"]).max()
-    As, cfs, Bs, ells = to_device(_cases(3)[:1])
-    _, _, st = clair.clair_build_R_batched(As, cfs, Bs, ells, ctx=_ctx(), check=False)
-    assert st == clair.CLAIR_ERR_UNSUPPORTED
+        assert np.array_equal(x["val"], y["val"])
+
+
+@pytest.mark.parametrize("ell", [3, 4])
+def test_mixed_path_searches_literally(ell):
+    # the register search with C-points as interior vertices, the workgroup
+    # search for rows that pass more than 32 vertices (the random pattern and
+    # ell = 4), and the workgroup solver's own search for blocks above 32
+    from paper_2307_00229_amd import clair
+
+    ps = _cases(ell) + [P.small_2d(48, stencil=9, eps=1e-2, angle=0.7, k=3, ell=ell)]
+    ctx = _ctx()
+    print(f"[gpu] literal pattern, mixed form, ell={ell} {[p.name for p in ps]}", flush=True)
+    res, infos, st = gpu_build(ps, ctx=ctx)
+    assert st == 0, infos
+    larger = 0
+    for p, g, inf in zip(ps, res, infos):
+        o = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, literal=True)
+        assert_matches_oracle(p, g, o, inf)
+        larger += o["nnz"] > oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell)["nnz"]
+    assert larger > 0
+    As, cfs, _, ells = to_device(ps)
+    ncs, nzs = clair.clair_size_R(As, cfs, ells, ctx=ctx)
+    assert list(nzs) == [i["nnz"] for i in infos]
+    # the FP64 form agrees on the pattern where its 64-vertex search holds the rows
+    fp, finfos, st = gpu_build(ps[:3], ctx=ctx, precision=clair.CLAIR_PREC_FP64, check=False)
+    for x, y, fi in zip(res, fp, finfos):
+        if fi["status"] == 0:
+            assert np.array_equal(x["col_idx"], y["col_idx"])
+
+
+def test_mixed_literal_with_threshold_and_strength_matrix():
+    from paper_2307_00229_amd import clair
+
+    from .test_gpu_strength import _dev_csr, _random_graph
+
+    p = P.small_2d(40, stencil=5, eps=0.1, angle=0.5, ell=3)
+    ctx = _ctx()
+    ctx.set_strength(0.25)
+    print("[gpu] literal pattern, theta=0.25, ell=3, mixed form", flush=True)
+    res, infos, st = gpu_build([p], ctx=ctx)
+    assert st == 0, infos
+    o = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, theta=0.25, literal=True)
+    assert_matches_oracle(p, res[0], o, infos[0])
+    ps = [P.random_sparse(300, 0.01, 41, ell=3), P.small_2d(40, stencil=9, eps=1e-2, angle=0.7, k=3, ell=3)]
+    graphs = [_random_graph(q, 7 + k) for k, q in enumerate(ps)]
+    ctx = _ctx()
+    ctx.set_graph([_dev_csr(*g, n=q.n) for g, q in zip(graphs, ps)])
+    print("[gpu] literal pattern on strength matrices, ell=3, mixed form", flush=True)
+    res, infos, st = gpu_build(ps, ctx=ctx)
+    assert st == 0, infos
+    for q, g, gr, inf in zip(ps, res, graphs, infos):
+        o = oracle.build_R(q.n, q.row_ptr, q.col_idx, q.val, q.cf, q.B, q.ell, strength=gr, literal=True)
+        assert_matches_oracle(q, g, o, inf)
 
 
 def test_approximate_inverse_build_with_the_literal_pattern():
@@ -139,27 +188,29 @@ def test_flag_values_and_switching_back():
     ps = _cases(3)[:1]
     _, _, st = gpu_build(ps, ctx=ctx, check=False)  # rejected values left the default
     assert st == 0
+    a, _, st = gpu_build(ps, ctx=ctx, check=False)
     ctx.set_literal_pattern(True)
-    _, _, st = gpu_build(ps, ctx=ctx, check=False)
-    assert st == clair.CLAIR_ERR_UNSUPPORTED
+    b, _, st2 = gpu_build(ps, ctx=ctx, check=False)
+    assert st2 == 0 and b[0]["nnz"] > a[0]["nnz"]
     ctx.set_literal_pattern(False)
-    _, _, st = gpu_build(ps, ctx=ctx, check=False)
-    assert st == 0
+    c, _, st3 = gpu_build(ps, ctx=ctx, check=False)
+    assert st3 == 0 and np.array_equal(c[0]["col_idx"], a[0]["col_idx"])
 
 
 @pytest.mark.parametrize("theta", [0.0, 0.3])
 def test_literal_pattern_c_points_without_f_neighbours(theta):
     # many C-points, so that some have no (strong) F-neighbour: T's identity
-    # part still lets the second step expand them; FP64 form against the
+    # part still lets the second step expand them; both forms against the
     # oracle's literal search (pinned against boolean products) at ell = 3
     from paper_2307_00229_amd import clair
 
     ps = [P.random_sparse(300, 0.01, 60 + k, c_frac=0.55, ell=3) for k in range(2)]
     ctx = _ctx()
     ctx.set_strength(theta)
-    print(f"[gpu] literal pattern, dense C-points, theta={theta}, ell=3, FP64 form", flush=True)
-    res, infos, st = gpu_build(ps, ctx=ctx, precision=clair.CLAIR_PREC_FP64)
-    assert st == 0, infos
-    for p, g, inf in zip(ps, res, infos):
-        o = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, theta=theta, literal=True)
-        assert_matches_oracle(p, g, o, inf)
+    for prec in (clair.CLAIR_PREC_FP64, clair.CLAIR_PREC_MIXED):
+        print(f"[gpu] literal pattern, dense C-points, theta={theta}, ell=3, precision {prec}", flush=True)
+        res, infos, st = gpu_build(ps, ctx=ctx, precision=prec)
+        assert st == 0, infos
+        for p, g, inf in zip(ps, res, infos):
+            o = oracle.build_R(p.n, p.row_ptr, p.col_idx, p.val, p.cf, p.B, p.ell, theta=theta, literal=True)
+            assert_matches_oracle(p, g, o, inf)
