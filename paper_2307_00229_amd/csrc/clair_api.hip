@@ -72,7 +72,7 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
   size_t desc, st, cnt, chunk_nc, chunk_nnz, chunk_rbase, chunk_nzbase, chunk_mat, chunk_bins, row_block_chunk, clocal, lnz, chead,
-      slotA, slotB, binC, bigq, big_size, ovf, cmax, agg_cnt, agg_rp, agg_list, agg_sums, fadj, total;
+      slotA, slotB, binC, bigq, big_size, ovf, cmax, agg_cnt, agg_rp, agg_list, agg_sums, fadj, midq, total;
   size_t head_bytes;  // desc + st + counters (the uploaded head)
   int64_t capC;
 };
@@ -117,6 +117,7 @@ Layout make_layout(int nmat, int nchunks, int64_t n_total, int GA, bool any_agg,
   L.agg_list = take(sizeof(int32_t) * (na + 1));
   L.agg_sums = take(sizeof(int32_t) * (na / 1024 + 4));
   L.fadj = take(sizeof(int32_t) * (adj_w ? n_total * adj_w : 1));
+  L.midq = take(sizeof(int32_t) * (nchunks + 1));
   L.total = o;
   return L;
 }
@@ -389,6 +390,7 @@ int prepare(clair_ctx* c, int32_t nmat, const clair_csr_t* A, const int8_t* cons
   w.fadj = reinterpret_cast<int32_t*>(base + b->L.fadj);
   w.bf16 = 0;
   w.pad1 = 0;
+  w.midq = reinterpret_cast<int32_t*>(base + b->L.midq);
 
   char* h = stage_base(c);
   MatDesc* hd = reinterpret_cast<MatDesc*>(h);
@@ -598,7 +600,7 @@ int enqueue_symbolic(clair_ctx* c, Batch& b, hipStream_t s, bool validate, bool 
   HIPCHK(launch_count(b.w, s));
   if (capture_check(c->capturing, s, "k_count", __LINE__)) return CLAIR_ERR_HIP;
   timing_mark(c, timing, s, "count");
-  HIPCHK(launch_count_mid(b.w, s));
+  HIPCHK(launch_count_mid(b.w, occupancy_blocks(c, 4), s));
   if (capture_check(c->capturing, s, "k_count_mid", __LINE__)) return CLAIR_ERR_HIP;
   timing_mark(c, timing, s, "count_mid");
   HIPCHK(launch_count_big(b.w, std::max(8, c->cus * 2), s));

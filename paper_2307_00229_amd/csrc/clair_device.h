@@ -166,7 +166,8 @@ struct Counters {
   int32_t nB;          // rows for the 32-lane solver (GA < |N| <= 32)
   int32_t nC;          // rows queued for the workgroup solver (larger, or FP32 not trusted)
   int32_t nbig;        // rows with more than 32 points queued for k_count_big
-  int32_t pad0, pad1, pad2;
+  int32_t nmid;        // chunks k_count left to k_count_mid (queued in midq)
+  int32_t pad1, pad2;
 };
 
 // Row t of chunk c: fine offset base = fine0 + (c - chunk0) * chunk of its
@@ -213,6 +214,7 @@ struct Work {
   int32_t* fadj;          // [n_total * adj_w]
   int32_t bf16;           // 1: the workgroup solver's trailing updates take bfloat16 inputs
   int32_t pad1;
+  int32_t* midq;          // [nchunks] chunks k_count left unfinished
 };
 
 // status codes (mirror clair_status)

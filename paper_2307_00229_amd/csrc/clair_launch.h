@@ -20,7 +20,7 @@ hipError_t launch_agg_lists(const Work& w, int64_t n_total, int blocks, int cus,
 hipError_t launch_colmax(const Work& w, int64_t n_total, int blocks, hipStream_t s);
 hipError_t launch_adj(const Work& w, hipStream_t s);
 hipError_t launch_count(const Work& w, hipStream_t s);
-hipError_t launch_count_mid(const Work& w, hipStream_t s);
+hipError_t launch_count_mid(const Work& w, int blocks, hipStream_t s);
 hipError_t launch_count_big(const Work& w, int blocks, hipStream_t s);
 hipError_t launch_scan(const Work& w, hipStream_t s);
 // which = 0: bin A with group = GA; which = 1: bin B with group = 32
