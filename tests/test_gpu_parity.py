@@ -84,6 +84,25 @@ def test_cfg5_128cube_7pt():
     assert infos[0]["n_uncovered"] == 262144
 
 
+def test_cfg3_2048_plain_fp64():
+    p = P.cfg3()
+    res, infos = _check([p], precision=1)
+    assert infos[0]["max_block"] == 24
+
+
+def test_cfg4_64_matrices_plain_fp64():
+    ps = P.cfg4()
+    res, infos = _check(ps, precision=1)
+    assert sum(i["n_c"] for i in infos) == 3189226
+
+
+def test_cfg5_128cube_plain_fp64():
+    p = P.cfg5()
+    res, infos = _check([p], precision=1)
+    assert infos[0]["max_block"] == 18
+    assert infos[0]["n_uncovered"] == 262144
+
+
 # ---------------------------------------------------------------------------
 # larger neighbourhoods: one thread per row (|N| <= 8), lane groups of
 # 8/16/32, workgroup-per-row in LDS and in global scratch
