@@ -1020,10 +1020,18 @@ __global__ __launch_bounds__(1024) void k_scan(Work w) {
 template <int G, int SM>
 struct NumGroupBuf {
   double K[SM * (SM + 1)];  // FP64 block, row q = row q of (A[N,N])^T, stride SM+1
-  double f[SM];             // -A[i,N]
-  double z[SM];             // refinement broadcast
-  float y[SM];              // right-hand side of a correction, FP32
-  int nb[G];                // sorted N(i), INT32_MAX beyond |N|
+  // -A[i,N] (written by the gather, read once after the factorisation), the
+  // refinement broadcast z and a correction's FP32 right-hand side y are
+  // never live together, so they share one buffer: every store to it comes
+  // after the group's last load of the previous contents in program order,
+  // and a wavefront's LDS instructions execute in order.  (At 24 points
+  // this holds a group to 5,120 bytes, eight workgroups of four per CU.)
+  union {
+    double f[SM];
+    double z[SM];
+    float y[SM];
+  };
+  int nb[G];  // sorted N(i), INT32_MAX beyond |N|
 };
 
 // Communication inside a group of G lanes (G = 8, 16 or 32; groups are
