@@ -364,6 +364,7 @@ def main():
         elif not args.no_autotune and aggs is None:
             clair.clair_autotune(ctx, As, cfs, Bs, ells, outs, reps=3, stream=stream)
         tuning = ctx.get_tuning()
+        tuning["binB_lanes"] = ctx.get_bin_shape()
         rows = sum(n_c_list)
 
         direct_step = clair.BatchedCall(ctx, As, cfs, Bs, ells, outs, async_=True, stream=stream, aggs=aggs)
