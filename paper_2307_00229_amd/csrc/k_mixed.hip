@@ -1776,7 +1776,7 @@ struct QuadBuf {
 #define QB_ROW(arr0, arr1, k, p) ((k) & 1 ? qb(arr1[p], (k) / 2) : qb(arr0[p], (k) / 2))
 
 template <int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_quad8(Work w) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3))) void k_quad8(Work w) {
   constexpr int NQ = NT / 4;
   __shared__ QuadBuf qbuf[NQ];
   const int tid = threadIdx.x;
@@ -1874,6 +1874,101 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
       }
     }
     wave_sync();
+    if (s <= 4) {
+      // Blocks of at most four points (every row at distance 1 on a
+      // five-point graph): lane l owns row l of the 4 x 4 corner of K (the
+      // padding rows are identity there as in the full block), so the LU, the
+      // substitutions and the residual take four steps instead of eight.
+      const int q = ql;
+      double kq[4];
+      float amax = 0.f;
+      double rs = 0.0;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        kq[p] = B.K[q * 8 + p];
+        amax = fmaxf(amax, (float)fabs(kq[p]));
+        rs += fabs(kq[p]);
+      }
+      const double fq = B.f[q];
+      const int nq = B.nb[q];  // INT32_MAX on padding rows
+      amax = qmaxf(amax);
+      const double knorm = qmaxd(rs);
+      const double fnorm = qmaxd(fabs(fq));
+      int ex = 0;
+      frexpf(amax, &ex);
+      const double scale = ldexp(1.0, -ex);
+      float a[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) a[p] = (float)(kq[p] * scale);
+      int bad = !(amax > 0.f) || !(amax < 3.0e38f);
+      float ui = 1.f;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        float pr[4];
+#pragma unroll
+        for (int p = k; p < 4; ++p) pr[p] = qb(a[p], k);
+        bad |= !(fabsf(pr[k]) >= 0x1p-24f);
+        const float pinv = __builtin_amdgcn_rcpf(pr[k]);
+        if (q == k) ui = pinv;
+        if (q > k) {
+          const float l = a[k] * pinv;
+          a[k] = l;
+#pragma unroll
+          for (int p = k + 1; p < 4; ++p) a[p] = fmaf(-l, pr[p], a[p]);
+        }
+      }
+      bad = qori(bad);
+      double z = 0.0;
+      int it = 0;
+      bool conv = false;
+      if (!bad) {
+        // K y = rhs for this lane's entry of y
+        auto solve4 = [&](float y) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {  // forward, unit lower
+            const float yk = qb(y, k);
+            if (q > k) y = fmaf(-a[k], yk, y);
+          }
+#pragma unroll
+          for (int k = 3; k >= 0; --k) {  // backward, upper
+            if (q == k) y *= ui;
+            const float zk = qb(y, k);
+            if (q < k) y = fmaf(-a[k], zk, y);
+          }
+          return y;
+        };
+        z = solve4((float)(fq * scale));
+        for (it = 1; it <= kRefineMax; ++it) {
+          double r = fq;
+#pragma unroll
+          for (int p = 0; p < 4; ++p) r = fma(-kq[p], qbd(z, p), r);
+          const double rn = qmaxd(fabs(r));
+          const double zn = qmaxd(fabs(z));
+          if (rn <= 0x1p-47 * (knorm * zn + fnorm)) { conv = true; break; }
+          z += (double)solve4((float)(r * scale));
+        }
+        conv = conv && (z == z);
+        conv = qori(conv ? 0 : 1) == 0;
+      }
+      if (!conv) {
+        if (ql == 0) {
+          const int qc = atomicAdd(&w.cnt->nC, 1);
+          if (qc < w.capC) w.binC[qc] = c * w.chunk + t;
+          else flag_row(st, ST_UNSUPPORTED, i);
+        }
+        continue;
+      }
+      if (ql == 0) rmx.add(w, ri.m, it);
+      const int below = nq < i ? 1 : 0;
+      const int b2 = below + __builtin_amdgcn_mov_dpp(below, 0xB1, 0xF, 0xF, false);
+      const int dpos4 = b2 + __builtin_amdgcn_mov_dpp(b2, 0x4E, 0xF, 0xF, false);
+      if (q < s) put_f_entry(w, d, ri.fine0, ri.off + q + (q >= dpos4 ? 1 : 0), nq, i, z);
+      if (ql == 0) {
+        d.Rci[ri.off + dpos4] = i;
+        d.Rva[ri.off + dpos4] = 1.0;
+      }
+      continue;
+    }
     // rows q0, q1 of K (FP64), scaled FP32 copies
     double k0[8], k1[8];
     float amax = 0.f;
