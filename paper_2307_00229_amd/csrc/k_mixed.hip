@@ -1724,7 +1724,9 @@ __global__ __launch_bounds__(NT) void k_lanes(Work w, int which) {
 // owns rows 2l and 2l+1 of K = (A[N,N])^T.  The block is transposed once
 // through LDS after the gather; the LU, both triangular solves and the FP64
 // residual then broadcast within the quad with DPP quad permutations
-// (register moves, no LDS round trip).
+// (register moves, no LDS round trip).  A row of at most four points takes
+// the 4 x 4 corner only, one block row per lane.  The kernel runs at three
+// wavefronts per SIMD: at four the compiler spills the two paths' registers.
 // ---------------------------------------------------------------------------
 // lane src of the quad, to all four (src is a constant once the calling loops
 // are unrolled, so the switch folds to one DPP move)
