@@ -162,6 +162,29 @@ def test_tuning_shapes(group, wg, chunk):
     _check(ps, precision=0, ctx=ctx)
 
 
+def test_quad_solver_small_blocks_and_untrusted_rows():
+    # the quad solver (four lanes per row) on random patterns at distance 1:
+    # blocks of 0..4 points take its four-point path (a C-point with only
+    # C-neighbours has an empty block), larger ones the eight-point path;
+    # without diagonal dominance a row the FP32 factorisation cannot be
+    # trusted with goes to the FP64 pivoting solver
+    from paper_2307_00229_amd import clair
+
+    ctx = clair.Context()
+    ctx.set_tuning(4, 128, 1024)
+    ps = [P.random_sparse(400, 0.006, 70, c_frac=0.55, ell=1, B="ones"),
+          P.random_sparse(300, 0.01, 71, c_frac=0.4, ell=1),
+          P.random_sparse(250, 0.008, 72, c_frac=0.5, ell=2)]
+    sizes = [np.diff(oracle.build_R_problem(p)["row_ptr"]) - 1 for p in ps]
+    assert any((sz == 0).any() for sz in sizes) and any(((sz > 0) & (sz <= 4)).any() for sz in sizes)
+    _check(ps, precision=0, ctx=ctx)
+    qs = [P.random_sparse(300, 0.01, 80 + k, c_frac=0.4, ell=1, dominant=False) for k in range(3)]
+    for q in qs:
+        if oracle.build_R_problem(q, allow_singular=True)["status"] != 0:
+            pytest.skip("random matrix happened to have a singular block")
+    _check(qs, precision=0, ctx=ctx)
+
+
 # ---------------------------------------------------------------------------
 # general sparse inputs and degenerate cases
 # ---------------------------------------------------------------------------
