@@ -331,6 +331,14 @@ __device__ __forceinline__ int xcd_logical_block(int nb) {
   return x * q + min(x, r) + b / 8;
 }
 __device__ __forceinline__ int xcd_logical_block() { return xcd_logical_block(gridDim.x); }
+// The same ranges, each walked from its end: the first workgroups of an XCD
+// take the last blocks of its range.
+__device__ __forceinline__ int xcd_logical_block_reversed() {
+  const int nb = gridDim.x;
+  const int b = blockIdx.x;
+  const int x = b % 8, q = nb / 8, r = nb % 8;
+  return x * q + min(x, r) + (q + (x < r ? 1 : 0)) - 1 - b / 8;
+}
 
 // Rows of the persistent numeric kernels: XCD x (= blockIdx.x % 8, the
 // hardware deals workgroups round-robin) owns a contiguous eighth of all
@@ -655,7 +663,11 @@ __global__ __launch_bounds__(kNT) void k_count(Work w) {
   __shared__ int s_flag[4];  // max |N|, -, rows in bin A, rows in bin B
   __shared__ int s_ndef, s_qbase;
 
-  const int c = xcd_logical_block();
+  // each XCD's chunks newest first: k_adj wrote them in ascending order, so
+  // the last ones' adjacency is the part most likely still cached (and the
+  // numeric kernels, walking rows in ascending order, then first read the
+  // slots written last here)
+  const int c = xcd_logical_block_reversed();
   const int tid = threadIdx.x;
   const int m = chunk_matrix(w.desc, w.nmat, c);
   const GDesc d = gview(w.desc[m]);
@@ -3001,7 +3013,10 @@ constexpr int kIC = 4, kPI = 4;
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_colproj(Work w) {
   __shared__ int s_unc;
-  const int c = xcd_logical_block();
+  // chunks newest first: the numeric kernels walked each XCD's rows in
+  // ascending order, so the last chunks' records and values are the ones
+  // most likely still in the caches
+  const int c = xcd_logical_block_reversed();
   const int tid = threadIdx.x;
   const int m = w.chunk_mat[c];
   const GDesc d = gview(w.desc[m]);
