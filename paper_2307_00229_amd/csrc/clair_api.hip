@@ -547,13 +547,15 @@ int enqueue_numeric(clair_ctx* c, Batch& b, hipStream_t s, bool timing, const Co
   if (c->group < 32 && (!known || known->nB > 0)) {
     // bin B: the smallest block bound that holds the largest block seen (rows
     // beyond it go to the workgroup solver, so any bound is correct)
-    // block bound 16, 20, 24 or 32 (the smallest that holds the largest
+    // block bound 16, 18, 20, 24 or 32 (the smallest that holds the largest
     // block read back).  binB_lanes = 32: one lane per block row (16 lanes at
     // the bound 16); 8 or 16: ceil(bound / lanes) block rows per lane (8
     // lanes at 32 points would need more LDS than a workgroup has: 16 then)
     const int bsm = c->binB_max <= 16 ? 16 : c->binB_max <= 20 ? 20 : c->binB_max <= 24 ? 24 : 32;
     if (c->binB_lanes == 32) {
-      HIPCHK(launch_numeric(b.w, 1, bsm == 16 ? 16 : 32, bsm, 128, c->cus, s));
+      // (17 and 18 points, the 128^3 seven-point rows, have a bound of their own)
+      const int b32 = (c->binB_max > 16 && c->binB_max <= 18) ? 18 : bsm;
+      HIPCHK(launch_numeric(b.w, 1, b32 == 16 ? 16 : 32, b32, 128, c->cus, s));
     } else {
       const int bg = (bsm == 32 && c->binB_lanes == 8) ? 16 : c->binB_lanes;
       const int br = (bsm + bg - 1) / bg;

@@ -1149,7 +1149,7 @@ constexpr int kRefineMax = 5;
 // (at SM = 20 the registers fit four wavefronts per SIMD without spilling;
 // the other shapes are held to fewer by their LDS or would spill)
 template <int G, int NT, int SM>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((SM == 20 || SM == 24) ? 4 : 1))) void k_numeric(Work w, int which) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu((SM == 18 || SM == 20 || SM == 24) ? 4 : 1))) void k_numeric(Work w, int which) {
   static_assert(SM <= G, "block bound");
   constexpr int NG = NT / G;
   constexpr int LD = SM + 1;
@@ -3275,7 +3275,7 @@ hipError_t launch_scan(const Work& w, hipStream_t s) {
 
 // persistent grid: as many workgroups as fit on the device at once.
 // which = 0: bin A with `group` lanes per row; which = 1: bin B with blocks of
-// up to sm points (16: 16 lanes per row; 20, 24 or 32: 32 lanes per row).
+// up to sm points (16: 16 lanes per row; 18, 20, 24 or 32: 32 lanes per row).
 hipError_t launch_numeric(const Work& w, int which, int group, int sm, int wg_threads, int cus, hipStream_t s) {
 #define CLAIR_NUM(GG, NTT, SMM)                                                                         \
   if (group == GG && wg_threads == NTT && sm == SMM) {                                                  \
@@ -3295,6 +3295,7 @@ hipError_t launch_numeric(const Work& w, int which, int group, int sm, int wg_th
   CLAIR_NUM(32, 256, 32)
   CLAIR_NUM(32, 128, 32)
   CLAIR_NUM(32, 64, 32)
+  CLAIR_NUM(32, 128, 18)
   CLAIR_NUM(32, 128, 20)
   CLAIR_NUM(32, 128, 24)
 #undef CLAIR_NUM
